@@ -1,0 +1,178 @@
+/*
+ * rdhei.h -- C ABI of the MI355X (gfx950) EMR-/LMR-RDHEI library.
+ *
+ * Method: Zhang & Luo, "Vector-based Efficient Data Hiding in Encrypted Images
+ * via Multi-MSB Replacement" (arXiv 2302.07992).  The three roles of the
+ * reserving-room-before-encryption scheme (Sec. I, RRBE figure; Sec. III):
+ *   content owner  -> rdhei_encrypt   (key K1: location map, rotation, XOR)
+ *   data hider     -> rdhei_embed     (key K2: multi-MSB replacement)
+ *   recipient      -> rdhei_extract   (key K2) and/or rdhei_recover (key K1)
+ *
+ * Conventions shared by every entry point
+ *   - Images are 8-bit grey, row-major, height M rows by width N columns,
+ *     M*N bytes, in DEVICE memory owned by the caller.  The fast tiled path
+ *     is taken when M and N are multiples of 64 and buffers are 16-byte
+ *     aligned; every other shape runs a per-pixel path with identical output.
+ *   - Messages are bit strings packed MSB-first into bytes (bit t is bit
+ *     7 - t%8 of byte t/8), in DEVICE memory owned by the caller.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *     stream-ordered and return before the GPU work finishes, except where a
+ *     function says it synchronises (the LMR entry points, which run a host
+ *     stage).
+ *   - Return value: RDHEI_OK (0) or a negative RDHEI_E* code.  Argument
+ *     errors are reported before anything is launched.  Conditions only the
+ *     device can see (message longer than the capacity computed on the
+ *     device) are written to meta->status and the affected image is left
+ *     unmodified by that stage.
+ *   - A context owns device workspace; two calls that use one context must be
+ *     ordered on one stream (use one context per concurrent stream).  The
+ *     library never frees caller memory.
+ *
+ * Keystream: Philox4x32-10 (Salmon et al., SC'11) stands in for the
+ * "cryptographically secure stream cipher" the paper asks for (Sec. III-A,
+ * secret key generation).  Byte idx of stream (key, domain) is little-endian
+ * byte idx%16 of Philox4x32-10 with counter (idx/16 low word, idx/16 high
+ * word, domain, 0) and key (key low word, key high word).  Domain 1 = image
+ * keystream s (K1), domain 2 = message keystream (K2).
+ */
+#ifndef RDHEI_H
+#define RDHEI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RDHEI_OK         0
+#define RDHEI_EINVAL    -1   /* bad size, pointer, method or parameter       */
+#define RDHEI_ECAPACITY -2   /* message longer than the image's capacity      */
+#define RDHEI_ENOFIT    -3   /* LMR: no candidate map compresses into M*N bits */
+#define RDHEI_ENOMEM    -4   /* device or host allocation failed              */
+#define RDHEI_EDEVICE   -5   /* HIP runtime error (see rdhei_last_error)      */
+#define RDHEI_ECORRUPT  -6   /* LMR: map stream in the MSB plane is malformed */
+
+#define RDHEI_EMR 0          /* Sec. III-A: map in the LSB plane, b in [2,7]   */
+#define RDHEI_LMR 1          /* Sec. III-B: maps compressed into the MSB plane */
+
+/* Public side information of one encrypted image (64 bytes, plain data).
+ * The paper carries b and the message length implicitly; this record makes
+ * them explicit.  Written by rdhei_encrypt (on the device), read by the other
+ * three entry points (on the device). */
+typedef struct rdhei_meta {
+    int32_t height;          /* M                                              */
+    int32_t width;           /* N                                              */
+    int32_t method;          /* RDHEI_EMR or RDHEI_LMR                         */
+    int32_t b;               /* MSBs compared per pixel (EMR 2..7, LMR 2..8)   */
+    int32_t min_level;       /* rotation block sizes 2^min_level..2^max_level  */
+    int32_t max_level;
+    int64_t redundant;       /* Z_b: pixels labelled 0 (redundant)             */
+    int64_t capacity_bits;   /* b*Z_b (EMR) or (b-1)*Z_b (LMR)                 */
+    int64_t map_bits;        /* LMR: bits of the map stream in the MSB plane   */
+    int32_t status;          /* RDHEI_OK or the device-side error of a stage   */
+    int32_t reserved[3];
+} rdhei_meta;
+
+typedef struct rdhei_ctx rdhei_ctx;
+typedef struct rdhei_plan rdhei_plan;
+
+/* Context on HIP device `device` (workspace arena, kernels' tile choice). */
+int  rdhei_ctx_create(rdhei_ctx **out, int device);
+void rdhei_ctx_destroy(rdhei_ctx *ctx);
+
+/* Content owner (Sec. III-A encoding phase; Sec. III-B encoding phase).
+ * Reads d_img (M x N), writes the encrypted image d_enc (M x N; must not
+ * alias d_img) and *d_meta (device memory).
+ * EMR: location map for the b in [2,7] maximising b*Z_b (optimal-b equation),
+ * rotation of image and map by key-driven block turns at block sizes
+ * 2^1..2^n (rotation equation), XOR with s (encryption equation), map into
+ * the LSB plane.  Asynchronous.
+ * LMR: b in [2,8], rotation at 2^4..2^n, first-MSB map, both maps compressed
+ * on the host and written into the MSB plane (candidates tried in order of
+ * (b-1)*Z_b; RDHEI_ENOFIT when none fits).  Synchronises `stream`. */
+int rdhei_encrypt(rdhei_ctx *ctx, const uint8_t *d_img, uint8_t *d_enc, int32_t M, int32_t N,
+                  uint64_t k1, int32_t method, rdhei_meta *d_meta, void *stream);
+
+/* Data hider (Sec. III-A / III-B data hiding phase).  d_marked holds I_e on
+ * entry and I_e' on return (in place).  The first nbits bits of d_msg are
+ * XORed with K2's keystream and written, in raster order, into the
+ * replaceable bits of the redundant pixels (EMR: bits 7..8-b of pixels with
+ * LSB 0; LMR: bits 6..8-b of pixels the decompressed map marks 0).  nbits < 0
+ * means "the full capacity".  Unused replaceable bits are left unchanged.
+ * EMR: asynchronous; LMR: synchronises (host map decompression). */
+int rdhei_embed(rdhei_ctx *ctx, uint8_t *d_marked, const rdhei_meta *d_meta,
+                const uint8_t *d_msg, int64_t nbits, uint64_t k2, void *stream);
+
+/* Recipient with K2 (Sec. III-A/B decoding with K2).  Writes ceil(nbits/8)
+ * bytes to d_msg (trailing bits of the last byte zero); nbits < 0 = capacity
+ * (d_msg must then hold ceil(capacity/8) bytes). */
+int rdhei_extract(rdhei_ctx *ctx, const uint8_t *d_marked, const rdhei_meta *d_meta,
+                  uint8_t *d_msg, int64_t nbits, uint64_t k2, void *stream);
+
+/* Recipient with K1 (Sec. III-A/B decoding with K1).  Writes the recovered
+ * image to d_img (M x N; must not alias d_marked).  EMR output differs from
+ * the original only in bit 0 (expected PSNR about 51.14 dB); LMR output is
+ * exact.  EMR: asynchronous; LMR: synchronises. */
+int rdhei_recover(rdhei_ctx *ctx, const uint8_t *d_marked, const rdhei_meta *d_meta,
+                  uint8_t *d_img, uint64_t k1, void *stream);
+
+/* ---- Batches: many independent images per launch ------------------------ */
+
+#define RDHEI_OP_ENCRYPT 0
+#define RDHEI_OP_EMBED   1
+#define RDHEI_OP_EXTRACT 2
+#define RDHEI_OP_RECOVER 3
+
+/* One image of a batch.  All pointers are device memory; sizes may differ
+ * between images.  in/out/msg follow the single-image call of the op:
+ * ENCRYPT: in = I, out = I_e;  EMBED: out = I_e (modified in place), msg in;
+ * EXTRACT: in = I_e', msg out;  RECOVER: in = I_e', out = I'. */
+typedef struct rdhei_job {
+    const uint8_t *in;
+    uint8_t *out;
+    uint8_t *msg;
+    rdhei_meta *meta;
+    uint64_t key;
+    int64_t nbits;           /* EMBED/EXTRACT: bits, or < 0 for the capacity   */
+    int32_t height, width;
+} rdhei_job;
+
+/* Build a reusable plan for one EMR op over `njobs` images (host array, copied).
+ * The plan owns its device job table and workspace; its first run captures the
+ * launches in a hipGraph that later runs replay.  Plans are independent of
+ * each other and of their context's single-image workspace. */
+int  rdhei_plan_create(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t njobs, rdhei_plan **out);
+int  rdhei_plan_run(rdhei_plan *plan, void *stream);
+/* Same launches as rdhei_plan_run, issued directly (no graph). */
+int  rdhei_plan_run_eager(rdhei_plan *plan, void *stream);
+void rdhei_plan_destroy(rdhei_plan *plan);
+
+/* Per-image launches of the same op, one image after another on `stream`
+ * (the per-image baseline the batched plan is compared with). */
+int  rdhei_run_each(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t njobs, void *stream);
+
+/* ---- LMR host stage: bi-level map coder (Sec. III-B, map compression) ---- */
+/* The paper compresses the rotated first-MSB map and the rotated location map
+ * with JBIG-KIT.  This library uses its own context-modelled binary
+ * arithmetic coder.  Inputs are host bit planes (M*N bits, MSB-first packed,
+ * raster order).  The stream is: 32-bit big-endian byte length of the eta
+ * part, 32-bit big-endian byte length of the l part, eta part, l part.
+ * rdhei_lmr_compress writes at most `capacity_bytes` bytes and returns
+ * RDHEI_ENOFIT if the stream would be longer; *stream_bits receives its length
+ * in bits.  rdhei_lmr_decompress returns RDHEI_ECORRUPT on a malformed stream. */
+int rdhei_lmr_compress(const uint8_t *eta_bits, const uint8_t *l_bits, int32_t M, int32_t N,
+                       uint8_t *stream, int64_t capacity_bytes, int64_t *stream_bits);
+int rdhei_lmr_decompress(const uint8_t *stream, int64_t stream_bytes, int32_t M, int32_t N,
+                         uint8_t *eta_bits, uint8_t *l_bits);
+
+/* ---- Diagnostics ---------------------------------------------------------- */
+const char *rdhei_strerror(int code);
+/* Text of the last HIP error seen by this thread (empty if none). */
+const char *rdhei_last_error(void);
+/* Library version string. */
+const char *rdhei_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RDHEI_H */

@@ -1,0 +1,423 @@
+/*
+ * Plain, single-threaded CPU oracle for EMR-RDHEI and LMR-RDHEI
+ * (Zhang & Luo, "Vector-based Efficient Data Hiding in Encrypted Images via
+ * Multi-MSB Replacement", arXiv 2302.07992).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no code, header, table or constant generator
+ * with the HIP path.  It runs every step the way the paper states it:
+ * the Omega glide once per candidate b, the block rotation level by level with
+ * the whole image materialised after each level, embedding with a running bit
+ * counter, and the omega glide for recovery.  No closed forms, no blocking.
+ *
+ * Conventions the paper leaves open are fixed as follows (each is a reading of
+ * a silent or ambiguous passage; the product follows the same readings):
+ *   - keystream: Philox4x32-10 (Salmon et al., SC'11); byte idx of a stream is
+ *     little-endian byte (idx & 15) of the block with counter
+ *     (idx>>4 low word, idx>>4 high word, domain, 0) and key (K low, K high).
+ *     Domain 1 = image keystream s (key K1), domain 2 = message keystream
+ *     (key K2).  The paper asks only for a secure stream cipher (Sec. III-A,
+ *     "Secret key generation").
+ *   - a pixel is redundant (label 0) when its b MSBs equal those of the
+ *     tracker (the text of Sec. III-A wins over the indicator printed in the
+ *     gliding equation).
+ *   - optimal b: the first b reaching the largest b*Z_b (ties -> smaller b).
+ *   - n = floor(log2(min(M, N))); only full 2^m x 2^m blocks are rotated.
+ *   - a rotation code r turns the block r quarter turns counter-clockwise
+ *     (out[a][c] = in[c][k-1-a] per turn); decoding turns (4-r) mod 4.
+ *   - payload bits fill pixels in raster order of the encrypted image, the
+ *     most significant replaceable bit first; message bytes are read
+ *     MSB-first; the message is XORed with the K2 stream bit by bit.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Keystream (Sec. III-A "Secret key generation"): Philox4x32-10.            */
+/* ------------------------------------------------------------------------ */
+
+void or_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t prod0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t prod1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+        uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Bytes [first, first+count) of the stream (key, domain). */
+void or_keystream(uint64_t key, uint32_t domain, uint64_t first, uint64_t count, uint8_t *out)
+{
+    uint32_t k[2] = {(uint32_t)key, (uint32_t)(key >> 32)};
+    for (uint64_t t = 0; t < count; ++t) {
+        uint64_t idx = first + t;
+        uint64_t blk = idx >> 4;
+        uint32_t ctr[4] = {(uint32_t)blk, (uint32_t)(blk >> 32), domain, 0u};
+        uint32_t w[4];
+        or_philox4x32_10(ctr, k, w);
+        unsigned within = (unsigned)(idx & 15);
+        out[t] = (uint8_t)(w[within >> 2] >> (8 * (within & 3)));
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Location maps (Sec. III-A "Optimal location map generation", Eqs. for the */
+/* initialisation, the glide and the map update).                            */
+/* ------------------------------------------------------------------------ */
+
+/* Location map for one b by gliding the tracker omega along each row.
+ * L[i][0] = 1; for j >= 1 the pixel is redundant (0) when its b MSBs match
+ * the tracker; the tracker takes the pixel whenever the pixel is
+ * non-redundant.  Returns Z_b, the number of zeros. */
+int64_t or_location_map(const uint8_t *I, int32_t M, int32_t N, int b, uint8_t *L)
+{
+    int64_t zeros = 0;
+    int shift = 8 - b;
+    for (int32_t i = 0; i < M; ++i) {
+        uint8_t omega = I[(int64_t)i * N];
+        L[(int64_t)i * N] = 1;
+        for (int32_t j = 1; j < N; ++j) {
+            uint8_t phi = I[(int64_t)i * N + j];
+            if ((phi >> shift) == (omega >> shift)) {
+                L[(int64_t)i * N + j] = 0;
+                ++zeros;
+            } else {
+                L[(int64_t)i * N + j] = 1;
+                omega = phi;
+            }
+        }
+    }
+    return zeros;
+}
+
+/* Z_b for b = bmin..bmax (Z[b - bmin]), each from its own glide. */
+void or_redundancy_counts(const uint8_t *I, int32_t M, int32_t N, int bmin, int bmax, int64_t *Z)
+{
+    uint8_t *L = (uint8_t *)malloc((size_t)M * (size_t)N + 1);
+    for (int b = bmin; b <= bmax; ++b)
+        Z[b - bmin] = or_location_map(I, M, N, b, L);
+    free(L);
+}
+
+/* Eq. for the optimal b: the b maximising b * Z_b / (M N), first on ties. */
+int or_select_b(const int64_t *Z, int bmin, int bmax)
+{
+    int best = bmin;
+    for (int b = bmin + 1; b <= bmax; ++b)
+        if ((int64_t)b * Z[b - bmin] > (int64_t)best * Z[best - bmin])
+            best = b;
+    return best;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Block rotation (Sec. III-A "Rotation and image encryption", rotation       */
+/* equation; decoding: Sec. III-A decoding with K1, de-rotation equation).   */
+/* ------------------------------------------------------------------------ */
+
+int or_max_level(int32_t M, int32_t N)
+{
+    int32_t m = M < N ? M : N;
+    int n = 0;
+    while (((int64_t)2 << n) <= m) ++n;   /* largest n with 2^n <= min(M,N) */
+    return n;
+}
+
+/* Rotation code of the full block (C1, C2) of side 2^m: (sum of s) mod 4. */
+static int block_code(const uint8_t *s, int32_t N, int m, int32_t C1, int32_t C2)
+{
+    int32_t k = (int32_t)1 << m;
+    uint64_t sum = 0;
+    for (int32_t a = 0; a < k; ++a)
+        for (int32_t c = 0; c < k; ++c)
+            sum += s[((int64_t)C1 * k + a) * N + (int64_t)C2 * k + c];
+    return (int)(sum % 4);
+}
+
+/* One level: every full 2^m block of X (M x N) turned `turns(code)` quarter
+ * turns counter-clockwise, written into a fresh copy of the image. */
+static void rotate_level(uint8_t *X, int32_t M, int32_t N, const uint8_t *s, int m, int inverse)
+{
+    int32_t k = (int32_t)1 << m;
+    size_t bytes = (size_t)M * (size_t)N;
+    uint8_t *next = (uint8_t *)malloc(bytes + 1);
+    uint8_t *blk = (uint8_t *)malloc((size_t)k * (size_t)k);
+    uint8_t *tmp = (uint8_t *)malloc((size_t)k * (size_t)k);
+    memcpy(next, X, bytes);
+    for (int32_t C1 = 0; C1 < M / k; ++C1) {
+        for (int32_t C2 = 0; C2 < N / k; ++C2) {
+            int r = block_code(s, N, m, C1, C2);
+            int turns = inverse ? (4 - r) % 4 : r;
+            for (int32_t a = 0; a < k; ++a)
+                for (int32_t c = 0; c < k; ++c)
+                    blk[a * k + c] = X[((int64_t)C1 * k + a) * N + (int64_t)C2 * k + c];
+            for (int t = 0; t < turns; ++t) {
+                for (int32_t a = 0; a < k; ++a)
+                    for (int32_t c = 0; c < k; ++c)
+                        tmp[a * k + c] = blk[c * k + (k - 1 - a)];
+                memcpy(blk, tmp, (size_t)k * (size_t)k);
+            }
+            for (int32_t a = 0; a < k; ++a)
+                for (int32_t c = 0; c < k; ++c)
+                    next[((int64_t)C1 * k + a) * N + (int64_t)C2 * k + c] = blk[a * k + c];
+        }
+    }
+    memcpy(X, next, bytes);
+    free(next); free(blk); free(tmp);
+}
+
+/* Encoding: levels min_level..n ascending.  Decoding: n..min_level with the
+ * opposite turn. */
+void or_rotate(uint8_t *X, int32_t M, int32_t N, const uint8_t *s, int min_level, int inverse)
+{
+    int n = or_max_level(M, N);
+    if (!inverse) {
+        for (int m = min_level; m <= n; ++m) rotate_level(X, M, N, s, m, 0);
+    } else {
+        for (int m = n; m >= min_level; --m) rotate_level(X, M, N, s, m, 1);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* EMR-RDHEI                                                                 */
+/* ------------------------------------------------------------------------ */
+
+typedef struct or_meta {
+    int32_t b;
+    int32_t min_level;
+    int32_t max_level;
+    int32_t pad;
+    int64_t redundant;
+    int64_t capacity_bits;
+} or_meta;
+
+/* Encoding phase (Sec. III-A): location map for the optimal b in [2,7],
+ * rotation of I and l with K1's keystream, XOR encryption, and the rotated
+ * map written into the LSB plane. */
+void or_emr_encrypt(const uint8_t *I, int32_t M, int32_t N, uint64_t k1, uint8_t *Ie, or_meta *meta)
+{
+    size_t MN = (size_t)M * (size_t)N;
+    int64_t Z[6];
+    or_redundancy_counts(I, M, N, 2, 7, Z);
+    int b = or_select_b(Z, 2, 7);
+    uint8_t *l = (uint8_t *)malloc(MN + 1);
+    or_location_map(I, M, N, b, l);
+
+    uint8_t *s = (uint8_t *)malloc(MN + 1);
+    or_keystream(k1, 1, 0, MN, s);
+
+    uint8_t *Irot = (uint8_t *)malloc(MN + 1);
+    memcpy(Irot, I, MN);
+    or_rotate(Irot, M, N, s, 1, 0);
+    or_rotate(l, M, N, s, 1, 0);
+
+    for (size_t p = 0; p < MN; ++p) {
+        uint8_t enc = (uint8_t)(s[p] ^ Irot[p]);
+        Ie[p] = (uint8_t)((enc & 0xFE) | (l[p] & 1));
+    }
+    meta->b = b;
+    meta->min_level = 1;
+    meta->max_level = or_max_level(M, N);
+    meta->redundant = Z[b - 2];
+    meta->capacity_bits = (int64_t)b * Z[b - 2];
+    free(l); free(s); free(Irot);
+}
+
+static int get_bit(const uint8_t *bytes, int64_t t) { return (bytes[t >> 3] >> (7 - (t & 7))) & 1; }
+static void put_bit(uint8_t *bytes, int64_t t, int v)
+{
+    if (v) bytes[t >> 3] |= (uint8_t)(0x80 >> (t & 7));
+    else   bytes[t >> 3] &= (uint8_t)~(0x80 >> (t & 7));
+}
+
+/* Data hiding (Sec. III-A "Data hiding phase" for EMR, Sec. III-B for LMR):
+ * the message is encrypted with K2's stream and written into the replaceable
+ * bits (top `nrep` bits below `top`) of every pixel that the rotated location
+ * map marks 0, in raster order, using a running bit counter.  `lmap` is the
+ * rotated location map (1 byte per pixel).  Returns the number of bits
+ * written, or -1 if the message does not fit. */
+int64_t or_hide(uint8_t *X, int32_t M, int32_t N, const uint8_t *lmap, int top, int nrep,
+                const uint8_t *msg, int64_t nbits, uint64_t k2)
+{
+    size_t MN = (size_t)M * (size_t)N;
+    int64_t cap = 0;
+    for (size_t p = 0; p < MN; ++p) cap += (lmap[p] == 0) ? nrep : 0;
+    if (nbits > cap) return -1;
+    int64_t nbytes = (nbits + 7) / 8;
+    uint8_t *ks = (uint8_t *)malloc((size_t)nbytes + 1);
+    or_keystream(k2, 2, 0, (uint64_t)nbytes, ks);
+    int64_t t = 0;
+    for (size_t p = 0; p < MN && t < nbits; ++p) {
+        if (lmap[p] != 0) continue;
+        for (int u = 0; u < nrep && t < nbits; ++u, ++t) {
+            int bit = get_bit(msg, t) ^ get_bit(ks, t);
+            int pos = top - u;
+            X[p] = (uint8_t)((X[p] & ~(1u << pos)) | ((unsigned)bit << pos));
+        }
+    }
+    free(ks);
+    return t;
+}
+
+/* Extraction (Sec. III-A decoding with K2): concatenate the replaceable bits
+ * of the pixels marked 0, raster order, and decrypt with K2's stream. */
+int64_t or_reveal(const uint8_t *X, int32_t M, int32_t N, const uint8_t *lmap, int top, int nrep,
+                  uint8_t *msg, int64_t nbits, uint64_t k2)
+{
+    size_t MN = (size_t)M * (size_t)N;
+    int64_t nbytes = (nbits + 7) / 8;
+    uint8_t *ks = (uint8_t *)malloc((size_t)nbytes + 1);
+    or_keystream(k2, 2, 0, (uint64_t)nbytes, ks);
+    memset(msg, 0, (size_t)nbytes);
+    int64_t t = 0;
+    for (size_t p = 0; p < MN && t < nbits; ++p) {
+        if (lmap[p] != 0) continue;
+        for (int u = 0; u < nrep && t < nbits; ++u, ++t) {
+            int bit = (X[p] >> (top - u)) & 1;
+            put_bit(msg, t, bit ^ get_bit(ks, t));
+        }
+    }
+    free(ks);
+    return t;
+}
+
+/* EMR data hiding: the rotated map is the LSB plane of I_e; b MSBs replaced. */
+int64_t or_emr_embed(uint8_t *Ie, int32_t M, int32_t N, int b, const uint8_t *msg, int64_t nbits, uint64_t k2)
+{
+    size_t MN = (size_t)M * (size_t)N;
+    uint8_t *l = (uint8_t *)malloc(MN + 1);
+    for (size_t p = 0; p < MN; ++p) l[p] = Ie[p] & 1;
+    int64_t r = or_hide(Ie, M, N, l, 7, b, msg, nbits, k2);
+    free(l);
+    return r;
+}
+
+int64_t or_emr_extract(const uint8_t *Ie, int32_t M, int32_t N, int b, uint8_t *msg, int64_t nbits, uint64_t k2)
+{
+    size_t MN = (size_t)M * (size_t)N;
+    uint8_t *l = (uint8_t *)malloc(MN + 1);
+    for (size_t p = 0; p < MN; ++p) l[p] = Ie[p] & 1;
+    int64_t r = or_reveal(Ie, M, N, l, 7, b, msg, nbits, k2);
+    free(l);
+    return r;
+}
+
+/* Recovery glide (Sec. III-A decoding with K1, last paragraph): omega starts
+ * from column 0 and keeps the replaceable bits of the last pixel marked 1;
+ * every pixel marked 0 takes them.  `mask` selects the replaceable bits. */
+static void recovery_glide(uint8_t *D, const uint8_t *l, int32_t M, int32_t N, uint8_t mask)
+{
+    for (int32_t i = 0; i < M; ++i) {
+        uint8_t omega = D[(int64_t)i * N] & mask;
+        for (int32_t j = 1; j < N; ++j) {
+            int64_t p = (int64_t)i * N + j;
+            if (l[p] == 1) omega = D[p] & mask;
+            else D[p] = (uint8_t)((D[p] & (uint8_t)~mask) | omega);
+        }
+    }
+}
+
+/* EMR image recovery: l from the LSBs, XOR decryption, de-rotation of the
+ * decrypted image and the map in descending level order, then the glide. */
+void or_emr_recover(const uint8_t *Ie, int32_t M, int32_t N, int b, uint64_t k1, uint8_t *out)
+{
+    size_t MN = (size_t)M * (size_t)N;
+    uint8_t *s = (uint8_t *)malloc(MN + 1);
+    uint8_t *l = (uint8_t *)malloc(MN + 1);
+    or_keystream(k1, 1, 0, MN, s);
+    for (size_t p = 0; p < MN; ++p) {
+        l[p] = Ie[p] & 1;
+        out[p] = (uint8_t)(Ie[p] ^ s[p]);
+    }
+    or_rotate(out, M, N, s, 1, 1);
+    or_rotate(l, M, N, s, 1, 1);
+    recovery_glide(out, l, M, N, (uint8_t)(0xFF << (8 - b)));
+    free(s); free(l);
+}
+
+/* ------------------------------------------------------------------------ */
+/* LMR-RDHEI (Sec. III-B).  The map compression is an external step here:    */
+/* the caller hands in the compressed stream; this file never compresses.    */
+/* ------------------------------------------------------------------------ */
+
+/* Maps for LMR with a given b (b in [2,8]) and min_level: the rotated
+ * location map and the rotated first-MSB map eta = (I AND 128) mod 127, one
+ * byte per pixel each. */
+void or_lmr_rotated_maps(const uint8_t *I, int32_t M, int32_t N, int b, int min_level, uint64_t k1,
+                         uint8_t *l_rot, uint8_t *eta_rot)
+{
+    size_t MN = (size_t)M * (size_t)N;
+    uint8_t *s = (uint8_t *)malloc(MN + 1);
+    or_keystream(k1, 1, 0, MN, s);
+    or_location_map(I, M, N, b, l_rot);
+    for (size_t p = 0; p < MN; ++p) eta_rot[p] = (uint8_t)((I[p] & 128) % 127);
+    or_rotate(l_rot, M, N, s, min_level, 0);
+    or_rotate(eta_rot, M, N, s, min_level, 0);
+    free(s);
+}
+
+/* LMR encryption with a given stream for the first-MSB plane: rotate I,
+ * XOR with s, then bit 7 of pixel p (raster order) := stream bit p for
+ * p < stream_bits. */
+void or_lmr_encrypt(const uint8_t *I, int32_t M, int32_t N, int min_level, uint64_t k1,
+                    const uint8_t *stream, int64_t stream_bits, uint8_t *Ie)
+{
+    size_t MN = (size_t)M * (size_t)N;
+    uint8_t *s = (uint8_t *)malloc(MN + 1);
+    or_keystream(k1, 1, 0, MN, s);
+    memcpy(Ie, I, MN);
+    or_rotate(Ie, M, N, s, min_level, 0);
+    for (size_t p = 0; p < MN; ++p) Ie[p] = (uint8_t)(Ie[p] ^ s[p]);
+    for (int64_t p = 0; p < stream_bits && p < (int64_t)MN; ++p)
+        Ie[p] = (uint8_t)((Ie[p] & 0x7F) | (get_bit(stream, p) << 7));
+    free(s);
+}
+
+/* LMR data hiding / extraction: (b-1) bits at bits 6..8-b of every pixel the
+ * (decompressed, rotated) location map marks 0. */
+int64_t or_lmr_embed(uint8_t *Ie, int32_t M, int32_t N, int b, const uint8_t *l_rot,
+                     const uint8_t *msg, int64_t nbits, uint64_t k2)
+{
+    return or_hide(Ie, M, N, l_rot, 6, b - 1, msg, nbits, k2);
+}
+
+int64_t or_lmr_extract(const uint8_t *Ie, int32_t M, int32_t N, int b, const uint8_t *l_rot,
+                       uint8_t *msg, int64_t nbits, uint64_t k2)
+{
+    return or_reveal(Ie, M, N, l_rot, 6, b - 1, msg, nbits, k2);
+}
+
+/* LMR recovery (Sec. III-B decoding with K1): XOR decryption, de-rotation of
+ * the image and both maps, bit 7 from eta, then the glide over bits
+ * 6..8-b guided by l. */
+void or_lmr_recover(const uint8_t *Ie, int32_t M, int32_t N, int b, int min_level, uint64_t k1,
+                    const uint8_t *l_rot, const uint8_t *eta_rot, uint8_t *out)
+{
+    size_t MN = (size_t)M * (size_t)N;
+    uint8_t *s = (uint8_t *)malloc(MN + 1);
+    uint8_t *l = (uint8_t *)malloc(MN + 1);
+    uint8_t *eta = (uint8_t *)malloc(MN + 1);
+    or_keystream(k1, 1, 0, MN, s);
+    memcpy(l, l_rot, MN);
+    memcpy(eta, eta_rot, MN);
+    for (size_t p = 0; p < MN; ++p) out[p] = (uint8_t)(Ie[p] ^ s[p]);
+    or_rotate(out, M, N, s, min_level, 1);
+    or_rotate(l, M, N, s, min_level, 1);
+    or_rotate(eta, M, N, s, min_level, 1);
+    for (size_t p = 0; p < MN; ++p) out[p] = (uint8_t)((out[p] & 0x7F) | ((eta[p] & 1) << 7));
+    uint8_t mask = (uint8_t)((0xFF << (8 - b)) & 0x7F);
+    recovery_glide(out, l, M, N, mask);
+    free(s); free(l); free(eta);
+}

@@ -1,0 +1,179 @@
+"""Pins of the CPU oracle against facts fixed outside the oracle itself.
+
+Each test names the passage of arXiv 2302.07992 (or the external definition)
+it pins.  The oracle is test infrastructure; these tests are what make it
+trustworthy before any GPU result is compared with it.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2302_07992_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return [ln.rstrip("\n") for ln in f if ln.strip() and not ln.startswith("#")]
+
+
+# ---------------------------------------------------------------- keystream
+def test_philox_known_answers():
+    """Philox4x32-10 against the published known-answer vectors (SC'11)."""
+    for ln in _read_golden("philox4x32_10_kat.txt"):
+        v = [int(t, 16) for t in ln.split()]
+        got = O.philox4x32_10(v[0:4], v[4:6])
+        assert [int(x) for x in got] == v[6:10]
+
+
+def test_keystream_byte_layout():
+    """Byte idx of a stream is little-endian byte idx%16 of block idx/16
+    with counter (idx/16, 0, domain, 0) -- the layout the library header fixes."""
+    key = 0x0123456789ABCDEF
+    ks = O.keystream(key, 1, 0, 64)
+    for blk in range(4):
+        w = O.philox4x32_10([blk, 0, 1, 0], [key & 0xFFFFFFFF, key >> 32])
+        expect = np.frombuffer(w.astype("<u4").tobytes(), dtype=np.uint8)
+        assert np.array_equal(ks[16 * blk:16 * blk + 16], expect)
+    # an offset window is the same stream
+    assert np.array_equal(O.keystream(key, 1, 5, 40), ks[5:45])
+    # domains are distinct streams
+    assert not np.array_equal(O.keystream(key, 2, 0, 64), ks)
+
+
+# ----------------------------------------------------------- location maps
+def test_glide_hand_worked_rows():
+    """Rows labelled by hand from the Omega glide (Sec. III-A)."""
+    for ln in _read_golden("glide_rows.txt"):
+        b_s, vals_s, labels_s, z_s = [t.strip() for t in ln.split("|")]
+        row = np.array([[int(t, 16) for t in vals_s.split()]], dtype=np.uint8)
+        L, z = O.location_map(row, int(b_s))
+        assert L[0].tolist() == [int(t) for t in labels_s.split()], ln
+        assert z == int(z_s)
+
+
+@pytest.mark.parametrize("b", range(2, 9))
+def test_glide_equals_left_neighbour_rule_all_pairs(b):
+    """Every pair of pixel values: the second pixel of a two-pixel row is
+    redundant exactly when its b MSBs equal the first pixel's."""
+    a, c = np.meshgrid(np.arange(256), np.arange(256), indexing="ij")
+    img = np.stack([a.ravel(), c.ravel()], 1).astype(np.uint8)   # 65536 rows of 2
+    L, z = O.location_map(img, b)
+    expect = ((img[:, 0] >> (8 - b)) != (img[:, 1] >> (8 - b))).astype(np.uint8)
+    assert np.array_equal(L[:, 1], expect)
+    assert np.all(L[:, 0] == 1)
+    assert z == int((expect == 0).sum())
+
+
+def test_glide_long_rows_match_leading_bits_count():
+    """Rows of any length: the glide labels pixel j (j >= 1) redundant exactly
+    when the number of leading bits shared with pixel j-1 is at least b
+    (the tracker always holds the b MSBs of the previous pixel)."""
+    rng = np.random.default_rng(7)
+    for trial in range(40):
+        M, N = rng.integers(1, 9), rng.integers(1, 40)
+        base = rng.integers(0, 256, (M, N))
+        img = np.clip(base // rng.integers(1, 64) * rng.integers(1, 64), 0, 255).astype(np.uint8)
+        x = img[:, 1:] ^ img[:, :-1]
+        lead = np.array([8 if v == 0 else 8 - int(v).bit_length() for v in x.ravel()]).reshape(x.shape)
+        for b in range(2, 9):
+            L, z = O.location_map(img, b)
+            assert np.all(L[:, 0] == 1)
+            assert np.array_equal(L[:, 1:], (lead < b).astype(np.uint8))
+            assert z == int((lead >= b).sum())
+
+
+def test_select_b_ties_and_argmax():
+    """Optimal-b equation: argmax of b*Z_b, first (smallest) b on ties."""
+    assert O.select_b([10, 0, 0, 0, 0, 0], 2) == 2
+    assert O.select_b([30, 20, 15, 12, 10, 0], 2) == 2        # 60 60 60 60 60: tie -> 2
+    assert O.select_b([30, 20, 16, 12, 10, 0], 2) == 4        # 60 60 64 60 60
+    assert O.select_b([0, 0, 0, 0, 0, 1], 2) == 7
+    assert O.select_b([0, 0, 0, 0, 0, 0], 2) == 2             # no redundancy
+    assert O.select_b([8, 4, 2, 2, 2, 2, 2], 2) == 2          # 16 12 8 10 12 14 16: tie 2/8 -> 2
+    assert O.select_b([8, 4, 2, 2, 2, 2, 3], 2) == 8          # 16 12 8 10 12 14 24
+
+
+# ---------------------------------------------------------------- rotation
+def _read_matrices(name):
+    lines = _read_golden(name)
+    out, cur, key = {}, [], None
+    for ln in lines:
+        if ln[0].isalpha():
+            if key:
+                out[key] = np.array(cur, dtype=np.uint8)
+            key, cur = ln.strip(), []
+        else:
+            cur.append([int(t) for t in ln.split()])
+    out[key] = np.array(cur, dtype=np.uint8)
+    return out
+
+
+def test_rotation_hand_worked_4x4():
+    """Rotation equation (Sec. III-A): hand-worked levels 2^1 and 2^2."""
+    g = _read_matrices("rotation_4x4.txt")
+    n = O.max_level(4, 4)
+    assert n == 2
+    # both levels from the input, then level 2 alone from the level-1 result
+    full = O.rotate(g["input"], g["s"], min_level=1)
+    assert np.array_equal(full, g["after_level_2"])
+    lvl2_only = O.rotate(g["after_level_1"], g["s"], min_level=2)
+    assert np.array_equal(lvl2_only, g["after_level_2"])
+    back = O.rotate(full, g["s"], min_level=1, inverse=True)
+    assert np.array_equal(back, g["input"])
+
+
+def _np_rotate_reference(X, s, min_level):
+    """Same definition built from numpy's rot90 (counter-clockwise)."""
+    X = X.copy()
+    M, N = X.shape
+    n = int(np.floor(np.log2(min(M, N)))) if min(M, N) >= 1 else 0
+    for m in range(min_level, n + 1):
+        k = 1 << m
+        for C1 in range(M // k):
+            for C2 in range(N // k):
+                r = int(s[C1 * k:(C1 + 1) * k, C2 * k:(C2 + 1) * k].astype(np.int64).sum()) % 4
+                X[C1 * k:(C1 + 1) * k, C2 * k:(C2 + 1) * k] = np.rot90(X[C1 * k:(C1 + 1) * k, C2 * k:(C2 + 1) * k], r)
+    return X
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (2, 2), (3, 5), (8, 8), (7, 12), (16, 9), (13, 13), (16, 16)])
+def test_rotation_against_rot90_and_bijective(shape):
+    """Rotation vs numpy's rot90 block by block; bijective; inverse exact."""
+    M, N = shape
+    rng = np.random.default_rng(M * 100 + N)
+    for min_level in (1, 2, 4):
+        s = rng.integers(0, 256, (M, N)).astype(np.uint8)
+        if M * N <= 256:
+            X = np.arange(M * N, dtype=np.int64).reshape(M, N).astype(np.uint8)
+        else:
+            X = rng.integers(0, 256, (M, N)).astype(np.uint8)
+        Y = O.rotate(X, s, min_level=min_level)
+        assert np.array_equal(Y, _np_rotate_reference(X, s, min_level))
+        if M * N <= 256:
+            assert sorted(Y.ravel().tolist()) == list(range(M * N))
+        assert np.array_equal(O.rotate(Y, s, min_level=min_level, inverse=True), X)
+
+
+def test_rotation_keeps_partial_blocks():
+    """Pixels outside every full block stay where they are (Sec. III-A: the
+    remainder that does not divide into blocks is retained)."""
+    rng = np.random.default_rng(3)
+    M, N = 5, 7           # n = 2; rows 4 and column 6 are in no 2x2 block
+    s = rng.integers(0, 256, (M, N)).astype(np.uint8)
+    X = rng.integers(0, 256, (M, N)).astype(np.uint8)
+    Y = O.rotate(X, s)
+    assert np.array_equal(Y[4, :], X[4, :])
+    assert np.array_equal(Y[:, 6], X[:, 6])
+
+
+def test_max_level():
+    """n = floor(log2 min(M, N)); 512 x 512 gives 2^9 blocks (Sec. IV)."""
+    assert O.max_level(512, 512) == 9
+    assert O.max_level(512, 1024) == 9
+    assert O.max_level(1, 7) == 0
+    assert O.max_level(3, 3) == 1
+    assert O.max_level(16384, 16384) == 14
