@@ -14,7 +14,11 @@
  *     is taken when M and N are multiples of 64 and buffers are 16-byte
  *     aligned; every other shape runs a per-pixel path with identical output.
  *   - Messages are bit strings packed MSB-first into bytes (bit t is bit
- *     7 - t%8 of byte t/8), in DEVICE memory owned by the caller.
+ *     7 - t%8 of byte t/8), in DEVICE memory owned by the caller, 16-byte
+ *     aligned and padded to a multiple of 16 bytes (at least
+ *     ceil(nbits/128)*16 bytes): the kernels move whole 16-byte blocks.
+ *   - The method (EMR or LMR) and the image size are public: the data hider
+ *     and the recipient pass them to every call along with the meta record.
  *   - `stream` is a hipStream_t (NULL = the default stream).  Calls are
  *     stream-ordered and return before the GPU work finishes, except where a
  *     function says it synchronises (the LMR entry points, which run a host
@@ -99,22 +103,24 @@ int rdhei_encrypt(rdhei_ctx *ctx, const uint8_t *d_img, uint8_t *d_enc, int32_t 
  * replaceable bits of the redundant pixels (EMR: bits 7..8-b of pixels with
  * LSB 0; LMR: bits 6..8-b of pixels the decompressed map marks 0).  nbits < 0
  * means "the full capacity".  Unused replaceable bits are left unchanged.
+ * A message longer than the capacity sets d_meta->status = RDHEI_ECAPACITY
+ * and leaves the image unchanged.
  * EMR: asynchronous; LMR: synchronises (host map decompression). */
-int rdhei_embed(rdhei_ctx *ctx, uint8_t *d_marked, const rdhei_meta *d_meta,
-                const uint8_t *d_msg, int64_t nbits, uint64_t k2, void *stream);
+int rdhei_embed(rdhei_ctx *ctx, uint8_t *d_marked, int32_t M, int32_t N, int32_t method,
+                rdhei_meta *d_meta, const uint8_t *d_msg, int64_t nbits, uint64_t k2, void *stream);
 
-/* Recipient with K2 (Sec. III-A/B decoding with K2).  Writes ceil(nbits/8)
- * bytes to d_msg (trailing bits of the last byte zero); nbits < 0 = capacity
- * (d_msg must then hold ceil(capacity/8) bytes). */
-int rdhei_extract(rdhei_ctx *ctx, const uint8_t *d_marked, const rdhei_meta *d_meta,
-                  uint8_t *d_msg, int64_t nbits, uint64_t k2, void *stream);
+/* Recipient with K2 (Sec. III-A/B decoding with K2).  Writes the first nbits
+ * message bits to d_msg (nbits < 0: the capacity), zero-filled to a whole
+ * number of 32-bit words; d_msg must hold ceil(nbits/128)*16 bytes. */
+int rdhei_extract(rdhei_ctx *ctx, const uint8_t *d_marked, int32_t M, int32_t N, int32_t method,
+                  rdhei_meta *d_meta, uint8_t *d_msg, int64_t nbits, uint64_t k2, void *stream);
 
 /* Recipient with K1 (Sec. III-A/B decoding with K1).  Writes the recovered
  * image to d_img (M x N; must not alias d_marked).  EMR output differs from
  * the original only in bit 0 (expected PSNR about 51.14 dB); LMR output is
  * exact.  EMR: asynchronous; LMR: synchronises. */
-int rdhei_recover(rdhei_ctx *ctx, const uint8_t *d_marked, const rdhei_meta *d_meta,
-                  uint8_t *d_img, uint64_t k1, void *stream);
+int rdhei_recover(rdhei_ctx *ctx, const uint8_t *d_marked, int32_t M, int32_t N, int32_t method,
+                  rdhei_meta *d_meta, uint8_t *d_img, uint64_t k1, void *stream);
 
 /* ---- Batches: many independent images per launch ------------------------ */
 
@@ -135,21 +141,40 @@ typedef struct rdhei_job {
     uint64_t key;
     int64_t nbits;           /* EMBED/EXTRACT: bits, or < 0 for the capacity   */
     int32_t height, width;
+    int32_t method;          /* plans run EMR only (RDHEI_EMR)                 */
+    int32_t reserved;
 } rdhei_job;
 
-/* Build a reusable plan for one EMR op over `njobs` images (host array, copied).
- * The plan owns its device job table and workspace; its first run captures the
- * launches in a hipGraph that later runs replay.  Plans are independent of
- * each other and of their context's single-image workspace. */
-int  rdhei_plan_create(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t njobs, rdhei_plan **out);
-int  rdhei_plan_run(rdhei_plan *plan, void *stream);
-/* Same launches as rdhei_plan_run, issued directly (no graph). */
-int  rdhei_plan_run_eager(rdhei_plan *plan, void *stream);
-void rdhei_plan_destroy(rdhei_plan *plan);
+/* Plan flags. */
+#define RDHEI_PLAN_GRAPH     0   /* batched launches, captured once in a hipGraph */
+#define RDHEI_PLAN_EAGER     1   /* batched launches issued directly             */
+#define RDHEI_PLAN_PER_IMAGE 2   /* the same kernels launched image by image      */
 
-/* Per-image launches of the same op, one image after another on `stream`
- * (the per-image baseline the batched plan is compared with). */
-int  rdhei_run_each(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t njobs, void *stream);
+/* Build a reusable plan for one EMR op over `njobs` images (host array,
+ * copied).  The plan owns its device job table and workspace.  A GRAPH plan
+ * captures its launches on the first run and replays them afterwards; the
+ * job pointers are fixed at creation.  Plans are independent of each other
+ * and of their context's single-image workspace. */
+int  rdhei_plan_create(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t njobs, int32_t flags,
+                       rdhei_plan **out);
+int  rdhei_plan_run(rdhei_plan *plan, void *stream);
+void rdhei_plan_destroy(rdhei_plan *plan);
+/* Workgroup cap of the plan's grid-stride launches (0 = one workgroup per
+ * work unit), e.g. as chosen by the autotuner. */
+int  rdhei_plan_set_grid(rdhei_plan *plan, int32_t max_workgroups);
+
+/* A plan's batched sequence is a list of stages (kernels or kernel groups in
+ * the paper's phase order).  These run or name one stage on its own, for
+ * profiling; a stage reads what the earlier stages of a full run left in the
+ * plan's workspace. */
+int         rdhei_plan_stage_count(rdhei_plan *plan);
+const char *rdhei_plan_stage_name(rdhei_plan *plan, int32_t k);
+int         rdhei_plan_run_stage(rdhei_plan *plan, int32_t k, void *stream);
+
+/* Context options. */
+#define RDHEI_OPT_PER_PIXEL 1    /* 1: force the per-pixel path for every shape  */
+#define RDHEI_OPT_MAX_GRID  2    /* workgroup cap of grid-stride launches         */
+int rdhei_ctx_set_option(rdhei_ctx *ctx, int32_t option, int64_t value);
 
 /* ---- LMR host stage: bi-level map coder (Sec. III-B, map compression) ---- */
 /* The paper compresses the rotated first-MSB map and the rotated location map

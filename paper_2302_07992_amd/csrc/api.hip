@@ -1,0 +1,745 @@
+// Host side of librdhei: argument checks, job tables, workspace layout, the
+// launch sequence of every stage, plans (hipGraph capture/replay), and the
+// LMR host stages.
+#include <algorithm>
+#include <functional>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace rdhei {
+int lmr_compress_impl(const uint8_t *eta_bits, const uint8_t *l_bits, int32_t M, int32_t N, uint8_t *stream,
+                      int64_t capacity_bytes, int64_t *stream_bits);
+int lmr_decompress_impl(const uint8_t *stream, int64_t stream_bytes, int32_t M, int32_t N, uint8_t *eta_bits,
+                        uint8_t *l_bits);
+}  // namespace rdhei
+
+using namespace rdhei;
+
+namespace {
+
+thread_local std::string g_err;
+
+void set_err(const char *what, hipError_t e) {
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    g_err = buf;
+}
+
+#define HIPCHK(call)                                      \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) {                           \
+            set_err(#call, e_);                           \
+            return RDHEI_EDEVICE;                         \
+        }                                                 \
+    } while (0)
+
+// Growable device buffer.
+struct DevBuf {
+    uint8_t *p = nullptr;
+    size_t n = 0;
+    int need(size_t bytes) {
+        if (bytes <= n) return RDHEI_OK;
+        if (p) {
+            (void)hipDeviceSynchronize();
+            (void)hipFree(p);
+            p = nullptr;
+            n = 0;
+        }
+        size_t want = std::max<size_t>(bytes, 4096);
+        hipError_t e = hipMalloc(&p, want);
+        if (e != hipSuccess) {
+            set_err("hipMalloc", e);
+            p = nullptr;
+            return RDHEI_ENOMEM;
+        }
+        n = want;
+        return RDHEI_OK;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+int floor_log2_min(int32_t M, int32_t N) {
+    int64_t m = std::min(M, N);
+    int n = 0;
+    while (((int64_t)2 << n) <= m) ++n;
+    return n;
+}
+
+// Bytes of the fast path's tile-sum pyramid (levels kTileLog..n).
+uint64_t pyr_bytes(int32_t M, int32_t N, int n) {
+    uint64_t b = 0;
+    for (int k = kTileLog; k <= n; ++k) b += (uint64_t)(M >> k) * (uint64_t)(N >> k);
+    return b;
+}
+
+struct Layout {
+    std::vector<Job> jobs;
+    std::vector<uint32_t> ujob[UNIT_KINDS];   // job index of every work unit (batches)
+    std::vector<int> per_pixel;        // jobs on the per-pixel path
+    uint64_t ws_bytes = 0;
+    uint32_t units[UNIT_KINDS] = {0, 0, 0, 0};
+    bool multiseg = false;
+    int op = 0;
+    int method = RDHEI_EMR;
+};
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+// Build the device job table and workspace layout of one op over a batch.
+int make_layout(int op, const rdhei_job *in, int n, bool force_per_pixel, Layout &L) {
+    L = Layout();
+    L.op = op;
+    if (n < 1) return RDHEI_EINVAL;
+    L.method = in[0].method;
+    uint64_t ws = 0;
+    for (int i = 0; i < n; ++i) {
+        const rdhei_job &q = in[i];
+        if (q.height < 1 || q.width < 1) return RDHEI_EINVAL;
+        if ((int64_t)q.height * q.width > ((int64_t)1 << 31)) return RDHEI_EINVAL;
+        if (q.method != RDHEI_EMR && q.method != RDHEI_LMR) return RDHEI_EINVAL;
+        if (q.method != L.method) return RDHEI_EINVAL;
+        if (!q.meta) return RDHEI_EINVAL;
+        switch (op) {
+            case RDHEI_OP_ENCRYPT: if (!q.in || !q.out || q.in == q.out) return RDHEI_EINVAL; break;
+            case RDHEI_OP_EMBED: if (!q.out || !q.msg || !aligned16(q.msg)) return RDHEI_EINVAL; break;
+            case RDHEI_OP_EXTRACT: if (!q.in || !q.msg || !aligned16(q.msg)) return RDHEI_EINVAL; break;
+            case RDHEI_OP_RECOVER: if (!q.in || !q.out || q.in == q.out) return RDHEI_EINVAL; break;
+            default: return RDHEI_EINVAL;
+        }
+        Job J;
+        memset(&J, 0, sizeof J);
+        J.in = op == RDHEI_OP_EMBED ? q.out : q.in;
+        J.out = q.out;
+        J.msg = q.msg;
+        J.meta = q.meta;
+        J.key = q.key;
+        J.nbits = q.nbits;
+        J.M = q.height;
+        J.N = q.width;
+        J.method = q.method;
+        J.min_level = q.method == RDHEI_EMR ? 1 : 4;
+        J.max_level = floor_log2_min(q.height, q.width);
+        const uint64_t MN = (uint64_t)q.height * (uint64_t)q.width;
+        const bool rot = op == RDHEI_OP_ENCRYPT || op == RDHEI_OP_RECOVER;
+        J.fast = rot && !force_per_pixel && q.height % kTile == 0 && q.width % kTile == 0 && aligned16(J.in) &&
+                 aligned16(J.out) ? 1 : 0;
+        if (J.fast) {
+            J.tiles_x = q.width / kTile;
+            J.tiles_y = q.height / kTile;
+        }
+        J.nseg = (int32_t)((MN + seg_pixels() - 1) / seg_pixels());
+        if (rot) {
+            const uint64_t tiles = (uint64_t)J.tiles_x * J.tiles_y;
+            J.ws_codes = ws;
+            ws = align_up(ws + (J.fast ? tiles * kCodeRecord : generic_code_bytes(J.M, J.N, J.max_level)), 256);
+            J.ws_pyr = ws;
+            ws = align_up(ws + (J.fast ? pyr_bytes(J.M, J.N, J.max_level) : 0), 256);
+            J.ws_stats = ws;
+            ws = align_up(ws + (J.fast ? tiles : 1) * kStatWords * 4 + 64, 256);
+            if (q.method == RDHEI_LMR && !J.fast) {
+                J.ws_bytes = ws;
+                ws = align_up(ws + MN, 256);
+            }
+        } else if (J.nseg > 1) {
+            J.ws_seg = ws;
+            ws = align_up(ws + 8ull * (uint64_t)J.nseg, 256);
+            L.multiseg = true;
+        }
+        const uint32_t cnt[UNIT_KINDS] = {J.fast ? (uint32_t)(J.tiles_x * J.tiles_y) : 0u,
+                                          J.fast ? (uint32_t)J.tiles_y : 0u, (uint32_t)J.nseg, 1u};
+        for (int k = 0; k < UNIT_KINDS; ++k) {
+            J.ubase[k] = L.units[k];
+            J.ucount[k] = cnt[k];
+            L.units[k] += cnt[k];
+        }
+        if (rot && !J.fast) L.per_pixel.push_back(i);
+        if (n > 1)
+            for (int k = 0; k < UNIT_KINDS - 1; ++k) L.ujob[k].insert(L.ujob[k].end(), cnt[k], (uint32_t)i);
+        L.jobs.push_back(J);
+    }
+    L.ws_bytes = std::max<uint64_t>(ws, 256);
+    return RDHEI_OK;
+}
+
+// The launch sequence of an op, as named stages (the paper's phase order).
+struct Stage {
+    const char *name;
+    std::function<void(const Launch &)> fn;
+};
+
+std::vector<Stage> stages_of(const Layout &Ly, const uint32_t *units_in, std::vector<int> pp) {
+    std::vector<Stage> S;
+    const int op = Ly.op;
+    const std::vector<Job> hj = Ly.jobs;
+    uint32_t units[UNIT_KINDS];
+    for (int k = 0; k < UNIT_KINDS; ++k) units[k] = units_in[k];
+    const uint32_t ut = units[UNIT_TILE], ub = units[UNIT_BAND], us = units[UNIT_SEG];
+    const int method = Ly.method;
+    if (op == RDHEI_OP_ENCRYPT) {
+        if (ut) S.push_back({"tile_prep_stats", [=](const Launch &L) { launch_tile_prep(L, ut, true); }});
+        if (!pp.empty())
+            S.push_back({"per_pixel_levels_stats", [=](const Launch &L) {
+                             for (int j : pp) { launch_generic_levels(L, j, hj[j]); launch_generic_stats(L, j, hj[j]); }
+                         }});
+        S.push_back({"finalize_stats", [=](const Launch &L) { launch_finalize(L, true); }});
+        if (ut) S.push_back({"encrypt_tiles", [=](const Launch &L) { launch_encrypt_tiles(L, ut, ENC_EMR); }});
+        if (!pp.empty())
+            S.push_back({"per_pixel_encrypt", [=](const Launch &L) {
+                             for (int j : pp) launch_generic_encrypt(L, j, hj[j], ENC_EMR);
+                         }});
+    } else if (op == RDHEI_OP_RECOVER) {
+        if (ut) S.push_back({"tile_prep", [=](const Launch &L) { launch_tile_prep(L, ut, false); }});
+        if (!pp.empty())
+            S.push_back({"per_pixel_levels", [=](const Launch &L) {
+                             for (int j : pp) launch_generic_levels(L, j, hj[j]);
+                         }});
+        if (ut) S.push_back({"finalize_pyramid", [=](const Launch &L) { launch_finalize(L, false); }});
+        if (ub) S.push_back({"recover_bands", [=](const Launch &L) { launch_recover_bands(L, ub, method); }});
+        if (!pp.empty())
+            S.push_back({"per_pixel_recover", [=](const Launch &L) {
+                             for (int j : pp) launch_generic_recover(L, j, hj[j]);
+                         }});
+    } else if (op == RDHEI_OP_EMBED || op == RDHEI_OP_EXTRACT) {
+        if (Ly.multiseg) {
+            S.push_back({"segment_count", [=](const Launch &L) { launch_seg_count(L, us); }});
+            const int clear = op == RDHEI_OP_EXTRACT ? 1 : 0;
+            S.push_back({"segment_scan", [=](const Launch &L) { launch_seg_scan(L, clear); }});
+        }
+        if (op == RDHEI_OP_EMBED) S.push_back({"embed", [=](const Launch &L) { launch_embed(L, us); }});
+        else S.push_back({"extract", [=](const Launch &L) { launch_extract(L, us); }});
+    }
+    return S;
+}
+
+void issue(const Layout &Ly, const Launch &L, const uint32_t *units, const int *pp, int npp, int) {
+    for (const Stage &s : stages_of(Ly, units, std::vector<int>(pp, pp + npp))) s.fn(L);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------
+struct rdhei_ctx {
+    int device = 0;
+    int per_pixel = 0;
+    int max_grid = 0;
+    DevBuf ws, jobs, scratch;
+    std::vector<uint8_t> h_a, h_b, h_c;
+};
+
+struct rdhei_plan {
+    rdhei_ctx *ctx = nullptr;
+    Layout layout;
+    DevBuf ws, jobs, single;       // single: per-image one-job tables
+    int flags = 0;
+    int max_grid = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<Stage> stages;     // batched sequence (for per-stage runs)
+    Launch base;                   // device tables of the batched sequence
+    std::vector<std::vector<Stage>> per_image;   // PER_IMAGE plans: one sequence per image
+};
+
+namespace {
+
+int set_device(int dev) {
+    HIPCHK(hipSetDevice(dev));
+    return RDHEI_OK;
+}
+
+// Bytes of a layout's device table: jobs, then the unit -> job arrays.
+size_t table_bytes(const Layout &Ly, size_t off[UNIT_KINDS]) {
+    size_t b = align_up(Ly.jobs.size() * sizeof(Job), 256);
+    for (int k = 0; k < UNIT_KINDS; ++k) {
+        off[k] = b;
+        b = align_up(b + Ly.ujob[k].size() * sizeof(uint32_t), 256);
+    }
+    return b;
+}
+
+// Copy the job table and unit tables to `dst` (device) and fill L's pointers.
+int upload_tables(const Layout &Ly, uint8_t *dst, hipStream_t st, bool sync, Launch &L) {
+    size_t off[UNIT_KINDS];
+    table_bytes(Ly, off);
+    if (sync) {
+        HIPCHK(hipMemcpy(dst, Ly.jobs.data(), Ly.jobs.size() * sizeof(Job), hipMemcpyHostToDevice));
+    } else {
+        HIPCHK(hipMemcpyAsync(dst, Ly.jobs.data(), Ly.jobs.size() * sizeof(Job), hipMemcpyHostToDevice, st));
+    }
+    L.jobs = reinterpret_cast<const Job *>(dst);
+    for (int k = 0; k < UNIT_KINDS; ++k) {
+        L.ujob[k] = nullptr;
+        if (Ly.ujob[k].empty()) continue;
+        if (sync) {
+            HIPCHK(hipMemcpy(dst + off[k], Ly.ujob[k].data(), Ly.ujob[k].size() * 4, hipMemcpyHostToDevice));
+        } else {
+            HIPCHK(hipMemcpyAsync(dst + off[k], Ly.ujob[k].data(), Ly.ujob[k].size() * 4, hipMemcpyHostToDevice, st));
+        }
+        L.ujob[k] = reinterpret_cast<const uint32_t *>(dst + off[k]);
+    }
+    return RDHEI_OK;
+}
+
+// Upload a layout's job table into `jobs` and size `ws`; returns the Launch.
+int stage(rdhei_ctx *ctx, const Layout &Ly, DevBuf &jobs, DevBuf &ws, hipStream_t st, Launch &L) {
+    size_t off[UNIT_KINDS];
+    int rc = jobs.need(table_bytes(Ly, off));
+    if (rc) return rc;
+    rc = ws.need(Ly.ws_bytes);
+    if (rc) return rc;
+    rc = upload_tables(Ly, jobs.p, st, false, L);
+    if (rc) return rc;
+    L.njobs = (int32_t)Ly.jobs.size();
+    L.ws = ws.p;
+    L.stream = st;
+    L.max_grid = ctx->max_grid;
+    return RDHEI_OK;
+}
+
+int run_single(rdhei_ctx *ctx, int op, const rdhei_job &job, hipStream_t st) {
+    int rc = set_device(ctx->device);
+    if (rc) return rc;
+    Layout Ly;
+    rc = make_layout(op, &job, 1, ctx->per_pixel != 0, Ly);
+    if (rc) return rc;
+    Launch L;
+    rc = stage(ctx, Ly, ctx->jobs, ctx->ws, st, L);
+    if (rc) return rc;
+    issue(Ly, L, Ly.units, Ly.per_pixel.data(), (int)Ly.per_pixel.size(), 0);
+    HIPCHK(hipGetLastError());
+    return RDHEI_OK;
+}
+
+// ---- LMR (Sec. III-B): host stages around the GPU kernels ----------------------
+
+// Bit 7 of the first `bits` pixels (raster order), packed MSB-first.
+void msb_plane(const uint8_t *img, int64_t bits, std::vector<uint8_t> &out) {
+    out.assign((size_t)((bits + 7) / 8) + 16, 0);
+    for (int64_t p = 0; p < bits; ++p) out[(size_t)(p >> 3)] |= (uint8_t)(((img[p] >> 7) & 1u) << (7 - (p & 7)));
+}
+
+int lmr_encrypt(rdhei_ctx *ctx, const uint8_t *d_img, uint8_t *d_enc, int32_t M, int32_t N, uint64_t k1,
+                rdhei_meta *d_meta, hipStream_t st) {
+    int rc = set_device(ctx->device);
+    if (rc) return rc;
+    rdhei_job q{};
+    q.in = d_img; q.out = d_enc; q.meta = d_meta; q.key = k1; q.nbits = 0;
+    q.height = M; q.width = N; q.method = RDHEI_LMR;
+    Layout Ly;
+    rc = make_layout(RDHEI_OP_ENCRYPT, &q, 1, ctx->per_pixel != 0, Ly);
+    if (rc) return rc;
+    const uint64_t MN = (uint64_t)M * N;
+    const uint64_t plane = align_up((MN + 7) / 8 + 16, 256);
+    // scratch: l plane, eta plane, stream
+    rc = ctx->scratch.need(3 * plane);
+    if (rc) return rc;
+    uint8_t *d_l = ctx->scratch.p, *d_eta = d_l + plane, *d_stream = d_eta + plane;
+    Launch L;
+    rc = stage(ctx, Ly, ctx->jobs, ctx->ws, st, L);
+    if (rc) return rc;
+    const Job J0 = Ly.jobs[0];   // a copy: the candidate loop rewrites Ly.jobs[0]
+    launch_tile_prep(L, Ly.units[UNIT_TILE], true);
+    if (!J0.fast) {
+        launch_generic_levels(L, 0, J0);
+        launch_generic_stats(L, 0, J0);
+    }
+    launch_finalize(L, true);
+    int64_t Z[7];
+    const uint64_t zoff = J0.ws_stats + (uint64_t)(J0.fast ? J0.tiles_x * J0.tiles_y : 1) * kStatWords * 4;
+    HIPCHK(hipMemcpyAsync(Z, ctx->ws.p + zoff, sizeof Z, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    // candidates in order of LMR capacity (b-1)*Z_b, smaller b first on ties
+    std::vector<int> cand;
+    for (int b = 2; b <= 8; ++b) cand.push_back(b);
+    std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) {
+        return (int64_t)(a - 1) * Z[a - 2] > (int64_t)(b - 1) * Z[b - 2];
+    });
+    std::vector<uint8_t> &hl = ctx->h_a, &he = ctx->h_b, &hs = ctx->h_c;
+    hl.assign(plane, 0);
+    he.assign(plane, 0);
+    hs.assign(plane, 0);
+    int chosen = 0;
+    int64_t sbits = 0;
+    for (int b : cand) {
+        Job J = J0;
+        J.fixed_b = b;
+        J.out = d_l;
+        J.msg = d_eta;
+        Ly.jobs[0] = J;
+        HIPCHK(hipMemcpyAsync(ctx->jobs.p, &Ly.jobs[0], sizeof(Job), hipMemcpyHostToDevice, st));
+        if (J.fast) launch_encrypt_tiles(L, Ly.units[UNIT_TILE], ENC_LMR_MAPS);
+        else launch_generic_encrypt(L, 0, J, ENC_LMR_MAPS);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(hl.data(), d_l, (MN + 7) / 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(he.data(), d_eta, (MN + 7) / 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        int64_t bits = 0;
+        const int r = lmr_compress_impl(he.data(), hl.data(), M, N, hs.data(), (int64_t)(MN / 8), &bits);
+        if (r == RDHEI_OK) {
+            chosen = b;
+            sbits = bits;
+            break;
+        }
+        if (r != RDHEI_ENOFIT) return r;
+    }
+    rdhei_meta m{};
+    m.height = M; m.width = N; m.method = RDHEI_LMR; m.min_level = 4; m.max_level = J0.max_level;
+    if (!chosen) {
+        m.status = RDHEI_ENOFIT;
+        HIPCHK(hipMemcpyAsync(d_meta, &m, sizeof m, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return RDHEI_ENOFIT;
+    }
+    m.b = chosen;
+    m.redundant = Z[chosen - 2];
+    m.capacity_bits = (int64_t)(chosen - 1) * Z[chosen - 2];
+    m.map_bits = sbits;
+    m.status = RDHEI_OK;
+    HIPCHK(hipMemcpyAsync(d_meta, &m, sizeof m, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_stream, hs.data(), (size_t)((sbits + 7) / 8), hipMemcpyHostToDevice, st));
+    Job J = J0;
+    J.fixed_b = chosen;
+    J.stream = d_stream;
+    J.stream_bits = sbits;
+    Ly.jobs[0] = J;
+    HIPCHK(hipMemcpyAsync(ctx->jobs.p, &Ly.jobs[0], sizeof(Job), hipMemcpyHostToDevice, st));
+    if (J.fast) launch_encrypt_tiles(L, Ly.units[UNIT_TILE], ENC_LMR);
+    else launch_generic_encrypt(L, 0, J, ENC_LMR);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return RDHEI_OK;
+}
+
+// Decompress the maps of an LMR image into device bit planes (ctx scratch).
+int lmr_maps_to_device(rdhei_ctx *ctx, const uint8_t *d_marked, int32_t M, int32_t N, rdhei_meta *d_meta,
+                       hipStream_t st, rdhei_meta &m, uint8_t *&d_l, uint8_t *&d_eta) {
+    HIPCHK(hipMemcpyAsync(&m, d_meta, sizeof m, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (m.status != RDHEI_OK) return m.status;
+    if (m.method != RDHEI_LMR || m.height != M || m.width != N) return RDHEI_EINVAL;
+    const uint64_t MN = (uint64_t)M * N;
+    if (m.map_bits < 64 || (uint64_t)m.map_bits > MN) return RDHEI_ECORRUPT;
+    const uint64_t plane = align_up((MN + 7) / 8 + 16, 256);
+    int rc = ctx->scratch.need(3 * plane);
+    if (rc) return rc;
+    d_l = ctx->scratch.p;
+    d_eta = d_l + plane;
+    std::vector<uint8_t> head((size_t)m.map_bits);
+    HIPCHK(hipMemcpyAsync(head.data(), d_marked, (size_t)m.map_bits, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<uint8_t> stream;
+    msb_plane(head.data(), m.map_bits, stream);
+    std::vector<uint8_t> &hl = ctx->h_a, &he = ctx->h_b;
+    hl.assign(plane, 0);
+    he.assign(plane, 0);
+    rc = lmr_decompress_impl(stream.data(), (m.map_bits + 7) / 8, M, N, he.data(), hl.data());
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(d_l, hl.data(), plane, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_eta, he.data(), plane, hipMemcpyHostToDevice, st));
+    return RDHEI_OK;
+}
+
+int lmr_stage(rdhei_ctx *ctx, int op, const uint8_t *d_marked, uint8_t *d_out, int32_t M, int32_t N,
+              rdhei_meta *d_meta, uint8_t *d_msg, int64_t nbits, uint64_t key, hipStream_t st) {
+    int rc = set_device(ctx->device);
+    if (rc) return rc;
+    rdhei_meta m;
+    uint8_t *d_l = nullptr, *d_eta = nullptr;
+    rc = lmr_maps_to_device(ctx, d_marked, M, N, d_meta, st, m, d_l, d_eta);
+    if (rc) return rc;
+    rdhei_job q{};
+    q.in = d_marked; q.out = d_out; q.msg = d_msg; q.meta = d_meta; q.key = key; q.nbits = nbits;
+    q.height = M; q.width = N; q.method = RDHEI_LMR;
+    Layout Ly;
+    rc = make_layout(op, &q, 1, ctx->per_pixel != 0, Ly);
+    if (rc) return rc;
+    Ly.jobs[0].lbits = d_l;
+    Ly.jobs[0].etabits = d_eta;
+    Launch L;
+    rc = stage(ctx, Ly, ctx->jobs, ctx->ws, st, L);
+    if (rc) return rc;
+    issue(Ly, L, Ly.units, Ly.per_pixel.data(), (int)Ly.per_pixel.size(), 1);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return RDHEI_OK;
+}
+
+// Launch a plan's sequence (batched) or image by image.
+int plan_issue(rdhei_plan *P, hipStream_t st) {
+    Launch L;
+    L.ws = P->ws.p;
+    L.stream = st;
+    L.max_grid = P->max_grid;
+    const Layout &Ly = P->layout;
+    if (P->flags == RDHEI_PLAN_PER_IMAGE) {
+        const Job *tables = reinterpret_cast<const Job *>(P->single.p);
+        for (size_t j = 0; j < P->per_image.size(); ++j) {
+            L.jobs = tables + j;
+            L.njobs = 1;
+            for (const Stage &s : P->per_image[j]) s.fn(L);
+        }
+    } else {
+        L.jobs = P->base.jobs;
+        for (int k = 0; k < UNIT_KINDS; ++k) L.ujob[k] = P->base.ujob[k];
+        L.njobs = (int32_t)Ly.jobs.size();
+        for (const Stage &s : P->stages) s.fn(L);
+    }
+    HIPCHK(hipGetLastError());
+    return RDHEI_OK;
+}
+
+}  // namespace
+
+// ---- C ABI ---------------------------------------------------------------------------
+extern "C" {
+
+int rdhei_ctx_create(rdhei_ctx **out, int device) {
+    if (!out) return RDHEI_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) {
+        set_err("hipGetDeviceCount", e);
+        return RDHEI_EDEVICE;
+    }
+    if (device < 0 || device >= n) return RDHEI_EINVAL;
+    rdhei_ctx *c = new (std::nothrow) rdhei_ctx();
+    if (!c) return RDHEI_ENOMEM;
+    c->device = device;
+    *out = c;
+    return RDHEI_OK;
+}
+
+void rdhei_ctx_destroy(rdhei_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    ctx->ws.release();
+    ctx->jobs.release();
+    ctx->scratch.release();
+    delete ctx;
+}
+
+int rdhei_ctx_set_option(rdhei_ctx *ctx, int32_t option, int64_t value) {
+    if (!ctx) return RDHEI_EINVAL;
+    if (option == RDHEI_OPT_PER_PIXEL) ctx->per_pixel = value ? 1 : 0;
+    else if (option == RDHEI_OPT_MAX_GRID) {
+        if (value < 0 || value > (1 << 30)) return RDHEI_EINVAL;
+        ctx->max_grid = (int)value;
+    } else return RDHEI_EINVAL;
+    return RDHEI_OK;
+}
+
+int rdhei_encrypt(rdhei_ctx *ctx, const uint8_t *d_img, uint8_t *d_enc, int32_t M, int32_t N, uint64_t k1,
+                  int32_t method, rdhei_meta *d_meta, void *stream) {
+    if (!ctx) return RDHEI_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (method == RDHEI_LMR) {
+        if (!d_img || !d_enc || !d_meta || d_img == d_enc || M < 1 || N < 1) return RDHEI_EINVAL;
+        return lmr_encrypt(ctx, d_img, d_enc, M, N, k1, d_meta, st);
+    }
+    if (method != RDHEI_EMR) return RDHEI_EINVAL;
+    rdhei_job q{};
+    q.in = d_img; q.out = d_enc; q.meta = d_meta; q.key = k1;
+    q.height = M; q.width = N; q.method = RDHEI_EMR;
+    return run_single(ctx, RDHEI_OP_ENCRYPT, q, st);
+}
+
+int rdhei_embed(rdhei_ctx *ctx, uint8_t *d_marked, int32_t M, int32_t N, int32_t method, rdhei_meta *d_meta,
+                const uint8_t *d_msg, int64_t nbits, uint64_t k2, void *stream) {
+    if (!ctx || !d_marked || !d_meta || !d_msg || !aligned16(d_msg) || M < 1 || N < 1) return RDHEI_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (method == RDHEI_LMR)
+        return lmr_stage(ctx, RDHEI_OP_EMBED, d_marked, d_marked, M, N, d_meta, const_cast<uint8_t *>(d_msg), nbits, k2, st);
+    if (method != RDHEI_EMR) return RDHEI_EINVAL;
+    rdhei_job q{};
+    q.out = d_marked; q.msg = const_cast<uint8_t *>(d_msg); q.meta = d_meta; q.key = k2; q.nbits = nbits;
+    q.height = M; q.width = N; q.method = RDHEI_EMR;
+    return run_single(ctx, RDHEI_OP_EMBED, q, st);
+}
+
+int rdhei_extract(rdhei_ctx *ctx, const uint8_t *d_marked, int32_t M, int32_t N, int32_t method,
+                  rdhei_meta *d_meta, uint8_t *d_msg, int64_t nbits, uint64_t k2, void *stream) {
+    if (!ctx || !d_marked || !d_meta || !d_msg || !aligned16(d_msg) || M < 1 || N < 1) return RDHEI_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (method == RDHEI_LMR)
+        return lmr_stage(ctx, RDHEI_OP_EXTRACT, d_marked, nullptr, M, N, d_meta, d_msg, nbits, k2, st);
+    if (method != RDHEI_EMR) return RDHEI_EINVAL;
+    rdhei_job q{};
+    q.in = d_marked; q.msg = d_msg; q.meta = d_meta; q.key = k2; q.nbits = nbits;
+    q.height = M; q.width = N; q.method = RDHEI_EMR;
+    return run_single(ctx, RDHEI_OP_EXTRACT, q, st);
+}
+
+int rdhei_recover(rdhei_ctx *ctx, const uint8_t *d_marked, int32_t M, int32_t N, int32_t method,
+                  rdhei_meta *d_meta, uint8_t *d_img, uint64_t k1, void *stream) {
+    if (!ctx || !d_marked || !d_meta || !d_img || d_marked == d_img || M < 1 || N < 1) return RDHEI_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (method == RDHEI_LMR)
+        return lmr_stage(ctx, RDHEI_OP_RECOVER, d_marked, d_img, M, N, d_meta, nullptr, 0, k1, st);
+    if (method != RDHEI_EMR) return RDHEI_EINVAL;
+    rdhei_job q{};
+    q.in = d_marked; q.out = d_img; q.meta = d_meta; q.key = k1;
+    q.height = M; q.width = N; q.method = RDHEI_EMR;
+    return run_single(ctx, RDHEI_OP_RECOVER, q, st);
+}
+
+int rdhei_plan_create(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t njobs, int32_t flags,
+                      rdhei_plan **out) {
+    if (!ctx || !jobs || njobs < 1 || !out) return RDHEI_EINVAL;
+    if (flags != RDHEI_PLAN_GRAPH && flags != RDHEI_PLAN_EAGER && flags != RDHEI_PLAN_PER_IMAGE) return RDHEI_EINVAL;
+    *out = nullptr;
+    int rc = set_device(ctx->device);
+    if (rc) return rc;
+    rdhei_plan *P = new (std::nothrow) rdhei_plan();
+    if (!P) return RDHEI_ENOMEM;
+    P->ctx = ctx;
+    P->flags = flags;
+    P->max_grid = ctx->max_grid;
+    rc = make_layout(op, jobs, njobs, ctx->per_pixel != 0, P->layout);
+    if (!rc && P->layout.method != RDHEI_EMR) rc = RDHEI_EINVAL;
+    size_t toff[UNIT_KINDS];
+    if (!rc) rc = P->jobs.need(table_bytes(P->layout, toff));
+    if (!rc) rc = P->ws.need(P->layout.ws_bytes);
+    if (!rc) rc = upload_tables(P->layout, P->jobs.p, nullptr, true, P->base);
+    if (!rc && flags == RDHEI_PLAN_PER_IMAGE) {
+        std::vector<Job> single = P->layout.jobs;
+        for (Job &J : single)
+            for (int k = 0; k < UNIT_KINDS; ++k) J.ubase[k] = 0;
+        rc = P->single.need(single.size() * sizeof(Job));
+        if (!rc) {
+            hipError_t e = hipMemcpy(P->single.p, single.data(), single.size() * sizeof(Job), hipMemcpyHostToDevice);
+            if (e != hipSuccess) { set_err("hipMemcpy", e); rc = RDHEI_EDEVICE; }
+        }
+    }
+    if (rc) {
+        P->jobs.release();
+        P->ws.release();
+        P->single.release();
+        delete P;
+        return rc;
+    }
+    P->stages = stages_of(P->layout, P->layout.units, P->layout.per_pixel);
+    if (flags == RDHEI_PLAN_PER_IMAGE) {
+        for (const Job &h : P->layout.jobs) {
+            Layout one;
+            one.op = P->layout.op;
+            one.method = P->layout.method;
+            one.multiseg = h.nseg > 1;
+            one.jobs.push_back(h);
+            const bool pp = !h.fast && (one.op == RDHEI_OP_ENCRYPT || one.op == RDHEI_OP_RECOVER);
+            P->per_image.push_back(stages_of(one, h.ucount, pp ? std::vector<int>{0} : std::vector<int>{}));
+        }
+    }
+    *out = P;
+    return RDHEI_OK;
+}
+
+int rdhei_plan_set_grid(rdhei_plan *plan, int32_t max_workgroups) {
+    if (!plan || max_workgroups < 0) return RDHEI_EINVAL;
+    if (plan->max_grid != max_workgroups) {
+        plan->max_grid = max_workgroups;
+        if (plan->exec) { (void)hipGraphExecDestroy(plan->exec); plan->exec = nullptr; }
+        if (plan->graph) { (void)hipGraphDestroy(plan->graph); plan->graph = nullptr; }
+    }
+    return RDHEI_OK;
+}
+
+int rdhei_plan_run(rdhei_plan *P, void *stream) {
+    if (!P) return RDHEI_EINVAL;
+    int rc = set_device(P->ctx->device);
+    if (rc) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (P->flags != RDHEI_PLAN_GRAPH) return plan_issue(P, st);
+    if (!P->exec) {
+        hipStream_t cap;
+        HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) { (void)hipStreamDestroy(cap); set_err("hipStreamBeginCapture", e); return RDHEI_EDEVICE; }
+        rc = plan_issue(P, cap);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(cap, &g);
+        (void)hipStreamDestroy(cap);
+        if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+        if (e != hipSuccess) { set_err("hipStreamEndCapture", e); return RDHEI_EDEVICE; }
+        e = hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) { (void)hipGraphDestroy(g); set_err("hipGraphInstantiate", e); return RDHEI_EDEVICE; }
+        P->graph = g;
+    }
+    HIPCHK(hipGraphLaunch(P->exec, st));
+    return RDHEI_OK;
+}
+
+int rdhei_plan_stage_count(rdhei_plan *P) { return P ? (int)P->stages.size() : RDHEI_EINVAL; }
+
+const char *rdhei_plan_stage_name(rdhei_plan *P, int32_t k) {
+    if (!P || k < 0 || k >= (int)P->stages.size()) return "";
+    return P->stages[(size_t)k].name;
+}
+
+int rdhei_plan_run_stage(rdhei_plan *P, int32_t k, void *stream) {
+    if (!P || k < 0 || k >= (int)P->stages.size()) return RDHEI_EINVAL;
+    int rc = set_device(P->ctx->device);
+    if (rc) return rc;
+    Launch L = P->base;
+    L.njobs = (int32_t)P->layout.jobs.size();
+    L.ws = P->ws.p;
+    L.stream = reinterpret_cast<hipStream_t>(stream);
+    L.max_grid = P->max_grid;
+    P->stages[(size_t)k].fn(L);
+    HIPCHK(hipGetLastError());
+    return RDHEI_OK;
+}
+
+void rdhei_plan_destroy(rdhei_plan *P) {
+    if (!P) return;
+    (void)hipSetDevice(P->ctx->device);
+    (void)hipDeviceSynchronize();
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    P->jobs.release();
+    P->ws.release();
+    P->single.release();
+    delete P;
+}
+
+int rdhei_lmr_compress(const uint8_t *eta_bits, const uint8_t *l_bits, int32_t M, int32_t N, uint8_t *stream,
+                       int64_t capacity_bytes, int64_t *stream_bits) {
+    if (!eta_bits || !l_bits || !stream || !stream_bits || M < 1 || N < 1 || capacity_bytes < 8) return RDHEI_EINVAL;
+    return lmr_compress_impl(eta_bits, l_bits, M, N, stream, capacity_bytes, stream_bits);
+}
+
+int rdhei_lmr_decompress(const uint8_t *stream, int64_t stream_bytes, int32_t M, int32_t N, uint8_t *eta_bits,
+                         uint8_t *l_bits) {
+    if (!stream || !eta_bits || !l_bits || M < 1 || N < 1 || stream_bytes < 8) return RDHEI_EINVAL;
+    return lmr_decompress_impl(stream, stream_bytes, M, N, eta_bits, l_bits);
+}
+
+const char *rdhei_strerror(int code) {
+    switch (code) {
+        case RDHEI_OK: return "ok";
+        case RDHEI_EINVAL: return "invalid argument";
+        case RDHEI_ECAPACITY: return "message longer than the capacity";
+        case RDHEI_ENOFIT: return "LMR maps do not compress into the MSB plane";
+        case RDHEI_ENOMEM: return "out of memory";
+        case RDHEI_EDEVICE: return "HIP runtime error";
+        case RDHEI_ECORRUPT: return "malformed LMR map stream";
+        default: return "unknown error";
+    }
+}
+
+const char *rdhei_last_error(void) { return g_err.c_str(); }
+
+const char *rdhei_version(void) { return "rdhei 0.1 gfx950"; }
+
+}  // extern "C"

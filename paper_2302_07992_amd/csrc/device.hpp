@@ -1,0 +1,160 @@
+// Device helpers for gfx950: keystream, job lookup, the closed form of the
+// composed block rotation.
+#pragma once
+#include "internal.hpp"
+
+namespace rdhei {
+
+// ---- Keystream ---------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64
+// multiplies, key bumped by the Weyl constants between rounds.  The paper only
+// asks for a secure stream cipher (Sec. III-A, secret key generation); a
+// counter-based generator lets every 16-byte piece of the stream be produced
+// independently, which is what a data-parallel kernel needs.
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                     uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
+        const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+constexpr uint32_t kDomainImage = 1;
+constexpr uint32_t kDomainMessage = 2;
+
+// The 16 stream bytes [16*blk, 16*blk+16) as four little-endian words.
+__device__ __forceinline__ U4 stream_block(uint64_t key, uint32_t domain, uint64_t blk) {
+    return philox((uint32_t)blk, (uint32_t)(blk >> 32), domain, 0u, (uint32_t)key, (uint32_t)(key >> 32));
+}
+
+__device__ __forceinline__ uint32_t stream_byte(uint64_t key, uint32_t domain, uint64_t idx) {
+    U4 v = stream_block(key, domain, idx >> 4);
+    uint32_t w = ((idx >> 2) & 3) == 0 ? v.x : ((idx >> 2) & 3) == 1 ? v.y : ((idx >> 2) & 3) == 2 ? v.z : v.w;
+    return (w >> (8 * (idx & 3))) & 0xFFu;
+}
+
+// ---- Batches -----------------------------------------------------------------
+// Index of the job owning work unit u of a kind: one load from the per-unit
+// table when the launch has one, else a search over the ascending bases.
+template <int KIND>
+__device__ __forceinline__ int find_job(const Job *jobs, int njobs, uint32_t u, const uint32_t *ujob) {
+    if (ujob) return (int)ujob[u];
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].ubase[KIND] <= u) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---- Rotation ------------------------------------------------------------------
+// A quarter turn counter-clockwise of a 2^m block maps local (y, x) to
+// (2^m-1-x, y): per coordinate bit, (y_j, x_j) -> (!x_j, y_j).  Because a block
+// turn at level m acts on every bit below m the same way, and the block index
+// used at every level is a function of the untouched high bits, the composed
+// map of all levels turns bit pair j by R_j = sum of the codes of the blocks
+// (levels m > j, full blocks only) containing the pixel.
+__device__ __forceinline__ void turn_bits(uint32_t r, uint32_t &y, uint32_t &x, uint32_t mask) {
+    // r = 0: (y, x); 1: (!x, y); 2: (!y, !x); 3: (x, !y), on the bits in mask.
+    const uint32_t sw = r & 1u;
+    const uint32_t ny = sw ? x : y;
+    const uint32_t nx = sw ? y : x;
+    const uint32_t fy = (r == 1u || r == 2u) ? mask : 0u;
+    const uint32_t fx = (r >= 2u) ? mask : 0u;
+    y = (ny ^ fy) & mask;
+    x = (nx ^ fx) & mask;
+}
+
+// Code (2 bits) of block (by, bx) of tile-level m from a packed record in LDS.
+__device__ __forceinline__ uint32_t tile_code(const uint8_t *rec, int m, uint32_t by, uint32_t bx) {
+    const uint32_t q = by * (uint32_t)(kTile >> m) + bx;
+    return (rec[code_off(m) + (q >> 2)] >> (2 * (q & 3))) & 3u;
+}
+
+// Byte offset of level m (> kTileLog) of the upper pyramid, whose level
+// kTileLog is the tiles_y x tiles_x array of tile sums.
+__device__ __host__ inline uint64_t pyr_off(int M, int N, int m) {
+    uint64_t off = 0;
+    for (int k = kTileLog; k < m; ++k) off += (uint64_t)(M >> k) * (uint64_t)(N >> k);
+    return off;
+}
+
+// Where a whole tile goes: levels above the tile move the tile rigidly.  Walks
+// levels ascending on tile coordinates; returns the destination tile and the
+// number of quarter turns the tile's content receives.
+__device__ __forceinline__ void upper_walk(const Job &J, const uint8_t *pyr, int ty, int tx,
+                                           int &dy, int &dx, uint32_t &turns) {
+    uint32_t cy = (uint32_t)ty, cx = (uint32_t)tx, o = 0;
+    const int lo = J.min_level > kTileLog + 1 ? J.min_level : kTileLog + 1;
+    for (int m = lo; m <= J.max_level; ++m) {
+        const int sh = m - kTileLog;
+        const uint32_t BY = (uint32_t)ty >> sh, BX = (uint32_t)tx >> sh;
+        const uint32_t gy = (uint32_t)(J.M >> m), gx = (uint32_t)(J.N >> m);
+        if (BY < gy && BX < gx) {
+            const uint32_t r = pyr[pyr_off(J.M, J.N, m) + BY * gx + BX] & 3u;
+            o += r;
+            const uint32_t mask = (1u << sh) - 1u;
+            uint32_t ly = cy & mask, lx = cx & mask;
+            turn_bits(r, ly, lx, mask);
+            cy = (cy & ~mask) | ly;
+            cx = (cx & ~mask) | lx;
+        }
+    }
+    dy = (int)cy;
+    dx = (int)cx;
+    turns = o & 3u;
+}
+
+// Destinations inside the tile of the 16 pixels of 4x4 block (by, bx), given
+// the tile's code record and the turns added by the levels above the tile.
+// dst[k] = (row << 8) | col for pixel k = 4*u + v of the block.
+__device__ __forceinline__ void block_map(const uint8_t *rec, int min_level, uint32_t up_turns,
+                                          uint32_t by, uint32_t bx, uint32_t dst[16]) {
+    // turns per pixel bit j >= 2 (block bit j - 2), accumulated from the top
+    uint32_t acc = up_turns;
+    uint32_t ny = 0, nx = 0;
+#pragma unroll
+    for (int m = kTileLog; m >= 3; --m) {
+        if (m >= min_level) acc += tile_code(rec, m, by >> (m - 2), bx >> (m - 2));
+        const int j = m - 3;             // block bit j carries pixel bit m - 1
+        uint32_t yb = (by >> j) & 1u, xb = (bx >> j) & 1u;
+        turn_bits(acc & 3u, yb, xb, 1u);
+        ny |= yb << j;
+        nx |= xb << j;
+    }
+    const uint32_t r1 = (acc + (2 >= min_level ? tile_code(rec, 2, by, bx) : 0u)) & 3u;
+#pragma unroll
+    for (int su = 0; su < 2; ++su) {
+#pragma unroll
+        for (int sv = 0; sv < 2; ++sv) {
+            uint32_t y1 = (uint32_t)su, x1 = (uint32_t)sv;
+            turn_bits(r1, y1, x1, 1u);
+            const uint32_t r0 = (r1 + (1 >= min_level ? tile_code(rec, 1, 2 * by + su, 2 * bx + sv) : 0u)) & 3u;
+#pragma unroll
+            for (int pu = 0; pu < 2; ++pu) {
+#pragma unroll
+                for (int pv = 0; pv < 2; ++pv) {
+                    uint32_t y0 = (uint32_t)pu, x0 = (uint32_t)pv;
+                    turn_bits(r0, y0, x0, 1u);
+                    const uint32_t row = (ny << 2) | (y1 << 1) | y0;
+                    const uint32_t col = (nx << 2) | (x1 << 1) | x0;
+                    dst[(2 * su + pu) * 4 + (2 * sv + pv)] = (row << 8) | col;
+                }
+            }
+        }
+    }
+}
+
+}  // namespace rdhei

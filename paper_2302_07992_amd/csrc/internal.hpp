@@ -1,0 +1,95 @@
+// Internal declarations shared by the HIP translation units of librdhei.
+// Device code for gfx950 (wave64).  Nothing here is part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rdhei.h"
+
+namespace rdhei {
+
+// Fast-path tile: 64 x 64 pixels, one 256-thread workgroup per tile.
+constexpr int kTileLog = 6;
+constexpr int kTile = 1 << kTileLog;
+constexpr int kThreads = 256;
+
+// Per-tile record of in-tile rotation codes, levels 1..kTileLog, 2 bits per
+// block, row-major per level.  Level m starts at kCodeOff[m].
+__host__ __device__ constexpr int code_bytes_level(int m) { return ((kTile >> m) * (kTile >> m) + 3) / 4; }
+__host__ __device__ constexpr int code_off(int m) {
+    int off = 0;
+    for (int k = 1; k < m; ++k) off += code_bytes_level(k);
+    return off;
+}
+constexpr int kCodeRecord = (code_off(kTileLog + 1) + 15) / 16 * 16;   // 352 bytes for 64 x 64
+
+// Statistics record per tile: histogram of the leading-shared-bit count
+// lambda for lambda = 2..8 (7 counts) + 1 pad word.
+constexpr int kStatWords = 8;
+
+// Work-unit kinds (how a batch is cut into workgroup-sized pieces).
+enum UnitKind { UNIT_TILE = 0, UNIT_BAND = 1, UNIT_SEG = 2, UNIT_IMG = 3, UNIT_KINDS = 4 };
+
+// Device-side descriptor of one image of a launch.
+struct Job {
+    const uint8_t *in;
+    uint8_t *out;
+    uint8_t *msg;
+    rdhei_meta *meta;
+    const uint8_t *lbits;     // LMR: rotated location-map bit plane (encrypted domain)
+    const uint8_t *etabits;   // LMR: rotated first-MSB bit plane (encrypted domain)
+    const uint8_t *stream;    // LMR encrypt: map stream for the MSB plane
+    uint64_t key;
+    int64_t nbits;            // embed/extract request (< 0: capacity)
+    int64_t stream_bits;      // LMR encrypt: stream length in bits
+    int32_t M, N;
+    int32_t method;           // RDHEI_EMR / RDHEI_LMR
+    int32_t min_level;        // 1 (EMR) or 4 (LMR)
+    int32_t max_level;        // n = floor(log2 min(M, N))
+    int32_t fixed_b;          // > 0: b chosen on the host (LMR); 0: read meta->b
+    int32_t fast;             // 1: tiled path; 0: per-pixel path
+    int32_t tiles_x, tiles_y;
+    int32_t nseg;             // raster segments for hiding/extraction
+    uint32_t ubase[UNIT_KINDS];
+    uint32_t ucount[UNIT_KINDS];
+    uint64_t ws_codes;        // tile code records (fast) / all-level codes (per-pixel path)
+    uint64_t ws_pyr;          // tile sums + upper levels (fast path)
+    uint64_t ws_stats;        // statistics records
+    uint64_t ws_seg;          // per-segment counts and offsets (2 x nseg u32)
+    uint64_t ws_bytes;        // per-pixel path: byte-per-pixel scratch
+};
+
+// Raster segment for hiding / extraction: pixels handled by one workgroup in
+// order.  A chunk is what 256 threads cover with 16 pixels each.
+constexpr int kChunk = kThreads * 16;
+
+// ---- launchers (defined in the .hip files) ---------------------------------
+struct Launch {
+    const Job *jobs;          // device job table
+    const uint32_t *ujob[UNIT_KINDS] = {nullptr, nullptr, nullptr, nullptr};   // unit -> job tables
+    int32_t njobs;
+    uint8_t *ws;              // device workspace base
+    hipStream_t stream;
+    int max_grid;             // cap on workgroups of a grid-stride launch
+};
+
+void launch_tile_prep(const Launch &L, uint32_t units, bool stats);
+void launch_finalize(const Launch &L, bool stats);
+void launch_encrypt_tiles(const Launch &L, uint32_t units, int mode);
+void launch_recover_bands(const Launch &L, uint32_t units, int method);
+void launch_seg_count(const Launch &L, uint32_t units);
+void launch_seg_scan(const Launch &L, int clear_shared);
+uint64_t seg_pixels();
+void launch_embed(const Launch &L, uint32_t units);
+void launch_extract(const Launch &L, uint32_t units);
+// per-pixel path, one image (job index j of the table; host copy h)
+void launch_generic_levels(const Launch &L, int j, const Job &h);
+void launch_generic_stats(const Launch &L, int j, const Job &h);
+void launch_generic_encrypt(const Launch &L, int j, const Job &h, int mode);
+void launch_generic_recover(const Launch &L, int j, const Job &h);
+uint64_t generic_code_bytes(int M, int N, int n);
+
+// Encrypt-kernel modes.
+enum EncMode { ENC_EMR = 0, ENC_LMR = 1, ENC_LMR_MAPS = 2 };
+
+}  // namespace rdhei

@@ -1,0 +1,502 @@
+// Tiled fast path (M, N multiples of 64): keystream code pyramid + label
+// statistics, per-image finalisation (optimal b, upper rotation levels), the
+// permuting encryption, and the band-sequential recovery.
+#include "device.hpp"
+
+namespace rdhei {
+
+// LDS row stride of a 64-byte tile row (keeps 16-byte alignment).
+constexpr int kRow = kTile + 16;
+
+// ----------------------------------------------------------------------------
+// Keystream code pyramid of one tile (Sec. III-A rotation equation: block code
+// = (sum of s over the block) mod 4 at every level 2^1..2^6 inside the tile)
+// and, for encryption, the histogram of the leading-shared-bit count lambda of
+// each pixel with its left neighbour (Sec. III-A location map; the Omega glide
+// labels a pixel redundant for b exactly when lambda >= b).
+// ----------------------------------------------------------------------------
+template <bool STATS>
+__global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ jobs, int njobs,
+                                                         uint8_t *__restrict__ ws, uint32_t units,
+    const uint32_t *__restrict__ ujob) {
+    __shared__ uint8_t lvl[1024 + 256 + 64 + 16 + 4 + 4];   // unpacked codes, levels 1..6
+    __shared__ __align__(16) uint8_t rec[kCodeRecord];
+    __shared__ uint32_t hist[4][8];
+    const int tid = threadIdx.x;
+    const int r = tid >> 2, g = tid & 3;
+    const int lane = tid & 63, wave = tid >> 6;
+    uint8_t *L1 = lvl, *L2 = lvl + 1024, *L3 = L2 + 256, *L4 = L3 + 64, *L5 = L4 + 16, *L6 = L5 + 4;
+
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const int j = find_job<UNIT_TILE>(jobs, njobs, u, ujob);
+        const Job &J = jobs[j];
+        const uint32_t t = u - J.ubase[UNIT_TILE];
+        const int ty = (int)(t / (uint32_t)J.tiles_x), tx = (int)(t % (uint32_t)J.tiles_x);
+        const uint64_t idx = (uint64_t)(ty * kTile + r) * (uint64_t)J.N + (uint64_t)(tx * kTile + 16 * g);
+        const U4 s = stream_block(J.key, kDomainImage, idx >> 4);
+
+        // level 1: 2x2 sums from this row pair (row r even holds the sums)
+        uint32_t h[4] = {(s.x & 0x00FF00FFu) + ((s.x >> 8) & 0x00FF00FFu),
+                         (s.y & 0x00FF00FFu) + ((s.y >> 8) & 0x00FF00FFu),
+                         (s.z & 0x00FF00FFu) + ((s.z >> 8) & 0x00FF00FFu),
+                         (s.w & 0x00FF00FFu) + ((s.w >> 8) & 0x00FF00FFu)};
+        uint32_t v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = (h[k] + __shfl_down(h[k], 4, 64)) & 0x00030003u;
+        if ((r & 1) == 0) {
+            uint8_t *dst = L1 + (r >> 1) * 32 + 8 * g;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                dst[2 * k] = (uint8_t)(v[k] & 3u);
+                dst[2 * k + 1] = (uint8_t)((v[k] >> 16) & 3u);
+            }
+        }
+        __syncthreads();
+        {   // level 2: 16 x 16 codes, one per thread
+            const int Y = tid >> 4, X = tid & 15;
+            const uint8_t *a = L1 + (2 * Y) * 32 + 2 * X;
+            L2[tid] = (uint8_t)((a[0] + a[1] + a[32] + a[33]) & 3);
+        }
+        __syncthreads();
+        if (tid < 64) {
+            const int Y = tid >> 3, X = tid & 7;
+            const uint8_t *a = L2 + (2 * Y) * 16 + 2 * X;
+            L3[tid] = (uint8_t)((a[0] + a[1] + a[16] + a[17]) & 3);
+        }
+        __syncthreads();
+        if (tid < 16) {
+            const int Y = tid >> 2, X = tid & 3;
+            const uint8_t *a = L3 + (2 * Y) * 8 + 2 * X;
+            L4[tid] = (uint8_t)((a[0] + a[1] + a[8] + a[9]) & 3);
+        }
+        __syncthreads();
+        if (tid < 4) {
+            const int Y = tid >> 1, X = tid & 1;
+            const uint8_t *a = L4 + (2 * Y) * 4 + 2 * X;
+            L5[tid] = (uint8_t)((a[0] + a[1] + a[4] + a[5]) & 3);
+        }
+        __syncthreads();
+        if (tid == 0) L6[0] = (uint8_t)((L5[0] + L5[1] + L5[2] + L5[3]) & 3);
+        __syncthreads();
+        // pack 2-bit codes: byte q of level m holds codes 4q..4q+3
+        for (int q = tid; q < code_off(kTileLog + 1); q += kThreads) {
+            int m = 1, base = 0;
+            while (m < kTileLog && q >= code_off(m + 1)) ++m;
+            base = q - code_off(m);
+            const uint8_t *src = lvl + (m == 1 ? 0 : m == 2 ? 1024 : m == 3 ? 1280 : m == 4 ? 1344 : m == 5 ? 1360 : 1364);
+            const int cnt = (kTile >> m) * (kTile >> m);
+            uint32_t b = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int c = 4 * base + k;
+                if (c < cnt) b |= (uint32_t)src[c] << (2 * k);
+            }
+            rec[q] = (uint8_t)b;
+        }
+        __syncthreads();
+        uint8_t *out_rec = ws + J.ws_codes + (uint64_t)t * kCodeRecord;
+        if (tid < kCodeRecord / 16)
+            reinterpret_cast<uint4 *>(out_rec)[tid] = reinterpret_cast<const uint4 *>(rec)[tid];
+        if (tid == 0) ws[J.ws_pyr + t] = L6[0];
+
+        if (STATS) {
+            const uint8_t *row = J.in + (uint64_t)(ty * kTile + r) * (uint64_t)J.N + (uint64_t)(tx * kTile);
+            const uint4 p = *reinterpret_cast<const uint4 *>(row + 16 * g);
+            uint32_t left = __shfl_up(p.w >> 24, 1, 64);
+            if (g == 0) left = tx > 0 ? (uint32_t)row[-1] : 0u;
+            const uint32_t w[4] = {p.x, p.y, p.z, p.w};
+            const uint32_t lw[4] = {(p.x << 8) | left, (p.y << 8) | (p.x >> 24), (p.z << 8) | (p.y >> 24),
+                                    (p.w << 8) | (p.z >> 24)};
+            // packed counters, 9 bits per lambda in 2..8 (lambda < 2 dropped)
+            uint64_t acc = 0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const uint32_t x = ((w[k >> 2] ^ lw[k >> 2]) >> (8 * (k & 3))) & 0xFFu;
+                const uint32_t lam = __clz((x << 24) | 0x00800000u);       // leading shared bits, 0..8
+                const bool first_col = (tx == 0 && g == 0 && k == 0);
+                if (lam >= 2 && !first_col) acc += 1ull << (9 * (lam - 2));
+            }
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) acc += __shfl_xor(acc, off, 64);   // <= 256 per field
+            uint32_t c[7];
+#pragma unroll
+            for (int k = 0; k < 7; ++k) {
+                c[k] = (uint32_t)(acc >> (9 * k)) & 0x1FFu;
+                c[k] += __shfl_xor(c[k], 16, 64);
+                c[k] += __shfl_xor(c[k], 32, 64);
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int k = 0; k < 7; ++k) hist[wave][k] = c[k];
+            }
+            __syncthreads();
+            if (tid < 7) {
+                uint32_t *st = reinterpret_cast<uint32_t *>(ws + J.ws_stats) + (uint64_t)t * kStatWords;
+                st[tid] = hist[0][tid] + hist[1][tid] + hist[2][tid] + hist[3][tid];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------------------
+// One workgroup per image: sums the label histogram, picks the optimal b
+// (Sec. III-A optimal-b equation: argmax of b*Z_b, smallest b on ties), writes
+// the public meta record, and builds the rotation codes of the levels above
+// the tile from the tile sums (a level-m block code is the sum of its four
+// children mod 4 because block sums nest).
+// ----------------------------------------------------------------------------
+template <bool STATS>
+__global__ __launch_bounds__(kThreads) void k_finalize(const Job *__restrict__ jobs, int njobs,
+                                                        uint8_t *__restrict__ ws) {
+    __shared__ uint32_t part[kThreads / 64][8];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int j = blockIdx.x; j < njobs; j += gridDim.x) {
+        const Job &J = jobs[j];
+        if (STATS) {
+            const uint32_t nrec = J.fast ? (uint32_t)(J.tiles_x * J.tiles_y) : 1u;
+            const uint32_t *st = reinterpret_cast<const uint32_t *>(ws + J.ws_stats);
+            uint32_t c[7] = {0, 0, 0, 0, 0, 0, 0};
+            for (uint32_t q = tid; q < nrec; q += kThreads)
+#pragma unroll
+                for (int k = 0; k < 7; ++k) c[k] += st[(uint64_t)q * kStatWords + k];
+#pragma unroll
+            for (int k = 0; k < 7; ++k)
+                for (int off = 32; off > 0; off >>= 1) c[k] += __shfl_xor(c[k], off, 64);
+            if (lane == 0)
+#pragma unroll
+                for (int k = 0; k < 7; ++k) part[wave][k] = c[k];
+            __syncthreads();
+            if (tid == 0) {
+                int64_t hl[7];
+                for (int k = 0; k < 7; ++k) hl[k] = (int64_t)part[0][k] + part[1][k] + part[2][k] + part[3][k];
+                int64_t Z[9];                       // Z_b = #{lambda >= b}
+                Z[8] = hl[6];
+                for (int b = 7; b >= 2; --b) Z[b] = Z[b + 1] + hl[b - 2];
+                // keep the counts for the host (LMR candidate order)
+                int64_t *zout = reinterpret_cast<int64_t *>(ws + J.ws_stats) +
+                                (uint64_t)(J.fast ? J.tiles_x * J.tiles_y : 1) * (kStatWords / 2);
+                for (int b = 2; b <= 8; ++b) zout[b - 2] = Z[b];
+                if (J.method == RDHEI_EMR) {
+                    int best = 2;
+                    for (int b = 3; b <= 7; ++b)
+                        if ((int64_t)b * Z[b] > (int64_t)best * Z[best]) best = b;
+                    rdhei_meta m;
+                    m.height = J.M; m.width = J.N; m.method = RDHEI_EMR; m.b = best;
+                    m.min_level = J.min_level; m.max_level = J.max_level;
+                    m.redundant = Z[best]; m.capacity_bits = (int64_t)best * Z[best];
+                    m.map_bits = 0; m.status = RDHEI_OK;
+                    m.reserved[0] = m.reserved[1] = m.reserved[2] = 0;
+                    *J.meta = m;
+                }
+            }
+        }
+        if (J.fast) {
+            uint8_t *pyr = ws + J.ws_pyr;
+            // level kTileLog holds the tile sums
+            for (int m = kTileLog + 1; m <= J.max_level; ++m) {
+                __syncthreads();
+                const uint32_t gy = (uint32_t)(J.M >> m), gx = (uint32_t)(J.N >> m);
+                const uint32_t cx = (uint32_t)(J.N >> (m - 1));
+                const uint8_t *child = pyr + pyr_off(J.M, J.N, m - 1);
+                uint8_t *cur = pyr + pyr_off(J.M, J.N, m);
+                for (uint32_t q = tid; q < gy * gx; q += kThreads) {
+                    const uint32_t Y = q / gx, X = q % gx;
+                    const uint8_t *a = child + (2 * Y) * cx + 2 * X;
+                    cur[q] = (uint8_t)((a[0] + a[1] + a[cx] + a[cx + 1]) & 3);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Encryption of one source tile (Sec. III-A encoding): label each pixel
+// (l = 1 unless its b MSBs match its left neighbour's; column 0 always 1),
+// move it to its rotated position (closed form of the level-by-level block
+// turns), XOR with the keystream at the destination, and put l in the LSB.
+// LMR: full-byte XOR, then bit 7 of raster pixel p takes stream bit p.
+// LMR_MAPS: instead of the image, write the rotated location map and
+// first-MSB map as bit planes (for the host coder).
+// ----------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_encrypt_tile(const Job *__restrict__ jobs, int njobs,
+                                                            uint8_t *__restrict__ ws, uint32_t units,
+    const uint32_t *__restrict__ ujob) {
+    __shared__ __align__(16) uint8_t src[kTile * kRow];
+    __shared__ __align__(16) uint8_t dst[kTile * kRow];
+    __shared__ __align__(16) uint8_t rec[kCodeRecord];
+    const int tid = threadIdx.x;
+    const int r = tid >> 2, g = tid & 3;
+    const int by = tid >> 4, bx = tid & 15;
+
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const int j = find_job<UNIT_TILE>(jobs, njobs, u, ujob);
+        const Job &J = jobs[j];
+        const uint32_t t = u - J.ubase[UNIT_TILE];
+        const int ty = (int)(t / (uint32_t)J.tiles_x), tx = (int)(t % (uint32_t)J.tiles_x);
+        if (MODE == ENC_EMR && J.meta->status != RDHEI_OK) continue;
+        const int b = J.fixed_b > 0 ? J.fixed_b : J.meta->b;
+        int dy, dx;
+        uint32_t up;
+        upper_walk(J, ws + J.ws_pyr, ty, tx, dy, dx, up);
+
+        const uint8_t *row = J.in + (uint64_t)(ty * kTile + r) * (uint64_t)J.N + (uint64_t)(tx * kTile);
+        const uint4 p = *reinterpret_cast<const uint4 *>(row + 16 * g);
+        uint4 o = p;
+        if (MODE != ENC_LMR) {
+            uint32_t left = __shfl_up(p.w >> 24, 1, 64);
+            if (g == 0) left = tx > 0 ? (uint32_t)row[-1] : 0u;
+            const uint32_t topm = ((0xFFu << (8 - b)) & 0xFFu) * 0x01010101u;
+            const uint32_t w[4] = {p.x, p.y, p.z, p.w};
+            const uint32_t lw[4] = {(p.x << 8) | left, (p.y << 8) | (p.x >> 24), (p.z << 8) | (p.y >> 24),
+                                    (p.w << 8) | (p.z >> 24)};
+            uint32_t res[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t d = (w[k] ^ lw[k]) & topm;
+                uint32_t nz = ((((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d) >> 7) & 0x01010101u;  // l per byte
+                if (k == 0 && tx == 0 && g == 0) nz |= 1u;                                  // column 0
+                if (MODE == ENC_EMR) res[k] = (w[k] & 0xFEFEFEFEu) | nz;
+                else res[k] = (nz << 1) | ((w[k] >> 7) & 0x01010101u);                      // l<<1 | eta
+            }
+            o = make_uint4(res[0], res[1], res[2], res[3]);
+        }
+        *reinterpret_cast<uint4 *>(src + r * kRow + 16 * g) = o;
+        if (tid < kCodeRecord / 16)
+            reinterpret_cast<uint4 *>(rec)[tid] =
+                reinterpret_cast<const uint4 *>(ws + J.ws_codes + (uint64_t)t * kCodeRecord)[tid];
+        __syncthreads();
+
+        uint32_t dmap[16];
+        block_map(rec, J.min_level, up, (uint32_t)by, (uint32_t)bx, dmap);
+#pragma unroll
+        for (int uu = 0; uu < 4; ++uu) {
+            const uint32_t word = *reinterpret_cast<const uint32_t *>(src + (4 * by + uu) * kRow + 4 * bx);
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) {
+                const uint32_t d = dmap[4 * uu + vv];
+                dst[(d >> 8) * kRow + (d & 0xFFu)] = (uint8_t)(word >> (8 * vv));
+            }
+        }
+        __syncthreads();
+
+        const uint4 q = *reinterpret_cast<const uint4 *>(dst + r * kRow + 16 * g);
+        const uint64_t didx = (uint64_t)(dy * kTile + r) * (uint64_t)J.N + (uint64_t)(dx * kTile + 16 * g);
+        if (MODE == ENC_LMR_MAPS) {
+            // bit planes, MSB-first: pixel didx+k -> byte (didx+k)/8, bit 7-(k%8)
+            const uint32_t qq[4] = {q.x, q.y, q.z, q.w};
+            uint32_t lb = 0, eb = 0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const uint32_t v = (qq[k >> 2] >> (8 * (k & 3))) & 3u;
+                const int pos = (k < 8) ? (7 - k) : (23 - k);   // little-endian u16 of two MSB-first bytes
+                lb |= ((v >> 1) & 1u) << pos;
+                eb |= (v & 1u) << pos;
+            }
+            *reinterpret_cast<uint16_t *>(J.out + (didx >> 3)) = (uint16_t)lb;
+            *reinterpret_cast<uint16_t *>(J.msg + (didx >> 3)) = (uint16_t)eb;
+        } else {
+            const U4 s = stream_block(J.key, kDomainImage, didx >> 4);
+            uint4 e;
+            if (MODE == ENC_EMR) {
+                e = make_uint4(q.x ^ (s.x & 0xFEFEFEFEu), q.y ^ (s.y & 0xFEFEFEFEu), q.z ^ (s.z & 0xFEFEFEFEu),
+                               q.w ^ (s.w & 0xFEFEFEFEu));
+            } else {
+                e = make_uint4(q.x ^ s.x, q.y ^ s.y, q.z ^ s.z, q.w ^ s.w);
+                if ((int64_t)didx < J.stream_bits) {
+                    // 16 stream bits for pixels didx..didx+15 (didx is a multiple of 16)
+                    const uint32_t sb = ((uint32_t)J.stream[didx >> 3] << 8) | J.stream[(didx >> 3) + 1];
+                    uint32_t ew[4] = {e.x, e.y, e.z, e.w};
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) {
+                        if ((int64_t)didx + k < J.stream_bits) {
+                            const uint32_t bit = (sb >> (15 - k)) & 1u;
+                            ew[k >> 2] = (ew[k >> 2] & ~(0x80u << (8 * (k & 3)))) | (bit << (8 * (k & 3) + 7));
+                        }
+                    }
+                    e = make_uint4(ew[0], ew[1], ew[2], ew[3]);
+                }
+            }
+            *reinterpret_cast<uint4 *>(J.out + didx) = e;
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Recovery of one row band of tiles, left to right (Sec. III-A decoding with
+// K1): gather each original-domain tile from its rotated position, decrypt
+// with the keystream at the encrypted position, read l (EMR: the LSB; LMR:
+// the decompressed map, plus bit 7 from the first-MSB map), then the recovery
+// glide along each row: a pixel labelled 0 takes the replaceable bits of the
+// nearest pixel labelled 1 to its left.  Rows carry that value across tiles.
+// ----------------------------------------------------------------------------
+template <int METHOD>
+__global__ __launch_bounds__(kThreads) void k_recover_band(const Job *__restrict__ jobs, int njobs,
+                                                            uint8_t *__restrict__ ws, uint32_t units,
+    const uint32_t *__restrict__ ujob) {
+    constexpr int kRow2 = 2 * kTile + 32;   // u16 per pixel: value | l << 8
+    __shared__ __align__(16) uint8_t src[kTile * kRow2];
+    __shared__ __align__(16) uint8_t dst[kTile * kRow2];
+    __shared__ __align__(16) uint8_t rec[kCodeRecord];
+    const int tid = threadIdx.x;
+    const int r = tid >> 2, g = tid & 3;
+    const int by = tid >> 4, bx = tid & 15;
+    const int lane = tid & 63;
+
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const int j = find_job<UNIT_BAND>(jobs, njobs, u, ujob);
+        const Job &J = jobs[j];
+        const int ty = (int)(u - J.ubase[UNIT_BAND]);
+        const int b = J.meta->b;
+        const uint32_t mask = METHOD == RDHEI_EMR ? ((0xFFu << (8 - b)) & 0xFFu) : ((0xFFu << (8 - b)) & 0x7Fu);
+        uint32_t carry = 0;   // replaceable bits of the last marker in this row
+
+        for (int tx = 0; tx < J.tiles_x; ++tx) {
+            int ey, ex;
+            uint32_t up;
+            upper_walk(J, ws + J.ws_pyr, ty, tx, ey, ex, up);
+            const uint64_t eidx = (uint64_t)(ey * kTile + r) * (uint64_t)J.N + (uint64_t)(ex * kTile + 16 * g);
+            const uint4 e = *reinterpret_cast<const uint4 *>(J.in + eidx);
+            const U4 s = stream_block(J.key, kDomainImage, eidx >> 4);
+            uint32_t D[4] = {e.x ^ s.x, e.y ^ s.y, e.z ^ s.z, e.w ^ s.w};
+            uint32_t Lw[4];
+            if (METHOD == RDHEI_EMR) {
+                Lw[0] = e.x & 0x01010101u; Lw[1] = e.y & 0x01010101u;
+                Lw[2] = e.z & 0x01010101u; Lw[3] = e.w & 0x01010101u;
+            } else {
+                const uint32_t lb = ((uint32_t)J.lbits[eidx >> 3] << 8) | J.lbits[(eidx >> 3) + 1];
+                const uint32_t eb = ((uint32_t)J.etabits[eidx >> 3] << 8) | J.etabits[(eidx >> 3) + 1];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    uint32_t lw = 0, ew = 0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        lw |= ((lb >> (15 - (4 * k + q))) & 1u) << (8 * q);
+                        ew |= ((eb >> (15 - (4 * k + q))) & 1u) << (8 * q + 7);
+                    }
+                    Lw[k] = lw;
+                    D[k] = (D[k] & 0x7F7F7F7Fu) | ew;
+                }
+            }
+            uint32_t il[8];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                il[2 * k] = __builtin_amdgcn_perm(Lw[k], D[k], 0x05010400u);
+                il[2 * k + 1] = __builtin_amdgcn_perm(Lw[k], D[k], 0x07030602u);
+            }
+            uint4 *sp = reinterpret_cast<uint4 *>(src + r * kRow2 + 32 * g);
+            sp[0] = make_uint4(il[0], il[1], il[2], il[3]);
+            sp[1] = make_uint4(il[4], il[5], il[6], il[7]);
+            const uint32_t t = (uint32_t)(ty * J.tiles_x + tx);
+            if (tid < kCodeRecord / 16)
+                reinterpret_cast<uint4 *>(rec)[tid] =
+                    reinterpret_cast<const uint4 *>(ws + J.ws_codes + (uint64_t)t * kCodeRecord)[tid];
+            __syncthreads();
+
+            uint32_t dmap[16];
+            block_map(rec, J.min_level, up, (uint32_t)by, (uint32_t)bx, dmap);
+#pragma unroll
+            for (int uu = 0; uu < 4; ++uu) {
+                uint32_t vals[4];
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv) {
+                    const uint32_t d = dmap[4 * uu + vv];
+                    vals[vv] = *reinterpret_cast<const uint16_t *>(src + (d >> 8) * kRow2 + 2 * (d & 0xFFu));
+                }
+                *reinterpret_cast<uint2 *>(dst + (4 * by + uu) * kRow2 + 8 * bx) =
+                    make_uint2(vals[0] | (vals[1] << 16), vals[2] | (vals[3] << 16));
+            }
+            __syncthreads();
+
+            const uint4 *rp = reinterpret_cast<const uint4 *>(dst + r * kRow2 + 32 * g);
+            const uint4 a0 = rp[0], a1 = rp[1];
+            const uint32_t pk[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+            // segment summary: does it hold a marker, and the last marker's bits
+            uint32_t has = 0, last = 0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const uint32_t v = (pk[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+                const bool marker = ((v >> 8) & 1u) || (tx == 0 && g == 0 && k == 0);
+                if (marker) { has = 1; last = v & mask; }
+            }
+            // carry-in from the nearest segment to the left in this row
+            uint32_t cin = carry, found = 0;
+#pragma unroll
+            for (int d = 1; d <= 3; ++d) {
+                const uint32_t h2 = __shfl(has, (lane - d) & 63, 64);
+                const uint32_t l2 = __shfl(last, (lane - d) & 63, 64);
+                if (!found && d <= g && h2) { cin = l2; found = 1; }
+            }
+            // new row carry: last marker of the whole row so far
+            uint32_t rc = carry;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const uint32_t h2 = __shfl(has, (lane & ~3) | d, 64);
+                const uint32_t l2 = __shfl(last, (lane & ~3) | d, 64);
+                if (h2) rc = l2;
+            }
+            carry = rc;
+            uint32_t outw[4] = {0, 0, 0, 0};
+            uint32_t cur = cin;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const uint32_t v = (pk[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+                const bool marker = ((v >> 8) & 1u) || (tx == 0 && g == 0 && k == 0);
+                uint32_t px = v & 0xFFu;
+                if (marker) cur = px & mask;
+                else px = (px & ~mask) | cur;
+                outw[k >> 2] |= px << (8 * (k & 3));
+            }
+            const uint64_t oidx = (uint64_t)(ty * kTile + r) * (uint64_t)J.N + (uint64_t)(tx * kTile + 16 * g);
+            *reinterpret_cast<uint4 *>(J.out + oidx) = make_uint4(outw[0], outw[1], outw[2], outw[3]);
+        }
+        __syncthreads();
+    }
+}
+
+// ---- launchers ---------------------------------------------------------------
+static inline unsigned grid_for(const Launch &L, uint32_t units) {
+    uint32_t g = units;
+    if (L.max_grid > 0 && g > (uint32_t)L.max_grid) g = (uint32_t)L.max_grid;
+    return g ? g : 1;
+}
+
+void launch_tile_prep(const Launch &L, uint32_t units, bool stats) {
+    if (!units) return;
+    const uint32_t *UJ = L.ujob[UNIT_TILE];
+    if (stats)
+        hipLaunchKernelGGL(k_tile_prep<true>, dim3(grid_for(L, units)), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+    else
+        hipLaunchKernelGGL(k_tile_prep<false>, dim3(grid_for(L, units)), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+}
+
+void launch_finalize(const Launch &L, bool stats) {
+    if (!L.njobs) return;
+    const unsigned g = grid_for(L, (uint32_t)L.njobs);
+    if (stats)
+        hipLaunchKernelGGL(k_finalize<true>, dim3(g), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, L.ws);
+    else
+        hipLaunchKernelGGL(k_finalize<false>, dim3(g), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, L.ws);
+}
+
+void launch_encrypt_tiles(const Launch &L, uint32_t units, int mode) {
+    if (!units) return;
+    const uint32_t *UJ = L.ujob[UNIT_TILE];
+    const dim3 gr(grid_for(L, units)), bl(kThreads);
+    if (mode == ENC_EMR) hipLaunchKernelGGL(k_encrypt_tile<ENC_EMR>, gr, bl, 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+    else if (mode == ENC_LMR) hipLaunchKernelGGL(k_encrypt_tile<ENC_LMR>, gr, bl, 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+    else hipLaunchKernelGGL(k_encrypt_tile<ENC_LMR_MAPS>, gr, bl, 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+}
+
+void launch_recover_bands(const Launch &L, uint32_t units, int method) {
+    if (!units) return;
+    const uint32_t *UJ = L.ujob[UNIT_BAND];
+    const dim3 gr(grid_for(L, units)), bl(kThreads);
+    if (method == RDHEI_EMR) hipLaunchKernelGGL(k_recover_band<RDHEI_EMR>, gr, bl, 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+    else hipLaunchKernelGGL(k_recover_band<RDHEI_LMR>, gr, bl, 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+}
+
+}  // namespace rdhei

@@ -1,0 +1,292 @@
+"""Python binding of librdhei (argument marshalling only).
+
+Every stage runs in the HIP library; this module converts torch tensors to
+device pointers and forwards to the C ABI declared in ``include/rdhei.h``.
+Importing it without a built ``librdhei.so`` raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librdhei.so")
+
+OK, EINVAL, ECAPACITY, ENOFIT, ENOMEM, EDEVICE, ECORRUPT = 0, -1, -2, -3, -4, -5, -6
+EMR, LMR = 0, 1
+OP_ENCRYPT, OP_EMBED, OP_EXTRACT, OP_RECOVER = 0, 1, 2, 3
+PLAN_GRAPH, PLAN_EAGER, PLAN_PER_IMAGE = 0, 1, 2
+OPT_PER_PIXEL, OPT_MAX_GRID = 1, 2
+META_BYTES = 64
+
+EXPORTS = [
+    "rdhei_ctx_create", "rdhei_ctx_destroy", "rdhei_ctx_set_option",
+    "rdhei_encrypt", "rdhei_embed", "rdhei_extract", "rdhei_recover",
+    "rdhei_plan_create", "rdhei_plan_run", "rdhei_plan_destroy", "rdhei_plan_set_grid",
+    "rdhei_plan_stage_count", "rdhei_plan_stage_name", "rdhei_plan_run_stage",
+    "rdhei_lmr_compress", "rdhei_lmr_decompress",
+    "rdhei_strerror", "rdhei_last_error", "rdhei_version",
+]
+
+
+class RdheiError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(what)
+
+
+class MetaStruct(ctypes.Structure):
+    _fields_ = [("height", ctypes.c_int32), ("width", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("b", ctypes.c_int32), ("min_level", ctypes.c_int32), ("max_level", ctypes.c_int32),
+                ("redundant", ctypes.c_int64), ("capacity_bits", ctypes.c_int64), ("map_bits", ctypes.c_int64),
+                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+assert ctypes.sizeof(MetaStruct) == META_BYTES
+
+
+class JobStruct(ctypes.Structure):
+    _fields_ = [("inp", ctypes.c_void_p), ("out", ctypes.c_void_p), ("msg", ctypes.c_void_p),
+                ("meta", ctypes.c_void_p), ("key", ctypes.c_uint64), ("nbits", ctypes.c_int64),
+                ("height", ctypes.c_int32), ("width", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load librdhei.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"librdhei.so not found at {path}: build it with "
+                           "`python -m paper_2302_07992_amd.build` (no CPU fallback exists)")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    lib.rdhei_ctx_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+    lib.rdhei_ctx_destroy.argtypes = [vp]
+    lib.rdhei_ctx_destroy.restype = None
+    lib.rdhei_ctx_set_option.argtypes = [vp, i32, i64]
+    lib.rdhei_encrypt.argtypes = [vp, vp, vp, i32, i32, u64, i32, vp, vp]
+    lib.rdhei_embed.argtypes = [vp, vp, i32, i32, i32, vp, vp, i64, u64, vp]
+    lib.rdhei_extract.argtypes = [vp, vp, i32, i32, i32, vp, vp, i64, u64, vp]
+    lib.rdhei_recover.argtypes = [vp, vp, i32, i32, i32, vp, vp, u64, vp]
+    lib.rdhei_plan_create.argtypes = [vp, i32, ctypes.POINTER(JobStruct), i32, i32, ctypes.POINTER(vp)]
+    lib.rdhei_plan_run.argtypes = [vp, vp]
+    lib.rdhei_plan_destroy.argtypes = [vp]
+    lib.rdhei_plan_destroy.restype = None
+    lib.rdhei_plan_set_grid.argtypes = [vp, i32]
+    lib.rdhei_plan_stage_count.argtypes = [vp]
+    lib.rdhei_plan_stage_name.argtypes = [vp, i32]
+    lib.rdhei_plan_stage_name.restype = ctypes.c_char_p
+    lib.rdhei_plan_run_stage.argtypes = [vp, i32, vp]
+    lib.rdhei_lmr_compress.argtypes = [vp, vp, i32, i32, vp, i64, ctypes.POINTER(i64)]
+    lib.rdhei_lmr_decompress.argtypes = [vp, i64, i32, i32, vp, vp]
+    lib.rdhei_strerror.argtypes = [ctypes.c_int]
+    lib.rdhei_strerror.restype = ctypes.c_char_p
+    lib.rdhei_last_error.argtypes = []
+    lib.rdhei_last_error.restype = ctypes.c_char_p
+    lib.rdhei_version.argtypes = []
+    lib.rdhei_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != OK:
+        lib = load_library()
+        raise RdheiError(rc, f"{what}: {lib.rdhei_strerror(rc).decode()} {lib.rdhei_last_error().decode()}")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def msg_bytes(nbits: int) -> int:
+    """Bytes a message buffer needs: ceil(nbits / 128) * 16 (at least 16)."""
+    return max(16, (nbits + 127) // 128 * 16)
+
+
+def new_meta(n: Optional[int] = None, device="cuda") -> torch.Tensor:
+    shape = (META_BYTES,) if n is None else (n, META_BYTES)
+    return torch.zeros(shape, dtype=torch.uint8, device=device)
+
+
+@dataclass
+class Meta:
+    height: int
+    width: int
+    method: int
+    b: int
+    min_level: int
+    max_level: int
+    redundant: int
+    capacity_bits: int
+    map_bits: int
+    status: int
+
+
+def read_meta(t: torch.Tensor):
+    """Decode one (64,) or many (n, 64) meta records (copies to host)."""
+    a = t.detach().to("cpu").contiguous().numpy()
+    rows = a.reshape(-1, META_BYTES)
+    out = []
+    for r in rows:
+        m = MetaStruct.from_buffer_copy(r.tobytes())
+        out.append(Meta(m.height, m.width, m.method, m.b, m.min_level, m.max_level, m.redundant,
+                        m.capacity_bits, m.map_bits, m.status))
+    return out[0] if a.ndim == 1 else out
+
+
+def read_meta_array(t: torch.Tensor) -> np.ndarray:
+    """Vectorised decode of (n, 64) metas: structured numpy array."""
+    dt = np.dtype([("height", "<i4"), ("width", "<i4"), ("method", "<i4"), ("b", "<i4"), ("min_level", "<i4"),
+                   ("max_level", "<i4"), ("redundant", "<i8"), ("capacity_bits", "<i8"), ("map_bits", "<i8"),
+                   ("status", "<i4"), ("reserved", "<i4", (3,))])
+    return t.detach().to("cpu").contiguous().numpy().reshape(-1).view(dt)
+
+
+class Context:
+    """A librdhei context on one GPU (owns the single-image workspace)."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load_library()
+        h = ctypes.c_void_p()
+        _check(self.lib.rdhei_ctx_create(ctypes.byref(h), device), "rdhei_ctx_create")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rdhei_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_option(self, option: int, value: int) -> None:
+        _check(self.lib.rdhei_ctx_set_option(self.h, option, value), "rdhei_ctx_set_option")
+
+    def encrypt(self, img: torch.Tensor, enc: torch.Tensor, k1: int, meta: torch.Tensor, method: int = EMR,
+                stream=None) -> None:
+        M, N = img.shape
+        _check(self.lib.rdhei_encrypt(self.h, _ptr(img), _ptr(enc), M, N, k1, method, _ptr(meta), _stream(stream)),
+               "rdhei_encrypt")
+
+    def embed(self, marked: torch.Tensor, meta: torch.Tensor, msg: torch.Tensor, nbits: int, k2: int,
+              method: int = EMR, stream=None) -> None:
+        M, N = marked.shape
+        _check(self.lib.rdhei_embed(self.h, _ptr(marked), M, N, method, _ptr(meta), _ptr(msg), nbits, k2,
+                                    _stream(stream)), "rdhei_embed")
+
+    def extract(self, marked: torch.Tensor, meta: torch.Tensor, msg: torch.Tensor, nbits: int, k2: int,
+                method: int = EMR, stream=None) -> None:
+        M, N = marked.shape
+        _check(self.lib.rdhei_extract(self.h, _ptr(marked), M, N, method, _ptr(meta), _ptr(msg), nbits, k2,
+                                      _stream(stream)), "rdhei_extract")
+
+    def recover(self, marked: torch.Tensor, meta: torch.Tensor, out: torch.Tensor, k1: int, method: int = EMR,
+                stream=None) -> None:
+        M, N = marked.shape
+        _check(self.lib.rdhei_recover(self.h, _ptr(marked), M, N, method, _ptr(meta), _ptr(out), k1,
+                                      _stream(stream)), "rdhei_recover")
+
+
+def make_jobs(ins: Sequence, outs: Sequence, msgs: Sequence, metas: Sequence, keys: Sequence[int],
+              nbits: Sequence[int], shapes: Sequence, method: int = EMR):
+    """Job array from per-image pointers (ints) or tensors (None allowed)."""
+    n = len(keys)
+    arr = (JobStruct * n)()
+
+    def p(x):
+        if x is None:
+            return None
+        return x if isinstance(x, int) else x.data_ptr()
+
+    for i in range(n):
+        arr[i].inp = p(ins[i]) if ins is not None else None
+        arr[i].out = p(outs[i]) if outs is not None else None
+        arr[i].msg = p(msgs[i]) if msgs is not None else None
+        arr[i].meta = p(metas[i])
+        arr[i].key = int(keys[i]) & ((1 << 64) - 1)
+        arr[i].nbits = int(nbits[i]) if nbits is not None else 0
+        arr[i].height, arr[i].width = int(shapes[i][0]), int(shapes[i][1])
+        arr[i].method = method
+        arr[i].reserved = 0
+    return arr
+
+
+class Plan:
+    """A reusable batched launch of one op (graph-captured by default)."""
+
+    def __init__(self, ctx: Context, op: int, jobs, flags: int = PLAN_GRAPH):
+        self.lib = ctx.lib
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        _check(self.lib.rdhei_plan_create(ctx.h, op, jobs, len(jobs), flags, ctypes.byref(h)), "rdhei_plan_create")
+        self.h = h
+        self.jobs = jobs
+
+    def set_grid(self, max_workgroups: int) -> None:
+        _check(self.lib.rdhei_plan_set_grid(self.h, max_workgroups), "rdhei_plan_set_grid")
+
+    def run(self, stream=None) -> None:
+        _check(self.lib.rdhei_plan_run(self.h, _stream(stream)), "rdhei_plan_run")
+
+    def stages(self):
+        n = self.lib.rdhei_plan_stage_count(self.h)
+        return [self.lib.rdhei_plan_stage_name(self.h, k).decode() for k in range(n)]
+
+    def run_stage(self, k: int, stream=None) -> None:
+        _check(self.lib.rdhei_plan_run_stage(self.h, k, _stream(stream)), "rdhei_plan_run_stage")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rdhei_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lmr_compress(eta_bits: np.ndarray, l_bits: np.ndarray, M: int, N: int, capacity_bytes: int):
+    """Host map coder: returns (stream bytes, stream bits) or raises RdheiError(ENOFIT)."""
+    lib = load_library()
+    eta = np.ascontiguousarray(eta_bits, dtype=np.uint8)
+    lb = np.ascontiguousarray(l_bits, dtype=np.uint8)
+    out = np.zeros(max(capacity_bytes, 8) + 16, dtype=np.uint8)
+    bits = ctypes.c_int64()
+    rc = lib.rdhei_lmr_compress(eta.ctypes.data, lb.ctypes.data, M, N, out.ctypes.data, capacity_bytes,
+                                ctypes.byref(bits))
+    _check(rc, "rdhei_lmr_compress")
+    return out[: bits.value // 8].copy(), bits.value
+
+
+def lmr_decompress(stream: np.ndarray, M: int, N: int):
+    lib = load_library()
+    s = np.ascontiguousarray(stream, dtype=np.uint8)
+    nb = (M * N + 7) // 8
+    eta = np.zeros(nb + 16, dtype=np.uint8)
+    lb = np.zeros(nb + 16, dtype=np.uint8)
+    _check(lib.rdhei_lmr_decompress(s.ctypes.data, s.size, M, N, eta.ctypes.data, lb.ctypes.data),
+           "rdhei_lmr_decompress")
+    return eta[:nb], lb[:nb]

@@ -1,0 +1,251 @@
+"""Parity of the HIP path with the CPU oracle, element by element (bit-exact:
+all arithmetic is integer).  Every case calls the C ABI through the Python
+binding; inputs come from the seeded generators and the oracle sees the very
+bytes the GPU consumed."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2302_07992_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+FAST_SHAPES = [(64, 64), (128, 192), (256, 256), (512, 512), (64, 1024), (192, 128)]
+RAGGED_SHAPES = [(1, 1), (1, 9), (3, 5), (7, 12), (16, 16), (33, 47), (100, 63), (130, 257), (64, 100)]
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2302_07992_amd import rdhei
+    return rdhei
+
+
+@pytest.fixture(scope="module")
+def ctx(R):
+    return R.Context(0)
+
+
+def _image(seed, M, N, sigma=3.0, nsin=8):
+    return inputs.make_image_np(seed, M, N, nsin, sigma)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _msg_dev(R, msg, nbits):
+    buf = torch.zeros(R.msg_bytes(nbits), dtype=torch.uint8, device="cuda")
+    if msg.size:
+        buf[: msg.size] = torch.from_numpy(msg).cuda()
+    return buf
+
+
+def _roundtrip(R, ctx, I, k1, k2, frac=1.0):
+    M, N = I.shape
+    print(f"[emr roundtrip] shape={M}x{N} k1={k1}", flush=True)
+    Ie_o, mo = O.emr_encrypt(I, k1)
+    d_img = _dev(I)
+    d_enc = torch.empty_like(d_img)
+    meta = R.new_meta()
+    ctx.encrypt(d_img, d_enc, k1, meta)
+    torch.cuda.synchronize()
+    m = R.read_meta(meta)
+    assert (m.status, m.b, m.redundant, m.capacity_bits) == (0, mo.b, mo.redundant, mo.capacity_bits)
+    assert (m.min_level, m.max_level) == (mo.min_level, mo.max_level)
+    Ie = d_enc.cpu().numpy()
+    mism = np.argwhere(Ie != Ie_o)
+    assert mism.size == 0, f"encrypt mismatch at {mism[:5].tolist()} of {len(mism)}"
+
+    nbits = int(mo.capacity_bits * frac)
+    msg = inputs.make_payload(k2, nbits).numpy()
+    Iem_o = O.emr_embed(Ie_o, mo.b, msg, nbits, k2)
+    ctx.embed(d_enc, meta, _msg_dev(R, msg, nbits), nbits, k2)
+    torch.cuda.synchronize()
+    assert R.read_meta(meta).status == 0
+    Iem = d_enc.cpu().numpy()
+    mism = np.argwhere(Iem != Iem_o)
+    assert mism.size == 0, f"embed mismatch at {mism[:5].tolist()} of {len(mism)}"
+
+    d_out = torch.full((R.msg_bytes(nbits),), 0xAB, dtype=torch.uint8, device="cuda")
+    ctx.extract(d_enc, meta, d_out, nbits, k2)
+    got = d_out.cpu().numpy()
+    nb = (nbits + 7) // 8
+    assert np.array_equal(got[:nb], O.emr_extract(Iem_o, mo.b, nbits, k2))
+    assert np.array_equal(got[:nb], msg[:nb])
+    assert not got[nb:(nbits + 31) // 32 * 4].any()
+
+    d_rec = torch.empty_like(d_img)
+    ctx.recover(d_enc, meta, d_rec, k1)
+    rec = d_rec.cpu().numpy()
+    rec_o = O.emr_recover(Iem_o, mo.b, k1)
+    mism = np.argwhere(rec != rec_o)
+    assert mism.size == 0, f"recover mismatch at {mism[:5].tolist()} of {len(mism)}"
+    assert np.array_equal(rec >> 1, I >> 1)
+
+
+@pytest.mark.parametrize("shape", FAST_SHAPES, ids=lambda s: f"{s[0]}x{s[1]}")
+def test_emr_fast_path_matches_oracle(R, ctx, shape):
+    M, N = shape
+    I = _image(M * 7 + N, M, N)
+    _roundtrip(R, ctx, I, 11 + M, 22 + N)
+
+
+@pytest.mark.parametrize("shape", RAGGED_SHAPES, ids=lambda s: f"{s[0]}x{s[1]}")
+def test_emr_per_pixel_path_matches_oracle(R, ctx, shape):
+    M, N = shape
+    I = _image(M * 5 + N, M, N, sigma=8.0)
+    _roundtrip(R, ctx, I, 3 + M, 4 + N)
+
+
+@pytest.mark.parametrize("frac", [0.0, 0.01, 0.37, 0.999])
+def test_emr_partial_messages(R, ctx, frac):
+    I = _image(91, 256, 320)
+    _roundtrip(R, ctx, I, 5, 6, frac=frac)
+
+
+@pytest.mark.parametrize("shape", [(1024, 512), (1024, 1024), (640, 1088), (1000, 777)],
+                         ids=lambda s: f"{s[0]}x{s[1]}")
+def test_emr_multi_segment_images(R, ctx, shape):
+    """Images spanning several raster segments (count pass, per-image scan,
+    message words shared by two segments)."""
+    M, N = shape
+    I = _image(M + N, M, N, sigma=2.0)
+    for frac in (1.0, 0.6):
+        _roundtrip(R, ctx, I, 7 + M, 9 + N, frac=frac)
+
+
+def test_fast_and_per_pixel_paths_agree(R):
+    ctx2 = R.Context(0)
+    ctx2.set_option(R.OPT_PER_PIXEL, 1)
+    I = _image(5, 256, 192)
+    d_img = _dev(I)
+    outs = []
+    for c in (R.Context(0), ctx2):
+        d_enc = torch.empty_like(d_img)
+        meta = R.new_meta()
+        c.encrypt(d_img, d_enc, 77, meta)
+        d_rec = torch.empty_like(d_img)
+        c.recover(d_enc, meta, d_rec, 77)
+        torch.cuda.synchronize()
+        outs.append((d_enc.cpu().numpy(), d_rec.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_capacity_exceeded_sets_status(R, ctx):
+    I = _image(8, 64, 64)
+    d_img = _dev(I)
+    d_enc = torch.empty_like(d_img)
+    meta = R.new_meta()
+    ctx.encrypt(d_img, d_enc, 1, meta)
+    torch.cuda.synchronize()
+    cap = R.read_meta(meta).capacity_bits
+    before = d_enc.clone()
+    ctx.embed(d_enc, meta, torch.zeros(R.msg_bytes(cap + 1), dtype=torch.uint8, device="cuda"), cap + 1, 2)
+    torch.cuda.synchronize()
+    assert R.read_meta(meta).status == R.ECAPACITY
+    assert torch.equal(before, d_enc)
+
+
+def test_invalid_arguments_rejected_on_host(R, ctx):
+    d = torch.zeros(64, 64, dtype=torch.uint8, device="cuda")
+    meta = R.new_meta()
+    with pytest.raises(R.RdheiError):
+        ctx.encrypt(d, d, 1, meta)                 # aliasing input/output
+    with pytest.raises(R.RdheiError):
+        ctx.encrypt(d, torch.empty_like(d), 1, meta, method=7)
+
+
+def test_batched_plan_uneven_sizes_matches_oracle(R, ctx):
+    """One plan per op over images of different shapes (tiled and per-pixel
+    in the same launch), graph-captured, replayed twice."""
+    shapes = [(64, 64), (128, 64), (256, 256), (33, 47), (512, 512), (64, 192), (100, 63), (320, 256)]
+    imgs = [_image(100 + i, *s, sigma=(1, 3, 8, 20)[i % 4], nsin=2 + i) for i, s in enumerate(shapes)]
+    n = len(imgs)
+    d_in = [_dev(I) for I in imgs]
+    d_enc = [torch.empty_like(x) for x in d_in]
+    d_rec = [torch.empty_like(x) for x in d_in]
+    metas = R.new_meta(n)
+    k1s = [1000 + i for i in range(n)]
+    k2s = [2000 + i for i in range(n)]
+    jobs = R.make_jobs(d_in, d_enc, None, [metas[i] for i in range(n)], k1s, None, shapes)
+    enc_plan = R.Plan(ctx, R.OP_ENCRYPT, jobs)
+    enc_plan.run()
+    torch.cuda.synchronize()
+    ms = R.read_meta(metas)
+    oracle = [O.emr_encrypt(I, k) for I, k in zip(imgs, k1s)]
+    for i in range(n):
+        assert ms[i].b == oracle[i][1].b and ms[i].capacity_bits == oracle[i][1].capacity_bits
+        assert np.array_equal(d_enc[i].cpu().numpy(), oracle[i][0]), f"image {i} {shapes[i]}"
+    caps = [m.capacity_bits for m in ms]
+    msgs = [inputs.make_payload(k, c).numpy() for k, c in zip(k2s, caps)]
+    d_msg = [_msg_dev(R, m, c) for m, c in zip(msgs, caps)]
+    emb = R.Plan(ctx, R.OP_EMBED, R.make_jobs(None, d_enc, d_msg, [metas[i] for i in range(n)], k2s, caps, shapes))
+    emb.run()
+    d_got = [torch.zeros(R.msg_bytes(c), dtype=torch.uint8, device="cuda") for c in caps]
+    ext = R.Plan(ctx, R.OP_EXTRACT, R.make_jobs(d_enc, None, d_got, [metas[i] for i in range(n)], k2s, caps, shapes))
+    ext.run()
+    rec = R.Plan(ctx, R.OP_RECOVER, R.make_jobs(d_enc, d_rec, None, [metas[i] for i in range(n)], k1s, None, shapes))
+    rec.run()
+    torch.cuda.synchronize()
+    for i in range(n):
+        Iem_o = O.emr_embed(oracle[i][0], oracle[i][1].b, msgs[i], caps[i], k2s[i])
+        assert np.array_equal(d_enc[i].cpu().numpy(), Iem_o)
+        nb = (caps[i] + 7) // 8
+        assert np.array_equal(d_got[i].cpu().numpy()[:nb], msgs[i])
+        assert np.array_equal(d_rec[i].cpu().numpy(), O.emr_recover(Iem_o, oracle[i][1].b, k1s[i]))
+    # replays give the same bytes (recover and extract are pure functions of I_e')
+    first = [x.clone() for x in d_rec]
+    for _ in range(2):
+        for x in d_got:
+            x.zero_()
+        ext.run()
+        rec.run()
+        torch.cuda.synchronize()
+        for i in range(n):
+            assert torch.equal(d_rec[i], first[i])
+            assert np.array_equal(d_got[i].cpu().numpy()[:(caps[i] + 7) // 8], msgs[i])
+
+
+def test_per_image_plan_matches_batched(R, ctx):
+    shapes = [(256, 256)] * 6 + [(64, 128)] * 3
+    imgs = [_image(300 + i, *s) for i, s in enumerate(shapes)]
+    d_in = [_dev(I) for I in imgs]
+    res = []
+    for flags in (R.PLAN_GRAPH, R.PLAN_EAGER, R.PLAN_PER_IMAGE):
+        d_enc = [torch.empty_like(x) for x in d_in]
+        metas = R.new_meta(len(imgs))
+        jobs = R.make_jobs(d_in, d_enc, None, [metas[i] for i in range(len(imgs))],
+                           [5 + i for i in range(len(imgs))], None, shapes)
+        R.Plan(ctx, R.OP_ENCRYPT, jobs, flags).run()
+        torch.cuda.synchronize()
+        res.append([x.cpu().numpy() for x in d_enc])
+    for a, b in zip(res[0], res[1]):
+        assert np.array_equal(a, b)
+    for a, b in zip(res[0], res[2]):
+        assert np.array_equal(a, b)
+
+
+def test_lmr_roundtrip_is_lossless(R, ctx):
+    """LMR on the GPU with the library's host coder: exact recovery and
+    error-free extraction (Sec. III-B)."""
+    for shape in [(256, 256), (128, 320), (100, 90)]:
+        M, N = shape
+        print(f"[lmr roundtrip] shape={M}x{N}", flush=True)
+        I = _image(M + 3 * N, M, N, sigma=1.0)
+        d_img = _dev(I)
+        d_enc = torch.empty_like(d_img)
+        meta = R.new_meta()
+        ctx.encrypt(d_img, d_enc, 31, meta, method=R.LMR)
+        m = R.read_meta(meta)
+        assert m.status == 0 and 2 <= m.b <= 8
+        nbits = m.capacity_bits
+        msg = inputs.make_payload(9, nbits).numpy()
+        ctx.embed(d_enc, meta, _msg_dev(R, msg, nbits), nbits, 41, method=R.LMR)
+        d_got = torch.zeros(R.msg_bytes(nbits), dtype=torch.uint8, device="cuda")
+        ctx.extract(d_enc, meta, d_got, nbits, 41, method=R.LMR)
+        assert np.array_equal(d_got.cpu().numpy()[:(nbits + 7) // 8], msg)
+        d_rec = torch.empty_like(d_img)
+        ctx.recover(d_enc, meta, d_rec, 31, method=R.LMR)
+        assert np.array_equal(d_rec.cpu().numpy(), I)
