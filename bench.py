@@ -148,10 +148,12 @@ def main():
         log(f"[bench] parity on {parity['checked']} sampled images: {parity['ok']}")
 
     # ---- per-stage timing (HIP events on the launch stream) ----
+    # algorithmic bytes per pixel of each stage: the keystream
+    # pyramid of recovery reads nothing; finalisation is per image
     per_px = {"encrypt": {"tile_prep_stats": 1.0, "encrypt_tiles": 2.0},
               "recover": {"recover_bands": 2.0},
-              "embed": {"embed": 2.0 + der / 8},
-              "extract": {"extract": 1.0 + der / 8}}
+              "embed": {"embed_images": 2.0 + der / 8, "embed": 2.0 + der / 8},
+              "extract": {"extract_images": 1.0 + der / 8, "extract": 1.0 + der / 8}}
     stages = []
     for k in order:
         p = plans[k]

@@ -89,7 +89,7 @@ struct Layout {
     std::vector<int> per_pixel;        // jobs on the per-pixel path
     uint64_t ws_bytes = 0;
     uint32_t units[UNIT_KINDS] = {0, 0, 0, 0};
-    bool multiseg = false;
+    uint64_t g_status = 0, g_ticket = 0, g_part = 0;   // hiding workspace (embed/extract)
     int op = 0;
     int method = RDHEI_EMR;
 };
@@ -145,19 +145,22 @@ int make_layout(int op, const rdhei_job *in, int n, bool force_per_pixel, Layout
             ws = align_up(ws + (J.fast ? tiles * kCodeRecord : generic_code_bytes(J.M, J.N, J.max_level)), 256);
             J.ws_pyr = ws;
             ws = align_up(ws + (J.fast ? pyr_bytes(J.M, J.N, J.max_level) : 0), 256);
+            J.ws_tmap = ws;
+            ws = align_up(ws + (J.fast ? tiles * 4 : 0), 256);
             J.ws_stats = ws;
             ws = align_up(ws + (J.fast ? tiles : 1) * kStatWords * 4 + 64, 256);
             if (q.method == RDHEI_LMR && !J.fast) {
                 J.ws_bytes = ws;
                 ws = align_up(ws + MN, 256);
             }
-        } else if (J.nseg > 1) {
-            J.ws_seg = ws;
-            ws = align_up(ws + 8ull * (uint64_t)J.nseg, 256);
-            L.multiseg = true;
         }
+        // hiding: whole small images go to one workgroup each (UNIT_IMG), large
+        // images are cut into look-back segments (UNIT_SEG)
+        const bool hide = op == RDHEI_OP_EMBED || op == RDHEI_OP_EXTRACT;
+        const bool whole = hide && J.nseg <= seq_max_segments() && MN % 16 == 0 && aligned16(J.in) && aligned16(J.out);
         const uint32_t cnt[UNIT_KINDS] = {J.fast ? (uint32_t)(J.tiles_x * J.tiles_y) : 0u,
-                                          J.fast ? (uint32_t)J.tiles_y : 0u, (uint32_t)J.nseg, 1u};
+                                          J.fast ? (uint32_t)J.tiles_y : 0u,
+                                          hide && !whole ? (uint32_t)J.nseg : 0u, whole ? 1u : 0u};
         for (int k = 0; k < UNIT_KINDS; ++k) {
             J.ubase[k] = L.units[k];
             J.ucount[k] = cnt[k];
@@ -165,8 +168,13 @@ int make_layout(int op, const rdhei_job *in, int n, bool force_per_pixel, Layout
         }
         if (rot && !J.fast) L.per_pixel.push_back(i);
         if (n > 1)
-            for (int k = 0; k < UNIT_KINDS - 1; ++k) L.ujob[k].insert(L.ujob[k].end(), cnt[k], (uint32_t)i);
+            for (int k = 0; k < UNIT_KINDS; ++k) L.ujob[k].insert(L.ujob[k].end(), cnt[k], (uint32_t)i);
         L.jobs.push_back(J);
+    }
+    if (op == RDHEI_OP_EMBED || op == RDHEI_OP_EXTRACT) {
+        uint64_t end;
+        hide_ws_layout(L.units[UNIT_SEG], ws, L.g_status, L.g_ticket, L.g_part, end);
+        ws = end;
     }
     L.ws_bytes = std::max<uint64_t>(ws, 256);
     return RDHEI_OK;
@@ -211,13 +219,11 @@ std::vector<Stage> stages_of(const Layout &Ly, const uint32_t *units_in, std::ve
                              for (int j : pp) launch_generic_recover(L, j, hj[j]);
                          }});
     } else if (op == RDHEI_OP_EMBED || op == RDHEI_OP_EXTRACT) {
-        if (Ly.multiseg) {
-            S.push_back({"segment_count", [=](const Launch &L) { launch_seg_count(L, us); }});
-            const int clear = op == RDHEI_OP_EXTRACT ? 1 : 0;
-            S.push_back({"segment_scan", [=](const Launch &L) { launch_seg_scan(L, clear); }});
-        }
-        if (op == RDHEI_OP_EMBED) S.push_back({"embed", [=](const Launch &L) { launch_embed(L, us); }});
-        else S.push_back({"extract", [=](const Launch &L) { launch_extract(L, us); }});
+        const uint32_t ui = units[UNIT_IMG];
+        const bool emb = op == RDHEI_OP_EMBED;
+        if (ui) S.push_back({emb ? "embed_images" : "extract_images", [=](const Launch &L) { launch_hide_images(L, ui, emb); }});
+        if (us && op == RDHEI_OP_EMBED) S.push_back({"embed", [=](const Launch &L) { launch_embed(L, us); }});
+        else if (us) S.push_back({"extract", [=](const Launch &L) { launch_extract(L, us); }});
     }
     return S;
 }
@@ -303,6 +309,9 @@ int stage(rdhei_ctx *ctx, const Layout &Ly, DevBuf &jobs, DevBuf &ws, hipStream_
     L.ws = ws.p;
     L.stream = st;
     L.max_grid = ctx->max_grid;
+    L.g_status = Ly.g_status;
+    L.g_ticket = Ly.g_ticket;
+    L.g_part = Ly.g_part;
     return RDHEI_OK;
 }
 
@@ -481,6 +490,9 @@ int plan_issue(rdhei_plan *P, hipStream_t st) {
     L.stream = st;
     L.max_grid = P->max_grid;
     const Layout &Ly = P->layout;
+    L.g_status = Ly.g_status;
+    L.g_ticket = Ly.g_ticket;
+    L.g_part = Ly.g_part;
     if (P->flags == RDHEI_PLAN_PER_IMAGE) {
         const Job *tables = reinterpret_cast<const Job *>(P->single.p);
         for (size_t j = 0; j < P->per_image.size(); ++j) {
@@ -635,7 +647,6 @@ int rdhei_plan_create(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t
             Layout one;
             one.op = P->layout.op;
             one.method = P->layout.method;
-            one.multiseg = h.nseg > 1;
             one.jobs.push_back(h);
             const bool pp = !h.fast && (one.op == RDHEI_OP_ENCRYPT || one.op == RDHEI_OP_RECOVER);
             P->per_image.push_back(stages_of(one, h.ucount, pp ? std::vector<int>{0} : std::vector<int>{}));
@@ -693,6 +704,9 @@ int rdhei_plan_run_stage(rdhei_plan *P, int32_t k, void *stream) {
     if (rc) return rc;
     Launch L = P->base;
     L.njobs = (int32_t)P->layout.jobs.size();
+    L.g_status = P->layout.g_status;
+    L.g_ticket = P->layout.g_ticket;
+    L.g_part = P->layout.g_part;
     L.ws = P->ws.p;
     L.stream = reinterpret_cast<hipStream_t>(stream);
     L.max_grid = P->max_grid;

@@ -5,6 +5,30 @@
 
 namespace rdhei {
 
+// ---- Global-memory access ------------------------------------------------------
+// Loads and stores through address-space-1 pointers compile to global_* (not
+// flat_*) instructions, whose completion is counted on vmcnt only; flat
+// accesses also hold up every wait on scalar and LDS results.
+template <typename T>
+__device__ __forceinline__ T gload(const void *p) {
+    return *(const __attribute__((address_space(1))) T *)(p);
+}
+template <typename T>
+__device__ __forceinline__ void gstore(void *p, T v) {
+    *(__attribute__((address_space(1))) T *)(p) = v;
+}
+typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
+template <>
+__device__ __forceinline__ uint4 gload<uint4>(const void *p) {
+    const v4u32 v = *(const __attribute__((address_space(1))) v4u32 *)(p);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+template <>
+__device__ __forceinline__ void gstore<uint4>(void *p, uint4 v) {
+    const v4u32 w = {v.x, v.y, v.z, v.w};
+    *(__attribute__((address_space(1))) v4u32 *)(p) = w;
+}
+
 // ---- Keystream ---------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64
 // multiplies, key bumped by the Weyl constants between rounds.  The paper only
@@ -43,6 +67,14 @@ __device__ __forceinline__ uint32_t stream_byte(uint64_t key, uint32_t domain, u
     U4 v = stream_block(key, domain, idx >> 4);
     uint32_t w = ((idx >> 2) & 3) == 0 ? v.x : ((idx >> 2) & 3) == 1 ? v.y : ((idx >> 2) & 3) == 2 ? v.z : v.w;
     return (w >> (8 * (idx & 3))) & 0xFFu;
+}
+
+// Values that decide whether a workgroup reaches a barrier are made
+// wave-uniform (readfirstlane), so the compiler keeps that control flow scalar
+// instead of building exec-mask loops around the barriers.
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+    return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
 }
 
 // ---- Batches -----------------------------------------------------------------
@@ -115,6 +147,17 @@ __device__ __forceinline__ void upper_walk(const Job &J, const uint8_t *pyr, int
     dy = (int)cy;
     dx = (int)cx;
     turns = o & 3u;
+}
+
+// Tile-map entry: destination tile row (bits 0..13), column (bits 14..27) and
+// quarter turns of the content (bits 28..29).
+__device__ __forceinline__ uint32_t tmap_pack(int dy, int dx, uint32_t turns) {
+    return (uint32_t)dy | ((uint32_t)dx << 14) | (turns << 28);
+}
+__device__ __forceinline__ void tmap_unpack(uint32_t v, int &dy, int &dx, uint32_t &turns) {
+    dy = (int)(v & 0x3FFFu);
+    dx = (int)((v >> 14) & 0x3FFFu);
+    turns = (v >> 28) & 3u;
 }
 
 // Destinations inside the tile of the 16 pixels of 4x4 block (by, bx), given

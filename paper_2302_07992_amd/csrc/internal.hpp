@@ -54,8 +54,8 @@ struct Job {
     uint32_t ucount[UNIT_KINDS];
     uint64_t ws_codes;        // tile code records (fast) / all-level codes (per-pixel path)
     uint64_t ws_pyr;          // tile sums + upper levels (fast path)
+    uint64_t ws_tmap;         // per tile: destination tile and quarter turns (fast path)
     uint64_t ws_stats;        // statistics records
-    uint64_t ws_seg;          // per-segment counts and offsets (2 x nseg u32)
     uint64_t ws_bytes;        // per-pixel path: byte-per-pixel scratch
 };
 
@@ -71,15 +71,17 @@ struct Launch {
     uint8_t *ws;              // device workspace base
     hipStream_t stream;
     int max_grid;             // cap on workgroups of a grid-stride launch
+    uint64_t g_status = 0, g_ticket = 0, g_part = 0;   // launch-wide hiding workspace offsets
 };
 
 void launch_tile_prep(const Launch &L, uint32_t units, bool stats);
 void launch_finalize(const Launch &L, bool stats);
 void launch_encrypt_tiles(const Launch &L, uint32_t units, int mode);
 void launch_recover_bands(const Launch &L, uint32_t units, int method);
-void launch_seg_count(const Launch &L, uint32_t units);
-void launch_seg_scan(const Launch &L, int clear_shared);
 uint64_t seg_pixels();
+int seq_max_segments();
+void launch_hide_images(const Launch &L, uint32_t units, bool embed);
+void hide_ws_layout(uint32_t units, uint64_t base, uint64_t &status, uint64_t &ticket, uint64_t &part, uint64_t &end);
 void launch_embed(const Launch &L, uint32_t units);
 void launch_extract(const Launch &L, uint32_t units);
 // per-pixel path, one image (job index j of the table; host copy h)

@@ -4,20 +4,29 @@
 // top..top-rep+1 (rep = b for EMR, b-1 for LMR), so a pixel's bit offset is
 // rep times the number of redundant pixels before it: a prefix sum.
 //
-// Each workgroup walks one raster segment chunk by chunk (4096 pixels, 16 per
-// thread) with a workgroup scan; segments of one image get their starting
-// ranks from a count pass and a per-image scan.
+// Single pass over the image: each workgroup takes the next 16384-pixel
+// raster segment by ticket, counts its redundant pixels, and learns the count
+// before it from its predecessors by decoupled look-back (Merrill & Garland,
+// "Single-pass parallel prefix scan with decoupled look-back", 2016).  Tickets
+// hand segments out in order, so a workgroup only ever waits on segments
+// already owned by running workgroups.  The wait is bounded: past a spin limit
+// the image is flagged RDHEI_EDEVICE instead of waiting forever.
 #include "device.hpp"
 
 namespace rdhei {
 
-constexpr int kSegChunks = 64;                       // 64 chunks = 262144 pixels
-constexpr uint64_t kSegPx = (uint64_t)kSegChunks * kChunk;
-constexpr int kWinWords = (kChunk * 7 + 127) / 128 * 4 + 8;   // payload window of one chunk
+constexpr int kSegLoads = 4;                                       // 16-byte loads per thread
+constexpr uint64_t kSegPx = (uint64_t)kThreads * 16 * kSegLoads;   // 16384 pixels
+constexpr int kWinWords = (int)((kSegPx * 7 + 127) / 128) * 4 + 8; // payload window (words)
+constexpr uint32_t kSpinLimit = 1u << 24;
+
+// status word of a segment: bit 63 = inclusive prefix ready, bit 62 =
+// aggregate ready, low 62 bits = the value.
+constexpr uint64_t kAgg = 1ull << 62, kInc = 1ull << 63, kValMask = kAgg - 1;
 
 struct HideParams {
     uint32_t rep, shift;      // replaceable bits per redundant pixel, position of the lowest
-    int64_t nbits;            // bits requested (already resolved against the capacity)
+    int64_t nbits;            // bits requested (resolved against the capacity)
     bool ok;
 };
 
@@ -30,13 +39,17 @@ __device__ __forceinline__ HideParams hide_params(const Job &J) {
     const int64_t cap = m->capacity_bits;
     h.nbits = J.nbits < 0 ? cap : J.nbits;
     h.ok = (m->status == RDHEI_OK) && h.nbits <= cap;
+    h.rep = uni(h.rep);
+    h.shift = uni(h.shift);
+    h.nbits = (int64_t)uni64((uint64_t)h.nbits);
+    h.ok = uni(h.ok ? 1u : 0u) != 0;
     return h;
 }
 
-// 16 pixels starting at raster index pos (multiple of 16) of an image of
-// `total` pixels; pixels past the end read as 0x01 (never redundant).
+// 16 pixels at raster index pos (multiple of 16) of an image of `total`
+// pixels; pixels past the end read as 0x01 (never redundant).
 __device__ __forceinline__ uint4 load16(const uint8_t *img, uint64_t pos, uint64_t total) {
-    if (pos + 16 <= total) return *reinterpret_cast<const uint4 *>(img + pos);
+    if (pos + 16 <= total) return gload<uint4>(img + pos);
     uint32_t w[4] = {0x01010101u, 0x01010101u, 0x01010101u, 0x01010101u};
     for (int k = 0; k < 16; ++k)
         if (pos + k < total) w[k >> 2] = (w[k >> 2] & ~(0xFFu << (8 * (k & 3)))) | ((uint32_t)img[pos + k] << (8 * (k & 3)));
@@ -44,7 +57,7 @@ __device__ __forceinline__ uint4 load16(const uint8_t *img, uint64_t pos, uint64
 }
 
 __device__ __forceinline__ void store16(uint8_t *img, uint64_t pos, uint64_t total, uint4 v) {
-    if (pos + 16 <= total) { *reinterpret_cast<uint4 *>(img + pos) = v; return; }
+    if (pos + 16 <= total) { gstore<uint4>(img + pos, v); return; }
     const uint32_t w[4] = {v.x, v.y, v.z, v.w};
     for (int k = 0; k < 16; ++k)
         if (pos + k < total) img[pos + k] = (uint8_t)(w[k >> 2] >> (8 * (k & 3)));
@@ -53,34 +66,42 @@ __device__ __forceinline__ void store16(uint8_t *img, uint64_t pos, uint64_t tot
 // Redundancy mask of 16 pixels: bit k set when pixel pos+k is labelled 0.
 __device__ __forceinline__ uint32_t redundant16(const Job &J, uint4 px, uint64_t pos, uint64_t total) {
     uint32_t m = 0;
+    if (pos >= total) return 0u;
     if (J.method == RDHEI_EMR) {
-        const uint32_t w[4] = {px.x, px.y, px.z, px.w};
+        // LSB 0 -> redundant: gather the inverted LSB of each byte
+        const uint32_t w[4] = {~px.x & 0x01010101u, ~px.y & 0x01010101u, ~px.z & 0x01010101u, ~px.w & 0x01010101u};
 #pragma unroll
-        for (int k = 0; k < 16; ++k) m |= ((~(w[k >> 2] >> (8 * (k & 3)))) & 1u) << k;
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t v = w[q] * 0x01020408u;   // byte k's bit -> bit 24 + k
+            m |= ((v >> 24) & 0xFu) << (4 * q);
+        }
     } else {
         const uint32_t be = ((uint32_t)J.lbits[pos >> 3] << 8) | (pos + 8 < total ? J.lbits[(pos >> 3) + 1] : 0xFFu);
 #pragma unroll
         for (int k = 0; k < 16; ++k) m |= ((~(be >> (15 - k))) & 1u) << k;
     }
-    if (pos + 16 > total) m &= (total > pos) ? ((1u << (uint32_t)(total - pos)) - 1u) : 0u;
+    if (pos + 16 > total) m &= (1u << (uint32_t)(total - pos)) - 1u;
     return m;
 }
 
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t &total, uint32_t *sh) {
+// Exclusive scan over the workgroup of four 16-bit counters packed in a u64
+// (field k = count of load k); returns the thread's exclusive prefix per field
+// and the workgroup totals per field.
+__device__ __forceinline__ uint64_t block_scan4(uint64_t v, uint64_t &total, uint64_t *sh) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t x = v;
+    uint64_t x = v;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(x, d, 64);
+        const uint64_t y = __shfl_up(x, d, 64);
         if (lane >= d) x += y;
     }
     if (lane == 63) sh[wave] = x;
     __syncthreads();
-    uint32_t base = 0, tot = 0;
+    uint64_t base = 0, tot = 0;
 #pragma unroll
     for (int w = 0; w < kThreads / 64; ++w) {
-        const uint32_t t = sh[w];
-        base += (w < wave) ? t : 0u;
+        const uint64_t t = sh[w];
+        base += (w < wave) ? t : 0ull;
         tot += t;
     }
     __syncthreads();
@@ -88,148 +109,208 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t &total,
     return base + x - v;
 }
 
-// ---- count pass: redundant pixels per segment (images with > 1 segment) ----
-__global__ __launch_bounds__(kThreads) void k_seg_count(const Job *__restrict__ jobs, int njobs,
-                                                         uint8_t *__restrict__ ws, uint32_t units,
-    const uint32_t *__restrict__ ujob) {
-    __shared__ uint32_t sh[kThreads / 64];
-    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
-        const int j = find_job<UNIT_SEG>(jobs, njobs, u, ujob);
-        const Job &J = jobs[j];
-        if (J.nseg <= 1) continue;
-        const uint32_t seg = u - J.ubase[UNIT_SEG];
-        const uint64_t total = (uint64_t)J.M * (uint64_t)J.N;
-        const uint64_t s0 = (uint64_t)seg * kSegPx;
-        const uint64_t s1 = s0 + kSegPx < total ? s0 + kSegPx : total;
-        uint32_t cnt = 0;
-        for (uint64_t pos = s0 + 16 * threadIdx.x; pos < s1; pos += kChunk) {
-            const uint4 px = load16(J.in ? J.in : J.out, pos, total);
-            cnt += __popc(redundant16(J, px, pos, total));
-        }
-        uint32_t tot;
-        block_excl_scan(cnt, tot, sh);
-        if (threadIdx.x == 0) reinterpret_cast<uint32_t *>(ws + J.ws_seg)[seg] = tot;
+// Publish a segment's aggregate, look back over its predecessors in the same
+// image, publish its inclusive prefix; returns the exclusive prefix.  Run by
+// all 64 lanes of one wave: each pass reads 64 predecessors at once and stops
+// at the nearest one that already holds an inclusive prefix.  A status word
+// carries its own value, so relaxed device-scope atomics suffice.
+__device__ uint64_t look_back(uint64_t *status, uint32_t u, uint32_t first_u, uint64_t agg, bool &timed_out) {
+    const int lane = threadIdx.x & 63;
+    timed_out = false;
+    if (u == first_u) {
+        if (lane == 0) __hip_atomic_store(&status[u], kInc | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return 0;
     }
+    if (lane == 0) __hip_atomic_store(&status[u], kAgg | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t prefix = 0;
+    int64_t base = (int64_t)u - 1;          // this pass covers base, base-1, ..., base-63
+    uint32_t spins = 0;
+    while (true) {
+        const int64_t idx = base - lane;
+        uint64_t s = kInc;                   // before the image's first segment: nothing to add
+        if (idx >= (int64_t)first_u)
+            s = __hip_atomic_load(&status[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t incl = __ballot((s & kInc) != 0);
+        const uint64_t ready = __ballot((s & (kInc | kAgg)) != 0);
+        const int d = incl ? __ffsll((unsigned long long)incl) - 1 : 64;   // nearest inclusive
+        const uint64_t need = d >= 63 ? ~0ull : ((2ull << d) - 1);
+        if ((ready & need) != need) {
+            if (++spins > kSpinLimit) { timed_out = true; break; }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        uint64_t v = (lane <= d) ? (s & kValMask) : 0ull;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        prefix += v;
+        if (d < 64) break;
+        base -= 64;
+    }
+    if (lane == 0)
+        __hip_atomic_store(&status[u], kInc | (prefix + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return prefix;
 }
 
-// ---- per-image exclusive scan of the segment counts ---------------------------
-// Also clears the message words that two segments share (both OR into them).
-__global__ __launch_bounds__(kThreads) void k_seg_scan(const Job *__restrict__ jobs, int njobs,
-                                                        uint8_t *__restrict__ ws, int clear_shared) {
-    __shared__ uint32_t sh[kThreads / 64];
-    for (int j = blockIdx.x; j < njobs; j += gridDim.x) {
-        const Job &J = jobs[j];
-        if (J.nseg <= 1) continue;
-        const HideParams hp = hide_params(J);
-        uint32_t *cnt = reinterpret_cast<uint32_t *>(ws + J.ws_seg);
-        uint32_t *off = cnt + J.nseg;
-        uint32_t carry = 0;
-        for (int base = 0; base < J.nseg; base += kThreads) {
-            const int s = base + threadIdx.x;
-            const uint32_t c = s < J.nseg ? cnt[s] : 0u;
-            uint32_t tot;
-            const uint32_t ex = block_excl_scan(c, tot, sh);
-            if (s < J.nseg) {
-                off[s] = carry + ex;
-                const int64_t B = (int64_t)hp.rep * (int64_t)(carry + ex);
-                if (clear_shared && hp.ok && s > 0 && (B & 31) && B < hp.nbits)
-                    reinterpret_cast<uint32_t *>(J.msg)[B >> 5] = 0u;
-            }
-            carry += tot;
+// Resets the ticket counter and the segment status words of a launch.
+__global__ void k_hide_reset(uint64_t *status, uint32_t units, uint32_t *ticket) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < units) status[i] = 0;
+    if (i == 0) *ticket = 0;
+}
+
+// One segment's pixels, masks and ranks.
+struct SegState {
+    uint4 px[kSegLoads];
+    uint32_t rm[kSegLoads];
+    uint64_t rank[kSegLoads];   // rank (in the image) of the thread's first redundant pixel of load k
+    uint64_t seg_rank;          // redundant pixels before this segment
+    uint64_t seg_count;         // redundant pixels in this segment
+    uint64_t s0, s1, total;
+    bool timed_out;
+};
+
+// Load, count and look back for segment `seg` (work unit u) of job J.
+__device__ __forceinline__ void seg_count(const Job &J, const uint8_t *img, uint32_t u, uint32_t seg, uint64_t *status,
+                                          uint64_t *sh, uint64_t *shv, SegState &S) {
+    const int tid = threadIdx.x;
+    S.total = (uint64_t)J.M * (uint64_t)J.N;
+    S.s0 = (uint64_t)seg * kSegPx;
+    S.s1 = S.s0 + kSegPx < S.total ? S.s0 + kSegPx : S.total;
+#pragma unroll
+    for (int k = 0; k < kSegLoads; ++k) {
+        const uint64_t pos = S.s0 + (uint64_t)k * (kThreads * 16) + 16 * (uint64_t)tid;
+        S.px[k] = pos < S.s1 ? load16(img, pos, S.s1) : make_uint4(0x01010101u, 0x01010101u, 0x01010101u, 0x01010101u);
+    }
+    uint64_t packed = 0;
+#pragma unroll
+    for (int k = 0; k < kSegLoads; ++k) {
+        const uint64_t pos = S.s0 + (uint64_t)k * (kThreads * 16) + 16 * (uint64_t)tid;
+        S.rm[k] = redundant16(J, S.px[k], pos, S.s1);
+        packed |= (uint64_t)__popc(S.rm[k]) << (16 * k);
+    }
+    uint64_t tot;
+    const uint64_t ex = block_scan4(packed, tot, sh);
+    uint64_t chunk_base = 0;
+#pragma unroll
+    for (int k = 0; k < kSegLoads; ++k) {
+        S.rank[k] = chunk_base + ((ex >> (16 * k)) & 0xFFFFu);
+        chunk_base += (tot >> (16 * k)) & 0xFFFFu;
+    }
+    S.seg_count = uni64(chunk_base);
+    if (tid < 64) {
+        bool to;
+        const uint64_t pre = look_back(status, u, u - seg, chunk_base, to);
+        if (tid == 0) {
+            shv[0] = pre;
+            shv[1] = to ? 1u : 0u;
         }
+    }
+    __syncthreads();
+    S.seg_rank = uni64(shv[0]);
+    S.timed_out = uni((uint32_t)shv[1]) != 0;
+#pragma unroll
+    for (int k = 0; k < kSegLoads; ++k) S.rank[k] += S.seg_rank;
+    __syncthreads();
+}
+
+__device__ __forceinline__ uint32_t grab_ticket(uint32_t *ticket, uint32_t *sh_t) {
+    if (threadIdx.x == 0) *sh_t = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const uint32_t u = uni(*sh_t);
+    __syncthreads();
+    return u;
+}
+
+// Hide the payload bits that fall in one segment.  All branches that guard a
+// barrier test wave-uniform values.
+__device__ __forceinline__ void embed_unit(const Job &J, const HideParams &hp, uint32_t u, uint32_t seg,
+                                           uint64_t *status, uint64_t *sh, uint64_t *shv, uint32_t *win) {
+    const int tid = threadIdx.x;
+    SegState S;
+    seg_count(J, J.out, u, seg, status, sh, shv, S);
+    if (S.timed_out) {
+        if (tid == 0) J.meta->status = RDHEI_EDEVICE;
+        return;
+    }
+    const int64_t wstart = (int64_t)(S.seg_rank * hp.rep);
+    int64_t wend = (int64_t)((S.seg_rank + S.seg_count) * hp.rep);
+    if (wend > hp.nbits) wend = hp.nbits;
+    if (wstart >= wend) return;
+    // stage (payload XOR message keystream) for the window, 16-byte blocks, big-endian words
+    const int64_t fb = wstart >> 7, lb = (wend - 1) >> 7;
+    for (int64_t q = tid; q <= lb - fb; q += kThreads) {
+        const uint64_t blk = (uint64_t)(fb + q);
+        const uint4 mv = gload<uint4>(J.msg + 16 * blk);
+        const U4 ks = stream_block(J.key, kDomainMessage, blk);
+        uint32_t *wp = win + 4 * q;
+        wp[0] = __builtin_bswap32(mv.x ^ ks.x);
+        wp[1] = __builtin_bswap32(mv.y ^ ks.y);
+        wp[2] = __builtin_bswap32(mv.z ^ ks.z);
+        wp[3] = __builtin_bswap32(mv.w ^ ks.w);
+    }
+    __syncthreads();
+    const uint32_t top = hp.shift + hp.rep - 1;
+#pragma unroll
+    for (int k = 0; k < kSegLoads; ++k) {
+        const uint32_t rm = S.rm[k];
+        int64_t bit = (int64_t)(S.rank[k] * hp.rep);
+        if (!rm || bit >= wend) continue;
+        uint32_t w[4] = {S.px[k].x, S.px[k].y, S.px[k].z, S.px[k].w};
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            if (((rm >> q) & 1u) && bit < wend) {
+                const int64_t rel = bit - (fb << 7);
+                const uint32_t wi = (uint32_t)(rel >> 5), sb = (uint32_t)(rel & 31);
+                const uint64_t v64 = ((uint64_t)win[wi] << 32) | win[wi + 1];
+                const uint32_t val = (uint32_t)((v64 << sb) >> (64 - hp.rep));
+                const int64_t left = wend - bit;
+                const uint32_t take = left < (int64_t)hp.rep ? (uint32_t)left : hp.rep;
+                const uint32_t wmask = ((1u << take) - 1u) << (top + 1 - take);
+                const uint32_t sh8 = 8 * (q & 3);
+                w[q >> 2] = (w[q >> 2] & ~(wmask << sh8)) | (((val << hp.shift) & wmask) << sh8);
+                bit += hp.rep;
+            }
+        }
+        const uint64_t pos = S.s0 + (uint64_t)k * (kThreads * 16) + 16 * (uint64_t)tid;
+        store16(J.out, pos, S.s1, make_uint4(w[0], w[1], w[2], w[3]));
     }
 }
 
 // ---- embedding -------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_embed(const Job *__restrict__ jobs, int njobs,
-                                                     uint8_t *__restrict__ ws, uint32_t units,
-    const uint32_t *__restrict__ ujob) {
-    __shared__ uint32_t sh[kThreads / 64];
+__global__ __launch_bounds__(kThreads) void k_embed(const Job *__restrict__ jobs, int njobs, uint32_t units,
+                                                     const uint32_t *__restrict__ ujob, uint64_t *__restrict__ status,
+                                                     uint32_t *__restrict__ ticket) {
+    __shared__ uint64_t sh[kThreads / 64];
+    __shared__ uint64_t shv[2];
+    __shared__ uint32_t sh_t;
     __shared__ uint32_t win[kWinWords];
     const int tid = threadIdx.x;
-    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
-        const int j = find_job<UNIT_SEG>(jobs, njobs, u, ujob);
+    while (true) {
+        const uint32_t u = grab_ticket(ticket, &sh_t);
+        if (u >= units) break;
+        const int j = (int)uni((uint32_t)find_job<UNIT_SEG>(jobs, njobs, u, ujob));
         const Job &J = jobs[j];
         const HideParams hp = hide_params(J);
         if (!hp.ok) {
             if (tid == 0 && u == J.ubase[UNIT_SEG] && J.meta->status == RDHEI_OK) J.meta->status = RDHEI_ECAPACITY;
-            continue;
+        } else {
+            embed_unit(J, hp, u, u - J.ubase[UNIT_SEG], status, sh, shv, win);
         }
-        const uint32_t seg = u - J.ubase[UNIT_SEG];
-        const uint64_t total = (uint64_t)J.M * (uint64_t)J.N;
-        const uint64_t s0 = (uint64_t)seg * kSegPx;
-        const uint64_t s1 = s0 + kSegPx < total ? s0 + kSegPx : total;
-        uint64_t rank = J.nseg > 1 ? reinterpret_cast<const uint32_t *>(ws + J.ws_seg)[J.nseg + seg] : 0u;
-        if ((int64_t)(rank * hp.rep) >= hp.nbits) continue;
-        uint8_t *img = J.out;
-        for (uint64_t c0 = s0; c0 < s1; c0 += kChunk) {
-            const uint64_t pos = c0 + 16 * (uint64_t)tid;
-            const bool mine = pos < s1;
-            const uint4 px = mine ? load16(img, pos, s1) : make_uint4(0x01010101u, 0x01010101u, 0x01010101u, 0x01010101u);
-            const uint32_t rm = mine ? redundant16(J, px, pos, s1) : 0u;
-            uint32_t tot;
-            const uint32_t ex = block_excl_scan(__popc(rm), tot, sh);
-            const int64_t wstart = (int64_t)(rank * hp.rep);
-            int64_t wend = (int64_t)((rank + tot) * hp.rep);
-            if (wend > hp.nbits) wend = hp.nbits;
-            if (wstart >= hp.nbits) break;
-            if (tot == 0) continue;
-            // stage payload XOR message keystream, 16-byte blocks, big-endian words
-            const int64_t fb = wstart >> 7, lb = (wend - 1) >> 7;
-            if (tid <= lb - fb) {
-                const uint64_t blk = (uint64_t)(fb + tid);
-                const uint4 mv = *reinterpret_cast<const uint4 *>(J.msg + 16 * blk);
-                const U4 ks = stream_block(J.key, kDomainMessage, blk);
-                uint32_t *wp = win + 4 * tid;
-                wp[0] = __builtin_bswap32(mv.x ^ ks.x);
-                wp[1] = __builtin_bswap32(mv.y ^ ks.y);
-                wp[2] = __builtin_bswap32(mv.z ^ ks.z);
-                wp[3] = __builtin_bswap32(mv.w ^ ks.w);
-            }
-            __syncthreads();
-            if (mine && rm) {
-                int64_t bit = (int64_t)((rank + ex) * hp.rep);
-                uint32_t w[4] = {px.x, px.y, px.z, px.w};
-                const uint32_t top = hp.shift + hp.rep - 1;
-#pragma unroll
-                for (int k = 0; k < 16; ++k) {
-                    if (((rm >> k) & 1u) && bit < wend) {
-                        const int64_t rel = bit - (fb << 7);
-                        const uint32_t wi = (uint32_t)(rel >> 5), sb = (uint32_t)(rel & 31);
-                        const uint64_t v64 = ((uint64_t)win[wi] << 32) | win[wi + 1];
-                        const uint32_t val = (uint32_t)((v64 << sb) >> (64 - hp.rep));
-                        const int64_t left = wend - bit;
-                        const uint32_t take = left < (int64_t)hp.rep ? (uint32_t)left : hp.rep;
-                        const uint32_t wmask = ((1u << take) - 1u) << (top + 1 - take);
-                        const uint32_t pv = (w[k >> 2] >> (8 * (k & 3))) & 0xFFu;
-                        const uint32_t nv = (pv & ~wmask) | ((val << hp.shift) & wmask);
-                        w[k >> 2] = (w[k >> 2] & ~(0xFFu << (8 * (k & 3)))) | (nv << (8 * (k & 3)));
-                        bit += hp.rep;
-                    }
-                }
-                store16(img, pos, s1, make_uint4(w[0], w[1], w[2], w[3]));
-            }
-            rank += tot;
-            __syncthreads();
-        }
+        __syncthreads();
     }
 }
 
-// ---- extraction -----------------------------------------------------------------
-// Store one finished message word (big-endian bit order in `be`), XORed with the
-// message keystream; `own` selects the bits this workgroup produced (the rest
-// is stored as zero).  Words two segments share are ORed into memory the scan
-// pass cleared.
-__device__ __forceinline__ void put_word(const Job &J, int64_t w, uint32_t be, uint32_t own, bool shared) {
-    const U4 ks = stream_block(J.key, kDomainMessage, (uint64_t)w >> 2);
-    const uint32_t kw = (w & 3) == 0 ? ks.x : (w & 3) == 1 ? ks.y : (w & 3) == 2 ? ks.z : ks.w;
-    const uint32_t v = (be ^ __builtin_bswap32(kw)) & own;
-    uint32_t *dst = reinterpret_cast<uint32_t *>(J.msg) + w;
-    if (shared) atomicOr(dst, __builtin_bswap32(v));
-    else *dst = __builtin_bswap32(v);
-}
+// ---- extraction -------------------------------------------------------------------
+// Message words a segment only partly owns (shared with a neighbouring
+// segment, or the message's last word) go to a side record; two small passes
+// clear, then OR them into place.
+struct PartWord {
+    int64_t word;      // word index into the message (-1: none)
+    uint32_t bits;     // already XORed with the keystream and masked to the owner's bits
+    uint32_t job;
+};
 
-// mask of BE bits [lo, hi) of word w (bit 0 of the stream = bit 31 of the word)
+// mask of big-endian bits [lo, hi) of word w (stream bit 0 = bit 31 of word 0)
 __device__ __forceinline__ uint32_t be_mask(int64_t w, int64_t lo, int64_t hi) {
     int64_t a = lo - 32 * w, b = hi - 32 * w;
     if (a < 0) a = 0;
@@ -240,68 +321,237 @@ __device__ __forceinline__ uint32_t be_mask(int64_t w, int64_t lo, int64_t hi) {
     return upto_b & ~upto_a;
 }
 
-__global__ __launch_bounds__(kThreads) void k_extract(const Job *__restrict__ jobs, int njobs,
-                                                       uint8_t *__restrict__ ws, uint32_t units,
-    const uint32_t *__restrict__ ujob) {
-    __shared__ uint32_t sh[kThreads / 64];
+// Message keystream word w, big-endian bit order.
+__device__ __forceinline__ uint32_t ks_word(uint64_t key, int64_t w) {
+    const U4 ks = stream_block(key, kDomainMessage, (uint64_t)w >> 2);
+    const uint32_t kw = (w & 3) == 0 ? ks.x : (w & 3) == 1 ? ks.y : (w & 3) == 2 ? ks.z : ks.w;
+    return __builtin_bswap32(kw);
+}
+
+// Extract the payload bits of one segment.
+__device__ __forceinline__ void extract_unit(const Job &J, const HideParams &hp, int j, uint32_t u, uint32_t seg,
+                                             uint64_t *status, uint64_t *sh, uint64_t *shv, uint32_t *win,
+                                             PartWord *part) {
+    const int tid = threadIdx.x;
+    SegState S;
+    seg_count(J, J.in, u, seg, status, sh, shv, S);
+    if (S.timed_out) {
+        if (tid == 0) J.meta->status = RDHEI_EDEVICE;
+        return;
+    }
+    const int64_t wstart = (int64_t)(S.seg_rank * hp.rep);
+    int64_t wend = (int64_t)((S.seg_rank + S.seg_count) * hp.rep);
+    if (wend > hp.nbits) wend = hp.nbits;
+    if (wstart >= wend) return;
+    const int64_t W0 = wstart >> 5, W1 = (wend + 31) >> 5;
+    for (int64_t q = tid; q < W1 - W0 + 1; q += kThreads) win[q] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSegLoads; ++k) {
+        const uint32_t rm = S.rm[k];
+        int64_t bit = (int64_t)(S.rank[k] * hp.rep);
+        if (!rm || bit >= wend) continue;
+        const uint32_t w[4] = {S.px[k].x, S.px[k].y, S.px[k].z, S.px[k].w};
+        int64_t cw = (bit >> 5) - W0;
+        uint32_t nacc = (uint32_t)(bit & 31);
+        uint64_t acc = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            if (((rm >> q) & 1u) && bit < wend) {
+                const uint32_t pv = (w[q >> 2] >> (8 * (q & 3))) & 0xFFu;
+                const int64_t left = wend - bit;
+                const uint32_t take = left < (int64_t)hp.rep ? (uint32_t)left : hp.rep;
+                const uint32_t val = (pv >> (hp.shift + hp.rep - take)) & ((1u << take) - 1u);
+                acc |= (uint64_t)val << (64 - nacc - take);
+                nacc += take;
+                bit += take;
+                if (nacc >= 32) {
+                    atomicOr(&win[cw], (uint32_t)(acc >> 32));
+                    ++cw;
+                    acc <<= 32;
+                    nacc -= 32;
+                }
+            }
+        }
+        if (nacc) atomicOr(&win[cw], (uint32_t)(acc >> 32));
+    }
+    __syncthreads();
+    uint32_t *msgw = reinterpret_cast<uint32_t *>(J.msg);
+    for (int64_t q = tid; q < W1 - W0; q += kThreads) {
+        const int64_t w = W0 + q;
+        const uint32_t own = be_mask(w, wstart, wend);
+        const uint32_t v = (win[q] ^ ks_word(J.key, w)) & own;
+        if (own == 0xFFFFFFFFu) {
+            gstore<uint32_t>(msgw + w, __builtin_bswap32(v));
+        } else {
+            PartWord pw;
+            pw.word = w;
+            pw.bits = __builtin_bswap32(v);
+            pw.job = (uint32_t)j;
+            part[2 * u + (w == W0 ? 0 : 1)] = pw;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_extract(const Job *__restrict__ jobs, int njobs, uint32_t units,
+                                                       const uint32_t *__restrict__ ujob, uint64_t *__restrict__ status,
+                                                       uint32_t *__restrict__ ticket, PartWord *__restrict__ part) {
+    __shared__ uint64_t sh[kThreads / 64];
+    __shared__ uint64_t shv[2];
+    __shared__ uint32_t sh_t;
     __shared__ uint32_t win[kWinWords];
     const int tid = threadIdx.x;
-    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
-        const int j = find_job<UNIT_SEG>(jobs, njobs, u, ujob);
+    while (true) {
+        const uint32_t u = grab_ticket(ticket, &sh_t);
+        if (u >= units) break;
+        if (tid < 2) part[2 * u + tid].word = -1;
+        const int j = (int)uni((uint32_t)find_job<UNIT_SEG>(jobs, njobs, u, ujob));
         const Job &J = jobs[j];
         const HideParams hp = hide_params(J);
         if (!hp.ok) {
             if (tid == 0 && u == J.ubase[UNIT_SEG] && J.meta->status == RDHEI_OK) J.meta->status = RDHEI_ECAPACITY;
-            continue;
+        } else {
+            extract_unit(J, hp, j, u, u - J.ubase[UNIT_SEG], status, sh, shv, win, part);
         }
-        const uint32_t seg = u - J.ubase[UNIT_SEG];
-        const uint64_t total = (uint64_t)J.M * (uint64_t)J.N;
+        __syncthreads();
+    }
+}
+
+__global__ void k_extract_fix(const Job *__restrict__ jobs, const PartWord *__restrict__ part, uint32_t n, int phase) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const PartWord pw = part[i];
+    if (pw.word < 0) return;
+    uint32_t *dst = reinterpret_cast<uint32_t *>(jobs[pw.job].msg) + pw.word;
+    if (phase == 0) *dst = 0u;
+    else atomicOr(dst, pw.bits);
+}
+
+
+// ---- whole images, one workgroup each ---------------------------------------
+// Images of at most kSeqMaxSeg segments are walked segment by segment by one
+// workgroup: the rank carries over in registers, the next segment's pixels are
+// loaded while the current one is processed, and no other workgroup is waited
+// on.  Larger images use the look-back kernels above.
+constexpr int kSeqMaxSeg = 64;
+
+// Pixels of one segment.  Whole-image hiding is used only for images whose
+// pixel count is a multiple of 16, so every 16-byte piece is in or out.
+__device__ __forceinline__ void seg_load(const uint8_t *img, uint64_t s0, uint64_t s1, uint4 px[kSegLoads]) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kSegLoads; ++k) {
+        const uint64_t pos = s0 + (uint64_t)k * (kThreads * 16) + 16 * (uint64_t)tid;
+        px[k] = pos < s1 ? gload<uint4>(img + pos) : make_uint4(0x01010101u, 0x01010101u, 0x01010101u, 0x01010101u);
+    }
+}
+
+template <bool EMBED>
+__device__ __forceinline__ void hide_image(const Job &J, const HideParams &hp, uint64_t *sh, uint32_t *win) {
+    const int tid = threadIdx.x;
+    const uint8_t *img = EMBED ? J.out : J.in;
+    const uint64_t total = (uint64_t)J.M * (uint64_t)J.N;
+    const uint32_t nseg = (uint32_t)((total + kSegPx - 1) / kSegPx);
+    const uint32_t rep = hp.rep;
+    uint64_t rank = 0;
+    uint32_t carry = 0;          // extraction: bits of the partial word left by the previous segment
+    int64_t carry_word = -1;
+    uint4 nxt[kSegLoads];
+    seg_load(img, 0, total < kSegPx ? total : kSegPx, nxt);
+    for (uint32_t seg = 0; seg < nseg; ++seg) {
         const uint64_t s0 = (uint64_t)seg * kSegPx;
         const uint64_t s1 = s0 + kSegPx < total ? s0 + kSegPx : total;
-        uint64_t rank = J.nseg > 1 ? reinterpret_cast<const uint32_t *>(ws + J.ws_seg)[J.nseg + seg] : 0u;
-        const int64_t seg_start = (int64_t)(rank * hp.rep);
-        if (seg_start >= hp.nbits) continue;
-        // the segment's bit range ends where the next segment's begins (or at nbits)
-        int64_t seg_end = hp.nbits;
-        if (J.nseg > 1 && (int)seg + 1 < J.nseg) {
-            const int64_t nx = (int64_t)hp.rep * reinterpret_cast<const uint32_t *>(ws + J.ws_seg)[J.nseg + seg + 1];
-            if (nx < seg_end) seg_end = nx;
+        uint4 px[kSegLoads];
+#pragma unroll
+        for (int k = 0; k < kSegLoads; ++k) px[k] = nxt[k];
+        {   // the next segment's pixels (the last segment reloads itself)
+            const uint32_t ns = seg + 1 < nseg ? seg + 1 : seg;
+            const uint64_t n0 = (uint64_t)ns * kSegPx;
+            seg_load(img, n0, n0 + kSegPx < total ? n0 + kSegPx : total, nxt);
         }
-        const bool shared_start = seg > 0 && (seg_start & 31);
-        const bool shared_end = (seg_end & 31) && seg_end < hp.nbits;
-        uint32_t carry = 0;           // bits of the partial word left by the previous chunk
-        int64_t carry_word = -1;
-        for (uint64_t c0 = s0; c0 < s1; c0 += kChunk) {
-            const uint64_t pos = c0 + 16 * (uint64_t)tid;
-            const bool mine = pos < s1;
-            const uint4 px = mine ? load16(J.in, pos, s1) : make_uint4(0x01010101u, 0x01010101u, 0x01010101u, 0x01010101u);
-            const uint32_t rm = mine ? redundant16(J, px, pos, s1) : 0u;
-            uint32_t tot;
-            const uint32_t ex = block_excl_scan(__popc(rm), tot, sh);
-            const int64_t wstart = (int64_t)(rank * hp.rep);
-            int64_t wend = (int64_t)((rank + tot) * hp.rep);
-            if (wend > hp.nbits) wend = hp.nbits;
-            if (wstart >= hp.nbits) break;
-            if (tot == 0) continue;
-            const int64_t W0 = wstart >> 5, W1 = (wend + 31) >> 5;
-            for (int k = tid; k < W1 - W0 + 2; k += kThreads) win[k] = (k == 0 && carry_word == W0) ? carry : 0u;
+        uint32_t rm[kSegLoads];
+        uint64_t packed = 0;
+#pragma unroll
+        for (int k = 0; k < kSegLoads; ++k) {
+            const uint64_t pos = s0 + (uint64_t)k * (kThreads * 16) + 16 * (uint64_t)tid;
+            rm[k] = redundant16(J, px[k], pos, s1);
+            packed |= (uint64_t)__popc(rm[k]) << (16 * k);
+        }
+        uint64_t tot;
+        const uint64_t ex = block_scan4(packed, tot, sh);
+        uint32_t lr[kSegLoads], cbase = 0;      // local rank (within the segment) of the thread's first pixel of load k
+#pragma unroll
+        for (int k = 0; k < kSegLoads; ++k) {
+            lr[k] = cbase + (uint32_t)((ex >> (16 * k)) & 0xFFFFu);
+            cbase += (uint32_t)((tot >> (16 * k)) & 0xFFFFu);
+        }
+        const uint32_t T = uni(cbase);
+        const int64_t wstart = (int64_t)(rank * rep);
+        if (wstart >= hp.nbits) break;
+        int64_t wend = (int64_t)((rank + T) * rep);
+        if (wend > hp.nbits) wend = hp.nbits;
+        rank += T;
+        if (T > 0 && EMBED) {
+            // window bits relative to the first staged 16-byte block
+            const int64_t fb = wstart >> 7, lb = (wend - 1) >> 7;
+            const uint32_t off0 = (uint32_t)(wstart - (fb << 7)), rend = (uint32_t)(wend - (fb << 7));
+            for (int64_t q = tid; q <= lb - fb; q += kThreads) {
+                const uint64_t blk = (uint64_t)(fb + q);
+                const uint4 mv = gload<uint4>(J.msg + 16 * blk);
+                const U4 ks = stream_block(J.key, kDomainMessage, blk);
+                uint32_t *wp = win + 4 * q;
+                wp[0] = __builtin_bswap32(mv.x ^ ks.x);
+                wp[1] = __builtin_bswap32(mv.y ^ ks.y);
+                wp[2] = __builtin_bswap32(mv.z ^ ks.z);
+                wp[3] = __builtin_bswap32(mv.w ^ ks.w);
+            }
             __syncthreads();
-            if (mine && rm) {
-                int64_t bit = (int64_t)((rank + ex) * hp.rep);
-                const uint32_t w[4] = {px.x, px.y, px.z, px.w};
-                int64_t cw = (bit >> 5) - W0;            // current LDS word
-                uint32_t nacc = (uint32_t)(bit & 31);    // bits already in acc (alignment)
+            const uint32_t top = hp.shift + rep - 1;
+#pragma unroll
+            for (int k = 0; k < kSegLoads; ++k) {
+                uint32_t rel = off0 + lr[k] * rep;
+                if (!rm[k] || rel >= rend) continue;
+                uint32_t w[4] = {px[k].x, px[k].y, px[k].z, px[k].w};
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    if (((rm[k] >> q) & 1u) && rel < rend) {
+                        const uint32_t wi = rel >> 5, sb = rel & 31;
+                        const uint64_t v64 = ((uint64_t)win[wi] << 32) | win[wi + 1];
+                        const uint32_t val = (uint32_t)((v64 << sb) >> (64 - rep));
+                        const uint32_t left = rend - rel;
+                        const uint32_t take = left < rep ? left : rep;
+                        const uint32_t wmask = ((1u << take) - 1u) << (top + 1 - take);
+                        const uint32_t sh8 = 8 * (q & 3);
+                        w[q >> 2] = (w[q >> 2] & ~(wmask << sh8)) | (((val << hp.shift) & wmask) << sh8);
+                        rel += rep;
+                    }
+                }
+                gstore<uint4>(J.out + s0 + (uint64_t)k * (kThreads * 16) + 16 * (uint64_t)tid,
+                              make_uint4(w[0], w[1], w[2], w[3]));
+            }
+        } else if (T > 0) {
+            const int64_t W0 = wstart >> 5, W1 = (wend + 31) >> 5;
+            const uint32_t off0 = (uint32_t)(wstart & 31), rend = (uint32_t)(wend - 32 * W0);
+            for (int64_t q = tid; q < W1 - W0 + 1; q += kThreads) win[q] = (q == 0 && carry_word == W0) ? carry : 0u;
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kSegLoads; ++k) {
+                uint32_t rel = off0 + lr[k] * rep;
+                if (!rm[k] || rel >= rend) continue;
+                const uint32_t w[4] = {px[k].x, px[k].y, px[k].z, px[k].w};
+                uint32_t cw = rel >> 5;
+                uint32_t nacc = rel & 31;
                 uint64_t acc = 0;
 #pragma unroll
-                for (int k = 0; k < 16; ++k) {
-                    if (((rm >> k) & 1u) && bit < wend) {
-                        const uint32_t pv = (w[k >> 2] >> (8 * (k & 3))) & 0xFFu;
-                        const int64_t left = wend - bit;
-                        const uint32_t take = left < (int64_t)hp.rep ? (uint32_t)left : hp.rep;
-                        const uint32_t val = (pv >> (hp.shift + hp.rep - take)) & ((1u << take) - 1u);
+                for (int q = 0; q < 16; ++q) {
+                    if (((rm[k] >> q) & 1u) && rel < rend) {
+                        const uint32_t pv = (w[q >> 2] >> (8 * (q & 3))) & 0xFFu;
+                        const uint32_t left = rend - rel;
+                        const uint32_t take = left < rep ? left : rep;
+                        const uint32_t val = (pv >> (hp.shift + rep - take)) & ((1u << take) - 1u);
                         acc |= (uint64_t)val << (64 - nacc - take);
                         nacc += take;
-                        bit += take;
+                        rel += take;
                         if (nacc >= 32) {
                             atomicOr(&win[cw], (uint32_t)(acc >> 32));
                             ++cw;
@@ -313,28 +563,41 @@ __global__ __launch_bounds__(kThreads) void k_extract(const Job *__restrict__ jo
                 if (nacc) atomicOr(&win[cw], (uint32_t)(acc >> 32));
             }
             __syncthreads();
-            // words W0 .. W1-1; the last stays in LDS when the next chunk continues it
-            const bool last_partial = (wend & 31) != 0;
-            const int64_t nstore = last_partial ? (W1 - 1 - W0) : (W1 - W0);
-            for (int64_t k = tid; k < nstore; k += kThreads) {
-                const int64_t w = W0 + k;
-                const bool sh_w = (w == (seg_start >> 5)) && shared_start;
-                put_word(J, w, win[k], sh_w ? be_mask(w, seg_start, seg_end) : 0xFFFFFFFFu, sh_w);
-            }
-            if (last_partial) {
-                carry = win[W1 - 1 - W0];
-                carry_word = W1 - 1;
-            } else {
-                carry_word = -1;
-            }
-            rank += tot;
-            __syncthreads();
+            // complete words go out; a trailing partial word waits for the next segment
+            const bool partial = (wend & 31) != 0;
+            const int64_t nstore = partial ? (W1 - 1 - W0) : (W1 - W0);
+            uint32_t *msgw = reinterpret_cast<uint32_t *>(J.msg);
+            for (int64_t q = tid; q < nstore; q += kThreads)
+                gstore<uint32_t>(msgw + W0 + q, __builtin_bswap32(win[q] ^ ks_word(J.key, W0 + q)));
+            carry_word = partial ? W1 - 1 : -1;
+            carry = partial ? uni(win[W1 - 1 - W0]) : 0u;
         }
-        // flush the final partial word of the segment
-        if (carry_word >= 0 && tid == 0) {
-            const int64_t w = carry_word;
-            const bool sh_w = (w == (seg_start >> 5) && shared_start) || shared_end;
-            put_word(J, w, carry, be_mask(w, seg_start, seg_end), sh_w);
+        __syncthreads();
+    }
+    if (!EMBED && carry_word >= 0 && tid == 0) {
+        // the message's last word: bits past nbits are stored as zero
+        const uint32_t own = be_mask(carry_word, 0, hp.nbits);
+        gstore<uint32_t>(reinterpret_cast<uint32_t *>(J.msg) + carry_word,
+                         __builtin_bswap32((carry ^ ks_word(J.key, carry_word)) & own));
+    }
+}
+
+template <bool EMBED>
+__global__ __launch_bounds__(kThreads) void k_hide_seq(const Job *__restrict__ jobs, int njobs, uint32_t units,
+                                                        const uint32_t *__restrict__ ujob) {
+    __shared__ uint64_t sh[kThreads / 64];
+    __shared__ uint32_t win[kWinWords];
+    const int tid = threadIdx.x;
+    const uint32_t per = (units + gridDim.x - 1) / gridDim.x;
+    const uint32_t u0 = blockIdx.x * per, u1 = u0 + per < units ? u0 + per : units;
+    for (uint32_t u = u0; u < u1; ++u) {
+        const int j = (int)uni((uint32_t)find_job<UNIT_IMG>(jobs, njobs, u, ujob));
+        const Job &J = jobs[j];
+        const HideParams hp = hide_params(J);
+        if (!hp.ok) {
+            if (tid == 0 && J.meta->status == RDHEI_OK) J.meta->status = RDHEI_ECAPACITY;
+        } else {
+            hide_image<EMBED>(J, hp, sh, win);
         }
         __syncthreads();
     }
@@ -347,22 +610,66 @@ static inline unsigned grid_for(const Launch &L, uint32_t units) {
     return g ? g : 1;
 }
 
-void launch_seg_count(const Launch &L, uint32_t units) {
-    const uint32_t *UJ = L.ujob[UNIT_SEG];
-    if (units) hipLaunchKernelGGL(k_seg_count, dim3(grid_for(L, units)), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+template <typename K>
+static unsigned resident_grid(const Launch &L, K kernel, uint32_t units) {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (cus <= 0) cus = 1;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    uint32_t g = (uint32_t)cus * (uint32_t)per_cu;
+    if (L.max_grid > 0) g = (uint32_t)L.max_grid;
+    if (g > units) g = units;
+    return g ? g : 1;
 }
-void launch_seg_scan(const Launch &L, int clear_shared) {
-    if (L.njobs) hipLaunchKernelGGL(k_seg_scan, dim3(grid_for(L, (uint32_t)L.njobs)), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, L.ws, clear_shared);
+
+void launch_hide_images(const Launch &L, uint32_t units, bool embed) {
+    if (!units) return;
+    if (embed)
+        hipLaunchKernelGGL(k_hide_seq<true>, dim3(resident_grid(L, k_hide_seq<true>, units)), dim3(kThreads), 0,
+                           L.stream, L.jobs, L.njobs, units, L.ujob[UNIT_IMG]);
+    else
+        hipLaunchKernelGGL(k_hide_seq<false>, dim3(resident_grid(L, k_hide_seq<false>, units)), dim3(kThreads), 0,
+                           L.stream, L.jobs, L.njobs, units, L.ujob[UNIT_IMG]);
 }
+
+int seq_max_segments() { return kSeqMaxSeg; }
+
 void launch_embed(const Launch &L, uint32_t units) {
-    const uint32_t *UJ = L.ujob[UNIT_SEG];
-    if (units) hipLaunchKernelGGL(k_embed, dim3(grid_for(L, units)), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+    if (!units) return;
+    uint64_t *status = reinterpret_cast<uint64_t *>(L.ws + L.g_status);
+    uint32_t *ticket = reinterpret_cast<uint32_t *>(L.ws + L.g_ticket);
+    hipLaunchKernelGGL(k_hide_reset, dim3((units + 255) / 256), dim3(256), 0, L.stream, status, units, ticket);
+    hipLaunchKernelGGL(k_embed, dim3(grid_for(L, units)), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, units,
+                       L.ujob[UNIT_SEG], status, ticket);
 }
+
 void launch_extract(const Launch &L, uint32_t units) {
-    const uint32_t *UJ = L.ujob[UNIT_SEG];
-    if (units) hipLaunchKernelGGL(k_extract, dim3(grid_for(L, units)), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+    if (!units) return;
+    uint64_t *status = reinterpret_cast<uint64_t *>(L.ws + L.g_status);
+    uint32_t *ticket = reinterpret_cast<uint32_t *>(L.ws + L.g_ticket);
+    PartWord *part = reinterpret_cast<PartWord *>(L.ws + L.g_part);
+    hipLaunchKernelGGL(k_hide_reset, dim3((units + 255) / 256), dim3(256), 0, L.stream, status, units, ticket);
+    hipLaunchKernelGGL(k_extract, dim3(grid_for(L, units)), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, units,
+                       L.ujob[UNIT_SEG], status, ticket, part);
+    const uint32_t n = 2 * units;
+    hipLaunchKernelGGL(k_extract_fix, dim3((n + 255) / 256), dim3(256), 0, L.stream, L.jobs, part, n, 0);
+    hipLaunchKernelGGL(k_extract_fix, dim3((n + 255) / 256), dim3(256), 0, L.stream, L.jobs, part, n, 1);
 }
 
 uint64_t seg_pixels() { return kSegPx; }
+
+// Launch-wide hiding workspace: status words, ticket, partial-word records.
+void hide_ws_layout(uint32_t units, uint64_t base, uint64_t &status, uint64_t &ticket, uint64_t &part, uint64_t &end) {
+    status = base;
+    ticket = (status + (uint64_t)units * 8 + 255) / 256 * 256;
+    part = ticket + 256;
+    end = (part + (uint64_t)units * 2 * sizeof(PartWord) + 255) / 256 * 256;
+}
 
 }  // namespace rdhei

@@ -1,6 +1,10 @@
 // Tiled fast path (M, N multiples of 64): keystream code pyramid + label
 // statistics, per-image finalisation (optimal b, upper rotation levels), the
 // permuting encryption, and the band-sequential recovery.
+//
+// The tile kernels are persistent: each workgroup owns a contiguous range of
+// work units (tiles of one image stay on one workgroup, hence on one XCD and
+// its L2) and loads the next unit's inputs before working on the current one.
 #include "device.hpp"
 
 namespace rdhei {
@@ -8,103 +12,98 @@ namespace rdhei {
 // LDS row stride of a 64-byte tile row (keeps 16-byte alignment).
 constexpr int kRow = kTile + 16;
 
+// Contiguous unit range [u0, u1) of this workgroup.
+__device__ __forceinline__ void unit_range(uint32_t units, uint32_t &u0, uint32_t &u1) {
+    const uint32_t per = (units + gridDim.x - 1) / gridDim.x;
+    u0 = blockIdx.x * per;
+    u1 = u0 + per < units ? u0 + per : units;
+}
+
 // ----------------------------------------------------------------------------
 // Keystream code pyramid of one tile (Sec. III-A rotation equation: block code
 // = (sum of s over the block) mod 4 at every level 2^1..2^6 inside the tile)
 // and, for encryption, the histogram of the leading-shared-bit count lambda of
 // each pixel with its left neighbour (Sec. III-A location map; the Omega glide
 // labels a pixel redundant for b exactly when lambda >= b).
+// Thread (r, g) holds 16 keystream bytes of tile row r; a wave covers 16 rows,
+// so levels 1..4 reduce with lane shuffles and only levels 5..6 cross waves.
 // ----------------------------------------------------------------------------
 template <bool STATS>
 __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ jobs, int njobs,
                                                          uint8_t *__restrict__ ws, uint32_t units,
-    const uint32_t *__restrict__ ujob) {
-    __shared__ uint8_t lvl[1024 + 256 + 64 + 16 + 4 + 4];   // unpacked codes, levels 1..6
-    __shared__ __align__(16) uint8_t rec[kCodeRecord];
-    __shared__ uint32_t hist[4][8];
+                                                         const uint32_t *__restrict__ ujob) {
+    __shared__ __align__(16) uint8_t rec[2][kCodeRecord];
+    __shared__ uint8_t l4[2][16];
+    __shared__ uint32_t hist[2][4][8];
     const int tid = threadIdx.x;
     const int r = tid >> 2, g = tid & 3;
     const int lane = tid & 63, wave = tid >> 6;
-    uint8_t *L1 = lvl, *L2 = lvl + 1024, *L3 = L2 + 256, *L4 = L3 + 64, *L5 = L4 + 16, *L6 = L5 + 4;
+    uint32_t u0, u1;
+    unit_range(units, u0, u1);
 
-    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
-        const int j = find_job<UNIT_TILE>(jobs, njobs, u, ujob);
-        const Job &J = jobs[j];
+    uint4 p_n = make_uint4(0, 0, 0, 0);
+    uint32_t left_n = 0;
+    auto fetch = [&](uint32_t u) {
+        if (!STATS) return;
+        const Job &J = jobs[find_job<UNIT_TILE>(jobs, njobs, u, ujob)];
+        const uint32_t t = u - J.ubase[UNIT_TILE];
+        const int ty = (int)(t / (uint32_t)J.tiles_x), tx = (int)(t % (uint32_t)J.tiles_x);
+        const uint8_t *row = J.in + (uint64_t)(ty * kTile + r) * (uint64_t)J.N + (uint64_t)(tx * kTile);
+        p_n = gload<uint4>(row + 16 * g);
+        left_n = gload<uint8_t>(row + (tx > 0 ? -1 : 0));
+    };
+    if (u0 < u1) fetch(u0);
+
+    for (uint32_t u = u0; u < u1; ++u) {
+        const int par = (int)(u - u0) & 1;
+        const uint4 p = p_n;
+        const uint32_t left0 = left_n;
+        if (u + 1 < u1) fetch(u + 1);
+        const Job &J = jobs[find_job<UNIT_TILE>(jobs, njobs, u, ujob)];
         const uint32_t t = u - J.ubase[UNIT_TILE];
         const int ty = (int)(t / (uint32_t)J.tiles_x), tx = (int)(t % (uint32_t)J.tiles_x);
         const uint64_t idx = (uint64_t)(ty * kTile + r) * (uint64_t)J.N + (uint64_t)(tx * kTile + 16 * g);
         const U4 s = stream_block(J.key, kDomainImage, idx >> 4);
+        uint8_t *R = rec[par];
 
-        // level 1: 2x2 sums from this row pair (row r even holds the sums)
-        uint32_t h[4] = {(s.x & 0x00FF00FFu) + ((s.x >> 8) & 0x00FF00FFu),
-                         (s.y & 0x00FF00FFu) + ((s.y >> 8) & 0x00FF00FFu),
-                         (s.z & 0x00FF00FFu) + ((s.z >> 8) & 0x00FF00FFu),
-                         (s.w & 0x00FF00FFu) + ((s.w >> 8) & 0x00FF00FFu)};
+        // level 1: 2x2 blocks; even rows hold the sums of rows r, r+1
+        const uint32_t sw[4] = {s.x, s.y, s.z, s.w};
         uint32_t v[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] = (h[k] + __shfl_down(h[k], 4, 64)) & 0x00030003u;
-        if ((r & 1) == 0) {
-            uint8_t *dst = L1 + (r >> 1) * 32 + 8 * g;
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t h = (sw[k] & 0x00FF00FFu) + ((sw[k] >> 8) & 0x00FF00FFu);
+            v[k] = (h + __shfl_down(h, 4, 64)) & 0x00030003u;
+        }
+        uint32_t pack1 = 0, H2 = 0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                dst[2 * k] = (uint8_t)(v[k] & 3u);
-                dst[2 * k + 1] = (uint8_t)((v[k] >> 16) & 3u);
-            }
+        for (int k = 0; k < 4; ++k) {
+            pack1 |= ((v[k] & 3u) | (((v[k] >> 16) & 3u) << 2)) << (4 * k);
+            H2 |= ((v[k] & 3u) + ((v[k] >> 16) & 3u)) << (8 * k);
         }
-        __syncthreads();
-        {   // level 2: 16 x 16 codes, one per thread
-            const int Y = tid >> 4, X = tid & 15;
-            const uint8_t *a = L1 + (2 * Y) * 32 + 2 * X;
-            L2[tid] = (uint8_t)((a[0] + a[1] + a[32] + a[33]) & 3);
-        }
-        __syncthreads();
-        if (tid < 64) {
-            const int Y = tid >> 3, X = tid & 7;
-            const uint8_t *a = L2 + (2 * Y) * 16 + 2 * X;
-            L3[tid] = (uint8_t)((a[0] + a[1] + a[16] + a[17]) & 3);
-        }
-        __syncthreads();
-        if (tid < 16) {
-            const int Y = tid >> 2, X = tid & 3;
-            const uint8_t *a = L3 + (2 * Y) * 8 + 2 * X;
-            L4[tid] = (uint8_t)((a[0] + a[1] + a[8] + a[9]) & 3);
-        }
-        __syncthreads();
-        if (tid < 4) {
-            const int Y = tid >> 1, X = tid & 1;
-            const uint8_t *a = L4 + (2 * Y) * 4 + 2 * X;
-            L5[tid] = (uint8_t)((a[0] + a[1] + a[4] + a[5]) & 3);
-        }
-        __syncthreads();
-        if (tid == 0) L6[0] = (uint8_t)((L5[0] + L5[1] + L5[2] + L5[3]) & 3);
-        __syncthreads();
-        // pack 2-bit codes: byte q of level m holds codes 4q..4q+3
-        for (int q = tid; q < code_off(kTileLog + 1); q += kThreads) {
-            int m = 1, base = 0;
-            while (m < kTileLog && q >= code_off(m + 1)) ++m;
-            base = q - code_off(m);
-            const uint8_t *src = lvl + (m == 1 ? 0 : m == 2 ? 1024 : m == 3 ? 1280 : m == 4 ? 1344 : m == 5 ? 1360 : 1364);
-            const int cnt = (kTile >> m) * (kTile >> m);
-            uint32_t b = 0;
+        if ((r & 1) == 0) *reinterpret_cast<uint16_t *>(R + code_off(1) + (r >> 1) * 8 + 2 * g) = (uint16_t)pack1;
+        // level 2: 4x4 blocks, rows r and r+2 (lane + 8)
+        const uint32_t V2 = (H2 + __shfl_down(H2, 8, 64)) & 0x03030303u;
+        uint32_t pack2 = 0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int c = 4 * base + k;
-                if (c < cnt) b |= (uint32_t)src[c] << (2 * k);
-            }
-            rec[q] = (uint8_t)b;
-        }
-        __syncthreads();
-        uint8_t *out_rec = ws + J.ws_codes + (uint64_t)t * kCodeRecord;
-        if (tid < kCodeRecord / 16)
-            reinterpret_cast<uint4 *>(out_rec)[tid] = reinterpret_cast<const uint4 *>(rec)[tid];
-        if (tid == 0) ws[J.ws_pyr + t] = L6[0];
+        for (int k = 0; k < 4; ++k) pack2 |= ((V2 >> (8 * k)) & 3u) << (2 * k);
+        if ((r & 3) == 0) R[code_off(2) + (r >> 2) * 4 + g] = (uint8_t)pack2;
+        // level 3: 8x8 blocks, rows r and r+4 (lane + 16)
+        const uint32_t H3 = (((V2 & 3u) + ((V2 >> 8) & 3u))) | ((((V2 >> 16) & 3u) + ((V2 >> 24) & 3u)) << 8);
+        const uint32_t V3 = (H3 + __shfl_down(H3, 16, 64)) & 0x0303u;
+        const uint32_t nib = (V3 & 3u) | (((V3 >> 8) & 3u) << 2);
+        const uint32_t nib_hi = __shfl_down(nib, 1, 64);
+        if ((r & 7) == 0 && (g & 1) == 0) R[code_off(3) + 2 * (r >> 3) + (g >> 1)] = (uint8_t)(nib | (nib_hi << 4));
+        // level 4: 16x16 blocks, rows r and r+8 (lane + 32)
+        const uint32_t h4 = (V3 & 3u) + ((V3 >> 8) & 3u);
+        const uint32_t c4 = (h4 + __shfl_down(h4, 32, 64)) & 3u;
+        const uint32_t c4b = __shfl_down(c4, 1, 64), c4c = __shfl_down(c4, 2, 64), c4d = __shfl_down(c4, 3, 64);
+        if (lane == 0) R[code_off(4) + wave] = (uint8_t)(c4 | (c4b << 2) | (c4c << 4) | (c4d << 6));
+        if (lane < 4) l4[par][wave * 4 + lane] = (uint8_t)c4;
 
         if (STATS) {
-            const uint8_t *row = J.in + (uint64_t)(ty * kTile + r) * (uint64_t)J.N + (uint64_t)(tx * kTile);
-            const uint4 p = *reinterpret_cast<const uint4 *>(row + 16 * g);
-            uint32_t left = __shfl_up(p.w >> 24, 1, 64);
-            if (g == 0) left = tx > 0 ? (uint32_t)row[-1] : 0u;
             const uint32_t w[4] = {p.x, p.y, p.z, p.w};
+            uint32_t left = __shfl_up(p.w >> 24, 1, 64);
+            if (g == 0) left = tx > 0 ? left0 : 0u;
             const uint32_t lw[4] = {(p.x << 8) | left, (p.y << 8) | (p.x >> 24), (p.z << 8) | (p.y >> 24),
                                     (p.w << 8) | (p.z >> 24)};
             // packed counters, 9 bits per lambda in 2..8 (lambda < 2 dropped)
@@ -127,15 +126,31 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
             }
             if (lane == 0) {
 #pragma unroll
-                for (int k = 0; k < 7; ++k) hist[wave][k] = c[k];
-            }
-            __syncthreads();
-            if (tid < 7) {
-                uint32_t *st = reinterpret_cast<uint32_t *>(ws + J.ws_stats) + (uint64_t)t * kStatWords;
-                st[tid] = hist[0][tid] + hist[1][tid] + hist[2][tid] + hist[3][tid];
+                for (int k = 0; k < 7; ++k) hist[par][wave][k] = c[k];
             }
         }
         __syncthreads();
+        if (tid == 0) {
+            const uint8_t *a = l4[par];
+            uint32_t c5[4], c6 = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int Y = q >> 1, X = q & 1;
+                c5[q] = (a[(2 * Y) * 4 + 2 * X] + a[(2 * Y) * 4 + 2 * X + 1] + a[(2 * Y + 1) * 4 + 2 * X] +
+                         a[(2 * Y + 1) * 4 + 2 * X + 1]) & 3u;
+                c6 += c5[q];
+            }
+            R[code_off(5)] = (uint8_t)(c5[0] | (c5[1] << 2) | (c5[2] << 4) | (c5[3] << 6));
+            R[code_off(6)] = (uint8_t)(c6 & 3u);
+            ws[J.ws_pyr + t] = (uint8_t)(c6 & 3u);
+        }
+        if (STATS && tid < 7) {
+            uint32_t *st = reinterpret_cast<uint32_t *>(ws + J.ws_stats) + (uint64_t)t * kStatWords;
+            st[tid] = hist[par][0][tid] + hist[par][1][tid] + hist[par][2][tid] + hist[par][3][tid];
+        }
+        __syncthreads();
+        if (tid < kCodeRecord / 16)
+            gstore<uint4>(ws + J.ws_codes + (uint64_t)t * kCodeRecord + 16 * tid, reinterpret_cast<const uint4 *>(R)[tid]);
     }
 }
 
@@ -206,10 +221,21 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const Job *__restrict__ j
                     cur[q] = (uint8_t)((a[0] + a[1] + a[cx] + a[cx + 1]) & 3);
                 }
             }
+            __syncthreads();
+            // where every tile goes (levels above the tile move tiles rigidly)
+            uint32_t *tmap = reinterpret_cast<uint32_t *>(ws + J.ws_tmap);
+            const uint32_t ntiles = (uint32_t)(J.tiles_x * J.tiles_y);
+            for (uint32_t q = tid; q < ntiles; q += kThreads) {
+                int dy, dx;
+                uint32_t turns;
+                upper_walk(J, pyr, (int)(q / (uint32_t)J.tiles_x), (int)(q % (uint32_t)J.tiles_x), dy, dx, turns);
+                tmap[q] = tmap_pack(dy, dx, turns);
+            }
         }
         __syncthreads();
     }
 }
+
 
 // ----------------------------------------------------------------------------
 // Encryption of one source tile (Sec. III-A encoding): label each pixel
@@ -223,31 +249,50 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const Job *__restrict__ j
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_encrypt_tile(const Job *__restrict__ jobs, int njobs,
                                                             uint8_t *__restrict__ ws, uint32_t units,
-    const uint32_t *__restrict__ ujob) {
+                                                            const uint32_t *__restrict__ ujob) {
     __shared__ __align__(16) uint8_t src[kTile * kRow];
     __shared__ __align__(16) uint8_t dst[kTile * kRow];
     __shared__ __align__(16) uint8_t rec[kCodeRecord];
     const int tid = threadIdx.x;
     const int r = tid >> 2, g = tid & 3;
     const int by = tid >> 4, bx = tid & 15;
+    uint32_t u0, u1;
+    unit_range(units, u0, u1);
 
-    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
-        const int j = find_job<UNIT_TILE>(jobs, njobs, u, ujob);
-        const Job &J = jobs[j];
+    // The next unit's loads are issued unconditionally (the last unit reloads
+    // itself) so the compiler can count them and wait only for the current ones.
+    uint4 p_n = make_uint4(0, 0, 0, 0), rc_n = make_uint4(0, 0, 0, 0);
+    uint32_t left_n = 0, b_n = 0, st_n = 0;
+    auto fetch = [&](uint32_t u) {
+        const Job &J = jobs[uni((uint32_t)find_job<UNIT_TILE>(jobs, njobs, u, ujob))];
         const uint32_t t = u - J.ubase[UNIT_TILE];
         const int ty = (int)(t / (uint32_t)J.tiles_x), tx = (int)(t % (uint32_t)J.tiles_x);
-        if (MODE == ENC_EMR && J.meta->status != RDHEI_OK) continue;
-        const int b = J.fixed_b > 0 ? J.fixed_b : J.meta->b;
+        const uint8_t *row = J.in + (uint64_t)(ty * kTile + r) * (uint64_t)J.N + (uint64_t)(tx * kTile);
+        p_n = gload<uint4>(row + 16 * g);
+        left_n = gload<uint8_t>(row + (tx > 0 ? -1 : 0));
+        rc_n = gload<uint4>(ws + J.ws_codes + (uint64_t)t * kCodeRecord + 16 * (tid % (kCodeRecord / 16)));
+        b_n = (uint32_t)gload<int32_t>(&J.meta->b);
+        st_n = (uint32_t)gload<int32_t>(&J.meta->status);
+    };
+    if (u0 < u1) fetch(u0);
+
+    for (uint32_t u = u0; u < u1; ++u) {
+        const uint4 p = p_n, rc = rc_n;
+        const uint32_t left0 = left_n, b_cur = uni(b_n), st_cur = uni(st_n);
+        fetch(u + 1 < u1 ? u + 1 : u);
+        const Job &J = jobs[uni((uint32_t)find_job<UNIT_TILE>(jobs, njobs, u, ujob))];
+        const uint32_t t = u - J.ubase[UNIT_TILE];
+        const int ty = (int)(t / (uint32_t)J.tiles_x), tx = (int)(t % (uint32_t)J.tiles_x);
+        if (MODE == ENC_EMR && st_cur != (uint32_t)RDHEI_OK) continue;
+        const int b = J.fixed_b > 0 ? J.fixed_b : (int)b_cur;
         int dy, dx;
         uint32_t up;
-        upper_walk(J, ws + J.ws_pyr, ty, tx, dy, dx, up);
+        tmap_unpack(reinterpret_cast<const uint32_t *>(ws + J.ws_tmap)[t], dy, dx, up);
 
-        const uint8_t *row = J.in + (uint64_t)(ty * kTile + r) * (uint64_t)J.N + (uint64_t)(tx * kTile);
-        const uint4 p = *reinterpret_cast<const uint4 *>(row + 16 * g);
         uint4 o = p;
         if (MODE != ENC_LMR) {
             uint32_t left = __shfl_up(p.w >> 24, 1, 64);
-            if (g == 0) left = tx > 0 ? (uint32_t)row[-1] : 0u;
+            if (g == 0) left = tx > 0 ? left0 : 0u;
             const uint32_t topm = ((0xFFu << (8 - b)) & 0xFFu) * 0x01010101u;
             const uint32_t w[4] = {p.x, p.y, p.z, p.w};
             const uint32_t lw[4] = {(p.x << 8) | left, (p.y << 8) | (p.x >> 24), (p.z << 8) | (p.y >> 24),
@@ -264,9 +309,7 @@ __global__ __launch_bounds__(kThreads) void k_encrypt_tile(const Job *__restrict
             o = make_uint4(res[0], res[1], res[2], res[3]);
         }
         *reinterpret_cast<uint4 *>(src + r * kRow + 16 * g) = o;
-        if (tid < kCodeRecord / 16)
-            reinterpret_cast<uint4 *>(rec)[tid] =
-                reinterpret_cast<const uint4 *>(ws + J.ws_codes + (uint64_t)t * kCodeRecord)[tid];
+        if (tid < kCodeRecord / 16) reinterpret_cast<uint4 *>(rec)[tid] = rc;
         __syncthreads();
 
         uint32_t dmap[16];
@@ -295,8 +338,8 @@ __global__ __launch_bounds__(kThreads) void k_encrypt_tile(const Job *__restrict
                 lb |= ((v >> 1) & 1u) << pos;
                 eb |= (v & 1u) << pos;
             }
-            *reinterpret_cast<uint16_t *>(J.out + (didx >> 3)) = (uint16_t)lb;
-            *reinterpret_cast<uint16_t *>(J.msg + (didx >> 3)) = (uint16_t)eb;
+            gstore<uint16_t>(J.out + (didx >> 3), (uint16_t)lb);
+            gstore<uint16_t>(J.msg + (didx >> 3), (uint16_t)eb);
         } else {
             const U4 s = stream_block(J.key, kDomainImage, didx >> 4);
             uint4 e;
@@ -319,24 +362,23 @@ __global__ __launch_bounds__(kThreads) void k_encrypt_tile(const Job *__restrict
                     e = make_uint4(ew[0], ew[1], ew[2], ew[3]);
                 }
             }
-            *reinterpret_cast<uint4 *>(J.out + didx) = e;
+            gstore<uint4>(J.out + didx, e);
         }
-        __syncthreads();
     }
 }
 
 // ----------------------------------------------------------------------------
-// Recovery of one row band of tiles, left to right (Sec. III-A decoding with
-// K1): gather each original-domain tile from its rotated position, decrypt
-// with the keystream at the encrypted position, read l (EMR: the LSB; LMR:
-// the decompressed map, plus bit 7 from the first-MSB map), then the recovery
+// Recovery of row bands of tiles, left to right (Sec. III-A decoding with K1):
+// gather each original-domain tile from its rotated position, decrypt with
+// the keystream at the encrypted position, read l (EMR: the LSB; LMR: the
+// decompressed map, plus bit 7 from the first-MSB map), then the recovery
 // glide along each row: a pixel labelled 0 takes the replaceable bits of the
 // nearest pixel labelled 1 to its left.  Rows carry that value across tiles.
 // ----------------------------------------------------------------------------
 template <int METHOD>
 __global__ __launch_bounds__(kThreads) void k_recover_band(const Job *__restrict__ jobs, int njobs,
                                                             uint8_t *__restrict__ ws, uint32_t units,
-    const uint32_t *__restrict__ ujob) {
+                                                            const uint32_t *__restrict__ ujob) {
     constexpr int kRow2 = 2 * kTile + 32;   // u16 per pixel: value | l << 8
     __shared__ __align__(16) uint8_t src[kTile * kRow2];
     __shared__ __align__(16) uint8_t dst[kTile * kRow2];
@@ -345,21 +387,48 @@ __global__ __launch_bounds__(kThreads) void k_recover_band(const Job *__restrict
     const int r = tid >> 2, g = tid & 3;
     const int by = tid >> 4, bx = tid & 15;
     const int lane = tid & 63;
+    uint32_t u0, u1;
+    unit_range(units, u0, u1);
 
-    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
-        const int j = find_job<UNIT_BAND>(jobs, njobs, u, ujob);
-        const Job &J = jobs[j];
+    // prefetched inputs of the next (band, tile) step
+    uint4 e_n = make_uint4(0, 0, 0, 0), rc_n = make_uint4(0, 0, 0, 0);
+    uint32_t lb_n = 0, eb_n = 0, b_n = 0;
+    auto fetch = [&](uint32_t u, int tx) {
+        const Job &J = jobs[uni((uint32_t)find_job<UNIT_BAND>(jobs, njobs, u, ujob))];
         const int ty = (int)(u - J.ubase[UNIT_BAND]);
-        const int b = J.meta->b;
+        const uint32_t t = (uint32_t)(ty * J.tiles_x + tx);
+        int ey, ex;
+        uint32_t up;
+        tmap_unpack(reinterpret_cast<const uint32_t *>(ws + J.ws_tmap)[t], ey, ex, up);
+        const uint64_t eidx = (uint64_t)(ey * kTile + r) * (uint64_t)J.N + (uint64_t)(ex * kTile + 16 * g);
+        e_n = gload<uint4>(J.in + eidx);
+        if (METHOD == RDHEI_LMR) {
+            lb_n = __builtin_bswap16(gload<uint16_t>(J.lbits + (eidx >> 3)));
+            eb_n = __builtin_bswap16(gload<uint16_t>(J.etabits + (eidx >> 3)));
+        }
+        rc_n = gload<uint4>(ws + J.ws_codes + (uint64_t)t * kCodeRecord + 16 * (tid % (kCodeRecord / 16)));
+        b_n = (uint32_t)gload<int32_t>(&J.meta->b);
+    };
+    if (u0 < u1) fetch(u0, 0);
+
+    for (uint32_t u = u0; u < u1; ++u) {
+        const Job &J = jobs[uni((uint32_t)find_job<UNIT_BAND>(jobs, njobs, u, ujob))];
+        const int ty = (int)(u - J.ubase[UNIT_BAND]);
+        const int b = (int)uni(b_n);
         const uint32_t mask = METHOD == RDHEI_EMR ? ((0xFFu << (8 - b)) & 0xFFu) : ((0xFFu << (8 - b)) & 0x7Fu);
         uint32_t carry = 0;   // replaceable bits of the last marker in this row
 
         for (int tx = 0; tx < J.tiles_x; ++tx) {
+            const uint4 e = e_n, rc = rc_n;
+            const uint32_t lbv = lb_n, ebv = eb_n;
+            // next step: the next tile of this band, else the first tile of the next band
+            // (the last step reloads itself, so the loads are always issued)
+            const bool more = tx + 1 < J.tiles_x;
+            fetch(more ? u : (u + 1 < u1 ? u + 1 : u), more ? tx + 1 : (u + 1 < u1 ? 0 : tx));
             int ey, ex;
             uint32_t up;
-            upper_walk(J, ws + J.ws_pyr, ty, tx, ey, ex, up);
+            tmap_unpack(reinterpret_cast<const uint32_t *>(ws + J.ws_tmap)[ty * J.tiles_x + tx], ey, ex, up);
             const uint64_t eidx = (uint64_t)(ey * kTile + r) * (uint64_t)J.N + (uint64_t)(ex * kTile + 16 * g);
-            const uint4 e = *reinterpret_cast<const uint4 *>(J.in + eidx);
             const U4 s = stream_block(J.key, kDomainImage, eidx >> 4);
             uint32_t D[4] = {e.x ^ s.x, e.y ^ s.y, e.z ^ s.z, e.w ^ s.w};
             uint32_t Lw[4];
@@ -367,15 +436,13 @@ __global__ __launch_bounds__(kThreads) void k_recover_band(const Job *__restrict
                 Lw[0] = e.x & 0x01010101u; Lw[1] = e.y & 0x01010101u;
                 Lw[2] = e.z & 0x01010101u; Lw[3] = e.w & 0x01010101u;
             } else {
-                const uint32_t lb = ((uint32_t)J.lbits[eidx >> 3] << 8) | J.lbits[(eidx >> 3) + 1];
-                const uint32_t eb = ((uint32_t)J.etabits[eidx >> 3] << 8) | J.etabits[(eidx >> 3) + 1];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     uint32_t lw = 0, ew = 0;
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        lw |= ((lb >> (15 - (4 * k + q))) & 1u) << (8 * q);
-                        ew |= ((eb >> (15 - (4 * k + q))) & 1u) << (8 * q + 7);
+                        lw |= ((lbv >> (15 - (4 * k + q))) & 1u) << (8 * q);
+                        ew |= ((ebv >> (15 - (4 * k + q))) & 1u) << (8 * q + 7);
                     }
                     Lw[k] = lw;
                     D[k] = (D[k] & 0x7F7F7F7Fu) | ew;
@@ -390,10 +457,7 @@ __global__ __launch_bounds__(kThreads) void k_recover_band(const Job *__restrict
             uint4 *sp = reinterpret_cast<uint4 *>(src + r * kRow2 + 32 * g);
             sp[0] = make_uint4(il[0], il[1], il[2], il[3]);
             sp[1] = make_uint4(il[4], il[5], il[6], il[7]);
-            const uint32_t t = (uint32_t)(ty * J.tiles_x + tx);
-            if (tid < kCodeRecord / 16)
-                reinterpret_cast<uint4 *>(rec)[tid] =
-                    reinterpret_cast<const uint4 *>(ws + J.ws_codes + (uint64_t)t * kCodeRecord)[tid];
+            if (tid < kCodeRecord / 16) reinterpret_cast<uint4 *>(rec)[tid] = rc;
             __syncthreads();
 
             uint32_t dmap[16];
@@ -431,14 +495,14 @@ __global__ __launch_bounds__(kThreads) void k_recover_band(const Job *__restrict
                 if (!found && d <= g && h2) { cin = l2; found = 1; }
             }
             // new row carry: last marker of the whole row so far
-            uint32_t rc = carry;
+            uint32_t rc2 = carry;
 #pragma unroll
             for (int d = 0; d < 4; ++d) {
                 const uint32_t h2 = __shfl(has, (lane & ~3) | d, 64);
                 const uint32_t l2 = __shfl(last, (lane & ~3) | d, 64);
-                if (h2) rc = l2;
+                if (h2) rc2 = l2;
             }
-            carry = rc;
+            carry = rc2;
             uint32_t outw[4] = {0, 0, 0, 0};
             uint32_t cur = cin;
 #pragma unroll
@@ -451,13 +515,32 @@ __global__ __launch_bounds__(kThreads) void k_recover_band(const Job *__restrict
                 outw[k >> 2] |= px << (8 * (k & 3));
             }
             const uint64_t oidx = (uint64_t)(ty * kTile + r) * (uint64_t)J.N + (uint64_t)(tx * kTile + 16 * g);
-            *reinterpret_cast<uint4 *>(J.out + oidx) = make_uint4(outw[0], outw[1], outw[2], outw[3]);
+            gstore<uint4>(J.out + oidx, make_uint4(outw[0], outw[1], outw[2], outw[3]));
         }
-        __syncthreads();
     }
 }
 
 // ---- launchers ---------------------------------------------------------------
+// Workgroups of a persistent launch: what fits on the device at once (or the
+// caller's cap), never more than there are units.
+template <typename K>
+static unsigned persistent_grid(const Launch &L, K kernel, uint32_t units) {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (cus <= 0) cus = 1;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    uint32_t g = (uint32_t)cus * (uint32_t)per_cu;
+    if (L.max_grid > 0) g = (uint32_t)L.max_grid;
+    if (g > units) g = units;
+    return g ? g : 1;
+}
+
 static inline unsigned grid_for(const Launch &L, uint32_t units) {
     uint32_t g = units;
     if (L.max_grid > 0 && g > (uint32_t)L.max_grid) g = (uint32_t)L.max_grid;
@@ -468,9 +551,11 @@ void launch_tile_prep(const Launch &L, uint32_t units, bool stats) {
     if (!units) return;
     const uint32_t *UJ = L.ujob[UNIT_TILE];
     if (stats)
-        hipLaunchKernelGGL(k_tile_prep<true>, dim3(grid_for(L, units)), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+        hipLaunchKernelGGL(k_tile_prep<true>, dim3(persistent_grid(L, k_tile_prep<true>, units)), dim3(kThreads), 0,
+                           L.stream, L.jobs, L.njobs, L.ws, units, UJ);
     else
-        hipLaunchKernelGGL(k_tile_prep<false>, dim3(grid_for(L, units)), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+        hipLaunchKernelGGL(k_tile_prep<false>, dim3(persistent_grid(L, k_tile_prep<false>, units)), dim3(kThreads), 0,
+                           L.stream, L.jobs, L.njobs, L.ws, units, UJ);
 }
 
 void launch_finalize(const Launch &L, bool stats) {
@@ -485,18 +570,28 @@ void launch_finalize(const Launch &L, bool stats) {
 void launch_encrypt_tiles(const Launch &L, uint32_t units, int mode) {
     if (!units) return;
     const uint32_t *UJ = L.ujob[UNIT_TILE];
-    const dim3 gr(grid_for(L, units)), bl(kThreads);
-    if (mode == ENC_EMR) hipLaunchKernelGGL(k_encrypt_tile<ENC_EMR>, gr, bl, 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
-    else if (mode == ENC_LMR) hipLaunchKernelGGL(k_encrypt_tile<ENC_LMR>, gr, bl, 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
-    else hipLaunchKernelGGL(k_encrypt_tile<ENC_LMR_MAPS>, gr, bl, 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+    const dim3 bl(kThreads);
+    if (mode == ENC_EMR)
+        hipLaunchKernelGGL(k_encrypt_tile<ENC_EMR>, dim3(persistent_grid(L, k_encrypt_tile<ENC_EMR>, units)), bl, 0,
+                           L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+    else if (mode == ENC_LMR)
+        hipLaunchKernelGGL(k_encrypt_tile<ENC_LMR>, dim3(persistent_grid(L, k_encrypt_tile<ENC_LMR>, units)), bl, 0,
+                           L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+    else
+        hipLaunchKernelGGL(k_encrypt_tile<ENC_LMR_MAPS>, dim3(persistent_grid(L, k_encrypt_tile<ENC_LMR_MAPS>, units)),
+                           bl, 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
 }
 
 void launch_recover_bands(const Launch &L, uint32_t units, int method) {
     if (!units) return;
     const uint32_t *UJ = L.ujob[UNIT_BAND];
-    const dim3 gr(grid_for(L, units)), bl(kThreads);
-    if (method == RDHEI_EMR) hipLaunchKernelGGL(k_recover_band<RDHEI_EMR>, gr, bl, 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
-    else hipLaunchKernelGGL(k_recover_band<RDHEI_LMR>, gr, bl, 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+    const dim3 bl(kThreads);
+    if (method == RDHEI_EMR)
+        hipLaunchKernelGGL(k_recover_band<RDHEI_EMR>, dim3(persistent_grid(L, k_recover_band<RDHEI_EMR>, units)), bl, 0,
+                           L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+    else
+        hipLaunchKernelGGL(k_recover_band<RDHEI_LMR>, dim3(persistent_grid(L, k_recover_band<RDHEI_LMR>, units)), bl, 0,
+                           L.stream, L.jobs, L.njobs, L.ws, units, UJ);
 }
 
 }  // namespace rdhei
