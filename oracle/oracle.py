@@ -66,6 +66,14 @@ def _load():
     lib.or_lmr_extract.restype = ctypes.c_int64
     lib.or_lmr_recover.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_uint64, u8p, u8p, u8p]
+    lib.or_plane_encode.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, u8p, ctypes.c_int64]
+    lib.or_plane_encode.restype = ctypes.c_int64
+    lib.or_plane_decode.argtypes = [u8p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, u8p]
+    lib.or_lmr_compress.argtypes = [u8p, u8p, ctypes.c_int32, ctypes.c_int32, u8p, ctypes.c_int64]
+    lib.or_lmr_compress.restype = ctypes.c_int64
+    lib.or_lmr_decompress.argtypes = [u8p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, u8p, u8p]
+    lib.or_lmr_encode.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, u8p, ctypes.c_void_p,
+                                  u8p, ctypes.POINTER(ctypes.c_int64)]
     _lib = lib
     return lib
 
@@ -228,6 +236,57 @@ def lmr_recover(Ie, b: int, min_level: int, k1: int, l_rot, eta_rot) -> np.ndarr
     _load().or_lmr_recover(_u8(X), X.shape[0], X.shape[1], b, min_level, k1,
                            _u8(_img(l_rot)), _u8(_img(eta_rot)), _u8(out))
     return out
+
+
+def plane_encode(P, cap: int = -1) -> np.ndarray:
+    """Bi-level coder: one byte (0/1) per pixel in, bytes out (None if > cap)."""
+    P = _img(P)
+    cap = cap if cap >= 0 else 16 + 2 * P.size
+    out = np.zeros(cap + 1, dtype=np.uint8)
+    n = _load().or_plane_encode(_u8(P), P.shape[0], P.shape[1], _u8(out), cap)
+    return None if n < 0 else out[:n].copy()
+
+
+def plane_decode(stream, M: int, N: int) -> np.ndarray:
+    s = np.ascontiguousarray(stream, dtype=np.uint8)
+    if s.size == 0:
+        s = np.zeros(1, np.uint8)
+    out = np.zeros((M, N), dtype=np.uint8)
+    _load().or_plane_decode(_u8(s), int(np.asarray(stream).size), M, N, _u8(out))
+    return out
+
+
+def lmr_compress(eta_rot, l_rot, cap: int):
+    """Container of both maps (bytes) or None when longer than cap bytes."""
+    eta_rot, l_rot = _img(eta_rot), _img(l_rot)
+    out = np.zeros(max(cap, 8) + 1, dtype=np.uint8)
+    n = _load().or_lmr_compress(_u8(eta_rot), _u8(l_rot), eta_rot.shape[0], eta_rot.shape[1], _u8(out), cap)
+    return None if n < 0 else out[:n].copy()
+
+
+def lmr_decompress(stream, M: int, N: int):
+    s = np.ascontiguousarray(stream, dtype=np.uint8)
+    eta = np.zeros((M, N), dtype=np.uint8)
+    l = np.zeros((M, N), dtype=np.uint8)
+    rc = _load().or_lmr_decompress(_u8(s), s.size, M, N, _u8(eta), _u8(l))
+    if rc != 0:
+        raise ValueError("malformed LMR stream")
+    return eta, l
+
+
+def lmr_encode(I, k1: int):
+    """Full LMR encoding: (I_e, meta, stream bytes) or (None, meta, None) for a bad case."""
+    I = _img(I)
+    M, N = I.shape
+    Ie = np.zeros_like(I)
+    m = _OrMeta()
+    stream = np.zeros(M * N // 8 + 16, dtype=np.uint8)
+    bits = ctypes.c_int64()
+    rc = _load().or_lmr_encode(_u8(I), M, N, k1, _u8(Ie), ctypes.byref(m), _u8(stream), ctypes.byref(bits))
+    meta = OracleMeta(m.b, m.min_level, m.max_level, m.redundant, m.capacity_bits)
+    if rc != 0:
+        return None, meta, None
+    return Ie, meta, stream[: bits.value // 8].copy()
 
 
 def psnr(a, b) -> float:

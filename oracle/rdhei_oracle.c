@@ -421,3 +421,191 @@ void or_lmr_recover(const uint8_t *Ie, int32_t M, int32_t N, int b, int min_leve
     recovery_glide(out, l, M, N, mask);
     free(s); free(l); free(eta);
 }
+
+/* ------------------------------------------------------------------------ */
+/* LMR map compression (Sec. III-B "Maps generation, rotation, and           */
+/* compression").  The paper uses JBIG-KIT; the library defines its own      */
+/* bi-level coder and this is a second, plain implementation of that         */
+/* definition:                                                               */
+/*   pixels in raster order; context of ten already-coded neighbours         */
+/*   (row-2: j-1, j, j+1; row-1: j-2 .. j+2; row: j-2, j-1; first listed is  */
+/*   the highest bit; outside the plane = 0); per context a 12-bit           */
+/*   probability of a 0, starting at 2048, moved by 1/32 of the distance     */
+/*   to 0 or 4096 after each bit; a 32-bit range coder (bound =              */
+/*   (range >> 12) * p; 0 keeps the low part; renormalise by bytes while     */
+/*   range < 2^24; carries ripple into the bytes already written; four      */
+/*   bytes of low flush the end).  Container: 32-bit big-endian byte counts  */
+/*   of the eta part and the l part, then the two parts.                     */
+/* ------------------------------------------------------------------------ */
+
+static int plane_at(const uint8_t *P, int32_t M, int32_t N, int64_t i, int64_t j)
+{
+    if (i < 0 || i >= M || j < 0 || j >= N) return 0;
+    return P[i * N + j] ? 1 : 0;
+}
+
+static int plane_context(const uint8_t *P, int32_t M, int32_t N, int64_t i, int64_t j)
+{
+    int c = 0;
+    c = (c << 1) | plane_at(P, M, N, i - 2, j - 1);
+    c = (c << 1) | plane_at(P, M, N, i - 2, j);
+    c = (c << 1) | plane_at(P, M, N, i - 2, j + 1);
+    c = (c << 1) | plane_at(P, M, N, i - 1, j - 2);
+    c = (c << 1) | plane_at(P, M, N, i - 1, j - 1);
+    c = (c << 1) | plane_at(P, M, N, i - 1, j);
+    c = (c << 1) | plane_at(P, M, N, i - 1, j + 1);
+    c = (c << 1) | plane_at(P, M, N, i - 1, j + 2);
+    c = (c << 1) | plane_at(P, M, N, i, j - 2);
+    c = (c << 1) | plane_at(P, M, N, i, j - 1);
+    return c;
+}
+
+/* Encode a plane (one byte 0/1 per pixel) into out; returns the byte count,
+ * or -1 if it would exceed cap. */
+int64_t or_plane_encode(const uint8_t *P, int32_t M, int32_t N, uint8_t *out, int64_t cap)
+{
+    uint32_t prob[1024];
+    for (int c = 0; c < 1024; ++c) prob[c] = 2048;
+    uint64_t low = 0;
+    uint32_t range = 0xFFFFFFFFu;
+    int64_t n = 0;
+    for (int64_t i = 0; i < M; ++i) {
+        for (int64_t j = 0; j < N; ++j) {
+            int c = plane_context(P, M, N, i, j);
+            int bit = P[i * N + j] ? 1 : 0;
+            uint32_t bound = (range >> 12) * prob[c];
+            if (bit == 0) {
+                range = bound;
+                prob[c] += (4096 - prob[c]) >> 5;
+            } else {
+                low += bound;
+                range -= bound;
+                prob[c] -= prob[c] >> 5;
+            }
+            if (low >= ((uint64_t)1 << 32)) {          /* carry into written bytes */
+                low -= (uint64_t)1 << 32;
+                for (int64_t k = n - 1; k >= 0; --k) {
+                    out[k] = (uint8_t)(out[k] + 1);
+                    if (out[k] != 0) break;
+                }
+            }
+            while (range < ((uint32_t)1 << 24)) {
+                if (n >= cap) return -1;
+                out[n++] = (uint8_t)(low >> 24);
+                low = (low << 8) & 0xFFFFFFFFull;
+                range <<= 8;
+            }
+        }
+    }
+    for (int k = 0; k < 4; ++k) {
+        if (n >= cap) return -1;
+        out[n++] = (uint8_t)(low >> 24);
+        low = (low << 8) & 0xFFFFFFFFull;
+    }
+    return n;
+}
+
+/* Decode a plane of M x N bits from in[0..len) (bytes past the end read 0). */
+void or_plane_decode(const uint8_t *in, int64_t len, int32_t M, int32_t N, uint8_t *P)
+{
+    uint32_t prob[1024];
+    for (int c = 0; c < 1024; ++c) prob[c] = 2048;
+    int64_t pos = 0;
+    uint32_t code = 0, range = 0xFFFFFFFFu;
+    for (int k = 0; k < 4; ++k) code = (code << 8) | (pos < len ? in[pos] : 0), ++pos;
+    for (int64_t i = 0; i < M; ++i) {
+        for (int64_t j = 0; j < N; ++j) {
+            int c = plane_context(P, M, N, i, j);
+            uint32_t bound = (range >> 12) * prob[c];
+            int bit;
+            if (code < bound) {
+                bit = 0;
+                range = bound;
+                prob[c] += (4096 - prob[c]) >> 5;
+            } else {
+                bit = 1;
+                code -= bound;
+                range -= bound;
+                prob[c] -= prob[c] >> 5;
+            }
+            P[i * N + j] = (uint8_t)bit;
+            while (range < ((uint32_t)1 << 24)) {
+                code = (code << 8) | (pos < len ? in[pos] : 0);
+                ++pos;
+                range <<= 8;
+            }
+        }
+    }
+}
+
+/* Container of the two compressed maps; returns its length in bytes or -1
+ * when it exceeds cap bytes. */
+int64_t or_lmr_compress(const uint8_t *eta, const uint8_t *l, int32_t M, int32_t N, uint8_t *out, int64_t cap)
+{
+    if (cap < 8) return -1;
+    int64_t ne = or_plane_encode(eta, M, N, out + 8, cap - 8);
+    if (ne < 0) return -1;
+    int64_t nl = or_plane_encode(l, M, N, out + 8 + ne, cap - 8 - ne);
+    if (nl < 0) return -1;
+    out[0] = (uint8_t)(ne >> 24); out[1] = (uint8_t)(ne >> 16); out[2] = (uint8_t)(ne >> 8); out[3] = (uint8_t)ne;
+    out[4] = (uint8_t)(nl >> 24); out[5] = (uint8_t)(nl >> 16); out[6] = (uint8_t)(nl >> 8); out[7] = (uint8_t)nl;
+    return 8 + ne + nl;
+}
+
+int or_lmr_decompress(const uint8_t *in, int64_t len, int32_t M, int32_t N, uint8_t *eta, uint8_t *l)
+{
+    if (len < 8) return -1;
+    int64_t ne = ((int64_t)in[0] << 24) | ((int64_t)in[1] << 16) | ((int64_t)in[2] << 8) | in[3];
+    int64_t nl = ((int64_t)in[4] << 24) | ((int64_t)in[5] << 16) | ((int64_t)in[6] << 8) | in[7];
+    if (8 + ne + nl > len) return -1;
+    or_plane_decode(in + 8, ne, M, N, eta);
+    or_plane_decode(in + 8 + ne, nl, M, N, l);
+    return 0;
+}
+
+/* LMR encoding phase (Sec. III-B): b in [2,8]; candidates in order of the
+ * LMR capacity (b-1)*Z_b (ties: smaller b first); for each, rotate the maps
+ * with blocks 2^4..2^n, compress, and keep the first whose stream fits the
+ * M*N-bit MSB plane (the "next most optimal location map" fallback).
+ * Returns 0 and fills Ie/meta/stream, or -1 for a bad case. */
+int or_lmr_encode(const uint8_t *I, int32_t M, int32_t N, uint64_t k1, uint8_t *Ie, or_meta *meta,
+                  uint8_t *stream, int64_t *stream_bits)
+{
+    size_t MN = (size_t)M * (size_t)N;
+    int64_t Z[7];
+    or_redundancy_counts(I, M, N, 2, 8, Z);
+    int order[7];
+    for (int k = 0; k < 7; ++k) order[k] = 2 + k;
+    for (int a = 1; a < 7; ++a) {            /* stable insertion sort, descending capacity */
+        int v = order[a], k = a - 1;
+        while (k >= 0 && (int64_t)(order[k] - 1) * Z[order[k] - 2] < (int64_t)(v - 1) * Z[v - 2]) {
+            order[k + 1] = order[k];
+            --k;
+        }
+        order[k + 1] = v;
+    }
+    uint8_t *l_rot = (uint8_t *)malloc(MN + 1), *eta_rot = (uint8_t *)malloc(MN + 1);
+    int64_t cap = (int64_t)(MN / 8);
+    int chosen = 0;
+    int64_t len = -1;
+    for (int k = 0; k < 7 && !chosen; ++k) {
+        int b = order[k];
+        or_lmr_rotated_maps(I, M, N, b, 4, k1, l_rot, eta_rot);
+        len = or_lmr_compress(eta_rot, l_rot, M, N, stream, cap);
+        if (len >= 0) chosen = b;
+    }
+    free(l_rot); free(eta_rot);
+    meta->min_level = 4;
+    meta->max_level = or_max_level(M, N);
+    if (!chosen) {
+        meta->b = 0; meta->redundant = 0; meta->capacity_bits = 0;
+        *stream_bits = 0;
+        return -1;
+    }
+    meta->b = chosen;
+    meta->redundant = Z[chosen - 2];
+    meta->capacity_bits = (int64_t)(chosen - 1) * Z[chosen - 2];
+    *stream_bits = 8 * len;
+    or_lmr_encrypt(I, M, N, 4, k1, stream, 8 * len, Ie);
+    return 0;
+}

@@ -104,15 +104,23 @@ def test_emr_partial_messages(R, ctx, frac):
     _roundtrip(R, ctx, I, 5, 6, frac=frac)
 
 
-@pytest.mark.parametrize("shape", [(1024, 512), (1024, 1024), (640, 1088), (1000, 777)],
+@pytest.mark.parametrize("shape", [(1024, 512), (1024, 1024), (640, 1088), (1000, 777), (2048, 1024), (1040, 1024)],
                          ids=lambda s: f"{s[0]}x{s[1]}")
 def test_emr_multi_segment_images(R, ctx, shape):
-    """Images spanning several raster segments (count pass, per-image scan,
-    message words shared by two segments)."""
+    """Images spanning several raster segments: whole-image hiding up to 64
+    segments, decoupled look-back beyond (and for pixel counts that are not a
+    multiple of 16), with message words shared by two segments."""
     M, N = shape
     I = _image(M + N, M, N, sigma=2.0)
     for frac in (1.0, 0.6):
         _roundtrip(R, ctx, I, 7 + M, 9 + N, frac=frac)
+
+
+def test_emr_4096_full_image(R, ctx):
+    """A 4096 x 4096 image (1024 look-back segments, 64 x 64 tiles, levels up
+    to 2^12) compared with the oracle pixel for pixel."""
+    I = inputs.make_band_image(12, 4096, 4096, 8, 3.0, "cpu").numpy()
+    _roundtrip(R, ctx, I, 101, 202, frac=1.0)
 
 
 def test_fast_and_per_pixel_paths_agree(R):
@@ -227,25 +235,49 @@ def test_per_image_plan_matches_batched(R, ctx):
         assert np.array_equal(a, b)
 
 
-def test_lmr_roundtrip_is_lossless(R, ctx):
-    """LMR on the GPU with the library's host coder: exact recovery and
-    error-free extraction (Sec. III-B)."""
-    for shape in [(256, 256), (128, 320), (100, 90)]:
-        M, N = shape
-        print(f"[lmr roundtrip] shape={M}x{N}", flush=True)
-        I = _image(M + 3 * N, M, N, sigma=1.0)
-        d_img = _dev(I)
-        d_enc = torch.empty_like(d_img)
-        meta = R.new_meta()
-        ctx.encrypt(d_img, d_enc, 31, meta, method=R.LMR)
-        m = R.read_meta(meta)
-        assert m.status == 0 and 2 <= m.b <= 8
-        nbits = m.capacity_bits
-        msg = inputs.make_payload(9, nbits).numpy()
-        ctx.embed(d_enc, meta, _msg_dev(R, msg, nbits), nbits, 41, method=R.LMR)
-        d_got = torch.zeros(R.msg_bytes(nbits), dtype=torch.uint8, device="cuda")
-        ctx.extract(d_enc, meta, d_got, nbits, 41, method=R.LMR)
-        assert np.array_equal(d_got.cpu().numpy()[:(nbits + 7) // 8], msg)
-        d_rec = torch.empty_like(d_img)
-        ctx.recover(d_enc, meta, d_rec, 31, method=R.LMR)
-        assert np.array_equal(d_rec.cpu().numpy(), I)
+@pytest.mark.parametrize("shape", [(256, 256), (128, 320), (100, 90), (64, 64)], ids=lambda s: f"{s[0]}x{s[1]}")
+def test_lmr_matches_oracle(R, ctx, shape):
+    """LMR (Sec. III-B) on the GPU with the library's host coder, against the
+    oracle's full LMR encoding (own coder, candidate fallback): encrypted image,
+    meta, marked image, extracted message and the exact recovery."""
+    M, N = shape
+    print(f"[lmr parity] shape={M}x{N}", flush=True)
+    I = _image(M + 3 * N, M, N, sigma=1.0)
+    k1, k2 = 31 + M, 41 + N
+    Ie_o, mo, stream = O.lmr_encode(I, k1)
+    assert Ie_o is not None
+    d_img = _dev(I)
+    d_enc = torch.empty_like(d_img)
+    meta = R.new_meta()
+    ctx.encrypt(d_img, d_enc, k1, meta, method=R.LMR)
+    m = R.read_meta(meta)
+    assert (m.status, m.b, m.redundant, m.capacity_bits) == (0, mo.b, mo.redundant, mo.capacity_bits)
+    assert m.map_bits == 8 * stream.size
+    assert np.array_equal(d_enc.cpu().numpy(), Ie_o)
+    nbits = m.capacity_bits
+    msg = inputs.make_payload(9, nbits).numpy()
+    eta_rot, l_rot = O.lmr_decompress(stream, M, N)
+    Iem_o = O.lmr_embed(Ie_o, mo.b, l_rot, msg, nbits, k2)
+    ctx.embed(d_enc, meta, _msg_dev(R, msg, nbits), nbits, k2, method=R.LMR)
+    assert np.array_equal(d_enc.cpu().numpy(), Iem_o)
+    d_got = torch.zeros(R.msg_bytes(nbits), dtype=torch.uint8, device="cuda")
+    ctx.extract(d_enc, meta, d_got, nbits, k2, method=R.LMR)
+    nb = (nbits + 7) // 8
+    assert np.array_equal(d_got.cpu().numpy()[:nb], O.lmr_extract(Iem_o, mo.b, l_rot, nbits, k2))
+    assert np.array_equal(d_got.cpu().numpy()[:nb], msg)
+    d_rec = torch.empty_like(d_img)
+    ctx.recover(d_enc, meta, d_rec, k1, method=R.LMR)
+    rec = d_rec.cpu().numpy()
+    assert np.array_equal(rec, O.lmr_recover(Iem_o, mo.b, 4, k1, l_rot, eta_rot))
+    assert np.array_equal(rec, I)
+
+
+def test_lmr_bad_case_reported(R, ctx):
+    """A pure-noise image cannot hold its maps in the MSB plane: ENOFIT."""
+    noise = np.random.default_rng(1).integers(0, 256, (64, 64)).astype(np.uint8)
+    d = _dev(noise)
+    meta = R.new_meta()
+    with pytest.raises(R.RdheiError) as ei:
+        ctx.encrypt(d, torch.empty_like(d), 5, meta, method=R.LMR)
+    assert ei.value.code == R.ENOFIT
+    assert R.read_meta(meta).status == R.ENOFIT

@@ -82,3 +82,28 @@ def test_lmr_coder_reports_no_fit(R):
     with pytest.raises(R.RdheiError) as ei:
         R.lmr_compress(eta, lb, M, N, M * N // 8)
     assert ei.value.code == R.ENOFIT
+
+
+def test_library_coder_matches_oracle_coder(R):
+    """The library's host map coder and the oracle's independent coder emit
+    identical streams for the same bit planes (both follow one coder
+    definition), and each decodes the other's stream."""
+    import oracle as O
+    from paper_2302_07992_amd import inputs
+    rng = np.random.default_rng(4)
+    cases = []
+    for (M, N) in [(16, 16), (37, 101), (128, 128)]:
+        y, x = np.mgrid[0:M, 0:N]
+        cases.append((M, N, (((y // 7) + (x // 5)) % 3 == 0).astype(np.uint8),
+                      (rng.random((M, N)) < 0.25).astype(np.uint8)))
+    I = inputs.make_image_np(2, 256, 256, 8, 1.0)
+    l_rot, eta_rot = O.lmr_rotated_maps(I, 5, 4, 11)
+    cases.append((256, 256, eta_rot, l_rot))
+    for M, N, eta, l in cases:
+        want = O.lmr_compress(eta, l, 64 + M * N)
+        got, bits = R.lmr_compress(np.packbits(eta.ravel()), np.packbits(l.ravel()), M, N, 64 + M * N)
+        assert bits == 8 * got.size
+        assert np.array_equal(got, want)
+        e2, l2 = R.lmr_decompress(want, M, N)
+        assert np.array_equal(np.unpackbits(e2)[:M * N], eta.ravel())
+        assert np.array_equal(np.unpackbits(l2)[:M * N], l.ravel())

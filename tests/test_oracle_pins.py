@@ -177,3 +177,62 @@ def test_max_level():
     assert O.max_level(1, 7) == 0
     assert O.max_level(3, 3) == 1
     assert O.max_level(16384, 16384) == 14
+
+
+# ------------------------------------------------------------ LMR map coder
+def _planes(rng, M, N):
+    y, x = np.mgrid[0:M, 0:N]
+    yield np.zeros((M, N), np.uint8)
+    yield np.ones((M, N), np.uint8)
+    yield (((y // 5) + (x // 3)) % 2).astype(np.uint8)
+    yield (rng.random((M, N)) < 0.1).astype(np.uint8)
+    yield (rng.random((M, N)) < 0.5).astype(np.uint8)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 37), (5, 3), (32, 32), (61, 97)])
+def test_oracle_coder_roundtrip(shape):
+    """The bi-level coder is lossless on any plane (Sec. III-B needs the maps
+    back exactly for lossless recovery)."""
+    M, N = shape
+    rng = np.random.default_rng(M * 1000 + N)
+    for P in _planes(rng, M, N):
+        s = O.plane_encode(P)
+        assert np.array_equal(O.plane_decode(s, M, N), P)
+
+
+def test_oracle_coder_compresses_structure():
+    """Constant and smooth planes shrink far below one bit per pixel; a fair
+    coin plane does not (no coder beats its entropy)."""
+    rng = np.random.default_rng(9)
+    M, N = 128, 128
+    assert O.plane_encode(np.zeros((M, N), np.uint8)).size < 40
+    y, x = np.mgrid[0:M, 0:N]
+    smooth = ((x + y) < 100).astype(np.uint8)
+    assert O.plane_encode(smooth).size < 200
+    coin = (rng.random((M, N)) < 0.5).astype(np.uint8)
+    assert O.plane_encode(coin).size > 0.98 * M * N / 8
+
+
+def test_oracle_lmr_encode_fits_and_falls_back():
+    """Sec. III-B: the stream of both compressed maps fits the M*N-bit MSB
+    plane; a pure-noise image is a bad case; DER_LMR = (b-1)/b * b*Z_b / MN."""
+    I = inputs.make_image_np(3, 128, 128, 8, 1.0)
+    Ie, meta, stream = O.lmr_encode(I, 5)
+    assert Ie is not None and 2 <= meta.b <= 8
+    assert 8 * stream.size <= 128 * 128
+    Z = O.redundancy_counts(I, 2, 8)
+    assert meta.redundant == Z[meta.b - 2]
+    assert meta.capacity_bits == (meta.b - 1) * Z[meta.b - 2]
+    # chosen b is the best capacity among candidates that fit: every better
+    # candidate must fail to fit
+    s = O.image_keystream(5, 128, 128)
+    better = [b for b in range(2, 9) if (b - 1) * Z[b - 2] > meta.capacity_bits]
+    for b in better:
+        l_rot, eta_rot = O.lmr_rotated_maps(I, b, 4, 5)
+        assert O.lmr_compress(eta_rot, l_rot, 128 * 128 // 8) is None
+    eta, l = O.lmr_decompress(stream, 128, 128)
+    l_rot, eta_rot = O.lmr_rotated_maps(I, meta.b, 4, 5)
+    assert np.array_equal(eta, eta_rot) and np.array_equal(l, l_rot)
+    noise = np.random.default_rng(1).integers(0, 256, (64, 64)).astype(np.uint8)
+    Ie2, meta2, st2 = O.lmr_encode(noise, 5)
+    assert Ie2 is None and st2 is None
