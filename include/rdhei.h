@@ -171,9 +171,30 @@ int         rdhei_plan_stage_count(rdhei_plan *plan);
 const char *rdhei_plan_stage_name(rdhei_plan *plan, int32_t k);
 int         rdhei_plan_run_stage(rdhei_plan *plan, int32_t k, void *stream);
 
+/* One EMR op over a batch of images, launched directly on `stream` (no plan,
+ * no graph): for batches whose composition changes from call to call, such
+ * as a serving loop.
+ *   d_workspace  device scratch of at least rdhei_workspace_size() bytes,
+ *                256-byte aligned, owned by the caller and in use until the
+ *                launches on `stream` finish; NULL: the context's own
+ *                workspace, grown when needed (growing synchronises the
+ *                device; RDHEI_OPT_RESERVE_WS sizes it up front).
+ * The job table goes up through a ring of 16 pinned staging buffers, so the
+ * call blocks only when it runs more than 16 calls ahead of the GPU.  Calls
+ * on one context must use one stream. */
+int rdhei_workspace_size(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t njobs, int64_t *bytes);
+int rdhei_run_batch(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t njobs, void *d_workspace,
+                    int64_t workspace_bytes, void *stream);
+
 /* Context options. */
-#define RDHEI_OPT_PER_PIXEL 1    /* 1: force the per-pixel path for every shape  */
-#define RDHEI_OPT_MAX_GRID  2    /* workgroup cap of grid-stride launches         */
+#define RDHEI_OPT_PER_PIXEL  1   /* 1: force the per-pixel path for every shape  */
+#define RDHEI_OPT_MAX_GRID   2   /* workgroup cap of grid-stride launches         */
+#define RDHEI_OPT_RESERVE_WS 3   /* allocate this many workspace bytes now        */
+#define RDHEI_OPT_HIDE_MODE  4   /* embed/extract of images up to 1 Mpx: 0 one
+                                    workgroup per image once a batch holds enough
+                                    of them to fill the device, else segments;
+                                    1 always one workgroup per image; 2 always
+                                    segments.  Results are identical.            */
 int rdhei_ctx_set_option(rdhei_ctx *ctx, int32_t option, int64_t value);
 
 /* ---- LMR host stage: bi-level map coder (Sec. III-B, map compression) ---- */

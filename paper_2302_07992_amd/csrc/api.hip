@@ -97,11 +97,32 @@ struct Layout {
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 // Build the device job table and workspace layout of one op over a batch.
-int make_layout(int op, const rdhei_job *in, int n, bool force_per_pixel, Layout &L) {
+struct LayoutOpts {
+    bool per_pixel = false;   // every image on the per-pixel path
+    int hide_mode = 0;        // RDHEI_OPT_HIDE_MODE
+};
+
+// Whether image q of a hiding op may be walked whole by one workgroup.
+bool whole_eligible(int op, const rdhei_job &q) {
+    if (op != RDHEI_OP_EMBED && op != RDHEI_OP_EXTRACT) return false;
+    const uint64_t MN = (uint64_t)q.height * (uint64_t)q.width;
+    const void *pin = op == RDHEI_OP_EMBED ? (const void *)q.out : (const void *)q.in;
+    return (MN + seg_pixels() - 1) / seg_pixels() <= (uint64_t)seq_max_segments() && MN % 16 == 0 &&
+           aligned16(pin) && aligned16(q.out);
+}
+
+int make_layout(int op, const rdhei_job *in, int n, const LayoutOpts &opt, Layout &L) {
     L = Layout();
     L.op = op;
     if (n < 1) return RDHEI_EINVAL;
     L.method = in[0].method;
+    const bool force_per_pixel = opt.per_pixel;
+    bool whole_ok = opt.hide_mode == 1;
+    if (opt.hide_mode == 0) {
+        uint32_t eligible = 0;
+        for (int i = 0; i < n; ++i) eligible += whole_eligible(op, in[i]) ? 1u : 0u;
+        whole_ok = eligible >= whole_image_min();
+    }
     uint64_t ws = 0;
     for (int i = 0; i < n; ++i) {
         const rdhei_job &q = in[i];
@@ -157,7 +178,7 @@ int make_layout(int op, const rdhei_job *in, int n, bool force_per_pixel, Layout
         // hiding: whole small images go to one workgroup each (UNIT_IMG), large
         // images are cut into look-back segments (UNIT_SEG)
         const bool hide = op == RDHEI_OP_EMBED || op == RDHEI_OP_EXTRACT;
-        const bool whole = hide && J.nseg <= seq_max_segments() && MN % 16 == 0 && aligned16(J.in) && aligned16(J.out);
+        const bool whole = whole_ok && whole_eligible(op, q);
         const uint32_t cnt[UNIT_KINDS] = {J.fast ? (uint32_t)(J.tiles_x * J.tiles_y) : 0u,
                                           J.fast ? (uint32_t)J.tiles_y : 0u,
                                           hide && !whole ? (uint32_t)J.nseg : 0u, whole ? 1u : 0u};
@@ -235,11 +256,54 @@ void issue(const Layout &Ly, const Launch &L, const uint32_t *units, const int *
 }  // namespace
 
 // ------------------------------------------------------------------------------
+// Ring of pinned host buffers for asynchronous job-table uploads: a slot is
+// reused only after the copy issued from it has completed.
+struct PinnedRing {
+    static constexpr int kSlots = 16;
+    uint8_t *buf[kSlots] = {};
+    size_t cap[kSlots] = {};
+    hipEvent_t done[kSlots] = {};
+    bool used[kSlots] = {};
+    int next = 0;
+    int acquire(size_t bytes, uint8_t **out, int *slot) {
+        const int k = next;
+        next = (next + 1) % kSlots;
+        if (used[k]) {
+            HIPCHK(hipEventSynchronize(done[k]));
+            used[k] = false;
+        }
+        if (!done[k]) HIPCHK(hipEventCreateWithFlags(&done[k], hipEventDisableTiming));
+        if (cap[k] < bytes) {
+            if (buf[k]) (void)hipHostFree(buf[k]);
+            buf[k] = nullptr;
+            cap[k] = 0;
+            const size_t want = std::max<size_t>(bytes, 1 << 16);
+            HIPCHK(hipHostMalloc((void **)&buf[k], want, hipHostMallocDefault));
+            cap[k] = want;
+        }
+        *out = buf[k];
+        *slot = k;
+        return RDHEI_OK;
+    }
+    void release_all() {
+        for (int k = 0; k < kSlots; ++k) {
+            if (used[k]) (void)hipEventSynchronize(done[k]);
+            if (buf[k]) (void)hipHostFree(buf[k]);
+            if (done[k]) (void)hipEventDestroy(done[k]);
+            buf[k] = nullptr;
+            done[k] = nullptr;
+            used[k] = false;
+        }
+    }
+};
+
 struct rdhei_ctx {
     int device = 0;
     int per_pixel = 0;
+    int hide_mode = 0;
     int max_grid = 0;
-    DevBuf ws, jobs, scratch;
+    DevBuf ws, jobs, scratch, batch_tables;
+    PinnedRing ring;
     std::vector<uint8_t> h_a, h_b, h_c;
 };
 
@@ -253,10 +317,24 @@ struct rdhei_plan {
     hipGraphExec_t exec = nullptr;
     std::vector<Stage> stages;     // batched sequence (for per-stage runs)
     Launch base;                   // device tables of the batched sequence
-    std::vector<std::vector<Stage>> per_image;   // PER_IMAGE plans: one sequence per image
+    // PER_IMAGE plans: each image laid out and launched on its own, exactly
+    // as the single-image entry points would
+    struct One {
+        Layout layout;
+        size_t table_off = 0;
+        std::vector<Stage> stages;
+    };
+    std::vector<One> per_image;
 };
 
 namespace {
+
+LayoutOpts opts_of(const rdhei_ctx *ctx) {
+    LayoutOpts o;
+    o.per_pixel = ctx->per_pixel != 0;
+    o.hide_mode = ctx->hide_mode;
+    return o;
+}
 
 int set_device(int dev) {
     HIPCHK(hipSetDevice(dev));
@@ -319,7 +397,7 @@ int run_single(rdhei_ctx *ctx, int op, const rdhei_job &job, hipStream_t st) {
     int rc = set_device(ctx->device);
     if (rc) return rc;
     Layout Ly;
-    rc = make_layout(op, &job, 1, ctx->per_pixel != 0, Ly);
+    rc = make_layout(op, &job, 1, opts_of(ctx), Ly);
     if (rc) return rc;
     Launch L;
     rc = stage(ctx, Ly, ctx->jobs, ctx->ws, st, L);
@@ -345,7 +423,7 @@ int lmr_encrypt(rdhei_ctx *ctx, const uint8_t *d_img, uint8_t *d_enc, int32_t M,
     q.in = d_img; q.out = d_enc; q.meta = d_meta; q.key = k1; q.nbits = 0;
     q.height = M; q.width = N; q.method = RDHEI_LMR;
     Layout Ly;
-    rc = make_layout(RDHEI_OP_ENCRYPT, &q, 1, ctx->per_pixel != 0, Ly);
+    rc = make_layout(RDHEI_OP_ENCRYPT, &q, 1, opts_of(ctx), Ly);
     if (rc) return rc;
     const uint64_t MN = (uint64_t)M * N;
     const uint64_t plane = align_up((MN + 7) / 8 + 16, 256);
@@ -470,7 +548,7 @@ int lmr_stage(rdhei_ctx *ctx, int op, const uint8_t *d_marked, uint8_t *d_out, i
     q.in = d_marked; q.out = d_out; q.msg = d_msg; q.meta = d_meta; q.key = key; q.nbits = nbits;
     q.height = M; q.width = N; q.method = RDHEI_LMR;
     Layout Ly;
-    rc = make_layout(op, &q, 1, ctx->per_pixel != 0, Ly);
+    rc = make_layout(op, &q, 1, opts_of(ctx), Ly);
     if (rc) return rc;
     Ly.jobs[0].lbits = d_l;
     Ly.jobs[0].etabits = d_eta;
@@ -494,11 +572,14 @@ int plan_issue(rdhei_plan *P, hipStream_t st) {
     L.g_ticket = Ly.g_ticket;
     L.g_part = Ly.g_part;
     if (P->flags == RDHEI_PLAN_PER_IMAGE) {
-        const Job *tables = reinterpret_cast<const Job *>(P->single.p);
-        for (size_t j = 0; j < P->per_image.size(); ++j) {
-            L.jobs = tables + j;
+        for (const rdhei_plan::One &o : P->per_image) {
+            L.jobs = reinterpret_cast<const Job *>(P->single.p + o.table_off);
+            for (int k = 0; k < UNIT_KINDS; ++k) L.ujob[k] = nullptr;
             L.njobs = 1;
-            for (const Stage &s : P->per_image[j]) s.fn(L);
+            L.g_status = o.layout.g_status;
+            L.g_ticket = o.layout.g_ticket;
+            L.g_part = o.layout.g_part;
+            for (const Stage &s : o.stages) s.fn(L);
         }
     } else {
         L.jobs = P->base.jobs;
@@ -539,6 +620,8 @@ void rdhei_ctx_destroy(rdhei_ctx *ctx) {
     ctx->ws.release();
     ctx->jobs.release();
     ctx->scratch.release();
+    ctx->batch_tables.release();
+    ctx->ring.release_all();
     delete ctx;
 }
 
@@ -548,6 +631,14 @@ int rdhei_ctx_set_option(rdhei_ctx *ctx, int32_t option, int64_t value) {
     else if (option == RDHEI_OPT_MAX_GRID) {
         if (value < 0 || value > (1 << 30)) return RDHEI_EINVAL;
         ctx->max_grid = (int)value;
+    } else if (option == RDHEI_OPT_HIDE_MODE) {
+        if (value < 0 || value > 2) return RDHEI_EINVAL;
+        ctx->hide_mode = (int)value;
+    } else if (option == RDHEI_OPT_RESERVE_WS) {
+        if (value < 0) return RDHEI_EINVAL;
+        int rc = set_device(ctx->device);
+        if (rc) return rc;
+        return ctx->ws.need((size_t)value);
     } else return RDHEI_EINVAL;
     return RDHEI_OK;
 }
@@ -606,6 +697,72 @@ int rdhei_recover(rdhei_ctx *ctx, const uint8_t *d_marked, int32_t M, int32_t N,
     return run_single(ctx, RDHEI_OP_RECOVER, q, st);
 }
 
+int rdhei_workspace_size(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t njobs, int64_t *bytes) {
+    if (!ctx || !jobs || njobs < 1 || !bytes) return RDHEI_EINVAL;
+    int rc = set_device(ctx->device);
+    if (rc) return rc;
+    Layout Ly;
+    rc = make_layout(op, jobs, njobs, opts_of(ctx), Ly);
+    if (rc) return rc;
+    *bytes = (int64_t)Ly.ws_bytes;
+    return RDHEI_OK;
+}
+
+int rdhei_run_batch(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t njobs, void *d_workspace,
+                    int64_t workspace_bytes, void *stream) {
+    if (!ctx || !jobs || njobs < 1) return RDHEI_EINVAL;
+    if (d_workspace && ((uintptr_t)d_workspace & 255)) return RDHEI_EINVAL;
+    int rc = set_device(ctx->device);
+    if (rc) return rc;
+    Layout Ly;
+    rc = make_layout(op, jobs, njobs, opts_of(ctx), Ly);
+    if (rc) return rc;
+    if (Ly.method != RDHEI_EMR) return RDHEI_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    uint8_t *ws = (uint8_t *)d_workspace;
+    if (ws) {
+        if (workspace_bytes < (int64_t)Ly.ws_bytes) return RDHEI_EINVAL;
+    } else {
+        rc = ctx->ws.need(Ly.ws_bytes);
+        if (rc) return rc;
+        ws = ctx->ws.p;
+    }
+    size_t off[UNIT_KINDS];
+    const size_t tb = table_bytes(Ly, off);
+    // device tables: one region per staging slot inside one buffer, so a new
+    // batch never overwrites tables that an earlier launch may still read
+    // (stream order makes a region safe to rewrite kSlots calls later)
+    const size_t region = align_up(std::max<size_t>(tb, 1 << 16), 256);
+    if (ctx->batch_tables.n < PinnedRing::kSlots * region) {
+        rc = ctx->batch_tables.need(PinnedRing::kSlots * region);  // synchronises
+        if (rc) return rc;
+    }
+    uint8_t *host = nullptr;
+    int slot = 0;
+    rc = ctx->ring.acquire(tb, &host, &slot);
+    if (rc) return rc;
+    uint8_t *dtab = ctx->batch_tables.p + (size_t)slot * (ctx->batch_tables.n / PinnedRing::kSlots);
+    memcpy(host, Ly.jobs.data(), Ly.jobs.size() * sizeof(Job));
+    for (int k = 0; k < UNIT_KINDS; ++k)
+        if (!Ly.ujob[k].empty()) memcpy(host + off[k], Ly.ujob[k].data(), Ly.ujob[k].size() * 4);
+    HIPCHK(hipMemcpyAsync(dtab, host, tb, hipMemcpyHostToDevice, st));
+    HIPCHK(hipEventRecord(ctx->ring.done[slot], st));
+    ctx->ring.used[slot] = true;
+    Launch L;
+    L.jobs = reinterpret_cast<const Job *>(dtab);
+    for (int k = 0; k < UNIT_KINDS; ++k) L.ujob[k] = Ly.ujob[k].empty() ? nullptr : reinterpret_cast<const uint32_t *>(dtab + off[k]);
+    L.njobs = (int32_t)Ly.jobs.size();
+    L.ws = ws;
+    L.stream = st;
+    L.max_grid = ctx->max_grid;
+    L.g_status = Ly.g_status;
+    L.g_ticket = Ly.g_ticket;
+    L.g_part = Ly.g_part;
+    for (const Stage &sg : stages_of(Ly, Ly.units, Ly.per_pixel)) sg.fn(L);
+    HIPCHK(hipGetLastError());
+    return RDHEI_OK;
+}
+
 int rdhei_plan_create(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t njobs, int32_t flags,
                       rdhei_plan **out) {
     if (!ctx || !jobs || njobs < 1 || !out) return RDHEI_EINVAL;
@@ -618,20 +775,31 @@ int rdhei_plan_create(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t
     P->ctx = ctx;
     P->flags = flags;
     P->max_grid = ctx->max_grid;
-    rc = make_layout(op, jobs, njobs, ctx->per_pixel != 0, P->layout);
+    rc = make_layout(op, jobs, njobs, opts_of(ctx), P->layout);
     if (!rc && P->layout.method != RDHEI_EMR) rc = RDHEI_EINVAL;
     size_t toff[UNIT_KINDS];
     if (!rc) rc = P->jobs.need(table_bytes(P->layout, toff));
     if (!rc) rc = P->ws.need(P->layout.ws_bytes);
     if (!rc) rc = upload_tables(P->layout, P->jobs.p, nullptr, true, P->base);
     if (!rc && flags == RDHEI_PLAN_PER_IMAGE) {
-        std::vector<Job> single = P->layout.jobs;
-        for (Job &J : single)
-            for (int k = 0; k < UNIT_KINDS; ++k) J.ubase[k] = 0;
-        rc = P->single.need(single.size() * sizeof(Job));
-        if (!rc) {
-            hipError_t e = hipMemcpy(P->single.p, single.data(), single.size() * sizeof(Job), hipMemcpyHostToDevice);
+        P->per_image.resize((size_t)njobs);
+        size_t total = 0;
+        uint64_t ws = P->layout.ws_bytes;
+        for (int i = 0; i < njobs && !rc; ++i) {
+            rdhei_plan::One &o = P->per_image[(size_t)i];
+            rc = make_layout(op, jobs + i, 1, opts_of(ctx), o.layout);
+            o.table_off = total;
+            size_t off1[UNIT_KINDS];
+            total += align_up(table_bytes(o.layout, off1), 256);
+            ws = std::max<uint64_t>(ws, o.layout.ws_bytes);
+        }
+        if (!rc) rc = P->single.need(total);
+        if (!rc) rc = P->ws.need(ws);
+        for (int i = 0; i < njobs && !rc; ++i) {
+            rdhei_plan::One &o = P->per_image[(size_t)i];
+            hipError_t e = hipMemcpy(P->single.p + o.table_off, o.layout.jobs.data(), sizeof(Job), hipMemcpyHostToDevice);
             if (e != hipSuccess) { set_err("hipMemcpy", e); rc = RDHEI_EDEVICE; }
+            o.stages = stages_of(o.layout, o.layout.units, o.layout.per_pixel);
         }
     }
     if (rc) {
@@ -642,16 +810,6 @@ int rdhei_plan_create(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t
         return rc;
     }
     P->stages = stages_of(P->layout, P->layout.units, P->layout.per_pixel);
-    if (flags == RDHEI_PLAN_PER_IMAGE) {
-        for (const Job &h : P->layout.jobs) {
-            Layout one;
-            one.op = P->layout.op;
-            one.method = P->layout.method;
-            one.jobs.push_back(h);
-            const bool pp = !h.fast && (one.op == RDHEI_OP_ENCRYPT || one.op == RDHEI_OP_RECOVER);
-            P->per_image.push_back(stages_of(one, h.ucount, pp ? std::vector<int>{0} : std::vector<int>{}));
-        }
-    }
     *out = P;
     return RDHEI_OK;
 }

@@ -80,6 +80,7 @@ void launch_encrypt_tiles(const Launch &L, uint32_t units, int mode);
 void launch_recover_bands(const Launch &L, uint32_t units, int method);
 uint64_t seg_pixels();
 int seq_max_segments();
+uint32_t whole_image_min();
 void launch_hide_images(const Launch &L, uint32_t units, bool embed);
 void hide_ws_layout(uint32_t units, uint64_t base, uint64_t &status, uint64_t &ticket, uint64_t &part, uint64_t &end);
 void launch_embed(const Launch &L, uint32_t units);

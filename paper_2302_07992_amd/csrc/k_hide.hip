@@ -640,6 +640,21 @@ void launch_hide_images(const Launch &L, uint32_t units, bool embed) {
 
 int seq_max_segments() { return kSeqMaxSeg; }
 
+// Batches of at least this many small images hide one image per workgroup:
+// twice the workgroups of k_hide_seq resident on the device, so the
+// sequential walk of each image is hidden behind the others.  Smaller
+// batches (and single images) take the segment path, whose latency per image
+// is a few segments deep.
+uint32_t whole_image_min() {
+    static uint32_t v = 0;
+    if (!v) {
+        Launch L;
+        L.max_grid = 0;
+        v = 2u * resident_grid(L, k_hide_seq<true>, 0xffffffffu);
+    }
+    return v;
+}
+
 void launch_embed(const Launch &L, uint32_t units) {
     if (!units) return;
     uint64_t *status = reinterpret_cast<uint64_t *>(L.ws + L.g_status);

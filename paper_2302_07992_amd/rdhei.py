@@ -21,13 +21,13 @@ OK, EINVAL, ECAPACITY, ENOFIT, ENOMEM, EDEVICE, ECORRUPT = 0, -1, -2, -3, -4, -5
 EMR, LMR = 0, 1
 OP_ENCRYPT, OP_EMBED, OP_EXTRACT, OP_RECOVER = 0, 1, 2, 3
 PLAN_GRAPH, PLAN_EAGER, PLAN_PER_IMAGE = 0, 1, 2
-OPT_PER_PIXEL, OPT_MAX_GRID = 1, 2
+OPT_PER_PIXEL, OPT_MAX_GRID, OPT_RESERVE_WS, OPT_HIDE_MODE = 1, 2, 3, 4
 META_BYTES = 64
 
 EXPORTS = [
     "rdhei_ctx_create", "rdhei_ctx_destroy", "rdhei_ctx_set_option",
     "rdhei_encrypt", "rdhei_embed", "rdhei_extract", "rdhei_recover",
-    "rdhei_plan_create", "rdhei_plan_run", "rdhei_plan_destroy", "rdhei_plan_set_grid",
+    "rdhei_workspace_size", "rdhei_run_batch", "rdhei_plan_create", "rdhei_plan_run", "rdhei_plan_destroy", "rdhei_plan_set_grid",
     "rdhei_plan_stage_count", "rdhei_plan_stage_name", "rdhei_plan_run_stage",
     "rdhei_lmr_compress", "rdhei_lmr_decompress",
     "rdhei_strerror", "rdhei_last_error", "rdhei_version",
@@ -57,6 +57,22 @@ class JobStruct(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+# numpy view of rdhei_job, for building large job tables without Python loops
+JOB_DTYPE = np.dtype([("inp", "<u8"), ("out", "<u8"), ("msg", "<u8"), ("meta", "<u8"), ("key", "<u8"),
+                      ("nbits", "<i8"), ("height", "<i4"), ("width", "<i4"), ("method", "<i4"),
+                      ("reserved", "<i4")])
+assert JOB_DTYPE.itemsize == ctypes.sizeof(JobStruct)
+
+
+def _jobs_arg(jobs):
+    """(pointer, count) of a job table given as a ctypes array or a JOB_DTYPE array."""
+    if isinstance(jobs, np.ndarray):
+        if jobs.dtype != JOB_DTYPE or not jobs.flags.c_contiguous:
+            raise TypeError("job table must be a contiguous JOB_DTYPE array")
+        return jobs.ctypes.data_as(ctypes.POINTER(JobStruct)), len(jobs)
+    return jobs, len(jobs)
+
+
 _lib = None
 
 
@@ -78,6 +94,8 @@ def load_library(path: str = LIB_PATH):
     lib.rdhei_embed.argtypes = [vp, vp, i32, i32, i32, vp, vp, i64, u64, vp]
     lib.rdhei_extract.argtypes = [vp, vp, i32, i32, i32, vp, vp, i64, u64, vp]
     lib.rdhei_recover.argtypes = [vp, vp, i32, i32, i32, vp, vp, u64, vp]
+    lib.rdhei_workspace_size.argtypes = [vp, i32, ctypes.POINTER(JobStruct), i32, ctypes.POINTER(ctypes.c_int64)]
+    lib.rdhei_run_batch.argtypes = [vp, i32, ctypes.POINTER(JobStruct), i32, vp, ctypes.c_int64, vp]
     lib.rdhei_plan_create.argtypes = [vp, i32, ctypes.POINTER(JobStruct), i32, i32, ctypes.POINTER(vp)]
     lib.rdhei_plan_run.argtypes = [vp, vp]
     lib.rdhei_plan_destroy.argtypes = [vp]
@@ -200,6 +218,20 @@ class Context:
         M, N = marked.shape
         _check(self.lib.rdhei_extract(self.h, _ptr(marked), M, N, method, _ptr(meta), _ptr(msg), nbits, k2,
                                       _stream(stream)), "rdhei_extract")
+
+    def workspace_size(self, op: int, jobs) -> int:
+        """Device workspace bytes that run_batch needs for this op and job array."""
+        out = ctypes.c_int64(0)
+        p, n = _jobs_arg(jobs)
+        _check(self.lib.rdhei_workspace_size(self.h, op, p, n, ctypes.byref(out)), "rdhei_workspace_size")
+        return int(out.value)
+
+    def run_batch(self, op: int, jobs, workspace_ptr: int = 0, workspace_bytes: int = 0, stream=None) -> None:
+        """One EMR op over a job array (see make_jobs), launched directly on
+        `stream`; workspace_ptr 0 uses the context's own workspace."""
+        p, n = _jobs_arg(jobs)
+        _check(self.lib.rdhei_run_batch(self.h, op, p, n, ctypes.c_void_p(workspace_ptr or None),
+                                        workspace_bytes, _stream(stream)), "rdhei_run_batch")
 
     def recover(self, marked: torch.Tensor, meta: torch.Tensor, out: torch.Tensor, k1: int, method: int = EMR,
                 stream=None) -> None:

@@ -163,11 +163,74 @@ def test_invalid_arguments_rejected_on_host(R, ctx):
         ctx.encrypt(d, d, 1, meta)                 # aliasing input/output
     with pytest.raises(R.RdheiError):
         ctx.encrypt(d, torch.empty_like(d), 1, meta, method=7)
+    c2 = R.Context(0)
+    for opt, bad in ((R.OPT_HIDE_MODE, 3), (R.OPT_HIDE_MODE, -1), (R.OPT_MAX_GRID, -5), (R.OPT_RESERVE_WS, -1), (99, 0)):
+        with pytest.raises(R.RdheiError):
+            c2.set_option(opt, bad)
+    c2.set_option(R.OPT_RESERVE_WS, 1 << 20)
 
 
-def test_batched_plan_uneven_sizes_matches_oracle(R, ctx):
+def test_run_batch_matches_plan(R, ctx):
+    """rdhei_run_batch (direct launches, caller or context workspace) gives the
+    plan's bytes for all four ops; a short caller workspace is refused."""
+    shapes = [(128, 128), (64, 256), (45, 77), (256, 192)]
+    n = len(shapes)
+    imgs = [_dev(_image(700 + i, *s)) for i, s in enumerate(shapes)]
+    k1s, k2s = [71 + i for i in range(n)], [91 + i for i in range(n)]
+    outs = []
+    for how in ("plan", "ctx_ws", "caller_ws"):
+        print(f"[run_batch] {how}", flush=True)
+        enc = [torch.empty_like(x) for x in imgs]
+        rec = [torch.empty_like(x) for x in imgs]
+        metas = R.new_meta(n)
+        mp = [metas[i] for i in range(n)]
+        ej = R.make_jobs(imgs, enc, None, mp, k1s, None, shapes)
+        if how == "plan":
+            R.Plan(ctx, R.OP_ENCRYPT, ej).run()
+        else:
+            c = R.Context(0)
+            ws = None
+            if how == "caller_ws":
+                need = c.workspace_size(R.OP_ENCRYPT, ej)
+                ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+                p = (ws.data_ptr() + 255) // 256 * 256
+                with pytest.raises(R.RdheiError):
+                    c.run_batch(R.OP_ENCRYPT, ej, p, need - 256)
+                c.run_batch(R.OP_ENCRYPT, ej, p, need)
+            else:
+                c.run_batch(R.OP_ENCRYPT, ej)
+        torch.cuda.synchronize()
+        caps = [m.capacity_bits for m in R.read_meta(metas)]
+        msgs = [_msg_dev(R, inputs.make_payload(k, cp).numpy(), cp) for k, cp in zip(k2s, caps)]
+        got = [torch.zeros(R.msg_bytes(cp), dtype=torch.uint8, device="cuda") for cp in caps]
+        rest = [(R.OP_EMBED, R.make_jobs(None, enc, msgs, mp, k2s, caps, shapes)),
+                (R.OP_EXTRACT, R.make_jobs(enc, None, got, mp, k2s, caps, shapes)),
+                (R.OP_RECOVER, R.make_jobs(enc, rec, None, mp, k1s, None, shapes))]
+        for op, jobs in rest:
+            if how == "plan":
+                R.Plan(ctx, op, jobs).run()
+            elif how == "caller_ws":
+                need = c.workspace_size(op, jobs)
+                ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+                c.run_batch(op, jobs, (ws.data_ptr() + 255) // 256 * 256, need)
+                torch.cuda.synchronize()
+            else:
+                c.run_batch(op, jobs)
+        torch.cuda.synchronize()
+        outs.append([x.cpu().numpy() for x in enc + rec] + [x.cpu().numpy()[: (cp + 7) // 8] for x, cp in zip(got, caps)])
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("hide_mode", [0, 1, 2], ids=["auto", "whole", "segments"])
+def test_batched_plan_uneven_sizes_matches_oracle(R, hide_mode):
     """One plan per op over images of different shapes (tiled and per-pixel
-    in the same launch), graph-captured, replayed twice."""
+    in the same launch), graph-captured, replayed twice; hiding either walks
+    small images whole (one workgroup each) or in look-back segments."""
+    print(f"[batched uneven] hide_mode={hide_mode}", flush=True)
+    ctx = R.Context(0)
+    ctx.set_option(R.OPT_HIDE_MODE, hide_mode)
     shapes = [(64, 64), (128, 64), (256, 256), (33, 47), (512, 512), (64, 192), (100, 63), (320, 256)]
     imgs = [_image(100 + i, *s, sigma=(1, 3, 8, 20)[i % 4], nsin=2 + i) for i, s in enumerate(shapes)]
     n = len(imgs)
@@ -217,22 +280,37 @@ def test_batched_plan_uneven_sizes_matches_oracle(R, ctx):
 
 
 def test_per_image_plan_matches_batched(R, ctx):
-    shapes = [(256, 256)] * 6 + [(64, 128)] * 3
+    """The four ops as graph, eager and per-image plans give the same bytes;
+    per-image plans launch each image as the single-image entry points do."""
+    shapes = [(256, 256)] * 4 + [(64, 128)] * 2 + [(33, 47), (100, 64)]
     imgs = [_image(300 + i, *s) for i, s in enumerate(shapes)]
+    n = len(imgs)
     d_in = [_dev(I) for I in imgs]
+    k1s = [5 + i for i in range(n)]
+    k2s = [50 + i for i in range(n)]
     res = []
     for flags in (R.PLAN_GRAPH, R.PLAN_EAGER, R.PLAN_PER_IMAGE):
+        print(f"[plan flags] {flags}", flush=True)
         d_enc = [torch.empty_like(x) for x in d_in]
-        metas = R.new_meta(len(imgs))
-        jobs = R.make_jobs(d_in, d_enc, None, [metas[i] for i in range(len(imgs))],
-                           [5 + i for i in range(len(imgs))], None, shapes)
-        R.Plan(ctx, R.OP_ENCRYPT, jobs, flags).run()
+        d_rec = [torch.empty_like(x) for x in d_in]
+        metas = R.new_meta(n)
+        mp = [metas[i] for i in range(n)]
+        R.Plan(ctx, R.OP_ENCRYPT, R.make_jobs(d_in, d_enc, None, mp, k1s, None, shapes), flags).run()
         torch.cuda.synchronize()
-        res.append([x.cpu().numpy() for x in d_enc])
-    for a, b in zip(res[0], res[1]):
-        assert np.array_equal(a, b)
-    for a, b in zip(res[0], res[2]):
-        assert np.array_equal(a, b)
+        caps = [m.capacity_bits for m in R.read_meta(metas)]
+        d_msg = [_msg_dev(R, inputs.make_payload(k, c).numpy(), c) for k, c in zip(k2s, caps)]
+        d_got = [torch.zeros(R.msg_bytes(c), dtype=torch.uint8, device="cuda") for c in caps]
+        R.Plan(ctx, R.OP_EMBED, R.make_jobs(None, d_enc, d_msg, mp, k2s, caps, shapes), flags).run()
+        R.Plan(ctx, R.OP_EXTRACT, R.make_jobs(d_enc, None, d_got, mp, k2s, caps, shapes), flags).run()
+        R.Plan(ctx, R.OP_RECOVER, R.make_jobs(d_enc, d_rec, None, mp, k1s, None, shapes), flags).run()
+        torch.cuda.synchronize()
+        res.append(([x.cpu().numpy() for x in d_enc], [x.cpu().numpy() for x in d_got],
+                    [x.cpu().numpy() for x in d_rec], metas.cpu().numpy()))
+    for other in res[1:]:
+        for a, b in zip(res[0][:3], other[:3]):
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y)
+        assert np.array_equal(res[0][3], other[3])
 
 
 @pytest.mark.parametrize("shape", [(256, 256), (128, 320), (100, 90), (64, 64)], ids=lambda s: f"{s[0]}x{s[1]}")

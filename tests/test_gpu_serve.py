@@ -1,0 +1,146 @@
+"""Serving loop on the GPU: every request's outputs are byte-identical when
+served alone (single-image entry points) and inside mixed continuous
+batches, and match the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2302_07992_amd import serve
+    return serve
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2302_07992_amd import rdhei
+    return rdhei
+
+
+@pytest.fixture(scope="module")
+def workload(S, R):
+    # tiled and untiled sides; 48 requests of the 60/40 mix
+    print("[serve] building workload", flush=True)
+    return S.make_workload(48, seed=5, sides=[64, 128, 256, 96, 100, 320], weights=[3, 3, 2, 1, 1, 1],
+                           keep_originals=True)
+
+
+def _alone(R, wl, i):
+    """Request i through the single-image entry points, on its own."""
+    ctx = R.Context()
+    M = int(wl.side[i])
+    nbits = int(wl.nbits[i])
+    if wl.kind[i] == 0:
+        enc = torch.empty(M, M, dtype=torch.uint8, device="cuda")
+        meta = R.new_meta()
+        msg = torch.zeros(R.msg_bytes(nbits), dtype=torch.uint8, device="cuda")
+        msg[: wl.payloads[i].numel()] = wl.payloads[i]
+        ctx.encrypt(wl.images[i], enc, int(wl.k1[i]), meta)
+        ctx.embed(enc, meta, msg, nbits, int(wl.k2[i]))
+        torch.cuda.synchronize()
+        return {"marked": enc.cpu().numpy(), "meta": meta.cpu().numpy()}
+    meta_in = _meta_of(R, wl, i)
+    msg = torch.zeros(R.msg_bytes(nbits), dtype=torch.uint8, device="cuda")
+    rec = torch.empty(M, M, dtype=torch.uint8, device="cuda")
+    ctx.extract(wl.images[i], meta_in, msg, nbits, int(wl.k2[i]))
+    ctx.recover(wl.images[i], meta_in, rec, int(wl.k1[i]))
+    torch.cuda.synchronize()
+    return {"recovered": rec.cpu().numpy(), "payload": msg.cpu().numpy()}
+
+
+def _meta_of(R, wl, i):
+    """The resident metadata tensor of RECOVER request i."""
+    for t in wl.keep:
+        if t.data_ptr() == int(wl.meta_ptr[i]):
+            return t
+    raise KeyError(i)
+
+
+def _serve(S, wl, arrivals, **kw):
+    got = {}
+
+    def keep(i, views):
+        got[i] = {k: v.cpu().numpy().copy() for k, v in views.items()}
+
+    srv = S.Server(on_complete=keep, **kw)
+    res = srv.run(wl, arrivals)
+    return res, got
+
+
+def _bits(a, nbits):
+    return np.unpackbits(np.asarray(a, np.uint8))[:nbits]
+
+
+@pytest.mark.parametrize("mode", ["burst", "poisson", "per_request"])
+def test_served_equals_alone(S, R, workload, mode):
+    wl = workload
+    n = len(wl)
+    print(f"[serve] isolation mode={mode} n={n}", flush=True)
+    if mode == "burst":
+        arrivals = np.zeros(n)                        # all queued at once: large batches
+        kw = dict(pool_bytes=1 << 20, streams=2)      # pool binds: several batches
+    elif mode == "poisson":
+        arrivals = S.poisson_arrivals(n, 20000.0, seed=2)
+        kw = dict(pool_bytes=4 << 20, streams=3)
+    else:
+        arrivals = S.poisson_arrivals(n, 20000.0, seed=2)
+        kw = dict(pool_bytes=4 << 20, per_request=True)
+    res, got = _serve(S, wl, arrivals, **kw)
+    assert res.rejected == 0
+    assert sorted(got) == list(range(n))
+    assert np.all(np.isfinite(res.latency_s)) and np.all(res.latency_s > 0)
+    if mode == "burst":
+        assert 1 < res.batches < n                    # admission split the burst
+    if mode == "per_request":
+        assert res.batches == n
+    for i in range(n):
+        ref = _alone(R, wl, i)
+        if wl.kind[i] == 0:
+            assert np.array_equal(got[i]["marked"], ref["marked"]), i
+            assert np.array_equal(got[i]["meta"], ref["meta"]), i
+        else:
+            nb = int(wl.nbits[i])
+            assert np.array_equal(got[i]["recovered"], ref["recovered"]), i
+            assert np.array_equal(_bits(got[i]["payload"], nb), _bits(ref["payload"], nb)), i
+
+
+def test_served_matches_oracle(S, R, workload):
+    """Served outputs against the oracle: the marked image of EMBED requests,
+    and the payload and restored image of RECOVER requests."""
+    wl = workload
+    n = len(wl)
+    res, got = _serve(S, wl, np.zeros(n), pool_bytes=2 << 20, streams=2)
+    assert res.rejected == 0
+    checked = 0
+    for i in range(n):
+        I = wl.images[i].cpu().numpy()
+        k1, k2, nb = int(wl.k1[i]), int(wl.k2[i]), int(wl.nbits[i])
+        pay = wl.payloads[i].cpu().numpy()
+        if wl.kind[i] == 0:
+            Ie, mo = O.emr_encrypt(I, k1)
+            assert mo.capacity_bits == nb
+            marked = O.emr_embed(Ie, mo.b, pay, nb, k2)
+            assert np.array_equal(got[i]["marked"], marked), i
+        else:
+            orig = wl.originals[i].cpu().numpy()
+            _, mo = O.emr_encrypt(orig, k1)
+            assert np.array_equal(_bits(got[i]["payload"], nb), _bits(pay, nb)), i
+            assert np.array_equal(got[i]["recovered"], O.emr_recover(I, mo.b, k1)), i
+            assert np.all((got[i]["recovered"] ^ orig) <= 1)
+        checked += 1
+    assert checked == n
+
+
+def test_request_larger_than_pool_is_rejected(S, workload):
+    wl = workload
+    big = int(np.argmax(wl.footprint()))
+    pool = int(wl.footprint()[big]) - 1024
+    res, got = _serve(S, wl, np.zeros(len(wl)), pool_bytes=pool, streams=1)
+    assert res.rejected >= 1
+    assert not np.isfinite(res.latency_s[big])
+    assert big not in got
