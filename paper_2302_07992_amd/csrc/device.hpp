@@ -2,6 +2,7 @@
 // composed block rotation.
 #pragma once
 #include "internal.hpp"
+#include "perm4.hpp"
 
 namespace rdhei {
 
@@ -43,8 +44,9 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
         const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        // three-input XOR in one instruction (truth table 0x96)
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -198,6 +200,90 @@ __device__ __forceinline__ void block_map(const uint8_t *rec, int min_level, uin
             }
         }
     }
+}
+
+// Destination of 4x4 block (by, bx) inside the tile, and the turns of its
+// content: R1 (levels >= 2 and the turns from above the tile) and the level-1
+// codes of its 2x2 sub-blocks packed per row pair (left + 4 * right); levels
+// below min_level contribute nothing.
+__device__ __forceinline__ void block_turns(const uint8_t *rec, int min_level, uint32_t up_turns, uint32_t by,
+                                            uint32_t bx, uint32_t &ny, uint32_t &nx, uint32_t &R1, uint32_t &k0,
+                                            uint32_t &k1) {
+    uint32_t acc = up_turns;
+    ny = 0;
+    nx = 0;
+#pragma unroll
+    for (int m = kTileLog; m >= 3; --m) {
+        if (m >= min_level) acc += tile_code(rec, m, by >> (m - 2), bx >> (m - 2));
+        const int j = m - 3;
+        uint32_t yb = (by >> j) & 1u, xb = (bx >> j) & 1u;
+        turn_bits(acc & 3u, yb, xb, 1u);
+        ny |= yb << j;
+        nx |= xb << j;
+    }
+    R1 = (acc + (2 >= min_level ? tile_code(rec, 2, by, bx) : 0u)) & 3u;
+    if (min_level <= 1) {
+        const uint32_t q0 = (2u * by) * (uint32_t)(kTile >> 1) + 2u * bx;
+        const uint32_t q1 = q0 + (uint32_t)(kTile >> 1);
+        k0 = (rec[code_off(1) + (q0 >> 2)] >> (2 * (q0 & 3u))) & 0xFu;
+        k1 = (rec[code_off(1) + (q1 >> 2)] >> (2 * (q1 & 3u))) & 0xFu;
+    } else {
+        k0 = 0;
+        k1 = 0;
+    }
+}
+
+// ---- 4x4 block permutes (selector tables staged in LDS) -------------------------
+static __constant__ perm4::Tables kPermTables = perm4::kTables;
+constexpr int kPermSub = 0, kPermWhole = 32, kPermSubInv = 64;
+
+__device__ __forceinline__ void stage_perm_tables(uint32_t *lds, int tid) {
+    if (tid < perm4::kWords) lds[tid] = reinterpret_cast<const uint32_t *>(&kPermTables)[tid];
+}
+
+__device__ __forceinline__ uint32_t vperm(uint32_t a, uint32_t b, uint32_t sel) {
+    return __builtin_amdgcn_perm(a, b, sel);
+}
+
+// Rows w of a source block -> rows o of the block at its destination.
+__device__ __forceinline__ void block_forward(const uint32_t *T, uint32_t R1, uint32_t k0, uint32_t k1,
+                                              const uint32_t w[4], uint32_t o[4]) {
+    const uint2 s0 = *reinterpret_cast<const uint2 *>(T + kPermSub + 2 * k0);
+    const uint2 s1 = *reinterpret_cast<const uint2 *>(T + kPermSub + 2 * k1);
+    const uint32_t t0 = vperm(w[1], w[0], s0.x), t1 = vperm(w[1], w[0], s0.y);
+    const uint32_t t2 = vperm(w[3], w[2], s1.x), t3 = vperm(w[3], w[2], s1.y);
+    const uint4 a = *reinterpret_cast<const uint4 *>(T + kPermWhole + 8 * R1);
+    const uint4 b = *reinterpret_cast<const uint4 *>(T + kPermWhole + 8 * R1 + 4);
+    o[0] = vperm(t1, t0, a.x) | vperm(t3, t2, a.y);
+    o[1] = vperm(t1, t0, a.z) | vperm(t3, t2, a.w);
+    o[2] = vperm(t1, t0, b.x) | vperm(t3, t2, b.y);
+    o[3] = vperm(t1, t0, b.z) | vperm(t3, t2, b.w);
+}
+
+// Rows w of a block at its destination -> rows o of the source block.  The
+// selectors are shared by the two planes the recovery moves.
+struct InvSel {
+    uint4 a, b;
+    uint2 s0, s1;
+};
+__device__ __forceinline__ InvSel inverse_selectors(const uint32_t *T, uint32_t R1, uint32_t k0, uint32_t k1) {
+    const uint32_t r = (4u - R1) & 3u;
+    InvSel S;
+    S.a = *reinterpret_cast<const uint4 *>(T + kPermWhole + 8 * r);
+    S.b = *reinterpret_cast<const uint4 *>(T + kPermWhole + 8 * r + 4);
+    S.s0 = *reinterpret_cast<const uint2 *>(T + kPermSubInv + 2 * k0);
+    S.s1 = *reinterpret_cast<const uint2 *>(T + kPermSubInv + 2 * k1);
+    return S;
+}
+__device__ __forceinline__ void block_inverse(const InvSel &S, const uint32_t w[4], uint32_t o[4]) {
+    const uint32_t t0 = vperm(w[1], w[0], S.a.x) | vperm(w[3], w[2], S.a.y);
+    const uint32_t t1 = vperm(w[1], w[0], S.a.z) | vperm(w[3], w[2], S.a.w);
+    const uint32_t t2 = vperm(w[1], w[0], S.b.x) | vperm(w[3], w[2], S.b.y);
+    const uint32_t t3 = vperm(w[1], w[0], S.b.z) | vperm(w[3], w[2], S.b.w);
+    o[0] = vperm(t1, t0, S.s0.x);
+    o[1] = vperm(t1, t0, S.s0.y);
+    o[2] = vperm(t3, t2, S.s1.x);
+    o[3] = vperm(t3, t2, S.s1.y);
 }
 
 }  // namespace rdhei
