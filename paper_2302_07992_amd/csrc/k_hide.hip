@@ -12,6 +12,7 @@
 // already owned by running workgroups.  The wait is bounded: past a spin limit
 // the image is flagged RDHEI_EDEVICE instead of waiting forever.
 #include "device.hpp"
+#include "hide4.hpp"
 
 namespace rdhei {
 
@@ -82,6 +83,126 @@ __device__ __forceinline__ uint32_t redundant16(const Job &J, uint4 px, uint64_t
     }
     if (pos + 16 > total) m &= (1u << (uint32_t)(total - pos)) - 1u;
     return m;
+}
+
+// ---- four pixels per word ---------------------------------------------------------
+// Field permutes of hide4.hpp, staged once per workgroup in LDS: compact at 0,
+// expand at 16, redundant-byte masks at 32.
+static __constant__ hide4::Tables kHideTables = hide4::kTables;
+
+__device__ __forceinline__ void stage_hide_tables(uint32_t *lds, int tid) {
+    if (tid < hide4::kWords) lds[tid] = reinterpret_cast<const uint32_t *>(&kHideTables)[tid];
+}
+
+// Per-image constants of the word-wise field moves.
+struct Hide4 {
+    uint32_t rep, shift;
+    uint32_t low_bytes;   // (2^rep - 1) in every byte
+    uint32_t rep_bytes;   // the replaceable bits, in every byte
+    uint32_t low_pairs;   // (2^rep - 1) in bytes 0 and 2
+};
+
+__device__ __forceinline__ Hide4 hide4_params(const HideParams &hp) {
+    Hide4 h;
+    h.rep = hp.rep;
+    h.shift = hp.shift;
+    const uint32_t low = (1u << hp.rep) - 1u;
+    h.low_bytes = low * 0x01010101u;
+    h.rep_bytes = (low << hp.shift) * 0x01010101u;
+    h.low_pairs = low * 0x00010001u;
+    return h;
+}
+
+// 32 payload bits (top bit first) starting at bit p of a staged window whose
+// word 0 is a guard, so p >= 32 and the bits lie in words (p-1)/32 and the next.
+__device__ __forceinline__ uint32_t window_bits(const uint32_t *win, uint32_t p) {
+    const uint32_t t = p - 1u;
+    const uint32_t a = t >> 5;
+    return __builtin_amdgcn_alignbit(win[a], win[a + 1], 31u - (t & 31u));
+}
+
+// OR a run of bits (top-aligned in s) into an extraction window at bit p.
+__device__ __forceinline__ void window_or(uint32_t *win, uint32_t p, uint32_t s) {
+    const uint32_t a = p >> 5, sb = p & 31u;
+    atomicOr(&win[a], s >> sb);
+    atomicOr(&win[a + 1], __builtin_amdgcn_alignbit(s, 0u, sb));
+}
+
+// Embedding into 16 pixels (four words w) with redundancy mask rm: the first
+// redundant pixel takes the payload bits from window position rel (relative
+// to the staged window, before its guard word); bits at rend and beyond are
+// not part of the payload.  Whole words use the field permutes; the one word
+// where the payload ends goes pixel by pixel.
+__device__ __forceinline__ void embed16(uint32_t w[4], uint32_t rm, uint32_t rel, uint32_t rend, const uint32_t *win,
+                                        const Hide4 &hk, const uint32_t *T) {
+    const uint32_t rep = hk.rep;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t m = (rm >> (4 * q)) & 0xFu;
+        const uint32_t pos = rel;
+        rel += (uint32_t)__popc(m) * rep;
+        if (m == 0 || pos >= rend) continue;
+        if (rel <= rend) {
+            const uint32_t run = window_bits(win, pos + 32u);
+            const uint32_t F01 = run >> (32u - 2u * rep);
+            const uint32_t F23 = __builtin_amdgcn_ubfe(run, 32u - 4u * rep, 2u * rep);
+            const uint32_t t = (F01 << 16) | F23;
+            const uint32_t cp = (t & hk.low_pairs) | (((t >> rep) & hk.low_pairs) << 8);
+            const uint32_t e = vperm(0u, cp, T[16 + m]) << hk.shift;
+            const uint32_t K = T[32 + m] & hk.rep_bytes;
+            w[q] = (w[q] & ~K) | (e & K);
+        } else {
+            const uint32_t top = hk.shift + rep - 1u;
+            uint32_t p = pos, x = w[q];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (((m >> j) & 1u) && p < rend) {
+                    const uint32_t val = window_bits(win, p + 32u) >> (32u - rep);
+                    const uint32_t left = rend - p;
+                    const uint32_t take = left < rep ? left : rep;
+                    const uint32_t wmask = ((1u << take) - 1u) << (top + 1u - take);
+                    x = (x & ~(wmask << (8 * j))) | (((val << hk.shift) & wmask) << (8 * j));
+                    p += rep;
+                }
+            }
+            w[q] = x;
+        }
+    }
+}
+
+// Extraction from 16 pixels: the payload bits of the redundant pixels are ORed
+// into the window (word 0 = first window word) from position rel on; bits at
+// rend and beyond are dropped.
+__device__ __forceinline__ void extract16(const uint32_t w[4], uint32_t rm, uint32_t rel, uint32_t rend, uint32_t *win,
+                                          const Hide4 &hk, const uint32_t *T) {
+    const uint32_t rep = hk.rep;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t m = (rm >> (4 * q)) & 0xFu;
+        const uint32_t pos = rel;
+        rel += (uint32_t)__popc(m) * rep;
+        if (m == 0 || pos >= rend) continue;
+        if (rel <= rend) {
+            const uint32_t f = (w[q] >> hk.shift) & hk.low_bytes;
+            const uint32_t c = vperm(0u, f, T[m]);
+            const uint32_t s = (((c >> 24) << (3u * rep)) | (((c >> 16) & 0xFFu) << (2u * rep)) |
+                                (((c >> 8) & 0xFFu) << rep) | (c & 0xFFu)) << (32u - 4u * rep);
+            window_or(win, pos, s);
+        } else {
+            uint32_t p = pos;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (((m >> j) & 1u) && p < rend) {
+                    const uint32_t pv = (w[q] >> (8 * j)) & 0xFFu;
+                    const uint32_t left = rend - p;
+                    const uint32_t take = left < rep ? left : rep;
+                    const uint32_t val = (pv >> (hk.shift + rep - take)) & ((1u << take) - 1u);
+                    window_or(win, p, val << (32u - take));
+                    p += take;
+                }
+            }
+        }
+    }
 }
 
 // Exclusive scan over the workgroup of four 16-bit counters packed in a u64
@@ -224,7 +345,8 @@ __device__ __forceinline__ uint32_t grab_ticket(uint32_t *ticket, uint32_t *sh_t
 // Hide the payload bits that fall in one segment.  All branches that guard a
 // barrier test wave-uniform values.
 __device__ __forceinline__ void embed_unit(const Job &J, const HideParams &hp, uint32_t u, uint32_t seg,
-                                           uint64_t *status, uint64_t *sh, uint64_t *shv, uint32_t *win) {
+                                           uint64_t *status, uint64_t *sh, uint64_t *shv, uint32_t *win,
+                                           const uint32_t *htab) {
     const int tid = threadIdx.x;
     SegState S;
     seg_count(J, J.out, u, seg, status, sh, shv, S);
@@ -242,35 +364,23 @@ __device__ __forceinline__ void embed_unit(const Job &J, const HideParams &hp, u
         const uint64_t blk = (uint64_t)(fb + q);
         const uint4 mv = gload<uint4>(J.msg + 16 * blk);
         const U4 ks = stream_block(J.key, kDomainMessage, blk);
-        uint32_t *wp = win + 4 * q;
+        uint32_t *wp = win + 1 + 4 * q;   // word 0 is a guard
         wp[0] = __builtin_bswap32(mv.x ^ ks.x);
         wp[1] = __builtin_bswap32(mv.y ^ ks.y);
         wp[2] = __builtin_bswap32(mv.z ^ ks.z);
         wp[3] = __builtin_bswap32(mv.w ^ ks.w);
     }
     __syncthreads();
-    const uint32_t top = hp.shift + hp.rep - 1;
+    const Hide4 hk = hide4_params(hp);
+    const int64_t wbase = fb << 7;
+    const uint32_t rend = (uint32_t)(wend - wbase);
 #pragma unroll
     for (int k = 0; k < kSegLoads; ++k) {
         const uint32_t rm = S.rm[k];
-        int64_t bit = (int64_t)(S.rank[k] * hp.rep);
+        const int64_t bit = (int64_t)(S.rank[k] * hp.rep);
         if (!rm || bit >= wend) continue;
         uint32_t w[4] = {S.px[k].x, S.px[k].y, S.px[k].z, S.px[k].w};
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            if (((rm >> q) & 1u) && bit < wend) {
-                const int64_t rel = bit - (fb << 7);
-                const uint32_t wi = (uint32_t)(rel >> 5), sb = (uint32_t)(rel & 31);
-                const uint64_t v64 = ((uint64_t)win[wi] << 32) | win[wi + 1];
-                const uint32_t val = (uint32_t)((v64 << sb) >> (64 - hp.rep));
-                const int64_t left = wend - bit;
-                const uint32_t take = left < (int64_t)hp.rep ? (uint32_t)left : hp.rep;
-                const uint32_t wmask = ((1u << take) - 1u) << (top + 1 - take);
-                const uint32_t sh8 = 8 * (q & 3);
-                w[q >> 2] = (w[q >> 2] & ~(wmask << sh8)) | (((val << hp.shift) & wmask) << sh8);
-                bit += hp.rep;
-            }
-        }
+        embed16(w, rm, (uint32_t)(bit - wbase), rend, win, hk, htab);
         const uint64_t pos = S.s0 + (uint64_t)k * (kThreads * 16) + 16 * (uint64_t)tid;
         store16(J.out, pos, S.s1, make_uint4(w[0], w[1], w[2], w[3]));
     }
@@ -284,7 +394,9 @@ __global__ __launch_bounds__(kThreads) void k_embed(const Job *__restrict__ jobs
     __shared__ uint64_t shv[2];
     __shared__ uint32_t sh_t;
     __shared__ uint32_t win[kWinWords];
+    __shared__ uint32_t htab[hide4::kWords];
     const int tid = threadIdx.x;
+    stage_hide_tables(htab, tid);   // read after the ticket barrier
     while (true) {
         const uint32_t u = grab_ticket(ticket, &sh_t);
         if (u >= units) break;
@@ -294,7 +406,7 @@ __global__ __launch_bounds__(kThreads) void k_embed(const Job *__restrict__ jobs
         if (!hp.ok) {
             if (tid == 0 && u == J.ubase[UNIT_SEG] && J.meta->status == RDHEI_OK) J.meta->status = RDHEI_ECAPACITY;
         } else {
-            embed_unit(J, hp, u, u - J.ubase[UNIT_SEG], status, sh, shv, win);
+            embed_unit(J, hp, u, u - J.ubase[UNIT_SEG], status, sh, shv, win, htab);
         }
         __syncthreads();
     }
@@ -331,7 +443,7 @@ __device__ __forceinline__ uint32_t ks_word(uint64_t key, int64_t w) {
 // Extract the payload bits of one segment.
 __device__ __forceinline__ void extract_unit(const Job &J, const HideParams &hp, int j, uint32_t u, uint32_t seg,
                                              uint64_t *status, uint64_t *sh, uint64_t *shv, uint32_t *win,
-                                             PartWord *part) {
+                                             PartWord *part, const uint32_t *htab) {
     const int tid = threadIdx.x;
     SegState S;
     seg_count(J, J.in, u, seg, status, sh, shv, S);
@@ -346,34 +458,15 @@ __device__ __forceinline__ void extract_unit(const Job &J, const HideParams &hp,
     const int64_t W0 = wstart >> 5, W1 = (wend + 31) >> 5;
     for (int64_t q = tid; q < W1 - W0 + 1; q += kThreads) win[q] = 0u;
     __syncthreads();
+    const Hide4 hk = hide4_params(hp);
+    const uint32_t rend = (uint32_t)(wend - 32 * W0);
 #pragma unroll
     for (int k = 0; k < kSegLoads; ++k) {
         const uint32_t rm = S.rm[k];
-        int64_t bit = (int64_t)(S.rank[k] * hp.rep);
+        const int64_t bit = (int64_t)(S.rank[k] * hp.rep);
         if (!rm || bit >= wend) continue;
         const uint32_t w[4] = {S.px[k].x, S.px[k].y, S.px[k].z, S.px[k].w};
-        int64_t cw = (bit >> 5) - W0;
-        uint32_t nacc = (uint32_t)(bit & 31);
-        uint64_t acc = 0;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            if (((rm >> q) & 1u) && bit < wend) {
-                const uint32_t pv = (w[q >> 2] >> (8 * (q & 3))) & 0xFFu;
-                const int64_t left = wend - bit;
-                const uint32_t take = left < (int64_t)hp.rep ? (uint32_t)left : hp.rep;
-                const uint32_t val = (pv >> (hp.shift + hp.rep - take)) & ((1u << take) - 1u);
-                acc |= (uint64_t)val << (64 - nacc - take);
-                nacc += take;
-                bit += take;
-                if (nacc >= 32) {
-                    atomicOr(&win[cw], (uint32_t)(acc >> 32));
-                    ++cw;
-                    acc <<= 32;
-                    nacc -= 32;
-                }
-            }
-        }
-        if (nacc) atomicOr(&win[cw], (uint32_t)(acc >> 32));
+        extract16(w, rm, (uint32_t)(bit - 32 * W0), rend, win, hk, htab);
     }
     __syncthreads();
     uint32_t *msgw = reinterpret_cast<uint32_t *>(J.msg);
@@ -400,7 +493,9 @@ __global__ __launch_bounds__(kThreads) void k_extract(const Job *__restrict__ jo
     __shared__ uint64_t shv[2];
     __shared__ uint32_t sh_t;
     __shared__ uint32_t win[kWinWords];
+    __shared__ uint32_t htab[hide4::kWords];
     const int tid = threadIdx.x;
+    stage_hide_tables(htab, tid);   // read after the ticket barrier
     while (true) {
         const uint32_t u = grab_ticket(ticket, &sh_t);
         if (u >= units) break;
@@ -411,7 +506,7 @@ __global__ __launch_bounds__(kThreads) void k_extract(const Job *__restrict__ jo
         if (!hp.ok) {
             if (tid == 0 && u == J.ubase[UNIT_SEG] && J.meta->status == RDHEI_OK) J.meta->status = RDHEI_ECAPACITY;
         } else {
-            extract_unit(J, hp, j, u, u - J.ubase[UNIT_SEG], status, sh, shv, win, part);
+            extract_unit(J, hp, j, u, u - J.ubase[UNIT_SEG], status, sh, shv, win, part, htab);
         }
         __syncthreads();
     }
@@ -447,12 +542,14 @@ __device__ __forceinline__ void seg_load(const uint8_t *img, uint64_t s0, uint64
 }
 
 template <bool EMBED>
-__device__ __forceinline__ void hide_image(const Job &J, const HideParams &hp, uint64_t *sh, uint32_t *win) {
+__device__ __forceinline__ void hide_image(const Job &J, const HideParams &hp, uint64_t *sh, uint32_t *win,
+                                           const uint32_t *htab) {
     const int tid = threadIdx.x;
     const uint8_t *img = EMBED ? J.out : J.in;
     const uint64_t total = (uint64_t)J.M * (uint64_t)J.N;
     const uint32_t nseg = (uint32_t)((total + kSegPx - 1) / kSegPx);
     const uint32_t rep = hp.rep;
+    const Hide4 hk = hide4_params(hp);
     uint64_t rank = 0;
     uint32_t carry = 0;          // extraction: bits of the partial word left by the previous segment
     int64_t carry_word = -1;
@@ -499,33 +596,19 @@ __device__ __forceinline__ void hide_image(const Job &J, const HideParams &hp, u
                 const uint64_t blk = (uint64_t)(fb + q);
                 const uint4 mv = gload<uint4>(J.msg + 16 * blk);
                 const U4 ks = stream_block(J.key, kDomainMessage, blk);
-                uint32_t *wp = win + 4 * q;
+                uint32_t *wp = win + 1 + 4 * q;   // word 0 is a guard
                 wp[0] = __builtin_bswap32(mv.x ^ ks.x);
                 wp[1] = __builtin_bswap32(mv.y ^ ks.y);
                 wp[2] = __builtin_bswap32(mv.z ^ ks.z);
                 wp[3] = __builtin_bswap32(mv.w ^ ks.w);
             }
             __syncthreads();
-            const uint32_t top = hp.shift + rep - 1;
 #pragma unroll
             for (int k = 0; k < kSegLoads; ++k) {
-                uint32_t rel = off0 + lr[k] * rep;
+                const uint32_t rel = off0 + lr[k] * rep;
                 if (!rm[k] || rel >= rend) continue;
                 uint32_t w[4] = {px[k].x, px[k].y, px[k].z, px[k].w};
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    if (((rm[k] >> q) & 1u) && rel < rend) {
-                        const uint32_t wi = rel >> 5, sb = rel & 31;
-                        const uint64_t v64 = ((uint64_t)win[wi] << 32) | win[wi + 1];
-                        const uint32_t val = (uint32_t)((v64 << sb) >> (64 - rep));
-                        const uint32_t left = rend - rel;
-                        const uint32_t take = left < rep ? left : rep;
-                        const uint32_t wmask = ((1u << take) - 1u) << (top + 1 - take);
-                        const uint32_t sh8 = 8 * (q & 3);
-                        w[q >> 2] = (w[q >> 2] & ~(wmask << sh8)) | (((val << hp.shift) & wmask) << sh8);
-                        rel += rep;
-                    }
-                }
+                embed16(w, rm[k], rel, rend, win, hk, htab);
                 gstore<uint4>(J.out + s0 + (uint64_t)k * (kThreads * 16) + 16 * (uint64_t)tid,
                               make_uint4(w[0], w[1], w[2], w[3]));
             }
@@ -536,31 +619,10 @@ __device__ __forceinline__ void hide_image(const Job &J, const HideParams &hp, u
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < kSegLoads; ++k) {
-                uint32_t rel = off0 + lr[k] * rep;
+                const uint32_t rel = off0 + lr[k] * rep;
                 if (!rm[k] || rel >= rend) continue;
                 const uint32_t w[4] = {px[k].x, px[k].y, px[k].z, px[k].w};
-                uint32_t cw = rel >> 5;
-                uint32_t nacc = rel & 31;
-                uint64_t acc = 0;
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    if (((rm[k] >> q) & 1u) && rel < rend) {
-                        const uint32_t pv = (w[q >> 2] >> (8 * (q & 3))) & 0xFFu;
-                        const uint32_t left = rend - rel;
-                        const uint32_t take = left < rep ? left : rep;
-                        const uint32_t val = (pv >> (hp.shift + rep - take)) & ((1u << take) - 1u);
-                        acc |= (uint64_t)val << (64 - nacc - take);
-                        nacc += take;
-                        rel += take;
-                        if (nacc >= 32) {
-                            atomicOr(&win[cw], (uint32_t)(acc >> 32));
-                            ++cw;
-                            acc <<= 32;
-                            nacc -= 32;
-                        }
-                    }
-                }
-                if (nacc) atomicOr(&win[cw], (uint32_t)(acc >> 32));
+                extract16(w, rm[k], rel, rend, win, hk, htab);
             }
             __syncthreads();
             // complete words go out; a trailing partial word waits for the next segment
@@ -587,7 +649,9 @@ __global__ __launch_bounds__(kThreads) void k_hide_seq(const Job *__restrict__ j
                                                         const uint32_t *__restrict__ ujob) {
     __shared__ uint64_t sh[kThreads / 64];
     __shared__ uint32_t win[kWinWords];
+    __shared__ uint32_t htab[hide4::kWords];
     const int tid = threadIdx.x;
+    stage_hide_tables(htab, tid);   // read after the first scan barrier
     const uint32_t per = (units + gridDim.x - 1) / gridDim.x;
     const uint32_t u0 = blockIdx.x * per, u1 = u0 + per < units ? u0 + per : units;
     for (uint32_t u = u0; u < u1; ++u) {
@@ -597,7 +661,7 @@ __global__ __launch_bounds__(kThreads) void k_hide_seq(const Job *__restrict__ j
         if (!hp.ok) {
             if (tid == 0 && J.meta->status == RDHEI_OK) J.meta->status = RDHEI_ECAPACITY;
         } else {
-            hide_image<EMBED>(J, hp, sh, win);
+            hide_image<EMBED>(J, hp, sh, win, htab);
         }
         __syncthreads();
     }

@@ -279,6 +279,46 @@ def test_batched_plan_uneven_sizes_matches_oracle(R, hide_mode):
             assert np.array_equal(d_got[i].cpu().numpy()[:(caps[i] + 7) // 8], msgs[i])
 
 
+@pytest.mark.parametrize("hide_mode", [1, 2], ids=["whole", "segments"])
+def test_batched_partial_payloads_match_oracle(R, hide_mode):
+    """Batched embed/extract with payloads that end inside a pixel's field and
+    inside a word of four pixels (nbits not a multiple of rep), next to full
+    and empty ones; whole-image and segment hiding."""
+    print(f"[batched partial] hide_mode={hide_mode}", flush=True)
+    ctx = R.Context(0)
+    ctx.set_option(R.OPT_HIDE_MODE, hide_mode)
+    shapes = [(256, 256), (128, 320), (512, 512), (64, 64), (192, 128), (320, 256)]
+    n = len(shapes)
+    imgs = [_image(900 + i, *s, sigma=(1, 3, 8, 20)[i % 4]) for i, s in enumerate(shapes)]
+    d_in = [_dev(I) for I in imgs]
+    d_enc = [torch.empty_like(x) for x in d_in]
+    metas = R.new_meta(n)
+    mp = [metas[i] for i in range(n)]
+    k1s, k2s = [3000 + i for i in range(n)], [4000 + i for i in range(n)]
+    R.Plan(ctx, R.OP_ENCRYPT, R.make_jobs(d_in, d_enc, None, mp, k1s, None, shapes)).run()
+    torch.cuda.synchronize()
+    caps = [m.capacity_bits for m in R.read_meta(metas)]
+    oracle = [O.emr_encrypt(I, k) for I, k in zip(imgs, k1s)]
+    fr = [1.0, 0.37, 0.5, 0.0, 0.999, 0.73]
+    nbits = [max(0, int(c * f) - (1 if 0 < f < 1 else 0)) for c, f in zip(caps, fr)]
+    msgs = [inputs.make_payload(k, nb).numpy() for k, nb in zip(k2s, nbits)]
+    d_msg = [_msg_dev(R, m, nb) for m, nb in zip(msgs, nbits)]
+    R.Plan(ctx, R.OP_EMBED, R.make_jobs(None, d_enc, d_msg, mp, k2s, nbits, shapes)).run()
+    d_got = [torch.zeros(R.msg_bytes(nb), dtype=torch.uint8, device="cuda") for nb in nbits]
+    R.Plan(ctx, R.OP_EXTRACT, R.make_jobs(d_enc, None, d_got, mp, k2s, nbits, shapes)).run()
+    torch.cuda.synchronize()
+    for i in range(n):
+        Ie_o, mo = oracle[i]
+        Iem_o = O.emr_embed(Ie_o, mo.b, msgs[i], nbits[i], k2s[i])
+        assert np.array_equal(d_enc[i].cpu().numpy(), Iem_o), f"image {i} nbits {nbits[i]}"
+        nb = (nbits[i] + 7) // 8
+        got = d_got[i].cpu().numpy()
+        assert np.array_equal(got[:nb], O.emr_extract(Iem_o, mo.b, nbits[i], k2s[i])), f"image {i}"
+        assert np.array_equal(np.unpackbits(got[:nb])[:nbits[i]], np.unpackbits(msgs[i])[:nbits[i]])
+        if nbits[i] % 8:
+            assert got[nb - 1] & (0xFF >> (nbits[i] % 8)) == 0      # bits past nbits stored as zero
+
+
 def test_per_image_plan_matches_batched(R, ctx):
     """The four ops as graph, eager and per-image plans give the same bytes;
     per-image plans launch each image as the single-image entry points do."""
