@@ -62,7 +62,9 @@ def parse():
     ap.add_argument("--check", type=int, default=6, help="sampled images checked against the oracle")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="bounded oracle timing (0: skip)")
     ap.add_argument("--max-grid", type=int, default=0)
+    ap.add_argument("--autotune", type=int, default=3, help="timed runs per candidate launch shape (0: defaults)")
     ap.add_argument("--serve-requests", type=int, default=3000, help="serving-loop requests (0: skip)")
+    ap.add_argument("--large-sides", default="8192,16384", help="single large images timed stage by stage ('' to skip)")
     ap.add_argument("--serve-pool-mib", type=int, default=2048, help="device pool of the serving loop")
     ap.add_argument("--serve-streams", type=int, default=2)
     ap.add_argument("--serve-loads", default="0.5,0.7,0.9", help="offered load as fractions of batched capacity")
@@ -113,6 +115,82 @@ def serve_bench(args):
             "pool_MiB": args.serve_pool_mib, "streams": args.serve_streams,
             "capacity_req_per_s": cap, "capacity_mpx_per_s": burst["mpx_per_s"], "burst": burst,
             "loads": loads, "per_request": pr}
+
+
+def large_bench(args):
+    """Single large images (sigma 3, 8 sinusoids, drawn in row bands) through
+    encrypt / embed (payload at capacity) / extract / recover, each stage timed
+    with HIP events on its stream; checked at full size: the extracted bits
+    equal the payload, and the recovered image differs from the original only
+    in bit 0 (EMR keeps no copy of the LSB plane)."""
+    import numpy as np
+    import torch
+
+    from paper_2302_07992_amd import inputs, rdhei
+    dev = torch.device("cuda:0")
+    ctx = rdhei.Context(0)
+    out = []
+    for side in [int(x) for x in args.large_sides.split(",") if x]:
+        seed = 77 + side
+        log(f"[large] {side}x{side}")
+        img = inputs.make_band_image(seed, side, side, 8, 3.0, dev)
+        enc = torch.empty_like(img)
+        rec = torch.empty_like(img)
+        meta = rdhei.new_meta()
+        k1, k2 = inputs.key_pair(seed)
+        ctx.encrypt(img, enc, k1, meta)
+        torch.cuda.synchronize()
+        m = rdhei.read_meta(meta)
+        cap = int(m.capacity_bits)
+        nbytes = rdhei.msg_bytes(cap)
+        g = torch.Generator(device=dev)
+        g.manual_seed(seed)
+        msg = torch.randint(0, 256, (nbytes,), generator=g, device=dev, dtype=torch.int32).to(torch.uint8)
+        got = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
+        ops = {
+            "encrypt": lambda: ctx.encrypt(img, enc, k1, meta),
+            "embed": lambda: ctx.embed(enc, meta, msg, cap, k2),
+            "extract": lambda: ctx.extract(enc, meta, got, cap, k2),
+            "recover": lambda: ctx.recover(enc, meta, rec, k1),
+        }
+        times = {}
+        # embedding rewrites only the MSBs it owns from the unchanged labels,
+        # so repeating it in place gives the same marked image every time
+        for name in ["encrypt", "embed", "extract", "recover"]:
+            ops[name]()                                   # warm-up; leaves the stage's output
+            torch.cuda.synchronize()
+            reps = 3
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                ops[name]()
+            b.record()
+            torch.cuda.synchronize()
+            times[name] = a.elapsed_time(b) / reps
+        ops["extract"]()
+        ops["recover"]()
+        torch.cuda.synchronize()
+        nb = cap // 8
+        bits_ok = bool(torch.equal(got[:nb], msg[:nb]))
+        if cap % 8:
+            mk = (0xFF << (8 - cap % 8)) & 0xFF
+            bits_ok = bits_ok and int(got[nb]) & mk == int(msg[nb]) & mk
+        diff = (rec ^ img)
+        lsb_only = bool(int(diff.max()) <= 1)
+        mism = int(diff.sum(dtype=torch.int64))
+        psnr = 10 * np.log10(255.0 ** 2 / (mism / float(side * side))) if mism else float("inf")
+        px = side * side
+        rt = sum(times.values())
+        row = {"side": side, "b": int(m.b), "capacity_bits": cap, "der_bpp": round(cap / px, 4),
+               "ms": {k: round(v, 4) for k, v in times.items()}, "round_trip_ms": round(rt, 4),
+               "mpx_per_s": round(px / (rt * 1e-3) / 1e6, 1), "extract_ok": bits_ok, "lsb_only": lsb_only,
+               "psnr_db": round(psnr, 4)}
+        log(f"[large] {side}: {row['ms']} -> {row['mpx_per_s']} Mpx/s, extract_ok={bits_ok}, "
+            f"lsb_only={lsb_only}, PSNR {row['psnr_db']} dB")
+        out.append(row)
+        del img, enc, rec, msg, got
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -183,6 +261,15 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    tuned = None
+    if args.autotune > 0 and not args.max_grid:
+        tuned = {}
+        for k in order:
+            grids = plans[k].autotune(reps=args.autotune)
+            tuned[k] = dict(zip(plans[k].stages(), grids))
+        log(f"[bench] autotuned workgroups (0 = resident default): {tuned}")
+        step()
+        torch.cuda.synchronize()
     log(f"[bench] timing {args.steps} steps")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -293,6 +380,10 @@ def main():
                "sample": f"{n} images of the batch ({S}x{S}), full round trip, single thread, {el:.1f}s"}
         log(f"[bench] cpu oracle: {cpu['value']} Mpx/s over {n} images")
 
+    large = None
+    if args.large_sides:
+        large = large_bench(args)
+
     serving = None
     if args.serve_requests > 0:
         serving = serve_bench(args)
@@ -314,7 +405,8 @@ def main():
         "vs_baseline": None, "dtype": "u8", "data": "synthetic",
         "config": {"workload": f"batched EMR-RDHEI round trip, {B} x {S}x{S} uint8 synthetic images "
                                "(sinusoids + noise, sigma in 1/3/8/20, 2..32 sinusoids), payload at capacity",
-                   "images": B, "side": S, "mode": args.mode, "der_bpp": round(der, 4)},
+                   "images": B, "side": S, "mode": args.mode, "der_bpp": round(der, 4),
+                   "autotuned_workgroups": tuned},
         "roofline": roof,
         "step_hbm_frac": round(alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "cpu_baseline": cpu,
@@ -322,9 +414,10 @@ def main():
         "parity": parity,
         "stages": stages,
         "serving": serving,
+        "large": large,
     }
     print(json.dumps(out), flush=True)
-    if not parity["ok"]:
+    if not parity["ok"] or (large and not all(r["extract_ok"] and r["lsb_only"] for r in large)):
         sys.exit(3)
 
 

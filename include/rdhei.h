@@ -171,6 +171,21 @@ int         rdhei_plan_stage_count(rdhei_plan *plan);
 const char *rdhei_plan_stage_name(rdhei_plan *plan, int32_t k);
 int         rdhei_plan_run_stage(rdhei_plan *plan, int32_t k, void *stream);
 
+/* Launch-shape autotuner.  Times every stage of a batched plan at several
+ * workgroup counts (the launcher's default -- what fits on the device at
+ * once -- and 1, 2, 4, 8 and 16 workgroups per compute unit), `reps` runs
+ * each, and keeps the fastest per stage (a change must win by more than 2 %).
+ * Choices are cached in the context by op, stage and size class (log2 of the
+ * plan's pixels and images) and reused by later plans of the same class
+ * unless RDHEI_TUNE_FORCE is set.  Tuning reruns the stages on the plan's
+ * own buffers (every stage is idempotent) and leaves them as one run of the
+ * plan does; it synchronises `stream`.  PER_IMAGE plans are left as they are.
+ * rdhei_plan_set_grid clears the tuned counts. */
+#define RDHEI_TUNE_FORCE 1
+int rdhei_plan_autotune(rdhei_plan *plan, int32_t reps, int32_t flags, void *stream);
+/* Workgroup count stage k runs with (0: the launcher's default), or < 0 on error. */
+int rdhei_plan_stage_grid(rdhei_plan *plan, int32_t k);
+
 /* One EMR op over a batch of images, launched directly on `stream` (no plan,
  * no graph): for batches whose composition changes from call to call, such
  * as a serving loop.

@@ -3,6 +3,7 @@
 // LMR host stages.
 #include <algorithm>
 #include <functional>
+#include <map>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -301,6 +302,7 @@ struct rdhei_ctx {
     int device = 0;
     int per_pixel = 0;
     int hide_mode = 0;
+    std::map<std::string, int> tuned;   // autotuned workgroup counts by op/stage/size class
     int max_grid = 0;
     DevBuf ws, jobs, scratch, batch_tables;
     PinnedRing ring;
@@ -316,6 +318,7 @@ struct rdhei_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<Stage> stages;     // batched sequence (for per-stage runs)
+    std::vector<int> stage_grid;   // per-stage workgroup count (0: the launcher's default)
     Launch base;                   // device tables of the batched sequence
     // PER_IMAGE plans: each image laid out and launched on its own, exactly
     // as the single-image entry points would
@@ -585,7 +588,10 @@ int plan_issue(rdhei_plan *P, hipStream_t st) {
         L.jobs = P->base.jobs;
         for (int k = 0; k < UNIT_KINDS; ++k) L.ujob[k] = P->base.ujob[k];
         L.njobs = (int32_t)Ly.jobs.size();
-        for (const Stage &s : P->stages) s.fn(L);
+        for (size_t i = 0; i < P->stages.size(); ++i) {
+            L.max_grid = P->stage_grid[i] ? P->stage_grid[i] : P->max_grid;
+            P->stages[i].fn(L);
+        }
     }
     HIPCHK(hipGetLastError());
     return RDHEI_OK;
@@ -810,14 +816,17 @@ int rdhei_plan_create(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t
         return rc;
     }
     P->stages = stages_of(P->layout, P->layout.units, P->layout.per_pixel);
+    P->stage_grid.assign(P->stages.size(), 0);
     *out = P;
     return RDHEI_OK;
 }
 
 int rdhei_plan_set_grid(rdhei_plan *plan, int32_t max_workgroups) {
     if (!plan || max_workgroups < 0) return RDHEI_EINVAL;
-    if (plan->max_grid != max_workgroups) {
+    if (plan->max_grid != max_workgroups || std::any_of(plan->stage_grid.begin(), plan->stage_grid.end(),
+                                                          [](int g) { return g != 0; })) {
         plan->max_grid = max_workgroups;
+        std::fill(plan->stage_grid.begin(), plan->stage_grid.end(), 0);
         if (plan->exec) { (void)hipGraphExecDestroy(plan->exec); plan->exec = nullptr; }
         if (plan->graph) { (void)hipGraphDestroy(plan->graph); plan->graph = nullptr; }
     }
@@ -867,9 +876,77 @@ int rdhei_plan_run_stage(rdhei_plan *P, int32_t k, void *stream) {
     L.g_part = P->layout.g_part;
     L.ws = P->ws.p;
     L.stream = reinterpret_cast<hipStream_t>(stream);
-    L.max_grid = P->max_grid;
+    L.max_grid = P->stage_grid[(size_t)k] ? P->stage_grid[(size_t)k] : P->max_grid;
     P->stages[(size_t)k].fn(L);
     HIPCHK(hipGetLastError());
+    return RDHEI_OK;
+}
+
+int rdhei_plan_stage_grid(rdhei_plan *P, int32_t k) {
+    if (!P || k < 0 || k >= (int)P->stages.size()) return RDHEI_EINVAL;
+    return P->stage_grid[(size_t)k];
+}
+
+int rdhei_plan_autotune(rdhei_plan *P, int32_t reps, int32_t flags, void *stream) {
+    if (!P || reps < 1 || reps > 1000 || (flags & ~RDHEI_TUNE_FORCE)) return RDHEI_EINVAL;
+    if (P->flags == RDHEI_PLAN_PER_IMAGE) return RDHEI_OK;      // per-image launches keep their defaults
+    int rc = set_device(P->ctx->device);
+    if (rc) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    int cus = 0;
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->ctx->device));
+    // size class of the plan: log2 of its pixels and of its images
+    uint64_t px = 0;
+    for (const Job &J : P->layout.jobs) px += (uint64_t)J.M * (uint64_t)J.N;
+    int px_cls = 0, job_cls = 0;
+    while ((px >> px_cls) > 1) ++px_cls;
+    while (((uint64_t)P->layout.jobs.size() >> job_cls) > 1) ++job_cls;
+    // the stages read what the stages before them wrote: bring the plan's
+    // buffers to a consistent state first (every stage is idempotent)
+    std::fill(P->stage_grid.begin(), P->stage_grid.end(), 0);
+    rc = plan_issue(P, st);
+    if (rc) return rc;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const int cand[] = {0, cus, 2 * cus, 4 * cus, 8 * cus, 16 * cus};
+    for (size_t k = 0; k < P->stages.size() && !rc; ++k) {
+        const std::string key = std::to_string(P->layout.op) + "/" + P->stages[k].name + "/" + std::to_string(px_cls) +
+                                "/" + std::to_string(job_cls);
+        auto it = P->ctx->tuned.find(key);
+        if (it != P->ctx->tuned.end() && !(flags & RDHEI_TUNE_FORCE)) {
+            P->stage_grid[k] = it->second;
+            continue;
+        }
+        float best = 1e30f;
+        int best_g = 0;
+        for (int g : cand) {
+            P->stage_grid[k] = g;
+            rc = rdhei_plan_run_stage(P, (int32_t)k, stream);     // warm-up
+            if (rc) break;
+            if (hipEventRecord(e0, st) != hipSuccess) { rc = RDHEI_EDEVICE; break; }
+            for (int r = 0; r < reps && !rc; ++r) rc = rdhei_plan_run_stage(P, (int32_t)k, stream);
+            if (rc) break;
+            float ms = 0.f;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = RDHEI_EDEVICE; break; }
+            if (ms < best * 0.98f) {     // a new choice must win by more than noise
+                best = ms;
+                best_g = g;
+            }
+        }
+        P->stage_grid[k] = best_g;
+        if (!rc) P->ctx->tuned[key] = best_g;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    // leave the buffers as one run with the chosen shapes leaves them
+    if (P->exec) { (void)hipGraphExecDestroy(P->exec); P->exec = nullptr; }
+    if (P->graph) { (void)hipGraphDestroy(P->graph); P->graph = nullptr; }
+    rc = plan_issue(P, st);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(st));
     return RDHEI_OK;
 }
 

@@ -21,6 +21,7 @@ OK, EINVAL, ECAPACITY, ENOFIT, ENOMEM, EDEVICE, ECORRUPT = 0, -1, -2, -3, -4, -5
 EMR, LMR = 0, 1
 OP_ENCRYPT, OP_EMBED, OP_EXTRACT, OP_RECOVER = 0, 1, 2, 3
 PLAN_GRAPH, PLAN_EAGER, PLAN_PER_IMAGE = 0, 1, 2
+TUNE_FORCE = 1
 OPT_PER_PIXEL, OPT_MAX_GRID, OPT_RESERVE_WS, OPT_HIDE_MODE = 1, 2, 3, 4
 META_BYTES = 64
 
@@ -29,6 +30,7 @@ EXPORTS = [
     "rdhei_encrypt", "rdhei_embed", "rdhei_extract", "rdhei_recover",
     "rdhei_workspace_size", "rdhei_run_batch", "rdhei_plan_create", "rdhei_plan_run", "rdhei_plan_destroy", "rdhei_plan_set_grid",
     "rdhei_plan_stage_count", "rdhei_plan_stage_name", "rdhei_plan_run_stage",
+    "rdhei_plan_autotune", "rdhei_plan_stage_grid",
     "rdhei_lmr_compress", "rdhei_lmr_decompress",
     "rdhei_strerror", "rdhei_last_error", "rdhei_version",
 ]
@@ -105,6 +107,8 @@ def load_library(path: str = LIB_PATH):
     lib.rdhei_plan_stage_name.argtypes = [vp, i32]
     lib.rdhei_plan_stage_name.restype = ctypes.c_char_p
     lib.rdhei_plan_run_stage.argtypes = [vp, i32, vp]
+    lib.rdhei_plan_autotune.argtypes = [vp, i32, i32, vp]
+    lib.rdhei_plan_stage_grid.argtypes = [vp, i32]
     lib.rdhei_lmr_compress.argtypes = [vp, vp, i32, i32, vp, i64, ctypes.POINTER(i64)]
     lib.rdhei_lmr_decompress.argtypes = [vp, i64, i32, i32, vp, vp]
     lib.rdhei_strerror.argtypes = [ctypes.c_int]
@@ -287,6 +291,16 @@ class Plan:
 
     def run_stage(self, k: int, stream=None) -> None:
         _check(self.lib.rdhei_plan_run_stage(self.h, k, _stream(stream)), "rdhei_plan_run_stage")
+
+    def autotune(self, reps: int = 3, force: bool = False, stream=None) -> list:
+        """Pick each stage's workgroup count by timing (see rdhei_plan_autotune);
+        returns the chosen counts (0 = the launcher's default)."""
+        _check(self.lib.rdhei_plan_autotune(self.h, reps, TUNE_FORCE if force else 0, _stream(stream)),
+               "rdhei_plan_autotune")
+        return self.stage_grids()
+
+    def stage_grids(self) -> list:
+        return [int(self.lib.rdhei_plan_stage_grid(self.h, k)) for k in range(self.lib.rdhei_plan_stage_count(self.h))]
 
     def close(self):
         if getattr(self, "h", None):

@@ -107,9 +107,10 @@ def test_emr_partial_messages(R, ctx, frac):
 @pytest.mark.parametrize("shape", [(1024, 512), (1024, 1024), (640, 1088), (1000, 777), (2048, 1024), (1040, 1024)],
                          ids=lambda s: f"{s[0]}x{s[1]}")
 def test_emr_multi_segment_images(R, ctx, shape):
-    """Images spanning several raster segments: whole-image hiding up to 64
-    segments, decoupled look-back beyond (and for pixel counts that are not a
-    multiple of 16), with message words shared by two segments."""
+    """Images spanning several raster segments, hidden by decoupled look-back
+    across segments (single images always take this path), including pixel
+    counts that are not a multiple of 16 and message words shared by two
+    segments."""
     M, N = shape
     I = _image(M + N, M, N, sigma=2.0)
     for frac in (1.0, 0.6):
@@ -121,6 +122,15 @@ def test_emr_4096_full_image(R, ctx):
     to 2^12) compared with the oracle pixel for pixel."""
     I = inputs.make_band_image(12, 4096, 4096, 8, 3.0, "cpu").numpy()
     _roundtrip(R, ctx, I, 101, 202, frac=1.0)
+
+
+def test_emr_8192_full_image(R, ctx):
+    """An 8192 x 8192 image (the large-image workload's smaller size: 16,384
+    tiles, 4096 look-back segments, rotation levels up to 2^13) against the
+    oracle pixel for pixel, with a payload that ends inside a pixel."""
+    print("[large] 8192x8192 oracle parity", flush=True)
+    I = inputs.make_band_image(13, 8192, 8192, 8, 3.0, "cpu").numpy()
+    _roundtrip(R, ctx, I, 303, 404, frac=0.77)
 
 
 def test_fast_and_per_pixel_paths_agree(R):
@@ -399,3 +409,52 @@ def test_lmr_bad_case_reported(R, ctx):
         ctx.encrypt(d, torch.empty_like(d), 5, meta, method=R.LMR)
     assert ei.value.code == R.ENOFIT
     assert R.read_meta(meta).status == R.ENOFIT
+
+
+def test_autotune_keeps_results_and_caches(R):
+    """The launch-shape autotuner only changes workgroup counts: tuned plans
+    give the untuned plans' bytes, every choice is one of the candidates, and a
+    second plan of the same size class reuses the cached choices."""
+    print("[autotune]", flush=True)
+    ctx = R.Context(0)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    cand = {0, cus, 2 * cus, 4 * cus, 8 * cus, 16 * cus}
+    shapes = [(256, 256)] * 12 + [(128, 64)] * 4 + [(45, 77)]
+    n = len(shapes)
+    imgs = [_dev(_image(1300 + i, *s)) for i, s in enumerate(shapes)]
+    k1s, k2s = [17 + i for i in range(n)], [29 + i for i in range(n)]
+
+    def run(tune):
+        enc = [torch.empty_like(x) for x in imgs]
+        rec = [torch.empty_like(x) for x in imgs]
+        metas = R.new_meta(n)
+        mp = [metas[i] for i in range(n)]
+        p_enc = R.Plan(ctx, R.OP_ENCRYPT, R.make_jobs(imgs, enc, None, mp, k1s, None, shapes))
+        p_enc.run()
+        torch.cuda.synchronize()
+        caps = [m.capacity_bits for m in R.read_meta(metas)]
+        msgs = [_msg_dev(R, inputs.make_payload(k, c).numpy(), c) for k, c in zip(k2s, caps)]
+        got = [torch.zeros(R.msg_bytes(c), dtype=torch.uint8, device="cuda") for c in caps]
+        plans = [p_enc,
+                 R.Plan(ctx, R.OP_EMBED, R.make_jobs(None, enc, msgs, mp, k2s, caps, shapes)),
+                 R.Plan(ctx, R.OP_EXTRACT, R.make_jobs(enc, None, got, mp, k2s, caps, shapes)),
+                 R.Plan(ctx, R.OP_RECOVER, R.make_jobs(enc, rec, None, mp, k1s, None, shapes))]
+        grids = []
+        for p in plans:
+            p.run()
+            if tune:
+                grids.append(p.autotune(reps=1))
+        for p in plans:          # a full pass after tuning, graph re-captured
+            p.run()
+        torch.cuda.synchronize()
+        outs = [x.cpu().numpy() for x in enc + rec] + [g.cpu().numpy()[: (c + 7) // 8] for g, c in zip(got, caps)]
+        return outs, grids, plans
+
+    base, _, _ = run(False)
+    tuned, grids, plans = run(True)
+    for a, b in zip(base, tuned):
+        assert np.array_equal(a, b)
+    for g in grids:
+        assert set(g) <= cand
+    again = plans[0].autotune(reps=1)            # cached: same answer without forcing
+    assert again == grids[0]
