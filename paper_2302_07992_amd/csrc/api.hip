@@ -216,13 +216,16 @@ std::vector<Stage> stages_of(const Layout &Ly, const uint32_t *units_in, std::ve
     for (int k = 0; k < UNIT_KINDS; ++k) units[k] = units_in[k];
     const uint32_t ut = units[UNIT_TILE], ub = units[UNIT_BAND], us = units[UNIT_SEG];
     const int method = Ly.method;
+    std::vector<int> big;   // images finalised across many workgroups
+    for (size_t i = 0; i < hj.size(); ++i)
+        if (hj[i].fast && (uint32_t)(hj[i].tiles_x * hj[i].tiles_y) >= kBigTiles) big.push_back((int)i);
     if (op == RDHEI_OP_ENCRYPT) {
         if (ut) S.push_back({"tile_prep_stats", [=](const Launch &L) { launch_tile_prep(L, ut, true); }});
         if (!pp.empty())
             S.push_back({"per_pixel_levels_stats", [=](const Launch &L) {
                              for (int j : pp) { launch_generic_levels(L, j, hj[j]); launch_generic_stats(L, j, hj[j]); }
                          }});
-        S.push_back({"finalize_stats", [=](const Launch &L) { launch_finalize(L, true); }});
+        S.push_back({"finalize_stats", [=](const Launch &L) { launch_finalize(L, true, big, hj); }});
         if (ut) S.push_back({"encrypt_tiles", [=](const Launch &L) { launch_encrypt_tiles(L, ut, ENC_EMR); }});
         if (!pp.empty())
             S.push_back({"per_pixel_encrypt", [=](const Launch &L) {
@@ -234,7 +237,7 @@ std::vector<Stage> stages_of(const Layout &Ly, const uint32_t *units_in, std::ve
             S.push_back({"per_pixel_levels", [=](const Launch &L) {
                              for (int j : pp) launch_generic_levels(L, j, hj[j]);
                          }});
-        if (ut) S.push_back({"finalize_pyramid", [=](const Launch &L) { launch_finalize(L, false); }});
+        if (ut) S.push_back({"finalize_pyramid", [=](const Launch &L) { launch_finalize(L, false, big, hj); }});
         if (ub) S.push_back({"recover_bands", [=](const Launch &L) { launch_recover_bands(L, ub, method); }});
         if (!pp.empty())
             S.push_back({"per_pixel_recover", [=](const Launch &L) {
@@ -443,7 +446,11 @@ int lmr_encrypt(rdhei_ctx *ctx, const uint8_t *d_img, uint8_t *d_enc, int32_t M,
         launch_generic_levels(L, 0, J0);
         launch_generic_stats(L, 0, J0);
     }
-    launch_finalize(L, true);
+    {
+        std::vector<int> big;
+        if (J0.fast && (uint32_t)(J0.tiles_x * J0.tiles_y) >= kBigTiles) big.push_back(0);
+        launch_finalize(L, true, big, Ly.jobs);
+    }
     int64_t Z[7];
     const uint64_t zoff = J0.ws_stats + (uint64_t)(J0.fast ? J0.tiles_x * J0.tiles_y : 1) * kStatWords * 4;
     HIPCHK(hipMemcpyAsync(Z, ctx->ws.p + zoff, sizeof Z, hipMemcpyDeviceToHost, st));

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <vector>
 
 #include "../../include/rdhei.h"
 
@@ -75,7 +76,12 @@ struct Launch {
 };
 
 void launch_tile_prep(const Launch &L, uint32_t units, bool stats);
-void launch_finalize(const Launch &L, bool stats);
+// Images with at least kBigTiles tiles are finalised across many workgroups,
+// in blocks of kFinBlock x kFinBlock tiles.
+constexpr uint32_t kBigTiles = 4096;
+constexpr int kFinBlock = 16;
+// big: indices of such jobs; hj: the host copy of the job table
+void launch_finalize(const Launch &L, bool stats, const std::vector<int> &big, const std::vector<Job> &hj);
 void launch_encrypt_tiles(const Launch &L, uint32_t units, int mode);
 void launch_recover_bands(const Launch &L, uint32_t units, int method);
 uint64_t seg_pixels();

@@ -161,13 +161,79 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
 // the tile from the tile sums (a level-m block code is the sum of its four
 // children mod 4 because block sums nest).
 // ----------------------------------------------------------------------------
+// Optimal b (Sec. III-A: argmax of b*Z_b, smallest b on ties) and the public
+// meta record from an image's label histogram hl[k] = #{lambda = k + 2}; the
+// suffix sums Z_b also stay in the workspace for the host (LMR candidates).
+__device__ void finish_stats(const Job &J, const int64_t hl[7], uint8_t *ws) {
+    int64_t Z[9];                       // Z_b = #{lambda >= b}
+    Z[8] = hl[6];
+    for (int b = 7; b >= 2; --b) Z[b] = Z[b + 1] + hl[b - 2];
+    int64_t *zout = reinterpret_cast<int64_t *>(ws + J.ws_stats) +
+                    (uint64_t)(J.fast ? J.tiles_x * J.tiles_y : 1) * (kStatWords / 2);
+    for (int b = 2; b <= 8; ++b) zout[b - 2] = Z[b];
+    if (J.method == RDHEI_EMR) {
+        int best = 2;
+        for (int b = 3; b <= 7; ++b)
+            if ((int64_t)b * Z[b] > (int64_t)best * Z[best]) best = b;
+        rdhei_meta m;
+        m.height = J.M; m.width = J.N; m.method = RDHEI_EMR; m.b = best;
+        m.min_level = J.min_level; m.max_level = J.max_level;
+        m.redundant = Z[best]; m.capacity_bits = (int64_t)best * Z[best];
+        m.map_bits = 0; m.status = RDHEI_OK;
+        m.reserved[0] = m.reserved[1] = m.reserved[2] = 0;
+        *J.meta = m;
+    }
+}
+
+// Workgroup-wide sums of seven counters; valid in thread 0.
+__device__ __forceinline__ void wg_sum7(uint32_t c[7], uint32_t (*part)[8]) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int k = 0; k < 7; ++k)
+        for (int off = 32; off > 0; off >>= 1) c[k] += __shfl_xor(c[k], off, 64);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 7; ++k) part[wave][k] = c[k];
+    __syncthreads();
+    if (tid == 0)
+#pragma unroll
+        for (int k = 0; k < 7; ++k) c[k] = part[0][k] + part[1][k] + part[2][k] + part[3][k];
+}
+
+// Upper pyramid levels lo..max_level, level by level, by one workgroup.
+__device__ void upper_levels(const Job &J, uint8_t *pyr, int lo) {
+    const int tid = threadIdx.x;
+    for (int m = lo; m <= J.max_level; ++m) {
+        __syncthreads();
+        const uint32_t gy = (uint32_t)(J.M >> m), gx = (uint32_t)(J.N >> m);
+        const uint32_t cx = (uint32_t)(J.N >> (m - 1));
+        const uint8_t *child = pyr + pyr_off(J.M, J.N, m - 1);
+        uint8_t *cur = pyr + pyr_off(J.M, J.N, m);
+        for (uint32_t q = tid; q < gy * gx; q += kThreads) {
+            const uint32_t Y = q / gx, X = q % gx;
+            const uint8_t *a = child + (2 * Y) * cx + 2 * X;
+            cur[q] = (uint8_t)((a[0] + a[1] + a[cx] + a[cx + 1]) & 3);
+        }
+    }
+    __syncthreads();
+}
+
+// ----------------------------------------------------------------------------
+// One workgroup per image: sums the label histogram, picks the optimal b,
+// writes the public meta record, and builds the rotation codes of the levels
+// above the tile from the tile sums (a level-m block code is the sum of its
+// four children mod 4 because block sums nest), then the tile map.  Images of
+// kBigTiles tiles or more are finalised across many workgroups instead
+// (k_fin_blocks, k_fin_top, k_fin_tmap).
+// ----------------------------------------------------------------------------
 template <bool STATS>
 __global__ __launch_bounds__(kThreads) void k_finalize(const Job *__restrict__ jobs, int njobs,
                                                         uint8_t *__restrict__ ws) {
     __shared__ uint32_t part[kThreads / 64][8];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x;
     for (int j = blockIdx.x; j < njobs; j += gridDim.x) {
         const Job &J = jobs[j];
+        if (J.fast && (uint32_t)(J.tiles_x * J.tiles_y) >= kBigTiles) continue;   // uniform per workgroup
         if (STATS) {
             const uint32_t nrec = J.fast ? (uint32_t)(J.tiles_x * J.tiles_y) : 1u;
             const uint32_t *st = reinterpret_cast<const uint32_t *>(ws + J.ws_stats);
@@ -175,53 +241,16 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const Job *__restrict__ j
             for (uint32_t q = tid; q < nrec; q += kThreads)
 #pragma unroll
                 for (int k = 0; k < 7; ++k) c[k] += st[(uint64_t)q * kStatWords + k];
-#pragma unroll
-            for (int k = 0; k < 7; ++k)
-                for (int off = 32; off > 0; off >>= 1) c[k] += __shfl_xor(c[k], off, 64);
-            if (lane == 0)
-#pragma unroll
-                for (int k = 0; k < 7; ++k) part[wave][k] = c[k];
-            __syncthreads();
+            wg_sum7(c, part);
             if (tid == 0) {
                 int64_t hl[7];
-                for (int k = 0; k < 7; ++k) hl[k] = (int64_t)part[0][k] + part[1][k] + part[2][k] + part[3][k];
-                int64_t Z[9];                       // Z_b = #{lambda >= b}
-                Z[8] = hl[6];
-                for (int b = 7; b >= 2; --b) Z[b] = Z[b + 1] + hl[b - 2];
-                // keep the counts for the host (LMR candidate order)
-                int64_t *zout = reinterpret_cast<int64_t *>(ws + J.ws_stats) +
-                                (uint64_t)(J.fast ? J.tiles_x * J.tiles_y : 1) * (kStatWords / 2);
-                for (int b = 2; b <= 8; ++b) zout[b - 2] = Z[b];
-                if (J.method == RDHEI_EMR) {
-                    int best = 2;
-                    for (int b = 3; b <= 7; ++b)
-                        if ((int64_t)b * Z[b] > (int64_t)best * Z[best]) best = b;
-                    rdhei_meta m;
-                    m.height = J.M; m.width = J.N; m.method = RDHEI_EMR; m.b = best;
-                    m.min_level = J.min_level; m.max_level = J.max_level;
-                    m.redundant = Z[best]; m.capacity_bits = (int64_t)best * Z[best];
-                    m.map_bits = 0; m.status = RDHEI_OK;
-                    m.reserved[0] = m.reserved[1] = m.reserved[2] = 0;
-                    *J.meta = m;
-                }
+                for (int k = 0; k < 7; ++k) hl[k] = c[k];
+                finish_stats(J, hl, ws);
             }
         }
         if (J.fast) {
             uint8_t *pyr = ws + J.ws_pyr;
-            // level kTileLog holds the tile sums
-            for (int m = kTileLog + 1; m <= J.max_level; ++m) {
-                __syncthreads();
-                const uint32_t gy = (uint32_t)(J.M >> m), gx = (uint32_t)(J.N >> m);
-                const uint32_t cx = (uint32_t)(J.N >> (m - 1));
-                const uint8_t *child = pyr + pyr_off(J.M, J.N, m - 1);
-                uint8_t *cur = pyr + pyr_off(J.M, J.N, m);
-                for (uint32_t q = tid; q < gy * gx; q += kThreads) {
-                    const uint32_t Y = q / gx, X = q % gx;
-                    const uint8_t *a = child + (2 * Y) * cx + 2 * X;
-                    cur[q] = (uint8_t)((a[0] + a[1] + a[cx] + a[cx + 1]) & 3);
-                }
-            }
-            __syncthreads();
+            upper_levels(J, pyr, kTileLog + 1);     // level kTileLog holds the tile sums
             // where every tile goes (levels above the tile move tiles rigidly)
             uint32_t *tmap = reinterpret_cast<uint32_t *>(ws + J.ws_tmap);
             const uint32_t ntiles = (uint32_t)(J.tiles_x * J.tiles_y);
@@ -234,6 +263,95 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const Job *__restrict__ j
         }
         __syncthreads();
     }
+}
+
+// Large image, step 1: one workgroup per 16 x 16 block of tiles sums the
+// block's tile statistics (partial records, kept in the tile-map area until
+// step 2 has read them) and builds pyramid levels kTileLog+1..kTileLog+4
+// inside the block.
+template <bool STATS>
+__global__ __launch_bounds__(kThreads) void k_fin_blocks(const Job *__restrict__ jobs, int j,
+                                                          uint8_t *__restrict__ ws) {
+    __shared__ uint8_t lv[2][kFinBlock * kFinBlock];
+    __shared__ uint32_t part[kThreads / 64][8];
+    const Job &J = jobs[j];
+    const int tid = threadIdx.x;
+    const uint32_t nbx = (uint32_t)(J.tiles_x + kFinBlock - 1) / kFinBlock;
+    const uint32_t BY = blockIdx.x / nbx, BX = blockIdx.x % nbx;
+    const uint32_t ty = BY * kFinBlock + (uint32_t)(tid / kFinBlock), tx = BX * kFinBlock + (uint32_t)(tid % kFinBlock);
+    const bool in = ty < (uint32_t)J.tiles_y && tx < (uint32_t)J.tiles_x;
+    const uint32_t t = ty * (uint32_t)J.tiles_x + tx;
+    uint8_t *pyr = ws + J.ws_pyr;
+    if (STATS) {
+        uint32_t c[7] = {0, 0, 0, 0, 0, 0, 0};
+        if (in) {
+            const uint32_t *st = reinterpret_cast<const uint32_t *>(ws + J.ws_stats) + (uint64_t)t * kStatWords;
+#pragma unroll
+            for (int k = 0; k < 7; ++k) c[k] = st[k];
+        }
+        wg_sum7(c, part);
+        if (tid == 0) {
+            uint32_t *pp = reinterpret_cast<uint32_t *>(ws + J.ws_tmap) + (uint64_t)blockIdx.x * 8;
+#pragma unroll
+            for (int k = 0; k < 7; ++k) pp[k] = c[k];
+        }
+    }
+    lv[0][tid] = in ? pyr[t] : (uint8_t)0;
+    int cur = 0;
+    uint32_t side = kFinBlock;
+    for (int m = kTileLog + 1; m <= kTileLog + 4; ++m) {
+        __syncthreads();
+        if (m > J.max_level) break;                  // uniform
+        side >>= 1;
+        const uint32_t gy = (uint32_t)(J.M >> m), gx = (uint32_t)(J.N >> m);
+        if ((uint32_t)tid < side * side) {
+            const uint32_t y = (uint32_t)tid / side, x = (uint32_t)tid % side;
+            const uint8_t *a = lv[cur] + (2 * y) * (2 * side) + 2 * x;
+            const uint8_t v = (uint8_t)((a[0] + a[1] + a[2 * side] + a[2 * side + 1]) & 3);
+            lv[cur ^ 1][y * side + x] = v;
+            const uint32_t Y = BY * side + y, X = BX * side + x;
+            if (Y < gy && X < gx) pyr[pyr_off(J.M, J.N, m) + (uint64_t)Y * gx + X] = v;
+        }
+        cur ^= 1;
+    }
+}
+
+// Large image, step 2 (one workgroup): the image's statistics from the
+// partial records, the optimal b and meta, and the pyramid levels above
+// kTileLog+4.
+template <bool STATS>
+__global__ __launch_bounds__(kThreads) void k_fin_top(const Job *__restrict__ jobs, int j, uint8_t *__restrict__ ws) {
+    __shared__ uint32_t part[kThreads / 64][8];
+    const Job &J = jobs[j];
+    const int tid = threadIdx.x;
+    if (STATS) {
+        const uint32_t nparts = (uint32_t)((J.tiles_y + kFinBlock - 1) / kFinBlock) *
+                                (uint32_t)((J.tiles_x + kFinBlock - 1) / kFinBlock);
+        const uint32_t *pp = reinterpret_cast<const uint32_t *>(ws + J.ws_tmap);
+        uint32_t c[7] = {0, 0, 0, 0, 0, 0, 0};
+        for (uint32_t q = tid; q < nparts; q += kThreads)
+#pragma unroll
+            for (int k = 0; k < 7; ++k) c[k] += pp[(uint64_t)q * 8 + k];
+        wg_sum7(c, part);
+        if (tid == 0) {
+            int64_t hl[7];
+            for (int k = 0; k < 7; ++k) hl[k] = c[k];
+            finish_stats(J, hl, ws);
+        }
+    }
+    upper_levels(J, ws + J.ws_pyr, kTileLog + 5);
+}
+
+// Large image, step 3: the tile map, one thread per tile.
+__global__ __launch_bounds__(kThreads) void k_fin_tmap(const Job *__restrict__ jobs, int j, uint8_t *__restrict__ ws) {
+    const Job &J = jobs[j];
+    const uint32_t q = blockIdx.x * kThreads + threadIdx.x;
+    const uint32_t ntiles = (uint32_t)(J.tiles_x * J.tiles_y);
+    if (q >= ntiles) return;
+    int dy, dx;
+    uint32_t turns;
+    upper_walk(J, ws + J.ws_pyr, (int)(q / (uint32_t)J.tiles_x), (int)(q % (uint32_t)J.tiles_x), dy, dx, turns);
+    reinterpret_cast<uint32_t *>(ws + J.ws_tmap)[q] = tmap_pack(dy, dx, turns);
 }
 
 
@@ -686,13 +804,28 @@ void launch_tile_prep(const Launch &L, uint32_t units, bool stats) {
                            L.stream, L.jobs, L.njobs, L.ws, units, UJ);
 }
 
-void launch_finalize(const Launch &L, bool stats) {
+void launch_finalize(const Launch &L, bool stats, const std::vector<int> &big, const std::vector<Job> &hj) {
     if (!L.njobs) return;
-    const unsigned g = grid_for(L, (uint32_t)L.njobs);
-    if (stats)
-        hipLaunchKernelGGL(k_finalize<true>, dim3(g), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, L.ws);
-    else
-        hipLaunchKernelGGL(k_finalize<false>, dim3(g), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, L.ws);
+    if (big.size() < (size_t)L.njobs) {
+        const unsigned g = grid_for(L, (uint32_t)L.njobs);
+        if (stats)
+            hipLaunchKernelGGL(k_finalize<true>, dim3(g), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, L.ws);
+        else
+            hipLaunchKernelGGL(k_finalize<false>, dim3(g), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, L.ws);
+    }
+    for (int j : big) {
+        const Job &J = hj[(size_t)j];
+        const unsigned nb = (unsigned)(((J.tiles_y + kFinBlock - 1) / kFinBlock) * ((J.tiles_x + kFinBlock - 1) / kFinBlock));
+        const unsigned nt = (unsigned)(((uint32_t)(J.tiles_x * J.tiles_y) + kThreads - 1) / kThreads);
+        if (stats) {
+            hipLaunchKernelGGL(k_fin_blocks<true>, dim3(nb), dim3(kThreads), 0, L.stream, L.jobs, j, L.ws);
+            hipLaunchKernelGGL(k_fin_top<true>, dim3(1), dim3(kThreads), 0, L.stream, L.jobs, j, L.ws);
+        } else {
+            hipLaunchKernelGGL(k_fin_blocks<false>, dim3(nb), dim3(kThreads), 0, L.stream, L.jobs, j, L.ws);
+            hipLaunchKernelGGL(k_fin_top<false>, dim3(1), dim3(kThreads), 0, L.stream, L.jobs, j, L.ws);
+        }
+        hipLaunchKernelGGL(k_fin_tmap, dim3(nt), dim3(kThreads), 0, L.stream, L.jobs, j, L.ws);
+    }
 }
 
 void launch_encrypt_tiles(const Launch &L, uint32_t units, int mode) {

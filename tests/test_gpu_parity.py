@@ -124,6 +124,14 @@ def test_emr_4096_full_image(R, ctx):
     _roundtrip(R, ctx, I, 101, 202, frac=1.0)
 
 
+def test_emr_large_ragged_tile_grid(R, ctx):
+    """4480 x 3840: 70 x 60 tiles, above the size where finalisation is split
+    over 16 x 16-tile blocks, with partial blocks at both edges."""
+    print("[large] 4480x3840 oracle parity", flush=True)
+    I = inputs.make_band_image(14, 4480, 3840, 8, 3.0, "cpu").numpy()
+    _roundtrip(R, ctx, I, 505, 606, frac=0.5)
+
+
 def test_emr_8192_full_image(R, ctx):
     """An 8192 x 8192 image (the large-image workload's smaller size: 16,384
     tiles, 4096 look-back segments, rotation levels up to 2^13) against the
@@ -363,7 +371,8 @@ def test_per_image_plan_matches_batched(R, ctx):
         assert np.array_equal(res[0][3], other[3])
 
 
-@pytest.mark.parametrize("shape", [(256, 256), (128, 320), (100, 90), (64, 64)], ids=lambda s: f"{s[0]}x{s[1]}")
+@pytest.mark.parametrize("shape", [(256, 256), (128, 320), (100, 90), (64, 64), (4096, 4096)],
+                         ids=lambda s: f"{s[0]}x{s[1]}")
 def test_lmr_matches_oracle(R, ctx, shape):
     """LMR (Sec. III-B) on the GPU with the library's host coder, against the
     oracle's full LMR encoding (own coder, candidate fallback): encrypted image,
