@@ -212,6 +212,25 @@ int rdhei_run_batch(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t n
                                     segments.  Results are identical.            */
 int rdhei_ctx_set_option(rdhei_ctx *ctx, int32_t option, int64_t value);
 
+/* ---- LMR over a batch of images (Sec. III-B) ---------------------------------
+ * One call per role, every device stage batched over the images and the map
+ * coder run on `threads` host threads (0: all hardware threads).
+ *   RDHEI_OP_ENCRYPT  jobs {in = I, out = I_e, meta, key = K1}: statistics, then
+ *                     for each image the candidate b in order of (b-1)*Z_b whose
+ *                     compressed rotated maps fit the MSB plane, then the
+ *                     encryption carrying that stream in bit 7.  An image that
+ *                     fits no candidate gets meta.status RDHEI_ENOFIT and its
+ *                     output is not written; the call still returns RDHEI_OK.
+ *   RDHEI_OP_EMBED / RDHEI_OP_EXTRACT / RDHEI_OP_RECOVER: jobs as for the EMR
+ *                     batch ops; the maps are read back from each marked image's
+ *                     MSB plane and decoded on the host first.  Images whose
+ *                     meta is not usable are skipped; a stream that does not
+ *                     decode sets meta.status RDHEI_ECORRUPT.
+ * times (optional, 3 doubles): seconds spent in device stages and copies, in
+ * the host coder, and in the whole call.  Synchronises `stream`. */
+int rdhei_lmr_batch(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t njobs, int32_t threads,
+                    double *times, void *stream);
+
 /* ---- LMR host stage: bi-level map coder (Sec. III-B, map compression) ---- */
 /* The paper compresses the rotated first-MSB map and the rotated location map
  * with JBIG-KIT.  This library uses its own context-modelled binary

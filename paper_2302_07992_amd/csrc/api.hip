@@ -2,8 +2,11 @@
 // launch sequence of every stage, plans (hipGraph capture/replay), and the
 // LMR host stages.
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <functional>
 #include <map>
+#include <thread>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -63,6 +66,31 @@ struct DevBuf {
     }
     void release() {
         if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+// Growable pinned host buffer (staging for bulk copies).
+struct HostBuf {
+    uint8_t *p = nullptr;
+    size_t n = 0;
+    int need(size_t bytes) {
+        if (bytes <= n) return RDHEI_OK;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        n = 0;
+        hipError_t e = hipHostMalloc((void **)&p, std::max<size_t>(bytes, 1 << 16), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            set_err("hipHostMalloc", e);
+            p = nullptr;
+            return RDHEI_ENOMEM;
+        }
+        n = std::max<size_t>(bytes, 1 << 16);
+        return RDHEI_OK;
+    }
+    void release() {
+        if (p) (void)hipHostFree(p);
         p = nullptr;
         n = 0;
     }
@@ -307,7 +335,8 @@ struct rdhei_ctx {
     int hide_mode = 0;
     std::map<std::string, int> tuned;   // autotuned workgroup counts by op/stage/size class
     int max_grid = 0;
-    DevBuf ws, jobs, scratch, batch_tables;
+    DevBuf ws, jobs, scratch, batch_tables, lmr_dev;
+    HostBuf lmr_host;
     PinnedRing ring;
     std::vector<uint8_t> h_a, h_b, h_c;
 };
@@ -571,6 +600,309 @@ int lmr_stage(rdhei_ctx *ctx, int op, const uint8_t *d_marked, uint8_t *d_out, i
     return RDHEI_OK;
 }
 
+// ---- LMR batches (Sec. III-B) ------------------------------------------------------
+// Device stages run batched; the map coder runs on host threads.
+
+using Clock = std::chrono::steady_clock;
+inline double secs(Clock::time_point a, Clock::time_point b) { return std::chrono::duration<double>(b - a).count(); }
+
+template <typename F>
+void parallel_for(int n, int threads, F f) {
+    if (n <= 0) return;
+    if (threads < 1) threads = (int)std::max(1u, std::thread::hardware_concurrency());
+    threads = std::min(threads, n);
+    std::atomic<int> next(0);
+    auto work = [&]() {
+        for (int i; (i = next.fetch_add(1)) < n;) f(i);
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < threads; ++t) pool.emplace_back(work);
+    work();
+    for (std::thread &t : pool) t.join();
+}
+
+// The jobs idx of a layout as a layout of their own: each job keeps its
+// workspace offsets; unit bases and unit tables are rebuilt.
+Layout subset_layout(const Layout &full, const std::vector<int> &idx) {
+    Layout S;
+    S.op = full.op;
+    S.method = full.method;
+    S.ws_bytes = full.ws_bytes;
+    S.g_status = full.g_status;
+    S.g_ticket = full.g_ticket;
+    S.g_part = full.g_part;
+    const bool rot = full.op == RDHEI_OP_ENCRYPT || full.op == RDHEI_OP_RECOVER;
+    for (size_t q = 0; q < idx.size(); ++q) {
+        Job J = full.jobs[(size_t)idx[q]];
+        for (int k = 0; k < UNIT_KINDS; ++k) {
+            J.ubase[k] = S.units[k];
+            S.units[k] += J.ucount[k];
+        }
+        if (rot && !J.fast) S.per_pixel.push_back((int)q);
+        S.jobs.push_back(J);
+    }
+    if (idx.size() > 1)
+        for (size_t q = 0; q < S.jobs.size(); ++q)
+            for (int k = 0; k < UNIT_KINDS; ++k) S.ujob[k].insert(S.ujob[k].end(), S.jobs[q].ucount[k], (uint32_t)q);
+    return S;
+}
+
+std::vector<int> big_jobs(const Layout &Ly) {
+    std::vector<int> big;
+    for (size_t i = 0; i < Ly.jobs.size(); ++i)
+        if (Ly.jobs[i].fast && (uint32_t)(Ly.jobs[i].tiles_x * Ly.jobs[i].tiles_y) >= kBigTiles) big.push_back((int)i);
+    return big;
+}
+
+struct LmrTimes {
+    double device = 0, coder = 0;
+};
+
+int lmr_encrypt_batch(rdhei_ctx *ctx, const rdhei_job *jobs, int n, int threads, LmrTimes &T, hipStream_t st) {
+    Layout Ly;
+    int rc = make_layout(RDHEI_OP_ENCRYPT, jobs, n, opts_of(ctx), Ly);
+    if (rc) return rc;
+    if (Ly.method != RDHEI_LMR) return RDHEI_EINVAL;
+    // per image: l plane, eta plane, coder output (MN/8 bytes at most)
+    std::vector<uint64_t> plane((size_t)n), poff((size_t)n);
+    uint64_t tot = 0;
+    for (int i = 0; i < n; ++i) {
+        const uint64_t MN = (uint64_t)Ly.jobs[(size_t)i].M * (uint64_t)Ly.jobs[(size_t)i].N;
+        plane[(size_t)i] = align_up((MN + 7) / 8 + 16, 256);
+        poff[(size_t)i] = tot;
+        tot += 3 * plane[(size_t)i];
+    }
+    const uint64_t zoff = tot, moff = zoff + align_up((uint64_t)n * 56, 256);
+    const uint64_t soff = moff + align_up((uint64_t)n * sizeof(rdhei_meta), 256);   // packed streams
+    const uint64_t all = soff + tot / 3 + 256;
+    if ((rc = ctx->lmr_dev.need(all)) || (rc = ctx->lmr_host.need(all))) return rc;
+    uint8_t *D = ctx->lmr_dev.p, *H = ctx->lmr_host.p;
+    auto t0 = Clock::now();
+    Launch L;
+    if ((rc = stage(ctx, Ly, ctx->jobs, ctx->ws, st, L))) return rc;
+    launch_tile_prep(L, Ly.units[UNIT_TILE], true);
+    for (int j : Ly.per_pixel) {
+        launch_generic_levels(L, j, Ly.jobs[(size_t)j]);
+        launch_generic_stats(L, j, Ly.jobs[(size_t)j]);
+    }
+    launch_finalize(L, true, big_jobs(Ly), Ly.jobs);
+    launch_gather_z(L, reinterpret_cast<int64_t *>(D + zoff));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(H + zoff, D + zoff, (size_t)n * 56, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    T.device += secs(t0, Clock::now());
+    const int64_t *Z = reinterpret_cast<const int64_t *>(H + zoff);
+    // candidates in order of LMR capacity (b-1)*Z_b, smaller b first on ties
+    std::vector<std::vector<int>> cand((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        std::vector<int> &c = cand[(size_t)i];
+        for (int b = 2; b <= 8; ++b) c.push_back(b);
+        const int64_t *z = Z + 7 * i;
+        std::stable_sort(c.begin(), c.end(),
+                         [&](int a, int b) { return (int64_t)(a - 1) * z[a - 2] > (int64_t)(b - 1) * z[b - 2]; });
+    }
+    std::vector<int> cur((size_t)n, 0), chosen((size_t)n, 0), res;
+    std::vector<int64_t> sbits((size_t)n, 0);
+    std::vector<int> pending;
+    for (int i = 0; i < n; ++i) pending.push_back(i);
+    while (!pending.empty()) {
+        auto t1 = Clock::now();
+        Layout S = subset_layout(Ly, pending);
+        for (size_t q = 0; q < pending.size(); ++q) {
+            const int i = pending[q];
+            Job &J = S.jobs[q];
+            J.fixed_b = cand[(size_t)i][(size_t)cur[(size_t)i]];
+            J.out = D + poff[(size_t)i];
+            J.msg = D + poff[(size_t)i] + plane[(size_t)i];
+        }
+        Launch LS;
+        if ((rc = stage(ctx, S, ctx->jobs, ctx->ws, st, LS))) return rc;
+        if (S.units[UNIT_TILE]) launch_encrypt_tiles(LS, S.units[UNIT_TILE], ENC_LMR_MAPS);
+        for (int q : S.per_pixel) launch_generic_encrypt(LS, q, S.jobs[(size_t)q], ENC_LMR_MAPS);
+        HIPCHK(hipGetLastError());
+        if (pending.size() == (size_t)n) {
+            HIPCHK(hipMemcpyAsync(H, D, (size_t)tot, hipMemcpyDeviceToHost, st));
+        } else {
+            for (int i : pending)
+                HIPCHK(hipMemcpyAsync(H + poff[(size_t)i], D + poff[(size_t)i], (size_t)(2 * plane[(size_t)i]),
+                                      hipMemcpyDeviceToHost, st));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        auto t2 = Clock::now();
+        T.device += secs(t1, t2);
+        res.assign(pending.size(), 0);
+        parallel_for((int)pending.size(), threads, [&](int q) {
+            const int i = pending[(size_t)q];
+            const Job &J = Ly.jobs[(size_t)i];
+            const uint64_t MN = (uint64_t)J.M * (uint64_t)J.N;
+            uint8_t *hl = H + poff[(size_t)i], *he = hl + plane[(size_t)i], *hs = he + plane[(size_t)i];
+            res[(size_t)q] = lmr_compress_impl(he, hl, J.M, J.N, hs, (int64_t)(MN / 8), &sbits[(size_t)i]);
+        });
+        T.coder += secs(t2, Clock::now());
+        std::vector<int> next;
+        for (size_t q = 0; q < pending.size(); ++q) {
+            const int i = pending[q];
+            if (res[q] == RDHEI_OK) chosen[(size_t)i] = cand[(size_t)i][(size_t)cur[(size_t)i]];
+            else if (res[q] == RDHEI_ENOFIT) {
+                if (++cur[(size_t)i] < 7) next.push_back(i);
+            } else return res[q];
+        }
+        pending.swap(next);
+    }
+    auto t3 = Clock::now();
+    // meta records, packed streams, then the encryption of every image that fits
+    rdhei_meta *hm = reinterpret_cast<rdhei_meta *>(H + moff);
+    std::vector<uint64_t> so((size_t)n, 0);
+    std::vector<int> ok;
+    uint64_t sp = 0;
+    for (int i = 0; i < n; ++i) {
+        const Job &J = Ly.jobs[(size_t)i];
+        rdhei_meta m{};
+        m.height = J.M; m.width = J.N; m.method = RDHEI_LMR; m.min_level = J.min_level; m.max_level = J.max_level;
+        const int b = chosen[(size_t)i];
+        if (b) {
+            const int64_t *z = Z + 7 * i;
+            m.b = b;
+            m.redundant = z[b - 2];
+            m.capacity_bits = (int64_t)(b - 1) * z[b - 2];
+            m.map_bits = sbits[(size_t)i];
+            m.status = RDHEI_OK;
+            so[(size_t)i] = sp;
+            memcpy(H + soff + sp, H + poff[(size_t)i] + 2 * plane[(size_t)i], (size_t)((sbits[(size_t)i] + 7) / 8));
+            sp = align_up(sp + (uint64_t)((sbits[(size_t)i] + 7) / 8), 16);
+            ok.push_back(i);
+        } else {
+            m.status = RDHEI_ENOFIT;
+        }
+        hm[i] = m;
+    }
+    HIPCHK(hipMemcpyAsync(D + moff, H + moff, (size_t)n * sizeof(rdhei_meta), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(D + soff, H + soff, (size_t)std::max<uint64_t>(sp, 16), hipMemcpyHostToDevice, st));
+    if ((rc = stage(ctx, Ly, ctx->jobs, ctx->ws, st, L))) return rc;
+    launch_scatter_meta(L, reinterpret_cast<const rdhei_meta *>(D + moff));
+    if (!ok.empty()) {
+        Layout S = subset_layout(Ly, ok);
+        for (size_t q = 0; q < ok.size(); ++q) {
+            const int i = ok[q];
+            Job &J = S.jobs[q];
+            J.fixed_b = chosen[(size_t)i];
+            J.stream = D + soff + so[(size_t)i];
+            J.stream_bits = sbits[(size_t)i];
+        }
+        Launch LS;
+        if ((rc = stage(ctx, S, ctx->jobs, ctx->ws, st, LS))) return rc;
+        if (S.units[UNIT_TILE]) launch_encrypt_tiles(LS, S.units[UNIT_TILE], ENC_LMR);
+        for (int q : S.per_pixel) launch_generic_encrypt(LS, q, S.jobs[(size_t)q], ENC_LMR);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    T.device += secs(t3, Clock::now());
+    return RDHEI_OK;
+}
+
+// Decode the maps of every usable LMR image of a layout (status OK, shape as
+// recorded, stream length in range) and point its job at device bit planes;
+// returns the usable jobs in ok.  A stream that fails to decode marks its
+// image RDHEI_ECORRUPT.
+int lmr_decode_batch(rdhei_ctx *ctx, Layout &Ly, int threads, LmrTimes &T, hipStream_t st, std::vector<int> &ok) {
+    const int n = (int)Ly.jobs.size();
+    std::vector<uint64_t> plane((size_t)n), poff((size_t)n), soffs((size_t)n, 0);
+    uint64_t tot = 0, smax = 0;
+    for (int i = 0; i < n; ++i) {
+        const uint64_t MN = (uint64_t)Ly.jobs[(size_t)i].M * (uint64_t)Ly.jobs[(size_t)i].N;
+        plane[(size_t)i] = align_up((MN + 7) / 8 + 16, 256);
+        poff[(size_t)i] = tot;
+        tot += 2 * plane[(size_t)i];
+        soffs[(size_t)i] = smax;
+        smax += plane[(size_t)i];
+    }
+    const uint64_t moff = tot, ooff = moff + align_up((uint64_t)n * sizeof(rdhei_meta), 256);
+    const uint64_t soff = ooff + align_up((uint64_t)n * 8, 256), all = soff + smax;
+    int rc;
+    if ((rc = ctx->lmr_dev.need(all)) || (rc = ctx->lmr_host.need(all))) return rc;
+    uint8_t *D = ctx->lmr_dev.p, *H = ctx->lmr_host.p;
+    auto t0 = Clock::now();
+    Launch L;
+    if ((rc = stage(ctx, Ly, ctx->jobs, ctx->ws, st, L))) return rc;
+    launch_gather_meta(L, reinterpret_cast<rdhei_meta *>(D + moff));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(H + moff, D + moff, (size_t)n * sizeof(rdhei_meta), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    rdhei_meta *hm = reinterpret_cast<rdhei_meta *>(H + moff);
+    uint64_t *ho = reinterpret_cast<uint64_t *>(H + ooff);
+    uint64_t maxb = 0;
+    ok.clear();
+    for (int i = 0; i < n; ++i) {
+        const Job &J = Ly.jobs[(size_t)i];
+        const rdhei_meta &m = hm[i];
+        const int64_t MN = (int64_t)J.M * J.N;
+        ho[i] = soffs[(size_t)i];
+        if (m.status == RDHEI_OK && m.method == RDHEI_LMR && m.height == J.M && m.width == J.N && m.map_bits >= 64 &&
+            m.map_bits <= MN) {
+            ok.push_back(i);
+            maxb = std::max<uint64_t>(maxb, (uint64_t)(m.map_bits + 7) / 8);
+        }
+    }
+    HIPCHK(hipMemcpyAsync(D + ooff, H + ooff, (size_t)n * 8, hipMemcpyHostToDevice, st));
+    launch_msb_plane(L, reinterpret_cast<const uint64_t *>(D + ooff), D + soff, maxb);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(H + soff, D + soff, (size_t)smax, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    auto t1 = Clock::now();
+    T.device += secs(t0, t1);
+    std::vector<int> res(ok.size(), 0);
+    parallel_for((int)ok.size(), threads, [&](int q) {
+        const int i = ok[(size_t)q];
+        const Job &J = Ly.jobs[(size_t)i];
+        uint8_t *hl = H + poff[(size_t)i], *he = hl + plane[(size_t)i];
+        res[(size_t)q] = lmr_decompress_impl(H + soff + soffs[(size_t)i], (hm[i].map_bits + 7) / 8, J.M, J.N, he, hl);
+    });
+    auto t2 = Clock::now();
+    T.coder += secs(t1, t2);
+    std::vector<int> good;
+    bool corrupt = false;
+    for (size_t q = 0; q < ok.size(); ++q) {
+        const int i = ok[q];
+        if (res[q] == RDHEI_OK) {
+            good.push_back(i);
+            Ly.jobs[(size_t)i].lbits = D + poff[(size_t)i];
+            Ly.jobs[(size_t)i].etabits = D + poff[(size_t)i] + plane[(size_t)i];
+        } else {
+            hm[i].status = RDHEI_ECORRUPT;
+            corrupt = true;
+        }
+    }
+    ok.swap(good);
+    HIPCHK(hipMemcpyAsync(D, H, (size_t)tot, hipMemcpyHostToDevice, st));
+    if (corrupt) {
+        HIPCHK(hipMemcpyAsync(D + moff, H + moff, (size_t)n * sizeof(rdhei_meta), hipMemcpyHostToDevice, st));
+        launch_scatter_meta(L, reinterpret_cast<const rdhei_meta *>(D + moff));
+    }
+    T.device += secs(t2, Clock::now());
+    return RDHEI_OK;
+}
+
+int lmr_batch(rdhei_ctx *ctx, int op, const rdhei_job *jobs, int n, int threads, LmrTimes &T, hipStream_t st) {
+    if (op == RDHEI_OP_ENCRYPT) return lmr_encrypt_batch(ctx, jobs, n, threads, T, st);
+    Layout Ly;
+    int rc = make_layout(op, jobs, n, opts_of(ctx), Ly);
+    if (rc) return rc;
+    if (Ly.method != RDHEI_LMR) return RDHEI_EINVAL;
+    std::vector<int> ok;
+    if ((rc = lmr_decode_batch(ctx, Ly, threads, T, st, ok))) return rc;
+    auto t0 = Clock::now();
+    if (!ok.empty()) {
+        Layout S = subset_layout(Ly, ok);
+        Launch L;
+        if ((rc = stage(ctx, S, ctx->jobs, ctx->ws, st, L))) return rc;
+        for (const Stage &sg : stages_of(S, S.units, S.per_pixel)) sg.fn(L);
+        HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    T.device += secs(t0, Clock::now());
+    return RDHEI_OK;
+}
+
 // Launch a plan's sequence (batched) or image by image.
 int plan_issue(rdhei_plan *P, hipStream_t st) {
     Launch L;
@@ -634,6 +966,8 @@ void rdhei_ctx_destroy(rdhei_ctx *ctx) {
     ctx->jobs.release();
     ctx->scratch.release();
     ctx->batch_tables.release();
+    ctx->lmr_dev.release();
+    ctx->lmr_host.release();
     ctx->ring.release_all();
     delete ctx;
 }
@@ -708,6 +1042,23 @@ int rdhei_recover(rdhei_ctx *ctx, const uint8_t *d_marked, int32_t M, int32_t N,
     q.in = d_marked; q.out = d_img; q.meta = d_meta; q.key = k1;
     q.height = M; q.width = N; q.method = RDHEI_EMR;
     return run_single(ctx, RDHEI_OP_RECOVER, q, st);
+}
+
+int rdhei_lmr_batch(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t njobs, int32_t threads,
+                    double *times, void *stream) {
+    if (!ctx || !jobs || njobs < 1 || threads < 0) return RDHEI_EINVAL;
+    if (op < RDHEI_OP_ENCRYPT || op > RDHEI_OP_RECOVER) return RDHEI_EINVAL;
+    int rc = set_device(ctx->device);
+    if (rc) return rc;
+    LmrTimes T;
+    const auto t0 = Clock::now();
+    rc = lmr_batch(ctx, op, jobs, njobs, threads, T, reinterpret_cast<hipStream_t>(stream));
+    if (times) {
+        times[0] = T.device;
+        times[1] = T.coder;
+        times[2] = secs(t0, Clock::now());
+    }
+    return rc;
 }
 
 int rdhei_workspace_size(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t njobs, int64_t *bytes) {

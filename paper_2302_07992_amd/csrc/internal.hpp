@@ -76,6 +76,12 @@ struct Launch {
 };
 
 void launch_tile_prep(const Launch &L, uint32_t units, bool stats);
+// LMR batch helpers (k_lmr.hip)
+void launch_gather_z(const Launch &L, int64_t *out);
+void launch_gather_meta(const Launch &L, rdhei_meta *out);
+void launch_scatter_meta(const Launch &L, const rdhei_meta *in);
+void launch_msb_plane(const Launch &L, const uint64_t *off, uint8_t *out, uint64_t max_bytes);
+
 // Images with at least kBigTiles tiles are finalised across many workgroups,
 // in blocks of kFinBlock x kFinBlock tiles.
 constexpr uint32_t kBigTiles = 4096;

@@ -31,7 +31,7 @@ EXPORTS = [
     "rdhei_workspace_size", "rdhei_run_batch", "rdhei_plan_create", "rdhei_plan_run", "rdhei_plan_destroy", "rdhei_plan_set_grid",
     "rdhei_plan_stage_count", "rdhei_plan_stage_name", "rdhei_plan_run_stage",
     "rdhei_plan_autotune", "rdhei_plan_stage_grid",
-    "rdhei_lmr_compress", "rdhei_lmr_decompress",
+    "rdhei_lmr_batch", "rdhei_lmr_compress", "rdhei_lmr_decompress",
     "rdhei_strerror", "rdhei_last_error", "rdhei_version",
 ]
 
@@ -109,6 +109,7 @@ def load_library(path: str = LIB_PATH):
     lib.rdhei_plan_run_stage.argtypes = [vp, i32, vp]
     lib.rdhei_plan_autotune.argtypes = [vp, i32, i32, vp]
     lib.rdhei_plan_stage_grid.argtypes = [vp, i32]
+    lib.rdhei_lmr_batch.argtypes = [vp, i32, ctypes.POINTER(JobStruct), i32, i32, ctypes.POINTER(ctypes.c_double), vp]
     lib.rdhei_lmr_compress.argtypes = [vp, vp, i32, i32, vp, i64, ctypes.POINTER(i64)]
     lib.rdhei_lmr_decompress.argtypes = [vp, i64, i32, i32, vp, vp]
     lib.rdhei_strerror.argtypes = [ctypes.c_int]
@@ -236,6 +237,14 @@ class Context:
         p, n = _jobs_arg(jobs)
         _check(self.lib.rdhei_run_batch(self.h, op, p, n, ctypes.c_void_p(workspace_ptr or None),
                                         workspace_bytes, _stream(stream)), "rdhei_run_batch")
+
+    def lmr_batch(self, op: int, jobs, threads: int = 0, stream=None) -> dict:
+        """One LMR role over a job array (method LMR); returns the seconds spent
+        in device stages, in the host coder and in total."""
+        p, n = _jobs_arg(jobs)
+        t = (ctypes.c_double * 3)()
+        _check(self.lib.rdhei_lmr_batch(self.h, op, p, n, threads, t, _stream(stream)), "rdhei_lmr_batch")
+        return {"device_s": t[0], "coder_s": t[1], "total_s": t[2]}
 
     def recover(self, marked: torch.Tensor, meta: torch.Tensor, out: torch.Tensor, k1: int, method: int = EMR,
                 stream=None) -> None:

@@ -467,3 +467,54 @@ def test_autotune_keeps_results_and_caches(R):
         assert set(g) <= cand
     again = plans[0].autotune(reps=1)            # cached: same answer without forcing
     assert again == grids[0]
+
+
+def test_lmr_batch_matches_single_image(R):
+    """The batched LMR roles (device stages batched, map coder on host
+    threads) give the single-image LMR calls' bytes: encrypted image and meta,
+    marked image, extracted payload, and exact recovery (PSNR infinite).  A
+    pure-noise image fits no candidate and comes back RDHEI_ENOFIT."""
+    print("[lmr batch]", flush=True)
+    ctx = R.Context(0)
+    shapes = [(256, 256), (128, 320), (100, 90), (64, 64), (256, 256), (192, 128)]
+    imgs = [_image(1500 + i, *s, sigma=(1.0, 3.0, 8.0)[i % 3]) for i, s in enumerate(shapes)]
+    imgs.append(np.random.default_rng(3).integers(0, 256, (64, 64)).astype(np.uint8))
+    shapes.append((64, 64))
+    n = len(imgs)
+    d_in = [_dev(I) for I in imgs]
+    k1s, k2s = [700 + i for i in range(n)], [800 + i for i in range(n)]
+    enc = [torch.zeros_like(x) for x in d_in]
+    metas = R.new_meta(n)
+    mp = [metas[i] for i in range(n)]
+    t = ctx.lmr_batch(R.OP_ENCRYPT, R.make_jobs(d_in, enc, None, mp, k1s, None, shapes, method=R.LMR), threads=3)
+    assert t["total_s"] > 0
+    ms = R.read_meta(metas)
+    assert ms[-1].status == R.ENOFIT
+    okk = [i for i in range(n - 1)]
+    assert all(ms[i].status == 0 for i in okk)
+    ref = R.Context(0)
+    for i in okk:
+        e = torch.empty_like(d_in[i])
+        m = R.new_meta()
+        ref.encrypt(d_in[i], e, k1s[i], m, method=R.LMR)
+        assert torch.equal(e, enc[i]), i
+        assert torch.equal(m, metas[i]), i
+    caps = [ms[i].capacity_bits if ms[i].status == 0 else 0 for i in range(n)]
+    msgs = [inputs.make_payload(k, c).numpy() for k, c in zip(k2s, caps)]
+    d_msg = [_msg_dev(R, m, c) for m, c in zip(msgs, caps)]
+    ctx.lmr_batch(R.OP_EMBED, R.make_jobs(None, enc, d_msg, mp, k2s, caps, shapes, method=R.LMR))
+    got = [torch.zeros(R.msg_bytes(c), dtype=torch.uint8, device="cuda") for c in caps]
+    ctx.lmr_batch(R.OP_EXTRACT, R.make_jobs(enc, None, got, mp, k2s, caps, shapes, method=R.LMR))
+    rec = [torch.zeros_like(x) for x in d_in]
+    ctx.lmr_batch(R.OP_RECOVER, R.make_jobs(enc, rec, None, mp, k1s, None, shapes, method=R.LMR))
+    torch.cuda.synchronize()
+    for i in okk:
+        e = torch.empty_like(d_in[i])
+        m = R.new_meta()
+        ref.encrypt(d_in[i], e, k1s[i], m, method=R.LMR)
+        ref.embed(e, m, d_msg[i], caps[i], k2s[i], method=R.LMR)
+        assert torch.equal(e, enc[i]), i
+        nb = (caps[i] + 7) // 8
+        assert np.array_equal(got[i].cpu().numpy()[:nb], msgs[i]), i
+        assert torch.equal(rec[i], d_in[i]), i          # exact recovery
+    assert not rec[-1].any()                            # the ENOFIT image was left alone
