@@ -198,7 +198,7 @@ int make_layout(int op, const rdhei_job *in, int n, const LayoutOpts &opt, Layou
             J.ws_tmap = ws;
             ws = align_up(ws + (J.fast ? tiles * 4 : 0), 256);
             J.ws_stats = ws;
-            ws = align_up(ws + (J.fast ? tiles : 1) * kStatWords * 4 + 64, 256);
+            ws = align_up(stat_z_offset(J) + 64, 256);   // counter slots, then Z as 64-bit values
             if (q.method == RDHEI_LMR && !J.fast) {
                 J.ws_bytes = ws;
                 ws = align_up(ws + MN, 256);
@@ -481,7 +481,7 @@ int lmr_encrypt(rdhei_ctx *ctx, const uint8_t *d_img, uint8_t *d_enc, int32_t M,
         launch_finalize(L, true, big, Ly.jobs);
     }
     int64_t Z[7];
-    const uint64_t zoff = J0.ws_stats + (uint64_t)(J0.fast ? J0.tiles_x * J0.tiles_y : 1) * kStatWords * 4;
+    const uint64_t zoff = stat_z_offset(J0);
     HIPCHK(hipMemcpyAsync(Z, ctx->ws.p + zoff, sizeof Z, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     // candidates in order of LMR capacity (b-1)*Z_b, smaller b first on ties

@@ -24,8 +24,10 @@ __host__ __device__ constexpr int code_off(int m) {
 }
 constexpr int kCodeRecord = (code_off(kTileLog + 1) + 15) / 16 * 16;   // 352 bytes for 64 x 64
 
-// Statistics record per tile: histogram of the leading-shared-bit count
-// lambda for lambda = 2..8 (7 counts) + 1 pad word.
+// Statistics of an image: Z_b for b = 2..8 (pixels whose leading-shared-bit
+// count lambda is at least b) + 1 pad word, in stat_slots() copies that
+// workgroups add into by turns (spreads the atomics of a large image), then
+// the image's Z as 64-bit values for the host.
 constexpr int kStatWords = 8;
 
 // Work-unit kinds (how a batch is cut into workgroup-sized pieces).
@@ -59,6 +61,16 @@ struct Job {
     uint64_t ws_stats;        // statistics records
     uint64_t ws_bytes;        // per-pixel path: byte-per-pixel scratch
 };
+
+// Counter slots of an image's statistics: one per 64 tiles, at most 64.
+__host__ __device__ inline uint32_t stat_slots(const Job &J) {
+    if (!J.fast) return 1u;
+    const uint32_t t = (uint32_t)(J.tiles_x * J.tiles_y) / 64u;
+    return t < 1u ? 1u : (t > 64u ? 64u : t);
+}
+__host__ __device__ inline uint64_t stat_z_offset(const Job &J) {
+    return J.ws_stats + (uint64_t)stat_slots(J) * kStatWords * 4;
+}
 
 // Raster segment for hiding / extraction: pixels handled by one workgroup in
 // order.  A chunk is what 256 threads cover with 16 pixels each.

@@ -42,7 +42,7 @@ __global__ void k_gen_level_up(const Job *__restrict__ jobs, int j, uint8_t *__r
     ws[J.ws_codes + gen_off(J.M, J.N, m) + q] = (uint8_t)((c[0] + c[1] + c[cx] + c[cx + 1]) & 3);
 }
 
-// Histogram of lambda (2..8) over pixels with a left neighbour.
+// Z_b (b = 2..8): pixels with a left neighbour and lambda >= b.
 __global__ void k_gen_stats(const Job *__restrict__ jobs, int j, uint8_t *__restrict__ ws) {
     const Job &J = jobs[j];
     __shared__ uint32_t h[7];
@@ -56,7 +56,11 @@ __global__ void k_gen_stats(const Job *__restrict__ jobs, int j, uint8_t *__rest
         if (lam >= 2) atomicAdd(&h[lam - 2], 1u);
     }
     __syncthreads();
-    if (threadIdx.x < 7 && h[threadIdx.x]) atomicAdd(reinterpret_cast<uint32_t *>(ws + J.ws_stats) + threadIdx.x, h[threadIdx.x]);
+    if (threadIdx.x < 7) {
+        uint32_t z = 0;
+        for (int k = (int)threadIdx.x; k < 7; ++k) z += h[k];
+        if (z) atomicAdd(reinterpret_cast<uint32_t *>(ws + J.ws_stats) + threadIdx.x, z);
+    }
 }
 
 // Forward rotation of original position (y, x): levels min_level..n ascending.

@@ -12,8 +12,7 @@ __global__ void k_gather_z(const Job *__restrict__ jobs, int njobs, const uint8_
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= njobs) return;
     const Job &J = jobs[j];
-    const int64_t *z = reinterpret_cast<const int64_t *>(
-        ws + J.ws_stats + (uint64_t)(J.fast ? J.tiles_x * J.tiles_y : 1) * kStatWords * 4);
+    const int64_t *z = reinterpret_cast<const int64_t *>(ws + stat_z_offset(J));
     for (int k = 0; k < 7; ++k) out[7 * j + k] = z[k];
 }
 

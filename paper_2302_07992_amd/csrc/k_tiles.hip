@@ -22,9 +22,13 @@ __device__ __forceinline__ void unit_range(uint32_t units, uint32_t &u0, uint32_
 // ----------------------------------------------------------------------------
 // Keystream code pyramid of one tile (Sec. III-A rotation equation: block code
 // = (sum of s over the block) mod 4 at every level 2^1..2^6 inside the tile)
-// and, for encryption, the histogram of the leading-shared-bit count lambda of
-// each pixel with its left neighbour (Sec. III-A location map; the Omega glide
-// labels a pixel redundant for b exactly when lambda >= b).
+// and, for encryption, the counts Z_b of pixels whose leading-shared-bit count
+// lambda with their left neighbour is at least b (Sec. III-A location map; the
+// Omega glide labels a pixel redundant for b exactly when lambda >= b).
+// lambda >= b means x = pixel XOR left neighbour is below 2^(8-b): four pixels
+// per word test that with one add and one three-input logic op, and a bit
+// count accumulates it.  Counts stay in registers across the tiles of one
+// image and go to the image's record with one atomic add per wave.
 // Thread (r, g) holds 16 keystream bytes of tile row r; a wave covers 16 rows,
 // so levels 1..4 reduce with lane shuffles and only levels 5..6 cross waves.
 // ----------------------------------------------------------------------------
@@ -34,7 +38,6 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
                                                          const uint32_t *__restrict__ ujob) {
     __shared__ __align__(16) uint8_t rec[2][kCodeRecord];
     __shared__ uint8_t l4[2][16];
-    __shared__ uint32_t hist[2][4][8];
     const int tid = threadIdx.x;
     const int r = tid >> 2, g = tid & 3;
     const int lane = tid & 63, wave = tid >> 6;
@@ -53,6 +56,23 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
         left_n = gload<uint8_t>(row + (tx > 0 ? -1 : 0));
     };
     if (u0 < u1) fetch(u0);
+
+    uint32_t cnt[7] = {0, 0, 0, 0, 0, 0, 0};   // this thread's Z_2..Z_8 for the current image
+    int cur_j = -1;
+    auto flush = [&](int jj) {                  // wave sums into one of the image's counter slots
+        if (!STATS || jj < 0) return;
+        const Job &Jf = jobs[jj];
+        const uint32_t slot = (blockIdx.x * (kThreads / 64) + (uint32_t)wave) % stat_slots(Jf);
+        uint32_t *st = reinterpret_cast<uint32_t *>(ws + Jf.ws_stats) + slot * kStatWords;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            uint32_t v = cnt[k];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0 && v) atomicAdd(&st[k], v);
+            cnt[k] = 0;
+        }
+    };
 
     for (uint32_t u = u0; u < u1; ++u) {
         const int par = (int)(u - u0) & 1;
@@ -101,32 +121,31 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
         if (lane < 4) l4[par][wave * 4 + lane] = (uint8_t)c4;
 
         if (STATS) {
+            const int jj = (int)uni((uint32_t)find_job<UNIT_TILE>(jobs, njobs, u, ujob));
+            if (jj != cur_j) {
+                flush(cur_j);
+                cur_j = jj;
+            }
             const uint32_t w[4] = {p.x, p.y, p.z, p.w};
-            uint32_t left = __shfl_up(p.w >> 24, 1, 64);
+            // last byte of the segment to the left (lane g-1 of the quad; the previous tile for g = 0)
+            uint32_t left = (uint32_t)__builtin_amdgcn_mov_dpp((int)(p.w >> 24), 0x90, 0xF, 0xF, false);
             if (g == 0) left = tx > 0 ? left0 : 0u;
-            const uint32_t lw[4] = {(p.x << 8) | left, (p.y << 8) | (p.x >> 24), (p.z << 8) | (p.y >> 24),
-                                    (p.w << 8) | (p.z >> 24)};
-            // packed counters, 9 bits per lambda in 2..8 (lambda < 2 dropped)
-            uint64_t acc = 0;
+            uint32_t x[4];
+            x[0] = w[0] ^ ((w[0] << 8) | left);
+            x[1] = w[1] ^ __builtin_amdgcn_alignbit(w[1], w[0], 24);
+            x[2] = w[2] ^ __builtin_amdgcn_alignbit(w[2], w[1], 24);
+            x[3] = w[3] ^ __builtin_amdgcn_alignbit(w[3], w[2], 24);
+            if (tx == 0 && g == 0) x[0] |= 0xFFu;       // column 0 has no left neighbour
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const uint32_t x = ((w[k >> 2] ^ lw[k >> 2]) >> (8 * (k & 3))) & 0xFFu;
-                const uint32_t lam = __clz((x << 24) | 0x00800000u);       // leading shared bits, 0..8
-                const bool first_col = (tx == 0 && g == 0 && k == 0);
-                if (lam >= 2 && !first_col) acc += 1ull << (9 * (lam - 2));
-            }
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t x7 = x[k] & 0x7F7F7F7Fu;
 #pragma unroll
-            for (int off = 1; off < 16; off <<= 1) acc += __shfl_xor(acc, off, 64);   // <= 256 per field
-            uint32_t c[7];
-#pragma unroll
-            for (int k = 0; k < 7; ++k) {
-                c[k] = (uint32_t)(acc >> (9 * k)) & 0x1FFu;
-                c[k] += __shfl_xor(c[k], 16, 64);
-                c[k] += __shfl_xor(c[k], 32, 64);
-            }
-            if (lane == 0) {
-#pragma unroll
-                for (int k = 0; k < 7; ++k) hist[par][wave][k] = c[k];
+                for (int b = 2; b <= 8; ++b) {
+                    // bit 7 of each byte of s: low 7 bits of x >= 2^(8-b); lt: x < 2^(8-b)
+                    const uint32_t s7 = x7 + (0x80u - (1u << (8 - b))) * 0x01010101u;
+                    const uint32_t lt = __builtin_amdgcn_bitop3_b32(s7, x[k], 0x80808080u, 0x02);
+                    cnt[b - 2] += (uint32_t)__popc(lt);
+                }
             }
         }
         __syncthreads();
@@ -144,14 +163,21 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
             R[code_off(6)] = (uint8_t)(c6 & 3u);
             ws[J.ws_pyr + t] = (uint8_t)(c6 & 3u);
         }
-        if (STATS && tid < 7) {
-            uint32_t *st = reinterpret_cast<uint32_t *>(ws + J.ws_stats) + (uint64_t)t * kStatWords;
-            st[tid] = hist[par][0][tid] + hist[par][1][tid] + hist[par][2][tid] + hist[par][3][tid];
-        }
         __syncthreads();
         if (tid < kCodeRecord / 16)
             gstore<uint4>(ws + J.ws_codes + (uint64_t)t * kCodeRecord + 16 * tid, reinterpret_cast<const uint4 *>(R)[tid]);
     }
+    flush(cur_j);
+}
+
+// Clears the statistics record of every tiled image before k_tile_prep<true>
+// adds into it (images on the per-pixel path clear their own).
+__global__ void k_stats_zero(const Job *__restrict__ jobs, int njobs, uint8_t *__restrict__ ws) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= njobs || !jobs[j].fast) return;
+    uint32_t *st = reinterpret_cast<uint32_t *>(ws + jobs[j].ws_stats);
+    const uint32_t n = stat_slots(jobs[j]) * kStatWords;
+    for (uint32_t k = 0; k < n; ++k) st[k] = 0;
 }
 
 // ----------------------------------------------------------------------------
@@ -162,14 +188,16 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
 // children mod 4 because block sums nest).
 // ----------------------------------------------------------------------------
 // Optimal b (Sec. III-A: argmax of b*Z_b, smallest b on ties) and the public
-// meta record from an image's label histogram hl[k] = #{lambda = k + 2}; the
-// suffix sums Z_b also stay in the workspace for the host (LMR candidates).
-__device__ void finish_stats(const Job &J, const int64_t hl[7], uint8_t *ws) {
-    int64_t Z[9];                       // Z_b = #{lambda >= b}
-    Z[8] = hl[6];
-    for (int b = 7; b >= 2; --b) Z[b] = Z[b + 1] + hl[b - 2];
-    int64_t *zout = reinterpret_cast<int64_t *>(ws + J.ws_stats) +
-                    (uint64_t)(J.fast ? J.tiles_x * J.tiles_y : 1) * (kStatWords / 2);
+// meta record from an image's statistics record (words 0..6: Z_b for b =
+// 2..8, the pixels with lambda >= b); Z also stays in the workspace as 64-bit
+// values for the host (LMR candidates).
+__device__ void finish_stats(const Job &J, uint8_t *ws) {
+    const uint32_t *st = reinterpret_cast<const uint32_t *>(ws + J.ws_stats);
+    int64_t Z[9];
+    for (int b = 2; b <= 8; ++b) Z[b] = 0;
+    for (uint32_t q = 0; q < stat_slots(J); ++q)
+        for (int b = 2; b <= 8; ++b) Z[b] += st[q * kStatWords + (uint32_t)(b - 2)];
+    int64_t *zout = reinterpret_cast<int64_t *>(ws + stat_z_offset(J));
     for (int b = 2; b <= 8; ++b) zout[b - 2] = Z[b];
     if (J.method == RDHEI_EMR) {
         int best = 2;
@@ -183,21 +211,6 @@ __device__ void finish_stats(const Job &J, const int64_t hl[7], uint8_t *ws) {
         m.reserved[0] = m.reserved[1] = m.reserved[2] = 0;
         *J.meta = m;
     }
-}
-
-// Workgroup-wide sums of seven counters; valid in thread 0.
-__device__ __forceinline__ void wg_sum7(uint32_t c[7], uint32_t (*part)[8]) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-#pragma unroll
-    for (int k = 0; k < 7; ++k)
-        for (int off = 32; off > 0; off >>= 1) c[k] += __shfl_xor(c[k], off, 64);
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < 7; ++k) part[wave][k] = c[k];
-    __syncthreads();
-    if (tid == 0)
-#pragma unroll
-        for (int k = 0; k < 7; ++k) c[k] = part[0][k] + part[1][k] + part[2][k] + part[3][k];
 }
 
 // Upper pyramid levels lo..max_level, level by level, by one workgroup.
@@ -219,7 +232,7 @@ __device__ void upper_levels(const Job &J, uint8_t *pyr, int lo) {
 }
 
 // ----------------------------------------------------------------------------
-// One workgroup per image: sums the label histogram, picks the optimal b,
+// One workgroup per image: picks the optimal b from the image's counts,
 // writes the public meta record, and builds the rotation codes of the levels
 // above the tile from the tile sums (a level-m block code is the sum of its
 // four children mod 4 because block sums nest), then the tile map.  Images of
@@ -229,25 +242,11 @@ __device__ void upper_levels(const Job &J, uint8_t *pyr, int lo) {
 template <bool STATS>
 __global__ __launch_bounds__(kThreads) void k_finalize(const Job *__restrict__ jobs, int njobs,
                                                         uint8_t *__restrict__ ws) {
-    __shared__ uint32_t part[kThreads / 64][8];
     const int tid = threadIdx.x;
     for (int j = blockIdx.x; j < njobs; j += gridDim.x) {
         const Job &J = jobs[j];
         if (J.fast && (uint32_t)(J.tiles_x * J.tiles_y) >= kBigTiles) continue;   // uniform per workgroup
-        if (STATS) {
-            const uint32_t nrec = J.fast ? (uint32_t)(J.tiles_x * J.tiles_y) : 1u;
-            const uint32_t *st = reinterpret_cast<const uint32_t *>(ws + J.ws_stats);
-            uint32_t c[7] = {0, 0, 0, 0, 0, 0, 0};
-            for (uint32_t q = tid; q < nrec; q += kThreads)
-#pragma unroll
-                for (int k = 0; k < 7; ++k) c[k] += st[(uint64_t)q * kStatWords + k];
-            wg_sum7(c, part);
-            if (tid == 0) {
-                int64_t hl[7];
-                for (int k = 0; k < 7; ++k) hl[k] = c[k];
-                finish_stats(J, hl, ws);
-            }
-        }
+        if (STATS && tid == 0) finish_stats(J, ws);
         if (J.fast) {
             uint8_t *pyr = ws + J.ws_pyr;
             upper_levels(J, pyr, kTileLog + 1);     // level kTileLog holds the tile sums
@@ -265,38 +264,18 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const Job *__restrict__ j
     }
 }
 
-// Large image, step 1: one workgroup per 16 x 16 block of tiles sums the
-// block's tile statistics (partial records, kept in the tile-map area until
-// step 2 has read them) and builds pyramid levels kTileLog+1..kTileLog+4
-// inside the block.
-template <bool STATS>
-__global__ __launch_bounds__(kThreads) void k_fin_blocks(const Job *__restrict__ jobs, int j,
-                                                          uint8_t *__restrict__ ws) {
+// Large image, step 1: one workgroup per 16 x 16 block of tiles builds
+// pyramid levels kTileLog+1..kTileLog+4 inside the block.
+__global__ __launch_bounds__(kThreads) void k_fin_blocks(const Job *__restrict__ jobs, int j, uint8_t *__restrict__ ws) {
     __shared__ uint8_t lv[2][kFinBlock * kFinBlock];
-    __shared__ uint32_t part[kThreads / 64][8];
     const Job &J = jobs[j];
     const int tid = threadIdx.x;
     const uint32_t nbx = (uint32_t)(J.tiles_x + kFinBlock - 1) / kFinBlock;
     const uint32_t BY = blockIdx.x / nbx, BX = blockIdx.x % nbx;
     const uint32_t ty = BY * kFinBlock + (uint32_t)(tid / kFinBlock), tx = BX * kFinBlock + (uint32_t)(tid % kFinBlock);
     const bool in = ty < (uint32_t)J.tiles_y && tx < (uint32_t)J.tiles_x;
-    const uint32_t t = ty * (uint32_t)J.tiles_x + tx;
     uint8_t *pyr = ws + J.ws_pyr;
-    if (STATS) {
-        uint32_t c[7] = {0, 0, 0, 0, 0, 0, 0};
-        if (in) {
-            const uint32_t *st = reinterpret_cast<const uint32_t *>(ws + J.ws_stats) + (uint64_t)t * kStatWords;
-#pragma unroll
-            for (int k = 0; k < 7; ++k) c[k] = st[k];
-        }
-        wg_sum7(c, part);
-        if (tid == 0) {
-            uint32_t *pp = reinterpret_cast<uint32_t *>(ws + J.ws_tmap) + (uint64_t)blockIdx.x * 8;
-#pragma unroll
-            for (int k = 0; k < 7; ++k) pp[k] = c[k];
-        }
-    }
-    lv[0][tid] = in ? pyr[t] : (uint8_t)0;
+    lv[0][tid] = in ? pyr[ty * (uint32_t)J.tiles_x + tx] : (uint8_t)0;
     int cur = 0;
     uint32_t side = kFinBlock;
     for (int m = kTileLog + 1; m <= kTileLog + 4; ++m) {
@@ -316,29 +295,12 @@ __global__ __launch_bounds__(kThreads) void k_fin_blocks(const Job *__restrict__
     }
 }
 
-// Large image, step 2 (one workgroup): the image's statistics from the
-// partial records, the optimal b and meta, and the pyramid levels above
-// kTileLog+4.
+// Large image, step 2 (one workgroup): the optimal b and meta, and the
+// pyramid levels above kTileLog+4.
 template <bool STATS>
 __global__ __launch_bounds__(kThreads) void k_fin_top(const Job *__restrict__ jobs, int j, uint8_t *__restrict__ ws) {
-    __shared__ uint32_t part[kThreads / 64][8];
     const Job &J = jobs[j];
-    const int tid = threadIdx.x;
-    if (STATS) {
-        const uint32_t nparts = (uint32_t)((J.tiles_y + kFinBlock - 1) / kFinBlock) *
-                                (uint32_t)((J.tiles_x + kFinBlock - 1) / kFinBlock);
-        const uint32_t *pp = reinterpret_cast<const uint32_t *>(ws + J.ws_tmap);
-        uint32_t c[7] = {0, 0, 0, 0, 0, 0, 0};
-        for (uint32_t q = tid; q < nparts; q += kThreads)
-#pragma unroll
-            for (int k = 0; k < 7; ++k) c[k] += pp[(uint64_t)q * 8 + k];
-        wg_sum7(c, part);
-        if (tid == 0) {
-            int64_t hl[7];
-            for (int k = 0; k < 7; ++k) hl[k] = c[k];
-            finish_stats(J, hl, ws);
-        }
-    }
+    if (STATS && threadIdx.x == 0) finish_stats(J, ws);
     upper_levels(J, ws + J.ws_pyr, kTileLog + 5);
 }
 
@@ -796,12 +758,14 @@ static inline unsigned grid_for(const Launch &L, uint32_t units) {
 void launch_tile_prep(const Launch &L, uint32_t units, bool stats) {
     if (!units) return;
     const uint32_t *UJ = L.ujob[UNIT_TILE];
-    if (stats)
+    if (stats) {
+        hipLaunchKernelGGL(k_stats_zero, dim3((L.njobs + 255) / 256), dim3(256), 0, L.stream, L.jobs, L.njobs, L.ws);
         hipLaunchKernelGGL(k_tile_prep<true>, dim3(persistent_grid(L, k_tile_prep<true>, units)), dim3(kThreads), 0,
                            L.stream, L.jobs, L.njobs, L.ws, units, UJ);
-    else
+    } else {
         hipLaunchKernelGGL(k_tile_prep<false>, dim3(persistent_grid(L, k_tile_prep<false>, units)), dim3(kThreads), 0,
                            L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+    }
 }
 
 void launch_finalize(const Launch &L, bool stats, const std::vector<int> &big, const std::vector<Job> &hj) {
@@ -817,13 +781,9 @@ void launch_finalize(const Launch &L, bool stats, const std::vector<int> &big, c
         const Job &J = hj[(size_t)j];
         const unsigned nb = (unsigned)(((J.tiles_y + kFinBlock - 1) / kFinBlock) * ((J.tiles_x + kFinBlock - 1) / kFinBlock));
         const unsigned nt = (unsigned)(((uint32_t)(J.tiles_x * J.tiles_y) + kThreads - 1) / kThreads);
-        if (stats) {
-            hipLaunchKernelGGL(k_fin_blocks<true>, dim3(nb), dim3(kThreads), 0, L.stream, L.jobs, j, L.ws);
-            hipLaunchKernelGGL(k_fin_top<true>, dim3(1), dim3(kThreads), 0, L.stream, L.jobs, j, L.ws);
-        } else {
-            hipLaunchKernelGGL(k_fin_blocks<false>, dim3(nb), dim3(kThreads), 0, L.stream, L.jobs, j, L.ws);
-            hipLaunchKernelGGL(k_fin_top<false>, dim3(1), dim3(kThreads), 0, L.stream, L.jobs, j, L.ws);
-        }
+        hipLaunchKernelGGL(k_fin_blocks, dim3(nb), dim3(kThreads), 0, L.stream, L.jobs, j, L.ws);
+        if (stats) hipLaunchKernelGGL(k_fin_top<true>, dim3(1), dim3(kThreads), 0, L.stream, L.jobs, j, L.ws);
+        else hipLaunchKernelGGL(k_fin_top<false>, dim3(1), dim3(kThreads), 0, L.stream, L.jobs, j, L.ws);
         hipLaunchKernelGGL(k_fin_tmap, dim3(nt), dim3(kThreads), 0, L.stream, L.jobs, j, L.ws);
     }
 }
