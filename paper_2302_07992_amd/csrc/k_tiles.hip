@@ -25,44 +25,53 @@ __device__ __forceinline__ void unit_range(uint32_t units, uint32_t &u0, uint32_
 // and, for encryption, the counts Z_b of pixels whose leading-shared-bit count
 // lambda with their left neighbour is at least b (Sec. III-A location map; the
 // Omega glide labels a pixel redundant for b exactly when lambda >= b).
+//
+// One wave per tile, no workgroup barriers: lane (q, g) holds rows 4q..4q+3,
+// columns 16g..16g+15 (four keystream blocks), so levels 1 and 2 sum inside
+// the lane, and levels 3..6 take a few lane shuffles.  Only the low two bits
+// of every keystream byte matter for the codes.
 // lambda >= b means x = pixel XOR left neighbour is below 2^(8-b): four pixels
-// per word test that with one add and one three-input logic op, and a bit
-// count accumulates it.  Counts stay in registers across the tiles of one
-// image and go to the image's record with one atomic add per wave.
-// Thread (r, g) holds 16 keystream bytes of tile row r; a wave covers 16 rows,
-// so levels 1..4 reduce with lane shuffles and only levels 5..6 cross waves.
+// per word are tested with one add and one three-input logic op, and a bit
+// count accumulates the result.  Counts stay in registers across the tiles
+// of one image and go to one of the image's counter slots with one atomic add
+// per wave.
 // ----------------------------------------------------------------------------
 template <bool STATS>
 __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ jobs, int njobs,
                                                          uint8_t *__restrict__ ws, uint32_t units,
                                                          const uint32_t *__restrict__ ujob) {
-    __shared__ __align__(16) uint8_t rec[2][kCodeRecord];
-    __shared__ uint8_t l4[2][16];
-    const int tid = threadIdx.x;
-    const int r = tid >> 2, g = tid & 3;
-    const int lane = tid & 63, wave = tid >> 6;
-    uint32_t u0, u1;
-    unit_range(units, u0, u1);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane >> 2, g = lane & 3;
+    // contiguous tile range of this wave
+    const uint32_t nw = gridDim.x * (kThreads / 64), gw = blockIdx.x * (kThreads / 64) + (uint32_t)wave;
+    const uint32_t per = (units + nw - 1) / nw;
+    const uint32_t u0 = gw * per, u1 = u0 + per < units ? u0 + per : units;
 
-    uint4 p_n = make_uint4(0, 0, 0, 0);
+    // next tile's pixels (STATS): rows 4q..4q+3, and for g = 0 the byte left of each row
+    uint4 p_n[4];
     uint32_t left_n = 0;
     auto fetch = [&](uint32_t u) {
         if (!STATS) return;
-        const Job &J = jobs[find_job<UNIT_TILE>(jobs, njobs, u, ujob)];
+        const Job &J = jobs[uni((uint32_t)find_job<UNIT_TILE>(jobs, njobs, u, ujob))];
         const uint32_t t = u - J.ubase[UNIT_TILE];
         const int ty = (int)(t / (uint32_t)J.tiles_x), tx = (int)(t % (uint32_t)J.tiles_x);
-        const uint8_t *row = J.in + (uint64_t)(ty * kTile + r) * (uint64_t)J.N + (uint64_t)(tx * kTile);
-        p_n = gload<uint4>(row + 16 * g);
-        left_n = gload<uint8_t>(row + (tx > 0 ? -1 : 0));
+        const uint8_t *row = J.in + (uint64_t)(ty * kTile + 4 * q) * (uint64_t)J.N + (uint64_t)(tx * kTile + 16 * g);
+        uint32_t lb = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            p_n[i] = gload<uint4>(row + (uint64_t)i * J.N);
+            lb |= (uint32_t)gload<uint8_t>(row + (uint64_t)i * J.N - ((g == 0 && tx > 0) ? 1 : 0)) << (8 * i);
+        }
+        left_n = lb;
     };
-    if (u0 < u1) fetch(u0);
+    if (STATS && u0 < u1) fetch(u0);
 
-    uint32_t cnt[7] = {0, 0, 0, 0, 0, 0, 0};   // this thread's Z_2..Z_8 for the current image
+    uint32_t cnt[7] = {0, 0, 0, 0, 0, 0, 0};   // this lane's Z_2..Z_8 for the current image
     int cur_j = -1;
     auto flush = [&](int jj) {                  // wave sums into one of the image's counter slots
         if (!STATS || jj < 0) return;
         const Job &Jf = jobs[jj];
-        const uint32_t slot = (blockIdx.x * (kThreads / 64) + (uint32_t)wave) % stat_slots(Jf);
+        const uint32_t slot = gw % stat_slots(Jf);
         uint32_t *st = reinterpret_cast<uint32_t *>(ws + Jf.ws_stats) + slot * kStatWords;
 #pragma unroll
         for (int k = 0; k < 7; ++k) {
@@ -75,97 +84,109 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
     };
 
     for (uint32_t u = u0; u < u1; ++u) {
-        const int par = (int)(u - u0) & 1;
-        const uint4 p = p_n;
-        const uint32_t left0 = left_n;
-        if (u + 1 < u1) fetch(u + 1);
-        const Job &J = jobs[find_job<UNIT_TILE>(jobs, njobs, u, ujob)];
+        uint4 p[4];
+        uint32_t left = 0;
+        if (STATS) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) p[i] = p_n[i];
+            left = left_n;
+            fetch(u + 1 < u1 ? u + 1 : u);      // the last tile reloads itself: loads always issued
+        }
+        const int j = (int)uni((uint32_t)find_job<UNIT_TILE>(jobs, njobs, u, ujob));
+        const Job &J = jobs[j];
         const uint32_t t = u - J.ubase[UNIT_TILE];
         const int ty = (int)(t / (uint32_t)J.tiles_x), tx = (int)(t % (uint32_t)J.tiles_x);
-        const uint64_t idx = (uint64_t)(ty * kTile + r) * (uint64_t)J.N + (uint64_t)(tx * kTile + 16 * g);
-        const U4 s = stream_block(J.key, kDomainImage, idx >> 4);
-        uint8_t *R = rec[par];
+        const uint64_t idx0 = (uint64_t)(ty * kTile + 4 * q) * (uint64_t)J.N + (uint64_t)(tx * kTile + 16 * g);
 
-        // level 1: 2x2 blocks; even rows hold the sums of rows r, r+1
-        const uint32_t sw[4] = {s.x, s.y, s.z, s.w};
-        uint32_t v[4];
+        // level 1 (2x2) pair sums: h[pp][k] bytes 0 and 2, rows 4q+2pp..+1, columns 16g+4k..+3
+        uint32_t h[2][4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t h = (sw[k] & 0x00FF00FFu) + ((sw[k] >> 8) & 0x00FF00FFu);
-            v[k] = (h + __shfl_down(h, 4, 64)) & 0x00030003u;
-        }
-        uint32_t pack1 = 0, H2 = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            pack1 |= ((v[k] & 3u) | (((v[k] >> 16) & 3u) << 2)) << (4 * k);
-            H2 |= ((v[k] & 3u) + ((v[k] >> 16) & 3u)) << (8 * k);
-        }
-        if ((r & 1) == 0) *reinterpret_cast<uint16_t *>(R + code_off(1) + (r >> 1) * 8 + 2 * g) = (uint16_t)pack1;
-        // level 2: 4x4 blocks, rows r and r+2 (lane + 8)
-        const uint32_t V2 = (H2 + __shfl_down(H2, 8, 64)) & 0x03030303u;
-        uint32_t pack2 = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) pack2 |= ((V2 >> (8 * k)) & 3u) << (2 * k);
-        if ((r & 3) == 0) R[code_off(2) + (r >> 2) * 4 + g] = (uint8_t)pack2;
-        // level 3: 8x8 blocks, rows r and r+4 (lane + 16)
-        const uint32_t H3 = (((V2 & 3u) + ((V2 >> 8) & 3u))) | ((((V2 >> 16) & 3u) + ((V2 >> 24) & 3u)) << 8);
-        const uint32_t V3 = (H3 + __shfl_down(H3, 16, 64)) & 0x0303u;
-        const uint32_t nib = (V3 & 3u) | (((V3 >> 8) & 3u) << 2);
-        const uint32_t nib_hi = __shfl_down(nib, 1, 64);
-        if ((r & 7) == 0 && (g & 1) == 0) R[code_off(3) + 2 * (r >> 3) + (g >> 1)] = (uint8_t)(nib | (nib_hi << 4));
-        // level 4: 16x16 blocks, rows r and r+8 (lane + 32)
-        const uint32_t h4 = (V3 & 3u) + ((V3 >> 8) & 3u);
-        const uint32_t c4 = (h4 + __shfl_down(h4, 32, 64)) & 3u;
-        const uint32_t c4b = __shfl_down(c4, 1, 64), c4c = __shfl_down(c4, 2, 64), c4d = __shfl_down(c4, 3, 64);
-        if (lane == 0) R[code_off(4) + wave] = (uint8_t)(c4 | (c4b << 2) | (c4c << 4) | (c4d << 6));
-        if (lane < 4) l4[par][wave * 4 + lane] = (uint8_t)c4;
-
-        if (STATS) {
-            const int jj = (int)uni((uint32_t)find_job<UNIT_TILE>(jobs, njobs, u, ujob));
-            if (jj != cur_j) {
-                flush(cur_j);
-                cur_j = jj;
-            }
-            const uint32_t w[4] = {p.x, p.y, p.z, p.w};
-            // last byte of the segment to the left (lane g-1 of the quad; the previous tile for g = 0)
-            uint32_t left = (uint32_t)__builtin_amdgcn_mov_dpp((int)(p.w >> 24), 0x90, 0xF, 0xF, false);
-            if (g == 0) left = tx > 0 ? left0 : 0u;
-            uint32_t x[4];
-            x[0] = w[0] ^ ((w[0] << 8) | left);
-            x[1] = w[1] ^ __builtin_amdgcn_alignbit(w[1], w[0], 24);
-            x[2] = w[2] ^ __builtin_amdgcn_alignbit(w[2], w[1], 24);
-            x[3] = w[3] ^ __builtin_amdgcn_alignbit(w[3], w[2], 24);
-            if (tx == 0 && g == 0) x[0] |= 0xFFu;       // column 0 has no left neighbour
+        for (int pp = 0; pp < 2; ++pp) {
+            const U4 sa = stream_block(J.key, kDomainImage, (idx0 + (uint64_t)(2 * pp) * J.N) >> 4);
+            const U4 sb = stream_block(J.key, kDomainImage, (idx0 + (uint64_t)(2 * pp + 1) * J.N) >> 4);
+            const uint32_t wa[4] = {sa.x, sa.y, sa.z, sa.w}, wb[4] = {sb.x, sb.y, sb.z, sb.w};
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const uint32_t x7 = x[k] & 0x7F7F7F7Fu;
+                const uint32_t a = (wa[k] & 0x03030303u) + (wb[k] & 0x03030303u);   // <= 6 per byte
+                h[pp][k] = a + (a >> 8);                                            // bytes 0, 2: <= 12
+            }
+        }
+        // level-1 codes: code row 4q/2 + pp, code columns 8g..8g+7 -> 16 bits
+        uint8_t *rec = ws + J.ws_codes + (uint64_t)t * kCodeRecord;
 #pragma unroll
-                for (int b = 2; b <= 8; ++b) {
-                    // bit 7 of each byte of s: low 7 bits of x >= 2^(8-b); lt: x < 2^(8-b)
-                    const uint32_t s7 = x7 + (0x80u - (1u << (8 - b))) * 0x01010101u;
-                    const uint32_t lt = __builtin_amdgcn_bitop3_b32(s7, x[k], 0x80808080u, 0x02);
-                    cnt[b - 2] += (uint32_t)__popc(lt);
+        for (int pp = 0; pp < 2; ++pp) {
+            const uint32_t c = vperm(h[pp][1], h[pp][0], 0x06040200u) & 0x03030303u;
+            const uint32_t d = vperm(h[pp][3], h[pp][2], 0x06040200u) & 0x03030303u;
+            const uint32_t c8 = (c | (c >> 6) | (c >> 12) | (c >> 18)) & 0xFFu;
+            const uint32_t d8 = (d | (d >> 6) | (d >> 12) | (d >> 18)) & 0xFFu;
+            gstore<uint16_t>(rec + code_off(1) + (2 * q + pp) * 8 + 2 * g, (uint16_t)(c8 | (d8 << 8)));
+        }
+        // level 2 (4x4): block (q, 4g + k)
+        uint32_t L2[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t v = h[0][k] + h[1][k];
+            L2[k] = (v + (v >> 16)) & 0xFFu;                    // <= 48
+        }
+        gstore<uint8_t>(rec + code_off(2) + q * 4 + g,
+                        (uint8_t)((L2[0] & 3u) | ((L2[1] & 3u) << 2) | ((L2[2] & 3u) << 4) | ((L2[3] & 3u) << 6)));
+        // level 3 (8x8): block (q/2, 2g + jj) for even q, from lanes q and q+1
+        const uint32_t hs = (L2[0] + L2[1]) | ((L2[2] + L2[3]) << 16);
+        const uint32_t L3 = hs + __shfl_down(hs, 4, 64);        // halves: columns 2g, 2g+1
+        const uint32_t nib = (L3 & 3u) | ((L3 >> 14) & 0xCu);
+        const uint32_t nib_hi = __shfl_down(nib, 1, 64);
+        if ((q & 1) == 0 && (g & 1) == 0)
+            gstore<uint8_t>(rec + code_off(3) + (q >> 1) * 2 + (g >> 1), (uint8_t)(nib | (nib_hi << 4)));
+        // level 4 (16x16): block (q/4, g) for q % 4 == 0, from lanes q, q+2
+        const uint32_t l3s = (L3 & 0xFFFFu) + (L3 >> 16);
+        const uint32_t L4 = l3s + __shfl_down(l3s, 8, 64);
+        const uint32_t c4 = L4 & 3u;
+        const uint32_t c4row = c4 | (__shfl_down(c4, 1, 64) << 2) | (__shfl_down(c4, 2, 64) << 4) |
+                               (__shfl_down(c4, 3, 64) << 6);
+        if ((q & 3) == 0 && g == 0) gstore<uint8_t>(rec + code_off(4) + (q >> 2), (uint8_t)c4row);
+        // level 5 (32x32): block (q/8, g/2) at lanes q % 8 == 0, g even
+        const uint32_t l4h = L4 + __shfl_down(L4, 1, 64);
+        const uint32_t L5 = l4h + __shfl_down(l4h, 16, 64);
+        // level 6 (the tile) and the level-5 byte, gathered in lane 0
+        const uint32_t c5a = L5 & 3u, c5b = __shfl_down(L5, 2, 64) & 3u;
+        const uint32_t c5c = __shfl_down(L5, 32, 64) & 3u, c5d = __shfl_down(L5, 34, 64) & 3u;
+        if (lane == 0) {
+            const uint32_t c6 = (c5a + c5b + c5c + c5d) & 3u;
+            gstore<uint8_t>(rec + code_off(5), (uint8_t)(c5a | (c5b << 2) | (c5c << 4) | (c5d << 6)));
+            gstore<uint8_t>(rec + code_off(6), (uint8_t)c6);
+            ws[J.ws_pyr + t] = (uint8_t)c6;
+        }
+
+        if (STATS) {
+            if (j != cur_j) {
+                flush(cur_j);
+                cur_j = j;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t w[4] = {p[i].x, p[i].y, p[i].z, p[i].w};
+                // byte left of this segment: lane g-1 of the quad, or the previous tile for g = 0
+                uint32_t lb = (uint32_t)__builtin_amdgcn_mov_dpp((int)(p[i].w >> 24), 0x90, 0xF, 0xF, false);
+                if (g == 0) lb = (left >> (8 * i)) & 0xFFu;
+                uint32_t x[4];
+                x[0] = w[0] ^ ((w[0] << 8) | lb);
+                x[1] = w[1] ^ __builtin_amdgcn_alignbit(w[1], w[0], 24);
+                x[2] = w[2] ^ __builtin_amdgcn_alignbit(w[2], w[1], 24);
+                x[3] = w[3] ^ __builtin_amdgcn_alignbit(w[3], w[2], 24);
+                if (tx == 0 && g == 0) x[0] |= 0xFFu;     // column 0 has no left neighbour
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t x7 = x[k] & 0x7F7F7F7Fu;
+#pragma unroll
+                    for (int b = 2; b <= 8; ++b) {
+                        // bit 7 of each byte of s7: low 7 bits of x >= 2^(8-b); lt: x < 2^(8-b)
+                        const uint32_t s7 = x7 + (0x80u - (1u << (8 - b))) * 0x01010101u;
+                        const uint32_t lt = __builtin_amdgcn_bitop3_b32(s7, x[k], 0x80808080u, 0x02);
+                        cnt[b - 2] += (uint32_t)__popc(lt);
+                    }
                 }
             }
         }
-        __syncthreads();
-        if (tid == 0) {
-            const uint8_t *a = l4[par];
-            uint32_t c5[4], c6 = 0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int Y = q >> 1, X = q & 1;
-                c5[q] = (a[(2 * Y) * 4 + 2 * X] + a[(2 * Y) * 4 + 2 * X + 1] + a[(2 * Y + 1) * 4 + 2 * X] +
-                         a[(2 * Y + 1) * 4 + 2 * X + 1]) & 3u;
-                c6 += c5[q];
-            }
-            R[code_off(5)] = (uint8_t)(c5[0] | (c5[1] << 2) | (c5[2] << 4) | (c5[3] << 6));
-            R[code_off(6)] = (uint8_t)(c6 & 3u);
-            ws[J.ws_pyr + t] = (uint8_t)(c6 & 3u);
-        }
-        __syncthreads();
-        if (tid < kCodeRecord / 16)
-            gstore<uint4>(ws + J.ws_codes + (uint64_t)t * kCodeRecord + 16 * tid, reinterpret_cast<const uint4 *>(R)[tid]);
     }
     flush(cur_j);
 }
