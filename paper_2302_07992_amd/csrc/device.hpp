@@ -233,6 +233,62 @@ __device__ __forceinline__ void block_turns(const uint8_t *rec, int min_level, u
     }
 }
 
+// Quarter turns of one coordinate bit pair as a 32-bit table: entry r*4 + y*2 + x
+// (2 bits) holds (y', x') as y'*2 + x' for r = 0 (y, x), 1 (!x, y), 2 (!y, !x),
+// 3 (x, !y).
+constexpr uint32_t turn_lut() {
+    uint32_t t = 0;
+    for (uint32_t r = 0; r < 4; ++r)
+        for (uint32_t y = 0; y < 2; ++y)
+            for (uint32_t x = 0; x < 2; ++x) {
+                const uint32_t oy = r == 0 ? y : r == 1 ? (x ^ 1u) : r == 2 ? (y ^ 1u) : x;
+                const uint32_t ox = r == 0 ? x : r == 1 ? y : r == 2 ? (x ^ 1u) : (y ^ 1u);
+                t |= (oy * 2 + ox) << (2 * (r * 4 + y * 2 + x));
+            }
+    return t;
+}
+constexpr uint32_t kTurnLut = turn_lut();
+__device__ __forceinline__ uint32_t turn2(uint32_t r, uint32_t y, uint32_t x) {   // -> y' * 2 + x'
+    return (kTurnLut >> (2 * (((r & 3u) << 2) | (y << 1) | x))) & 3u;
+}
+
+// block_turns for the four blocks (by, 4c..4c+3) of one lane's 4x16 strip:
+// the codes of levels 4..6 and the upper bits are shared, and the level-1,
+// 2 and 3 codes of the four blocks come from a few record bytes.
+__device__ __forceinline__ void block_turns4(const uint8_t *rec, int min_level, uint32_t up, uint32_t by, uint32_t c,
+                                             uint32_t ny[4], uint32_t nx[4], uint32_t R1[4], uint32_t k0[4],
+                                             uint32_t k1[4]) {
+    // levels 6 and 5 turn block bits 3 and 2, shared by the four blocks (bx = 4c + k)
+    uint32_t acc = up;
+    if (6 >= min_level) acc += rec[code_off(6)] & 3u;
+    const uint32_t t6 = turn2(acc, (by >> 3) & 1u, (c >> 1) & 1u);
+    if (5 >= min_level) acc += tile_code(rec, 5, by >> 3, c >> 1);
+    const uint32_t t5 = turn2(acc, (by >> 2) & 1u, c & 1u);
+    if (4 >= min_level) acc += tile_code(rec, 4, by >> 2, c);
+    const uint32_t hy = ((t6 >> 1) << 3) | ((t5 >> 1) << 2), hx = ((t6 & 1u) << 3) | ((t5 & 1u) << 2);
+    // level 3: two codes (bx >> 1 = 2c, 2c + 1) in one byte; level 2: four codes in one byte
+    const uint32_t q3 = (by >> 1) * 8u + 2u * c;
+    const uint32_t c3b = 3 >= min_level ? (uint32_t)rec[code_off(3) + (q3 >> 2)] >> (2 * (q3 & 3u)) : 0u;
+    const uint32_t c2b = 2 >= min_level ? (uint32_t)rec[code_off(2) + by * 4u + c] : 0u;
+    // level 1: per row pair of sub-blocks, 16 bits = the four blocks' nibbles
+    uint32_t l1a = 0, l1b = 0;
+    if (min_level <= 1) {
+        l1a = *reinterpret_cast<const uint16_t *>(rec + code_off(1) + (2u * by) * 8u + 2u * c);
+        l1b = *reinterpret_cast<const uint16_t *>(rec + code_off(1) + (2u * by + 1u) * 8u + 2u * c);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t t4 = turn2(acc, (by >> 1) & 1u, (uint32_t)(k >> 1));
+        const uint32_t a3 = acc + ((c3b >> (2 * (k >> 1))) & 3u);
+        const uint32_t t3 = turn2(a3, by & 1u, (uint32_t)(k & 1));
+        ny[k] = hy | ((t4 >> 1) << 1) | (t3 >> 1);
+        nx[k] = hx | ((t4 & 1u) << 1) | (t3 & 1u);
+        R1[k] = (a3 + ((c2b >> (2 * k)) & 3u)) & 3u;
+        k0[k] = (l1a >> (4 * k)) & 0xFu;
+        k1[k] = (l1b >> (4 * k)) & 0xFu;
+    }
+}
+
 // ---- 4x4 block permutes (selector tables staged in LDS) -------------------------
 static __constant__ perm4::Tables kPermTables = perm4::kTables;
 constexpr int kPermSub = 0, kPermWhole = 32, kPermSubInv = 64;

@@ -351,119 +351,151 @@ template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_encrypt_tile(const Job *__restrict__ jobs, int njobs,
                                                             uint8_t *__restrict__ ws, uint32_t units,
                                                             const uint32_t *__restrict__ ujob) {
-    __shared__ __align__(16) uint8_t src[kTile * kRow];
-    __shared__ __align__(16) uint8_t dst[kTile * kRow];
-    __shared__ __align__(16) uint8_t rec[kCodeRecord];
+    constexpr int kW = kThreads / 64;
+    __shared__ __align__(16) uint8_t dsts[kW][kTile * kRow];    // per wave: the destination tile
+    __shared__ __align__(16) uint8_t recs[kW][kCodeRecord];     // per wave: the tile's code record
     __shared__ __align__(16) uint32_t ptab[perm4::kWords];
-    const int tid = threadIdx.x;
-    const int r = tid >> 2, g = tid & 3;
-    const int by = tid >> 4, bx = tid & 15;
-    uint32_t u0, u1;
-    unit_range(units, u0, u1);
-    stage_perm_tables(ptab, tid);   // read after the first barrier below
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane >> 2, g = lane & 3;                       // rows 4q..4q+3, columns 16g..16g+15
+    uint8_t *dst = dsts[wave];
+    uint8_t *rec = recs[wave];
+    stage_perm_tables(ptab, (int)threadIdx.x);
+    __syncthreads();
+    const uint32_t nw = gridDim.x * kW, gw = blockIdx.x * kW + (uint32_t)wave;
+    const uint32_t per = (units + nw - 1) / nw;
+    const uint32_t u0 = gw * per, u1 = u0 + per < units ? u0 + per : units;
 
-    // The next unit's loads are issued unconditionally (the last unit reloads
-    // itself) so the compiler can count them and wait only for the current ones.
-    uint4 p_n = make_uint4(0, 0, 0, 0), rc_n = make_uint4(0, 0, 0, 0);
-    uint32_t left_n = 0, b_n = 0, st_n = 0;
-    auto fetch = [&](uint32_t u) {
+    // The next tile's loads are issued unconditionally (the last tile reloads
+    // itself).  Only the first tile of the range loads the byte left of each
+    // row; later tiles take it from the previous tile's registers.
+    uint4 p_n[4], rc_n = make_uint4(0, 0, 0, 0);
+    uint32_t halo = 0, b_n = 0, st_n = 0, tm_n = 0;
+    auto fetch = [&](uint32_t u, bool with_halo) {
         const Job &J = jobs[uni((uint32_t)find_job<UNIT_TILE>(jobs, njobs, u, ujob))];
         const uint32_t t = u - J.ubase[UNIT_TILE];
         const int ty = (int)(t / (uint32_t)J.tiles_x), tx = (int)(t % (uint32_t)J.tiles_x);
-        const uint8_t *row = J.in + (uint64_t)(ty * kTile + r) * (uint64_t)J.N + (uint64_t)(tx * kTile);
-        p_n = gload<uint4>(row + 16 * g);
-        left_n = gload<uint8_t>(row + (tx > 0 ? -1 : 0));
-        rc_n = gload<uint4>(ws + J.ws_codes + (uint64_t)t * kCodeRecord + 16 * (tid % (kCodeRecord / 16)));
+        const uint8_t *row = J.in + (uint64_t)(ty * kTile + 4 * q) * (uint64_t)J.N + (uint64_t)(tx * kTile + 16 * g);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) p_n[i] = gload<uint4>(row + (uint64_t)i * J.N);
+        if (with_halo) {
+            uint32_t hb = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                hb |= (uint32_t)gload<uint8_t>(row + (uint64_t)i * J.N - ((g == 0 && tx > 0) ? 1 : 0)) << (8 * i);
+            halo = hb;
+        }
+        rc_n = gload<uint4>(ws + J.ws_codes + (uint64_t)t * kCodeRecord + 16 * (lane % (kCodeRecord / 16)));
         b_n = (uint32_t)gload<int32_t>(&J.meta->b);
         st_n = (uint32_t)gload<int32_t>(&J.meta->status);
+        tm_n = gload<uint32_t>(ws + J.ws_tmap + 4 * (uint64_t)t);
     };
-    if (u0 < u1) fetch(u0);
+    if (u0 < u1) fetch(u0, true);
+    uint32_t prev3[4] = {0, 0, 0, 0};   // word 3 of each row of the previous tile
 
     for (uint32_t u = u0; u < u1; ++u) {
-        const uint4 p = p_n, rc = rc_n;
-        const uint32_t left0 = left_n, b_cur = uni(b_n), st_cur = uni(st_n);
-        fetch(u + 1 < u1 ? u + 1 : u);
+        uint4 p[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) p[i] = p_n[i];
+        const uint4 rc = rc_n;
+        const uint32_t b_cur = uni(b_n), st_cur = uni(st_n), tm = uni(tm_n);
+        fetch(u + 1 < u1 ? u + 1 : u, false);
         const Job &J = jobs[uni((uint32_t)find_job<UNIT_TILE>(jobs, njobs, u, ujob))];
         const uint32_t t = u - J.ubase[UNIT_TILE];
-        const int ty = (int)(t / (uint32_t)J.tiles_x), tx = (int)(t % (uint32_t)J.tiles_x);
-        if (MODE == ENC_EMR && st_cur != (uint32_t)RDHEI_OK) continue;
+        const int tx = (int)(t % (uint32_t)J.tiles_x);
+        if (MODE == ENC_EMR && st_cur != (uint32_t)RDHEI_OK) continue;     // uniform: no barriers below
         const int b = J.fixed_b > 0 ? J.fixed_b : (int)b_cur;
         int dy, dx;
         uint32_t up;
-        tmap_unpack(reinterpret_cast<const uint32_t *>(ws + J.ws_tmap)[t], dy, dx, up);
+        tmap_unpack(tm, dy, dx, up);
 
-        uint4 o = p;
-        if (MODE != ENC_LMR) {
-            uint32_t left = __shfl_up(p.w >> 24, 1, 64);
-            if (g == 0) left = tx > 0 ? left0 : 0u;
+        // labels (Sec. III-A location map): l = 1 unless the b MSBs equal the left neighbour's
+        uint32_t o[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t w[4] = {p[i].x, p[i].y, p[i].z, p[i].w};
+            const uint32_t from_left = (uint32_t)__builtin_amdgcn_mov_dpp((int)(p[i].w >> 24), 0x90, 0xF, 0xF, false);
+            const uint32_t from_prev = (uint32_t)__builtin_amdgcn_mov_dpp((int)(prev3[i] >> 24), 0xFF, 0xF, 0xF, false);
+            prev3[i] = p[i].w;
+            if (MODE == ENC_LMR) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) o[i][k] = w[k];
+                continue;
+            }
+            const uint32_t left = g > 0 ? from_left : (u > u0 ? from_prev : (halo >> (8 * i)) & 0xFFu);
             const uint32_t topm = ((0xFFu << (8 - b)) & 0xFFu) * 0x01010101u;
-            const uint32_t w[4] = {p.x, p.y, p.z, p.w};
-            const uint32_t lw[4] = {(p.x << 8) | left, (p.y << 8) | (p.x >> 24), (p.z << 8) | (p.y >> 24),
-                                    (p.w << 8) | (p.z >> 24)};
-            uint32_t res[4];
+            const uint32_t lw[4] = {(w[0] << 8) | left, __builtin_amdgcn_alignbit(w[1], w[0], 24),
+                                    __builtin_amdgcn_alignbit(w[2], w[1], 24), __builtin_amdgcn_alignbit(w[3], w[2], 24)};
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const uint32_t d = (w[k] ^ lw[k]) & topm;
                 uint32_t nz = ((((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d) >> 7) & 0x01010101u;  // l per byte
                 if (k == 0 && tx == 0 && g == 0) nz |= 1u;                                  // column 0
-                if (MODE == ENC_EMR) res[k] = (w[k] & 0xFEFEFEFEu) | nz;
-                else res[k] = (nz << 1) | ((w[k] >> 7) & 0x01010101u);                      // l<<1 | eta
+                if (MODE == ENC_EMR) o[i][k] = (w[k] & 0xFEFEFEFEu) | nz;
+                else o[i][k] = (nz << 1) | ((w[k] >> 7) & 0x01010101u);                     // l<<1 | eta
             }
-            o = make_uint4(res[0], res[1], res[2], res[3]);
         }
-        *reinterpret_cast<uint4 *>(src + r * kRow + 16 * g) = o;
-        if (tid < kCodeRecord / 16) reinterpret_cast<uint4 *>(rec)[tid] = rc;
-        __syncthreads();
+        if (lane < kCodeRecord / 16) reinterpret_cast<uint4 *>(rec)[lane] = rc;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-        // this thread's 4x4 block goes whole to its destination block
-        uint32_t ny, nx, R1, k0, k1;
-        block_turns(rec, J.min_level, up, (uint32_t)by, (uint32_t)bx, ny, nx, R1, k0, k1);
-        uint32_t w[4], ob[4];
+        // this lane's four 4x4 blocks (row q, columns 4g..4g+3) go whole to their destinations
+        uint32_t ny[4], nx[4], R1[4], k0[4], k1[4];
+        block_turns4(rec, J.min_level, up, (uint32_t)q, (uint32_t)g, ny, nx, R1, k0, k1);
 #pragma unroll
-        for (int uu = 0; uu < 4; ++uu) w[uu] = *reinterpret_cast<const uint32_t *>(src + (4 * by + uu) * kRow + 4 * bx);
-        block_forward(ptab, R1, k0, k1, w, ob);
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t w[4] = {o[0][k], o[1][k], o[2][k], o[3][k]};
+            uint32_t ob[4];
+            block_forward(ptab, R1[k], k0[k], k1[k], w, ob);
 #pragma unroll
-        for (int uu = 0; uu < 4; ++uu) *reinterpret_cast<uint32_t *>(dst + (4 * ny + uu) * kRow + 4 * nx) = ob[uu];
-        __syncthreads();
+            for (int uu = 0; uu < 4; ++uu)
+                *reinterpret_cast<uint32_t *>(dst + (4 * ny[k] + uu) * kRow + 4 * nx[k]) = ob[uu];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-        const uint4 q = *reinterpret_cast<const uint4 *>(dst + r * kRow + 16 * g);
-        const uint64_t didx = (uint64_t)(dy * kTile + r) * (uint64_t)J.N + (uint64_t)(dx * kTile + 16 * g);
-        if (MODE == ENC_LMR_MAPS) {
-            // bit planes, MSB-first: pixel didx+k -> byte (didx+k)/8, bit 7-(k%8)
-            const uint32_t qq[4] = {q.x, q.y, q.z, q.w};
-            uint32_t lb = 0, eb = 0;
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const uint32_t v = (qq[k >> 2] >> (8 * (k & 3))) & 3u;
-                const int pos = (k < 8) ? (7 - k) : (23 - k);   // little-endian u16 of two MSB-first bytes
-                lb |= ((v >> 1) & 1u) << pos;
-                eb |= (v & 1u) << pos;
-            }
-            gstore<uint16_t>(J.out + (didx >> 3), (uint16_t)lb);
-            gstore<uint16_t>(J.msg + (didx >> 3), (uint16_t)eb);
-        } else {
-            const U4 s = stream_block(J.key, kDomainImage, didx >> 4);
-            uint4 e;
-            if (MODE == ENC_EMR) {
-                e = make_uint4(q.x ^ (s.x & 0xFEFEFEFEu), q.y ^ (s.y & 0xFEFEFEFEu), q.z ^ (s.z & 0xFEFEFEFEu),
-                               q.w ^ (s.w & 0xFEFEFEFEu));
-            } else {
-                e = make_uint4(q.x ^ s.x, q.y ^ s.y, q.z ^ s.z, q.w ^ s.w);
-                if ((int64_t)didx < J.stream_bits) {
-                    // 16 stream bits for pixels didx..didx+15 (didx is a multiple of 16)
-                    const uint32_t sb = ((uint32_t)J.stream[didx >> 3] << 8) | J.stream[(didx >> 3) + 1];
-                    uint32_t ew[4] = {e.x, e.y, e.z, e.w};
+        for (int i = 0; i < 4; ++i) {
+            const uint4 qv = *reinterpret_cast<const uint4 *>(dst + (4 * q + i) * kRow + 16 * g);
+            const uint64_t didx = (uint64_t)(dy * kTile + 4 * q + i) * (uint64_t)J.N + (uint64_t)(dx * kTile + 16 * g);
+            if (MODE == ENC_LMR_MAPS) {
+                // bit planes, MSB-first: pixel didx+k -> byte (didx+k)/8, bit 7-(k%8)
+                const uint32_t qq[4] = {qv.x, qv.y, qv.z, qv.w};
+                uint32_t lb = 0, eb = 0;
 #pragma unroll
-                    for (int k = 0; k < 16; ++k) {
-                        if ((int64_t)didx + k < J.stream_bits) {
-                            const uint32_t bit = (sb >> (15 - k)) & 1u;
-                            ew[k >> 2] = (ew[k >> 2] & ~(0x80u << (8 * (k & 3)))) | (bit << (8 * (k & 3) + 7));
-                        }
-                    }
-                    e = make_uint4(ew[0], ew[1], ew[2], ew[3]);
+                for (int k = 0; k < 16; ++k) {
+                    const uint32_t v = (qq[k >> 2] >> (8 * (k & 3))) & 3u;
+                    const int pos = (k < 8) ? (7 - k) : (23 - k);   // little-endian u16 of two MSB-first bytes
+                    lb |= ((v >> 1) & 1u) << pos;
+                    eb |= (v & 1u) << pos;
                 }
+                gstore<uint16_t>(J.out + (didx >> 3), (uint16_t)lb);
+                gstore<uint16_t>(J.msg + (didx >> 3), (uint16_t)eb);
+            } else {
+                const U4 sk = stream_block(J.key, kDomainImage, didx >> 4);
+                uint4 e;
+                if (MODE == ENC_EMR) {
+                    e = make_uint4(qv.x ^ (sk.x & 0xFEFEFEFEu), qv.y ^ (sk.y & 0xFEFEFEFEu),
+                                   qv.z ^ (sk.z & 0xFEFEFEFEu), qv.w ^ (sk.w & 0xFEFEFEFEu));
+                } else {
+                    e = make_uint4(qv.x ^ sk.x, qv.y ^ sk.y, qv.z ^ sk.z, qv.w ^ sk.w);
+                    if ((int64_t)didx < J.stream_bits) {
+                        // 16 stream bits for pixels didx..didx+15 (didx is a multiple of 16)
+                        const uint32_t sb = ((uint32_t)J.stream[didx >> 3] << 8) | J.stream[(didx >> 3) + 1];
+                        uint32_t ew[4] = {e.x, e.y, e.z, e.w};
+#pragma unroll
+                        for (int k = 0; k < 16; ++k) {
+                            if ((int64_t)didx + k < J.stream_bits) {
+                                const uint32_t bit = (sb >> (15 - k)) & 1u;
+                                ew[k >> 2] = (ew[k >> 2] & ~(0x80u << (8 * (k & 3)))) | (bit << (8 * (k & 3) + 7));
+                            }
+                        }
+                        e = make_uint4(ew[0], ew[1], ew[2], ew[3]);
+                    }
+                }
+                gstore<uint4>(J.out + didx, e);
             }
-            gstore<uint4>(J.out + didx, e);
         }
     }
 }
