@@ -40,12 +40,14 @@ template <bool STATS>
 __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ jobs, int njobs,
                                                          uint8_t *__restrict__ ws, uint32_t units,
                                                          const uint32_t *__restrict__ ujob) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr uint32_t kW = kThreads / 64;
+    const int lane = threadIdx.x & 63, wave = (int)uni(threadIdx.x >> 6);   // wave-uniform
     const int q = lane >> 2, g = lane & 3;
-    // contiguous tile range of this wave
-    const uint32_t nw = gridDim.x * (kThreads / 64), gw = blockIdx.x * (kThreads / 64) + (uint32_t)wave;
-    const uint32_t per = (units + nw - 1) / nw;
-    const uint32_t u0 = gw * per, u1 = u0 + per < units ? u0 + per : units;
+    // the workgroup's contiguous tile range, dealt to its waves in turn so
+    // that neighbouring tiles (which share 128-byte lines) are read together
+    uint32_t r0, r1;
+    unit_range(units, r0, r1);
+    const uint32_t u0 = r0 + (uint32_t)wave, gw = blockIdx.x * kW + (uint32_t)wave;
 
     // next tile's pixels (STATS): rows 4q..4q+3, and for g = 0 the byte left of each row
     uint4 p_n[4];
@@ -64,7 +66,7 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
         }
         left_n = lb;
     };
-    if (STATS && u0 < u1) fetch(u0);
+    if (STATS && u0 < r1) fetch(u0);
 
     uint32_t cnt[7] = {0, 0, 0, 0, 0, 0, 0};   // this lane's Z_2..Z_8 for the current image
     int cur_j = -1;
@@ -83,14 +85,14 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
         }
     };
 
-    for (uint32_t u = u0; u < u1; ++u) {
+    for (uint32_t u = u0; u < r1; u += kW) {
         uint4 p[4];
         uint32_t left = 0;
         if (STATS) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) p[i] = p_n[i];
             left = left_n;
-            fetch(u + 1 < u1 ? u + 1 : u);      // the last tile reloads itself: loads always issued
+            fetch(u + kW < r1 ? u + kW : u);    // the last tile reloads itself: loads always issued
         }
         const int j = (int)uni((uint32_t)find_job<UNIT_TILE>(jobs, njobs, u, ujob));
         const Job &J = jobs[j];
@@ -355,54 +357,61 @@ __global__ __launch_bounds__(kThreads) void k_encrypt_tile(const Job *__restrict
     __shared__ __align__(16) uint8_t dsts[kW][kTile * kRow];    // per wave: the destination tile
     __shared__ __align__(16) uint8_t recs[kW][kCodeRecord];     // per wave: the tile's code record
     __shared__ __align__(16) uint32_t ptab[perm4::kWords];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = (int)uni(threadIdx.x >> 6);   // wave-uniform
     const int q = lane >> 2, g = lane & 3;                       // rows 4q..4q+3, columns 16g..16g+15
     uint8_t *dst = dsts[wave];
     uint8_t *rec = recs[wave];
     stage_perm_tables(ptab, (int)threadIdx.x);
     __syncthreads();
-    const uint32_t nw = gridDim.x * kW, gw = blockIdx.x * kW + (uint32_t)wave;
-    const uint32_t per = (units + nw - 1) / nw;
-    const uint32_t u0 = gw * per, u1 = u0 + per < units ? u0 + per : units;
+    // the workgroup's contiguous tile range, dealt to its waves in turn so
+    // that neighbouring tiles (which share 128-byte lines) are read together
+    uint32_t r0, r1;
+    unit_range(units, r0, r1);
+    const uint32_t u0 = r0 + (uint32_t)wave;
 
     // The next tile's loads are issued unconditionally (the last tile reloads
-    // itself).  Only the first tile of the range loads the byte left of each
-    // row; later tiles take it from the previous tile's registers.
+    // itself), including the byte left of each row (read by the neighbouring
+    // wave at the same time).
     uint4 p_n[4], rc_n = make_uint4(0, 0, 0, 0);
-    uint32_t halo = 0, b_n = 0, st_n = 0, tm_n = 0;
-    auto fetch = [&](uint32_t u, bool with_halo) {
+    uint32_t halo_n = 0, b_n = 0, st_n = 0, tm_n = 0;
+    auto fetch = [&](uint32_t u) {
         const Job &J = jobs[uni((uint32_t)find_job<UNIT_TILE>(jobs, njobs, u, ujob))];
         const uint32_t t = u - J.ubase[UNIT_TILE];
         const int ty = (int)(t / (uint32_t)J.tiles_x), tx = (int)(t % (uint32_t)J.tiles_x);
         const uint8_t *row = J.in + (uint64_t)(ty * kTile + 4 * q) * (uint64_t)J.N + (uint64_t)(tx * kTile + 16 * g);
 #pragma unroll
         for (int i = 0; i < 4; ++i) p_n[i] = gload<uint4>(row + (uint64_t)i * J.N);
-        if (with_halo) {
-            uint32_t hb = 0;
+        uint32_t hb = 0;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                hb |= (uint32_t)gload<uint8_t>(row + (uint64_t)i * J.N - ((g == 0 && tx > 0) ? 1 : 0)) << (8 * i);
-            halo = hb;
-        }
+        for (int i = 0; i < 4; ++i)
+            hb |= (uint32_t)gload<uint8_t>(row + (uint64_t)i * J.N - ((g == 0 && tx > 0) ? 1 : 0)) << (8 * i);
+        halo_n = hb;
         rc_n = gload<uint4>(ws + J.ws_codes + (uint64_t)t * kCodeRecord + 16 * (lane % (kCodeRecord / 16)));
         b_n = (uint32_t)gload<int32_t>(&J.meta->b);
         st_n = (uint32_t)gload<int32_t>(&J.meta->status);
         tm_n = gload<uint32_t>(ws + J.ws_tmap + 4 * (uint64_t)t);
     };
-    if (u0 < u1) fetch(u0, true);
-    uint32_t prev3[4] = {0, 0, 0, 0};   // word 3 of each row of the previous tile
+    // every wave runs the same number of rounds (a wave past the range idles
+    // through its last ones) so that one barrier per round keeps the waves'
+    // loads together
+    const uint32_t rounds = r1 > r0 ? (r1 - r0 + kW - 1) / kW : 0u;
+    const uint32_t ulast = r1 > r0 ? r1 - 1 : 0u;
+    if (rounds) fetch(u0 < r1 ? u0 : ulast);
 
-    for (uint32_t u = u0; u < u1; ++u) {
+    for (uint32_t it = 0; it < rounds; ++it) {
+        const uint32_t u = u0 + it * kW;
         uint4 p[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) p[i] = p_n[i];
         const uint4 rc = rc_n;
-        const uint32_t b_cur = uni(b_n), st_cur = uni(st_n), tm = uni(tm_n);
-        fetch(u + 1 < u1 ? u + 1 : u, false);
+        const uint32_t halo = halo_n, b_cur = uni(b_n), st_cur = uni(st_n), tm = uni(tm_n);
+        __syncthreads();
+        fetch(u + kW < r1 ? u + kW : (u < r1 ? u : ulast));
+        if (u >= r1) continue;                                            // uniform per wave
         const Job &J = jobs[uni((uint32_t)find_job<UNIT_TILE>(jobs, njobs, u, ujob))];
         const uint32_t t = u - J.ubase[UNIT_TILE];
         const int tx = (int)(t % (uint32_t)J.tiles_x);
-        if (MODE == ENC_EMR && st_cur != (uint32_t)RDHEI_OK) continue;     // uniform: no barriers below
+        if (MODE == ENC_EMR && st_cur != (uint32_t)RDHEI_OK) continue;     // uniform per wave
         const int b = J.fixed_b > 0 ? J.fixed_b : (int)b_cur;
         int dy, dx;
         uint32_t up;
@@ -414,14 +423,12 @@ __global__ __launch_bounds__(kThreads) void k_encrypt_tile(const Job *__restrict
         for (int i = 0; i < 4; ++i) {
             const uint32_t w[4] = {p[i].x, p[i].y, p[i].z, p[i].w};
             const uint32_t from_left = (uint32_t)__builtin_amdgcn_mov_dpp((int)(p[i].w >> 24), 0x90, 0xF, 0xF, false);
-            const uint32_t from_prev = (uint32_t)__builtin_amdgcn_mov_dpp((int)(prev3[i] >> 24), 0xFF, 0xF, 0xF, false);
-            prev3[i] = p[i].w;
             if (MODE == ENC_LMR) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) o[i][k] = w[k];
                 continue;
             }
-            const uint32_t left = g > 0 ? from_left : (u > u0 ? from_prev : (halo >> (8 * i)) & 0xFFu);
+            const uint32_t left = g > 0 ? from_left : (halo >> (8 * i)) & 0xFFu;
             const uint32_t topm = ((0xFFu << (8 - b)) & 0xFFu) * 0x01010101u;
             const uint32_t lw[4] = {(w[0] << 8) | left, __builtin_amdgcn_alignbit(w[1], w[0], 24),
                                     __builtin_amdgcn_alignbit(w[2], w[1], 24), __builtin_amdgcn_alignbit(w[3], w[2], 24)};
