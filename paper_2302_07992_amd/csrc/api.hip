@@ -209,7 +209,7 @@ int make_layout(int op, const rdhei_job *in, int n, const LayoutOpts &opt, Layou
         const bool hide = op == RDHEI_OP_EMBED || op == RDHEI_OP_EXTRACT;
         const bool whole = whole_ok && whole_eligible(op, q);
         const uint32_t cnt[UNIT_KINDS] = {J.fast ? (uint32_t)(J.tiles_x * J.tiles_y) : 0u,
-                                          J.fast ? (uint32_t)J.tiles_y : 0u,
+                                          J.fast ? (uint32_t)(q.method == RDHEI_EMR ? (J.tiles_y + 1) / 2 : J.tiles_y) : 0u,
                                           hide && !whole ? (uint32_t)J.nseg : 0u, whole ? 1u : 0u};
         for (int k = 0; k < UNIT_KINDS; ++k) {
             J.ubase[k] = L.units[k];

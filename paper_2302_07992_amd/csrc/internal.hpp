@@ -31,6 +31,7 @@ constexpr int kCodeRecord = (code_off(kTileLog + 1) + 15) / 16 * 16;   // 352 by
 constexpr int kStatWords = 8;
 
 // Work-unit kinds (how a batch is cut into workgroup-sized pieces).
+// UNIT_BAND: EMR recovery takes band pairs (tile rows 2p, 2p + 1), LMR single tile rows.
 enum UnitKind { UNIT_TILE = 0, UNIT_BAND = 1, UNIT_SEG = 2, UNIT_IMG = 3, UNIT_KINDS = 4 };
 
 // Device-side descriptor of one image of a launch.

@@ -6,6 +6,7 @@
 // work units (tiles of one image stay on one workgroup, hence on one XCD and
 // its L2) and loads the next unit's inputs before working on the current one.
 #include "device.hpp"
+#include "glide4.hpp"
 
 namespace rdhei {
 
@@ -788,6 +789,242 @@ __global__ __launch_bounds__(kThreads) void k_recover_band_emr(const Job *__rest
     }
 }
 
+// ----------------------------------------------------------------------------
+// EMR recovery by quads: the 2x2 tiles of tile rows 2p, 2p+1 and tile columns
+// 2c, 2c+1, one wave per tile, quads of a band pair left to right.  The four
+// tiles of a full quad form a level-7 block, so their encrypted data is one
+// 128 x 128 block (whole 128-byte lines), read by the four waves together.
+//
+// Each wave decrypts its encrypted tile (keystream at the encrypted position)
+// into LDS as 4x4 blocks (pixels and labels l = LSB), then each lane gathers
+// its own four original blocks and turns them back with one composed permute
+// per row.  The glide (a pixel labelled 0 takes the replaceable bits of the
+// nearest pixel labelled 1 to its left) is one permute per 4-pixel word,
+// selected by the word's label pattern; values cross lanes by a quad scan
+// and cross tiles through LDS (left tile of a row -> right tile -> next quad),
+// with one workgroup barrier per quad.
+// ----------------------------------------------------------------------------
+// Byte offset of 4x4 block (by, bx) in a wave's tile of blocks: 16 bytes per
+// block, 16 blocks per block row, columns swizzled so that the writes of
+// lanes (q, g) and (q + 1, g) fall in different banks.
+__device__ __forceinline__ uint32_t blk_addr(uint32_t by, uint32_t bx) {
+    const uint32_t sw = (((bx >> 3) & 1u) << 1) ^ (by & 1u);
+    return by * 256u + ((bx ^ sw) << 4);
+}
+
+static __constant__ perm4::InvTables kInvTables = perm4::kInvTables;
+static __constant__ glide4::Tables kGlideTables = glide4::kTables;
+
+__global__ __launch_bounds__(kThreads) void k_recover_quad_emr(const Job *__restrict__ jobs, int njobs,
+                                                               uint8_t *__restrict__ ws, uint32_t units,
+                                                               const uint32_t *__restrict__ ujob) {
+    constexpr int kW = kThreads / 64;
+    __shared__ __align__(16) uint8_t dts[kW][kTile * kTile];   // per wave: decrypted tile, 4x4 blocks
+    __shared__ __align__(16) uint8_t lbs[kW][kTile * kTile];   // per wave: labels, same layout
+    __shared__ __align__(16) uint8_t recs[kW][kCodeRecord];    // per wave: the tile's code record
+    __shared__ __align__(16) uint32_t itab[perm4::kInvWords];
+    __shared__ __align__(16) uint32_t gtab[glide4::kWords];
+    __shared__ __align__(8) uint16_t sums[2][kW][kTile];       // per tile row: last labelled value | 0x100, or 0
+    __shared__ __align__(8) uint16_t carry[2][2][kTile];       // per band half: carry into the next quad
+    const int lane = threadIdx.x & 63, wave = (int)uni(threadIdx.x >> 6);   // wave-uniform
+    const int q = lane >> 2, g = lane & 3;                      // rows 4q..4q+3, columns 16g..16g+15
+    const int side = wave & 1, half = wave >> 1;                // this wave's tile in the quad
+    uint8_t *dt = dts[wave];
+    uint8_t *lb = lbs[wave];
+    uint8_t *rec = recs[wave];
+    for (int i = (int)threadIdx.x; i < perm4::kInvWords; i += kThreads)
+        itab[i] = reinterpret_cast<const uint32_t *>(&kInvTables)[i];
+    if (threadIdx.x < glide4::kWords) gtab[threadIdx.x] = kGlideTables.fill_sel[threadIdx.x];
+    __syncthreads();
+
+    uint32_t r0, r1;
+    unit_range(units, r0, r1);
+    auto job_of = [&](uint32_t u) { return (int)uni((uint32_t)find_job<UNIT_BAND>(jobs, njobs, u, ujob)); };
+    // quads (u, c): band pair u of the launch, quad column c
+    auto step = [&](uint32_t &u, uint32_t &c) {
+        if (u >= r1) return;
+        const Job &J = jobs[job_of(u)];
+        if (++c >= (uint32_t)((J.tiles_x + 1) >> 1)) {
+            ++u;
+            c = 0;
+        }
+    };
+    // this wave's tile of quad (u, c); false when it lies outside the image
+    auto tile_of = [&](uint32_t u, uint32_t c, int &j, int &ty, int &tx) {
+        if (u >= r1) return false;
+        j = job_of(u);
+        const Job &J = jobs[j];
+        ty = 2 * (int)(u - J.ubase[UNIT_BAND]) + half;
+        tx = 2 * (int)c + side;
+        return ty < J.tiles_y && tx < J.tiles_x;
+    };
+    // tile-map entry and b of a quad's tile (loaded an iteration before the pixels)
+    auto load_tm = [&](uint32_t u, uint32_t c, uint32_t &tm, uint32_t &bb) {
+        int j = 0, ty = 0, tx = 0;
+        if (!tile_of(u, c, j, ty, tx)) return;
+        const Job &J = jobs[j];
+        tm = gload<uint32_t>(ws + J.ws_tmap + 4 * (uint64_t)(ty * J.tiles_x + tx));
+        bb = (uint32_t)gload<int32_t>(&J.meta->b);
+    };
+    uint4 e_n[4], rc_n = make_uint4(0, 0, 0, 0);
+    auto fetch = [&](uint32_t u, uint32_t c, uint32_t tm) {
+        int j = 0, ty = 0, tx = 0;
+        if (!tile_of(u, c, j, ty, tx)) return;
+        const Job &J = jobs[j];
+        int ey, ex;
+        uint32_t up;
+        tmap_unpack(uni(tm), ey, ex, up);
+        const uint8_t *src = J.in + (uint64_t)(ey * kTile + 4 * q) * (uint64_t)J.N + (uint64_t)(ex * kTile + 16 * g);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) e_n[i] = gload<uint4>(src + (uint64_t)i * J.N);
+        rc_n = gload<uint4>(ws + J.ws_codes + (uint64_t)(ty * J.tiles_x + tx) * kCodeRecord + 16 * (lane % (kCodeRecord / 16)));
+    };
+
+    uint32_t u = r0, c = 0;              // current quad
+    uint32_t u1 = r0, c1 = 0;            // the next one
+    step(u1, c1);
+    uint32_t tm = 0, b_cur = 0, tm1 = 0, b1 = 0;
+    load_tm(u, c, tm, b_cur);
+    fetch(u, c, tm);
+    load_tm(u1, c1, tm1, b1);
+
+    for (uint32_t it = 0; u < r1; ++it) {
+        uint4 e[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) e[i] = e_n[i];
+        const uint4 rc = rc_n;
+        const uint32_t tm_cur = uni(tm), bq = uni(b_cur);
+        // pipeline: pixels of the next quad, tile map of the one after
+        fetch(u1, c1, tm1);
+        uint32_t u2 = u1, c2 = c1;
+        step(u2, c2);
+        tm = tm1;
+        b_cur = b1;
+        load_tm(u2, c2, tm1, b1);
+
+        int j = 0, ty = 0, tx = 0;
+        const bool have = tile_of(u, c, j, ty, tx);   // wave-uniform
+        const bool first = c == 0;
+        const uint32_t slot = it & 1u;
+        uint32_t Do[4][4], sel[4][4], excl[4], tsum[4];
+        if (have) {
+            const Job &J = jobs[j];
+            int ey, ex;
+            uint32_t up;
+            tmap_unpack(tm_cur, ey, ex, up);
+            // decrypt at the encrypted position; blocks (q, 4g + k) of the encrypted tile
+            const uint64_t e0 = (uint64_t)(ey * kTile + 4 * q) * (uint64_t)J.N + (uint64_t)(ex * kTile + 16 * g);
+            uint32_t dw[4][4], lw[4][4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const U4 s = stream_block(J.key, kDomainImage, (e0 + (uint64_t)i * J.N) >> 4);
+                const uint32_t ew[4] = {e[i].x, e[i].y, e[i].z, e[i].w}, sw[4] = {s.x, s.y, s.z, s.w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    dw[i][k] = ew[k] ^ sw[k];
+                    lw[i][k] = ew[k] & 0x01010101u;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t a = blk_addr((uint32_t)q, (uint32_t)(4 * g + k));
+                *reinterpret_cast<uint4 *>(dt + a) = make_uint4(dw[0][k], dw[1][k], dw[2][k], dw[3][k]);
+                *reinterpret_cast<uint4 *>(lb + a) = make_uint4(lw[0][k], lw[1][k], lw[2][k], lw[3][k]);
+            }
+            if (lane < kCodeRecord / 16) reinterpret_cast<uint4 *>(rec)[lane] = rc;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+            // this lane's original blocks (q, 4g + k), gathered and turned back
+            uint32_t ny[4], nx[4], R1[4], k0[4], k1[4];
+            block_turns4(rec, J.min_level, up, (uint32_t)q, (uint32_t)g, ny, nx, R1, k0, k1);
+            uint32_t m[4][4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t a = blk_addr(ny[k], nx[k]);
+                const uint4 wd = *reinterpret_cast<const uint4 *>(dt + a);
+                const uint4 wl = *reinterpret_cast<const uint4 *>(lb + a);
+                const uint4 f0 = *reinterpret_cast<const uint4 *>(itab + ((R1[k] * 2u) * 16u + k0[k]) * 4u);
+                const uint4 f1 = *reinterpret_cast<const uint4 *>(itab + ((R1[k] * 2u + 1u) * 16u + k1[k]) * 4u);
+                const uint32_t fs[8] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    Do[i][k] = vperm(wd.y, wd.x, fs[2 * i]) | vperm(wd.w, wd.z, fs[2 * i + 1]);
+                    const uint32_t l = vperm(wl.y, wl.x, fs[2 * i]) | vperm(wl.w, wl.z, fs[2 * i + 1]);
+                    m[i][k] = __builtin_amdgcn_udot4(l, 0x08040201u, 0u, false);   // label pattern
+                }
+            }
+            if (tx == 0 && g == 0) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) m[i][0] |= 1u;   // column 0 has no left neighbour
+            }
+            // per row: the lane's last labelled value, then a scan over the four lanes of the row
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                uint32_t f = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    sel[i][k] = gtab[m[i][k]];
+                    f = vperm(Do[i][k], f, sel[i][k]);
+                }
+                const uint32_t any = m[i][0] | m[i][1] | m[i][2] | m[i][3];
+                uint32_t v = any ? ((f >> 24) | 0x100u) : 0u;
+                uint32_t p = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x90, 0xF, 0xF, false);   // lane g-1 (0: itself)
+                v = v ? v : p;
+                p = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x44, 0xF, 0xF, false);            // lane g-2 (0, 1: themselves)
+                v = v ? v : p;
+                const uint32_t x = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x90, 0xF, 0xF, false);
+                excl[i] = g == 0 ? 0u : x;
+                tsum[i] = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xFF, 0xF, 0xF, false);      // lane 3
+            }
+            if (g == 0)
+                *reinterpret_cast<uint2 *>(&sums[slot][wave][4 * q]) =
+                    make_uint2(tsum[0] | (tsum[1] << 16), tsum[2] | (tsum[3] << 16));
+        }
+        __syncthreads();
+        if (have) {
+            const Job &J = jobs[j];
+            const int b = J.fixed_b > 0 ? J.fixed_b : (int)bq;
+            const uint32_t mrep = ((0xFFu << (8 - b)) & 0xFFu) * 0x01010101u;   // replaceable bits, every byte
+            const uint2 cw = *reinterpret_cast<const uint2 *>(&carry[slot][half][4 * q]);
+            const uint32_t cr[4] = {cw.x & 0xFFFFu, cw.x >> 16, cw.y & 0xFFFFu, cw.y >> 16};
+            uint32_t lf[4] = {0, 0, 0, 0};
+            if (side) {
+                const uint2 lw2 = *reinterpret_cast<const uint2 *>(&sums[slot][wave - 1][4 * q]);
+                lf[0] = lw2.x & 0xFFFFu;
+                lf[1] = lw2.x >> 16;
+                lf[2] = lw2.y & 0xFFFFu;
+                lf[3] = lw2.y >> 16;
+            }
+            uint32_t nc[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t from_left = first ? 0u : cr[i];           // into the quad
+                const uint32_t tin = lf[i] ? lf[i] : from_left;          // into this tile
+                const uint32_t cin = excl[i] ? excl[i] : tin;            // into this lane
+                nc[i] = tsum[i] ? tsum[i] : tin;                         // out of this tile
+                uint32_t f = (cin & 0xFFu) << 24;
+                uint32_t o[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    f = vperm(Do[i][k], f, sel[i][k]);
+                    o[k] = (f & mrep) | (Do[i][k] & ~mrep);
+                }
+                const uint64_t oidx = (uint64_t)(ty * kTile + 4 * q + i) * (uint64_t)J.N + (uint64_t)(tx * kTile + 16 * g);
+                gstore<uint4>(J.out + oidx, make_uint4(o[0], o[1], o[2], o[3]));
+            }
+            if (side && g == 0)
+                *reinterpret_cast<uint2 *>(&carry[slot ^ 1u][half][4 * q]) =
+                    make_uint2(nc[0] | (nc[1] << 16), nc[2] | (nc[3] << 16));
+        }
+        u = u1;
+        c = c1;
+        u1 = u2;
+        c1 = c2;
+    }
+}
+
 // ---- launchers ---------------------------------------------------------------
 // Workgroups of a persistent launch: what fits on the device at once (or the
 // caller's cap), never more than there are units.
@@ -868,7 +1105,7 @@ void launch_recover_bands(const Launch &L, uint32_t units, int method) {
     const uint32_t *UJ = L.ujob[UNIT_BAND];
     const dim3 bl(kThreads);
     if (method == RDHEI_EMR)
-        hipLaunchKernelGGL(k_recover_band_emr, dim3(persistent_grid(L, k_recover_band_emr, units)), bl, 0, L.stream,
+        hipLaunchKernelGGL(k_recover_quad_emr, dim3(persistent_grid(L, k_recover_quad_emr, units)), bl, 0, L.stream,
                            L.jobs, L.njobs, L.ws, units, UJ);
     else
         hipLaunchKernelGGL(k_recover_band<RDHEI_LMR>, dim3(persistent_grid(L, k_recover_band<RDHEI_LMR>, units)), bl, 0,

@@ -89,5 +89,43 @@ constexpr Tables make_tables() {
 constexpr Tables kTables = make_tables();
 constexpr int kWords = (int)(sizeof(Tables) / sizeof(uint32_t));   // 96
 
+// The inverse as one step: the whole-block turn by -R1 and the negated
+// level-1 turns composed, so that row 2h + Y of the source block is
+//   vperm(w1, w0, c) | vperm(w3, w2, d),  (c, d) = inv[R1][h][k][2Y], [2Y + 1],
+// with k the level-1 codes (left + 4 right) of row pair h.  Every selector
+// byte of c or d is either a byte of the composed move or 0x0C, and exactly
+// one of the two is not 0x0C.
+struct InvTables {
+    uint32_t inv[4][2][16][4];
+};
+
+constexpr InvTables make_inv_tables() {
+    const Tables t = make_tables();
+    InvTables f{};
+    for (uint32_t R1 = 0; R1 < 4; ++R1) {
+        const uint32_t r = (4u - R1) & 3u;
+        for (uint32_t h = 0; h < 2; ++h)
+            for (uint32_t k = 0; k < 16; ++k)
+                for (uint32_t Y = 0; Y < 2; ++Y) {
+                    const uint32_t s = t.sub_inv[k][Y];
+                    uint32_t c = 0, d = 0;
+                    for (uint32_t J = 0; J < 4; ++J) {
+                        const uint32_t sj = (s >> (8 * J)) & 0xFFu;      // byte of t[2h] (0..3) or t[2h+1] (4..7)
+                        const uint32_t I = 2 * h + (sj >> 2), jj = sj & 3u;
+                        const uint32_t a = (t.whole[r][2 * I] >> (8 * jj)) & 0xFFu;
+                        const uint32_t b = (t.whole[r][2 * I + 1] >> (8 * jj)) & 0xFFu;
+                        c |= a << (8 * J);
+                        d |= b << (8 * J);
+                    }
+                    f.inv[R1][h][k][2 * Y] = c;
+                    f.inv[R1][h][k][2 * Y + 1] = d;
+                }
+    }
+    return f;
+}
+
+constexpr InvTables kInvTables = make_inv_tables();
+constexpr int kInvWords = (int)(sizeof(InvTables) / sizeof(uint32_t));   // 512
+
 }  // namespace perm4
 }  // namespace rdhei

@@ -1,7 +1,8 @@
 // Host check of the 4x4 block permute selectors: a CPU model of v_perm_b32
 // applied with the tables must move every pixel where the bit-pair turn rule
 // sends it, for every R1 and every set of four level-1 codes, and the inverse
-// sequence must restore the block.
+// sequence must restore the block, both as two steps and as the composed
+// one-step selectors.
 #include <cstdio>
 #include <cstdint>
 #include "../../paper_2302_07992_amd/csrc/perm4.hpp"
@@ -70,6 +71,18 @@ int main() {
             inverse(out, R1, c, back);
             for (int i = 0; i < 4; ++i)
                 if (back[i] != w[i]) ++bad;
+            for (int h = 0; h < 2; ++h) {
+                const uint32_t kk = c[2 * h] + 4 * c[2 * h + 1];
+                for (int Y = 0; Y < 2; ++Y) {
+                    const uint32_t cs = kInvTables.inv[R1][h][kk][2 * Y], ds = kInvTables.inv[R1][h][kk][2 * Y + 1];
+                    for (int J = 0; J < 4; ++J) {   // exactly one of the two selectors picks each byte
+                        const bool cz = ((cs >> (8 * J)) & 0xFFu) == 0x0Cu, dz = ((ds >> (8 * J)) & 0xFFu) == 0x0Cu;
+                        if (cz == dz) ++bad;
+                    }
+                    const uint32_t row = vperm(out[1], out[0], cs) | vperm(out[3], out[2], ds);
+                    if (row != w[2 * h + Y]) ++bad;
+                }
+            }
             ++cases;
         }
     printf("cases %d mismatches %d\n", cases, bad);
