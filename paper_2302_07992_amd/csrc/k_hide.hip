@@ -39,7 +39,7 @@ __device__ __forceinline__ HideParams hide_params(const Job &J) {
     h.shift = (uint32_t)(8 - b);
     const int64_t cap = m->capacity_bits;
     h.nbits = J.nbits < 0 ? cap : J.nbits;
-    h.ok = (m->status == RDHEI_OK) && h.nbits <= cap;
+    h.ok = (m->status == RDHEI_OK) && h.nbits <= cap && h.rep >= 1 && h.rep <= 7;
     h.rep = uni(h.rep);
     h.shift = uni(h.shift);
     h.nbits = (int64_t)uni64((uint64_t)h.nbits);
@@ -69,13 +69,13 @@ __device__ __forceinline__ uint32_t redundant16(const Job &J, uint4 px, uint64_t
     uint32_t m = 0;
     if (pos >= total) return 0u;
     if (J.method == RDHEI_EMR) {
-        // LSB 0 -> redundant: gather the inverted LSB of each byte
-        const uint32_t w[4] = {~px.x & 0x01010101u, ~px.y & 0x01010101u, ~px.z & 0x01010101u, ~px.w & 0x01010101u};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t v = w[q] * 0x01020408u;   // byte k's bit -> bit 24 + k
-            m |= ((v >> 24) & 0xFu) << (4 * q);
-        }
+        // LSB 0 -> redundant: the inverted LSBs of the bytes, weighted by their
+        // bit position with 4-byte dot products
+        const uint32_t lo = __builtin_amdgcn_udot4(
+            ~px.y & 0x01010101u, 0x80402010u, __builtin_amdgcn_udot4(~px.x & 0x01010101u, 0x08040201u, 0u, false), false);
+        const uint32_t hi = __builtin_amdgcn_udot4(
+            ~px.w & 0x01010101u, 0x80402010u, __builtin_amdgcn_udot4(~px.z & 0x01010101u, 0x08040201u, 0u, false), false);
+        m = lo | (hi << 8);
     } else {
         const uint32_t be = ((uint32_t)J.lbits[pos >> 3] << 8) | (pos + 8 < total ? J.lbits[(pos >> 3) + 1] : 0xFFu);
 #pragma unroll
@@ -470,18 +470,26 @@ __device__ __forceinline__ void extract_unit(const Job &J, const HideParams &hp,
     }
     __syncthreads();
     uint32_t *msgw = reinterpret_cast<uint32_t *>(J.msg);
-    for (int64_t q = tid; q < W1 - W0; q += kThreads) {
-        const int64_t w = W0 + q;
-        const uint32_t own = be_mask(w, wstart, wend);
-        const uint32_t v = (win[q] ^ ks_word(J.key, w)) & own;
-        if (own == 0xFFFFFFFFu) {
-            gstore<uint32_t>(msgw + w, __builtin_bswap32(v));
-        } else {
-            PartWord pw;
-            pw.word = w;
-            pw.bits = __builtin_bswap32(v);
-            pw.job = (uint32_t)j;
-            part[2 * u + (w == W0 ? 0 : 1)] = pw;
+    // one keystream block per four message words
+    const int64_t B0 = W0 >> 2, B1 = (W1 - 1) >> 2;
+    for (int64_t bq = tid; bq <= B1 - B0; bq += kThreads) {
+        const U4 ks = stream_block(J.key, kDomainMessage, (uint64_t)(B0 + bq));
+        const uint32_t kw[4] = {ks.x, ks.y, ks.z, ks.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t w = 4 * (B0 + bq) + i;
+            if (w < W0 || w >= W1) continue;
+            const uint32_t own = be_mask(w, wstart, wend);
+            const uint32_t v = (win[w - W0] ^ __builtin_bswap32(kw[i])) & own;
+            if (own == 0xFFFFFFFFu) {
+                gstore<uint32_t>(msgw + w, __builtin_bswap32(v));
+            } else {
+                PartWord pw;
+                pw.word = w;
+                pw.bits = __builtin_bswap32(v);
+                pw.job = (uint32_t)j;
+                part[2 * u + (w == W0 ? 0 : 1)] = pw;
+            }
         }
     }
 }
@@ -523,66 +531,84 @@ __global__ void k_extract_fix(const Job *__restrict__ jobs, const PartWord *__re
 }
 
 
-// ---- whole images, one workgroup each ---------------------------------------
-// Images of at most kSeqMaxSeg segments are walked segment by segment by one
-// workgroup: the rank carries over in registers, the next segment's pixels are
-// loaded while the current one is processed, and no other workgroup is waited
-// on.  Larger images use the look-back kernels above.
+// ---- whole images, one wave each ----------------------------------------------
+// Images of at most kSeqMaxSeg look-back segments, in batches large enough to
+// fill the device, are walked by one wave each, 4096 pixels per step: the
+// rank carries over in registers, the next step's pixels are loaded while the
+// current one is processed, ranks inside a step come from a wave scan (DPP),
+// and nothing waits on another wave.  Larger images and small batches use the
+// look-back kernels above.
 constexpr int kSeqMaxSeg = 64;
+constexpr int kWLoads = 4;                                           // 16-byte loads per lane
+constexpr uint64_t kWSegPx = 64ull * 16 * kWLoads;                   // 4096 pixels
+constexpr int kWWinWords = (int)((kWSegPx * 7 + 127) / 128 + 1) * 4 + 8;
 
-// Pixels of one segment.  Whole-image hiding is used only for images whose
+// Inclusive sum over the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);    // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);    // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);    // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true);    // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);   // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);   // row_bcast:31
+    return x;
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Pixels of one step.  Whole-image hiding is used only for images whose
 // pixel count is a multiple of 16, so every 16-byte piece is in or out.
-__device__ __forceinline__ void seg_load(const uint8_t *img, uint64_t s0, uint64_t s1, uint4 px[kSegLoads]) {
-    const int tid = threadIdx.x;
+__device__ __forceinline__ void wseg_load(const uint8_t *img, uint64_t s0, uint64_t s1, int lane, uint4 px[kWLoads]) {
 #pragma unroll
-    for (int k = 0; k < kSegLoads; ++k) {
-        const uint64_t pos = s0 + (uint64_t)k * (kThreads * 16) + 16 * (uint64_t)tid;
+    for (int k = 0; k < kWLoads; ++k) {
+        const uint64_t pos = s0 + (uint64_t)k * 1024u + 16 * (uint64_t)lane;
         px[k] = pos < s1 ? gload<uint4>(img + pos) : make_uint4(0x01010101u, 0x01010101u, 0x01010101u, 0x01010101u);
     }
 }
 
 template <bool EMBED>
-__device__ __forceinline__ void hide_image(const Job &J, const HideParams &hp, uint64_t *sh, uint32_t *win,
-                                           const uint32_t *htab) {
-    const int tid = threadIdx.x;
+__device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &hp, uint32_t *win, const uint32_t *htab) {
+    const int lane = threadIdx.x & 63;
     const uint8_t *img = EMBED ? J.out : J.in;
     const uint64_t total = (uint64_t)J.M * (uint64_t)J.N;
-    const uint32_t nseg = (uint32_t)((total + kSegPx - 1) / kSegPx);
+    const uint32_t nseg = (uint32_t)((total + kWSegPx - 1) / kWSegPx);
     const uint32_t rep = hp.rep;
     const Hide4 hk = hide4_params(hp);
     uint64_t rank = 0;
-    uint32_t carry = 0;          // extraction: bits of the partial word left by the previous segment
+    uint32_t carry = 0;          // extraction: bits of the partial word left by the previous step
     int64_t carry_word = -1;
-    uint4 nxt[kSegLoads];
-    seg_load(img, 0, total < kSegPx ? total : kSegPx, nxt);
+    uint4 nxt[kWLoads];
+    wseg_load(img, 0, total < kWSegPx ? total : kWSegPx, lane, nxt);
     for (uint32_t seg = 0; seg < nseg; ++seg) {
-        const uint64_t s0 = (uint64_t)seg * kSegPx;
-        const uint64_t s1 = s0 + kSegPx < total ? s0 + kSegPx : total;
-        uint4 px[kSegLoads];
+        const uint64_t s0 = (uint64_t)seg * kWSegPx;
+        const uint64_t s1 = s0 + kWSegPx < total ? s0 + kWSegPx : total;
+        uint4 px[kWLoads];
 #pragma unroll
-        for (int k = 0; k < kSegLoads; ++k) px[k] = nxt[k];
-        {   // the next segment's pixels (the last segment reloads itself)
+        for (int k = 0; k < kWLoads; ++k) px[k] = nxt[k];
+        {   // the next step's pixels (the last step reloads itself)
             const uint32_t ns = seg + 1 < nseg ? seg + 1 : seg;
-            const uint64_t n0 = (uint64_t)ns * kSegPx;
-            seg_load(img, n0, n0 + kSegPx < total ? n0 + kSegPx : total, nxt);
+            const uint64_t n0 = (uint64_t)ns * kWSegPx;
+            wseg_load(img, n0, n0 + kWSegPx < total ? n0 + kWSegPx : total, lane, nxt);
         }
-        uint32_t rm[kSegLoads];
-        uint64_t packed = 0;
+        uint32_t rm[kWLoads];
 #pragma unroll
-        for (int k = 0; k < kSegLoads; ++k) {
-            const uint64_t pos = s0 + (uint64_t)k * (kThreads * 16) + 16 * (uint64_t)tid;
-            rm[k] = redundant16(J, px[k], pos, s1);
-            packed |= (uint64_t)__popc(rm[k]) << (16 * k);
-        }
-        uint64_t tot;
-        const uint64_t ex = block_scan4(packed, tot, sh);
-        uint32_t lr[kSegLoads], cbase = 0;      // local rank (within the segment) of the thread's first pixel of load k
-#pragma unroll
-        for (int k = 0; k < kSegLoads; ++k) {
-            lr[k] = cbase + (uint32_t)((ex >> (16 * k)) & 0xFFFFu);
-            cbase += (uint32_t)((tot >> (16 * k)) & 0xFFFFu);
-        }
-        const uint32_t T = uni(cbase);
+        for (int k = 0; k < kWLoads; ++k)
+            rm[k] = redundant16(J, px[k], s0 + (uint64_t)k * 1024u + 16 * (uint64_t)lane, s1);
+        // ranks: counts of loads 0, 1 and 2, 3 in 16-bit halves (at most 1024 each)
+        const uint32_t c01 = (uint32_t)__popc(rm[0]) | ((uint32_t)__popc(rm[1]) << 16);
+        const uint32_t c23 = (uint32_t)__popc(rm[2]) | ((uint32_t)__popc(rm[3]) << 16);
+        const uint32_t i01 = wave_scan_incl(c01), i23 = wave_scan_incl(c23);
+        const uint32_t t01 = uni((uint32_t)__builtin_amdgcn_readlane((int)i01, 63));
+        const uint32_t t23 = uni((uint32_t)__builtin_amdgcn_readlane((int)i23, 63));
+        const uint32_t e01 = i01 - c01, e23 = i23 - c23;
+        const uint32_t tot0 = t01 & 0xFFFFu, tot1 = t01 >> 16, tot2 = t23 & 0xFFFFu, tot3 = t23 >> 16;
+        const uint32_t lr[kWLoads] = {e01 & 0xFFFFu, tot0 + (e01 >> 16), tot0 + tot1 + (e23 & 0xFFFFu),
+                                      tot0 + tot1 + tot2 + (e23 >> 16)};
+        const uint32_t T = tot0 + tot1 + tot2 + tot3;
         const int64_t wstart = (int64_t)(rank * rep);
         if (wstart >= hp.nbits) break;
         int64_t wend = (int64_t)((rank + T) * rep);
@@ -592,51 +618,59 @@ __device__ __forceinline__ void hide_image(const Job &J, const HideParams &hp, u
             // window bits relative to the first staged 16-byte block
             const int64_t fb = wstart >> 7, lb = (wend - 1) >> 7;
             const uint32_t off0 = (uint32_t)(wstart - (fb << 7)), rend = (uint32_t)(wend - (fb << 7));
-            for (int64_t q = tid; q <= lb - fb; q += kThreads) {
+            for (int64_t q = lane; q <= lb - fb; q += 64) {
                 const uint64_t blk = (uint64_t)(fb + q);
                 const uint4 mv = gload<uint4>(J.msg + 16 * blk);
                 const U4 ks = stream_block(J.key, kDomainMessage, blk);
-                uint32_t *wp = win + 1 + 4 * q;   // word 0 is a guard
-                wp[0] = __builtin_bswap32(mv.x ^ ks.x);
-                wp[1] = __builtin_bswap32(mv.y ^ ks.y);
-                wp[2] = __builtin_bswap32(mv.z ^ ks.z);
-                wp[3] = __builtin_bswap32(mv.w ^ ks.w);
+                *reinterpret_cast<uint4 *>(win + 4 + 4 * q) =
+                    make_uint4(__builtin_bswap32(mv.x ^ ks.x), __builtin_bswap32(mv.y ^ ks.y),
+                               __builtin_bswap32(mv.z ^ ks.z), __builtin_bswap32(mv.w ^ ks.w));
             }
-            __syncthreads();
+            wave_sync();
 #pragma unroll
-            for (int k = 0; k < kSegLoads; ++k) {
+            for (int k = 0; k < kWLoads; ++k) {
                 const uint32_t rel = off0 + lr[k] * rep;
                 if (!rm[k] || rel >= rend) continue;
                 uint32_t w[4] = {px[k].x, px[k].y, px[k].z, px[k].w};
-                embed16(w, rm[k], rel, rend, win, hk, htab);
-                gstore<uint4>(J.out + s0 + (uint64_t)k * (kThreads * 16) + 16 * (uint64_t)tid,
-                              make_uint4(w[0], w[1], w[2], w[3]));
+                embed16(w, rm[k], rel, rend, win + 3, hk, htab);   // word 0 of the window is a guard
+                gstore<uint4>(J.out + s0 + (uint64_t)k * 1024u + 16 * (uint64_t)lane, make_uint4(w[0], w[1], w[2], w[3]));
             }
+            wave_sync();
         } else if (T > 0) {
             const int64_t W0 = wstart >> 5, W1 = (wend + 31) >> 5;
             const uint32_t off0 = (uint32_t)(wstart & 31), rend = (uint32_t)(wend - 32 * W0);
-            for (int64_t q = tid; q < W1 - W0 + 1; q += kThreads) win[q] = (q == 0 && carry_word == W0) ? carry : 0u;
-            __syncthreads();
+            for (int64_t q = lane; q < W1 - W0 + 1; q += 64) win[q] = (q == 0 && carry_word == W0) ? carry : 0u;
+            wave_sync();
 #pragma unroll
-            for (int k = 0; k < kSegLoads; ++k) {
+            for (int k = 0; k < kWLoads; ++k) {
                 const uint32_t rel = off0 + lr[k] * rep;
                 if (!rm[k] || rel >= rend) continue;
                 const uint32_t w[4] = {px[k].x, px[k].y, px[k].z, px[k].w};
                 extract16(w, rm[k], rel, rend, win, hk, htab);
             }
-            __syncthreads();
-            // complete words go out; a trailing partial word waits for the next segment
+            wave_sync();
+            // complete words go out; a trailing partial word waits for the next step
             const bool partial = (wend & 31) != 0;
             const int64_t nstore = partial ? (W1 - 1 - W0) : (W1 - W0);
             uint32_t *msgw = reinterpret_cast<uint32_t *>(J.msg);
-            for (int64_t q = tid; q < nstore; q += kThreads)
-                gstore<uint32_t>(msgw + W0 + q, __builtin_bswap32(win[q] ^ ks_word(J.key, W0 + q)));
+            if (nstore > 0) {   // one keystream block per four message words
+                const int64_t B0 = W0 >> 2, B1 = (W0 + nstore - 1) >> 2;
+                for (int64_t bq = lane; bq <= B1 - B0; bq += 64) {
+                    const U4 ks = stream_block(J.key, kDomainMessage, (uint64_t)(B0 + bq));
+                    const uint32_t kw[4] = {ks.x, ks.y, ks.z, ks.w};
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int64_t w = 4 * (B0 + bq) + i;
+                        if (w >= W0 && w < W0 + nstore) gstore<uint32_t>(msgw + w, __builtin_bswap32(win[w - W0]) ^ kw[i]);
+                    }
+                }
+            }
             carry_word = partial ? W1 - 1 : -1;
             carry = partial ? uni(win[W1 - 1 - W0]) : 0u;
+            wave_sync();
         }
-        __syncthreads();
     }
-    if (!EMBED && carry_word >= 0 && tid == 0) {
+    if (!EMBED && carry_word >= 0 && lane == 0) {
         // the message's last word: bits past nbits are stored as zero
         const uint32_t own = be_mask(carry_word, 0, hp.nbits);
         gstore<uint32_t>(reinterpret_cast<uint32_t *>(J.msg) + carry_word,
@@ -644,26 +678,26 @@ __device__ __forceinline__ void hide_image(const Job &J, const HideParams &hp, u
     }
 }
 
+// One wave per workgroup, one image per wave (a grid-stride loop when the grid
+// is capped).
 template <bool EMBED>
-__global__ __launch_bounds__(kThreads) void k_hide_seq(const Job *__restrict__ jobs, int njobs, uint32_t units,
-                                                        const uint32_t *__restrict__ ujob) {
-    __shared__ uint64_t sh[kThreads / 64];
-    __shared__ uint32_t win[kWinWords];
+__global__ __launch_bounds__(64) void k_hide_wave(const Job *__restrict__ jobs, int njobs, uint32_t units,
+                                                  const uint32_t *__restrict__ ujob) {
+    __shared__ __align__(16) uint32_t win[kWWinWords];
     __shared__ uint32_t htab[hide4::kWords];
-    const int tid = threadIdx.x;
-    stage_hide_tables(htab, tid);   // read after the first scan barrier
-    const uint32_t per = (units + gridDim.x - 1) / gridDim.x;
-    const uint32_t u0 = blockIdx.x * per, u1 = u0 + per < units ? u0 + per : units;
-    for (uint32_t u = u0; u < u1; ++u) {
+    const int lane = threadIdx.x;
+    if (lane < hide4::kWords) htab[lane] = reinterpret_cast<const uint32_t *>(&kHideTables)[lane];
+    wave_sync();
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
         const int j = (int)uni((uint32_t)find_job<UNIT_IMG>(jobs, njobs, u, ujob));
         const Job &J = jobs[j];
         const HideParams hp = hide_params(J);
         if (!hp.ok) {
-            if (tid == 0 && J.meta->status == RDHEI_OK) J.meta->status = RDHEI_ECAPACITY;
+            if (lane == 0 && J.meta->status == RDHEI_OK) J.meta->status = RDHEI_ECAPACITY;
         } else {
-            hide_image<EMBED>(J, hp, sh, win, htab);
+            hide_image_wave<EMBED>(J, hp, win, htab);
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 
@@ -674,47 +708,31 @@ static inline unsigned grid_for(const Launch &L, uint32_t units) {
     return g ? g : 1;
 }
 
-template <typename K>
-static unsigned resident_grid(const Launch &L, K kernel, uint32_t units) {
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (cus <= 0) cus = 1;
-    }
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess || per_cu < 1)
-        per_cu = 1;
-    uint32_t g = (uint32_t)cus * (uint32_t)per_cu;
-    if (L.max_grid > 0) g = (uint32_t)L.max_grid;
-    if (g > units) g = units;
-    return g ? g : 1;
-}
-
 void launch_hide_images(const Launch &L, uint32_t units, bool embed) {
     if (!units) return;
+    const unsigned g = grid_for(L, units);
     if (embed)
-        hipLaunchKernelGGL(k_hide_seq<true>, dim3(resident_grid(L, k_hide_seq<true>, units)), dim3(kThreads), 0,
-                           L.stream, L.jobs, L.njobs, units, L.ujob[UNIT_IMG]);
+        hipLaunchKernelGGL(k_hide_wave<true>, dim3(g), dim3(64), 0, L.stream, L.jobs, L.njobs, units, L.ujob[UNIT_IMG]);
     else
-        hipLaunchKernelGGL(k_hide_seq<false>, dim3(resident_grid(L, k_hide_seq<false>, units)), dim3(kThreads), 0,
-                           L.stream, L.jobs, L.njobs, units, L.ujob[UNIT_IMG]);
+        hipLaunchKernelGGL(k_hide_wave<false>, dim3(g), dim3(64), 0, L.stream, L.jobs, L.njobs, units, L.ujob[UNIT_IMG]);
 }
 
 int seq_max_segments() { return kSeqMaxSeg; }
 
-// Batches of at least this many small images hide one image per workgroup:
-// twice the workgroups of k_hide_seq resident on the device, so the
-// sequential walk of each image is hidden behind the others.  Smaller
-// batches (and single images) take the segment path, whose latency per image
-// is a few segments deep.
+// Batches of at least this many small images hide one image per wave: a
+// quarter of the waves of k_hide_wave resident on the device, so that the
+// walks of the images overlap.  Smaller batches (and single images) take the
+// segment path, whose latency per image is a few segments deep.
 uint32_t whole_image_min() {
     static uint32_t v = 0;
     if (!v) {
-        Launch L;
-        L.max_grid = 0;
-        v = 2u * resident_grid(L, k_hide_seq<true>, 0xffffffffu);
+        int dev = 0, cus = 0, per_cu = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_hide_wave<true>, 64, 0) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        v = (uint32_t)(cus > 0 ? cus : 1) * (uint32_t)per_cu / 4u;
+        if (v < 1) v = 1;
     }
     return v;
 }

@@ -1,6 +1,6 @@
 // Tiled fast path (M, N multiples of 64): keystream code pyramid + label
 // statistics, per-image finalisation (optimal b, upper rotation levels), the
-// permuting encryption, and the band-sequential recovery.
+// permuting encryption, and the recovery (EMR by 2x2 tile quads, LMR by bands).
 //
 // The tile kernels are persistent: each workgroup owns a contiguous range of
 // work units (tiles of one image stay on one workgroup, hence on one XCD and
@@ -12,6 +12,14 @@ namespace rdhei {
 
 // LDS row stride of a 64-byte tile row (keeps 16-byte alignment).
 constexpr int kRow = kTile + 16;
+
+// Byte offset of 4x4 block (by, bx) in a wave's tile of blocks: 16 bytes per
+// block, 16 blocks per block row, columns swizzled so that the writes of
+// lanes (q, g) and (q + 1, g) fall in different banks.
+__device__ __forceinline__ uint32_t blk_addr(uint32_t by, uint32_t bx) {
+    const uint32_t sw = (((bx >> 3) & 1u) << 1) ^ (by & 1u);
+    return by * 256u + ((bx ^ sw) << 4);
+}
 
 // Contiguous unit range [u0, u1) of this workgroup.
 __device__ __forceinline__ void unit_range(uint32_t units, uint32_t &u0, uint32_t &u1) {
@@ -355,7 +363,7 @@ __global__ __launch_bounds__(kThreads) void k_encrypt_tile(const Job *__restrict
                                                             uint8_t *__restrict__ ws, uint32_t units,
                                                             const uint32_t *__restrict__ ujob) {
     constexpr int kW = kThreads / 64;
-    __shared__ __align__(16) uint8_t dsts[kW][kTile * kRow];    // per wave: the destination tile
+    __shared__ __align__(16) uint8_t dsts[kW][kTile * kTile];   // per wave: the destination tile, 4x4 blocks
     __shared__ __align__(16) uint8_t recs[kW][kCodeRecord];     // per wave: the tile's code record
     __shared__ __align__(16) uint32_t ptab[perm4::kWords];
     const int lane = threadIdx.x & 63, wave = (int)uni(threadIdx.x >> 6);   // wave-uniform
@@ -455,17 +463,21 @@ __global__ __launch_bounds__(kThreads) void k_encrypt_tile(const Job *__restrict
             const uint32_t w[4] = {o[0][k], o[1][k], o[2][k], o[3][k]};
             uint32_t ob[4];
             block_forward(ptab, R1[k], k0[k], k1[k], w, ob);
-#pragma unroll
-            for (int uu = 0; uu < 4; ++uu)
-                *reinterpret_cast<uint32_t *>(dst + (4 * ny[k] + uu) * kRow + 4 * nx[k]) = ob[uu];
+            *reinterpret_cast<uint4 *>(dst + blk_addr(ny[k], nx[k])) = make_uint4(ob[0], ob[1], ob[2], ob[3]);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
+        // the lane's destination blocks (q, 4g + k): row i of the strip is row i of each
+        uint4 db[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) db[k] = *reinterpret_cast<const uint4 *>(dst + blk_addr((uint32_t)q, (uint32_t)(4 * g + k)));
+        const uint32_t rows[4][4] = {{db[0].x, db[1].x, db[2].x, db[3].x}, {db[0].y, db[1].y, db[2].y, db[3].y},
+                                     {db[0].z, db[1].z, db[2].z, db[3].z}, {db[0].w, db[1].w, db[2].w, db[3].w}};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const uint4 qv = *reinterpret_cast<const uint4 *>(dst + (4 * q + i) * kRow + 16 * g);
+            const uint4 qv = make_uint4(rows[i][0], rows[i][1], rows[i][2], rows[i][3]);
             const uint64_t didx = (uint64_t)(dy * kTile + 4 * q + i) * (uint64_t)J.N + (uint64_t)(dx * kTile + 16 * g);
             if (MODE == ENC_LMR_MAPS) {
                 // bit planes, MSB-first: pixel didx+k -> byte (didx+k)/8, bit 7-(k%8)
@@ -662,134 +674,6 @@ __global__ __launch_bounds__(kThreads) void k_recover_band(const Job *__restrict
 }
 
 // ----------------------------------------------------------------------------
-// EMR recovery of row bands of tiles (Sec. III-A decoding with K1), byte-wise:
-// each tile is decrypted at its rotated position (full XOR, so the recovered
-// LSB is the decrypted one), its labels l (the LSBs of the marked image) are
-// kept as a second byte plane, and both planes are moved back to the original
-// positions with 4x4 block permutes.  The recovery glide (a pixel labelled 0
-// takes the replaceable b MSBs of the nearest pixel to its left labelled 1;
-// column 0 always counts as labelled) runs four pixels per word: a doubling
-// fill inside each word, a scan over the four segments of a tile row
-// (lanes of one quad), and a carry along the row from tile to tile.
-// ----------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_recover_band_emr(const Job *__restrict__ jobs, int njobs,
-                                                               uint8_t *__restrict__ ws, uint32_t units,
-                                                               const uint32_t *__restrict__ ujob) {
-    __shared__ __align__(16) uint8_t srcD[kTile * kRow];
-    __shared__ __align__(16) uint8_t srcL[kTile * kRow];
-    __shared__ __align__(16) uint8_t dstD[kTile * kRow];
-    __shared__ __align__(16) uint8_t dstL[kTile * kRow];
-    __shared__ __align__(16) uint8_t rec[kCodeRecord];
-    __shared__ __align__(16) uint32_t ptab[perm4::kWords];
-    const int tid = threadIdx.x;
-    const int r = tid >> 2, g = tid & 3;
-    const int by = tid >> 4, bx = tid & 15;
-    uint32_t u0, u1;
-    unit_range(units, u0, u1);
-    stage_perm_tables(ptab, tid);   // read after the first barrier below
-
-    uint4 e_n = make_uint4(0, 0, 0, 0), rc_n = make_uint4(0, 0, 0, 0);
-    uint32_t b_n = 0;
-    auto fetch = [&](uint32_t u, int tx) {
-        const Job &J = jobs[uni((uint32_t)find_job<UNIT_BAND>(jobs, njobs, u, ujob))];
-        const int ty = (int)(u - J.ubase[UNIT_BAND]);
-        const uint32_t t = (uint32_t)(ty * J.tiles_x + tx);
-        int ey, ex;
-        uint32_t up;
-        tmap_unpack(reinterpret_cast<const uint32_t *>(ws + J.ws_tmap)[t], ey, ex, up);
-        const uint64_t eidx = (uint64_t)(ey * kTile + r) * (uint64_t)J.N + (uint64_t)(ex * kTile + 16 * g);
-        e_n = gload<uint4>(J.in + eidx);
-        rc_n = gload<uint4>(ws + J.ws_codes + (uint64_t)t * kCodeRecord + 16 * (tid % (kCodeRecord / 16)));
-        b_n = (uint32_t)gload<int32_t>(&J.meta->b);
-    };
-    if (u0 < u1) fetch(u0, 0);
-
-    for (uint32_t u = u0; u < u1; ++u) {
-        const Job &J = jobs[uni((uint32_t)find_job<UNIT_BAND>(jobs, njobs, u, ujob))];
-        const int ty = (int)(u - J.ubase[UNIT_BAND]);
-        const int b = (int)uni(b_n);
-        const uint32_t mrep = ((0xFFu << (8 - b)) & 0xFFu) * 0x01010101u;   // replaceable bits, every byte
-        uint32_t crep = 0;   // replaceable bits of the last labelled pixel of this row, every byte
-        for (int tx = 0; tx < J.tiles_x; ++tx) {
-            const uint4 e = e_n, rc = rc_n;
-            const bool more = tx + 1 < J.tiles_x;
-            fetch(more ? u : (u + 1 < u1 ? u + 1 : u), more ? tx + 1 : (u + 1 < u1 ? 0 : tx));
-            int ey, ex;
-            uint32_t up;
-            tmap_unpack(reinterpret_cast<const uint32_t *>(ws + J.ws_tmap)[ty * J.tiles_x + tx], ey, ex, up);
-            const uint64_t eidx = (uint64_t)(ey * kTile + r) * (uint64_t)J.N + (uint64_t)(ex * kTile + 16 * g);
-            const U4 s = stream_block(J.key, kDomainImage, eidx >> 4);
-            *reinterpret_cast<uint4 *>(srcD + r * kRow + 16 * g) =
-                make_uint4(e.x ^ s.x, e.y ^ s.y, e.z ^ s.z, e.w ^ s.w);
-            *reinterpret_cast<uint4 *>(srcL + r * kRow + 16 * g) =
-                make_uint4(e.x & 0x01010101u, e.y & 0x01010101u, e.z & 0x01010101u, e.w & 0x01010101u);
-            if (tid < kCodeRecord / 16) reinterpret_cast<uint4 *>(rec)[tid] = rc;
-            __syncthreads();
-
-            // this thread's original 4x4 block sits whole at its destination block
-            uint32_t ny, nx, R1, k0, k1;
-            block_turns(rec, J.min_level, up, (uint32_t)by, (uint32_t)bx, ny, nx, R1, k0, k1);
-            const InvSel S = inverse_selectors(ptab, R1, k0, k1);
-            uint32_t wd[4], wl[4], od[4], ol[4];
-#pragma unroll
-            for (int uu = 0; uu < 4; ++uu) {
-                wd[uu] = *reinterpret_cast<const uint32_t *>(srcD + (4 * ny + uu) * kRow + 4 * nx);
-                wl[uu] = *reinterpret_cast<const uint32_t *>(srcL + (4 * ny + uu) * kRow + 4 * nx);
-            }
-            block_inverse(S, wd, od);
-            block_inverse(S, wl, ol);
-#pragma unroll
-            for (int uu = 0; uu < 4; ++uu) {
-                *reinterpret_cast<uint32_t *>(dstD + (4 * by + uu) * kRow + 4 * bx) = od[uu];
-                *reinterpret_cast<uint32_t *>(dstL + (4 * by + uu) * kRow + 4 * bx) = ol[uu];
-            }
-            __syncthreads();
-
-            const uint4 xd4 = *reinterpret_cast<const uint4 *>(dstD + r * kRow + 16 * g);
-            const uint4 xl4 = *reinterpret_cast<const uint4 *>(dstL + r * kRow + 16 * g);
-            const uint32_t xd[4] = {xd4.x, xd4.y, xd4.z, xd4.w};
-            uint32_t xl[4] = {xl4.x, xl4.y, xl4.z, xl4.w};
-            if (tx == 0 && g == 0) xl[0] |= 1u;   // column 0
-            // fill inside each word: V = replaceable bits of the last labelled
-            // pixel at or before each byte, K = bytes that have one
-            uint32_t V[4], K[4];
-            uint32_t last = 0;   // (last labelled value of this segment) | 0x100, or 0
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint32_t M = (xl[k] << 8) - xl[k];
-                uint32_t v = xd[k] & M & mrep, kk = M;
-                v |= (v << 8) & ~kk;
-                kk |= kk << 8;
-                v |= (v << 16) & ~kk;
-                kk |= kk << 16;
-                V[k] = v;
-                K[k] = kk;
-                if (kk) last = (v >> 24) | 0x100u;
-            }
-            // carry-in: nearest segment to the left in this tile row, else the row carry
-            const uint32_t c1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)last, 0x90, 0xF, 0xF, false);   // lane g-1
-            const uint32_t c2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)last, 0x40, 0xF, 0xF, false);   // lane g-2
-            const uint32_t c3 = (uint32_t)__builtin_amdgcn_mov_dpp((int)last, 0x00, 0xF, 0xF, false);   // lane g-3
-            uint32_t cin = crep;
-            if (g >= 3 && (c3 & 0x100u)) cin = vperm(c3, c3, 0);   // byte 0 in every byte
-            if (g >= 2 && (c2 & 0x100u)) cin = vperm(c2, c2, 0);
-            if (g >= 1 && (c1 & 0x100u)) cin = vperm(c1, c1, 0);
-            uint32_t outw[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint32_t v = V[k] | (cin & ~K[k]);
-                outw[k] = (xd[k] & ~mrep) | v;
-                cin = vperm(v, v, 0x03030303u);
-            }
-            // row carry for the next tile: the last segment's outgoing value
-            crep = (uint32_t)__builtin_amdgcn_mov_dpp((int)cin, 0xFF, 0xF, 0xF, false);   // lane 3 of the quad
-            const uint64_t oidx = (uint64_t)(ty * kTile + r) * (uint64_t)J.N + (uint64_t)(tx * kTile + 16 * g);
-            gstore<uint4>(J.out + oidx, make_uint4(outw[0], outw[1], outw[2], outw[3]));
-        }
-    }
-}
-
-// ----------------------------------------------------------------------------
 // EMR recovery by quads: the 2x2 tiles of tile rows 2p, 2p+1 and tile columns
 // 2c, 2c+1, one wave per tile, quads of a band pair left to right.  The four
 // tiles of a full quad form a level-7 block, so their encrypted data is one
@@ -804,13 +688,6 @@ __global__ __launch_bounds__(kThreads) void k_recover_band_emr(const Job *__rest
 // and cross tiles through LDS (left tile of a row -> right tile -> next quad),
 // with one workgroup barrier per quad.
 // ----------------------------------------------------------------------------
-// Byte offset of 4x4 block (by, bx) in a wave's tile of blocks: 16 bytes per
-// block, 16 blocks per block row, columns swizzled so that the writes of
-// lanes (q, g) and (q + 1, g) fall in different banks.
-__device__ __forceinline__ uint32_t blk_addr(uint32_t by, uint32_t bx) {
-    const uint32_t sw = (((bx >> 3) & 1u) << 1) ^ (by & 1u);
-    return by * 256u + ((bx ^ sw) << 4);
-}
 
 static __constant__ perm4::InvTables kInvTables = perm4::kInvTables;
 static __constant__ glide4::Tables kGlideTables = glide4::kTables;
