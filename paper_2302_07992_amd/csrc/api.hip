@@ -117,7 +117,7 @@ struct Layout {
     std::vector<uint32_t> ujob[UNIT_KINDS];   // job index of every work unit (batches)
     std::vector<int> per_pixel;        // jobs on the per-pixel path
     uint64_t ws_bytes = 0;
-    uint32_t units[UNIT_KINDS] = {0, 0, 0, 0};
+    uint32_t units[UNIT_KINDS] = {};
     uint64_t g_status = 0, g_ticket = 0, g_part = 0;   // hiding workspace (embed/extract)
     int op = 0;
     int method = RDHEI_EMR;
@@ -208,9 +208,16 @@ int make_layout(int op, const rdhei_job *in, int n, const LayoutOpts &opt, Layou
         // images are cut into look-back segments (UNIT_SEG)
         const bool hide = op == RDHEI_OP_EMBED || op == RDHEI_OP_EXTRACT;
         const bool whole = whole_ok && whole_eligible(op, q);
+        const bool quads = J.fast && (op == RDHEI_OP_ENCRYPT || (op == RDHEI_OP_RECOVER && q.method == RDHEI_EMR));
+        const bool bands = J.fast && op == RDHEI_OP_RECOVER && q.method == RDHEI_LMR;
         const uint32_t cnt[UNIT_KINDS] = {J.fast ? (uint32_t)(J.tiles_x * J.tiles_y) : 0u,
-                                          J.fast ? (uint32_t)(q.method == RDHEI_EMR ? (J.tiles_y + 1) / 2 : J.tiles_y) : 0u,
-                                          hide && !whole ? (uint32_t)J.nseg : 0u, whole ? 1u : 0u};
+                                          bands ? (uint32_t)J.tiles_y : 0u,
+                                          hide && !whole ? (uint32_t)J.nseg : 0u, whole ? 1u : 0u,
+                                          quads ? (uint32_t)((J.tiles_y + 1) / 2) *
+                                                      (op == RDHEI_OP_ENCRYPT
+                                                           ? (uint32_t)(((J.tiles_x + 1) / 2 + kQuadSeg - 1) / kQuadSeg)
+                                                           : 1u)
+                                                : 0u};
         for (int k = 0; k < UNIT_KINDS; ++k) {
             J.ubase[k] = L.units[k];
             J.ucount[k] = cnt[k];
@@ -242,7 +249,7 @@ std::vector<Stage> stages_of(const Layout &Ly, const uint32_t *units_in, std::ve
     const std::vector<Job> hj = Ly.jobs;
     uint32_t units[UNIT_KINDS];
     for (int k = 0; k < UNIT_KINDS; ++k) units[k] = units_in[k];
-    const uint32_t ut = units[UNIT_TILE], ub = units[UNIT_BAND], us = units[UNIT_SEG];
+    const uint32_t ut = units[UNIT_TILE], ub = units[UNIT_BAND], us = units[UNIT_SEG], uq = units[UNIT_QROW];
     const int method = Ly.method;
     std::vector<int> big;   // images finalised across many workgroups
     for (size_t i = 0; i < hj.size(); ++i)
@@ -254,7 +261,7 @@ std::vector<Stage> stages_of(const Layout &Ly, const uint32_t *units_in, std::ve
                              for (int j : pp) { launch_generic_levels(L, j, hj[j]); launch_generic_stats(L, j, hj[j]); }
                          }});
         S.push_back({"finalize_stats", [=](const Launch &L) { launch_finalize(L, true, big, hj); }});
-        if (ut) S.push_back({"encrypt_tiles", [=](const Launch &L) { launch_encrypt_tiles(L, ut, ENC_EMR); }});
+        if (uq) S.push_back({"encrypt_tiles", [=](const Launch &L) { launch_encrypt_tiles(L, uq, ENC_EMR); }});
         if (!pp.empty())
             S.push_back({"per_pixel_encrypt", [=](const Launch &L) {
                              for (int j : pp) launch_generic_encrypt(L, j, hj[j], ENC_EMR);
@@ -266,7 +273,8 @@ std::vector<Stage> stages_of(const Layout &Ly, const uint32_t *units_in, std::ve
                              for (int j : pp) launch_generic_levels(L, j, hj[j]);
                          }});
         if (ut) S.push_back({"finalize_pyramid", [=](const Launch &L) { launch_finalize(L, false, big, hj); }});
-        if (ub) S.push_back({"recover_bands", [=](const Launch &L) { launch_recover_bands(L, ub, method); }});
+        const uint32_t urec = method == RDHEI_EMR ? uq : ub;
+        if (urec) S.push_back({"recover_bands", [=](const Launch &L) { launch_recover_bands(L, urec, method); }});
         if (!pp.empty())
             S.push_back({"per_pixel_recover", [=](const Launch &L) {
                              for (int j : pp) launch_generic_recover(L, j, hj[j]);
@@ -503,7 +511,7 @@ int lmr_encrypt(rdhei_ctx *ctx, const uint8_t *d_img, uint8_t *d_enc, int32_t M,
         J.msg = d_eta;
         Ly.jobs[0] = J;
         HIPCHK(hipMemcpyAsync(ctx->jobs.p, &Ly.jobs[0], sizeof(Job), hipMemcpyHostToDevice, st));
-        if (J.fast) launch_encrypt_tiles(L, Ly.units[UNIT_TILE], ENC_LMR_MAPS);
+        if (J.fast) launch_encrypt_tiles(L, Ly.units[UNIT_QROW], ENC_LMR_MAPS);
         else launch_generic_encrypt(L, 0, J, ENC_LMR_MAPS);
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(hl.data(), d_l, (MN + 7) / 8, hipMemcpyDeviceToHost, st));
@@ -539,7 +547,7 @@ int lmr_encrypt(rdhei_ctx *ctx, const uint8_t *d_img, uint8_t *d_enc, int32_t M,
     J.stream_bits = sbits;
     Ly.jobs[0] = J;
     HIPCHK(hipMemcpyAsync(ctx->jobs.p, &Ly.jobs[0], sizeof(Job), hipMemcpyHostToDevice, st));
-    if (J.fast) launch_encrypt_tiles(L, Ly.units[UNIT_TILE], ENC_LMR);
+    if (J.fast) launch_encrypt_tiles(L, Ly.units[UNIT_QROW], ENC_LMR);
     else launch_generic_encrypt(L, 0, J, ENC_LMR);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
@@ -717,7 +725,7 @@ int lmr_encrypt_batch(rdhei_ctx *ctx, const rdhei_job *jobs, int n, int threads,
         }
         Launch LS;
         if ((rc = stage(ctx, S, ctx->jobs, ctx->ws, st, LS))) return rc;
-        if (S.units[UNIT_TILE]) launch_encrypt_tiles(LS, S.units[UNIT_TILE], ENC_LMR_MAPS);
+        if (S.units[UNIT_QROW]) launch_encrypt_tiles(LS, S.units[UNIT_QROW], ENC_LMR_MAPS);
         for (int q : S.per_pixel) launch_generic_encrypt(LS, q, S.jobs[(size_t)q], ENC_LMR_MAPS);
         HIPCHK(hipGetLastError());
         if (pending.size() == (size_t)n) {
@@ -791,7 +799,7 @@ int lmr_encrypt_batch(rdhei_ctx *ctx, const rdhei_job *jobs, int n, int threads,
         }
         Launch LS;
         if ((rc = stage(ctx, S, ctx->jobs, ctx->ws, st, LS))) return rc;
-        if (S.units[UNIT_TILE]) launch_encrypt_tiles(LS, S.units[UNIT_TILE], ENC_LMR);
+        if (S.units[UNIT_QROW]) launch_encrypt_tiles(LS, S.units[UNIT_QROW], ENC_LMR);
         for (int q : S.per_pixel) launch_generic_encrypt(LS, q, S.jobs[(size_t)q], ENC_LMR);
     }
     HIPCHK(hipGetLastError());

@@ -31,8 +31,13 @@ constexpr int kCodeRecord = (code_off(kTileLog + 1) + 15) / 16 * 16;   // 352 by
 constexpr int kStatWords = 8;
 
 // Work-unit kinds (how a batch is cut into workgroup-sized pieces).
-// UNIT_BAND: EMR recovery takes band pairs (tile rows 2p, 2p + 1), LMR single tile rows.
-enum UnitKind { UNIT_TILE = 0, UNIT_BAND = 1, UNIT_SEG = 2, UNIT_IMG = 3, UNIT_KINDS = 4 };
+// Tiles, tile rows (LMR recovery), hiding segments, whole images, and band
+// pairs (tile rows 2p, 2p + 1: encryption and EMR recovery go by 2x2 quads).
+enum UnitKind { UNIT_TILE = 0, UNIT_BAND = 1, UNIT_SEG = 2, UNIT_IMG = 3, UNIT_QROW = 4, UNIT_KINDS = 5 };
+
+// Encryption cuts band pairs into segments of at most kQuadSeg 2x2 tile quads
+// (one work unit each); EMR recovery takes whole band pairs.
+constexpr int kQuadSeg = 4;
 
 // Device-side descriptor of one image of a launch.
 struct Job {
@@ -80,7 +85,7 @@ constexpr int kChunk = kThreads * 16;
 // ---- launchers (defined in the .hip files) ---------------------------------
 struct Launch {
     const Job *jobs;          // device job table
-    const uint32_t *ujob[UNIT_KINDS] = {nullptr, nullptr, nullptr, nullptr};   // unit -> job tables
+    const uint32_t *ujob[UNIT_KINDS] = {};   // unit -> job tables
     int32_t njobs;
     uint8_t *ws;              // device workspace base
     hipStream_t stream;

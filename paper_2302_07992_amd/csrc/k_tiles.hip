@@ -350,81 +350,121 @@ __global__ __launch_bounds__(kThreads) void k_fin_tmap(const Job *__restrict__ j
 
 
 // ----------------------------------------------------------------------------
-// Encryption of one source tile (Sec. III-A encoding): label each pixel
-// (l = 1 unless its b MSBs match its left neighbour's; column 0 always 1),
-// move it to its rotated position (closed form of the level-by-level block
-// turns), XOR with the keystream at the destination, and put l in the LSB.
+// Encryption (Sec. III-A encoding): label each pixel (l = 1 unless its b MSBs
+// match its left neighbour's; column 0 always 1), move it to its rotated
+// position (closed form of the level-by-level block turns), XOR with the
+// keystream at the destination, and put l in the LSB.
 // LMR: full-byte XOR, then bit 7 of raster pixel p takes stream bit p.
 // LMR_MAPS: instead of the image, write the rotated location map and
 // first-MSB map as bit planes (for the host coder).
+//
+// Work goes by 2x2 tile quads of a band pair (tile rows 2p, 2p + 1), left to
+// right, one wave per tile.  The four tiles of a full quad form a level-7
+// block, which moves whole: its four destination tiles form one 128 x 128
+// block, so the quad's reads and writes both cover whole 128-byte lines.  The
+// byte left of each tile row comes from the wave holding the left tile, by
+// LDS (same quad, or the right tile of the previous quad).
 // ----------------------------------------------------------------------------
 template <int MODE>
-__global__ __launch_bounds__(kThreads) void k_encrypt_tile(const Job *__restrict__ jobs, int njobs,
+__global__ __launch_bounds__(kThreads) void k_encrypt_quad(const Job *__restrict__ jobs, int njobs,
                                                             uint8_t *__restrict__ ws, uint32_t units,
                                                             const uint32_t *__restrict__ ujob) {
     constexpr int kW = kThreads / 64;
     __shared__ __align__(16) uint8_t dsts[kW][kTile * kTile];   // per wave: the destination tile, 4x4 blocks
     __shared__ __align__(16) uint8_t recs[kW][kCodeRecord];     // per wave: the tile's code record
     __shared__ __align__(16) uint32_t ptab[perm4::kWords];
+    __shared__ __align__(16) uint32_t edge[2][kW][kTile / 4];   // per tile: column 63, four rows per word
     const int lane = threadIdx.x & 63, wave = (int)uni(threadIdx.x >> 6);   // wave-uniform
     const int q = lane >> 2, g = lane & 3;                       // rows 4q..4q+3, columns 16g..16g+15
+    const int side = wave & 1, half = wave >> 1;                 // this wave's tile in the quad
     uint8_t *dst = dsts[wave];
     uint8_t *rec = recs[wave];
     stage_perm_tables(ptab, (int)threadIdx.x);
     __syncthreads();
-    // the workgroup's contiguous tile range, dealt to its waves in turn so
-    // that neighbouring tiles (which share 128-byte lines) are read together
+
     uint32_t r0, r1;
     unit_range(units, r0, r1);
-    const uint32_t u0 = r0 + (uint32_t)wave;
-
-    // The next tile's loads are issued unconditionally (the last tile reloads
-    // itself), including the byte left of each row (read by the neighbouring
-    // wave at the same time).
+    // unit u: quads c0 .. c0 + nc - 1 of band pair p of image j (wave-uniform)
+    struct QSeg {
+        int j, p, c0, nc;
+    };
+    auto seg_of = [&](uint32_t u) {
+        QSeg r;
+        r.j = (int)uni((uint32_t)find_job<UNIT_QROW>(jobs, njobs, u, ujob));
+        const Job &J = jobs[r.j];
+        const uint32_t nq = (uint32_t)((J.tiles_x + 1) >> 1), ns = (nq + kQuadSeg - 1) / kQuadSeg;
+        const uint32_t v = u - J.ubase[UNIT_QROW];
+        r.p = (int)(v / ns);
+        r.c0 = (int)((v % ns) * kQuadSeg);
+        r.nc = (int)(nq - (uint32_t)r.c0 < (uint32_t)kQuadSeg ? nq - (uint32_t)r.c0 : (uint32_t)kQuadSeg);
+        return r;
+    };
     uint4 p_n[4], rc_n = make_uint4(0, 0, 0, 0);
-    uint32_t halo_n = 0, b_n = 0, st_n = 0, tm_n = 0;
-    auto fetch = [&](uint32_t u) {
-        const Job &J = jobs[uni((uint32_t)find_job<UNIT_TILE>(jobs, njobs, u, ujob))];
-        const uint32_t t = u - J.ubase[UNIT_TILE];
-        const int ty = (int)(t / (uint32_t)J.tiles_x), tx = (int)(t % (uint32_t)J.tiles_x);
+    uint32_t b_n = 0, st_n = 0, tm_n = 0, halo_n = 0;
+    // loads of this wave's tile of quad c of segment S; false when it lies outside the image
+    auto fetch = [&](const QSeg &S, int c) {
+        const Job &J = jobs[S.j];
+        const int ty = 2 * S.p + half, tx = 2 * (S.c0 + c) + side;
+        if (ty >= J.tiles_y || tx >= J.tiles_x) return;
+        const uint32_t t = (uint32_t)(ty * J.tiles_x + tx);
         const uint8_t *row = J.in + (uint64_t)(ty * kTile + 4 * q) * (uint64_t)J.N + (uint64_t)(tx * kTile + 16 * g);
 #pragma unroll
         for (int i = 0; i < 4; ++i) p_n[i] = gload<uint4>(row + (uint64_t)i * J.N);
-        uint32_t hb = 0;
+        if (side == 0 && c == 0 && tx > 0 && g == 0) {   // left column of the segment, from memory
+            uint32_t hb = 0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            hb |= (uint32_t)gload<uint8_t>(row + (uint64_t)i * J.N - ((g == 0 && tx > 0) ? 1 : 0)) << (8 * i);
-        halo_n = hb;
+            for (int i = 0; i < 4; ++i) hb |= (uint32_t)gload<uint8_t>(row + (uint64_t)i * J.N - 1) << (8 * i);
+            halo_n = hb;
+        }
         rc_n = gload<uint4>(ws + J.ws_codes + (uint64_t)t * kCodeRecord + 16 * (lane % (kCodeRecord / 16)));
         b_n = (uint32_t)gload<int32_t>(&J.meta->b);
         st_n = (uint32_t)gload<int32_t>(&J.meta->status);
         tm_n = gload<uint32_t>(ws + J.ws_tmap + 4 * (uint64_t)t);
     };
-    // every wave runs the same number of rounds (a wave past the range idles
-    // through its last ones) so that one barrier per round keeps the waves'
-    // loads together
-    const uint32_t rounds = r1 > r0 ? (r1 - r0 + kW - 1) / kW : 0u;
-    const uint32_t ulast = r1 > r0 ? r1 - 1 : 0u;
-    if (rounds) fetch(u0 < r1 ? u0 : ulast);
 
-    for (uint32_t it = 0; it < rounds; ++it) {
-        const uint32_t u = u0 + it * kW;
+    uint32_t u = r0;
+    int c = 0;
+    QSeg S{0, 0, 0, 1};
+    if (u < r1) {
+        S = seg_of(u);
+        fetch(S, c);
+    }
+    for (uint32_t it = 0; u < r1; ++it) {
+        uint32_t u1 = u;
+        int c1 = c + 1;
+        QSeg S1 = S;
+        if (c1 >= S.nc) {
+            ++u1;
+            c1 = 0;
+            if (u1 < r1) S1 = seg_of(u1);
+        }
         uint4 p[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) p[i] = p_n[i];
         const uint4 rc = rc_n;
-        const uint32_t halo = halo_n, b_cur = uni(b_n), st_cur = uni(st_n), tm = uni(tm_n);
+        const uint32_t b_cur = uni(b_n), st_cur = uni(st_n), tm = uni(tm_n), halo_mem = halo_n;
+        const Job &J = jobs[S.j];
+        const int ty = 2 * S.p + half, tx = 2 * (S.c0 + c) + side;
+        const bool have = ty < J.tiles_y && tx < J.tiles_x;   // wave-uniform
+        const bool first = c == 0;
+        const uint32_t slot = it & 1u;
+        // column 63 of this tile for the wave of the tile to its right
+        if (have && g == 3)
+            edge[slot][wave][q] = (p[0].w >> 24) | ((p[1].w >> 24) << 8) | ((p[2].w >> 24) << 16) | (p[3].w & 0xFF000000u);
         __syncthreads();
-        fetch(u + kW < r1 ? u + kW : (u < r1 ? u : ulast));
-        if (u >= r1) continue;                                            // uniform per wave
-        const Job &J = jobs[uni((uint32_t)find_job<UNIT_TILE>(jobs, njobs, u, ujob))];
-        const uint32_t t = u - J.ubase[UNIT_TILE];
-        const int tx = (int)(t % (uint32_t)J.tiles_x);
+        if (u1 < r1) fetch(S1, c1);
+        u = u1;
+        c = c1;
+        S = S1;
+        if (!have) continue;                                              // uniform per wave
         if (MODE == ENC_EMR && st_cur != (uint32_t)RDHEI_OK) continue;     // uniform per wave
         const int b = J.fixed_b > 0 ? J.fixed_b : (int)b_cur;
         int dy, dx;
         uint32_t up;
         tmap_unpack(tm, dy, dx, up);
+        // the byte left of rows 4q..4q+3 of this tile (column 0 of the image has none)
+        const uint32_t halo = side ? edge[slot][wave - 1][q]
+                                   : (tx == 0 ? 0u : (first ? halo_mem : edge[slot ^ 1u][wave + 1][q]));
 
         // labels (Sec. III-A location map): l = 1 unless the b MSBs equal the left neighbour's
         uint32_t o[4][4];
@@ -716,7 +756,7 @@ __global__ __launch_bounds__(kThreads) void k_recover_quad_emr(const Job *__rest
 
     uint32_t r0, r1;
     unit_range(units, r0, r1);
-    auto job_of = [&](uint32_t u) { return (int)uni((uint32_t)find_job<UNIT_BAND>(jobs, njobs, u, ujob)); };
+    auto job_of = [&](uint32_t u) { return (int)uni((uint32_t)find_job<UNIT_QROW>(jobs, njobs, u, ujob)); };
     // quads (u, c): band pair u of the launch, quad column c
     auto step = [&](uint32_t &u, uint32_t &c) {
         if (u >= r1) return;
@@ -731,7 +771,7 @@ __global__ __launch_bounds__(kThreads) void k_recover_quad_emr(const Job *__rest
         if (u >= r1) return false;
         j = job_of(u);
         const Job &J = jobs[j];
-        ty = 2 * (int)(u - J.ubase[UNIT_BAND]) + half;
+        ty = 2 * (int)(u - J.ubase[UNIT_QROW]) + half;
         tx = 2 * (int)c + side;
         return ty < J.tiles_y && tx < J.tiles_x;
     };
@@ -964,16 +1004,16 @@ void launch_finalize(const Launch &L, bool stats, const std::vector<int> &big, c
 
 void launch_encrypt_tiles(const Launch &L, uint32_t units, int mode) {
     if (!units) return;
-    const uint32_t *UJ = L.ujob[UNIT_TILE];
+    const uint32_t *UJ = L.ujob[UNIT_QROW];
     const dim3 bl(kThreads);
     if (mode == ENC_EMR)
-        hipLaunchKernelGGL(k_encrypt_tile<ENC_EMR>, dim3(persistent_grid(L, k_encrypt_tile<ENC_EMR>, units)), bl, 0,
+        hipLaunchKernelGGL(k_encrypt_quad<ENC_EMR>, dim3(persistent_grid(L, k_encrypt_quad<ENC_EMR>, units)), bl, 0,
                            L.stream, L.jobs, L.njobs, L.ws, units, UJ);
     else if (mode == ENC_LMR)
-        hipLaunchKernelGGL(k_encrypt_tile<ENC_LMR>, dim3(persistent_grid(L, k_encrypt_tile<ENC_LMR>, units)), bl, 0,
+        hipLaunchKernelGGL(k_encrypt_quad<ENC_LMR>, dim3(persistent_grid(L, k_encrypt_quad<ENC_LMR>, units)), bl, 0,
                            L.stream, L.jobs, L.njobs, L.ws, units, UJ);
     else
-        hipLaunchKernelGGL(k_encrypt_tile<ENC_LMR_MAPS>, dim3(persistent_grid(L, k_encrypt_tile<ENC_LMR_MAPS>, units)),
+        hipLaunchKernelGGL(k_encrypt_quad<ENC_LMR_MAPS>, dim3(persistent_grid(L, k_encrypt_quad<ENC_LMR_MAPS>, units)),
                            bl, 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
 }
 
@@ -983,7 +1023,7 @@ void launch_recover_bands(const Launch &L, uint32_t units, int method) {
     const dim3 bl(kThreads);
     if (method == RDHEI_EMR)
         hipLaunchKernelGGL(k_recover_quad_emr, dim3(persistent_grid(L, k_recover_quad_emr, units)), bl, 0, L.stream,
-                           L.jobs, L.njobs, L.ws, units, UJ);
+                           L.jobs, L.njobs, L.ws, units, L.ujob[UNIT_QROW]);
     else
         hipLaunchKernelGGL(k_recover_band<RDHEI_LMR>, dim3(persistent_grid(L, k_recover_band<RDHEI_LMR>, units)), bl, 0,
                            L.stream, L.jobs, L.njobs, L.ws, units, UJ);
