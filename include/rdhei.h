@@ -103,6 +103,8 @@ int rdhei_encrypt(rdhei_ctx *ctx, const uint8_t *d_img, uint8_t *d_enc, int32_t 
  * replaceable bits of the redundant pixels (EMR: bits 7..8-b of pixels with
  * LSB 0; LMR: bits 6..8-b of pixels the decompressed map marks 0).  nbits < 0
  * means "the full capacity".  Unused replaceable bits are left unchanged.
+ * d_msg is read in whole 16-byte blocks: it must hold ceil(n/128)*16 bytes,
+ * n = nbits (the capacity when nbits < 0).
  * A message longer than the capacity sets d_meta->status = RDHEI_ECAPACITY
  * and leaves the image unchanged.
  * EMR: asynchronous; LMR: synchronises (host map decompression). */

@@ -140,20 +140,21 @@ __device__ __forceinline__ void embed16(uint32_t w[4], uint32_t rm, uint32_t rel
     for (int q = 0; q < 4; ++q) {
         const uint32_t m = (rm >> (4 * q)) & 0xFu;
         const uint32_t pos = rel;
-        rel += (uint32_t)__popc(m) * rep;
-        if (m == 0 || pos >= rend) continue;
-        if (rel <= rend) {
-            const uint32_t run = window_bits(win, pos + 32u);
-            const uint32_t F01 = run >> (32u - 2u * rep);
-            const uint32_t F23 = __builtin_amdgcn_ubfe(run, 32u - 4u * rep, 2u * rep);
-            const uint32_t t = (F01 << 16) | F23;
-            const uint32_t cp = (t & hk.low_pairs) | (((t >> rep) & hk.low_pairs) << 8);
-            const uint32_t e = vperm(0u, cp, T[16 + m]) << hk.shift;
-            const uint32_t K = T[32 + m] & hk.rep_bytes;
-            w[q] = (w[q] & ~K) | (e & K);
-        } else {
+        rel += __umul24((uint32_t)__popc(m), rep);
+        // whole word (every field inside the payload), computed unconditionally
+        const uint32_t run = window_bits(win, pos + 32u);
+        const uint32_t F01 = run >> (32u - 2u * rep);
+        const uint32_t F23 = __builtin_amdgcn_ubfe(run, 32u - 4u * rep, 2u * rep);
+        const uint32_t t = (F01 << 16) | F23;
+        const uint32_t cp = (t & hk.low_pairs) | (((t >> rep) & hk.low_pairs) << 8);
+        const uint32_t e = vperm(0u, cp, T[16 + m]) << hk.shift;
+        const uint32_t K = T[32 + m] & hk.rep_bytes;
+        const uint32_t x = w[q];
+        w[q] = rel <= rend ? ((x & ~K) | (e & K)) : x;
+        if (__builtin_expect(rel > rend && pos < rend, 0)) {
+            // the word where the payload ends: pixel by pixel
             const uint32_t top = hk.shift + rep - 1u;
-            uint32_t p = pos, x = w[q];
+            uint32_t p = pos, y = x;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 if (((m >> j) & 1u) && p < rend) {
@@ -161,11 +162,11 @@ __device__ __forceinline__ void embed16(uint32_t w[4], uint32_t rm, uint32_t rel
                     const uint32_t left = rend - p;
                     const uint32_t take = left < rep ? left : rep;
                     const uint32_t wmask = ((1u << take) - 1u) << (top + 1u - take);
-                    x = (x & ~(wmask << (8 * j))) | (((val << hk.shift) & wmask) << (8 * j));
+                    y = (y & ~(wmask << (8 * j))) | (((val << hk.shift) & wmask) << (8 * j));
                     p += rep;
                 }
             }
-            w[q] = x;
+            w[q] = y;
         }
     }
 }
@@ -583,6 +584,18 @@ __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &
     int64_t carry_word = -1;
     uint4 nxt[kWLoads];
     wseg_load(img, 0, total < kWSegPx ? total : kWSegPx, lane, nxt);
+    // embedding: the message blocks of the next step, loaded a step ahead
+    // (a step needs at most 4096 * 7 bits = 224 blocks from its first one)
+    uint4 mpre[4];
+    auto msg_prefetch = [&](uint64_t first_blk) {
+        const uint64_t nblk = (uint64_t)(hp.nbits + 127) >> 7;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint64_t blk = first_blk + (uint64_t)(lane + 64 * i);
+            mpre[i] = blk < nblk ? gload<uint4>(J.msg + 16 * blk) : make_uint4(0, 0, 0, 0);
+        }
+    };
+    if (EMBED) msg_prefetch(0);
     for (uint32_t seg = 0; seg < nseg; ++seg) {
         const uint64_t s0 = (uint64_t)seg * kWSegPx;
         const uint64_t s1 = s0 + kWSegPx < total ? s0 + kWSegPx : total;
@@ -615,17 +628,20 @@ __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &
         if (wend > hp.nbits) wend = hp.nbits;
         rank += T;
         if (T > 0 && EMBED) {
-            // window bits relative to the first staged 16-byte block
+            // window bits relative to the first staged 16-byte block (the prefetch base)
             const int64_t fb = wstart >> 7, lb = (wend - 1) >> 7;
             const uint32_t off0 = (uint32_t)(wstart - (fb << 7)), rend = (uint32_t)(wend - (fb << 7));
-            for (int64_t q = lane; q <= lb - fb; q += 64) {
-                const uint64_t blk = (uint64_t)(fb + q);
-                const uint4 mv = gload<uint4>(J.msg + 16 * blk);
-                const U4 ks = stream_block(J.key, kDomainMessage, blk);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t q = lane + 64 * i;
+                if (q > lb - fb) continue;
+                const uint4 mv = mpre[i];
+                const U4 ks = stream_block(J.key, kDomainMessage, (uint64_t)(fb + q));
                 *reinterpret_cast<uint4 *>(win + 4 + 4 * q) =
                     make_uint4(__builtin_bswap32(mv.x ^ ks.x), __builtin_bswap32(mv.y ^ ks.y),
                                __builtin_bswap32(mv.z ^ ks.z), __builtin_bswap32(mv.w ^ ks.w));
             }
+            msg_prefetch((rank * rep) >> 7);   // rank already counts this step
             wave_sync();
 #pragma unroll
             for (int k = 0; k < kWLoads; ++k) {

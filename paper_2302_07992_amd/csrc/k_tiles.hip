@@ -173,6 +173,7 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
                 flush(cur_j);
                 cur_j = j;
             }
+            const bool lmr = J.method == RDHEI_LMR;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const uint32_t w[4] = {p[i].x, p[i].y, p[i].z, p[i].w};
@@ -190,6 +191,7 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
                     const uint32_t x7 = x[k] & 0x7F7F7F7Fu;
 #pragma unroll
                     for (int b = 2; b <= 8; ++b) {
+                        if (b == 8 && !lmr) continue;   // b = 8 is an LMR choice only
                         // bit 7 of each byte of s7: low 7 bits of x >= 2^(8-b); lt: x < 2^(8-b)
                         const uint32_t s7 = x7 + (0x80u - (1u << (8 - b))) * 0x01010101u;
                         const uint32_t lt = __builtin_amdgcn_bitop3_b32(s7, x[k], 0x80808080u, 0x02);
