@@ -132,6 +132,12 @@ struct LayoutOpts {
 };
 
 // Whether image q of a hiding op may be walked whole by one workgroup.
+// Segments of at most kQuadSeg 2x2 tile quads per band pair (tiled images).
+uint32_t quad_segments(const Job &J) {
+    const uint32_t nq = (uint32_t)((J.tiles_x + 1) / 2);
+    return (nq + kQuadSeg - 1) / kQuadSeg;
+}
+
 bool whole_eligible(int op, const rdhei_job &q) {
     if (op != RDHEI_OP_EMBED && op != RDHEI_OP_EXTRACT) return false;
     const uint64_t MN = (uint64_t)q.height * (uint64_t)q.width;
@@ -199,6 +205,10 @@ int make_layout(int op, const rdhei_job *in, int n, const LayoutOpts &opt, Layou
             ws = align_up(ws + (J.fast ? tiles * 4 : 0), 256);
             J.ws_stats = ws;
             ws = align_up(stat_z_offset(J) + 64, 256);   // counter slots, then Z as 64-bit values
+            if (op == RDHEI_OP_RECOVER && q.method == RDHEI_EMR && J.fast && quad_segments(J) > 1) {
+                J.ws_fix = ws;   // two u16 per image row and quad segment
+                ws = align_up(ws + (uint64_t)J.M * quad_segments(J) * 4u, 256);
+            }
             if (q.method == RDHEI_LMR && !J.fast) {
                 J.ws_bytes = ws;
                 ws = align_up(ws + MN, 256);
@@ -213,11 +223,7 @@ int make_layout(int op, const rdhei_job *in, int n, const LayoutOpts &opt, Layou
         const uint32_t cnt[UNIT_KINDS] = {J.fast ? (uint32_t)(J.tiles_x * J.tiles_y) : 0u,
                                           bands ? (uint32_t)J.tiles_y : 0u,
                                           hide && !whole ? (uint32_t)J.nseg : 0u, whole ? 1u : 0u,
-                                          quads ? (uint32_t)((J.tiles_y + 1) / 2) *
-                                                      (op == RDHEI_OP_ENCRYPT
-                                                           ? (uint32_t)(((J.tiles_x + 1) / 2 + kQuadSeg - 1) / kQuadSeg)
-                                                           : 1u)
-                                                : 0u};
+                                          quads ? (uint32_t)((J.tiles_y + 1) / 2) * quad_segments(J) : 0u};
         for (int k = 0; k < UNIT_KINDS; ++k) {
             J.ubase[k] = L.units[k];
             J.ucount[k] = cnt[k];
@@ -274,7 +280,16 @@ std::vector<Stage> stages_of(const Layout &Ly, const uint32_t *units_in, std::ve
                          }});
         if (ut) S.push_back({"finalize_pyramid", [=](const Launch &L) { launch_finalize(L, false, big, hj); }});
         const uint32_t urec = method == RDHEI_EMR ? uq : ub;
-        if (urec) S.push_back({"recover_bands", [=](const Launch &L) { launch_recover_bands(L, urec, method); }});
+        uint32_t fix_rows = 0, fix_segs = 0;   // images cut into quad segments get their rows completed afterwards
+        for (const Job &J : hj)
+            if (J.fast && method == RDHEI_EMR && quad_segments(J) > 1) {
+                fix_rows = std::max(fix_rows, (uint32_t)J.M);
+                fix_segs = std::max(fix_segs, quad_segments(J));
+            }
+        if (urec)
+            S.push_back({"recover_bands", [=](const Launch &L) {
+                             launch_recover_bands(L, urec, method, fix_rows, fix_segs);
+                         }});
         if (!pp.empty())
             S.push_back({"per_pixel_recover", [=](const Launch &L) {
                              for (int j : pp) launch_generic_recover(L, j, hj[j]);

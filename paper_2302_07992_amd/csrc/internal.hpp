@@ -66,6 +66,8 @@ struct Job {
     uint64_t ws_tmap;         // per tile: destination tile and quarter turns (fast path)
     uint64_t ws_stats;        // statistics records
     uint64_t ws_bytes;        // per-pixel path: byte-per-pixel scratch
+    uint64_t ws_fix;          // EMR recovery of images cut into quad segments: per segment and row,
+                              // leading pixels without a carry, then the last labelled value (u16 each)
 };
 
 // Counter slots of an image's statistics: one per 64 tiles, at most 64.
@@ -107,7 +109,9 @@ constexpr int kFinBlock = 16;
 // big: indices of such jobs; hj: the host copy of the job table
 void launch_finalize(const Launch &L, bool stats, const std::vector<int> &big, const std::vector<Job> &hj);
 void launch_encrypt_tiles(const Launch &L, uint32_t units, int mode);
-void launch_recover_bands(const Launch &L, uint32_t units, int method);
+// fix_rows, fix_segs: most rows and most quad segments per band pair of the EMR
+// images cut into segments (fix_rows 0: none)
+void launch_recover_bands(const Launch &L, uint32_t units, int method, uint32_t fix_rows, uint32_t fix_segs);
 uint64_t seg_pixels();
 int seq_max_segments();
 uint32_t whole_image_min();

@@ -351,6 +351,26 @@ __global__ __launch_bounds__(kThreads) void k_fin_tmap(const Job *__restrict__ j
 }
 
 
+// Work unit u of a quad launch: quads c0 .. c0 + nc - 1 of band pair p (tile
+// rows 2p, 2p + 1) of image j; band pairs are cut into ns segments of at most
+// kQuadSeg quads, s is this one.  Wave-uniform.
+struct QSeg {
+    int j, p, c0, nc, s, ns;
+};
+__device__ __forceinline__ QSeg qseg_of(const Job *jobs, int njobs, const uint32_t *ujob, uint32_t u) {
+    QSeg r;
+    r.j = (int)uni((uint32_t)find_job<UNIT_QROW>(jobs, njobs, u, ujob));
+    const Job &J = jobs[r.j];
+    const uint32_t nq = (uint32_t)((J.tiles_x + 1) >> 1), ns = (nq + kQuadSeg - 1) / kQuadSeg;
+    const uint32_t v = u - J.ubase[UNIT_QROW];
+    r.p = (int)(v / ns);
+    r.s = (int)(v % ns);
+    r.ns = (int)ns;
+    r.c0 = r.s * kQuadSeg;
+    r.nc = (int)(nq - (uint32_t)r.c0 < (uint32_t)kQuadSeg ? nq - (uint32_t)r.c0 : (uint32_t)kQuadSeg);
+    return r;
+}
+
 // ----------------------------------------------------------------------------
 // Encryption (Sec. III-A encoding): label each pixel (l = 1 unless its b MSBs
 // match its left neighbour's; column 0 always 1), move it to its rotated
@@ -386,21 +406,7 @@ __global__ __launch_bounds__(kThreads) void k_encrypt_quad(const Job *__restrict
 
     uint32_t r0, r1;
     unit_range(units, r0, r1);
-    // unit u: quads c0 .. c0 + nc - 1 of band pair p of image j (wave-uniform)
-    struct QSeg {
-        int j, p, c0, nc;
-    };
-    auto seg_of = [&](uint32_t u) {
-        QSeg r;
-        r.j = (int)uni((uint32_t)find_job<UNIT_QROW>(jobs, njobs, u, ujob));
-        const Job &J = jobs[r.j];
-        const uint32_t nq = (uint32_t)((J.tiles_x + 1) >> 1), ns = (nq + kQuadSeg - 1) / kQuadSeg;
-        const uint32_t v = u - J.ubase[UNIT_QROW];
-        r.p = (int)(v / ns);
-        r.c0 = (int)((v % ns) * kQuadSeg);
-        r.nc = (int)(nq - (uint32_t)r.c0 < (uint32_t)kQuadSeg ? nq - (uint32_t)r.c0 : (uint32_t)kQuadSeg);
-        return r;
-    };
+    auto seg_of = [&](uint32_t u) { return qseg_of(jobs, njobs, ujob, u); };
     uint4 p_n[4], rc_n = make_uint4(0, 0, 0, 0);
     uint32_t b_n = 0, st_n = 0, tm_n = 0, halo_n = 0;
     // loads of this wave's tile of quad c of segment S; false when it lies outside the image
@@ -426,7 +432,7 @@ __global__ __launch_bounds__(kThreads) void k_encrypt_quad(const Job *__restrict
 
     uint32_t u = r0;
     int c = 0;
-    QSeg S{0, 0, 0, 1};
+    QSeg S{0, 0, 0, 1, 0, 1};
     if (u < r1) {
         S = seg_of(u);
         fetch(S, c);
@@ -734,16 +740,18 @@ __global__ __launch_bounds__(kThreads) void k_recover_band(const Job *__restrict
 static __constant__ perm4::InvTables kInvTables = perm4::kInvTables;
 static __constant__ glide4::Tables kGlideTables = glide4::kTables;
 
-__global__ __launch_bounds__(kThreads) void k_recover_quad_emr(const Job *__restrict__ jobs, int njobs,
-                                                               uint8_t *__restrict__ ws, uint32_t units,
-                                                               const uint32_t *__restrict__ ujob) {
+// (At most 128 VGPRs: four waves per SIMD, which is what the LDS allows.)
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_recover_quad_emr(
+    const Job *__restrict__ jobs, int njobs, uint8_t *__restrict__ ws, uint32_t units, const uint32_t *__restrict__ ujob) {
     constexpr int kW = kThreads / 64;
     __shared__ __align__(16) uint8_t dts[kW][kTile * kTile];   // per wave: decrypted tile, 4x4 blocks
     __shared__ __align__(16) uint8_t lbs[kW][kTile * kTile];   // per wave: labels, same layout
     __shared__ __align__(16) uint8_t recs[kW][kCodeRecord];    // per wave: the tile's code record
     __shared__ __align__(16) uint32_t itab[perm4::kInvWords];
     __shared__ __align__(16) uint32_t gtab[glide4::kWords];
-    __shared__ __align__(8) uint16_t sums[2][kW][kTile];       // per tile row: last labelled value | 0x100, or 0
+    // per tile row: last labelled value | 0x100 (0: none), and in bits 9..15
+    // the column of its first labelled pixel (64: none; segmented images only)
+    __shared__ __align__(8) uint16_t sums[2][kW][kTile];
     __shared__ __align__(8) uint16_t carry[2][2][kTile];       // per band half: carry into the next quad
     const int lane = threadIdx.x & 63, wave = (int)uni(threadIdx.x >> 6);   // wave-uniform
     const int q = lane >> 2, g = lane & 3;                      // rows 4q..4q+3, columns 16g..16g+15
@@ -758,38 +766,43 @@ __global__ __launch_bounds__(kThreads) void k_recover_quad_emr(const Job *__rest
 
     uint32_t r0, r1;
     unit_range(units, r0, r1);
-    auto job_of = [&](uint32_t u) { return (int)uni((uint32_t)find_job<UNIT_QROW>(jobs, njobs, u, ujob)); };
-    // quads (u, c): band pair u of the launch, quad column c
-    auto step = [&](uint32_t &u, uint32_t &c) {
-        if (u >= r1) return;
-        const Job &J = jobs[job_of(u)];
-        if (++c >= (uint32_t)((J.tiles_x + 1) >> 1)) {
-            ++u;
-            c = 0;
-        }
+    // quad positions (unit u, quad c of its segment S), wave-uniform
+    struct Pos {
+        uint32_t u;
+        int c;
+        QSeg S;
     };
-    // this wave's tile of quad (u, c); false when it lies outside the image
-    auto tile_of = [&](uint32_t u, uint32_t c, int &j, int &ty, int &tx) {
-        if (u >= r1) return false;
-        j = job_of(u);
-        const Job &J = jobs[j];
-        ty = 2 * (int)(u - J.ubase[UNIT_QROW]) + half;
-        tx = 2 * (int)c + side;
+    auto advance = [&](const Pos &P) {
+        Pos n = P;
+        if (n.u >= r1) return n;
+        if (++n.c >= n.S.nc) {
+            ++n.u;
+            n.c = 0;
+            if (n.u < r1) n.S = qseg_of(jobs, njobs, ujob, n.u);
+        }
+        return n;
+    };
+    // this wave's tile of a quad; false when it lies outside the image
+    auto tile_of = [&](const Pos &P, int &ty, int &tx) {
+        if (P.u >= r1) return false;
+        const Job &J = jobs[P.S.j];
+        ty = 2 * P.S.p + half;
+        tx = 2 * (P.S.c0 + P.c) + side;
         return ty < J.tiles_y && tx < J.tiles_x;
     };
     // tile-map entry and b of a quad's tile (loaded an iteration before the pixels)
-    auto load_tm = [&](uint32_t u, uint32_t c, uint32_t &tm, uint32_t &bb) {
-        int j = 0, ty = 0, tx = 0;
-        if (!tile_of(u, c, j, ty, tx)) return;
-        const Job &J = jobs[j];
+    auto load_tm = [&](const Pos &P, uint32_t &tm, uint32_t &bb) {
+        int ty = 0, tx = 0;
+        if (!tile_of(P, ty, tx)) return;
+        const Job &J = jobs[P.S.j];
         tm = gload<uint32_t>(ws + J.ws_tmap + 4 * (uint64_t)(ty * J.tiles_x + tx));
         bb = (uint32_t)gload<int32_t>(&J.meta->b);
     };
     uint4 e_n[4], rc_n = make_uint4(0, 0, 0, 0);
-    auto fetch = [&](uint32_t u, uint32_t c, uint32_t tm) {
-        int j = 0, ty = 0, tx = 0;
-        if (!tile_of(u, c, j, ty, tx)) return;
-        const Job &J = jobs[j];
+    auto fetch = [&](const Pos &P, uint32_t tm) {
+        int ty = 0, tx = 0;
+        if (!tile_of(P, ty, tx)) return;
+        const Job &J = jobs[P.S.j];
         int ey, ex;
         uint32_t up;
         tmap_unpack(uni(tm), ey, ex, up);
@@ -799,35 +812,37 @@ __global__ __launch_bounds__(kThreads) void k_recover_quad_emr(const Job *__rest
         rc_n = gload<uint4>(ws + J.ws_codes + (uint64_t)(ty * J.tiles_x + tx) * kCodeRecord + 16 * (lane % (kCodeRecord / 16)));
     };
 
-    uint32_t u = r0, c = 0;              // current quad
-    uint32_t u1 = r0, c1 = 0;            // the next one
-    step(u1, c1);
+    Pos cur{r0, 0, QSeg{0, 0, 0, 1, 0, 1}};
+    if (r0 < r1) cur.S = qseg_of(jobs, njobs, ujob, r0);
+    Pos nxt = advance(cur);
     uint32_t tm = 0, b_cur = 0, tm1 = 0, b1 = 0;
-    load_tm(u, c, tm, b_cur);
-    fetch(u, c, tm);
-    load_tm(u1, c1, tm1, b1);
+    load_tm(cur, tm, b_cur);
+    fetch(cur, tm);
+    load_tm(nxt, tm1, b1);
+    uint32_t lead[4] = {0, 0, 0, 0}, open[4] = {1, 1, 1, 1};   // left waves of segmented images
 
-    for (uint32_t it = 0; u < r1; ++it) {
+    for (uint32_t it = 0; cur.u < r1; ++it) {
         uint4 e[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) e[i] = e_n[i];
         const uint4 rc = rc_n;
         const uint32_t tm_cur = uni(tm), bq = uni(b_cur);
         // pipeline: pixels of the next quad, tile map of the one after
-        fetch(u1, c1, tm1);
-        uint32_t u2 = u1, c2 = c1;
-        step(u2, c2);
+        fetch(nxt, tm1);
+        const Pos nn = advance(nxt);
         tm = tm1;
         b_cur = b1;
-        load_tm(u2, c2, tm1, b1);
+        load_tm(nn, tm1, b1);
 
-        int j = 0, ty = 0, tx = 0;
-        const bool have = tile_of(u, c, j, ty, tx);   // wave-uniform
-        const bool first = c == 0;
+        int ty = 0, tx = 0;
+        const bool have = tile_of(cur, ty, tx);   // wave-uniform
+        const Job &J = jobs[cur.S.j];
+        const bool first = cur.c == 0, last = cur.c == cur.S.nc - 1;
+        const bool segd = cur.S.ns > 1;            // rows continue in other segments (fixed up afterwards)
+        const bool right_in = 2 * (cur.S.c0 + cur.c) + 1 < J.tiles_x;
         const uint32_t slot = it & 1u;
-        uint32_t Do[4][4], sel[4][4], excl[4], tsum[4];
+        uint32_t Do[4][4], sel[4][4], excl[4], tsum[4], fcol[4];
         if (have) {
-            const Job &J = jobs[j];
             int ey, ex;
             uint32_t up;
             tmap_unpack(tm_cur, ey, ex, up);
@@ -896,30 +911,49 @@ __global__ __launch_bounds__(kThreads) void k_recover_quad_emr(const Job *__rest
                 const uint32_t x = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x90, 0xF, 0xF, false);
                 excl[i] = g == 0 ? 0u : x;
                 tsum[i] = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xFF, 0xF, 0xF, false);      // lane 3
+                fcol[i] = 64u;
+            }
+            if (segd) {
+                // column of the first labelled pixel of each tile row (minimum over the row's lanes)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const uint32_t m16 = m[i][0] | (m[i][1] << 4) | (m[i][2] << 8) | (m[i][3] << 12);
+                    uint32_t f = m16 ? 16u * (uint32_t)g + (uint32_t)__builtin_ctz(m16) : 64u;
+                    uint32_t o = (uint32_t)__builtin_amdgcn_mov_dpp((int)f, 0xB1, 0xF, 0xF, false);   // lane g ^ 1
+                    f = f < o ? f : o;
+                    o = (uint32_t)__builtin_amdgcn_mov_dpp((int)f, 0x4E, 0xF, 0xF, false);            // lane g ^ 2
+                    fcol[i] = f < o ? f : o;
+                }
             }
             if (g == 0)
                 *reinterpret_cast<uint2 *>(&sums[slot][wave][4 * q]) =
-                    make_uint2(tsum[0] | (tsum[1] << 16), tsum[2] | (tsum[3] << 16));
+                    make_uint2((tsum[0] | (fcol[0] << 9)) | ((tsum[1] | (fcol[1] << 9)) << 16),
+                               (tsum[2] | (fcol[2] << 9)) | ((tsum[3] | (fcol[3] << 9)) << 16));
         }
         __syncthreads();
         if (have) {
-            const Job &J = jobs[j];
             const int b = J.fixed_b > 0 ? J.fixed_b : (int)bq;
             const uint32_t mrep = ((0xFFu << (8 - b)) & 0xFFu) * 0x01010101u;   // replaceable bits, every byte
             const uint2 cw = *reinterpret_cast<const uint2 *>(&carry[slot][half][4 * q]);
             const uint32_t cr[4] = {cw.x & 0xFFFFu, cw.x >> 16, cw.y & 0xFFFFu, cw.y >> 16};
-            uint32_t lf[4] = {0, 0, 0, 0};
+            uint32_t lf[4] = {0, 0, 0, 0}, rf[4] = {64, 64, 64, 64};
             if (side) {
                 const uint2 lw2 = *reinterpret_cast<const uint2 *>(&sums[slot][wave - 1][4 * q]);
-                lf[0] = lw2.x & 0xFFFFu;
-                lf[1] = lw2.x >> 16;
-                lf[2] = lw2.y & 0xFFFFu;
-                lf[3] = lw2.y >> 16;
+                lf[0] = lw2.x & 0x1FFu;
+                lf[1] = (lw2.x >> 16) & 0x1FFu;
+                lf[2] = lw2.y & 0x1FFu;
+                lf[3] = (lw2.y >> 16) & 0x1FFu;
+            } else if (segd && right_in) {
+                const uint2 rw2 = *reinterpret_cast<const uint2 *>(&sums[slot][wave + 1][4 * q]);
+                rf[0] = (rw2.x >> 9) & 0x7Fu;
+                rf[1] = (rw2.x >> 25) & 0x7Fu;
+                rf[2] = (rw2.y >> 9) & 0x7Fu;
+                rf[3] = (rw2.y >> 25) & 0x7Fu;
             }
             uint32_t nc[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const uint32_t from_left = first ? 0u : cr[i];           // into the quad
+                const uint32_t from_left = first ? 0u : cr[i];           // into the quad (none at a segment start)
                 const uint32_t tin = lf[i] ? lf[i] : from_left;          // into this tile
                 const uint32_t cin = excl[i] ? excl[i] : tin;            // into this lane
                 nc[i] = tsum[i] ? tsum[i] : tin;                         // out of this tile
@@ -936,12 +970,81 @@ __global__ __launch_bounds__(kThreads) void k_recover_quad_emr(const Job *__rest
             if (side && g == 0)
                 *reinterpret_cast<uint2 *>(&carry[slot ^ 1u][half][4 * q]) =
                     make_uint2(nc[0] | (nc[1] << 16), nc[2] | (nc[3] << 16));
+            if (segd) {
+                // per image row and segment: leading pixels still waiting for a carry (left
+                // wave) and the last labelled value (wave with the segment's last tile)
+                const uint32_t ns = (uint32_t)cur.S.ns, sg = (uint32_t)cur.S.s;
+                const uint64_t R0 = (uint64_t)(128 * cur.S.p + 64 * half + 4 * q);
+                uint16_t *fix_lead = reinterpret_cast<uint16_t *>(ws + J.ws_fix);
+                uint16_t *fix_sum = fix_lead + (uint64_t)J.M * ns;
+                if (!side) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        if (first) {
+                            lead[i] = 0;
+                            open[i] = 1;
+                        }
+                        if (open[i]) {
+                            if (fcol[i] < 64u) {
+                                lead[i] += fcol[i];
+                                open[i] = 0;
+                            } else if (rf[i] < 64u) {
+                                lead[i] += 64u + rf[i];
+                                open[i] = 0;
+                            } else {
+                                lead[i] += right_in ? 128u : 64u;
+                            }
+                        }
+                    }
+                    if (last && g == 0) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) fix_lead[(uint64_t)sg * J.M + R0 + i] = (uint16_t)lead[i];
+                    }
+                }
+                if (last && g == 0 && (side || !right_in)) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) fix_sum[(uint64_t)sg * J.M + R0 + i] = (uint16_t)nc[i];
+                }
+            }
         }
-        u = u1;
-        c = c1;
-        u1 = u2;
-        c1 = c2;
+        cur = nxt;
+        nxt = nn;
     }
+}
+
+// Rows of images whose band pairs were cut into segments: a segment started
+// without the value carried in from its left, so the pixels before its first
+// labelled pixel (per row) still lack their replaceable bits.  One thread per
+// image row and segment s >= 1 (blockIdx.y + 1) finds the nearest segment to
+// the left with a labelled pixel in that row (column 0 always is one) and
+// completes those pixels.  Records are segment-major: [s][row].  Image
+// blockIdx.z.
+__global__ void k_recover_fix(const Job *__restrict__ jobs, const uint8_t *__restrict__ ws) {
+    const Job &J = jobs[blockIdx.z];
+    if (!J.fast || J.method != RDHEI_EMR) return;
+    const uint32_t nq = (uint32_t)((J.tiles_x + 1) >> 1), ns = (nq + kQuadSeg - 1) / kQuadSeg;
+    const uint32_t sg = blockIdx.y + 1u;
+    if (sg >= ns) return;
+    const uint32_t R = blockIdx.x * blockDim.x + threadIdx.x;
+    if (R >= (uint32_t)J.M) return;
+    const uint16_t *fix_lead = reinterpret_cast<const uint16_t *>(ws + J.ws_fix);
+    const uint16_t *fix_sum = fix_lead + (uint64_t)J.M * ns;
+    const uint32_t lead = fix_lead[(uint64_t)sg * J.M + R];
+    if (!lead) return;
+    uint32_t carry = 0;
+    for (uint32_t t = sg; t-- > 0;) {
+        const uint32_t sum = fix_sum[(uint64_t)t * J.M + R];
+        if (sum & 0x100u) {
+            carry = sum & 0xFFu;
+            break;
+        }
+    }
+    const int b = J.fixed_b > 0 ? J.fixed_b : J.meta->b;
+    const uint32_t mrep = (0xFFu << (8 - b)) & 0xFFu;
+    const uint32_t x0 = sg * (uint32_t)kQuadSeg * 2u * (uint32_t)kTile;
+    const uint32_t n = lead < (uint32_t)J.N - x0 ? lead : (uint32_t)J.N - x0;
+    uint8_t *row = J.out + (uint64_t)R * (uint64_t)J.N + x0;
+    for (uint32_t k = 0; k < n; ++k) row[k] = (uint8_t)((row[k] & ~mrep) | (carry & mrep));
 }
 
 // ---- launchers ---------------------------------------------------------------
@@ -1019,13 +1122,17 @@ void launch_encrypt_tiles(const Launch &L, uint32_t units, int mode) {
                            bl, 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
 }
 
-void launch_recover_bands(const Launch &L, uint32_t units, int method) {
+void launch_recover_bands(const Launch &L, uint32_t units, int method, uint32_t fix_rows, uint32_t fix_segs) {
     if (!units) return;
     const uint32_t *UJ = L.ujob[UNIT_BAND];
     const dim3 bl(kThreads);
-    if (method == RDHEI_EMR)
+    if (method == RDHEI_EMR) {
         hipLaunchKernelGGL(k_recover_quad_emr, dim3(persistent_grid(L, k_recover_quad_emr, units)), bl, 0, L.stream,
                            L.jobs, L.njobs, L.ws, units, L.ujob[UNIT_QROW]);
+        if (fix_rows)
+            hipLaunchKernelGGL(k_recover_fix, dim3((fix_rows + 255) / 256, fix_segs - 1, (unsigned)L.njobs), dim3(256),
+                               0, L.stream, L.jobs, L.ws);
+    }
     else
         hipLaunchKernelGGL(k_recover_band<RDHEI_LMR>, dim3(persistent_grid(L, k_recover_band<RDHEI_LMR>, units)), bl, 0,
                            L.stream, L.jobs, L.njobs, L.ws, units, UJ);

@@ -141,6 +141,29 @@ def test_emr_8192_full_image(R, ctx):
     _roundtrip(R, ctx, I, 303, 404, frac=0.77)
 
 
+def test_emr_rows_without_labels_across_segments(R, ctx):
+    """512 x 1536 (three quad segments per band pair): constant rows, labelled
+    0 everywhere but column 0, and rows whose first label in a segment lies
+    deep inside it, so recovery carries values across whole segments and
+    completes their leading pixels afterwards."""
+    M, N = 512, 1536
+    rng = np.random.default_rng(31)
+    I = np.empty((M, N), np.uint8)
+    for r in range(M):
+        kind = r % 4
+        if kind == 0:
+            I[r] = (37 * r) % 256
+        elif kind == 1:
+            I[r] = rng.integers(0, 256, N)
+        elif kind == 2:
+            I[r] = (11 * r) % 256
+            I[r, 700:] = (11 * r + 128) % 256
+        else:
+            I[r] = (5 * r) % 256
+            I[r, 1100] = (5 * r + 64) % 256
+    _roundtrip(R, ctx, I, 808, 909)
+
+
 def test_fast_and_per_pixel_paths_agree(R):
     ctx2 = R.Context(0)
     ctx2.set_option(R.OPT_PER_PIXEL, 1)
