@@ -118,7 +118,7 @@ struct Layout {
     std::vector<int> per_pixel;        // jobs on the per-pixel path
     uint64_t ws_bytes = 0;
     uint32_t units[UNIT_KINDS] = {};
-    uint64_t g_status = 0, g_ticket = 0, g_part = 0;   // hiding workspace (embed/extract)
+    uint64_t g_status = 0, g_part = 0;   // hiding workspace (embed/extract)
     int op = 0;
     int method = RDHEI_EMR;
 };
@@ -142,7 +142,7 @@ bool whole_eligible(int op, const rdhei_job &q) {
     if (op != RDHEI_OP_EMBED && op != RDHEI_OP_EXTRACT) return false;
     const uint64_t MN = (uint64_t)q.height * (uint64_t)q.width;
     const void *pin = op == RDHEI_OP_EMBED ? (const void *)q.out : (const void *)q.in;
-    return (MN + seg_pixels() - 1) / seg_pixels() <= (uint64_t)seq_max_segments() && MN % 16 == 0 &&
+    return MN <= whole_max_pixels() && MN % 16 == 0 &&
            aligned16(pin) && aligned16(q.out);
 }
 
@@ -214,8 +214,8 @@ int make_layout(int op, const rdhei_job *in, int n, const LayoutOpts &opt, Layou
                 ws = align_up(ws + MN, 256);
             }
         }
-        // hiding: whole small images go to one workgroup each (UNIT_IMG), large
-        // images are cut into look-back segments (UNIT_SEG)
+        // hiding: whole small images go to one wave each (UNIT_IMG), others
+        // are cut into 4096-pixel steps (UNIT_SEG)
         const bool hide = op == RDHEI_OP_EMBED || op == RDHEI_OP_EXTRACT;
         const bool whole = whole_ok && whole_eligible(op, q);
         const bool quads = J.fast && (op == RDHEI_OP_ENCRYPT || (op == RDHEI_OP_RECOVER && q.method == RDHEI_EMR));
@@ -236,7 +236,7 @@ int make_layout(int op, const rdhei_job *in, int n, const LayoutOpts &opt, Layou
     }
     if (op == RDHEI_OP_EMBED || op == RDHEI_OP_EXTRACT) {
         uint64_t end;
-        hide_ws_layout(L.units[UNIT_SEG], ws, L.g_status, L.g_ticket, L.g_part, end);
+        hide_ws_layout(L.units[UNIT_SEG], ws, L.g_status, L.g_part, end);
         ws = end;
     }
     L.ws_bytes = std::max<uint64_t>(ws, 256);
@@ -446,7 +446,6 @@ int stage(rdhei_ctx *ctx, const Layout &Ly, DevBuf &jobs, DevBuf &ws, hipStream_
     L.stream = st;
     L.max_grid = ctx->max_grid;
     L.g_status = Ly.g_status;
-    L.g_ticket = Ly.g_ticket;
     L.g_part = Ly.g_part;
     return RDHEI_OK;
 }
@@ -652,7 +651,6 @@ Layout subset_layout(const Layout &full, const std::vector<int> &idx) {
     S.method = full.method;
     S.ws_bytes = full.ws_bytes;
     S.g_status = full.g_status;
-    S.g_ticket = full.g_ticket;
     S.g_part = full.g_part;
     const bool rot = full.op == RDHEI_OP_ENCRYPT || full.op == RDHEI_OP_RECOVER;
     for (size_t q = 0; q < idx.size(); ++q) {
@@ -934,7 +932,6 @@ int plan_issue(rdhei_plan *P, hipStream_t st) {
     L.max_grid = P->max_grid;
     const Layout &Ly = P->layout;
     L.g_status = Ly.g_status;
-    L.g_ticket = Ly.g_ticket;
     L.g_part = Ly.g_part;
     if (P->flags == RDHEI_PLAN_PER_IMAGE) {
         for (const rdhei_plan::One &o : P->per_image) {
@@ -942,7 +939,6 @@ int plan_issue(rdhei_plan *P, hipStream_t st) {
             for (int k = 0; k < UNIT_KINDS; ++k) L.ujob[k] = nullptr;
             L.njobs = 1;
             L.g_status = o.layout.g_status;
-            L.g_ticket = o.layout.g_ticket;
             L.g_part = o.layout.g_part;
             for (const Stage &s : o.stages) s.fn(L);
         }
@@ -1143,7 +1139,6 @@ int rdhei_run_batch(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t n
     L.stream = st;
     L.max_grid = ctx->max_grid;
     L.g_status = Ly.g_status;
-    L.g_ticket = Ly.g_ticket;
     L.g_part = Ly.g_part;
     for (const Stage &sg : stages_of(Ly, Ly.units, Ly.per_pixel)) sg.fn(L);
     HIPCHK(hipGetLastError());
@@ -1253,7 +1248,6 @@ int rdhei_plan_run_stage(rdhei_plan *P, int32_t k, void *stream) {
     Launch L = P->base;
     L.njobs = (int32_t)P->layout.jobs.size();
     L.g_status = P->layout.g_status;
-    L.g_ticket = P->layout.g_ticket;
     L.g_part = P->layout.g_part;
     L.ws = P->ws.p;
     L.stream = reinterpret_cast<hipStream_t>(stream);

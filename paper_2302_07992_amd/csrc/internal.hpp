@@ -92,7 +92,7 @@ struct Launch {
     uint8_t *ws;              // device workspace base
     hipStream_t stream;
     int max_grid;             // cap on workgroups of a grid-stride launch
-    uint64_t g_status = 0, g_ticket = 0, g_part = 0;   // launch-wide hiding workspace offsets
+    uint64_t g_status = 0, g_part = 0;   // hiding workspace: step counts / ranks, partial-word records
 };
 
 void launch_tile_prep(const Launch &L, uint32_t units, bool stats);
@@ -112,11 +112,11 @@ void launch_encrypt_tiles(const Launch &L, uint32_t units, int mode);
 // fix_rows, fix_segs: most rows and most quad segments per band pair of the EMR
 // images cut into segments (fix_rows 0: none)
 void launch_recover_bands(const Launch &L, uint32_t units, int method, uint32_t fix_rows, uint32_t fix_segs);
-uint64_t seg_pixels();
-int seq_max_segments();
+uint64_t seg_pixels();          // pixels per hiding step (work unit)
+uint64_t whole_max_pixels();    // largest image walked whole by one wave
 uint32_t whole_image_min();
 void launch_hide_images(const Launch &L, uint32_t units, bool embed);
-void hide_ws_layout(uint32_t units, uint64_t base, uint64_t &status, uint64_t &ticket, uint64_t &part, uint64_t &end);
+void hide_ws_layout(uint32_t units, uint64_t base, uint64_t &ranks, uint64_t &part, uint64_t &end);
 void launch_embed(const Launch &L, uint32_t units);
 void launch_extract(const Launch &L, uint32_t units);
 // per-pixel path, one image (job index j of the table; host copy h)

@@ -4,26 +4,25 @@
 // top..top-rep+1 (rep = b for EMR, b-1 for LMR), so a pixel's bit offset is
 // rep times the number of redundant pixels before it: a prefix sum.
 //
-// Single pass over the image: each workgroup takes the next 16384-pixel
-// raster segment by ticket, counts its redundant pixels, and learns the count
-// before it from its predecessors by decoupled look-back (Merrill & Garland,
-// "Single-pass parallel prefix scan with decoupled look-back", 2016).  Tickets
-// hand segments out in order, so a workgroup only ever waits on segments
-// already owned by running workgroups.  The wait is bounded: past a spin limit
-// the image is flagged RDHEI_EDEVICE instead of waiting forever.
+// The work is cut into steps of 4096 raster pixels, one wave each.  Batches
+// of small images walk each image with one wave, step after step, the rank
+// carried in registers.  Otherwise (large images, small batches) three
+// launches, none of which waits on another workgroup: count the redundant
+// pixels of every step, turn each image's counts into exclusive prefix sums,
+// then hide or extract every step at its rank.
 #include "device.hpp"
 #include "hide4.hpp"
 
 namespace rdhei {
 
-constexpr int kSegLoads = 4;                                       // 16-byte loads per thread
-constexpr uint64_t kSegPx = (uint64_t)kThreads * 16 * kSegLoads;   // 16384 pixels
-constexpr int kWinWords = (int)((kSegPx * 7 + 127) / 128) * 4 + 8; // payload window (words)
-constexpr uint32_t kSpinLimit = 1u << 24;
-
-// status word of a segment: bit 63 = inclusive prefix ready, bit 62 =
-// aggregate ready, low 62 bits = the value.
-constexpr uint64_t kAgg = 1ull << 62, kInc = 1ull << 63, kValMask = kAgg - 1;
+// A step: four 16-byte loads per lane of a wave; lane l, load k covers
+// pixels 1024 k + 16 l .. +15 of the step.
+constexpr int kWLoads = 4;
+constexpr uint64_t kWSegPx = 64ull * 16 * kWLoads;                   // 4096 pixels
+// payload window of one step (at most 7 bits per pixel), in 32-bit words
+constexpr int kWWinWords = (int)((kWSegPx * 7 + 127) / 128 + 1) * 4 + 8;
+// images of at most this many pixels may be walked whole by one wave
+constexpr uint64_t kWholeMaxPx = 1ull << 20;
 
 struct HideParams {
     uint32_t rep, shift;      // replaceable bits per redundant pixel, position of the lowest
@@ -206,217 +205,10 @@ __device__ __forceinline__ void extract16(const uint32_t w[4], uint32_t rm, uint
     }
 }
 
-// Exclusive scan over the workgroup of four 16-bit counters packed in a u64
-// (field k = count of load k); returns the thread's exclusive prefix per field
-// and the workgroup totals per field.
-__device__ __forceinline__ uint64_t block_scan4(uint64_t v, uint64_t &total, uint64_t *sh) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint64_t x = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint64_t y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-    }
-    if (lane == 63) sh[wave] = x;
-    __syncthreads();
-    uint64_t base = 0, tot = 0;
-#pragma unroll
-    for (int w = 0; w < kThreads / 64; ++w) {
-        const uint64_t t = sh[w];
-        base += (w < wave) ? t : 0ull;
-        tot += t;
-    }
-    __syncthreads();
-    total = tot;
-    return base + x - v;
-}
-
-// Publish a segment's aggregate, look back over its predecessors in the same
-// image, publish its inclusive prefix; returns the exclusive prefix.  Run by
-// all 64 lanes of one wave: each pass reads 64 predecessors at once and stops
-// at the nearest one that already holds an inclusive prefix.  A status word
-// carries its own value, so relaxed device-scope atomics suffice.
-__device__ uint64_t look_back(uint64_t *status, uint32_t u, uint32_t first_u, uint64_t agg, bool &timed_out) {
-    const int lane = threadIdx.x & 63;
-    timed_out = false;
-    if (u == first_u) {
-        if (lane == 0) __hip_atomic_store(&status[u], kInc | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return 0;
-    }
-    if (lane == 0) __hip_atomic_store(&status[u], kAgg | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint64_t prefix = 0;
-    int64_t base = (int64_t)u - 1;          // this pass covers base, base-1, ..., base-63
-    uint32_t spins = 0;
-    while (true) {
-        const int64_t idx = base - lane;
-        uint64_t s = kInc;                   // before the image's first segment: nothing to add
-        if (idx >= (int64_t)first_u)
-            s = __hip_atomic_load(&status[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint64_t incl = __ballot((s & kInc) != 0);
-        const uint64_t ready = __ballot((s & (kInc | kAgg)) != 0);
-        const int d = incl ? __ffsll((unsigned long long)incl) - 1 : 64;   // nearest inclusive
-        const uint64_t need = d >= 63 ? ~0ull : ((2ull << d) - 1);
-        if ((ready & need) != need) {
-            if (++spins > kSpinLimit) { timed_out = true; break; }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-        }
-        uint64_t v = (lane <= d) ? (s & kValMask) : 0ull;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        prefix += v;
-        if (d < 64) break;
-        base -= 64;
-    }
-    if (lane == 0)
-        __hip_atomic_store(&status[u], kInc | (prefix + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return prefix;
-}
-
-// Resets the ticket counter and the segment status words of a launch.
-__global__ void k_hide_reset(uint64_t *status, uint32_t units, uint32_t *ticket) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < units) status[i] = 0;
-    if (i == 0) *ticket = 0;
-}
-
-// One segment's pixels, masks and ranks.
-struct SegState {
-    uint4 px[kSegLoads];
-    uint32_t rm[kSegLoads];
-    uint64_t rank[kSegLoads];   // rank (in the image) of the thread's first redundant pixel of load k
-    uint64_t seg_rank;          // redundant pixels before this segment
-    uint64_t seg_count;         // redundant pixels in this segment
-    uint64_t s0, s1, total;
-    bool timed_out;
-};
-
-// Load, count and look back for segment `seg` (work unit u) of job J.
-__device__ __forceinline__ void seg_count(const Job &J, const uint8_t *img, uint32_t u, uint32_t seg, uint64_t *status,
-                                          uint64_t *sh, uint64_t *shv, SegState &S) {
-    const int tid = threadIdx.x;
-    S.total = (uint64_t)J.M * (uint64_t)J.N;
-    S.s0 = (uint64_t)seg * kSegPx;
-    S.s1 = S.s0 + kSegPx < S.total ? S.s0 + kSegPx : S.total;
-#pragma unroll
-    for (int k = 0; k < kSegLoads; ++k) {
-        const uint64_t pos = S.s0 + (uint64_t)k * (kThreads * 16) + 16 * (uint64_t)tid;
-        S.px[k] = pos < S.s1 ? load16(img, pos, S.s1) : make_uint4(0x01010101u, 0x01010101u, 0x01010101u, 0x01010101u);
-    }
-    uint64_t packed = 0;
-#pragma unroll
-    for (int k = 0; k < kSegLoads; ++k) {
-        const uint64_t pos = S.s0 + (uint64_t)k * (kThreads * 16) + 16 * (uint64_t)tid;
-        S.rm[k] = redundant16(J, S.px[k], pos, S.s1);
-        packed |= (uint64_t)__popc(S.rm[k]) << (16 * k);
-    }
-    uint64_t tot;
-    const uint64_t ex = block_scan4(packed, tot, sh);
-    uint64_t chunk_base = 0;
-#pragma unroll
-    for (int k = 0; k < kSegLoads; ++k) {
-        S.rank[k] = chunk_base + ((ex >> (16 * k)) & 0xFFFFu);
-        chunk_base += (tot >> (16 * k)) & 0xFFFFu;
-    }
-    S.seg_count = uni64(chunk_base);
-    if (tid < 64) {
-        bool to;
-        const uint64_t pre = look_back(status, u, u - seg, chunk_base, to);
-        if (tid == 0) {
-            shv[0] = pre;
-            shv[1] = to ? 1u : 0u;
-        }
-    }
-    __syncthreads();
-    S.seg_rank = uni64(shv[0]);
-    S.timed_out = uni((uint32_t)shv[1]) != 0;
-#pragma unroll
-    for (int k = 0; k < kSegLoads; ++k) S.rank[k] += S.seg_rank;
-    __syncthreads();
-}
-
-__device__ __forceinline__ uint32_t grab_ticket(uint32_t *ticket, uint32_t *sh_t) {
-    if (threadIdx.x == 0) *sh_t = atomicAdd(ticket, 1u);
-    __syncthreads();
-    const uint32_t u = uni(*sh_t);
-    __syncthreads();
-    return u;
-}
-
-// Hide the payload bits that fall in one segment.  All branches that guard a
-// barrier test wave-uniform values.
-__device__ __forceinline__ void embed_unit(const Job &J, const HideParams &hp, uint32_t u, uint32_t seg,
-                                           uint64_t *status, uint64_t *sh, uint64_t *shv, uint32_t *win,
-                                           const uint32_t *htab) {
-    const int tid = threadIdx.x;
-    SegState S;
-    seg_count(J, J.out, u, seg, status, sh, shv, S);
-    if (S.timed_out) {
-        if (tid == 0) J.meta->status = RDHEI_EDEVICE;
-        return;
-    }
-    const int64_t wstart = (int64_t)(S.seg_rank * hp.rep);
-    int64_t wend = (int64_t)((S.seg_rank + S.seg_count) * hp.rep);
-    if (wend > hp.nbits) wend = hp.nbits;
-    if (wstart >= wend) return;
-    // stage (payload XOR message keystream) for the window, 16-byte blocks, big-endian words
-    const int64_t fb = wstart >> 7, lb = (wend - 1) >> 7;
-    for (int64_t q = tid; q <= lb - fb; q += kThreads) {
-        const uint64_t blk = (uint64_t)(fb + q);
-        const uint4 mv = gload<uint4>(J.msg + 16 * blk);
-        const U4 ks = stream_block(J.key, kDomainMessage, blk);
-        uint32_t *wp = win + 1 + 4 * q;   // word 0 is a guard
-        wp[0] = __builtin_bswap32(mv.x ^ ks.x);
-        wp[1] = __builtin_bswap32(mv.y ^ ks.y);
-        wp[2] = __builtin_bswap32(mv.z ^ ks.z);
-        wp[3] = __builtin_bswap32(mv.w ^ ks.w);
-    }
-    __syncthreads();
-    const Hide4 hk = hide4_params(hp);
-    const int64_t wbase = fb << 7;
-    const uint32_t rend = (uint32_t)(wend - wbase);
-#pragma unroll
-    for (int k = 0; k < kSegLoads; ++k) {
-        const uint32_t rm = S.rm[k];
-        const int64_t bit = (int64_t)(S.rank[k] * hp.rep);
-        if (!rm || bit >= wend) continue;
-        uint32_t w[4] = {S.px[k].x, S.px[k].y, S.px[k].z, S.px[k].w};
-        embed16(w, rm, (uint32_t)(bit - wbase), rend, win, hk, htab);
-        const uint64_t pos = S.s0 + (uint64_t)k * (kThreads * 16) + 16 * (uint64_t)tid;
-        store16(J.out, pos, S.s1, make_uint4(w[0], w[1], w[2], w[3]));
-    }
-}
-
-// ---- embedding -------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_embed(const Job *__restrict__ jobs, int njobs, uint32_t units,
-                                                     const uint32_t *__restrict__ ujob, uint64_t *__restrict__ status,
-                                                     uint32_t *__restrict__ ticket) {
-    __shared__ uint64_t sh[kThreads / 64];
-    __shared__ uint64_t shv[2];
-    __shared__ uint32_t sh_t;
-    __shared__ uint32_t win[kWinWords];
-    __shared__ uint32_t htab[hide4::kWords];
-    const int tid = threadIdx.x;
-    stage_hide_tables(htab, tid);   // read after the ticket barrier
-    while (true) {
-        const uint32_t u = grab_ticket(ticket, &sh_t);
-        if (u >= units) break;
-        const int j = (int)uni((uint32_t)find_job<UNIT_SEG>(jobs, njobs, u, ujob));
-        const Job &J = jobs[j];
-        const HideParams hp = hide_params(J);
-        if (!hp.ok) {
-            if (tid == 0 && u == J.ubase[UNIT_SEG] && J.meta->status == RDHEI_OK) J.meta->status = RDHEI_ECAPACITY;
-        } else {
-            embed_unit(J, hp, u, u - J.ubase[UNIT_SEG], status, sh, shv, win, htab);
-        }
-        __syncthreads();
-    }
-}
-
 // ---- extraction -------------------------------------------------------------------
-// Message words a segment only partly owns (shared with a neighbouring
-// segment, or the message's last word) go to a side record; two small passes
-// clear, then OR them into place.
+// Message words a step only partly owns (shared with a neighbouring step, or
+// the message's last word) go to a side record; two small passes clear, then
+// OR them into place.
 struct PartWord {
     int64_t word;      // word index into the message (-1: none)
     uint32_t bits;     // already XORed with the keystream and masked to the owner's bits
@@ -441,86 +233,6 @@ __device__ __forceinline__ uint32_t ks_word(uint64_t key, int64_t w) {
     return __builtin_bswap32(kw);
 }
 
-// Extract the payload bits of one segment.
-__device__ __forceinline__ void extract_unit(const Job &J, const HideParams &hp, int j, uint32_t u, uint32_t seg,
-                                             uint64_t *status, uint64_t *sh, uint64_t *shv, uint32_t *win,
-                                             PartWord *part, const uint32_t *htab) {
-    const int tid = threadIdx.x;
-    SegState S;
-    seg_count(J, J.in, u, seg, status, sh, shv, S);
-    if (S.timed_out) {
-        if (tid == 0) J.meta->status = RDHEI_EDEVICE;
-        return;
-    }
-    const int64_t wstart = (int64_t)(S.seg_rank * hp.rep);
-    int64_t wend = (int64_t)((S.seg_rank + S.seg_count) * hp.rep);
-    if (wend > hp.nbits) wend = hp.nbits;
-    if (wstart >= wend) return;
-    const int64_t W0 = wstart >> 5, W1 = (wend + 31) >> 5;
-    for (int64_t q = tid; q < W1 - W0 + 1; q += kThreads) win[q] = 0u;
-    __syncthreads();
-    const Hide4 hk = hide4_params(hp);
-    const uint32_t rend = (uint32_t)(wend - 32 * W0);
-#pragma unroll
-    for (int k = 0; k < kSegLoads; ++k) {
-        const uint32_t rm = S.rm[k];
-        const int64_t bit = (int64_t)(S.rank[k] * hp.rep);
-        if (!rm || bit >= wend) continue;
-        const uint32_t w[4] = {S.px[k].x, S.px[k].y, S.px[k].z, S.px[k].w};
-        extract16(w, rm, (uint32_t)(bit - 32 * W0), rend, win, hk, htab);
-    }
-    __syncthreads();
-    uint32_t *msgw = reinterpret_cast<uint32_t *>(J.msg);
-    // one keystream block per four message words
-    const int64_t B0 = W0 >> 2, B1 = (W1 - 1) >> 2;
-    for (int64_t bq = tid; bq <= B1 - B0; bq += kThreads) {
-        const U4 ks = stream_block(J.key, kDomainMessage, (uint64_t)(B0 + bq));
-        const uint32_t kw[4] = {ks.x, ks.y, ks.z, ks.w};
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t w = 4 * (B0 + bq) + i;
-            if (w < W0 || w >= W1) continue;
-            const uint32_t own = be_mask(w, wstart, wend);
-            const uint32_t v = (win[w - W0] ^ __builtin_bswap32(kw[i])) & own;
-            if (own == 0xFFFFFFFFu) {
-                gstore<uint32_t>(msgw + w, __builtin_bswap32(v));
-            } else {
-                PartWord pw;
-                pw.word = w;
-                pw.bits = __builtin_bswap32(v);
-                pw.job = (uint32_t)j;
-                part[2 * u + (w == W0 ? 0 : 1)] = pw;
-            }
-        }
-    }
-}
-
-__global__ __launch_bounds__(kThreads) void k_extract(const Job *__restrict__ jobs, int njobs, uint32_t units,
-                                                       const uint32_t *__restrict__ ujob, uint64_t *__restrict__ status,
-                                                       uint32_t *__restrict__ ticket, PartWord *__restrict__ part) {
-    __shared__ uint64_t sh[kThreads / 64];
-    __shared__ uint64_t shv[2];
-    __shared__ uint32_t sh_t;
-    __shared__ uint32_t win[kWinWords];
-    __shared__ uint32_t htab[hide4::kWords];
-    const int tid = threadIdx.x;
-    stage_hide_tables(htab, tid);   // read after the ticket barrier
-    while (true) {
-        const uint32_t u = grab_ticket(ticket, &sh_t);
-        if (u >= units) break;
-        if (tid < 2) part[2 * u + tid].word = -1;
-        const int j = (int)uni((uint32_t)find_job<UNIT_SEG>(jobs, njobs, u, ujob));
-        const Job &J = jobs[j];
-        const HideParams hp = hide_params(J);
-        if (!hp.ok) {
-            if (tid == 0 && u == J.ubase[UNIT_SEG] && J.meta->status == RDHEI_OK) J.meta->status = RDHEI_ECAPACITY;
-        } else {
-            extract_unit(J, hp, j, u, u - J.ubase[UNIT_SEG], status, sh, shv, win, part, htab);
-        }
-        __syncthreads();
-    }
-}
-
 __global__ void k_extract_fix(const Job *__restrict__ jobs, const PartWord *__restrict__ part, uint32_t n, int phase) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -533,16 +245,11 @@ __global__ void k_extract_fix(const Job *__restrict__ jobs, const PartWord *__re
 
 
 // ---- whole images, one wave each ----------------------------------------------
-// Images of at most kSeqMaxSeg look-back segments, in batches large enough to
-// fill the device, are walked by one wave each, 4096 pixels per step: the
-// rank carries over in registers, the next step's pixels are loaded while the
-// current one is processed, ranks inside a step come from a wave scan (DPP),
-// and nothing waits on another wave.  Larger images and small batches use the
-// look-back kernels above.
-constexpr int kSeqMaxSeg = 64;
-constexpr int kWLoads = 4;                                           // 16-byte loads per lane
-constexpr uint64_t kWSegPx = 64ull * 16 * kWLoads;                   // 4096 pixels
-constexpr int kWWinWords = (int)((kWSegPx * 7 + 127) / 128 + 1) * 4 + 8;
+// Images of at most kWholeMaxPx pixels, in batches large enough to fill the
+// device, are walked by one wave each, one step after the other: the rank
+// carries over in registers, the next step's pixels (and, embedding, message
+// blocks) are loaded while the current one is processed, ranks inside a step
+// come from a wave scan (DPP), and nothing waits on another wave.
 
 // Inclusive sum over the 64 lanes of a wave.
 __device__ __forceinline__ uint32_t wave_scan_incl(uint32_t x) {
@@ -569,6 +276,24 @@ __device__ __forceinline__ void wseg_load(const uint8_t *img, uint64_t s0, uint6
         const uint64_t pos = s0 + (uint64_t)k * 1024u + 16 * (uint64_t)lane;
         px[k] = pos < s1 ? gload<uint4>(img + pos) : make_uint4(0x01010101u, 0x01010101u, 0x01010101u, 0x01010101u);
     }
+}
+
+// Ranks of the step's redundant pixels: for each load k of the lane, the
+// redundant pixels of the step before its first pixel; T = the step's total.
+__device__ __forceinline__ void step_ranks(const uint32_t rm[kWLoads], uint32_t lr[kWLoads], uint32_t &T) {
+    // counts of loads 0, 1 and 2, 3 in 16-bit halves (at most 1024 each)
+    const uint32_t c01 = (uint32_t)__popc(rm[0]) | ((uint32_t)__popc(rm[1]) << 16);
+    const uint32_t c23 = (uint32_t)__popc(rm[2]) | ((uint32_t)__popc(rm[3]) << 16);
+    const uint32_t i01 = wave_scan_incl(c01), i23 = wave_scan_incl(c23);
+    const uint32_t t01 = uni((uint32_t)__builtin_amdgcn_readlane((int)i01, 63));
+    const uint32_t t23 = uni((uint32_t)__builtin_amdgcn_readlane((int)i23, 63));
+    const uint32_t e01 = i01 - c01, e23 = i23 - c23;
+    const uint32_t tot0 = t01 & 0xFFFFu, tot1 = t01 >> 16, tot2 = t23 & 0xFFFFu, tot3 = t23 >> 16;
+    lr[0] = e01 & 0xFFFFu;
+    lr[1] = tot0 + (e01 >> 16);
+    lr[2] = tot0 + tot1 + (e23 & 0xFFFFu);
+    lr[3] = tot0 + tot1 + tot2 + (e23 >> 16);
+    T = tot0 + tot1 + tot2 + tot3;
 }
 
 template <bool EMBED>
@@ -611,17 +336,8 @@ __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &
 #pragma unroll
         for (int k = 0; k < kWLoads; ++k)
             rm[k] = redundant16(J, px[k], s0 + (uint64_t)k * 1024u + 16 * (uint64_t)lane, s1);
-        // ranks: counts of loads 0, 1 and 2, 3 in 16-bit halves (at most 1024 each)
-        const uint32_t c01 = (uint32_t)__popc(rm[0]) | ((uint32_t)__popc(rm[1]) << 16);
-        const uint32_t c23 = (uint32_t)__popc(rm[2]) | ((uint32_t)__popc(rm[3]) << 16);
-        const uint32_t i01 = wave_scan_incl(c01), i23 = wave_scan_incl(c23);
-        const uint32_t t01 = uni((uint32_t)__builtin_amdgcn_readlane((int)i01, 63));
-        const uint32_t t23 = uni((uint32_t)__builtin_amdgcn_readlane((int)i23, 63));
-        const uint32_t e01 = i01 - c01, e23 = i23 - c23;
-        const uint32_t tot0 = t01 & 0xFFFFu, tot1 = t01 >> 16, tot2 = t23 & 0xFFFFu, tot3 = t23 >> 16;
-        const uint32_t lr[kWLoads] = {e01 & 0xFFFFu, tot0 + (e01 >> 16), tot0 + tot1 + (e23 & 0xFFFFu),
-                                      tot0 + tot1 + tot2 + (e23 >> 16)};
-        const uint32_t T = tot0 + tot1 + tot2 + tot3;
+        uint32_t lr[kWLoads], T;
+        step_ranks(rm, lr, T);
         const int64_t wstart = (int64_t)(rank * rep);
         if (wstart >= hp.nbits) break;
         int64_t wend = (int64_t)((rank + T) * rep);
@@ -717,6 +433,165 @@ __global__ __launch_bounds__(64) void k_hide_wave(const Job *__restrict__ jobs, 
     }
 }
 
+// ---- steps of any image: count, scan, hide -------------------------------------
+// Every step is one work unit (UNIT_SEG).  Pixels of a step past the image's
+// end read as never redundant, so any image size works.
+__device__ __forceinline__ void step_load(const uint8_t *img, uint64_t s0, uint64_t s1, int lane, uint4 px[kWLoads]) {
+#pragma unroll
+    for (int k = 0; k < kWLoads; ++k) {
+        const uint64_t pos = s0 + (uint64_t)k * 1024u + 16 * (uint64_t)lane;
+        px[k] = pos < s1 ? load16(img, pos, s1) : make_uint4(0x01010101u, 0x01010101u, 0x01010101u, 0x01010101u);
+    }
+}
+
+// Pass 1: redundant pixels of every step.
+__global__ __launch_bounds__(kThreads) void k_seg_count(const Job *__restrict__ jobs, int njobs, uint32_t units,
+                                                         const uint32_t *__restrict__ ujob, uint32_t *__restrict__ cnt) {
+    const int lane = threadIdx.x & 63, wave = (int)uni(threadIdx.x >> 6);
+    const uint32_t stride = gridDim.x * (uint32_t)(kThreads / 64);
+    for (uint32_t u = blockIdx.x * (uint32_t)(kThreads / 64) + (uint32_t)wave; u < units; u += stride) {
+        const Job &J = jobs[uni((uint32_t)find_job<UNIT_SEG>(jobs, njobs, u, ujob))];
+        const uint64_t total = (uint64_t)J.M * (uint64_t)J.N;
+        const uint64_t s0 = (uint64_t)(u - J.ubase[UNIT_SEG]) * kWSegPx;
+        const uint64_t s1 = s0 + kWSegPx < total ? s0 + kWSegPx : total;
+        uint4 px[kWLoads];
+        step_load(J.in, s0, s1, lane, px);
+        uint32_t c = 0;
+#pragma unroll
+        for (int k = 0; k < kWLoads; ++k)
+            c += (uint32_t)__popc(redundant16(J, px[k], s0 + (uint64_t)k * 1024u + 16 * (uint64_t)lane, s1));
+        c = wave_scan_incl(c);
+        if (lane == 63) cnt[u] = c;
+    }
+}
+
+// Pass 2: each image's step counts -> exclusive prefix sums, in place.  One
+// workgroup per image; thread t takes a contiguous run of steps.
+__global__ __launch_bounds__(kThreads) void k_seg_scan(const Job *__restrict__ jobs, uint32_t *__restrict__ cnt) {
+    __shared__ uint32_t wsum[kThreads / 64];
+    const Job &J = jobs[blockIdx.x];
+    const uint32_t n = J.ucount[UNIT_SEG];
+    if (n == 0) return;   // uniform over the workgroup
+    uint32_t *c = cnt + J.ubase[UNIT_SEG];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t per = (n + kThreads - 1) / kThreads;
+    const uint32_t a = tid * per < n ? tid * per : n, b = a + per < n ? a + per : n;
+    uint32_t sum = 0;
+    for (uint32_t i = a; i < b; ++i) sum += c[i];
+    const uint32_t incl = wave_scan_incl(sum);
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t base = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < kThreads / 64; ++w) base += w < wave ? wsum[w] : 0u;
+    uint32_t ex = base + incl - sum;
+    for (uint32_t i = a; i < b; ++i) {
+        const uint32_t v = c[i];
+        c[i] = ex;
+        ex += v;
+    }
+}
+
+// Pass 3: hide (EMBED) or extract the payload bits of every step at its rank.
+template <bool EMBED>
+__global__ __launch_bounds__(kThreads) void k_seg_hide(const Job *__restrict__ jobs, int njobs, uint32_t units,
+                                                        const uint32_t *__restrict__ ujob,
+                                                        const uint32_t *__restrict__ rank, PartWord *__restrict__ part) {
+    __shared__ __align__(16) uint32_t wins[kThreads / 64][kWWinWords];
+    __shared__ uint32_t htab[hide4::kWords];
+    const int lane = threadIdx.x & 63, wave = (int)uni(threadIdx.x >> 6);
+    uint32_t *win = wins[wave];
+    stage_hide_tables(htab, (int)threadIdx.x);
+    __syncthreads();
+    const uint32_t stride = gridDim.x * (uint32_t)(kThreads / 64);
+    for (uint32_t u = blockIdx.x * (uint32_t)(kThreads / 64) + (uint32_t)wave; u < units; u += stride) {
+        if (!EMBED && lane < 2) part[2 * u + lane].word = -1;
+        const int j = (int)uni((uint32_t)find_job<UNIT_SEG>(jobs, njobs, u, ujob));
+        const Job &J = jobs[j];
+        const HideParams hp = hide_params(J);
+        if (!hp.ok) {
+            if (lane == 0 && u == J.ubase[UNIT_SEG] && J.meta->status == RDHEI_OK) J.meta->status = RDHEI_ECAPACITY;
+            continue;
+        }
+        const uint32_t rep = hp.rep;
+        const Hide4 hk = hide4_params(hp);
+        const uint64_t total = (uint64_t)J.M * (uint64_t)J.N;
+        const uint64_t s0 = (uint64_t)(u - J.ubase[UNIT_SEG]) * kWSegPx;
+        const uint64_t s1 = s0 + kWSegPx < total ? s0 + kWSegPx : total;
+        uint4 px[kWLoads];
+        step_load(J.in, s0, s1, lane, px);
+        uint32_t rm[kWLoads], lr[kWLoads], T;
+#pragma unroll
+        for (int k = 0; k < kWLoads; ++k) rm[k] = redundant16(J, px[k], s0 + (uint64_t)k * 1024u + 16 * (uint64_t)lane, s1);
+        step_ranks(rm, lr, T);
+        const uint64_t r0 = uni(rank[u]);
+        const int64_t wstart = (int64_t)(r0 * rep);
+        int64_t wend = (int64_t)((r0 + T) * rep);
+        if (wend > hp.nbits) wend = hp.nbits;
+        if (T == 0 || wstart >= wend) continue;
+        if (EMBED) {
+            // window bits relative to the first staged 16-byte block
+            const int64_t fb = wstart >> 7, lb = (wend - 1) >> 7;
+            const uint32_t off0 = (uint32_t)(wstart - (fb << 7)), rend = (uint32_t)(wend - (fb << 7));
+            for (int64_t q = lane; q <= lb - fb; q += 64) {
+                const uint64_t blk = (uint64_t)(fb + q);
+                const uint4 mv = gload<uint4>(J.msg + 16 * blk);
+                const U4 ks = stream_block(J.key, kDomainMessage, blk);
+                *reinterpret_cast<uint4 *>(win + 4 + 4 * q) =
+                    make_uint4(__builtin_bswap32(mv.x ^ ks.x), __builtin_bswap32(mv.y ^ ks.y),
+                               __builtin_bswap32(mv.z ^ ks.z), __builtin_bswap32(mv.w ^ ks.w));
+            }
+            wave_sync();
+#pragma unroll
+            for (int k = 0; k < kWLoads; ++k) {
+                const uint32_t rel = off0 + lr[k] * rep;
+                if (!rm[k] || rel >= rend) continue;
+                uint32_t w[4] = {px[k].x, px[k].y, px[k].z, px[k].w};
+                embed16(w, rm[k], rel, rend, win + 3, hk, htab);   // word 0 of the window is a guard
+                store16(J.out, s0 + (uint64_t)k * 1024u + 16 * (uint64_t)lane, s1, make_uint4(w[0], w[1], w[2], w[3]));
+            }
+        } else {
+            const int64_t W0 = wstart >> 5, W1 = (wend + 31) >> 5;
+            const uint32_t off0 = (uint32_t)(wstart & 31), rend = (uint32_t)(wend - 32 * W0);
+            for (int64_t q = lane; q < W1 - W0 + 1; q += 64) win[q] = 0u;
+            wave_sync();
+#pragma unroll
+            for (int k = 0; k < kWLoads; ++k) {
+                const uint32_t rel = off0 + lr[k] * rep;
+                if (!rm[k] || rel >= rend) continue;
+                const uint32_t w[4] = {px[k].x, px[k].y, px[k].z, px[k].w};
+                extract16(w, rm[k], rel, rend, win, hk, htab);
+            }
+            wave_sync();
+            // one keystream block per four message words; words shared with a
+            // neighbouring step go to the side records
+            uint32_t *msgw = reinterpret_cast<uint32_t *>(J.msg);
+            const int64_t B0 = W0 >> 2, B1 = (W1 - 1) >> 2;
+            for (int64_t bq = lane; bq <= B1 - B0; bq += 64) {
+                const U4 ks = stream_block(J.key, kDomainMessage, (uint64_t)(B0 + bq));
+                const uint32_t kw[4] = {ks.x, ks.y, ks.z, ks.w};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int64_t w = 4 * (B0 + bq) + i;
+                    if (w < W0 || w >= W1) continue;
+                    const uint32_t own = be_mask(w, wstart, wend);
+                    const uint32_t v = (win[w - W0] ^ __builtin_bswap32(kw[i])) & own;
+                    if (own == 0xFFFFFFFFu) {
+                        gstore<uint32_t>(msgw + w, __builtin_bswap32(v));
+                    } else {
+                        PartWord pw;
+                        pw.word = w;
+                        pw.bits = __builtin_bswap32(v);
+                        pw.job = (uint32_t)j;
+                        part[2 * u + (w == W0 ? 0 : 1)] = pw;
+                    }
+                }
+            }
+        }
+        wave_sync();
+    }
+}
+
 // ---- launchers ---------------------------------------------------------------------
 static inline unsigned grid_for(const Launch &L, uint32_t units) {
     uint32_t g = units;
@@ -733,7 +608,6 @@ void launch_hide_images(const Launch &L, uint32_t units, bool embed) {
         hipLaunchKernelGGL(k_hide_wave<false>, dim3(g), dim3(64), 0, L.stream, L.jobs, L.njobs, units, L.ujob[UNIT_IMG]);
 }
 
-int seq_max_segments() { return kSeqMaxSeg; }
 
 // Batches of at least this many small images hide one image per wave: a
 // quarter of the waves of k_hide_wave resident on the device, so that the
@@ -753,35 +627,43 @@ uint32_t whole_image_min() {
     return v;
 }
 
+static inline unsigned step_grid(const Launch &L, uint32_t units) {
+    return grid_for(L, (units + kThreads / 64 - 1) / (kThreads / 64));
+}
+
 void launch_embed(const Launch &L, uint32_t units) {
     if (!units) return;
-    uint64_t *status = reinterpret_cast<uint64_t *>(L.ws + L.g_status);
-    uint32_t *ticket = reinterpret_cast<uint32_t *>(L.ws + L.g_ticket);
-    hipLaunchKernelGGL(k_hide_reset, dim3((units + 255) / 256), dim3(256), 0, L.stream, status, units, ticket);
-    hipLaunchKernelGGL(k_embed, dim3(grid_for(L, units)), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, units,
-                       L.ujob[UNIT_SEG], status, ticket);
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(L.ws + L.g_status);
+    PartWord *part = reinterpret_cast<PartWord *>(L.ws + L.g_part);
+    const unsigned g = step_grid(L, units);
+    hipLaunchKernelGGL(k_seg_count, dim3(g), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, units, L.ujob[UNIT_SEG], cnt);
+    hipLaunchKernelGGL(k_seg_scan, dim3((unsigned)L.njobs), dim3(kThreads), 0, L.stream, L.jobs, cnt);
+    hipLaunchKernelGGL(k_seg_hide<true>, dim3(g), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, units,
+                       L.ujob[UNIT_SEG], cnt, part);
 }
 
 void launch_extract(const Launch &L, uint32_t units) {
     if (!units) return;
-    uint64_t *status = reinterpret_cast<uint64_t *>(L.ws + L.g_status);
-    uint32_t *ticket = reinterpret_cast<uint32_t *>(L.ws + L.g_ticket);
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(L.ws + L.g_status);
     PartWord *part = reinterpret_cast<PartWord *>(L.ws + L.g_part);
-    hipLaunchKernelGGL(k_hide_reset, dim3((units + 255) / 256), dim3(256), 0, L.stream, status, units, ticket);
-    hipLaunchKernelGGL(k_extract, dim3(grid_for(L, units)), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, units,
-                       L.ujob[UNIT_SEG], status, ticket, part);
+    const unsigned g = step_grid(L, units);
+    hipLaunchKernelGGL(k_seg_count, dim3(g), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, units, L.ujob[UNIT_SEG], cnt);
+    hipLaunchKernelGGL(k_seg_scan, dim3((unsigned)L.njobs), dim3(kThreads), 0, L.stream, L.jobs, cnt);
+    hipLaunchKernelGGL(k_seg_hide<false>, dim3(g), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, units,
+                       L.ujob[UNIT_SEG], cnt, part);
     const uint32_t n = 2 * units;
     hipLaunchKernelGGL(k_extract_fix, dim3((n + 255) / 256), dim3(256), 0, L.stream, L.jobs, part, n, 0);
     hipLaunchKernelGGL(k_extract_fix, dim3((n + 255) / 256), dim3(256), 0, L.stream, L.jobs, part, n, 1);
 }
 
-uint64_t seg_pixels() { return kSegPx; }
+uint64_t seg_pixels() { return kWSegPx; }
+uint64_t whole_max_pixels() { return kWholeMaxPx; }
 
-// Launch-wide hiding workspace: status words, ticket, partial-word records.
-void hide_ws_layout(uint32_t units, uint64_t base, uint64_t &status, uint64_t &ticket, uint64_t &part, uint64_t &end) {
-    status = base;
-    ticket = (status + (uint64_t)units * 8 + 255) / 256 * 256;
-    part = ticket + 256;
+// Hiding workspace of a launch: the count / rank of every step, then two
+// partial-word records per step.
+void hide_ws_layout(uint32_t units, uint64_t base, uint64_t &ranks, uint64_t &part, uint64_t &end) {
+    ranks = base;
+    part = (ranks + (uint64_t)units * 4 + 255) / 256 * 256;
     end = (part + (uint64_t)units * 2 * sizeof(PartWord) + 255) / 256 * 256;
 }
 

@@ -107,10 +107,9 @@ def test_emr_partial_messages(R, ctx, frac):
 @pytest.mark.parametrize("shape", [(1024, 512), (1024, 1024), (640, 1088), (1000, 777), (2048, 1024), (1040, 1024)],
                          ids=lambda s: f"{s[0]}x{s[1]}")
 def test_emr_multi_segment_images(R, ctx, shape):
-    """Images spanning several raster segments, hidden by decoupled look-back
-    across segments (single images always take this path), including pixel
-    counts that are not a multiple of 16 and message words shared by two
-    segments."""
+    """Images spanning many 4096-pixel steps, hidden by the count / scan /
+    hide passes (single images always take this path), including pixel counts
+    that are not a multiple of 16 and message words shared by two steps."""
     M, N = shape
     I = _image(M + N, M, N, sigma=2.0)
     for frac in (1.0, 0.6):
@@ -118,8 +117,8 @@ def test_emr_multi_segment_images(R, ctx, shape):
 
 
 def test_emr_4096_full_image(R, ctx):
-    """A 4096 x 4096 image (1024 look-back segments, 64 x 64 tiles, levels up
-    to 2^12) compared with the oracle pixel for pixel."""
+    """A 4096 x 4096 image (4096 hiding steps, 64 x 64 tiles, levels up to
+    2^12) compared with the oracle pixel for pixel."""
     I = inputs.make_band_image(12, 4096, 4096, 8, 3.0, "cpu").numpy()
     _roundtrip(R, ctx, I, 101, 202, frac=1.0)
 
@@ -134,7 +133,7 @@ def test_emr_large_ragged_tile_grid(R, ctx):
 
 def test_emr_8192_full_image(R, ctx):
     """An 8192 x 8192 image (the large-image workload's smaller size: 16,384
-    tiles, 4096 look-back segments, rotation levels up to 2^13) against the
+    tiles, 16,384 hiding steps, rotation levels up to 2^13) against the
     oracle pixel for pixel, with a payload that ends inside a pixel."""
     print("[large] 8192x8192 oracle parity", flush=True)
     I = inputs.make_band_image(13, 8192, 8192, 8, 3.0, "cpu").numpy()
@@ -268,7 +267,7 @@ def test_run_batch_matches_plan(R, ctx):
 def test_batched_plan_uneven_sizes_matches_oracle(R, hide_mode):
     """One plan per op over images of different shapes (tiled and per-pixel
     in the same launch), graph-captured, replayed twice; hiding either walks
-    small images whole (one workgroup each) or in look-back segments."""
+    small images whole (one wave each) or in counted 4096-pixel steps."""
     print(f"[batched uneven] hide_mode={hide_mode}", flush=True)
     ctx = R.Context(0)
     ctx.set_option(R.OPT_HIDE_MODE, hide_mode)
