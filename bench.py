@@ -23,9 +23,9 @@ if ROOT not in sys.path:
 METRIC = "Mpixel/s embed+recover (batched vs per-image) at bit-exact; p99 latency served"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_emr_batch_4000x512.md")
-STAGE_KERNEL = {"tile_prep_stats": "rdhei::k_tile_prep<true>", "encrypt_tiles": "rdhei::k_encrypt_tile<0>",
-                "embed_images": "rdhei::k_hide_seq<true>", "extract_images": "rdhei::k_hide_seq<false>",
-                "recover_bands": "rdhei::k_recover_band_emr"}
+STAGE_KERNEL = {"tile_prep_stats": "rdhei::k_tile_prep<true>", "encrypt_tiles": "rdhei::k_encrypt_quad<0>",
+                "embed_images": "rdhei::k_hide_wave<true>", "extract_images": "rdhei::k_hide_wave<false>",
+                "recover_bands": "rdhei::k_recover_quad_emr"}
 
 
 def log(*a):

@@ -175,7 +175,7 @@ int         rdhei_plan_run_stage(rdhei_plan *plan, int32_t k, void *stream);
 
 /* Launch-shape autotuner.  Times every stage of a batched plan at several
  * workgroup counts (the launcher's default -- what fits on the device at
- * once -- and 1, 2, 4, 8 and 16 workgroups per compute unit), `reps` runs
+ * once -- and 1, 2, 4, 8, 16 and 32 workgroups per compute unit), `reps` runs
  * each, and keeps the fastest per stage (a change must win by more than 2 %).
  * Choices are cached in the context by op, stage and size class (log2 of the
  * plan's pixels and images) and reused by later plans of the same class

@@ -1284,7 +1284,7 @@ int rdhei_plan_autotune(rdhei_plan *P, int32_t reps, int32_t flags, void *stream
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    const int cand[] = {0, cus, 2 * cus, 4 * cus, 8 * cus, 16 * cus};
+    const int cand[] = {0, cus, 2 * cus, 4 * cus, 8 * cus, 16 * cus, 32 * cus};
     for (size_t k = 0; k < P->stages.size() && !rc; ++k) {
         const std::string key = std::to_string(P->layout.op) + "/" + P->stages[k].name + "/" + std::to_string(px_cls) +
                                 "/" + std::to_string(job_cls);

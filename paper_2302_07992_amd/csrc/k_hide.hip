@@ -309,18 +309,23 @@ __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &
     int64_t carry_word = -1;
     uint4 nxt[kWLoads];
     wseg_load(img, 0, total < kWSegPx ? total : kWSegPx, lane, nxt);
-    // embedding: the message blocks of the next step, loaded a step ahead
-    // (a step needs at most 4096 * 7 bits = 224 blocks from its first one)
+    // embedding: message blocks of the next step, loaded a step ahead.  A step
+    // needs at most 4096 * 7 bits = 224 blocks from its first one; as many are
+    // prefetched as the previous step used, plus two (neighbouring steps of an
+    // image hold similar numbers of redundant pixels), and a step loads any
+    // further blocks it needs itself.
     uint4 mpre[4];
-    auto msg_prefetch = [&](uint64_t first_blk) {
-        const uint64_t nblk = (uint64_t)(hp.nbits + 127) >> 7;
+    uint32_t npre = 0;
+    const uint64_t nblk = (uint64_t)(hp.nbits + 127) >> 7;
+    auto msg_prefetch = [&](uint64_t first_blk, uint32_t n) {
+        npre = n;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const uint64_t blk = first_blk + (uint64_t)(lane + 64 * i);
-            mpre[i] = blk < nblk ? gload<uint4>(J.msg + 16 * blk) : make_uint4(0, 0, 0, 0);
+            mpre[i] = (uint32_t)(lane + 64 * i) < n && blk < nblk ? gload<uint4>(J.msg + 16 * blk) : make_uint4(0, 0, 0, 0);
         }
     };
-    if (EMBED) msg_prefetch(0);
+    if (EMBED) msg_prefetch(0, (uint32_t)((kWSegPx / 2 * rep + 127) / 128));   // first step: half its pixels
     for (uint32_t seg = 0; seg < nseg; ++seg) {
         const uint64_t s0 = (uint64_t)seg * kWSegPx;
         const uint64_t s1 = s0 + kWSegPx < total ? s0 + kWSegPx : total;
@@ -351,13 +356,15 @@ __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &
             for (int i = 0; i < 4; ++i) {
                 const int64_t q = lane + 64 * i;
                 if (q > lb - fb) continue;
-                const uint4 mv = mpre[i];
+                const uint4 mv = q < (int64_t)npre ? mpre[i] : gload<uint4>(J.msg + 16 * (uint64_t)(fb + q));
                 const U4 ks = stream_block(J.key, kDomainMessage, (uint64_t)(fb + q));
                 *reinterpret_cast<uint4 *>(win + 4 + 4 * q) =
                     make_uint4(__builtin_bswap32(mv.x ^ ks.x), __builtin_bswap32(mv.y ^ ks.y),
                                __builtin_bswap32(mv.z ^ ks.z), __builtin_bswap32(mv.w ^ ks.w));
             }
-            msg_prefetch((rank * rep) >> 7);   // rank already counts this step
+            // rank already counts this step
+            const uint32_t used = (uint32_t)(lb - fb + 1) + 2u;
+            msg_prefetch((rank * rep) >> 7, used < 256u ? used : 256u);
             wave_sync();
 #pragma unroll
             for (int k = 0; k < kWLoads; ++k) {
