@@ -180,13 +180,15 @@ __device__ __forceinline__ void extract16(const uint32_t w[4], uint32_t rm, uint
     for (int q = 0; q < 4; ++q) {
         const uint32_t m = (rm >> (4 * q)) & 0xFu;
         const uint32_t pos = rel;
-        rel += (uint32_t)__popc(m) * rep;
+        rel += __umul24((uint32_t)__popc(m), rep);
         if (m == 0 || pos >= rend) continue;
-        if (rel <= rend) {
-            const uint32_t f = (w[q] >> hk.shift) & hk.low_bytes;
-            const uint32_t c = vperm(0u, f, T[m]);
-            const uint32_t s = (((c >> 24) << (3u * rep)) | (((c >> 16) & 0xFFu) << (2u * rep)) |
-                                (((c >> 8) & 0xFFu) << rep) | (c & 0xFFu)) << (32u - 4u * rep);
+        if (__builtin_expect(rel <= rend, 1)) {
+            // the fields of the word's redundant pixels, in order, then packed
+            // pairwise: P = f0 f1 in bits 16.., Q = f2 f3 in bits 0..
+            const uint32_t c = vperm(0u, (w[q] >> hk.shift) & hk.low_bytes, T[m]);
+            const uint32_t v = ((c >> 8) & 0x00FF00FFu) << rep | (c & 0x00FF00FFu);
+            // f0 f1 f2 f3 top-aligned: P on top, Q right below it
+            const uint32_t s = __builtin_amdgcn_alignbit(v >> 16, v << (32u - 2u * rep), 2u * rep);
             window_or(win, pos, s);
         } else {
             uint32_t p = pos;
@@ -250,17 +252,6 @@ __global__ void k_extract_fix(const Job *__restrict__ jobs, const PartWord *__re
 // carries over in registers, the next step's pixels (and, embedding, message
 // blocks) are loaded while the current one is processed, ranks inside a step
 // come from a wave scan (DPP), and nothing waits on another wave.
-
-// Inclusive sum over the 64 lanes of a wave.
-__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t x) {
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);    // row_shr:1
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);    // row_shr:2
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);    // row_shr:4
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true);    // row_shr:8
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);   // row_bcast:15
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);   // row_bcast:31
-    return x;
-}
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -5,6 +5,9 @@
 // The tile kernels are persistent: each workgroup owns a contiguous range of
 // work units (tiles of one image stay on one workgroup, hence on one XCD and
 // its L2) and loads the next unit's inputs before working on the current one.
+#include <mutex>
+#include <unordered_map>
+
 #include "device.hpp"
 #include "glide4.hpp"
 
@@ -86,10 +89,8 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
         uint32_t *st = reinterpret_cast<uint32_t *>(ws + Jf.ws_stats) + slot * kStatWords;
 #pragma unroll
         for (int k = 0; k < 7; ++k) {
-            uint32_t v = cnt[k];
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-            if (lane == 0 && v) atomicAdd(&st[k], v);
+            const uint32_t v = wave_scan_incl(cnt[k]);   // lane 63: the wave's total
+            if (lane == 63 && v) atomicAdd(&st[k], v);
             cnt[k] = 0;
         }
     };
@@ -143,24 +144,24 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
                         (uint8_t)((L2[0] & 3u) | ((L2[1] & 3u) << 2) | ((L2[2] & 3u) << 4) | ((L2[3] & 3u) << 6)));
         // level 3 (8x8): block (q/2, 2g + jj) for even q, from lanes q and q+1
         const uint32_t hs = (L2[0] + L2[1]) | ((L2[2] + L2[3]) << 16);
-        const uint32_t L3 = hs + __shfl_down(hs, 4, 64);        // halves: columns 2g, 2g+1
+        // (lanes of a row of 16 are q = 4r..4r+3, so these partners stay in the row)
+        const uint32_t L3 = hs + row_shl<4>(hs);                // halves: columns 2g, 2g+1
         const uint32_t nib = (L3 & 3u) | ((L3 >> 14) & 0xCu);
-        const uint32_t nib_hi = __shfl_down(nib, 1, 64);
+        const uint32_t nib_hi = row_shl<1>(nib);
         if ((q & 1) == 0 && (g & 1) == 0)
             gstore<uint8_t>(rec + code_off(3) + (q >> 1) * 2 + (g >> 1), (uint8_t)(nib | (nib_hi << 4)));
         // level 4 (16x16): block (q/4, g) for q % 4 == 0, from lanes q, q+2
         const uint32_t l3s = (L3 & 0xFFFFu) + (L3 >> 16);
-        const uint32_t L4 = l3s + __shfl_down(l3s, 8, 64);
+        const uint32_t L4 = l3s + row_shl<8>(l3s);
         const uint32_t c4 = L4 & 3u;
-        const uint32_t c4row = c4 | (__shfl_down(c4, 1, 64) << 2) | (__shfl_down(c4, 2, 64) << 4) |
-                               (__shfl_down(c4, 3, 64) << 6);
+        const uint32_t c4row = c4 | (row_shl<1>(c4) << 2) | (row_shl<2>(c4) << 4) | (row_shl<3>(c4) << 6);
         if ((q & 3) == 0 && g == 0) gstore<uint8_t>(rec + code_off(4) + (q >> 2), (uint8_t)c4row);
-        // level 5 (32x32): block (q/8, g/2) at lanes q % 8 == 0, g even
-        const uint32_t l4h = L4 + __shfl_down(L4, 1, 64);
-        const uint32_t L5 = l4h + __shfl_down(l4h, 16, 64);
-        // level 6 (the tile) and the level-5 byte, gathered in lane 0
-        const uint32_t c5a = L5 & 3u, c5b = __shfl_down(L5, 2, 64) & 3u;
-        const uint32_t c5c = __shfl_down(L5, 32, 64) & 3u, c5d = __shfl_down(L5, 34, 64) & 3u;
+        // level 5 (32x32): the sums of 16x16 column pairs sit in lanes 0, 2 (rows 0..15),
+        // 16, 18 (16..31), 32, 34, 48, 50; level 6 (the tile) follows, on the scalar unit
+        const uint32_t l4h = L4 + row_shl<1>(L4);
+        auto at = [&](int l) { return (uint32_t)__builtin_amdgcn_readlane((int)l4h, l); };
+        const uint32_t c5a = (at(0) + at(16)) & 3u, c5b = (at(2) + at(18)) & 3u;
+        const uint32_t c5c = (at(32) + at(48)) & 3u, c5d = (at(34) + at(50)) & 3u;
         if (lane == 0) {
             const uint32_t c6 = (c5a + c5b + c5c + c5d) & 3u;
             gstore<uint8_t>(rec + code_off(5), (uint8_t)(c5a | (c5b << 2) | (c5c << 4) | (c5d << 6)));
@@ -1050,6 +1051,20 @@ __global__ void k_recover_fix(const Job *__restrict__ jobs, const uint8_t *__res
 // ---- launchers ---------------------------------------------------------------
 // Workgroups of a persistent launch: what fits on the device at once (or the
 // caller's cap), never more than there are units.
+// The resident count of each kernel is asked of the runtime once and kept.
+static int resident_per_cu(const void *kernel) {
+    static std::mutex mu;
+    static std::unordered_map<const void *, int> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(kernel);
+    if (it != cache.end()) return it->second;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    cache[kernel] = per_cu;
+    return per_cu;
+}
+
 template <typename K>
 static unsigned persistent_grid(const Launch &L, K kernel, uint32_t units) {
     static int cus = 0;
@@ -1059,9 +1074,7 @@ static unsigned persistent_grid(const Launch &L, K kernel, uint32_t units) {
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (cus <= 0) cus = 1;
     }
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess || per_cu < 1)
-        per_cu = 1;
+    const int per_cu = resident_per_cu(reinterpret_cast<const void *>(kernel));
     uint32_t g = (uint32_t)cus * (uint32_t)per_cu;
     if (L.max_grid > 0) g = (uint32_t)L.max_grid;
     if (g > units) g = units;
