@@ -597,9 +597,33 @@ static inline unsigned grid_for(const Launch &L, uint32_t units) {
     return g ? g : 1;
 }
 
+// Waves of k_hide_wave resident on the device.
+static uint32_t hide_wave_resident() {
+    static uint32_t v = 0;
+    if (!v) {
+        int dev = 0, cus = 0, per_cu = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_hide_wave<true>, 64, 0) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        v = (uint32_t)(cus > 0 ? cus : 1) * (uint32_t)per_cu;
+    }
+    return v;
+}
+
+// One wave per image walks the whole image, so a launch of more images than
+// resident waves runs in rounds; the default grid deals the images out evenly
+// (every wave the same number of images) instead of leaving a partial last
+// round.
 void launch_hide_images(const Launch &L, uint32_t units, bool embed) {
     if (!units) return;
-    const unsigned g = grid_for(L, units);
+    unsigned g;
+    if (L.max_grid > 0) {
+        g = grid_for(L, units);
+    } else {
+        const uint32_t res = hide_wave_resident(), rounds = (units + res - 1) / res;
+        g = (units + rounds - 1) / rounds;
+    }
     if (embed)
         hipLaunchKernelGGL(k_hide_wave<true>, dim3(g), dim3(64), 0, L.stream, L.jobs, L.njobs, units, L.ujob[UNIT_IMG]);
     else
@@ -612,17 +636,8 @@ void launch_hide_images(const Launch &L, uint32_t units, bool embed) {
 // walks of the images overlap.  Smaller batches (and single images) take the
 // segment path, whose latency per image is a few segments deep.
 uint32_t whole_image_min() {
-    static uint32_t v = 0;
-    if (!v) {
-        int dev = 0, cus = 0, per_cu = 0;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_hide_wave<true>, 64, 0) != hipSuccess || per_cu < 1)
-            per_cu = 1;
-        v = (uint32_t)(cus > 0 ? cus : 1) * (uint32_t)per_cu / 4u;
-        if (v < 1) v = 1;
-    }
-    return v;
+    const uint32_t v = hide_wave_resident() / 4u;
+    return v < 1 ? 1 : v;
 }
 
 static inline unsigned step_grid(const Launch &L, uint32_t units) {
