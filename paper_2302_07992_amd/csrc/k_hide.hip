@@ -611,18 +611,16 @@ static uint32_t hide_wave_resident() {
     return v;
 }
 
-// One wave per image walks the whole image, so a launch of more images than
-// resident waves runs in rounds; the default grid deals the images out evenly
-// (every wave the same number of images) instead of leaving a partial last
-// round.
+// One wave per image walks the whole image; by default as many waves as are
+// resident, each taking images in turn.
 void launch_hide_images(const Launch &L, uint32_t units, bool embed) {
     if (!units) return;
     unsigned g;
     if (L.max_grid > 0) {
         g = grid_for(L, units);
     } else {
-        const uint32_t res = hide_wave_resident(), rounds = (units + res - 1) / res;
-        g = (units + rounds - 1) / rounds;
+        const uint32_t res = hide_wave_resident();
+        g = units < res ? units : res;
     }
     if (embed)
         hipLaunchKernelGGL(k_hide_wave<true>, dim3(g), dim3(64), 0, L.stream, L.jobs, L.njobs, units, L.ujob[UNIT_IMG]);
