@@ -319,6 +319,43 @@ def test_batched_plan_uneven_sizes_matches_oracle(R, hide_mode):
             assert np.array_equal(d_got[i].cpu().numpy()[:(caps[i] + 7) // 8], msgs[i])
 
 
+def test_batched_wide_images_quad_segments(R):
+    """One batch of images two to four quad segments wide (odd tile counts
+    in both directions, so quads and band pairs are cut at the edges): the
+    recovery of every image is completed across its segments by the row
+    fix-up pass of the same launch."""
+    print("[batched wide] quad segments", flush=True)
+    ctx = R.Context(0)
+    shapes = [(192, 1088), (128, 640), (64, 2048), (320, 1216), (256, 512)]
+    imgs = [_image(300 + i, *s, sigma=(1, 3, 8, 20)[i % 4], nsin=3 + i) for i, s in enumerate(shapes)]
+    n = len(imgs)
+    d_in = [_dev(I) for I in imgs]
+    d_enc = [torch.empty_like(x) for x in d_in]
+    d_rec = [torch.empty_like(x) for x in d_in]
+    metas = R.new_meta(n)
+    k1s = [3000 + i for i in range(n)]
+    k2s = [4000 + i for i in range(n)]
+    R.Plan(ctx, R.OP_ENCRYPT, R.make_jobs(d_in, d_enc, None, [metas[i] for i in range(n)], k1s, None, shapes)).run()
+    torch.cuda.synchronize()
+    ms = R.read_meta(metas)
+    oracle = [O.emr_encrypt(I, k) for I, k in zip(imgs, k1s)]
+    for i in range(n):
+        assert np.array_equal(d_enc[i].cpu().numpy(), oracle[i][0]), f"encrypt image {i} {shapes[i]}"
+    caps = [m.capacity_bits for m in ms]
+    msgs = [inputs.make_payload(k, c).numpy() for k, c in zip(k2s, caps)]
+    d_msg = [_msg_dev(R, m, c) for m, c in zip(msgs, caps)]
+    R.Plan(ctx, R.OP_EMBED, R.make_jobs(None, d_enc, d_msg, [metas[i] for i in range(n)], k2s, caps, shapes)).run()
+    R.Plan(ctx, R.OP_RECOVER, R.make_jobs(d_enc, d_rec, None, [metas[i] for i in range(n)], k1s, None, shapes)).run()
+    torch.cuda.synchronize()
+    for i in range(n):
+        Iem_o = O.emr_embed(oracle[i][0], oracle[i][1].b, msgs[i], caps[i], k2s[i])
+        assert np.array_equal(d_enc[i].cpu().numpy(), Iem_o), f"embed image {i} {shapes[i]}"
+        got = d_rec[i].cpu().numpy()
+        want = O.emr_recover(Iem_o, oracle[i][1].b, k1s[i])
+        mism = np.argwhere(got != want)
+        assert mism.size == 0, f"recover image {i} {shapes[i]}: {mism[:5].tolist()} of {len(mism)}"
+
+
 @pytest.mark.parametrize("hide_mode", [1, 2], ids=["whole", "segments"])
 def test_batched_partial_payloads_match_oracle(R, hide_mode):
     """Batched embed/extract with payloads that end inside a pixel's field and
