@@ -70,6 +70,7 @@ def parse():
     ap.add_argument("--serve-pool-mib", type=int, default=2048, help="device pool of the serving loop")
     ap.add_argument("--serve-streams", type=int, default=2)
     ap.add_argument("--serve-loads", default="0.5,0.7,0.9", help="offered load as fractions of batched capacity")
+    ap.add_argument("--pipes", type=int, default=2, help="independent parts of the batch on as many streams")
     ap.add_argument("--serial-receiver", action="store_true",
                     help="run extraction and recovery one after the other instead of on two streams")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -332,6 +333,27 @@ def main():
         "recover": rdhei.Plan(ctx, rdhei.OP_RECOVER, rec_jobs, flags),
     }
     order = ["encrypt", "embed", "extract", "recover"]
+    # --pipes P: the batch is also cut into P equal parts with plans of their
+    # own, each part's round trip on a stream of its own, so that the kernels
+    # of different parts (vector-bound statistics next to memory-bound
+    # hiding) overlap; the step waits for every part.
+    pipes = []
+    if args.pipes > 1:
+        cut = np.linspace(0, B, args.pipes + 1).astype(int)
+        for a, b in zip(cut[:-1], cut[1:]):
+            sl = slice(int(a), int(b))
+            sh, mp, c1, c2, cp = shapes[sl], mptr[sl], k1[sl], k2[sl], caps[sl]
+            po, px_ = [base_p + int(o) for o in offs[sl]], [base_x + int(o) for o in offs[sl]]
+            pipes.append({
+                "encrypt": rdhei.Plan(ctx, rdhei.OP_ENCRYPT,
+                                      rdhei.make_jobs(list(imgs[sl]), list(enc[sl]), None, mp, c1, None, sh), flags),
+                "embed": rdhei.Plan(ctx, rdhei.OP_EMBED, rdhei.make_jobs(None, list(enc[sl]), po, mp, c2, cp, sh), flags),
+                "extract": rdhei.Plan(ctx, rdhei.OP_EXTRACT, rdhei.make_jobs(list(enc[sl]), None, px_, mp, c2, cp, sh),
+                                      flags),
+                "recover": rdhei.Plan(ctx, rdhei.OP_RECOVER,
+                                      rdhei.make_jobs(list(enc[sl]), list(rec[sl]), None, mp, c1, None, sh), flags),
+            })
+    pipe_streams = [(torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev)) for _ in pipes]
     # The receiver's two roles both only read the marked image (extraction with
     # K2 writes the message, recovery with K1 the restored image), so by
     # default they run side by side on two streams; the next step's
@@ -340,6 +362,29 @@ def main():
 
     def step():
         main = torch.cuda.current_stream()
+        if pipes:
+            start = torch.cuda.Event()
+            start.record(main)
+            for pp, (st, st2) in zip(pipes, pipe_streams):
+                st.wait_event(start)
+                pp["encrypt"].run(st)
+                pp["embed"].run(st)
+                if args.serial_receiver:
+                    pp["extract"].run(st)
+                    pp["recover"].run(st)
+                else:
+                    marked = torch.cuda.Event()
+                    marked.record(st)
+                    st2.wait_event(marked)
+                    pp["recover"].run(st2)
+                    pp["extract"].run(st)
+                    restored = torch.cuda.Event()
+                    restored.record(st2)
+                    main.wait_event(restored)
+                done = torch.cuda.Event()
+                done.record(st)
+                main.wait_event(done)
+            return
         plans["encrypt"].run(main)
         plans["embed"].run(main)
         if args.serial_receiver:
@@ -365,6 +410,8 @@ def main():
         for k in order:
             grids = plans[k].autotune(reps=args.autotune)
             tuned[k] = dict(zip(plans[k].stages(), grids))
+            for pp in pipes:
+                pp[k].autotune(reps=args.autotune)
         log(f"[bench] autotuned workgroups (0 = resident default): {tuned}")
         step()
         torch.cuda.synchronize()
@@ -509,6 +556,7 @@ def main():
                                "(sinusoids + noise, sigma in 1/3/8/20, 2..32 sinusoids), payload at capacity",
                    "images": B, "side": S, "mode": args.mode, "der_bpp": round(der, 4),
                    "receiver": "serial" if args.serial_receiver else "extract and recover on two streams",
+                   "pipes": max(1, args.pipes),
                    "autotuned_workgroups": tuned},
         "roofline": roof,
         "step_hbm_frac": round(alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
