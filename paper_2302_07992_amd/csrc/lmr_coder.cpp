@@ -27,6 +27,7 @@
 namespace rdhei {
 namespace {
 
+// Bit j of row i of a plane stored MSB-first, 0 outside the plane.
 struct PlaneView {
     const uint8_t *bits;
     int32_t M, N;
@@ -37,11 +38,24 @@ struct PlaneView {
     }
 };
 
-inline uint32_t context(const PlaneView &v, int64_t i, int64_t j) {
-    return (v.at(i - 2, j - 1) << 9) | (v.at(i - 2, j) << 8) | (v.at(i - 2, j + 1) << 7) | (v.at(i - 1, j - 2) << 6) |
-           (v.at(i - 1, j - 1) << 5) | (v.at(i - 1, j) << 4) | (v.at(i - 1, j + 1) << 3) | (v.at(i - 1, j + 2) << 2) |
-           (v.at(i, j - 2) << 1) | v.at(i, j - 1);
-}
+// The context of pixel (i, j), kept as three sliding windows: w2 = bits
+// x(i-2, j-1..j+1), w1 = x(i-1, j-2..j+2), w0 = x(i, j-2..j-1) (first pixel
+// in the highest bit).  Moving to j + 1 shifts one new pixel into each.
+struct Context {
+    uint32_t w2 = 0, w1 = 0, w0 = 0;
+    void start_row(const PlaneView &v, int64_t i) {
+        w2 = (v.at(i - 2, 0) << 1) | v.at(i - 2, 1);
+        w1 = (v.at(i - 1, 0) << 2) | (v.at(i - 1, 1) << 1) | v.at(i - 1, 2);
+        w0 = 0;
+    }
+    uint32_t value() const { return (w2 << 7) | (w1 << 2) | w0; }
+    // after pixel (i, j) with value `bit`
+    void advance(const PlaneView &v, int64_t i, int64_t j, uint32_t bit) {
+        w2 = ((w2 << 1) | v.at(i - 2, j + 2)) & 7u;
+        w1 = ((w1 << 1) | v.at(i - 1, j + 3)) & 31u;
+        w0 = ((w0 << 1) | bit) & 3u;
+    }
+};
 
 class Encoder {
    public:
@@ -121,8 +135,15 @@ void encode_plane(const uint8_t *bits, int32_t M, int32_t N, std::vector<uint8_t
     std::vector<uint16_t> p(1024, 2048);
     Encoder enc(out);
     PlaneView v{bits, M, N};
-    for (int64_t i = 0; i < M; ++i)
-        for (int64_t j = 0; j < N; ++j) enc.put(v.at(i, j), p[context(v, i, j)]);
+    Context c;
+    for (int64_t i = 0; i < M; ++i) {
+        c.start_row(v, i);
+        for (int64_t j = 0; j < N; ++j) {
+            const uint32_t bit = v.at(i, j);
+            enc.put(bit, p[c.value()]);
+            c.advance(v, i, j, bit);
+        }
+    }
     enc.finish();
 }
 
@@ -132,12 +153,16 @@ bool decode_plane(const uint8_t *in, int64_t n, int32_t M, int32_t N, uint8_t *b
     const uint64_t MN = (uint64_t)M * N;
     memset(bits, 0, (size_t)((MN + 7) / 8));
     PlaneView v{bits, M, N};
-    for (int64_t i = 0; i < M; ++i)
+    Context c;
+    for (int64_t i = 0; i < M; ++i) {
+        c.start_row(v, i);
         for (int64_t j = 0; j < N; ++j) {
-            const uint32_t bit = dec.get(p[context(v, i, j)]);
+            const uint32_t bit = dec.get(p[c.value()]);
             const int64_t q = i * N + j;
             if (bit) bits[q >> 3] |= (uint8_t)(0x80u >> (q & 7));
+            c.advance(v, i, j, bit);
         }
+    }
     return !dec.overrun();
 }
 
