@@ -208,10 +208,11 @@ int rdhei_run_batch(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t n
 #define RDHEI_OPT_MAX_GRID   2   /* workgroup cap of grid-stride launches         */
 #define RDHEI_OPT_RESERVE_WS 3   /* allocate this many workspace bytes now        */
 #define RDHEI_OPT_HIDE_MODE  4   /* embed/extract of images up to 1 Mpx: 0 one
-                                    workgroup per image once a batch holds enough
-                                    of them to fill the device, else segments;
-                                    1 always one workgroup per image; 2 always
-                                    segments.  Results are identical.            */
+                                    wave walks each image once a batch holds
+                                    enough of them to fill the device, else
+                                    counted 4096-pixel steps; 1 always one wave
+                                    per image; 2 always steps.  Results are
+                                    identical.                                   */
 int rdhei_ctx_set_option(rdhei_ctx *ctx, int32_t option, int64_t value);
 
 /* ---- LMR over a batch of images (Sec. III-B) ---------------------------------

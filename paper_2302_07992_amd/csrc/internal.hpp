@@ -31,7 +31,7 @@ constexpr int kCodeRecord = (code_off(kTileLog + 1) + 15) / 16 * 16;   // 352 by
 constexpr int kStatWords = 8;
 
 // Work-unit kinds (how a batch is cut into workgroup-sized pieces).
-// Tiles, tile rows (LMR recovery), hiding segments, whole images, and band
+// Tiles, tile rows (LMR recovery), hiding steps, whole images, and band
 // pairs (tile rows 2p, 2p + 1: encryption and EMR recovery go by 2x2 quads).
 enum UnitKind { UNIT_TILE = 0, UNIT_BAND = 1, UNIT_SEG = 2, UNIT_IMG = 3, UNIT_QROW = 4, UNIT_KINDS = 5 };
 
@@ -58,7 +58,7 @@ struct Job {
     int32_t fixed_b;          // > 0: b chosen on the host (LMR); 0: read meta->b
     int32_t fast;             // 1: tiled path; 0: per-pixel path
     int32_t tiles_x, tiles_y;
-    int32_t nseg;             // raster segments for hiding/extraction
+    int32_t nseg;             // hiding / extraction steps of seg_pixels() raster pixels
     uint32_t ubase[UNIT_KINDS];
     uint32_t ucount[UNIT_KINDS];
     uint64_t ws_codes;        // tile code records (fast) / all-level codes (per-pixel path)
@@ -79,10 +79,6 @@ __host__ __device__ inline uint32_t stat_slots(const Job &J) {
 __host__ __device__ inline uint64_t stat_z_offset(const Job &J) {
     return J.ws_stats + (uint64_t)stat_slots(J) * kStatWords * 4;
 }
-
-// Raster segment for hiding / extraction: pixels handled by one workgroup in
-// order.  A chunk is what 256 threads cover with 16 pixels each.
-constexpr int kChunk = kThreads * 16;
 
 // ---- launchers (defined in the .hip files) ---------------------------------
 struct Launch {

@@ -632,7 +632,7 @@ void launch_hide_images(const Launch &L, uint32_t units, bool embed) {
 // Batches of at least this many small images hide one image per wave: a
 // quarter of the waves of k_hide_wave resident on the device, so that the
 // walks of the images overlap.  Smaller batches (and single images) take the
-// segment path, whose latency per image is a few segments deep.
+// counted steps, which spread every image over many waves.
 uint32_t whole_image_min() {
     const uint32_t v = hide_wave_resident() / 4u;
     return v < 1 ? 1 : v;

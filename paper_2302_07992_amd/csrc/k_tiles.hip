@@ -178,7 +178,7 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const uint32_t w[4] = {p[i].x, p[i].y, p[i].z, p[i].w};
-                // byte left of this segment: lane g-1 of the quad, or the previous tile for g = 0
+                // byte left of the lane's 16 pixels: lane g-1 of the row, or the previous tile for g = 0
                 uint32_t lb = (uint32_t)__builtin_amdgcn_mov_dpp((int)(p[i].w >> 24), 0x90, 0xF, 0xF, false);
                 if (g == 0) lb = (left >> (8 * i)) & 0xFFu;
                 uint32_t x[4];
