@@ -464,29 +464,42 @@ __global__ __launch_bounds__(kThreads) void k_seg_count(const Job *__restrict__ 
 }
 
 // Pass 2: each image's step counts -> exclusive prefix sums, in place.  One
-// workgroup per image; thread t takes a contiguous run of steps.
-__global__ __launch_bounds__(kThreads) void k_seg_scan(const Job *__restrict__ jobs, uint32_t *__restrict__ cnt) {
-    __shared__ uint32_t wsum[kThreads / 64];
+// workgroup of kScanThreads per image; thread t takes a contiguous run of
+// steps and reads it kScanBatch counts at a time, all in flight together.
+constexpr int kScanThreads = 1024, kScanBatch = 16;
+__global__ __launch_bounds__(kScanThreads) void k_seg_scan(const Job *__restrict__ jobs, uint32_t *__restrict__ cnt) {
+    __shared__ uint32_t wsum[kScanThreads / 64];
     const Job &J = jobs[blockIdx.x];
     const uint32_t n = J.ucount[UNIT_SEG];
     if (n == 0) return;   // uniform over the workgroup
     uint32_t *c = cnt + J.ubase[UNIT_SEG];
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t per = (n + kThreads - 1) / kThreads;
+    const uint32_t per = (n + kScanThreads - 1) / kScanThreads;
     const uint32_t a = tid * per < n ? tid * per : n, b = a + per < n ? a + per : n;
     uint32_t sum = 0;
-    for (uint32_t i = a; i < b; ++i) sum += c[i];
+    for (uint32_t i0 = a; i0 < b; i0 += kScanBatch) {
+        uint32_t v[kScanBatch];
+#pragma unroll
+        for (int k = 0; k < kScanBatch; ++k) v[k] = i0 + k < b ? c[i0 + k] : 0u;
+#pragma unroll
+        for (int k = 0; k < kScanBatch; ++k) sum += v[k];
+    }
     const uint32_t incl = wave_scan_incl(sum);
     if (lane == 63) wsum[wave] = incl;
     __syncthreads();
     uint32_t base = 0;
 #pragma unroll
-    for (uint32_t w = 0; w < kThreads / 64; ++w) base += w < wave ? wsum[w] : 0u;
+    for (uint32_t w = 0; w < kScanThreads / 64; ++w) base += w < wave ? wsum[w] : 0u;
     uint32_t ex = base + incl - sum;
-    for (uint32_t i = a; i < b; ++i) {
-        const uint32_t v = c[i];
-        c[i] = ex;
-        ex += v;
+    for (uint32_t i0 = a; i0 < b; i0 += kScanBatch) {
+        uint32_t v[kScanBatch];
+#pragma unroll
+        for (int k = 0; k < kScanBatch; ++k) v[k] = i0 + k < b ? c[i0 + k] : 0u;
+#pragma unroll
+        for (int k = 0; k < kScanBatch; ++k) {
+            if (i0 + k < b) c[i0 + k] = ex;
+            ex += v[k];
+        }
     }
 }
 
@@ -648,7 +661,7 @@ void launch_embed(const Launch &L, uint32_t units) {
     PartWord *part = reinterpret_cast<PartWord *>(L.ws + L.g_part);
     const unsigned g = step_grid(L, units);
     hipLaunchKernelGGL(k_seg_count, dim3(g), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, units, L.ujob[UNIT_SEG], cnt);
-    hipLaunchKernelGGL(k_seg_scan, dim3((unsigned)L.njobs), dim3(kThreads), 0, L.stream, L.jobs, cnt);
+    hipLaunchKernelGGL(k_seg_scan, dim3((unsigned)L.njobs), dim3(kScanThreads), 0, L.stream, L.jobs, cnt);
     hipLaunchKernelGGL(k_seg_hide<true>, dim3(g), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, units,
                        L.ujob[UNIT_SEG], cnt, part);
 }
@@ -659,7 +672,7 @@ void launch_extract(const Launch &L, uint32_t units) {
     PartWord *part = reinterpret_cast<PartWord *>(L.ws + L.g_part);
     const unsigned g = step_grid(L, units);
     hipLaunchKernelGGL(k_seg_count, dim3(g), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, units, L.ujob[UNIT_SEG], cnt);
-    hipLaunchKernelGGL(k_seg_scan, dim3((unsigned)L.njobs), dim3(kThreads), 0, L.stream, L.jobs, cnt);
+    hipLaunchKernelGGL(k_seg_scan, dim3((unsigned)L.njobs), dim3(kScanThreads), 0, L.stream, L.jobs, cnt);
     hipLaunchKernelGGL(k_seg_hide<false>, dim3(g), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, units,
                        L.ujob[UNIT_SEG], cnt, part);
     const uint32_t n = 2 * units;
