@@ -457,6 +457,10 @@ __global__ __launch_bounds__(kThreads) void k_encrypt_quad(const Job *__restrict
         const bool have = ty < J.tiles_y && tx < J.tiles_x;   // wave-uniform
         const bool first = c == 0;
         const uint32_t slot = it & 1u;
+        // column 63 of the previous quad's right tile, read before this barrier: it
+        // was written before the last one, and its wave writes that slot again
+        // right after this one
+        const uint32_t edge_prev = side ? 0u : edge[slot ^ 1u][wave + 1][q];
         // column 63 of this tile for the wave of the tile to its right
         if (have && g == 3)
             edge[slot][wave][q] = (p[0].w >> 24) | ((p[1].w >> 24) << 8) | ((p[2].w >> 24) << 16) | (p[3].w & 0xFF000000u);
@@ -473,7 +477,7 @@ __global__ __launch_bounds__(kThreads) void k_encrypt_quad(const Job *__restrict
         tmap_unpack(tm, dy, dx, up);
         // the byte left of rows 4q..4q+3 of this tile (column 0 of the image has none)
         const uint32_t halo = side ? edge[slot][wave - 1][q]
-                                   : (tx == 0 ? 0u : (first ? halo_mem : edge[slot ^ 1u][wave + 1][q]));
+                                   : (tx == 0 ? 0u : (first ? halo_mem : edge_prev));
 
         // labels (Sec. III-A location map): l = 1 unless the b MSBs equal the left neighbour's
         uint32_t o[4][4];

@@ -140,6 +140,50 @@ def test_emr_8192_full_image(R, ctx):
     _roundtrip(R, ctx, I, 303, 404, frac=0.77)
 
 
+@pytest.mark.parametrize("shape", [(8192, 16384), (12288, 12288), (16384, 16384)])
+def test_emr_large_images_roundtrip(R, ctx, shape):
+    """Images above 8192 in a dimension, where every workgroup of the tile
+    kernels takes several quad segments in a row.  Sizes the oracle cannot
+    finish in seconds, so properties that hold at any size: the labels written
+    by encryption (the LSB plane) count exactly the redundant pixels that the
+    statistics pass found; a full-capacity message comes back bit for bit;
+    recovery after hiding gives back every bit of the image above the LSB
+    plane."""
+    M, N = shape
+    seed = 77 + M
+    print(f"[large roundtrip] {M}x{N}", flush=True)
+    img = inputs.make_band_image(seed, M, N, 8, 3.0, "cuda")
+    enc = torch.empty_like(img)
+    rec = torch.empty_like(img)
+    meta = R.new_meta()
+    k1, k2 = inputs.key_pair(seed)
+    ctx.encrypt(img, enc, k1, meta)
+    torch.cuda.synchronize()
+    m = R.read_meta(meta)
+    assert m.status == 0
+    zeros = int((enc & 1).numel() - int((enc & 1).sum(dtype=torch.int64)))
+    assert zeros == m.redundant, f"labels 0: {zeros}, counted redundant: {m.redundant}"
+    cap = int(m.capacity_bits)
+    nbytes = R.msg_bytes(cap)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    msg = torch.randint(0, 256, (nbytes,), generator=g, device="cuda", dtype=torch.int32).to(torch.uint8)
+    ctx.embed(enc, meta, msg, cap, k2)
+    got = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    ctx.extract(enc, meta, got, cap, k2)
+    ctx.recover(enc, meta, rec, k1)
+    torch.cuda.synchronize()
+    assert R.read_meta(meta).status == 0
+    nb = cap // 8
+    bad = (got[:nb] != msg[:nb]).nonzero().flatten()
+    assert bad.numel() == 0, f"extracted bytes differ at {bad[:5].tolist()} of {nb}"
+    if cap % 8:
+        keep = (0xFF00 >> (cap % 8)) & 0xFF
+        assert int(got[nb]) & keep == int(msg[nb]) & keep
+    bad = ((rec ^ img) > 1).nonzero()   # the LSB plane carries the labels
+    assert bad.numel() == 0, f"recovered pixels differ at {bad[:5].tolist()} of {bad.shape[0]}"
+
+
 def test_emr_rows_without_labels_across_segments(R, ctx):
     """512 x 1536 (three quad segments per band pair): constant rows, labelled
     0 everywhere but column 0, and rows whose first label in a segment lies
