@@ -42,11 +42,11 @@ __device__ __forceinline__ void unit_range(uint32_t units, uint32_t &u0, uint32_
 // columns 16g..16g+15 (four keystream blocks), so levels 1 and 2 sum inside
 // the lane, and levels 3..6 take a few lane shuffles.  Only the low two bits
 // of every keystream byte matter for the codes.
-// lambda >= b means x = pixel XOR left neighbour is below 2^(8-b): four pixels
-// per word are tested with one add and one three-input logic op, and a bit
-// count accumulates the result.  Counts stay in registers across the tiles
-// of one image and go to one of the image's counter slots with one atomic add
-// per wave.
+// lambda >= b means x = pixel XOR left neighbour is below 2^(8-b); the
+// thresholds are nested, so each byte of x is smeared into a thermometer code
+// (bit k set when x >= 2^k) and the codes are summed bit-sliced, all seven
+// thresholds at once.  Counts stay in registers across the tiles of one image
+// and go to one of the image's counter slots with one atomic add per wave.
 // ----------------------------------------------------------------------------
 template <bool STATS>
 __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ jobs, int njobs,
@@ -80,19 +80,43 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
     };
     if (STATS && u0 < r1) fetch(u0);
 
-    uint32_t cnt[7] = {0, 0, 0, 0, 0, 0, 0};   // this lane's Z_2..Z_8 for the current image
+    // Per lane, the thermometer codes of its pixels (bit k of a byte: x >= 2^k)
+    // are summed bit-sliced: a carry-save tree over the 16 words of a tile
+    // (ones, twos, fours, eights: weights 1..8) and a ripple counter of the
+    // tree's sixteens across tiles (hi[p]: weight 16 * 2^p).  Z_b = pixels -
+    // (pixels with x >= 2^(8-b)), taken out when the wave leaves an image or
+    // after kHeldMax tiles (before hi can overflow).
+    constexpr int kHiPlanes = 6;
+    constexpr uint32_t kHeldMax = (1u << kHiPlanes) - 1u;
+    uint32_t ones = 0, twos = 0, fours = 0, eights = 0, hi[kHiPlanes] = {0, 0, 0, 0, 0, 0};
+    uint32_t held = 0;   // tiles in the counters (wave-uniform)
     int cur_j = -1;
     auto flush = [&](int jj) {                  // wave sums into one of the image's counter slots
         if (!STATS || jj < 0) return;
         const Job &Jf = jobs[jj];
         const uint32_t slot = gw % stat_slots(Jf);
         uint32_t *st = reinterpret_cast<uint32_t *>(ws + Jf.ws_stats) + slot * kStatWords;
+        const uint32_t px = 64u * held;         // this lane's pixels
 #pragma unroll
-        for (int k = 0; k < 7; ++k) {
-            const uint32_t v = wave_scan_incl(cnt[k]);   // lane 63: the wave's total
-            if (lane == 63 && v) atomicAdd(&st[k], v);
-            cnt[k] = 0;
+        for (int b = 2; b <= 8; ++b) {
+            const uint32_t m = 0x01010101u << (8 - b);
+            uint32_t h = 0;
+#pragma unroll
+            for (int p = 0; p < kHiPlanes; ++p) h += (uint32_t)__popc(hi[p] & m) << p;
+            const uint32_t ge = (uint32_t)__popc(ones & m) + 2u * (uint32_t)__popc(twos & m) +
+                                4u * (uint32_t)__popc(fours & m) + 8u * (uint32_t)__popc(eights & m) + 16u * h;
+            const uint32_t v = wave_scan_incl(px - ge);   // lane 63: the wave's Z_b
+            if (lane == 63 && v) atomicAdd(&st[b - 2], v);
         }
+        ones = twos = fours = eights = 0;
+#pragma unroll
+        for (int p = 0; p < kHiPlanes; ++p) hi[p] = 0;
+        held = 0;
+    };
+    // carry-save adder: h:l = a + b + c, bitwise
+    auto csa = [](uint32_t &h, uint32_t &l, uint32_t a, uint32_t b, uint32_t c) {
+        h = __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);   // majority
+        l = __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);   // parity
     };
 
     for (uint32_t u = u0; u < r1; u += kW) {
@@ -170,11 +194,13 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
         }
 
         if (STATS) {
-            if (j != cur_j) {
+            if (j != cur_j || held == kHeldMax) {
                 flush(cur_j);
                 cur_j = j;
             }
-            const bool lmr = J.method == RDHEI_LMR;
+            // lambda >= b exactly when x = pixel XOR left neighbour is below 2^(8-b):
+            // y smears each byte of x down, so bit k of y says x >= 2^k
+            uint32_t y[16];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const uint32_t w[4] = {p[i].x, p[i].y, p[i].z, p[i].w};
@@ -189,17 +215,37 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
                 if (tx == 0 && g == 0) x[0] |= 0xFFu;     // column 0 has no left neighbour
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    const uint32_t x7 = x[k] & 0x7F7F7F7Fu;
-#pragma unroll
-                    for (int b = 2; b <= 8; ++b) {
-                        if (b == 8 && !lmr) continue;   // b = 8 is an LMR choice only
-                        // bit 7 of each byte of s7: low 7 bits of x >= 2^(8-b); lt: x < 2^(8-b)
-                        const uint32_t s7 = x7 + (0x80u - (1u << (8 - b))) * 0x01010101u;
-                        const uint32_t lt = __builtin_amdgcn_bitop3_b32(s7, x[k], 0x80808080u, 0x02);
-                        cnt[b - 2] += (uint32_t)__popc(lt);
-                    }
+                    uint32_t t = x[k];                                                // t | (t >> s) & mask
+                    t = __builtin_amdgcn_bitop3_b32(t, t >> 1, 0x7F7F7F7Fu, 0xF8);
+                    t = __builtin_amdgcn_bitop3_b32(t, t >> 2, 0x3F3F3F3Fu, 0xF8);
+                    t = __builtin_amdgcn_bitop3_b32(t, t >> 4, 0x0F0F0F0Fu, 0xF8);
+                    y[4 * i + k] = t;
                 }
             }
+            // 16 words into ones/twos/fours/eights and one word of sixteens
+            uint32_t tA, tB, fA, fB, eA, eB, sx;
+            csa(tA, ones, ones, y[0], y[1]);
+            csa(tB, ones, ones, y[2], y[3]);
+            csa(fA, twos, twos, tA, tB);
+            csa(tA, ones, ones, y[4], y[5]);
+            csa(tB, ones, ones, y[6], y[7]);
+            csa(fB, twos, twos, tA, tB);
+            csa(eA, fours, fours, fA, fB);
+            csa(tA, ones, ones, y[8], y[9]);
+            csa(tB, ones, ones, y[10], y[11]);
+            csa(fA, twos, twos, tA, tB);
+            csa(tA, ones, ones, y[12], y[13]);
+            csa(tB, ones, ones, y[14], y[15]);
+            csa(fB, twos, twos, tA, tB);
+            csa(eB, fours, fours, fA, fB);
+            csa(sx, eights, eights, eA, eB);
+#pragma unroll
+            for (int p2 = 0; p2 < kHiPlanes; ++p2) {
+                const uint32_t c = hi[p2] & sx;
+                hi[p2] ^= sx;
+                sx = c;
+            }
+            ++held;
         }
     }
     flush(cur_j);

@@ -307,6 +307,32 @@ def test_run_batch_matches_plan(R, ctx):
             assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("max_grid", [1, 3, 7])
+def test_capped_grids_match_oracle(R, max_grid):
+    """Launches capped at a few workgroups: each wave of the statistics pass
+    sums the pixels of many tiles (96 per wave at one workgroup, past the
+    point where it takes its counts out early) and crosses image boundaries in
+    a batch; the quad kernels take many segments in a row."""
+    print(f"[capped grid] {max_grid}", flush=True)
+    ctx = R.Context(0)
+    ctx.set_option(R.OPT_MAX_GRID, max_grid)
+    _roundtrip(R, ctx, _image(4000 + max_grid, 1024, 1536), 51 + max_grid, 61 + max_grid, frac=0.9)
+    shapes = [(512, 512), (256, 768), (64, 64), (384, 1280), (128, 128)]
+    n = len(shapes)
+    imgs = [_image(4100 + i, *s, sigma=(1, 3, 8, 20)[i % 4]) for i, s in enumerate(shapes)]
+    d_in = [_dev(I) for I in imgs]
+    d_enc = [torch.empty_like(x) for x in d_in]
+    metas = R.new_meta(n)
+    k1s = [3000 + i for i in range(n)]
+    R.Plan(ctx, R.OP_ENCRYPT, R.make_jobs(d_in, d_enc, None, [metas[i] for i in range(n)], k1s, None, shapes)).run()
+    torch.cuda.synchronize()
+    ms = R.read_meta(metas)
+    for i, (I, k) in enumerate(zip(imgs, k1s)):
+        Ie_o, mo = O.emr_encrypt(I, k)
+        assert (ms[i].b, ms[i].redundant, ms[i].capacity_bits) == (mo.b, mo.redundant, mo.capacity_bits), shapes[i]
+        assert np.array_equal(d_enc[i].cpu().numpy(), Ie_o), shapes[i]
+
+
 @pytest.mark.parametrize("hide_mode", [0, 1, 2], ids=["auto", "whole", "segments"])
 def test_batched_plan_uneven_sizes_matches_oracle(R, hide_mode):
     """One plan per op over images of different shapes (tiled and per-pixel
@@ -530,7 +556,7 @@ def test_autotune_keeps_results_and_caches(R):
     print("[autotune]", flush=True)
     ctx = R.Context(0)
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    cand = {0, cus, 2 * cus, 4 * cus, 8 * cus, 16 * cus}
+    cand = {0, cus, 2 * cus, 4 * cus, 8 * cus, 16 * cus, 32 * cus}
     shapes = [(256, 256)] * 12 + [(128, 64)] * 4 + [(45, 77)]
     n = len(shapes)
     imgs = [_dev(_image(1300 + i, *s)) for i, s in enumerate(shapes)]
