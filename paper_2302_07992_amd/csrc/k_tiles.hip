@@ -24,11 +24,13 @@ __device__ __forceinline__ uint32_t blk_addr(uint32_t by, uint32_t bx) {
     return by * 256u + ((bx ^ sw) << 4);
 }
 
-// Contiguous unit range [u0, u1) of this workgroup.
-__device__ __forceinline__ void unit_range(uint32_t units, uint32_t &u0, uint32_t &u1) {
-    const uint32_t per = (units + gridDim.x - 1) / gridDim.x;
-    u0 = blockIdx.x * per;
-    u1 = u0 + per < units ? u0 + per : units;
+// Contiguous unit range [u0, u1) of this workgroup, its length rounded up to
+// a multiple of `align` (the last workgroups may get less, or nothing).
+__device__ __forceinline__ void unit_range(uint32_t units, uint32_t &u0, uint32_t &u1, uint32_t align = 1) {
+    const uint64_t per = (((uint64_t)units + gridDim.x - 1) / gridDim.x + align - 1) / align * align;
+    const uint64_t a = (uint64_t)blockIdx.x * per, b = a + per;
+    u0 = (uint32_t)(a < units ? a : units);
+    u1 = (uint32_t)(b < units ? b : units);
 }
 
 // ----------------------------------------------------------------------------
@@ -56,9 +58,12 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
     const int lane = threadIdx.x & 63, wave = (int)uni(threadIdx.x >> 6);   // wave-uniform
     const int q = lane >> 2, g = lane & 3;
     // the workgroup's contiguous tile range, dealt to its waves in turn so
-    // that neighbouring tiles (which share 128-byte lines) are read together
+    // that neighbouring tiles (which share 128-byte lines) are read together;
+    // ranges start at multiples of kW tiles, so the two tiles of a line pair
+    // (and the byte left of an even tile) fall in one iteration or the one
+    // before, never in another workgroup
     uint32_t r0, r1;
-    unit_range(units, r0, r1);
+    unit_range(units, r0, r1, kW);
     const uint32_t u0 = r0 + (uint32_t)wave, gw = blockIdx.x * kW + (uint32_t)wave;
 
     // next tile's pixels (STATS): rows 4q..4q+3, and for g = 0 the byte left of each row
@@ -119,7 +124,14 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
         l = __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);   // parity
     };
 
-    for (uint32_t u = u0; u < r1; u += kW) {
+    // STATS: one barrier per iteration keeps the waves of a workgroup on the
+    // same four tiles, so both halves of each 128-byte line are requested
+    // close together (waves that drift apart make the L2 fetch lines twice)
+    const uint32_t nit = r1 > r0 ? (r1 - r0 + kW - 1) / kW : 0u;   // uniform in the workgroup
+    for (uint32_t it = 0; it < nit; ++it) {
+        const uint32_t u = r0 + it * kW + (uint32_t)wave;
+        if (STATS) __syncthreads();
+        if (u >= r1) continue;                 // the tail of the last range
         uint4 p[4];
         uint32_t left = 0;
         if (STATS) {
