@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -59,11 +60,12 @@ def parse():
     ap.add_argument("--mode", choices=["graph", "eager"], default="graph")
     ap.add_argument("--per-image-steps", type=int, default=1, help="steps timed with per-image launches (0: skip)")
     ap.add_argument("--stage-reps", type=int, default=5)
-    ap.add_argument("--check", type=int, default=6, help="sampled images checked against the oracle")
+    ap.add_argument("--check", type=int, default=6, help="at least this many images of the CPU oracle leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="bounded oracle timing (0: skip)")
     ap.add_argument("--max-grid", type=int, default=0)
     ap.add_argument("--autotune", type=int, default=3, help="timed runs per candidate launch shape (0: defaults)")
-    ap.add_argument("--serve-requests", type=int, default=3000, help="serving-loop requests (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=5000, help="serving-loop requests (0: skip)")
+    ap.add_argument("--single-reps", type=int, default=200, help="runs of the one-image latency leg (0: skip)")
     ap.add_argument("--large-sides", default="8192,16384", help="single large images timed stage by stage ('' to skip)")
     ap.add_argument("--lmr-images", type=int, default=2000, help="LMR batch of 512x512 images (0: skip)")
     ap.add_argument("--lmr-threads", type=int, default=0, help="host coder threads (0: all)")
@@ -196,6 +198,86 @@ def lmr_bench(args):
     del imgs, enc, rec, payload, got
     torch.cuda.empty_cache()
     return out
+
+
+def single_bench(args):
+    """One 512x512 image (seed 0, sigma 3, 8 sinusoids, payload at capacity)
+    round-tripped through the single-image entry points on one stream, then
+    through one-image graph plans.  Each run starts on an idle GPU; HIP events
+    around each call give the device time per op and per round trip, the host
+    clock the time from the first call to the last op's completion (median and
+    p99 over the runs).  Every run must give the first run's bytes (compared
+    on the device)."""
+    import numpy as np
+    import torch
+
+    from paper_2302_07992_amd import inputs, rdhei
+    dev = torch.device("cuda:0")
+    ctx = rdhei.Context(0)
+    S, seed = 512, 0
+    img = inputs.make_image(seed, S, S, 8, 3.0, dev)
+    k1, k2 = inputs.key_pair(seed)
+    enc, rec = torch.empty_like(img), torch.empty_like(img)
+    meta = rdhei.new_meta()
+    ctx.encrypt(img, enc, k1, meta)
+    torch.cuda.synchronize()
+    cap = int(rdhei.read_meta(meta).capacity_bits)
+    nbytes = rdhei.msg_bytes(cap)
+    msg = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
+    pl = inputs.make_payload(seed, cap)
+    msg[:pl.numel()] = pl.to(dev)
+    got = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
+    names = ["encrypt", "embed", "extract", "recover"]
+    calls = [lambda: ctx.encrypt(img, enc, k1, meta), lambda: ctx.embed(enc, meta, msg, cap, k2),
+             lambda: ctx.extract(enc, meta, got, cap, k2), lambda: ctx.recover(enc, meta, rec, k1)]
+    shapes = [(S, S)]
+    plans = [rdhei.Plan(ctx, rdhei.OP_ENCRYPT, rdhei.make_jobs([img], [enc], None, [meta], [k1], None, shapes)),
+             rdhei.Plan(ctx, rdhei.OP_EMBED, rdhei.make_jobs(None, [enc], [msg], [meta], [k2], [cap], shapes)),
+             rdhei.Plan(ctx, rdhei.OP_EXTRACT, rdhei.make_jobs([enc], None, [got], [meta], [k2], [cap], shapes)),
+             rdhei.Plan(ctx, rdhei.OP_RECOVER, rdhei.make_jobs([enc], [rec], None, [meta], [k1], None, shapes))]
+    for f in calls:
+        f()
+    torch.cuda.synchronize()
+    ref = (enc.clone(), got.clone(), rec.clone())
+    same = True
+
+    def measure(ops, reps):
+        nonlocal same
+        dev_ms, rt_ms, wall_ms = [], [], []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+            t0 = time.perf_counter()
+            ev[0].record()
+            for k, f in enumerate(ops):
+                f()
+                ev[k + 1].record()
+            ev[4].synchronize()
+            wall_ms.append((time.perf_counter() - t0) * 1e3)
+            dev_ms.append([ev[k].elapsed_time(ev[k + 1]) for k in range(4)])
+            rt_ms.append(ev[0].elapsed_time(ev[4]))
+            same = same and torch.equal(enc, ref[0]) and torch.equal(got, ref[1]) and torch.equal(rec, ref[2])
+        d = np.array(dev_ms)
+        return {"ms": {n: round(float(np.median(d[:, k])), 4) for k, n in enumerate(names)},
+                "round_trip_ms_p50": round(float(np.median(rt_ms)), 4),
+                "round_trip_ms_p99": round(float(np.percentile(rt_ms, 99)), 4),
+                "wall_ms_p50": round(float(np.median(wall_ms)), 4),
+                "wall_ms_p99": round(float(np.percentile(wall_ms, 99)), 4)}
+
+    measure(calls, 20)                                   # warm-up
+    ep = measure(calls, args.single_reps)
+    graph_ops = [p.run for p in plans]
+    measure(graph_ops, 20)
+    gp = measure(graph_ops, args.single_reps)
+    for p in plans:
+        p.close()
+    best = min(ep["wall_ms_p50"], gp["wall_ms_p50"])
+    log(f"[single] {S}x{S}: entry points {ep['ms']} round trip {ep['round_trip_ms_p50']} ms (wall "
+        f"{ep['wall_ms_p50']}); graph plans round trip {gp['round_trip_ms_p50']} ms (wall {gp['wall_ms_p50']}); "
+        f"identical {same}")
+    return {"workload": f"one {S}x{S} image, seed 0, sigma 3, 8 sinusoids, payload at capacity ({cap} bits)",
+            "reps": args.single_reps, "entry_points": ep, "graph_plans": gp,
+            "mpx_per_s": round(S * S / (best * 1e-3) / 1e6, 1), "identical_runs": bool(same)}
 
 
 def large_bench(args):
@@ -430,26 +512,6 @@ def main():
     alg_bytes = 7.0 * px + caps.sum() / 4.0
     log(f"[bench] {ms:.3f} ms/step  {value:.0f} Mpx/s  DER {der:.3f}")
 
-    # ---- parity on sampled images (oracle on the host) ----
-    parity = {"checked": 0, "ok": True}
-    if args.check > 0:
-        import oracle as O
-        idx = np.linspace(0, B - 1, args.check).astype(int)
-        for i in idx:
-            I = imgs[i].cpu().numpy()
-            Ie_o, mo = O.emr_encrypt(I, k1[i])
-            cap = int(caps[i])
-            msg = payload[int(offs[i]):int(offs[i]) + (cap + 7) // 8].cpu().numpy()
-            Iem_o = O.emr_embed(Ie_o, mo.b, msg, cap, k2[i])
-            got = extracted[int(offs[i]):int(offs[i]) + (cap + 7) // 8].cpu().numpy()
-            bits_ok = np.array_equal(np.unpackbits(got)[:cap], np.unpackbits(msg)[:cap])
-            ok = (mo.capacity_bits == cap and np.array_equal(enc[i].cpu().numpy(), Iem_o) and bits_ok
-                  and np.array_equal(got, O.emr_extract(Iem_o, mo.b, cap, k2[i]))
-                  and np.array_equal(rec[i].cpu().numpy(), O.emr_recover(Iem_o, mo.b, k1[i])))
-            parity["checked"] += 1
-            parity["ok"] = parity["ok"] and bool(ok)
-        log(f"[bench] parity on {parity['checked']} sampled images: {parity['ok']}")
-
     # ---- per-stage timing (HIP events on the launch stream) ----
     # algorithmic bytes per pixel of each stage: the keystream
     # pyramid of recovery reads nothing; finalisation is per image
@@ -508,22 +570,41 @@ def main():
             p.close()
 
     # ---- CPU oracle on a bounded sample of the same workload ----
+    # Full round trips of the oracle, single thread, on images spread over the
+    # batch with their own keys and payloads; only the oracle calls are timed.
+    # The same round trips check the GPU's outputs of those images (marked
+    # image, extracted bits, recovered image), outside the timed part.
     cpu = None
-    if args.cpu_seconds > 0:
+    parity = {"checked": 0, "ok": True}
+    if args.cpu_seconds > 0 or args.check > 0:
         import oracle as O
-        n, t0 = 0, time.time()
-        while time.time() - t0 < args.cpu_seconds:
-            I = imgs[n % B].cpu().numpy()
-            Ie, mo = O.emr_encrypt(I, k1[n % B])
-            msg = np.frombuffer(os.urandom((mo.capacity_bits + 7) // 8), dtype=np.uint8)
-            Iem = O.emr_embed(Ie, mo.b, msg, mo.capacity_bits, k2[n % B])
-            O.emr_extract(Iem, mo.b, mo.capacity_bits, k2[n % B])
-            O.emr_recover(Iem, mo.b, k1[n % B])
+        step()                       # the outputs checked are the batched plans'
+        torch.cuda.synchronize()
+        stride = next(k for k in range(max(1, B // 7), B + 1) if math.gcd(k, B) == 1) if B > 1 else 1
+        n, el = 0, 0.0
+        while (args.cpu_seconds > 0 and el < args.cpu_seconds) or n < args.check:
+            i = (n * stride) % B
+            I = imgs[i].cpu().numpy()
+            cap = int(caps[i])
+            msg = payload[int(offs[i]):int(offs[i]) + (cap + 7) // 8].cpu().numpy()
+            t0 = time.perf_counter()
+            Ie_o, mo = O.emr_encrypt(I, k1[i])
+            Iem_o = O.emr_embed(Ie_o, mo.b, msg, mo.capacity_bits, k2[i])
+            got_o = O.emr_extract(Iem_o, mo.b, mo.capacity_bits, k2[i])
+            rec_o = O.emr_recover(Iem_o, mo.b, k1[i])
+            el += time.perf_counter() - t0
+            got = extracted[int(offs[i]):int(offs[i]) + (cap + 7) // 8].cpu().numpy()
+            ok = (mo.capacity_bits == cap and np.array_equal(enc[i].cpu().numpy(), Iem_o)
+                  and np.array_equal(got, got_o) and np.array_equal(rec[i].cpu().numpy(), rec_o))
+            parity["checked"] += 1
+            parity["ok"] = parity["ok"] and bool(ok)
             n += 1
-        el = time.time() - t0
-        cpu = {"value": round(n * MN / el / 1e6, 3), "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
-               "sample": f"{n} images of the batch ({S}x{S}), full round trip, single thread, {el:.1f}s"}
-        log(f"[bench] cpu oracle: {cpu['value']} Mpx/s over {n} images")
+        log(f"[bench] oracle round trips on {n} images, all equal to the GPU's: {parity['ok']}")
+        if args.cpu_seconds > 0:
+            cpu = {"value": round(n * MN / el / 1e6, 3), "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
+                   "sample": f"{n} images spread over the batch ({S}x{S}), full round trip, single thread, "
+                             f"{el:.1f}s of oracle time; the same round trips checked the GPU's outputs"}
+            log(f"[bench] cpu oracle: {cpu['value']} Mpx/s over {n} images")
 
     lmr = None
     if args.lmr_images > 0:
@@ -532,6 +613,7 @@ def main():
     large = None
     if args.large_sides:
         large = large_bench(args)
+    single = single_bench(args) if args.single_reps > 0 else None
 
     serving = None
     if args.serve_requests > 0:
@@ -566,10 +648,12 @@ def main():
         "stages": stages,
         "serving": serving,
         "large": large,
+        "single": single,
         "lmr": lmr,
     }
     print(json.dumps(out), flush=True)
     if (not parity["ok"] or (large and not all(r["extract_ok"] and r["lsb_only"] for r in large))
+            or (single and not single["identical_runs"])
             or (lmr and not (lmr["psnr_inf_all_good"] and lmr["payload_ok"]))):
         sys.exit(3)
 
