@@ -13,9 +13,6 @@
 
 namespace rdhei {
 
-// LDS row stride of a 64-byte tile row (keeps 16-byte alignment).
-constexpr int kRow = kTile + 16;
-
 // Byte offset of 4x4 block (by, bx) in a wave's tile of blocks: 16 bytes per
 // block, 16 blocks per block row, columns swizzled so that the writes of
 // lanes (q, g) and (q + 1, g) fall in different banks.
@@ -632,15 +629,14 @@ __global__ __launch_bounds__(kThreads) void k_encrypt_quad(const Job *__restrict
 }
 
 // ----------------------------------------------------------------------------
-// Recovery of row bands of tiles, left to right (Sec. III-A decoding with K1):
-// gather each original-domain tile from its rotated position, decrypt with
-// the keystream at the encrypted position, read l (EMR: the LSB; LMR: the
-// decompressed map, plus bit 7 from the first-MSB map), then the recovery
-// glide along each row: a pixel labelled 0 takes the replaceable bits of the
+// LMR recovery of row bands of tiles, left to right (Sec. III-B decoding with
+// K1): gather each original-domain tile from its rotated position, decrypt
+// with the keystream at the encrypted position, read l from the decompressed
+// location map and bit 7 from the first-MSB map, then the recovery glide
+// along each row: a pixel labelled 0 takes the replaceable bits of the
 // nearest pixel labelled 1 to its left.  Rows carry that value across tiles.
 // ----------------------------------------------------------------------------
-template <int METHOD>
-__global__ __launch_bounds__(kThreads) void k_recover_band(const Job *__restrict__ jobs, int njobs,
+__global__ __launch_bounds__(kThreads) void k_recover_band_lmr(const Job *__restrict__ jobs, int njobs,
                                                             uint8_t *__restrict__ ws, uint32_t units,
                                                             const uint32_t *__restrict__ ujob) {
     constexpr int kRow2 = 2 * kTile + 32;   // u16 per pixel: value | l << 8
@@ -666,10 +662,8 @@ __global__ __launch_bounds__(kThreads) void k_recover_band(const Job *__restrict
         tmap_unpack(reinterpret_cast<const uint32_t *>(ws + J.ws_tmap)[t], ey, ex, up);
         const uint64_t eidx = (uint64_t)(ey * kTile + r) * (uint64_t)J.N + (uint64_t)(ex * kTile + 16 * g);
         e_n = gload<uint4>(J.in + eidx);
-        if (METHOD == RDHEI_LMR) {
-            lb_n = __builtin_bswap16(gload<uint16_t>(J.lbits + (eidx >> 3)));
-            eb_n = __builtin_bswap16(gload<uint16_t>(J.etabits + (eidx >> 3)));
-        }
+        lb_n = __builtin_bswap16(gload<uint16_t>(J.lbits + (eidx >> 3)));
+        eb_n = __builtin_bswap16(gload<uint16_t>(J.etabits + (eidx >> 3)));
         rc_n = gload<uint4>(ws + J.ws_codes + (uint64_t)t * kCodeRecord + 16 * (tid % (kCodeRecord / 16)));
         b_n = (uint32_t)gload<int32_t>(&J.meta->b);
     };
@@ -679,7 +673,7 @@ __global__ __launch_bounds__(kThreads) void k_recover_band(const Job *__restrict
         const Job &J = jobs[uni((uint32_t)find_job<UNIT_BAND>(jobs, njobs, u, ujob))];
         const int ty = (int)(u - J.ubase[UNIT_BAND]);
         const int b = (int)uni(b_n);
-        const uint32_t mask = METHOD == RDHEI_EMR ? ((0xFFu << (8 - b)) & 0xFFu) : ((0xFFu << (8 - b)) & 0x7Fu);
+        const uint32_t mask = (0xFFu << (8 - b)) & 0x7Fu;   // bits 6..8-b (bit 7 comes from the eta map)
         uint32_t carry = 0;   // replaceable bits of the last marker in this row
 
         for (int tx = 0; tx < J.tiles_x; ++tx) {
@@ -696,21 +690,16 @@ __global__ __launch_bounds__(kThreads) void k_recover_band(const Job *__restrict
             const U4 s = stream_block(J.key, kDomainImage, eidx >> 4);
             uint32_t D[4] = {e.x ^ s.x, e.y ^ s.y, e.z ^ s.z, e.w ^ s.w};
             uint32_t Lw[4];
-            if (METHOD == RDHEI_EMR) {
-                Lw[0] = e.x & 0x01010101u; Lw[1] = e.y & 0x01010101u;
-                Lw[2] = e.z & 0x01010101u; Lw[3] = e.w & 0x01010101u;
-            } else {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    uint32_t lw = 0, ew = 0;
+            for (int k = 0; k < 4; ++k) {
+                uint32_t lw = 0, ew = 0;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        lw |= ((lbv >> (15 - (4 * k + q))) & 1u) << (8 * q);
-                        ew |= ((ebv >> (15 - (4 * k + q))) & 1u) << (8 * q + 7);
-                    }
-                    Lw[k] = lw;
-                    D[k] = (D[k] & 0x7F7F7F7Fu) | ew;
+                for (int q = 0; q < 4; ++q) {
+                    lw |= ((lbv >> (15 - (4 * k + q))) & 1u) << (8 * q);
+                    ew |= ((ebv >> (15 - (4 * k + q))) & 1u) << (8 * q + 7);
                 }
+                Lw[k] = lw;
+                D[k] = (D[k] & 0x7F7F7F7Fu) | ew;
             }
             uint32_t il[8];
 #pragma unroll
@@ -1209,7 +1198,7 @@ void launch_recover_bands(const Launch &L, uint32_t units, int method, uint32_t 
                                0, L.stream, L.jobs, L.ws);
     }
     else
-        hipLaunchKernelGGL(k_recover_band<RDHEI_LMR>, dim3(persistent_grid(L, k_recover_band<RDHEI_LMR>, units)), bl, 0,
+        hipLaunchKernelGGL(k_recover_band_lmr, dim3(persistent_grid(L, k_recover_band_lmr, units)), bl, 0,
                            L.stream, L.jobs, L.njobs, L.ws, units, UJ);
 }
 
