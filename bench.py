@@ -359,7 +359,7 @@ def large_bench(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is described, not built)"}))
         sys.exit(2)
     import numpy as np
@@ -513,8 +513,11 @@ def main():
     log(f"[bench] {ms:.3f} ms/step  {value:.0f} Mpx/s  DER {der:.3f}")
 
     # ---- per-stage timing (HIP events on the launch stream) ----
-    # algorithmic bytes per pixel of each stage: the keystream
-    # pyramid of recovery reads nothing; finalisation is per image
+    # algorithmic bytes per pixel of each stage: read I and write I_e
+    # (encryption), read I (statistics), read and write the marked image plus
+    # the payload (embedding), read the marked image and write the payload
+    # (extraction), read I_e' and write I' (recovery); the keystream pyramid
+    # of recovery reads nothing, finalisation is per image
     per_px = {"encrypt": {"tile_prep_stats": 1.0, "encrypt_tiles": 2.0},
               "recover": {"recover_bands": 2.0},
               "embed": {"embed_images": 2.0 + der / 8, "embed": 2.0 + der / 8},
