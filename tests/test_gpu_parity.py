@@ -184,6 +184,32 @@ def test_emr_large_images_roundtrip(R, ctx, shape):
     assert bad.numel() == 0, f"recovered pixels differ at {bad[:5].tolist()} of {bad.shape[0]}"
 
 
+def _degenerate(kind, M, N):
+    r, c = np.indices((M, N))
+    if kind == "zeros":
+        return np.zeros((M, N), np.uint8)
+    if kind == "white":
+        return np.full((M, N), 255, np.uint8)
+    if kind == "noise":
+        return np.random.default_rng(M * N).integers(0, 256, (M, N)).astype(np.uint8)
+    if kind == "checker":
+        return (((r + c) % 2) * 255).astype(np.uint8)
+    if kind == "rows":
+        return ((37 * r) % 256).astype(np.uint8)
+    return (c % 256).astype(np.uint8)   # "ramp": every pixel one above its left neighbour
+
+
+@pytest.mark.parametrize("shape", [(192, 320), (45, 77)], ids=lambda s: f"{s[0]}x{s[1]}")
+@pytest.mark.parametrize("kind", ["zeros", "white", "noise", "checker", "rows", "ramp"])
+def test_emr_degenerate_images(R, ctx, kind, shape):
+    """The ends of the method's range, tiled and per-pixel: constant images
+    (every pixel but column 0 redundant, b = 7), a checkerboard (no pixel
+    redundant: capacity 0, b = 2 on the all-zero tie), pure noise, constant
+    rows and a ramp; full round trip against the oracle."""
+    print(f"[degenerate] {kind} {shape}", flush=True)
+    _roundtrip(R, ctx, _degenerate(kind, *shape), 13, 14)
+
+
 def test_emr_rows_without_labels_across_segments(R, ctx):
     """512 x 1536 (three quad segments per band pair): constant rows, labelled
     0 everywhere but column 0, and rows whose first label in a segment lies

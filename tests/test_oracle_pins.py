@@ -97,6 +97,26 @@ def test_select_b_ties_and_argmax():
     assert O.select_b([8, 4, 2, 2, 2, 2, 3], 2) == 8          # 16 12 8 10 12 14 24
 
 
+@pytest.mark.parametrize("shape", [(64, 64), (45, 77), (1, 9)])
+def test_counts_of_closed_form_images(shape):
+    """Location map and optimal-b equations on images whose counts follow by
+    hand.  Constant image: every pixel but column 0 equals its left
+    neighbour, so Z_b = M(N-1) for every b and b = 7 maximises b*Z_b.
+    Checkerboard of 0 and 255: every pixel differs from its left neighbour in
+    the top bit, so Z_b = 0 for every b and the tie goes to b = 2.  Columns
+    that alternate 0 and 128 in pairs (0 0 128 128 ...): every second pixel
+    equals its left neighbour, the others differ in the top bit."""
+    M, N = shape
+    _, mo = O.emr_encrypt(np.full((M, N), 123, np.uint8), 5)
+    assert (mo.b, mo.redundant, mo.capacity_bits) == (7, M * (N - 1), 7 * M * (N - 1))
+    r, c = np.indices((M, N))
+    _, mo = O.emr_encrypt((((r + c) % 2) * 255).astype(np.uint8), 5)
+    assert (mo.b, mo.redundant, mo.capacity_bits) == (2, 0, 0)
+    _, mo = O.emr_encrypt(((c // 2) % 2 * 128).astype(np.uint8), 5)
+    z = M * (N // 2)          # pixels at odd columns 1, 3, ...
+    assert (mo.b, mo.redundant, mo.capacity_bits) == (7, z, 7 * z)
+
+
 # ---------------------------------------------------------------- rotation
 def _read_matrices(name):
     lines = _read_golden(name)
