@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--stage-reps", type=int, default=5)
     ap.add_argument("--check", type=int, default=6, help="at least this many images of the CPU oracle leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="bounded oracle timing (0: skip)")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="host threads of the all-core oracle figure (0: up to 16; 1: skip it)")
     ap.add_argument("--max-grid", type=int, default=0)
     ap.add_argument("--autotune", type=int, default=3, help="timed runs per candidate launch shape (0: defaults)")
     ap.add_argument("--serve-requests", type=int, default=5000, help="serving-loop requests (0: skip)")
@@ -577,7 +579,7 @@ def main():
     # batch with their own keys and payloads; only the oracle calls are timed.
     # The same round trips check the GPU's outputs of those images (marked
     # image, extracted bits, recovered image), outside the timed part.
-    cpu = None
+    cpu = cpu_all = None
     parity = {"checked": 0, "ok": True}
     if args.cpu_seconds > 0 or args.check > 0:
         import oracle as O
@@ -608,6 +610,42 @@ def main():
                    "sample": f"{n} images spread over the batch ({S}x{S}), full round trip, single thread, "
                              f"{el:.1f}s of oracle time; the same round trips checked the GPU's outputs"}
             log(f"[bench] cpu oracle: {cpu['value']} Mpx/s over {n} images")
+        if args.cpu_seconds > 0 and args.cpu_threads != 1:
+            # the same oracle on every host thread at once (its C calls release
+            # the interpreter lock), images taken in the same spread order
+            import threading
+            from concurrent.futures import ThreadPoolExecutor
+            nthr = args.cpu_threads or min(16, os.cpu_count() or 1)
+            host = []
+            for k in range(min(n, B)):
+                i = (k * stride) % B
+                c = int(caps[i])
+                host.append((imgs[i].cpu().numpy(), i, payload[int(offs[i]):int(offs[i]) + (c + 7) // 8].cpu().numpy()))
+            lock, box = threading.Lock(), {"next": 0, "done": 0}
+            stop = time.perf_counter() + args.cpu_seconds / 2
+
+            def worker():
+                while time.perf_counter() < stop:
+                    with lock:
+                        k = box["next"]
+                        box["next"] += 1
+                    I, i, m = host[k % len(host)]
+                    Ie_o, mo = O.emr_encrypt(I, k1[i])
+                    Iem_o = O.emr_embed(Ie_o, mo.b, m, mo.capacity_bits, k2[i])
+                    O.emr_extract(Iem_o, mo.b, mo.capacity_bits, k2[i])
+                    O.emr_recover(Iem_o, mo.b, k1[i])
+                    with lock:
+                        box["done"] += 1
+
+            t0 = time.perf_counter()
+            with ThreadPoolExecutor(max_workers=nthr) as ex:
+                for f in [ex.submit(worker) for _ in range(nthr)]:
+                    f.result()
+            wall = time.perf_counter() - t0
+            cpu_all = {"value": round(box["done"] * MN / wall / 1e6, 3), "unit": "Mpixel/s", "cores": nthr,
+                       "kind": "oracle", "sample": f"{box['done']} full round trips of the same images, {nthr} "
+                                                   f"threads, {wall:.1f}s wall"}
+            log(f"[bench] cpu oracle on {nthr} threads: {cpu_all['value']} Mpx/s")
 
     lmr = None
     if args.lmr_images > 0:
@@ -646,6 +684,7 @@ def main():
         "roofline": roof,
         "step_hbm_frac": round(alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "cpu_baseline": cpu,
+        "cpu_all_cores": cpu_all,
         "per_image": per_image,
         "parity": parity,
         "stages": stages,
