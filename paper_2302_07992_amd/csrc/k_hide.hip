@@ -464,42 +464,65 @@ __global__ __launch_bounds__(kThreads) void k_seg_count(const Job *__restrict__ 
 }
 
 // Pass 2: each image's step counts -> exclusive prefix sums, in place.  One
-// workgroup of kScanThreads per image; thread t takes a contiguous run of
-// steps and reads it kScanBatch counts at a time, all in flight together.
-constexpr int kScanThreads = 1024, kScanBatch = 16;
+// workgroup of kScanThreads per image, chunks of kScanChunk counts: a chunk
+// comes in with coalesced loads (consecutive threads, consecutive counts)
+// into LDS, where thread t scans its own run of kScanPer consecutive counts
+// (rows padded to an odd stride, so those reads do not collide in banks),
+// the runs' totals are scanned across the workgroup, and the prefix sums go
+// out with coalesced stores.
+constexpr int kScanThreads = 1024, kScanPer = 8;
+constexpr uint32_t kScanChunk = kScanThreads * kScanPer;
+__device__ __forceinline__ uint32_t scan_slot(uint32_t e) { return e / kScanPer * (kScanPer + 1) + e % kScanPer; }
 __global__ __launch_bounds__(kScanThreads) void k_seg_scan(const Job *__restrict__ jobs, uint32_t *__restrict__ cnt) {
+    __shared__ uint32_t sh[kScanThreads * (kScanPer + 1)];
     __shared__ uint32_t wsum[kScanThreads / 64];
     const Job &J = jobs[blockIdx.x];
     const uint32_t n = J.ucount[UNIT_SEG];
     if (n == 0) return;   // uniform over the workgroup
     uint32_t *c = cnt + J.ubase[UNIT_SEG];
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t per = (n + kScanThreads - 1) / kScanThreads;
-    const uint32_t a = tid * per < n ? tid * per : n, b = a + per < n ? a + per : n;
-    uint32_t sum = 0;
-    for (uint32_t i0 = a; i0 < b; i0 += kScanBatch) {
-        uint32_t v[kScanBatch];
+    uint32_t carry = 0;   // total of the earlier chunks (uniform)
+    for (uint32_t c0 = 0; c0 < n; c0 += kScanChunk) {
+        const uint32_t m = n - c0 < kScanChunk ? n - c0 : kScanChunk;
+        uint32_t v[kScanPer];
 #pragma unroll
-        for (int k = 0; k < kScanBatch; ++k) v[k] = i0 + k < b ? c[i0 + k] : 0u;
-#pragma unroll
-        for (int k = 0; k < kScanBatch; ++k) sum += v[k];
-    }
-    const uint32_t incl = wave_scan_incl(sum);
-    if (lane == 63) wsum[wave] = incl;
-    __syncthreads();
-    uint32_t base = 0;
-#pragma unroll
-    for (uint32_t w = 0; w < kScanThreads / 64; ++w) base += w < wave ? wsum[w] : 0u;
-    uint32_t ex = base + incl - sum;
-    for (uint32_t i0 = a; i0 < b; i0 += kScanBatch) {
-        uint32_t v[kScanBatch];
-#pragma unroll
-        for (int k = 0; k < kScanBatch; ++k) v[k] = i0 + k < b ? c[i0 + k] : 0u;
-#pragma unroll
-        for (int k = 0; k < kScanBatch; ++k) {
-            if (i0 + k < b) c[i0 + k] = ex;
-            ex += v[k];
+        for (int k = 0; k < kScanPer; ++k) {
+            const uint32_t e = (uint32_t)k * kScanThreads + tid;
+            v[k] = e < m ? c[c0 + e] : 0u;
         }
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) sh[scan_slot((uint32_t)k * kScanThreads + tid)] = v[k];
+        __syncthreads();
+        uint32_t r[kScanPer], sum = 0;
+#pragma unroll
+        for (int i = 0; i < kScanPer; ++i) {
+            r[i] = sh[tid * (kScanPer + 1) + i];
+            sum += r[i];
+        }
+        const uint32_t incl = wave_scan_incl(sum);
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        uint32_t base = carry, tot = 0;
+#pragma unroll
+        for (uint32_t w = 0; w < kScanThreads / 64; ++w) {
+            const uint32_t x = wsum[w];
+            base += w < wave ? x : 0u;
+            tot += x;
+        }
+        uint32_t ex = base + incl - sum;
+#pragma unroll
+        for (int i = 0; i < kScanPer; ++i) {
+            sh[tid * (kScanPer + 1) + i] = ex;
+            ex += r[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            const uint32_t e = (uint32_t)k * kScanThreads + tid;
+            if (e < m) c[c0 + e] = sh[scan_slot(e)];
+        }
+        carry += tot;
+        __syncthreads();   // the next chunk reuses sh and wsum
     }
 }
 

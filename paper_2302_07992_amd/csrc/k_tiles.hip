@@ -1069,8 +1069,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
 // labelled pixel (per row) still lack their replaceable bits.  One thread per
 // image row and segment s >= 1 (blockIdx.y + 1) finds the nearest segment to
 // the left with a labelled pixel in that row (column 0 always is one) and
-// completes those pixels.  Records are segment-major: [s][row].  Image
-// blockIdx.z.
+// completes those pixels, kFixPiece bytes at a time (all loads of a piece
+// before its stores).  Records are segment-major: [s][row].  Image blockIdx.z.
+constexpr uint32_t kFixPiece = 64;
 __global__ void k_recover_fix(const Job *__restrict__ jobs, const uint8_t *__restrict__ ws) {
     const Job &J = jobs[blockIdx.z];
     if (!J.fast || J.method != RDHEI_EMR) return;
@@ -1092,11 +1093,35 @@ __global__ void k_recover_fix(const Job *__restrict__ jobs, const uint8_t *__res
         }
     }
     const int b = J.fixed_b > 0 ? J.fixed_b : J.meta->b;
-    const uint32_t mrep = (0xFFu << (8 - b)) & 0xFFu;
+    const uint32_t mrep = ((0xFFu << (8 - b)) & 0xFFu) * 0x01010101u;   // replaceable bits, every byte
+    const uint32_t cv = carry * 0x01010101u;
     const uint32_t x0 = sg * (uint32_t)kQuadSeg * 2u * (uint32_t)kTile;
     const uint32_t n = lead < (uint32_t)J.N - x0 ? lead : (uint32_t)J.N - x0;
+    // rows and segments start on 64-byte boundaries; the bytes of the last
+    // block past the lead keep their values
     uint8_t *row = J.out + (uint64_t)R * (uint64_t)J.N + x0;
-    for (uint32_t k = 0; k < n; ++k) row[k] = (uint8_t)((row[k] & ~mrep) | (carry & mrep));
+    constexpr int kB = (int)(kFixPiece / 16);
+    for (uint32_t k0 = 0; k0 < n; k0 += kFixPiece) {
+        uint4 v[kB];
+#pragma unroll
+        for (int q = 0; q < kB; ++q)
+            if (k0 + 16u * (uint32_t)q < n) v[q] = *reinterpret_cast<const uint4 *>(row + k0 + 16u * (uint32_t)q);
+#pragma unroll
+        for (int q = 0; q < kB; ++q) {
+            const uint32_t k = k0 + 16u * (uint32_t)q;
+            if (k >= n) continue;
+            uint32_t w[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t lo = k + 4u * (uint32_t)j;
+                const uint32_t take = lo >= n ? 0u : (n - lo >= 4u ? 4u : n - lo);   // bytes of this word in the lead
+                const uint32_t bm = take == 4u ? 0xFFFFFFFFu : ((1u << (8u * take)) - 1u);
+                const uint32_t pm = bm & mrep;
+                w[j] = (w[j] & ~pm) | (cv & pm);
+            }
+            *reinterpret_cast<uint4 *>(row + k) = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
 }
 
 // ---- launchers ---------------------------------------------------------------
