@@ -262,12 +262,17 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
 
 // Clears the statistics record of every tiled image before k_tile_prep<true>
 // adds into it (images on the per-pixel path clear their own).
+// Thread (j, y) clears slots y, y + gridDim.y, ... of image j (two 16-byte
+// stores per slot).
 __global__ void k_stats_zero(const Job *__restrict__ jobs, int njobs, uint8_t *__restrict__ ws) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= njobs || !jobs[j].fast) return;
-    uint32_t *st = reinterpret_cast<uint32_t *>(ws + jobs[j].ws_stats);
-    const uint32_t n = stat_slots(jobs[j]) * kStatWords;
-    for (uint32_t k = 0; k < n; ++k) st[k] = 0;
+    uint4 *st = reinterpret_cast<uint4 *>(ws + jobs[j].ws_stats);
+    const uint32_t ns = stat_slots(jobs[j]);
+    for (uint32_t q = blockIdx.y; q < ns; q += gridDim.y) {
+        st[2 * q] = make_uint4(0, 0, 0, 0);
+        st[2 * q + 1] = make_uint4(0, 0, 0, 0);
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -281,12 +286,21 @@ __global__ void k_stats_zero(const Job *__restrict__ jobs, int njobs, uint8_t *_
 // meta record from an image's statistics record (words 0..6: Z_b for b =
 // 2..8, the pixels with lambda >= b); Z also stays in the workspace as 64-bit
 // values for the host (LMR candidates).
+// Called by the 64 lanes of one wave: lane q reads counter slot q (at most 64
+// slots), a shuffle tree adds the slots up, lane 0 writes the results.
 __device__ void finish_stats(const Job &J, uint8_t *ws) {
+    const uint32_t lane = threadIdx.x & 63u;
     const uint32_t *st = reinterpret_cast<const uint32_t *>(ws + J.ws_stats);
+    const uint32_t ns = stat_slots(J);
+    unsigned long long v[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) v[k] = lane < ns ? st[lane * kStatWords + (uint32_t)k] : 0ull;
+#pragma unroll
+    for (int k = 0; k < 7; ++k)
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
+    if (lane != 0) return;
     int64_t Z[9];
-    for (int b = 2; b <= 8; ++b) Z[b] = 0;
-    for (uint32_t q = 0; q < stat_slots(J); ++q)
-        for (int b = 2; b <= 8; ++b) Z[b] += st[q * kStatWords + (uint32_t)(b - 2)];
+    for (int b = 2; b <= 8; ++b) Z[b] = (int64_t)v[b - 2];
     int64_t *zout = reinterpret_cast<int64_t *>(ws + stat_z_offset(J));
     for (int b = 2; b <= 8; ++b) zout[b - 2] = Z[b];
     if (J.method == RDHEI_EMR) {
@@ -336,7 +350,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const Job *__restrict__ j
     for (int j = blockIdx.x; j < njobs; j += gridDim.x) {
         const Job &J = jobs[j];
         if (J.fast && (uint32_t)(J.tiles_x * J.tiles_y) >= kBigTiles) continue;   // uniform per workgroup
-        if (STATS && tid == 0) finish_stats(J, ws);
+        if (STATS && tid < 64) finish_stats(J, ws);                            // wave 0
         if (J.fast) {
             uint8_t *pyr = ws + J.ws_pyr;
             upper_levels(J, pyr, kTileLog + 1);     // level kTileLog holds the tile sums
@@ -390,7 +404,7 @@ __global__ __launch_bounds__(kThreads) void k_fin_blocks(const Job *__restrict__
 template <bool STATS>
 __global__ __launch_bounds__(kThreads) void k_fin_top(const Job *__restrict__ jobs, int j, uint8_t *__restrict__ ws) {
     const Job &J = jobs[j];
-    if (STATS && threadIdx.x == 0) finish_stats(J, ws);
+    if (STATS && threadIdx.x < 64) finish_stats(J, ws);                        // wave 0
     upper_levels(J, ws + J.ws_pyr, kTileLog + 5);
 }
 
@@ -1167,7 +1181,8 @@ void launch_tile_prep(const Launch &L, uint32_t units, bool stats) {
     if (!units) return;
     const uint32_t *UJ = L.ujob[UNIT_TILE];
     if (stats) {
-        hipLaunchKernelGGL(k_stats_zero, dim3((L.njobs + 255) / 256), dim3(256), 0, L.stream, L.jobs, L.njobs, L.ws);
+        hipLaunchKernelGGL(k_stats_zero, dim3((L.njobs + 255) / 256, L.njobs > 64 ? 1 : 8), dim3(256), 0, L.stream,
+                           L.jobs, L.njobs, L.ws);
         hipLaunchKernelGGL(k_tile_prep<true>, dim3(persistent_grid(L, k_tile_prep<true>, units)), dim3(kThreads), 0,
                            L.stream, L.jobs, L.njobs, L.ws, units, UJ);
     } else {
