@@ -248,6 +248,35 @@ int rdhei_lmr_compress(const uint8_t *eta_bits, const uint8_t *l_bits, int32_t M
 int rdhei_lmr_decompress(const uint8_t *stream, int64_t stream_bytes, int32_t M, int32_t N,
                          uint8_t *eta_bits, uint8_t *l_bits);
 
+/* ---- Image metrics (Sec. IV: Table EMR_results and the security analysis) ----
+ * Per pair of 8-bit images (a, b), eight doubles written to d_out[8*i + k]:
+ *   k = 0, 1  Shannon entropy (bits) and chi-square test of a (Sec. IV-B
+ *             equations: chi2 = 256 * M * N * sum_v (P_v - 1/256)^2);
+ *   k = 2, 3  the same for b;
+ *   k = 4     NPCR: percentage of positions where a and b differ (Sec. IV-B;
+ *             the printed indicator is inverted, the metric counts changes);
+ *   k = 5     UACI: mean |a - b| as a percentage of 255 (Sec. IV-B);
+ *   k = 6     PSNR = 10 log10(255^2 / MSE) dB, +inf for identical images;
+ *   k = 7     SSIM: mean over every 7x7 window inside the image of the
+ *             structural similarity with sample (co)variances, K1 = 0.01,
+ *             K2 = 0.03, L = 255 (the paper names no variant), computed only
+ *             with RDHEI_METRIC_SSIM.
+ * Values 2..7 are NaN when b is NULL; SSIM is NaN without the flag or when
+ * an image side is below 7.  a, b: device images, row-major height x width,
+ * caller-owned, read only (16-byte aligned images take vector loads).  d_out:
+ * device memory of 8 * njobs doubles, caller-owned.  The job array is host
+ * memory, copied.  Asynchronous on `stream`; errors: RDHEI_EINVAL for a
+ * NULL a or d_out, sizes below 1 or unknown flags. */
+typedef struct {
+    const uint8_t *a;
+    const uint8_t *b;
+    int32_t height, width;
+} rdhei_metric_job;
+#define RDHEI_METRIC_COUNT 8
+#define RDHEI_METRIC_SSIM  1
+int rdhei_metrics(rdhei_ctx *ctx, const rdhei_metric_job *jobs, int32_t njobs, int32_t flags, double *d_out,
+                  void *stream);
+
 /* ---- Diagnostics ---------------------------------------------------------- */
 const char *rdhei_strerror(int code);
 /* Text of the last HIP error seen by this thread (empty if none). */

@@ -358,7 +358,7 @@ struct rdhei_ctx {
     int hide_mode = 0;
     std::map<std::string, int> tuned;   // autotuned workgroup counts by op/stage/size class
     int max_grid = 0;
-    DevBuf ws, jobs, scratch, batch_tables, lmr_dev;
+    DevBuf ws, jobs, scratch, batch_tables, lmr_dev, metrics;
     HostBuf lmr_host;
     PinnedRing ring;
     std::vector<uint8_t> h_a, h_b, h_c;
@@ -986,6 +986,7 @@ void rdhei_ctx_destroy(rdhei_ctx *ctx) {
     ctx->scratch.release();
     ctx->batch_tables.release();
     ctx->lmr_dev.release();
+    ctx->metrics.release();
     ctx->lmr_host.release();
     ctx->ring.release_all();
     delete ctx;
@@ -1088,6 +1089,54 @@ int rdhei_workspace_size(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int3
     rc = make_layout(op, jobs, njobs, opts_of(ctx), Ly);
     if (rc) return rc;
     *bytes = (int64_t)Ly.ws_bytes;
+    return RDHEI_OK;
+}
+
+int rdhei_metrics(rdhei_ctx *ctx, const rdhei_metric_job *jobs, int32_t njobs, int32_t flags, double *d_out,
+                  void *stream) {
+    if (!ctx || !jobs || njobs < 1 || !d_out || (flags & ~RDHEI_METRIC_SSIM)) return RDHEI_EINVAL;
+    int rc = set_device(ctx->device);
+    if (rc) return rc;
+    const bool with_ssim = (flags & RDHEI_METRIC_SSIM) != 0;
+    std::vector<MetricJob> hj((size_t)njobs);
+    uint64_t units = 0, tiles = 0;
+    for (int i = 0; i < njobs; ++i) {
+        const rdhei_metric_job &q = jobs[i];
+        if (!q.a || q.height < 1 || q.width < 1) return RDHEI_EINVAL;
+        MetricJob &m = hj[(size_t)i];
+        m.a = q.a;
+        m.b = q.b;
+        m.M = q.height;
+        m.N = q.width;
+        m.vec = aligned16(q.a) && (!q.b || aligned16(q.b)) ? 1 : 0;
+        m.pad = 0;
+        const uint64_t MN = (uint64_t)q.height * (uint64_t)q.width;
+        m.sum_first = (uint32_t)units;
+        m.ssim_first = (uint32_t)tiles;
+        units += (MN + kMetricChunk - 1) / kMetricChunk;
+        if (with_ssim && q.b && q.height >= kSsimWin && q.width >= kSsimWin)
+            tiles += (uint64_t)((q.height - kSsimWin + 1 + kSsimRows - 1) / kSsimRows) *
+                     (uint64_t)((q.width - kSsimWin + 1 + kSsimCols - 1) / kSsimCols);
+        if (units > 0xFFFFFFFFull || tiles > 0xFFFFFFFFull) return RDHEI_EINVAL;
+    }
+    // device: job table, then the accumulators
+    const size_t tb = align_up((uint64_t)njobs * sizeof(MetricJob), 256);
+    const size_t total = tb + (size_t)njobs * sizeof(MetricAcc);
+    rc = ctx->metrics.need(total);
+    if (rc) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    uint8_t *host = nullptr;
+    int slot = 0;
+    rc = ctx->ring.acquire(tb, &host, &slot);
+    if (rc) return rc;
+    memcpy(host, hj.data(), (size_t)njobs * sizeof(MetricJob));
+    HIPCHK(hipMemcpyAsync(ctx->metrics.p, host, (size_t)njobs * sizeof(MetricJob), hipMemcpyHostToDevice, st));
+    HIPCHK(hipEventRecord(ctx->ring.done[slot], st));
+    ctx->ring.used[slot] = true;
+    launch_metrics(reinterpret_cast<const MetricJob *>(ctx->metrics.p), njobs,
+                   reinterpret_cast<MetricAcc *>(ctx->metrics.p + tb), (uint32_t)units, (uint32_t)tiles,
+                   with_ssim ? 1 : 0, d_out, st);
+    HIPCHK(hipGetLastError());
     return RDHEI_OK;
 }
 

@@ -125,4 +125,29 @@ uint64_t generic_code_bytes(int M, int N, int n);
 // Encrypt-kernel modes.
 enum EncMode { ENC_EMR = 0, ENC_LMR = 1, ENC_LMR_MAPS = 2 };
 
+// ---- image metrics (rdhei_metrics) ----
+// One image pair of a metrics launch.  Work units: kMetricChunk-pixel runs of
+// the image for the histogram-and-difference pass, tiles of kSsimRows x
+// kSsimCols window anchors for SSIM; *_first are each job's first unit.
+constexpr uint32_t kMetricChunk = 1u << 18;
+constexpr int kSsimWin = 7, kSsimRows = 64, kSsimCols = 256;
+struct MetricJob {
+    const uint8_t *a;
+    const uint8_t *b;          // nullptr: single-image metrics only
+    int32_t M, N;
+    int32_t vec;               // 1: both images 16-byte aligned (vector loads)
+    int32_t pad;
+    uint32_t sum_first, ssim_first;
+};
+// Per-job accumulators, cleared by the launch: level counts of a and b, the
+// number of differing pixels, the sums of |a - b| and of a^2 + b^2 - 2ab (=
+// sum of squared differences), and the sum of the windows' SSIM.
+struct MetricAcc {
+    uint32_t ha[256], hb[256];
+    unsigned long long ndiff, sabs, ssq;
+    double ssim;
+};
+void launch_metrics(const MetricJob *jobs, int njobs, MetricAcc *acc, uint32_t sum_units, uint32_t ssim_tiles,
+                    int with_ssim, double *out, hipStream_t st);
+
 }  // namespace rdhei

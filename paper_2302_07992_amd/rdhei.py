@@ -31,7 +31,7 @@ EXPORTS = [
     "rdhei_workspace_size", "rdhei_run_batch", "rdhei_plan_create", "rdhei_plan_run", "rdhei_plan_destroy", "rdhei_plan_set_grid",
     "rdhei_plan_stage_count", "rdhei_plan_stage_name", "rdhei_plan_run_stage",
     "rdhei_plan_autotune", "rdhei_plan_stage_grid",
-    "rdhei_lmr_batch", "rdhei_lmr_compress", "rdhei_lmr_decompress",
+    "rdhei_lmr_batch", "rdhei_lmr_compress", "rdhei_lmr_decompress", "rdhei_metrics",
     "rdhei_strerror", "rdhei_last_error", "rdhei_version",
 ]
 
@@ -50,6 +50,16 @@ class MetaStruct(ctypes.Structure):
 
 
 assert ctypes.sizeof(MetaStruct) == META_BYTES
+
+
+class MetricJobStruct(ctypes.Structure):
+    """rdhei_metric_job: one image pair of rdhei_metrics (device pointers)."""
+    _fields_ = [("a", ctypes.c_void_p), ("b", ctypes.c_void_p), ("height", ctypes.c_int32),
+                ("width", ctypes.c_int32)]
+
+
+METRIC_COUNT, METRIC_SSIM = 8, 1
+METRIC_NAMES = ("entropy_a", "chi2_a", "entropy_b", "chi2_b", "npcr", "uaci", "psnr", "ssim")
 
 
 class JobStruct(ctypes.Structure):
@@ -112,6 +122,7 @@ def load_library(path: str = LIB_PATH):
     lib.rdhei_lmr_batch.argtypes = [vp, i32, ctypes.POINTER(JobStruct), i32, i32, ctypes.POINTER(ctypes.c_double), vp]
     lib.rdhei_lmr_compress.argtypes = [vp, vp, i32, i32, vp, i64, ctypes.POINTER(i64)]
     lib.rdhei_lmr_decompress.argtypes = [vp, i64, i32, i32, vp, vp]
+    lib.rdhei_metrics.argtypes = [vp, ctypes.POINTER(MetricJobStruct), i32, i32, vp, vp]
     lib.rdhei_strerror.argtypes = [ctypes.c_int]
     lib.rdhei_strerror.restype = ctypes.c_char_p
     lib.rdhei_last_error.argtypes = []
@@ -237,6 +248,25 @@ class Context:
         p, n = _jobs_arg(jobs)
         _check(self.lib.rdhei_run_batch(self.h, op, p, n, ctypes.c_void_p(workspace_ptr or None),
                                         workspace_bytes, _stream(stream)), "rdhei_run_batch")
+
+    def metrics(self, pairs, ssim: bool = True, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """Sec. IV image metrics of each (a, b) pair (b may be None): a device
+        tensor of shape (n, 8), columns as METRIC_NAMES.  Asynchronous."""
+        n = len(pairs)
+        arr = (MetricJobStruct * n)()
+        for i, (a, b) in enumerate(pairs):
+            if a.dtype != torch.uint8 or a.dim() != 2 or not a.is_contiguous():
+                raise RdheiError(EINVAL, "metrics: images must be contiguous 2-D uint8 tensors")
+            if b is not None and (b.shape != a.shape or b.dtype != torch.uint8 or not b.is_contiguous()):
+                raise RdheiError(EINVAL, "metrics: b must match a")
+            arr[i].a = a.data_ptr()
+            arr[i].b = b.data_ptr() if b is not None else None
+            arr[i].height, arr[i].width = int(a.shape[0]), int(a.shape[1])
+        if out is None:
+            out = torch.empty((n, METRIC_COUNT), dtype=torch.float64, device=pairs[0][0].device)
+        _check(self.lib.rdhei_metrics(self.h, arr, n, METRIC_SSIM if ssim else 0, ctypes.c_void_p(out.data_ptr()),
+                                      _stream(stream)), "rdhei_metrics")
+        return out
 
     def lmr_batch(self, op: int, jobs, threads: int = 0, stream=None) -> dict:
         """One LMR role over a job array (method LMR); returns the seconds spent
