@@ -68,6 +68,7 @@ def parse():
     ap.add_argument("--autotune", type=int, default=3, help="timed runs per candidate launch shape (0: defaults)")
     ap.add_argument("--serve-requests", type=int, default=5000, help="serving-loop requests (0: skip)")
     ap.add_argument("--single-reps", type=int, default=200, help="runs of the one-image latency leg (0: skip)")
+    ap.add_argument("--metrics-reps", type=int, default=3, help="timed runs of the batch metrics leg (0: skip)")
     ap.add_argument("--large-sides", default="8192,16384", help="single large images timed stage by stage ('' to skip)")
     ap.add_argument("--lmr-images", type=int, default=2000, help="LMR batch of 512x512 images (0: skip)")
     ap.add_argument("--lmr-threads", type=int, default=0, help="host coder threads (0: all)")
@@ -574,6 +575,45 @@ def main():
         for p in pi.values():
             p.close()
 
+    # ---- Sec. IV image metrics of the whole batch (rdhei_metrics) ----
+    metrics = None
+    if args.metrics_reps > 0:
+        step()                       # fresh outputs of the batched plans
+        torch.cuda.synchronize()
+        pr = [(imgs[i], rec[i]) for i in range(B)]      # reconstruction quality (Table EMR_results)
+        pm = [(imgs[i], enc[i]) for i in range(B)]      # original against marked image (Table analysis)
+        rq = ctx.metrics(pr, ssim=True)
+        ra = ctx.metrics(pm, ssim=False)
+        torch.cuda.synchronize()
+        t_ms = {}
+        for name, pairs, with_ssim, out in (("quality_with_ssim", pr, True, rq), ("security", pm, False, ra)):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(args.metrics_reps):
+                ctx.metrics(pairs, ssim=with_ssim, out=out)
+            b.record()
+            torch.cuda.synchronize()
+            t_ms[name] = a.elapsed_time(b) / args.metrics_reps
+        q, sa = rq.cpu().numpy(), ra.cpu().numpy()
+        der = caps / float(MN)
+        mm = lambda v: {"min": round(float(np.min(v)), 4), "avg": round(float(np.mean(v)), 4),
+                        "max": round(float(np.max(v)), 4)}
+        metrics = {
+            "emr_results": {"der_bpp": mm(der), "psnr_db": mm(q[:, 6]), "ssim": mm(q[:, 7])},
+            "analysis_avg": {"entropy_I": round(float(np.mean(sa[:, 0])), 4),
+                             "chi2_I": round(float(np.mean(sa[:, 1])), 2),
+                             "entropy_marked": round(float(np.mean(sa[:, 2])), 4),
+                             "chi2_marked": round(float(np.mean(sa[:, 3])), 2),
+                             "npcr_pct": round(float(np.mean(sa[:, 4])), 4),
+                             "uaci_pct": round(float(np.mean(sa[:, 5])), 4),
+                             "psnr_db": round(float(np.mean(sa[:, 6])), 4)},
+            "ms": {k: round(v, 4) for k, v in t_ms.items()},
+            "mpx_per_s": {k: round(px / (v * 1e-3) / 1e6, 1) for k, v in t_ms.items()},
+            "read_GBps": {k: round(2.0 * px / (v * 1e-3) / 1e9, 1) for k, v in t_ms.items()},
+        }
+        log(f"[bench] metrics: {metrics['ms']} ms, Table EMR_results {metrics['emr_results']}, "
+            f"analysis {metrics['analysis_avg']}")
+
     # ---- CPU oracle on a bounded sample of the same workload ----
     # Full round trips of the oracle, single thread, on images spread over the
     # batch with their own keys and payloads; only the oracle calls are timed.
@@ -691,6 +731,7 @@ def main():
         "serving": serving,
         "large": large,
         "single": single,
+        "metrics": metrics,
         "lmr": lmr,
     }
     print(json.dumps(out), flush=True)

@@ -34,11 +34,10 @@ __global__ void k_metric_zero(MetricAcc *acc, uint32_t words16) {
 
 // ---- level counts and pixel differences -----------------------------------
 // One workgroup per kMetricChunk-pixel run of an image (grid-stride).  Each
-// wave counts levels into its own LDS histograms (fewer lanes on one
-// address); the run's counts then go to the job's counters with one atomic
-// add per level.  Per four pixels: bytes that differ from the XOR, sum |a-b|
-// with one sum-of-absolute-differences, sum (a-b)^2 as a.a + b.b - 2 a.b with
-// three 4-byte dot products.
+// wave counts levels into its own LDS histograms; the run's counts then go
+// to the job's counters with one atomic add per level.  Per four pixels: bytes that differ from the XOR,
+// sum |a-b| with one sum-of-absolute-differences, sum (a-b)^2 as a.a + b.b -
+// 2 a.b with three 4-byte dot products.
 __device__ __forceinline__ void diff4(uint32_t x, uint32_t y, uint32_t &nd, uint32_t &sa, uint32_t &s2, uint32_t &sxy) {
     const uint32_t d = x ^ y;
     nd += (uint32_t)__popc((((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d) & 0x80808080u);
@@ -73,20 +72,31 @@ __global__ __launch_bounds__(kThreads) void k_metric_sums(const MetricJob *__res
         };
         uint64_t q0 = p0;
         if (J.vec) {
-            // whole 16-byte groups (p0 is a multiple of 16), then the tail
+            // whole 16-byte groups (p0 is a multiple of 16), consecutive lanes on
+            // consecutive groups, the next group loaded ahead; then the tail
             const uint64_t g1 = p0 + (p1 - p0) / 16 * 16;
-            for (uint64_t p = p0 + 16 * (uint64_t)tid; p < g1; p += 16 * (uint64_t)kThreads) {
-                const uint4 x = gload<uint4>(J.a + p);
-                const uint4 y = pair ? gload<uint4>(J.b + p) : make_uint4(0, 0, 0, 0);
-                count4(x.x, y.x);
-                count4(x.y, y.y);
-                count4(x.z, y.z);
-                count4(x.w, y.w);
+            uint64_t q = p0 + 16 * (uint64_t)tid;
+            uint4 x = make_uint4(0, 0, 0, 0), y = make_uint4(0, 0, 0, 0);
+            if (q < g1) {
+                x = gload<uint4>(J.a + q);
+                if (pair) y = gload<uint4>(J.b + q);
+            }
+            for (; q < g1; q += 16 * (uint64_t)kThreads) {
+                const uint4 cx = x, cy = y;
+                const uint64_t qn = q + 16 * (uint64_t)kThreads;
+                if (qn < g1) {
+                    x = gload<uint4>(J.a + qn);
+                    if (pair) y = gload<uint4>(J.b + qn);
+                }
+                count4(cx.x, cy.x);
+                count4(cx.y, cy.y);
+                count4(cx.z, cy.z);
+                count4(cx.w, cy.w);
             }
             q0 = g1;
         }
-        for (uint64_t p = q0 + tid; p < p1; p += kThreads) {   // bytes one by one
-            const uint32_t x = J.a[p], y = pair ? J.b[p] : 0u;
+        for (uint64_t q = q0 + tid; q < p1; q += kThreads) {   // bytes one by one
+            const uint32_t x = J.a[q], y = pair ? J.b[q] : 0u;
             atomicAdd(&ha[x], 1u);
             if (pair) {
                 atomicAdd(&hb[y], 1u);
@@ -131,25 +141,28 @@ __global__ __launch_bounds__(kThreads) void k_metric_sums(const MetricJob *__res
 // stride): the tile's pixels of both images (anchors plus 6 rows and
 // columns) go to LDS; thread t owns anchor column t, runs down the rows with
 // the last seven rows' horizontal sums in registers (one ring slot per row
-// of a 7-row group) and a running vertical sum, and scores each window in
-// double precision, in the same order of operations as the definition.
+// of a 7-row group) and a running vertical sum, and scores each window from
+// its exact integer sums with one double division.
 __device__ __forceinline__ double ssim_window(int32_t sa, int32_t sb, int32_t saa, int32_t sbb, int32_t sab) {
-#pragma clang fp contract(off)
-    const double n = (double)(kSsimWin * kSsimWin);
-    const double ua = (double)sa / n, ub = (double)sb / n;
-    const double cov = n / (n - 1.0);
-    const double va = cov * ((double)saa / n - ua * ua);
-    const double vb = cov * ((double)sbb / n - ub * ub);
-    const double vab = cov * ((double)sab / n - ua * ub);
-    const double C1 = (0.01 * 255.0) * (0.01 * 255.0), C2 = (0.03 * 255.0) * (0.03 * 255.0);
-    return ((2.0 * ua * ub + C1) * (2.0 * vab + C2)) / ((ua * ua + ub * ub + C1) * (va + vb + C2));
+    // With n = 49 pixels the means are s/n and the sample (co)variances
+    // (n s_xy - s_x s_y) / (n (n - 1)); scaling the luminance factor by n^2
+    // and the contrast-structure factor by n (n - 1) leaves integers (below
+    // 2^31 for 8-bit pixels) plus the constants C1 n^2 and C2 n (n - 1).
+    constexpr int32_t n = kSsimWin * kSsimWin;
+    constexpr double C1n = (0.01 * 255.0) * (0.01 * 255.0) * (double)(n * n);
+    constexpr double C2n = (0.03 * 255.0) * (0.03 * 255.0) * (double)(n * (n - 1));
+    const int32_t pab = sa * sb;
+    const double l_num = (double)(2 * pab) + C1n, l_den = (double)(sa * sa + sb * sb) + C1n;
+    const double c_num = (double)(2 * (n * sab - pab)) + C2n;
+    const double c_den = (double)((n * saa - sa * sa) + (n * sbb - sb * sb)) + C2n;
+    return (l_num * c_num) / (l_den * c_den);
 }
 
 __global__ __launch_bounds__(kThreads) void k_metric_ssim(const MetricJob *__restrict__ jobs, int njobs,
                                                            MetricAcc *__restrict__ acc, uint32_t tiles) {
-    constexpr int kPR = kSsimRows + kSsimWin - 1, kPC = kSsimCols + kSsimWin - 1, kStride = kPC + 2;
+    constexpr int kPR = kSsimRows + kSsimWin - 1, kPC = kSsimCols + kSsimWin - 1, kStride = (kPC + 3) / 4 * 4 + 4;
     static_assert(kSsimCols == kThreads, "one anchor column per thread");
-    __shared__ uint8_t pa[kPR * kStride], pb[kPR * kStride];
+    __shared__ __align__(16) uint8_t pa[kPR * kStride], pb[kPR * kStride];
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
     for (uint32_t u = blockIdx.x; u < tiles; u += gridDim.x) {
         const int j = metric_job<true>(jobs, njobs, u);
@@ -160,12 +173,26 @@ __global__ __launch_bounds__(kThreads) void k_metric_ssim(const MetricJob *__res
         const int r0 = v / tcols * kSsimRows, c0 = v % tcols * kSsimCols;
         const int rows = (AR - r0 < kSsimRows ? AR - r0 : kSsimRows) + kSsimWin - 1;   // pixel rows of the tile
         __syncthreads();   // the previous tile's readers are done
-        for (int i = (int)tid; i < kPR * kPC; i += kThreads) {
-            const int y = i / kPC, x = i % kPC;
-            const bool in = y < rows && c0 + x < J.N;
-            const uint64_t off = (uint64_t)(r0 + y) * (uint64_t)J.N + (uint64_t)(c0 + x);
-            pa[y * kStride + x] = in ? J.a[off] : 0;
-            pb[y * kStride + x] = in ? J.b[off] : 0;
+        if (J.vec && (J.N & 3) == 0) {
+            // 4-byte words (rows and the tile's first column are 4-aligned)
+            constexpr int kPW = (kPC + 3) / 4;
+            for (int i = (int)tid; i < kPR * kPW; i += kThreads) {
+                const int y = i / kPW, x = 4 * (i % kPW);
+                const bool in = y < rows && c0 + x < J.N;   // a word is inside the row or outside it
+                const uint64_t off = (uint64_t)(r0 + y) * (uint64_t)J.N + (uint64_t)(c0 + x);
+                const uint32_t wa = in ? *reinterpret_cast<const uint32_t *>(J.a + off) : 0u;
+                const uint32_t wb = in ? *reinterpret_cast<const uint32_t *>(J.b + off) : 0u;
+                *reinterpret_cast<uint32_t *>(pa + y * kStride + x) = wa;
+                *reinterpret_cast<uint32_t *>(pb + y * kStride + x) = wb;
+            }
+        } else {
+            for (int i = (int)tid; i < kPR * kPC; i += kThreads) {
+                const int y = i / kPC, x = i % kPC;
+                const bool in = y < rows && c0 + x < J.N;
+                const uint64_t off = (uint64_t)(r0 + y) * (uint64_t)J.N + (uint64_t)(c0 + x);
+                pa[y * kStride + x] = in ? J.a[off] : 0;
+                pb[y * kStride + x] = in ? J.b[off] : 0;
+            }
         }
         __syncthreads();
         const bool col = c0 + (int)tid < AC;
