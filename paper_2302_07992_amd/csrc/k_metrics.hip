@@ -204,16 +204,22 @@ __global__ __launch_bounds__(kThreads) void k_metric_ssim(const MetricJob *__res
             for (int k = 0; k < kSsimWin; ++k) {
                 const int y = y0 + k;
                 if (y < rows) {   // uniform over the workgroup
-                    int32_t ha = 0, hb = 0, haa = 0, hbb = 0, hab = 0;
-#pragma unroll
-                    for (int d = 0; d < kSsimWin; ++d) {
-                        const int32_t x = pa[y * kStride + (int)tid + d], z = pb[y * kStride + (int)tid + d];
-                        ha += x;
-                        hb += z;
-                        haa += x * x;
-                        hbb += z * z;
-                        hab += x * z;
-                    }
+                    // bytes tid .. tid + 6 of the row as two words (the second
+                    // masked to three bytes), from three aligned LDS words
+                    const uint32_t *wa = reinterpret_cast<const uint32_t *>(pa + y * kStride) + (tid >> 2);
+                    const uint32_t *wb = reinterpret_cast<const uint32_t *>(pb + y * kStride) + (tid >> 2);
+                    const uint32_t sh = (tid & 3u) * 8u;
+                    const uint32_t a0 = __builtin_amdgcn_alignbit(wa[1], wa[0], sh);
+                    const uint32_t a1 = __builtin_amdgcn_alignbit(wa[2], wa[1], sh) & 0x00FFFFFFu;
+                    const uint32_t b0 = __builtin_amdgcn_alignbit(wb[1], wb[0], sh);
+                    const uint32_t b1 = __builtin_amdgcn_alignbit(wb[2], wb[1], sh) & 0x00FFFFFFu;
+                    // byte sums by sum-of-absolute-differences against 0, the
+                    // products by 4-byte dot products
+                    const int32_t ha = (int32_t)__builtin_amdgcn_sad_u8(a0, 0u, __builtin_amdgcn_sad_u8(a1, 0u, 0u));
+                    const int32_t hb = (int32_t)__builtin_amdgcn_sad_u8(b0, 0u, __builtin_amdgcn_sad_u8(b1, 0u, 0u));
+                    const int32_t haa = (int32_t)__builtin_amdgcn_udot4(a0, a0, __builtin_amdgcn_udot4(a1, a1, 0u, false), false);
+                    const int32_t hbb = (int32_t)__builtin_amdgcn_udot4(b0, b0, __builtin_amdgcn_udot4(b1, b1, 0u, false), false);
+                    const int32_t hab = (int32_t)__builtin_amdgcn_udot4(a0, b0, __builtin_amdgcn_udot4(a1, b1, 0u, false), false);
                     if (y >= kSsimWin) {   // row y - 7 leaves the window
                         sa -= ra[k];
                         sb -= rb[k];
@@ -241,45 +247,51 @@ __global__ __launch_bounds__(kThreads) void k_metric_ssim(const MetricJob *__res
 }
 
 // ---- per-job results -------------------------------------------------------
+// One wave per job: lane l takes levels 4l .. 4l + 3 of the entropy and
+// chi-square sums, a shuffle tree adds the lanes up, lane 0 writes
 // out[8 j + k]: entropy(a), chi2(a), entropy(b), chi2(b), NPCR, UACI, PSNR,
 // SSIM (NaN where b is absent, SSIM not asked for or the image is smaller
 // than the window; PSNR infinite for identical images).
-__device__ double level_entropy(const uint32_t *h, double MN) {
-    double H = 0.0;
-    for (int v = 0; v < 256; ++v) {
-        if (!h[v]) continue;
-        const double p = (double)h[v] / MN;
-        H -= p * log2(p);
+__device__ __forceinline__ void level_terms(const uint32_t *h, double MN, uint32_t lane, double &H, double &X) {
+    H = 0.0;
+    X = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t c = h[4 * lane + (uint32_t)k];
+        const double p = (double)c / MN;
+        if (c) H -= p * log2(p);
+        const double d = p - 1.0 / 256.0;
+        X += d * d;
     }
-    return H;
-}
-__device__ double level_chi2(const uint32_t *h, double MN) {
-    double s = 0.0;
-    for (int v = 0; v < 256; ++v) {
-        const double d = (double)h[v] / MN - 1.0 / 256.0;
-        s += d * d;
+    for (int off = 32; off > 0; off >>= 1) {
+        H += __shfl_down(H, off, 64);
+        X += __shfl_down(X, off, 64);
     }
-    return 256.0 * MN * s;
 }
 
-__global__ void k_metric_final(const MetricJob *__restrict__ jobs, int njobs, const MetricAcc *__restrict__ acc,
-                               int with_ssim, double *__restrict__ out) {
-#pragma clang fp contract(off)
-    const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (j >= njobs) return;
+__global__ __launch_bounds__(kThreads) void k_metric_final(const MetricJob *__restrict__ jobs, int njobs,
+                                                            const MetricAcc *__restrict__ acc, int with_ssim,
+                                                            double *__restrict__ out) {
+    const int j = (int)(blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6));
+    if (j >= njobs) return;   // whole waves
+    const uint32_t lane = threadIdx.x & 63u;
     const MetricJob &J = jobs[j];
     const MetricAcc &A = acc[j];
     const double MN = (double)J.M * (double)J.N;
     const double nan = __builtin_nan("");
     double *o = out + 8 * (uint64_t)j;
-    o[0] = level_entropy(A.ha, MN);
-    o[1] = level_chi2(A.ha, MN);
+    double Ha, Xa, Hb = 0.0, Xb = 0.0;
+    level_terms(A.ha, MN, lane, Ha, Xa);
+    if (J.b) level_terms(A.hb, MN, lane, Hb, Xb);
+    if (lane != 0) return;
+    o[0] = Ha;
+    o[1] = 256.0 * MN * Xa;
     if (!J.b) {
         for (int k = 2; k < 8; ++k) o[k] = nan;
         return;
     }
-    o[2] = level_entropy(A.hb, MN);
-    o[3] = level_chi2(A.hb, MN);
+    o[2] = Hb;
+    o[3] = 256.0 * MN * Xb;
     o[4] = 100.0 * (double)A.ndiff / MN;
     o[5] = 100.0 * (double)A.sabs / (255.0 * MN);
     o[6] = A.ssq == 0 ? __builtin_inf() : 10.0 * log10(255.0 * 255.0 / ((double)A.ssq / MN));
@@ -301,7 +313,9 @@ void launch_metrics(const MetricJob *jobs, int njobs, MetricAcc *acc, uint32_t s
     if (with_ssim && ssim_tiles)
         hipLaunchKernelGGL(k_metric_ssim, dim3(ssim_tiles < cap ? ssim_tiles : cap), dim3(kThreads), 0, st, jobs,
                            njobs, acc, ssim_tiles);
-    hipLaunchKernelGGL(k_metric_final, dim3((njobs + 255) / 256), dim3(256), 0, st, jobs, njobs, acc, with_ssim, out);
+    constexpr int kJobsPerBlock = kThreads / 64;
+    hipLaunchKernelGGL(k_metric_final, dim3((njobs + kJobsPerBlock - 1) / kJobsPerBlock), dim3(kThreads), 0, st, jobs,
+                       njobs, acc, with_ssim, out);
 }
 
 }  // namespace rdhei
