@@ -250,21 +250,15 @@ class Context:
                                         workspace_bytes, _stream(stream)), "rdhei_run_batch")
 
     def metrics(self, pairs, ssim: bool = True, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
-        """Sec. IV image metrics of each (a, b) pair (b may be None): a device
-        tensor of shape (n, 8), columns as METRIC_NAMES.  Asynchronous."""
-        n = len(pairs)
-        arr = (MetricJobStruct * n)()
-        for i, (a, b) in enumerate(pairs):
-            if a.dtype != torch.uint8 or a.dim() != 2 or not a.is_contiguous():
-                raise RdheiError(EINVAL, "metrics: images must be contiguous 2-D uint8 tensors")
-            if b is not None and (b.shape != a.shape or b.dtype != torch.uint8 or not b.is_contiguous()):
-                raise RdheiError(EINVAL, "metrics: b must match a")
-            arr[i].a = a.data_ptr()
-            arr[i].b = b.data_ptr() if b is not None else None
-            arr[i].height, arr[i].width = int(a.shape[0]), int(a.shape[1])
+        """Sec. IV image metrics of each (a, b) pair (b may be None), or of a
+        job array from make_metric_jobs: a device tensor of shape (n, 8),
+        columns as METRIC_NAMES.  Asynchronous."""
+        jobs = pairs if isinstance(pairs, ctypes.Array) else make_metric_jobs(pairs)
+        n = len(jobs)
         if out is None:
-            out = torch.empty((n, METRIC_COUNT), dtype=torch.float64, device=pairs[0][0].device)
-        _check(self.lib.rdhei_metrics(self.h, arr, n, METRIC_SSIM if ssim else 0, ctypes.c_void_p(out.data_ptr()),
+            dev = pairs[0][0].device if not isinstance(pairs, ctypes.Array) else torch.device("cuda")
+            out = torch.empty((n, METRIC_COUNT), dtype=torch.float64, device=dev)
+        _check(self.lib.rdhei_metrics(self.h, jobs, n, METRIC_SSIM if ssim else 0, ctypes.c_void_p(out.data_ptr()),
                                       _stream(stream)), "rdhei_metrics")
         return out
 
@@ -281,6 +275,22 @@ class Context:
         M, N = marked.shape
         _check(self.lib.rdhei_recover(self.h, _ptr(marked), M, N, method, _ptr(meta), _ptr(out), k1,
                                       _stream(stream)), "rdhei_recover")
+
+
+def make_metric_jobs(pairs) -> ctypes.Array:
+    """rdhei_metric_job array from (a, b) pairs of contiguous 2-D uint8
+    device tensors (b may be None)."""
+    n = len(pairs)
+    arr = (MetricJobStruct * n)()
+    for i, (a, b) in enumerate(pairs):
+        if a.dtype != torch.uint8 or a.dim() != 2 or not a.is_contiguous():
+            raise RdheiError(EINVAL, "metrics: images must be contiguous 2-D uint8 tensors")
+        if b is not None and (b.shape != a.shape or b.dtype != torch.uint8 or not b.is_contiguous()):
+            raise RdheiError(EINVAL, "metrics: b must match a")
+        arr[i].a = a.data_ptr()
+        arr[i].b = b.data_ptr() if b is not None else None
+        arr[i].height, arr[i].width = int(a.shape[0]), int(a.shape[1])
+    return arr
 
 
 def make_jobs(ins: Sequence, outs: Sequence, msgs: Sequence, metas: Sequence, keys: Sequence[int],
