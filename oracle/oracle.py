@@ -72,8 +72,8 @@ def _load():
     lib.or_lmr_compress.argtypes = [u8p, u8p, ctypes.c_int32, ctypes.c_int32, u8p, ctypes.c_int64]
     lib.or_lmr_compress.restype = ctypes.c_int64
     lib.or_lmr_decompress.argtypes = [u8p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, u8p, u8p]
-    lib.or_lmr_encode.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, u8p, ctypes.c_void_p,
-                                  u8p, ctypes.POINTER(ctypes.c_int64)]
+    lib.or_lmr_encode.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32, u8p,
+                                  ctypes.c_void_p, u8p, ctypes.POINTER(ctypes.c_int64)]
     _lib = lib
     return lib
 
@@ -274,15 +274,16 @@ def lmr_decompress(stream, M: int, N: int):
     return eta, l
 
 
-def lmr_encode(I, k1: int):
-    """Full LMR encoding: (I_e, meta, stream bytes) or (None, meta, None) for a bad case."""
+def lmr_encode(I, k1: int, min_level: int = 4):
+    """Full LMR encoding with rotation blocks 2^min_level..2^n: (I_e, meta,
+    stream bytes) or (None, meta, None) for a bad case."""
     I = _img(I)
     M, N = I.shape
     Ie = np.zeros_like(I)
     m = _OrMeta()
     stream = np.zeros(M * N // 8 + 16, dtype=np.uint8)
     bits = ctypes.c_int64()
-    rc = _load().or_lmr_encode(_u8(I), M, N, k1, _u8(Ie), ctypes.byref(m), _u8(stream), ctypes.byref(bits))
+    rc = _load().or_lmr_encode(_u8(I), M, N, k1, min_level, _u8(Ie), ctypes.byref(m), _u8(stream), ctypes.byref(bits))
     meta = OracleMeta(m.b, m.min_level, m.max_level, m.redundant, m.capacity_bits)
     if rc != 0:
         return None, meta, None

@@ -565,11 +565,12 @@ int or_lmr_decompress(const uint8_t *in, int64_t len, int32_t M, int32_t N, uint
 
 /* LMR encoding phase (Sec. III-B): b in [2,8]; candidates in order of the
  * LMR capacity (b-1)*Z_b (ties: smaller b first); for each, rotate the maps
- * with blocks 2^4..2^n, compress, and keep the first whose stream fits the
- * M*N-bit MSB plane (the "next most optimal location map" fallback).
- * Returns 0 and fills Ie/meta/stream, or -1 for a bad case. */
-int or_lmr_encode(const uint8_t *I, int32_t M, int32_t N, uint64_t k1, uint8_t *Ie, or_meta *meta,
-                  uint8_t *stream, int64_t *stream_bits)
+ * with blocks 2^min_level..2^n (the method uses 2^4; Table LMR_block_size
+ * also starts at 2^1, 2^2 and 2^3), compress, and keep the first whose
+ * stream fits the M*N-bit MSB plane (the "next most optimal location map"
+ * fallback).  Returns 0 and fills Ie/meta/stream, or -1 for a bad case. */
+int or_lmr_encode(const uint8_t *I, int32_t M, int32_t N, uint64_t k1, int32_t min_level, uint8_t *Ie,
+                  or_meta *meta, uint8_t *stream, int64_t *stream_bits)
 {
     size_t MN = (size_t)M * (size_t)N;
     int64_t Z[7];
@@ -590,12 +591,12 @@ int or_lmr_encode(const uint8_t *I, int32_t M, int32_t N, uint64_t k1, uint8_t *
     int64_t len = -1;
     for (int k = 0; k < 7 && !chosen; ++k) {
         int b = order[k];
-        or_lmr_rotated_maps(I, M, N, b, 4, k1, l_rot, eta_rot);
+        or_lmr_rotated_maps(I, M, N, b, min_level, k1, l_rot, eta_rot);
         len = or_lmr_compress(eta_rot, l_rot, M, N, stream, cap);
         if (len >= 0) chosen = b;
     }
     free(l_rot); free(eta_rot);
-    meta->min_level = 4;
+    meta->min_level = min_level;
     meta->max_level = or_max_level(M, N);
     if (!chosen) {
         meta->b = 0; meta->redundant = 0; meta->capacity_bits = 0;
@@ -606,6 +607,6 @@ int or_lmr_encode(const uint8_t *I, int32_t M, int32_t N, uint64_t k1, uint8_t *
     meta->redundant = Z[chosen - 2];
     meta->capacity_bits = (int64_t)(chosen - 1) * Z[chosen - 2];
     *stream_bits = 8 * len;
-    or_lmr_encrypt(I, M, N, 4, k1, stream, 8 * len, Ie);
+    or_lmr_encrypt(I, M, N, min_level, k1, stream, 8 * len, Ie);
     return 0;
 }

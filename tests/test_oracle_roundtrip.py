@@ -147,3 +147,26 @@ def test_lmr_lossless_with_any_stream(shape):
         assert np.array_equal(_bits(O.lmr_extract(Iem, b, l_rot, cap, k2), cap), _bits(msg, cap))
         R = O.lmr_recover(Iem, b, 4, k1, l_rot, eta_rot)
         assert np.array_equal(R, I)
+
+
+@pytest.mark.parametrize("min_level", [1, 2, 3, 4])
+def test_lmr_encode_any_block_start_lossless(min_level):
+    """Table LMR_block_size: rotation blocks from 2^min_level up.  The chosen
+    maps are the location and first-MSB maps rotated with those levels (the
+    rotation itself is pinned against rot90), they fit the MSB plane, and the
+    round trip is exact."""
+    I = inputs.make_image_np(40 + min_level, 96, 128, 8, 2.0)
+    k1, k2 = 99 + min_level, 1234
+    Ie, meta, stream = O.lmr_encode(I, k1, min_level)
+    assert Ie is not None and meta.min_level == min_level
+    M, N = I.shape
+    s = O.image_keystream(k1, M, N)
+    l, z = O.location_map(I, meta.b)
+    eta, lr = O.lmr_decompress(stream, M, N)
+    assert np.array_equal(lr, O.rotate(l, s, min_level=min_level))
+    assert np.array_equal(eta, O.rotate(I >> 7, s, min_level=min_level))
+    cap = meta.capacity_bits
+    msg = np.packbits(np.random.default_rng(min_level).integers(0, 2, cap).astype(np.uint8))
+    Iem = O.lmr_embed(Ie, meta.b, lr, msg, cap, k2)
+    assert np.array_equal(_bits(O.lmr_extract(Iem, meta.b, lr, cap, k2), cap), _bits(msg, cap))
+    assert np.array_equal(O.lmr_recover(Iem, meta.b, min_level, k1, lr, eta), I)
