@@ -213,6 +213,11 @@ int rdhei_run_batch(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t n
                                     counted 4096-pixel steps; 1 always one wave
                                     per image; 2 always steps.  Results are
                                     identical.                                   */
+#define RDHEI_OPT_LMR_MIN_LEVEL 5 /* LMR rotation blocks 2^v..2^n, v in 1..4
+                                    (default 4, the method's; Table
+                                    LMR_block_size compares 1..4).  Every role
+                                    of an image must use the same value; it is
+                                    recorded in meta.min_level.                  */
 int rdhei_ctx_set_option(rdhei_ctx *ctx, int32_t option, int64_t value);
 
 /* ---- LMR over a batch of images (Sec. III-B) ---------------------------------

@@ -129,6 +129,7 @@ bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 struct LayoutOpts {
     bool per_pixel = false;   // every image on the per-pixel path
     int hide_mode = 0;        // RDHEI_OPT_HIDE_MODE
+    int lmr_min_level = 4;    // RDHEI_OPT_LMR_MIN_LEVEL
 };
 
 // Whether image q of a hiding op may be walked whole by one workgroup.
@@ -184,7 +185,7 @@ int make_layout(int op, const rdhei_job *in, int n, const LayoutOpts &opt, Layou
         J.M = q.height;
         J.N = q.width;
         J.method = q.method;
-        J.min_level = q.method == RDHEI_EMR ? 1 : 4;
+        J.min_level = q.method == RDHEI_EMR ? 1 : opt.lmr_min_level;
         J.max_level = floor_log2_min(q.height, q.width);
         const uint64_t MN = (uint64_t)q.height * (uint64_t)q.width;
         const bool rot = op == RDHEI_OP_ENCRYPT || op == RDHEI_OP_RECOVER;
@@ -356,6 +357,7 @@ struct rdhei_ctx {
     int device = 0;
     int per_pixel = 0;
     int hide_mode = 0;
+    int lmr_min_level = 4;
     std::map<std::string, int> tuned;   // autotuned workgroup counts by op/stage/size class
     int max_grid = 0;
     DevBuf ws, jobs, scratch, batch_tables, lmr_dev, metrics;
@@ -391,6 +393,7 @@ LayoutOpts opts_of(const rdhei_ctx *ctx) {
     LayoutOpts o;
     o.per_pixel = ctx->per_pixel != 0;
     o.hide_mode = ctx->hide_mode;
+    o.lmr_min_level = ctx->lmr_min_level;
     return o;
 }
 
@@ -541,7 +544,7 @@ int lmr_encrypt(rdhei_ctx *ctx, const uint8_t *d_img, uint8_t *d_enc, int32_t M,
         if (r != RDHEI_ENOFIT) return r;
     }
     rdhei_meta m{};
-    m.height = M; m.width = N; m.method = RDHEI_LMR; m.min_level = 4; m.max_level = J0.max_level;
+    m.height = M; m.width = N; m.method = RDHEI_LMR; m.min_level = J0.min_level; m.max_level = J0.max_level;
     if (!chosen) {
         m.status = RDHEI_ENOFIT;
         HIPCHK(hipMemcpyAsync(d_meta, &m, sizeof m, hipMemcpyHostToDevice, st));
@@ -1001,6 +1004,9 @@ int rdhei_ctx_set_option(rdhei_ctx *ctx, int32_t option, int64_t value) {
     } else if (option == RDHEI_OPT_HIDE_MODE) {
         if (value < 0 || value > 2) return RDHEI_EINVAL;
         ctx->hide_mode = (int)value;
+    } else if (option == RDHEI_OPT_LMR_MIN_LEVEL) {
+        if (value < 1 || value > 4) return RDHEI_EINVAL;
+        ctx->lmr_min_level = (int)value;
     } else if (option == RDHEI_OPT_RESERVE_WS) {
         if (value < 0) return RDHEI_EINVAL;
         int rc = set_device(ctx->device);

@@ -274,7 +274,8 @@ def test_invalid_arguments_rejected_on_host(R, ctx):
     with pytest.raises(R.RdheiError):
         ctx.encrypt(d, torch.empty_like(d), 1, meta, method=7)
     c2 = R.Context(0)
-    for opt, bad in ((R.OPT_HIDE_MODE, 3), (R.OPT_HIDE_MODE, -1), (R.OPT_MAX_GRID, -5), (R.OPT_RESERVE_WS, -1), (99, 0)):
+    for opt, bad in ((R.OPT_HIDE_MODE, 3), (R.OPT_HIDE_MODE, -1), (R.OPT_MAX_GRID, -5), (R.OPT_RESERVE_WS, -1),
+                     (R.OPT_LMR_MIN_LEVEL, 0), (R.OPT_LMR_MIN_LEVEL, 5), (99, 0)):
         with pytest.raises(R.RdheiError):
             c2.set_option(opt, bad)
     c2.set_option(R.OPT_RESERVE_WS, 1 << 20)
@@ -534,9 +535,24 @@ def test_lmr_matches_oracle(R, ctx, shape):
     meta, marked image, extracted message and the exact recovery."""
     M, N = shape
     print(f"[lmr parity] shape={M}x{N}", flush=True)
-    I = _image(M + 3 * N, M, N, sigma=1.0)
-    k1, k2 = 31 + M, 41 + N
-    Ie_o, mo, stream = O.lmr_encode(I, k1)
+    _lmr_parity(R, ctx, _image(M + 3 * N, M, N, sigma=1.0), 31 + M, 41 + N, 4)
+
+
+@pytest.mark.parametrize("level", [1, 2, 3])
+@pytest.mark.parametrize("shape", [(256, 256), (100, 90)], ids=lambda s: f"{s[0]}x{s[1]}")
+def test_lmr_block_starts_match_oracle(R, shape, level):
+    """Table LMR_block_size: rotation blocks from 2^1, 2^2 or 2^3 instead of
+    the method's 2^4 (RDHEI_OPT_LMR_MIN_LEVEL), tiled and per-pixel."""
+    M, N = shape
+    print(f"[lmr parity] shape={M}x{N} level={level}", flush=True)
+    c = R.Context(0)
+    c.set_option(R.OPT_LMR_MIN_LEVEL, level)
+    _lmr_parity(R, c, _image(M + 5 * N + level, M, N, sigma=1.0), 61 + level, 71 + level, level)
+
+
+def _lmr_parity(R, ctx, I, k1, k2, level):
+    M, N = I.shape
+    Ie_o, mo, stream = O.lmr_encode(I, k1, level)
     assert Ie_o is not None
     d_img = _dev(I)
     d_enc = torch.empty_like(d_img)
@@ -544,6 +560,7 @@ def test_lmr_matches_oracle(R, ctx, shape):
     ctx.encrypt(d_img, d_enc, k1, meta, method=R.LMR)
     m = R.read_meta(meta)
     assert (m.status, m.b, m.redundant, m.capacity_bits) == (0, mo.b, mo.redundant, mo.capacity_bits)
+    assert m.min_level == level
     assert m.map_bits == 8 * stream.size
     assert np.array_equal(d_enc.cpu().numpy(), Ie_o)
     nbits = m.capacity_bits
@@ -560,7 +577,7 @@ def test_lmr_matches_oracle(R, ctx, shape):
     d_rec = torch.empty_like(d_img)
     ctx.recover(d_enc, meta, d_rec, k1, method=R.LMR)
     rec = d_rec.cpu().numpy()
-    assert np.array_equal(rec, O.lmr_recover(Iem_o, mo.b, 4, k1, l_rot, eta_rot))
+    assert np.array_equal(rec, O.lmr_recover(Iem_o, mo.b, level, k1, l_rot, eta_rot))
     assert np.array_equal(rec, I)
 
 
