@@ -148,57 +148,71 @@ def lmr_bench(args):
     imgs = torch.empty(B, S, S, dtype=torch.uint8, device=dev)
     for i in range(B):
         imgs[i].copy_(inputs.make_image(50_000 + i, S, S, 8, (1.0, 3.0, 8.0)[i % 3], dev))
-    enc = torch.zeros_like(imgs)
-    rec = torch.zeros_like(imgs)
-    metas = rdhei.new_meta(B)
-    ctx = rdhei.Context(0)
-    shapes = [(S, S)] * B
-    k1 = [inputs.key_pair(50_000 + i)[0] for i in range(B)]
-    k2 = [inputs.key_pair(50_000 + i)[1] for i in range(B)]
-    mp = [metas[i] for i in range(B)]
-    torch.cuda.synchronize()
-    times = {}
-    times["encrypt"] = ctx.lmr_batch(rdhei.OP_ENCRYPT, rdhei.make_jobs(list(imgs), list(enc), None, mp, k1, None, shapes,
-                                                                      method=rdhei.LMR), args.lmr_threads)
-    meta = rdhei.read_meta_array(metas)
-    good = meta["status"] == 0
-    caps = np.where(good, meta["capacity_bits"], 0).astype(np.int64)
-    sizes = np.array([rdhei.msg_bytes(int(c)) for c in caps], dtype=np.int64)
-    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]])
-    g = torch.Generator(device=dev)
-    g.manual_seed(4242)
-    payload = torch.randint(0, 256, (int(sizes.sum()),), generator=g, device=dev, dtype=torch.int32).to(torch.uint8)
-    got = torch.zeros_like(payload)
-    bp, bx = payload.data_ptr(), got.data_ptr()
-    times["embed"] = ctx.lmr_batch(rdhei.OP_EMBED, rdhei.make_jobs(None, list(enc), [bp + int(o) for o in offs], mp, k2,
-                                                                  caps, shapes, method=rdhei.LMR), args.lmr_threads)
-    times["extract"] = ctx.lmr_batch(rdhei.OP_EXTRACT, rdhei.make_jobs(list(enc), None, [bx + int(o) for o in offs], mp,
-                                                                      k2, caps, shapes, method=rdhei.LMR), args.lmr_threads)
-    times["recover"] = ctx.lmr_batch(rdhei.OP_RECOVER, rdhei.make_jobs(list(enc), list(rec), None, mp, k1, None, shapes,
-                                                                      method=rdhei.LMR), args.lmr_threads)
-    torch.cuda.synchronize()
-    gi = torch.from_numpy(np.nonzero(good)[0]).to(dev)
-    exact = bool(torch.equal(rec[gi], imgs[gi]))
-    bits_ok = True
-    for i in np.nonzero(good)[0][:: max(1, int(good.sum()) // 50)]:          # sampled payload checks
-        c = int(caps[i])
-        a = payload[int(offs[i]):int(offs[i]) + (c + 7) // 8].cpu().numpy()
-        b = got[int(offs[i]):int(offs[i]) + (c + 7) // 8].cpu().numpy()
-        bits_ok = bits_ok and np.array_equal(np.unpackbits(a)[:c], np.unpackbits(b)[:c])
-    px = B * S * S
-    dev_s = sum(t["device_s"] for t in times.values())
-    cod_s = sum(t["coder_s"] for t in times.values())
-    tot_s = sum(t["total_s"] for t in times.values())
-    der = float(caps[good].sum()) / float(int(good.sum()) * S * S) if good.any() else 0.0
-    out = {"workload": f"{B} x {S}x{S}, sigma 1/3/8, 8 sinusoids, payload at capacity", "good": int(good.sum()),
-           "bad": int((meta["status"] == rdhei.ENOFIT).sum()), "psnr_inf_all_good": exact, "payload_ok": bits_ok,
-           "der_bpp": round(der, 4), "b_hist": {int(b): int((meta["b"][good] == b).sum()) for b in range(2, 9)},
-           "seconds": {k: {kk: round(vv, 4) for kk, vv in t.items()} for k, t in times.items()},
-           "device_mpx_per_s": round(px / dev_s / 1e6, 1), "end_to_end_mpx_per_s": round(px / tot_s / 1e6, 1),
-           "coder_s": round(cod_s, 4), "coder_threads": args.lmr_threads or _os.cpu_count()}
-    log(f"[lmr] good {out['good']} bad {out['bad']} exact={exact} payload_ok={bits_ok} DER {out['der_bpp']}; "
-        f"device {dev_s:.3f}s coder {cod_s:.3f}s total {tot_s:.3f}s")
-    del imgs, enc, rec, payload, got
+    def run(level):
+        enc = torch.zeros_like(imgs)
+        rec = torch.zeros_like(imgs)
+        metas = rdhei.new_meta(B)
+        ctx = rdhei.Context(0)
+        ctx.set_option(rdhei.OPT_LMR_MIN_LEVEL, level)
+        shapes = [(S, S)] * B
+        k1 = [inputs.key_pair(50_000 + i)[0] for i in range(B)]
+        k2 = [inputs.key_pair(50_000 + i)[1] for i in range(B)]
+        mp = [metas[i] for i in range(B)]
+        torch.cuda.synchronize()
+        times = {}
+        times["encrypt"] = ctx.lmr_batch(rdhei.OP_ENCRYPT, rdhei.make_jobs(list(imgs), list(enc), None, mp, k1, None, shapes,
+                                                                          method=rdhei.LMR), args.lmr_threads)
+        meta = rdhei.read_meta_array(metas)
+        good = meta["status"] == 0
+        caps = np.where(good, meta["capacity_bits"], 0).astype(np.int64)
+        sizes = np.array([rdhei.msg_bytes(int(c)) for c in caps], dtype=np.int64)
+        offs = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+        g = torch.Generator(device=dev)
+        g.manual_seed(4242)
+        payload = torch.randint(0, 256, (int(sizes.sum()),), generator=g, device=dev, dtype=torch.int32).to(torch.uint8)
+        got = torch.zeros_like(payload)
+        bp, bx = payload.data_ptr(), got.data_ptr()
+        times["embed"] = ctx.lmr_batch(rdhei.OP_EMBED, rdhei.make_jobs(None, list(enc), [bp + int(o) for o in offs], mp, k2,
+                                                                      caps, shapes, method=rdhei.LMR), args.lmr_threads)
+        times["extract"] = ctx.lmr_batch(rdhei.OP_EXTRACT, rdhei.make_jobs(list(enc), None, [bx + int(o) for o in offs], mp,
+                                                                          k2, caps, shapes, method=rdhei.LMR), args.lmr_threads)
+        times["recover"] = ctx.lmr_batch(rdhei.OP_RECOVER, rdhei.make_jobs(list(enc), list(rec), None, mp, k1, None, shapes,
+                                                                          method=rdhei.LMR), args.lmr_threads)
+        torch.cuda.synchronize()
+        gi = torch.from_numpy(np.nonzero(good)[0]).to(dev)
+        exact = bool(torch.equal(rec[gi], imgs[gi]))
+        bits_ok = True
+        for i in np.nonzero(good)[0][:: max(1, int(good.sum()) // 50)]:          # sampled payload checks
+            c = int(caps[i])
+            a = payload[int(offs[i]):int(offs[i]) + (c + 7) // 8].cpu().numpy()
+            b = got[int(offs[i]):int(offs[i]) + (c + 7) // 8].cpu().numpy()
+            bits_ok = bits_ok and np.array_equal(np.unpackbits(a)[:c], np.unpackbits(b)[:c])
+        px = B * S * S
+        dev_s = sum(t["device_s"] for t in times.values())
+        cod_s = sum(t["coder_s"] for t in times.values())
+        tot_s = sum(t["total_s"] for t in times.values())
+        der = float(caps[good].sum()) / float(int(good.sum()) * S * S) if good.any() else 0.0
+        out = {"workload": f"{B} x {S}x{S}, sigma 1/3/8, 8 sinusoids, payload at capacity", "good": int(good.sum()),
+               "bad": int((meta["status"] == rdhei.ENOFIT).sum()), "psnr_inf_all_good": exact, "payload_ok": bits_ok,
+               "der_bpp": round(der, 4), "b_hist": {int(b): int((meta["b"][good] == b).sum()) for b in range(2, 9)},
+               "seconds": {k: {kk: round(vv, 4) for kk, vv in t.items()} for k, t in times.items()},
+               "device_mpx_per_s": round(px / dev_s / 1e6, 1), "end_to_end_mpx_per_s": round(px / tot_s / 1e6, 1),
+               "coder_s": round(cod_s, 4), "coder_threads": args.lmr_threads or _os.cpu_count()}
+        log(f"[lmr] blocks from 2^{level}: good {out['good']} bad {out['bad']} exact={exact} payload_ok={bits_ok} "
+            f"DER {out['der_bpp']}; "
+            f"device {dev_s:.3f}s coder {cod_s:.3f}s total {tot_s:.3f}s")
+        del enc, rec, payload, got
+        torch.cuda.empty_cache()
+        return out
+
+    out = run(4)
+    # Table LMR_block_size: the same batch with rotation blocks from 2^1, 2^2, 2^3 (and 2^4 above)
+    out["block_sizes"] = []
+    for level in (1, 2, 3, 4):
+        r = out if level == 4 else run(level)
+        out["block_sizes"].append({"min_level": level, "der_bpp": r["der_bpp"], "good": r["good"], "bad": r["bad"],
+                                   "psnr_inf_all_good": r["psnr_inf_all_good"], "payload_ok": r["payload_ok"]})
+    del imgs
     torch.cuda.empty_cache()
     return out
 
@@ -740,7 +754,7 @@ def main():
     print(json.dumps(out), flush=True)
     if (not parity["ok"] or (large and not all(r["extract_ok"] and r["lsb_only"] for r in large))
             or (single and not single["identical_runs"])
-            or (lmr and not (lmr["psnr_inf_all_good"] and lmr["payload_ok"]))):
+            or (lmr and not all(r["psnr_inf_all_good"] and r["payload_ok"] for r in lmr["block_sizes"]))):
         sys.exit(3)
 
 
