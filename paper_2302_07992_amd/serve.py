@@ -25,6 +25,7 @@ streams and events only: every step of the method runs in librdhei.
 from __future__ import annotations
 
 import ctypes
+import gc
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -370,7 +371,18 @@ class Server:
     # ---- the loop --------------------------------------------------------
     def run(self, wl: Workload, arrivals: np.ndarray, count: Optional[int] = None) -> ServeResult:
         """Serve the first `count` (default all) of wl's requests, arriving at
-        `arrivals` (seconds, ascending)."""
+        `arrivals` (seconds, ascending).  The interpreter's cyclic garbage
+        collector is paused meanwhile (the loop makes small objects per batch;
+        a collection in the middle of a run stalls every request queued)."""
+        was = gc.isenabled()
+        gc.disable()
+        try:
+            return self._run(wl, arrivals, count)
+        finally:
+            if was:
+                gc.enable()
+
+    def _run(self, wl: Workload, arrivals: np.ndarray, count: Optional[int] = None) -> ServeResult:
         n = len(wl) if count is None else int(count)
         arrivals = np.asarray(arrivals, dtype=np.float64)
         assert len(arrivals) == n and np.all(np.diff(arrivals) >= 0)
