@@ -24,9 +24,9 @@ if ROOT not in sys.path:
 METRIC = "Mpixel/s embed+recover (batched vs per-image) at bit-exact; p99 latency served"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_emr_batch_4000x512.md")
-STAGE_KERNEL = {"tile_prep_stats": "rdhei::k_tile_prep<true>", "encrypt_tiles": "rdhei::k_encrypt_quad<0>",
-                "embed_images": "rdhei::k_hide_wave<true>", "extract_images": "rdhei::k_hide_wave<false>",
-                "recover_bands": "rdhei::k_recover_quad_emr"}
+STAGE_KERNEL = {"tile_prep_stats": "rdhei::k_tile_prep<true, 0>", "encrypt_tiles": "rdhei::k_encrypt_quad<0, 0>",
+                "embed_images": "rdhei::k_hide_wave<true, 0>", "extract_images": "rdhei::k_hide_wave<false, 0>",
+                "recover_bands": "rdhei::k_recover_quad_emr<0>"}
 
 
 def log(*a):
@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--metrics-reps", type=int, default=3, help="timed runs of the batch metrics leg (0: skip)")
     ap.add_argument("--large-sides", default="8192,16384", help="single large images timed stage by stage ('' to skip)")
     ap.add_argument("--lmr-images", type=int, default=2000, help="LMR batch of 512x512 images (0: skip)")
+    ap.add_argument("--keystream-images", type=int, default=2000,
+                    help="batch of 512x512 images timed under both keystream families (0: skip)")
     ap.add_argument("--lmr-threads", type=int, default=0, help="host coder threads (0: all)")
     ap.add_argument("--serve-pool-mib", type=int, default=2048, help="device pool of the serving loop")
     ap.add_argument("--serve-streams", type=int, default=2)
@@ -370,6 +372,90 @@ def large_bench(args):
         out.append(row)
         del img, enc, rec, msg, got
         torch.cuda.empty_cache()
+    return out
+
+
+def keystream_bench(args):
+    """The EMR round trip of one batch (512x512, the main batch's image mix)
+    under each keystream family (Philox4x32-10, ChaCha20), graph plans, each
+    stage timed with HIP events; ChaCha20 draws a whole 64-byte block per 16
+    stream bytes, so the VALU cost of the cipher shows in the stages that
+    decrypt (encrypt, recover) and whiten the payload (embed, extract).
+    Checked: the payload comes back and the recovered images differ from the
+    originals only in bit 0."""
+    import numpy as np
+    import torch
+
+    from paper_2302_07992_amd import inputs, rdhei
+    dev = torch.device("cuda:0")
+    B, S = args.keystream_images, 512
+    imgs = torch.empty(B, S, S, dtype=torch.uint8, device=dev)
+    for i in range(B):
+        imgs[i].copy_(inputs.make_image(i, S, S, inputs.batch_nsin(i), inputs.batch_sigma(i), dev))
+    enc, rec = torch.empty_like(imgs), torch.empty_like(imgs)
+    shapes = [(S, S)] * B
+    k1 = [inputs.key_pair(i)[0] for i in range(B)]
+    k2 = [inputs.key_pair(i)[1] for i in range(B)]
+    out = {"images": B, "side": S}
+    for name, fam in (("philox", rdhei.KEYSTREAM_PHILOX), ("chacha20", rdhei.KEYSTREAM_CHACHA20)):
+        log(f"[keystream] {name}: {B} x {S}x{S}")
+        ctx = rdhei.Context(0)
+        ctx.set_option(rdhei.OPT_KEYSTREAM, fam)
+        metas = rdhei.new_meta(B)
+        mptr = [metas[i] for i in range(B)]
+        enc_plan = rdhei.Plan(ctx, rdhei.OP_ENCRYPT, rdhei.make_jobs(list(imgs), list(enc), None, mptr, k1, None, shapes))
+        enc_plan.run()
+        torch.cuda.synchronize()
+        meta = rdhei.read_meta_array(metas)
+        caps = meta["capacity_bits"].astype(np.int64)
+        sizes = np.array([rdhei.msg_bytes(int(c)) for c in caps], dtype=np.int64)
+        offs = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+        g = torch.Generator(device=dev)
+        g.manual_seed(999)
+        payload = torch.randint(0, 256, (int(sizes.sum()),), generator=g, device=dev, dtype=torch.int32).to(torch.uint8)
+        got = torch.zeros_like(payload)
+        pp, px = payload.data_ptr(), got.data_ptr()
+        plans = {
+            "encrypt": enc_plan,
+            "embed": rdhei.Plan(ctx, rdhei.OP_EMBED,
+                                rdhei.make_jobs(None, list(enc), [pp + int(o) for o in offs], mptr, k2, caps, shapes)),
+            "extract": rdhei.Plan(ctx, rdhei.OP_EXTRACT,
+                                  rdhei.make_jobs(list(enc), None, [px + int(o) for o in offs], mptr, k2, caps, shapes)),
+            "recover": rdhei.Plan(ctx, rdhei.OP_RECOVER,
+                                  rdhei.make_jobs(list(enc), list(rec), None, mptr, k1, None, shapes)),
+        }
+        times = {}
+        for st in ["encrypt", "embed", "extract", "recover"]:
+            plans[st].run()                              # warm-up; leaves the stage's output
+            torch.cuda.synchronize()
+            reps = 3
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                plans[st].run()
+            b.record()
+            torch.cuda.synchronize()
+            times[st] = a.elapsed_time(b) / reps
+        ok = True
+        for i in range(B):
+            nb, r = int(caps[i]) // 8, int(caps[i]) % 8
+            o = int(offs[i])
+            ok = ok and bool(torch.equal(got[o:o + nb], payload[o:o + nb]))
+            if r:
+                mk = (0xFF << (8 - r)) & 0xFF
+                ok = ok and (int(got[o + nb]) & mk) == (int(payload[o + nb]) & mk)
+        lsb_only = bool(int((rec ^ imgs).max()) <= 1)
+        rt = sum(times.values())
+        out[name] = {"ms": {k: round(v, 4) for k, v in times.items()}, "round_trip_ms": round(rt, 4),
+                     "mpx_per_s": round(B * S * S / (rt * 1e-3) / 1e6, 1),
+                     "der_bpp": round(float(caps.sum()) / (B * S * S), 4), "extract_ok": ok, "lsb_only": lsb_only}
+        log(f"[keystream] {name}: {out[name]['ms']} -> {out[name]['mpx_per_s']} Mpx/s, extract_ok={ok}, "
+            f"lsb_only={lsb_only}")
+        del plans, enc_plan, payload, got
+        torch.cuda.synchronize()
+    out["chacha20_over_philox_time"] = round(out["chacha20"]["round_trip_ms"] / out["philox"]["round_trip_ms"], 3)
+    del imgs, enc, rec
+    torch.cuda.empty_cache()
     return out
 
 
@@ -712,6 +798,7 @@ def main():
     if args.large_sides:
         large = large_bench(args)
     single = single_bench(args) if args.single_reps > 0 else None
+    keystream = keystream_bench(args) if args.keystream_images > 0 else None
 
     serving = None
     if args.serve_requests > 0:
@@ -750,10 +837,13 @@ def main():
         "single": single,
         "metrics": metrics,
         "lmr": lmr,
+        "keystream": keystream,
     }
     print(json.dumps(out), flush=True)
     if (not parity["ok"] or (large and not all(r["extract_ok"] and r["lsb_only"] for r in large))
             or (single and not single["identical_runs"])
+            or (keystream and not all(keystream[f]["extract_ok"] and keystream[f]["lsb_only"]
+                                      for f in ("philox", "chacha20")))
             or (lmr and not all(r["psnr_inf_all_good"] and r["payload_ok"] for r in lmr["block_sizes"]))):
         sys.exit(3)
 

@@ -32,12 +32,20 @@
  *     ordered on one stream (use one context per concurrent stream).  The
  *     library never frees caller memory.
  *
- * Keystream: Philox4x32-10 (Salmon et al., SC'11) stands in for the
- * "cryptographically secure stream cipher" the paper asks for (Sec. III-A,
- * secret key generation).  Byte idx of stream (key, domain) is little-endian
- * byte idx%16 of Philox4x32-10 with counter (idx/16 low word, idx/16 high
- * word, domain, 0) and key (key low word, key high word).  Domain 1 = image
- * keystream s (K1), domain 2 = message keystream (K2).
+ * Keystream (Sec. III-A, secret key generation, asks for a cryptographically
+ * secure stream cipher); one of two counter-based families, chosen per context
+ * with RDHEI_OPT_KEYSTREAM.  Domain 1 = image keystream s (K1), domain 2 =
+ * message keystream (K2).
+ *   - RDHEI_KEYSTREAM_PHILOX (default): byte idx of stream (key, domain) is
+ *     little-endian byte idx%16 of Philox4x32-10 (Salmon et al., SC'11) with
+ *     counter (idx/16 low word, idx/16 high word, domain, 0) and key (key low
+ *     word, key high word).
+ *   - RDHEI_KEYSTREAM_CHACHA20: byte idx is byte idx%64 of the ChaCha20 block
+ *     (Bernstein 2008; the 32-bit-counter, 96-bit-nonce layout of RFC 8439)
+ *     with the 256-bit key (key as 8 little-endian bytes, then 24 zero
+ *     bytes), block counter (idx/64) mod 2^32 and nonce words (domain,
+ *     idx/2^38, 0): for images below 2^38 pixels, exactly the RFC 8439
+ *     keystream for that key and nonce from counter 0.
  */
 #ifndef RDHEI_H
 #define RDHEI_H
@@ -218,6 +226,13 @@ int rdhei_run_batch(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t n
                                     LMR_block_size compares 1..4).  Every role
                                     of an image must use the same value; it is
                                     recorded in meta.min_level.                  */
+#define RDHEI_OPT_KEYSTREAM 6    /* keystream family of every role on the
+                                    context: RDHEI_KEYSTREAM_PHILOX (default)
+                                    or RDHEI_KEYSTREAM_CHACHA20.  Like the
+                                    keys, the parties of an image must agree
+                                    on it; it is not recorded in the meta.     */
+#define RDHEI_KEYSTREAM_PHILOX   0
+#define RDHEI_KEYSTREAM_CHACHA20 1
 int rdhei_ctx_set_option(rdhei_ctx *ctx, int32_t option, int64_t value);
 
 /* ---- LMR over a batch of images (Sec. III-B) ---------------------------------

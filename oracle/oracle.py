@@ -6,6 +6,7 @@ the arithmetic is in the C file.  The library is built with gcc into
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 import subprocess
@@ -40,6 +41,8 @@ def _load():
     u32p = ctypes.POINTER(ctypes.c_uint32)
     lib.or_philox4x32_10.argtypes = [u32p, u32p, u32p]
     lib.or_keystream.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, u8p]
+    lib.or_chacha20_block.argtypes = [u32p, ctypes.c_uint32, u32p, u8p]
+    lib.or_set_keystream.argtypes = [ctypes.c_int]
     lib.or_location_map.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, u8p]
     lib.or_location_map.restype = ctypes.c_int64
     lib.or_redundancy_counts.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.c_int, i64p]
@@ -111,6 +114,35 @@ def philox4x32_10(ctr, key) -> np.ndarray:
     P = ctypes.POINTER(ctypes.c_uint32)
     lib.or_philox4x32_10(c.ctypes.data_as(P), k.ctypes.data_as(P), out.ctypes.data_as(P))
     return out
+
+
+def chacha20_block(key_words, counter: int, nonce_words) -> np.ndarray:
+    """The 64 output bytes of the ChaCha20 block function."""
+    lib = _load()
+    k = np.ascontiguousarray(key_words, dtype=np.uint32)
+    n = np.ascontiguousarray(nonce_words, dtype=np.uint32)
+    assert k.size == 8 and n.size == 3
+    out = np.zeros(64, dtype=np.uint8)
+    P = ctypes.POINTER(ctypes.c_uint32)
+    lib.or_chacha20_block(k.ctypes.data_as(P), counter, n.ctypes.data_as(P), _u8(out))
+    return out
+
+
+KEYSTREAM_PHILOX = 0
+KEYSTREAM_CHACHA20 = 1
+
+
+@contextlib.contextmanager
+def keystream_family(family: int):
+    """Every oracle call inside the block draws its keystreams from `family`
+    (KEYSTREAM_PHILOX or KEYSTREAM_CHACHA20); Philox again afterwards."""
+    assert family in (KEYSTREAM_PHILOX, KEYSTREAM_CHACHA20)
+    lib = _load()
+    lib.or_set_keystream(family)
+    try:
+        yield
+    finally:
+        lib.or_set_keystream(KEYSTREAM_PHILOX)
 
 
 def keystream(key: int, domain: int, first: int, count: int) -> np.ndarray:

@@ -18,7 +18,11 @@
  *     (idx>>4 low word, idx>>4 high word, domain, 0) and key (K low, K high).
  *     Domain 1 = image keystream s (key K1), domain 2 = message keystream
  *     (key K2).  The paper asks only for a secure stream cipher (Sec. III-A,
- *     "Secret key generation").
+ *     "Secret key generation").  The second family, selected with
+ *     or_set_keystream(1), is ChaCha20: byte idx is byte idx%64 of the
+ *     ChaCha20 block (IETF layout) with key (K as 8 little-endian bytes, 24
+ *     zero bytes), counter (idx/64) mod 2^32 and nonce words (domain,
+ *     idx/2^38, 0).
  *   - a pixel is redundant (label 0) when its b MSBs equal those of the
  *     tracker (the text of Sec. III-A wins over the indicator printed in the
  *     gliding equation).
@@ -58,10 +62,71 @@ void or_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
+/* ChaCha20 block function (Bernstein 2008; IETF layout: state words 0-3 the
+ * constant "expand 32-byte k", 4-11 the key, 12 the block counter, 13-15 the
+ * nonce).  Twenty rounds, alternately on the columns and the diagonals of the
+ * 4x4 state, then the input state added word by word; the 64 output bytes
+ * are the 16 words little-endian. */
+static uint32_t or_rotl32(uint32_t v, int n) { return (v << n) | (v >> (32 - n)); }
+
+static void or_quarter_round(uint32_t *x, int a, int b, int c, int d)
+{
+    x[a] += x[b]; x[d] ^= x[a]; x[d] = or_rotl32(x[d], 16);
+    x[c] += x[d]; x[b] ^= x[c]; x[b] = or_rotl32(x[b], 12);
+    x[a] += x[b]; x[d] ^= x[a]; x[d] = or_rotl32(x[d], 8);
+    x[c] += x[d]; x[b] ^= x[c]; x[b] = or_rotl32(x[b], 7);
+}
+
+void or_chacha20_block(const uint32_t key[8], uint32_t counter, const uint32_t nonce[3], uint8_t out[64])
+{
+    uint32_t in[16], x[16];
+    in[0] = 0x61707865u; in[1] = 0x3320646eu; in[2] = 0x79622d32u; in[3] = 0x6b206574u;
+    for (int i = 0; i < 8; ++i) in[4 + i] = key[i];
+    in[12] = counter;
+    in[13] = nonce[0]; in[14] = nonce[1]; in[15] = nonce[2];
+    memcpy(x, in, sizeof x);
+    for (int round = 0; round < 20; round += 2) {
+        or_quarter_round(x, 0, 4, 8, 12);     /* columns */
+        or_quarter_round(x, 1, 5, 9, 13);
+        or_quarter_round(x, 2, 6, 10, 14);
+        or_quarter_round(x, 3, 7, 11, 15);
+        or_quarter_round(x, 0, 5, 10, 15);    /* diagonals */
+        or_quarter_round(x, 1, 6, 11, 12);
+        or_quarter_round(x, 2, 7, 8, 13);
+        or_quarter_round(x, 3, 4, 9, 14);
+    }
+    for (int i = 0; i < 16; ++i) {
+        uint32_t v = x[i] + in[i];
+        for (int k = 0; k < 4; ++k) out[4 * i + k] = (uint8_t)(v >> (8 * k));
+    }
+}
+
+/* Keystream family of every later or_keystream call: 0 Philox4x32-10, 1
+ * ChaCha20 (see the header note). */
+static int or_family = 0;
+
+void or_set_keystream(int family) { or_family = family; }
+
 /* Bytes [first, first+count) of the stream (key, domain). */
 void or_keystream(uint64_t key, uint32_t domain, uint64_t first, uint64_t count, uint8_t *out)
 {
     uint32_t k[2] = {(uint32_t)key, (uint32_t)(key >> 32)};
+    if (or_family == 1) {
+        uint32_t ck[8] = {k[0], k[1], 0u, 0u, 0u, 0u, 0u, 0u};
+        uint8_t block[64];
+        uint64_t have = ~(uint64_t)0;      /* index of the block in `block` */
+        for (uint64_t t = 0; t < count; ++t) {
+            uint64_t idx = first + t;
+            uint64_t c = idx >> 6;
+            if (c != have) {
+                uint32_t nonce[3] = {domain, (uint32_t)(c >> 32), 0u};
+                or_chacha20_block(ck, (uint32_t)c, nonce, block);
+                have = c;
+            }
+            out[t] = block[idx & 63];
+        }
+        return;
+    }
     for (uint64_t t = 0; t < count; ++t) {
         uint64_t idx = first + t;
         uint64_t blk = idx >> 4;

@@ -121,6 +121,7 @@ struct Layout {
     uint64_t g_status = 0, g_part = 0;   // hiding workspace (embed/extract)
     int op = 0;
     int method = RDHEI_EMR;
+    int keystream = kKsPhilox;
 };
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
@@ -130,6 +131,7 @@ struct LayoutOpts {
     bool per_pixel = false;   // every image on the per-pixel path
     int hide_mode = 0;        // RDHEI_OPT_HIDE_MODE
     int lmr_min_level = 4;    // RDHEI_OPT_LMR_MIN_LEVEL
+    int keystream = kKsPhilox;   // RDHEI_OPT_KEYSTREAM
 };
 
 // Whether image q of a hiding op may be walked whole by one workgroup.
@@ -150,6 +152,7 @@ bool whole_eligible(int op, const rdhei_job &q) {
 int make_layout(int op, const rdhei_job *in, int n, const LayoutOpts &opt, Layout &L) {
     L = Layout();
     L.op = op;
+    L.keystream = opt.keystream;
     if (n < 1) return RDHEI_EINVAL;
     L.method = in[0].method;
     const bool force_per_pixel = opt.per_pixel;
@@ -358,6 +361,7 @@ struct rdhei_ctx {
     int per_pixel = 0;
     int hide_mode = 0;
     int lmr_min_level = 4;
+    int keystream = kKsPhilox;
     std::map<std::string, int> tuned;   // autotuned workgroup counts by op/stage/size class
     int max_grid = 0;
     DevBuf ws, jobs, scratch, batch_tables, lmr_dev, metrics;
@@ -394,6 +398,7 @@ LayoutOpts opts_of(const rdhei_ctx *ctx) {
     o.per_pixel = ctx->per_pixel != 0;
     o.hide_mode = ctx->hide_mode;
     o.lmr_min_level = ctx->lmr_min_level;
+    o.keystream = ctx->keystream;
     return o;
 }
 
@@ -450,6 +455,7 @@ int stage(rdhei_ctx *ctx, const Layout &Ly, DevBuf &jobs, DevBuf &ws, hipStream_
     L.max_grid = ctx->max_grid;
     L.g_status = Ly.g_status;
     L.g_part = Ly.g_part;
+    L.keystream = Ly.keystream;
     return RDHEI_OK;
 }
 
@@ -652,6 +658,7 @@ Layout subset_layout(const Layout &full, const std::vector<int> &idx) {
     Layout S;
     S.op = full.op;
     S.method = full.method;
+    S.keystream = full.keystream;
     S.ws_bytes = full.ws_bytes;
     S.g_status = full.g_status;
     S.g_part = full.g_part;
@@ -934,6 +941,7 @@ int plan_issue(rdhei_plan *P, hipStream_t st) {
     L.stream = st;
     L.max_grid = P->max_grid;
     const Layout &Ly = P->layout;
+    L.keystream = Ly.keystream;
     L.g_status = Ly.g_status;
     L.g_part = Ly.g_part;
     if (P->flags == RDHEI_PLAN_PER_IMAGE) {
@@ -1007,6 +1015,9 @@ int rdhei_ctx_set_option(rdhei_ctx *ctx, int32_t option, int64_t value) {
     } else if (option == RDHEI_OPT_LMR_MIN_LEVEL) {
         if (value < 1 || value > 4) return RDHEI_EINVAL;
         ctx->lmr_min_level = (int)value;
+    } else if (option == RDHEI_OPT_KEYSTREAM) {
+        if (value != RDHEI_KEYSTREAM_PHILOX && value != RDHEI_KEYSTREAM_CHACHA20) return RDHEI_EINVAL;
+        ctx->keystream = (int)value;
     } else if (option == RDHEI_OPT_RESERVE_WS) {
         if (value < 0) return RDHEI_EINVAL;
         int rc = set_device(ctx->device);
@@ -1195,6 +1206,7 @@ int rdhei_run_batch(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t n
     L.max_grid = ctx->max_grid;
     L.g_status = Ly.g_status;
     L.g_part = Ly.g_part;
+    L.keystream = Ly.keystream;
     for (const Stage &sg : stages_of(Ly, Ly.units, Ly.per_pixel)) sg.fn(L);
     HIPCHK(hipGetLastError());
     return RDHEI_OK;
@@ -1218,6 +1230,7 @@ int rdhei_plan_create(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t
     if (!rc) rc = P->jobs.need(table_bytes(P->layout, toff));
     if (!rc) rc = P->ws.need(P->layout.ws_bytes);
     if (!rc) rc = upload_tables(P->layout, P->jobs.p, nullptr, true, P->base);
+    P->base.keystream = P->layout.keystream;
     if (!rc && flags == RDHEI_PLAN_PER_IMAGE) {
         P->per_image.resize((size_t)njobs);
         size_t total = 0;

@@ -57,16 +57,129 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
     return U4{c0, c1, c2, c3};
 }
 
+// ChaCha20 (Bernstein 2008, in the IETF layout: four constant words, eight
+// key words, a 32-bit block counter, three nonce words; ten double rounds of
+// four column and four diagonal quarter rounds, then the input added back).
+// It is the cryptographically secure stream cipher Sec. III-A asks for, and it
+// is counter-based too, so any 64-byte block comes on its own.
+__device__ __forceinline__ void chacha_qr(uint32_t &a, uint32_t &b, uint32_t &c, uint32_t &d) {
+    a += b; d = __builtin_rotateleft32(d ^ a, 16);
+    c += d; b = __builtin_rotateleft32(b ^ c, 12);
+    a += b; d = __builtin_rotateleft32(d ^ a, 8);
+    c += d; b = __builtin_rotateleft32(b ^ c, 7);
+}
+
+// Words 4q..4q+3 of the ChaCha20 block with key (k0, k1, 0, ..., 0), counter
+// ctr and nonce (n0, n1, 0).
+__device__ __forceinline__ U4 chacha20_quarter(uint32_t k0, uint32_t k1, uint32_t ctr, uint32_t n0, uint32_t n1,
+                                               uint32_t q) {
+    const uint32_t c0 = 0x61707865u, c1 = 0x3320646eu, c2 = 0x79622d32u, c3 = 0x6b206574u;
+    uint32_t x0 = c0, x1 = c1, x2 = c2, x3 = c3;
+    uint32_t x4 = k0, x5 = k1, x6 = 0, x7 = 0, x8 = 0, x9 = 0, x10 = 0, x11 = 0;
+    uint32_t x12 = ctr, x13 = n0, x14 = n1, x15 = 0;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        chacha_qr(x0, x4, x8, x12);
+        chacha_qr(x1, x5, x9, x13);
+        chacha_qr(x2, x6, x10, x14);
+        chacha_qr(x3, x7, x11, x15);
+        chacha_qr(x0, x5, x10, x15);
+        chacha_qr(x1, x6, x11, x12);
+        chacha_qr(x2, x7, x8, x13);
+        chacha_qr(x3, x4, x9, x14);
+    }
+    U4 o;
+    o.x = q == 0 ? x0 + c0 : q == 1 ? x4 + k0 : q == 2 ? x8 : x12 + ctr;
+    o.y = q == 0 ? x1 + c1 : q == 1 ? x5 + k1 : q == 2 ? x9 : x13 + n0;
+    o.z = q == 0 ? x2 + c2 : q == 1 ? x6 : q == 2 ? x10 : x14 + n1;
+    o.w = q == 0 ? x3 + c3 : q == 1 ? x7 : q == 2 ? x11 : x15;
+    return o;
+}
+
+// DPP quad_perm: lane i of each group of four lanes reads lane sel_i, CTRL =
+// sel_0 | sel_1 << 2 | sel_2 << 4 | sel_3 << 6.
+template <int CTRL>
+__device__ __forceinline__ uint32_t qperm(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t chacha_row(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t g) {
+    const uint32_t ra = qperm<CTRL>(a), rb = qperm<CTRL>(b), rc = qperm<CTRL>(c), rd = qperm<CTRL>(d);
+    return g == 0 ? ra : g == 1 ? rb : g == 2 ? rc : rd;
+}
+
+// One ChaCha20 block computed by the four lanes of a lane quad together (same
+// key, counter and nonce in all four): lane g = lane id mod 4 holds column g of
+// the state (words g, 4+g, 8+g, 12+g) and runs its quarter round; for the
+// diagonal rounds rows 1, 2 and 3 are first turned by one, two and three lanes
+// (lane g then holds words 4+(g+1)%4, 8+(g+2)%4, 12+(g+3)%4, which is diagonal
+// g) and turned back afterwards.  A transpose inside the quad leaves lane g
+// with words 4g..4g+3.  A quarter of the full block's work per lane; every lane
+// of each quad must be active.
+__device__ __forceinline__ U4 chacha20_quad(uint32_t k0, uint32_t k1, uint32_t ctr, uint32_t n0, uint32_t n1) {
+    const uint32_t g = __lane_id() & 3u;
+    const uint32_t cst = g == 0 ? 0x61707865u : g == 1 ? 0x3320646eu : g == 2 ? 0x79622d32u : 0x6b206574u;
+    const uint32_t key = g == 0 ? k0 : g == 1 ? k1 : 0u;
+    const uint32_t ctl = g == 0 ? ctr : g == 1 ? n0 : g == 2 ? n1 : 0u;
+    uint32_t a = cst, b = key, c = 0u, d = ctl;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        chacha_qr(a, b, c, d);
+        b = qperm<0x39>(b);     // from lane (g + 1) % 4
+        c = qperm<0x4E>(c);     // from lane (g + 2) % 4
+        d = qperm<0x93>(d);     // from lane (g + 3) % 4
+        chacha_qr(a, b, c, d);
+        b = qperm<0x93>(b);
+        c = qperm<0x4E>(c);
+        d = qperm<0x39>(d);
+    }
+    a += cst;
+    b += key;
+    d += ctl;
+    // word 4g + j is row g of column j: register g of lane j (every lane reads
+    // all four registers of lane j, then keeps its own row)
+    U4 o;
+    o.x = chacha_row<0x00>(a, b, c, d, g);
+    o.y = chacha_row<0x55>(a, b, c, d, g);
+    o.z = chacha_row<0xAA>(a, b, c, d, g);
+    o.w = chacha_row<0xFF>(a, b, c, d, g);
+    return o;
+}
+
 constexpr uint32_t kDomainImage = 1;
 constexpr uint32_t kDomainMessage = 2;
 
 // The 16 stream bytes [16*blk, 16*blk+16) as four little-endian words.
+// Philox: one block per 16 bytes, counter (blk, domain, 0).  ChaCha20: the
+// 64-byte block blk/4 with the 64-bit key in key words 0-1, block counter
+// (blk/4) mod 2^32 and nonce (domain, blk/2^34, 0), so the stream is ChaCha20's
+// own byte stream for that key and nonce.
+template <int KS>
 __device__ __forceinline__ U4 stream_block(uint64_t key, uint32_t domain, uint64_t blk) {
-    return philox((uint32_t)blk, (uint32_t)(blk >> 32), domain, 0u, (uint32_t)key, (uint32_t)(key >> 32));
+    if constexpr (KS == kKsChaCha20)
+        return chacha20_quarter((uint32_t)key, (uint32_t)(key >> 32), (uint32_t)(blk >> 2), domain,
+                                (uint32_t)(blk >> 34), (uint32_t)blk & 3u);
+    else
+        return philox((uint32_t)blk, (uint32_t)(blk >> 32), domain, 0u, (uint32_t)key, (uint32_t)(key >> 32));
 }
 
+// stream_block for call sites where the four lanes of every lane quad ask,
+// together, for the four 16-byte pieces of one 64-byte-aligned stream block,
+// lane l for piece l % 4 (the tiled kernels: lanes 4k..4k+3 cover one 64-byte
+// tile row, and tile rows start on multiples of 64 because M and N are).
+// ChaCha20 then shares one block among the four lanes.
+template <int KS>
+__device__ __forceinline__ U4 stream_block_quad(uint64_t key, uint32_t domain, uint64_t blk) {
+    if constexpr (KS == kKsChaCha20)
+        return chacha20_quad((uint32_t)key, (uint32_t)(key >> 32), (uint32_t)(blk >> 2), domain, (uint32_t)(blk >> 34));
+    else
+        return stream_block<KS>(key, domain, blk);
+}
+
+template <int KS>
 __device__ __forceinline__ uint32_t stream_byte(uint64_t key, uint32_t domain, uint64_t idx) {
-    U4 v = stream_block(key, domain, idx >> 4);
+    U4 v = stream_block<KS>(key, domain, idx >> 4);
     uint32_t w = ((idx >> 2) & 3) == 0 ? v.x : ((idx >> 2) & 3) == 1 ? v.y : ((idx >> 2) & 3) == 2 ? v.z : v.w;
     return (w >> (8 * (idx & 3))) & 0xFFu;
 }

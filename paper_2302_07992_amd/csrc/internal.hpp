@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/rdhei.h"
@@ -34,6 +35,18 @@ constexpr int kStatWords = 8;
 // Tiles, tile rows (LMR recovery), hiding steps, whole images, and band
 // pairs (tile rows 2p, 2p + 1: encryption and EMR recovery go by 2x2 quads).
 enum UnitKind { UNIT_TILE = 0, UNIT_BAND = 1, UNIT_SEG = 2, UNIT_IMG = 3, UNIT_QROW = 4, UNIT_KINDS = 5 };
+
+// Keystream families (the values of RDHEI_OPT_KEYSTREAM).  Kernels that draw
+// from the keystream are instantiated once per family.
+constexpr int kKsPhilox = RDHEI_KEYSTREAM_PHILOX;
+constexpr int kKsChaCha20 = RDHEI_KEYSTREAM_CHACHA20;
+
+// Calls f(std::integral_constant<int, KS>{}) for keystream family ks.
+template <typename F>
+inline void with_keystream(int ks, F &&f) {
+    if (ks == kKsChaCha20) f(std::integral_constant<int, kKsChaCha20>{});
+    else f(std::integral_constant<int, kKsPhilox>{});
+}
 
 // Encryption cuts band pairs into segments of at most kQuadSeg 2x2 tile quads
 // (one work unit each); EMR recovery takes whole band pairs.
@@ -89,6 +102,7 @@ struct Launch {
     hipStream_t stream;
     int max_grid;             // cap on workgroups of a grid-stride launch
     uint64_t g_status = 0, g_part = 0;   // hiding workspace: step counts / ranks, partial-word records
+    int keystream = kKsPhilox;           // keystream family of every job of the launch
 };
 
 void launch_tile_prep(const Launch &L, uint32_t units, bool stats);

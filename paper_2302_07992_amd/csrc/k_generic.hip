@@ -14,6 +14,7 @@ __host__ __device__ inline uint64_t gen_off(int M, int N, int m) {
 
 // Level 1: code of each full 2x2 block = (sum of its four keystream bytes) mod 4.
 // Also clears the image's statistics record.
+template <int KS>
 __global__ void k_gen_level1(const Job *__restrict__ jobs, int j, uint8_t *__restrict__ ws) {
     const Job &J = jobs[j];
     const uint32_t gx = (uint32_t)(J.N >> 1), gy = (uint32_t)(J.M >> 1);
@@ -25,8 +26,9 @@ __global__ void k_gen_level1(const Job *__restrict__ jobs, int j, uint8_t *__res
     if (q >= (uint64_t)gx * gy) return;
     const uint32_t Y = (uint32_t)(q / gx), X = (uint32_t)(q % gx);
     const uint64_t p = (uint64_t)(2 * Y) * (uint64_t)J.N + 2 * X;
-    const uint32_t sum = stream_byte(J.key, kDomainImage, p) + stream_byte(J.key, kDomainImage, p + 1) +
-                         stream_byte(J.key, kDomainImage, p + J.N) + stream_byte(J.key, kDomainImage, p + J.N + 1);
+    const uint32_t sum = stream_byte<KS>(J.key, kDomainImage, p) + stream_byte<KS>(J.key, kDomainImage, p + 1) +
+                         stream_byte<KS>(J.key, kDomainImage, p + J.N) +
+                         stream_byte<KS>(J.key, kDomainImage, p + J.N + 1);
     ws[J.ws_codes + gen_off(J.M, J.N, 1) + q] = (uint8_t)(sum & 3u);
 }
 
@@ -83,7 +85,7 @@ __device__ inline void gen_forward(const Job &J, const uint8_t *codes, uint32_t 
     ox = cx;
 }
 
-template <int MODE>
+template <int MODE, int KS>
 __global__ void k_gen_encrypt(const Job *__restrict__ jobs, int j, uint8_t *__restrict__ ws) {
     const Job &J = jobs[j];
     const uint64_t total = (uint64_t)J.M * (uint64_t)J.N;
@@ -102,7 +104,7 @@ __global__ void k_gen_encrypt(const Job *__restrict__ jobs, int j, uint8_t *__re
         ws[J.ws_bytes + p] = (uint8_t)((l << 1) | (v >> 7));
         return;
     }
-    const uint32_t s = stream_byte(J.key, kDomainImage, p);
+    const uint32_t s = stream_byte<KS>(J.key, kDomainImage, p);
     uint32_t e;
     if (MODE == ENC_EMR) {
         e = ((v ^ s) & 0xFEu) | l;
@@ -134,7 +136,7 @@ __global__ void k_gen_pack(const Job *__restrict__ jobs, int j, const uint8_t *_
 }
 
 // One thread per row: gather, decrypt, glide.
-template <int METHOD>
+template <int METHOD, int KS>
 __global__ void k_gen_recover(const Job *__restrict__ jobs, int j, const uint8_t *__restrict__ ws) {
     const Job &J = jobs[j];
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -147,7 +149,7 @@ __global__ void k_gen_recover(const Job *__restrict__ jobs, int j, const uint8_t
         gen_forward(J, ws + J.ws_codes, i, x, py, px);
         const uint64_t p = (uint64_t)py * (uint64_t)J.N + px;
         const uint32_t e = J.in[p];
-        uint32_t D = e ^ stream_byte(J.key, kDomainImage, p);
+        uint32_t D = e ^ stream_byte<KS>(J.key, kDomainImage, p);
         uint32_t l;
         if (METHOD == RDHEI_EMR) {
             l = e & 1u;
@@ -164,12 +166,11 @@ __global__ void k_gen_recover(const Job *__restrict__ jobs, int j, const uint8_t
 static inline unsigned blocks(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
 
 void launch_generic_levels(const Launch &L, int j, const Job &h) {
-    if (h.max_level >= 1) {
-        const uint64_t n1 = (uint64_t)(h.M >> 1) * (uint64_t)(h.N >> 1);
-        hipLaunchKernelGGL(k_gen_level1, dim3(blocks(n1 ? n1 : 1, 256)), dim3(256), 0, L.stream, L.jobs, j, L.ws);
-    } else {
-        hipLaunchKernelGGL(k_gen_level1, dim3(1), dim3(256), 0, L.stream, L.jobs, j, L.ws);
-    }
+    const uint64_t n1 = h.max_level >= 1 ? (uint64_t)(h.M >> 1) * (uint64_t)(h.N >> 1) : 1;
+    with_keystream(L.keystream, [&](auto K) {
+        hipLaunchKernelGGL(k_gen_level1<decltype(K)::value>, dim3(blocks(n1 ? n1 : 1, 256)), dim3(256), 0, L.stream,
+                           L.jobs, j, L.ws);
+    });
     for (int m = 2; m <= h.max_level; ++m) {
         const uint64_t n = (uint64_t)(h.M >> m) * (uint64_t)(h.N >> m);
         hipLaunchKernelGGL(k_gen_level_up, dim3(blocks(n, 256)), dim3(256), 0, L.stream, L.jobs, j, L.ws, m);
@@ -184,18 +185,23 @@ void launch_generic_stats(const Launch &L, int j, const Job &h) {
 void launch_generic_encrypt(const Launch &L, int j, const Job &h, int mode) {
     const uint64_t n = (uint64_t)h.M * (uint64_t)h.N;
     const dim3 g(blocks(n, 256)), b(256);
-    if (mode == ENC_EMR) hipLaunchKernelGGL(k_gen_encrypt<ENC_EMR>, g, b, 0, L.stream, L.jobs, j, L.ws);
-    else if (mode == ENC_LMR) hipLaunchKernelGGL(k_gen_encrypt<ENC_LMR>, g, b, 0, L.stream, L.jobs, j, L.ws);
-    else {
-        hipLaunchKernelGGL(k_gen_encrypt<ENC_LMR_MAPS>, g, b, 0, L.stream, L.jobs, j, L.ws);
+    with_keystream(L.keystream, [&](auto K) {
+        constexpr int KS = decltype(K)::value;
+        if (mode == ENC_EMR) hipLaunchKernelGGL((k_gen_encrypt<ENC_EMR, KS>), g, b, 0, L.stream, L.jobs, j, L.ws);
+        else if (mode == ENC_LMR) hipLaunchKernelGGL((k_gen_encrypt<ENC_LMR, KS>), g, b, 0, L.stream, L.jobs, j, L.ws);
+        else hipLaunchKernelGGL((k_gen_encrypt<ENC_LMR_MAPS, KS>), g, b, 0, L.stream, L.jobs, j, L.ws);
+    });
+    if (mode == ENC_LMR_MAPS)
         hipLaunchKernelGGL(k_gen_pack, dim3(blocks((n + 7) / 8, 256)), b, 0, L.stream, L.jobs, j, L.ws);
-    }
 }
 
 void launch_generic_recover(const Launch &L, int j, const Job &h) {
     const dim3 g(blocks((uint64_t)h.M, 64)), b(64);
-    if (h.method == RDHEI_EMR) hipLaunchKernelGGL(k_gen_recover<RDHEI_EMR>, g, b, 0, L.stream, L.jobs, j, L.ws);
-    else hipLaunchKernelGGL(k_gen_recover<RDHEI_LMR>, g, b, 0, L.stream, L.jobs, j, L.ws);
+    with_keystream(L.keystream, [&](auto K) {
+        constexpr int KS = decltype(K)::value;
+        if (h.method == RDHEI_EMR) hipLaunchKernelGGL((k_gen_recover<RDHEI_EMR, KS>), g, b, 0, L.stream, L.jobs, j, L.ws);
+        else hipLaunchKernelGGL((k_gen_recover<RDHEI_LMR, KS>), g, b, 0, L.stream, L.jobs, j, L.ws);
+    });
 }
 
 uint64_t generic_code_bytes(int M, int N, int n) { return gen_off(M, N, n + 1); }

@@ -229,8 +229,9 @@ __device__ __forceinline__ uint32_t be_mask(int64_t w, int64_t lo, int64_t hi) {
 }
 
 // Message keystream word w, big-endian bit order.
+template <int KS>
 __device__ __forceinline__ uint32_t ks_word(uint64_t key, int64_t w) {
-    const U4 ks = stream_block(key, kDomainMessage, (uint64_t)w >> 2);
+    const U4 ks = stream_block<KS>(key, kDomainMessage, (uint64_t)w >> 2);
     const uint32_t kw = (w & 3) == 0 ? ks.x : (w & 3) == 1 ? ks.y : (w & 3) == 2 ? ks.z : ks.w;
     return __builtin_bswap32(kw);
 }
@@ -287,7 +288,7 @@ __device__ __forceinline__ void step_ranks(const uint32_t rm[kWLoads], uint32_t 
     T = tot0 + tot1 + tot2 + tot3;
 }
 
-template <bool EMBED>
+template <bool EMBED, int KS>
 __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &hp, uint32_t *win, const uint32_t *htab) {
     const int lane = threadIdx.x & 63;
     const uint8_t *img = EMBED ? J.out : J.in;
@@ -348,7 +349,7 @@ __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &
                 const int64_t q = lane + 64 * i;
                 if (q > lb - fb) continue;
                 const uint4 mv = q < (int64_t)npre ? mpre[i] : gload<uint4>(J.msg + 16 * (uint64_t)(fb + q));
-                const U4 ks = stream_block(J.key, kDomainMessage, (uint64_t)(fb + q));
+                const U4 ks = stream_block<KS>(J.key, kDomainMessage, (uint64_t)(fb + q));
                 *reinterpret_cast<uint4 *>(win + 4 + 4 * q) =
                     make_uint4(__builtin_bswap32(mv.x ^ ks.x), __builtin_bswap32(mv.y ^ ks.y),
                                __builtin_bswap32(mv.z ^ ks.z), __builtin_bswap32(mv.w ^ ks.w));
@@ -386,7 +387,7 @@ __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &
             if (nstore > 0) {   // one keystream block per four message words
                 const int64_t B0 = W0 >> 2, B1 = (W0 + nstore - 1) >> 2;
                 for (int64_t bq = lane; bq <= B1 - B0; bq += 64) {
-                    const U4 ks = stream_block(J.key, kDomainMessage, (uint64_t)(B0 + bq));
+                    const U4 ks = stream_block<KS>(J.key, kDomainMessage, (uint64_t)(B0 + bq));
                     const uint32_t kw[4] = {ks.x, ks.y, ks.z, ks.w};
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
@@ -404,13 +405,13 @@ __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &
         // the message's last word: bits past nbits are stored as zero
         const uint32_t own = be_mask(carry_word, 0, hp.nbits);
         gstore<uint32_t>(reinterpret_cast<uint32_t *>(J.msg) + carry_word,
-                         __builtin_bswap32((carry ^ ks_word(J.key, carry_word)) & own));
+                         __builtin_bswap32((carry ^ ks_word<KS>(J.key, carry_word)) & own));
     }
 }
 
 // One wave per workgroup, one image per wave (a grid-stride loop when the grid
 // is capped).
-template <bool EMBED>
+template <bool EMBED, int KS>
 __global__ __launch_bounds__(64) void k_hide_wave(const Job *__restrict__ jobs, int njobs, uint32_t units,
                                                   const uint32_t *__restrict__ ujob) {
     __shared__ __align__(16) uint32_t win[kWWinWords];
@@ -425,7 +426,7 @@ __global__ __launch_bounds__(64) void k_hide_wave(const Job *__restrict__ jobs, 
         if (!hp.ok) {
             if (lane == 0 && J.meta->status == RDHEI_OK) J.meta->status = RDHEI_ECAPACITY;
         } else {
-            hide_image_wave<EMBED>(J, hp, win, htab);
+            hide_image_wave<EMBED, KS>(J, hp, win, htab);
         }
         wave_sync();
     }
@@ -527,7 +528,7 @@ __global__ __launch_bounds__(kScanThreads) void k_seg_scan(const Job *__restrict
 }
 
 // Pass 3: hide (EMBED) or extract the payload bits of every step at its rank.
-template <bool EMBED>
+template <bool EMBED, int KS>
 __global__ __launch_bounds__(kThreads) void k_seg_hide(const Job *__restrict__ jobs, int njobs, uint32_t units,
                                                         const uint32_t *__restrict__ ujob,
                                                         const uint32_t *__restrict__ rank, PartWord *__restrict__ part) {
@@ -570,7 +571,7 @@ __global__ __launch_bounds__(kThreads) void k_seg_hide(const Job *__restrict__ j
             for (int64_t q = lane; q <= lb - fb; q += 64) {
                 const uint64_t blk = (uint64_t)(fb + q);
                 const uint4 mv = gload<uint4>(J.msg + 16 * blk);
-                const U4 ks = stream_block(J.key, kDomainMessage, blk);
+                const U4 ks = stream_block<KS>(J.key, kDomainMessage, blk);
                 *reinterpret_cast<uint4 *>(win + 4 + 4 * q) =
                     make_uint4(__builtin_bswap32(mv.x ^ ks.x), __builtin_bswap32(mv.y ^ ks.y),
                                __builtin_bswap32(mv.z ^ ks.z), __builtin_bswap32(mv.w ^ ks.w));
@@ -602,7 +603,7 @@ __global__ __launch_bounds__(kThreads) void k_seg_hide(const Job *__restrict__ j
             uint32_t *msgw = reinterpret_cast<uint32_t *>(J.msg);
             const int64_t B0 = W0 >> 2, B1 = (W1 - 1) >> 2;
             for (int64_t bq = lane; bq <= B1 - B0; bq += 64) {
-                const U4 ks = stream_block(J.key, kDomainMessage, (uint64_t)(B0 + bq));
+                const U4 ks = stream_block<KS>(J.key, kDomainMessage, (uint64_t)(B0 + bq));
                 const uint32_t kw[4] = {ks.x, ks.y, ks.z, ks.w};
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
@@ -640,7 +641,7 @@ static uint32_t hide_wave_resident() {
         int dev = 0, cus = 0, per_cu = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_hide_wave<true>, 64, 0) != hipSuccess || per_cu < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_hide_wave<true, kKsPhilox>, 64, 0) != hipSuccess || per_cu < 1)
             per_cu = 1;
         v = (uint32_t)(cus > 0 ? cus : 1) * (uint32_t)per_cu;
     }
@@ -658,10 +659,15 @@ void launch_hide_images(const Launch &L, uint32_t units, bool embed) {
         const uint32_t res = hide_wave_resident();
         g = units < res ? units : res;
     }
-    if (embed)
-        hipLaunchKernelGGL(k_hide_wave<true>, dim3(g), dim3(64), 0, L.stream, L.jobs, L.njobs, units, L.ujob[UNIT_IMG]);
-    else
-        hipLaunchKernelGGL(k_hide_wave<false>, dim3(g), dim3(64), 0, L.stream, L.jobs, L.njobs, units, L.ujob[UNIT_IMG]);
+    with_keystream(L.keystream, [&](auto K) {
+        constexpr int KS = decltype(K)::value;
+        if (embed)
+            hipLaunchKernelGGL((k_hide_wave<true, KS>), dim3(g), dim3(64), 0, L.stream, L.jobs, L.njobs, units,
+                               L.ujob[UNIT_IMG]);
+        else
+            hipLaunchKernelGGL((k_hide_wave<false, KS>), dim3(g), dim3(64), 0, L.stream, L.jobs, L.njobs, units,
+                               L.ujob[UNIT_IMG]);
+    });
 }
 
 
@@ -685,8 +691,10 @@ void launch_embed(const Launch &L, uint32_t units) {
     const unsigned g = step_grid(L, units);
     hipLaunchKernelGGL(k_seg_count, dim3(g), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, units, L.ujob[UNIT_SEG], cnt);
     hipLaunchKernelGGL(k_seg_scan, dim3((unsigned)L.njobs), dim3(kScanThreads), 0, L.stream, L.jobs, cnt);
-    hipLaunchKernelGGL(k_seg_hide<true>, dim3(g), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, units,
-                       L.ujob[UNIT_SEG], cnt, part);
+    with_keystream(L.keystream, [&](auto K) {
+        hipLaunchKernelGGL((k_seg_hide<true, decltype(K)::value>), dim3(g), dim3(kThreads), 0, L.stream, L.jobs,
+                           L.njobs, units, L.ujob[UNIT_SEG], cnt, part);
+    });
 }
 
 void launch_extract(const Launch &L, uint32_t units) {
@@ -696,8 +704,10 @@ void launch_extract(const Launch &L, uint32_t units) {
     const unsigned g = step_grid(L, units);
     hipLaunchKernelGGL(k_seg_count, dim3(g), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, units, L.ujob[UNIT_SEG], cnt);
     hipLaunchKernelGGL(k_seg_scan, dim3((unsigned)L.njobs), dim3(kScanThreads), 0, L.stream, L.jobs, cnt);
-    hipLaunchKernelGGL(k_seg_hide<false>, dim3(g), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, units,
-                       L.ujob[UNIT_SEG], cnt, part);
+    with_keystream(L.keystream, [&](auto K) {
+        hipLaunchKernelGGL((k_seg_hide<false, decltype(K)::value>), dim3(g), dim3(kThreads), 0, L.stream, L.jobs,
+                           L.njobs, units, L.ujob[UNIT_SEG], cnt, part);
+    });
     const uint32_t n = 2 * units;
     hipLaunchKernelGGL(k_extract_fix, dim3((n + 255) / 256), dim3(256), 0, L.stream, L.jobs, part, n, 0);
     hipLaunchKernelGGL(k_extract_fix, dim3((n + 255) / 256), dim3(256), 0, L.stream, L.jobs, part, n, 1);

@@ -47,7 +47,7 @@ __device__ __forceinline__ void unit_range(uint32_t units, uint32_t &u0, uint32_
 // thresholds at once.  Counts stay in registers across the tiles of one image
 // and go to one of the image's counter slots with one atomic add per wave.
 // ----------------------------------------------------------------------------
-template <bool STATS>
+template <bool STATS, int KS>
 __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ jobs, int njobs,
                                                          uint8_t *__restrict__ ws, uint32_t units,
                                                          const uint32_t *__restrict__ ujob) {
@@ -147,8 +147,8 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
         uint32_t h[2][4];
 #pragma unroll
         for (int pp = 0; pp < 2; ++pp) {
-            const U4 sa = stream_block(J.key, kDomainImage, (idx0 + (uint64_t)(2 * pp) * J.N) >> 4);
-            const U4 sb = stream_block(J.key, kDomainImage, (idx0 + (uint64_t)(2 * pp + 1) * J.N) >> 4);
+            const U4 sa = stream_block_quad<KS>(J.key, kDomainImage, (idx0 + (uint64_t)(2 * pp) * J.N) >> 4);
+            const U4 sb = stream_block_quad<KS>(J.key, kDomainImage, (idx0 + (uint64_t)(2 * pp + 1) * J.N) >> 4);
             const uint32_t wa[4] = {sa.x, sa.y, sa.z, sa.w}, wb[4] = {sb.x, sb.y, sb.z, sb.w};
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -457,7 +457,7 @@ __device__ __forceinline__ QSeg qseg_of(const Job *jobs, int njobs, const uint32
 // byte left of each tile row comes from the wave holding the left tile, by
 // LDS (same quad, or the right tile of the previous quad).
 // ----------------------------------------------------------------------------
-template <int MODE>
+template <int MODE, int KS>
 __global__ __launch_bounds__(kThreads) void k_encrypt_quad(const Job *__restrict__ jobs, int njobs,
                                                             uint8_t *__restrict__ ws, uint32_t units,
                                                             const uint32_t *__restrict__ ujob) {
@@ -615,7 +615,7 @@ __global__ __launch_bounds__(kThreads) void k_encrypt_quad(const Job *__restrict
                 gstore<uint16_t>(J.out + (didx >> 3), (uint16_t)lb);
                 gstore<uint16_t>(J.msg + (didx >> 3), (uint16_t)eb);
             } else {
-                const U4 sk = stream_block(J.key, kDomainImage, didx >> 4);
+                const U4 sk = stream_block_quad<KS>(J.key, kDomainImage, didx >> 4);
                 uint4 e;
                 if (MODE == ENC_EMR) {
                     e = make_uint4(qv.x ^ (sk.x & 0xFEFEFEFEu), qv.y ^ (sk.y & 0xFEFEFEFEu),
@@ -650,6 +650,7 @@ __global__ __launch_bounds__(kThreads) void k_encrypt_quad(const Job *__restrict
 // along each row: a pixel labelled 0 takes the replaceable bits of the
 // nearest pixel labelled 1 to its left.  Rows carry that value across tiles.
 // ----------------------------------------------------------------------------
+template <int KS>
 __global__ __launch_bounds__(kThreads) void k_recover_band_lmr(const Job *__restrict__ jobs, int njobs,
                                                             uint8_t *__restrict__ ws, uint32_t units,
                                                             const uint32_t *__restrict__ ujob) {
@@ -701,7 +702,7 @@ __global__ __launch_bounds__(kThreads) void k_recover_band_lmr(const Job *__rest
             uint32_t up;
             tmap_unpack(reinterpret_cast<const uint32_t *>(ws + J.ws_tmap)[ty * J.tiles_x + tx], ey, ex, up);
             const uint64_t eidx = (uint64_t)(ey * kTile + r) * (uint64_t)J.N + (uint64_t)(ex * kTile + 16 * g);
-            const U4 s = stream_block(J.key, kDomainImage, eidx >> 4);
+            const U4 s = stream_block_quad<KS>(J.key, kDomainImage, eidx >> 4);
             uint32_t D[4] = {e.x ^ s.x, e.y ^ s.y, e.z ^ s.z, e.w ^ s.w};
             uint32_t Lw[4];
 #pragma unroll
@@ -807,6 +808,7 @@ static __constant__ perm4::InvTables kInvTables = perm4::kInvTables;
 static __constant__ glide4::Tables kGlideTables = glide4::kTables;
 
 // (At most 128 VGPRs: four waves per SIMD, which is what the LDS allows.)
+template <int KS>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_recover_quad_emr(
     const Job *__restrict__ jobs, int njobs, uint8_t *__restrict__ ws, uint32_t units, const uint32_t *__restrict__ ujob) {
     constexpr int kW = kThreads / 64;
@@ -917,7 +919,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
             uint32_t dw[4][4], lw[4][4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const U4 s = stream_block(J.key, kDomainImage, (e0 + (uint64_t)i * J.N) >> 4);
+                const U4 s = stream_block_quad<KS>(J.key, kDomainImage, (e0 + (uint64_t)i * J.N) >> 4);
                 const uint32_t ew[4] = {e[i].x, e[i].y, e[i].z, e[i].w}, sw[4] = {s.x, s.y, s.z, s.w};
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
@@ -1183,12 +1185,16 @@ void launch_tile_prep(const Launch &L, uint32_t units, bool stats) {
     if (stats) {
         hipLaunchKernelGGL(k_stats_zero, dim3((L.njobs + 255) / 256, L.njobs > 64 ? 1 : 8), dim3(256), 0, L.stream,
                            L.jobs, L.njobs, L.ws);
-        hipLaunchKernelGGL(k_tile_prep<true>, dim3(persistent_grid(L, k_tile_prep<true>, units)), dim3(kThreads), 0,
-                           L.stream, L.jobs, L.njobs, L.ws, units, UJ);
-    } else {
-        hipLaunchKernelGGL(k_tile_prep<false>, dim3(persistent_grid(L, k_tile_prep<false>, units)), dim3(kThreads), 0,
-                           L.stream, L.jobs, L.njobs, L.ws, units, UJ);
     }
+    with_keystream(L.keystream, [&](auto K) {
+        constexpr int KS = decltype(K)::value;
+        if (stats)
+            hipLaunchKernelGGL((k_tile_prep<true, KS>), dim3(persistent_grid(L, k_tile_prep<true, KS>, units)),
+                               dim3(kThreads), 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+        else
+            hipLaunchKernelGGL((k_tile_prep<false, KS>), dim3(persistent_grid(L, k_tile_prep<false, KS>, units)),
+                               dim3(kThreads), 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+    });
 }
 
 void launch_finalize(const Launch &L, bool stats, const std::vector<int> &big, const std::vector<Job> &hj) {
@@ -1215,15 +1221,19 @@ void launch_encrypt_tiles(const Launch &L, uint32_t units, int mode) {
     if (!units) return;
     const uint32_t *UJ = L.ujob[UNIT_QROW];
     const dim3 bl(kThreads);
-    if (mode == ENC_EMR)
-        hipLaunchKernelGGL(k_encrypt_quad<ENC_EMR>, dim3(persistent_grid(L, k_encrypt_quad<ENC_EMR>, units)), bl, 0,
-                           L.stream, L.jobs, L.njobs, L.ws, units, UJ);
-    else if (mode == ENC_LMR)
-        hipLaunchKernelGGL(k_encrypt_quad<ENC_LMR>, dim3(persistent_grid(L, k_encrypt_quad<ENC_LMR>, units)), bl, 0,
-                           L.stream, L.jobs, L.njobs, L.ws, units, UJ);
-    else
-        hipLaunchKernelGGL(k_encrypt_quad<ENC_LMR_MAPS>, dim3(persistent_grid(L, k_encrypt_quad<ENC_LMR_MAPS>, units)),
-                           bl, 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+    with_keystream(L.keystream, [&](auto K) {
+        constexpr int KS = decltype(K)::value;
+        if (mode == ENC_EMR)
+            hipLaunchKernelGGL((k_encrypt_quad<ENC_EMR, KS>), dim3(persistent_grid(L, k_encrypt_quad<ENC_EMR, KS>, units)),
+                               bl, 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+        else if (mode == ENC_LMR)
+            hipLaunchKernelGGL((k_encrypt_quad<ENC_LMR, KS>), dim3(persistent_grid(L, k_encrypt_quad<ENC_LMR, KS>, units)),
+                               bl, 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+        else
+            hipLaunchKernelGGL((k_encrypt_quad<ENC_LMR_MAPS, KS>),
+                               dim3(persistent_grid(L, k_encrypt_quad<ENC_LMR_MAPS, KS>, units)), bl, 0, L.stream, L.jobs,
+                               L.njobs, L.ws, units, UJ);
+    });
 }
 
 void launch_recover_bands(const Launch &L, uint32_t units, int method, uint32_t fix_rows, uint32_t fix_segs) {
@@ -1231,15 +1241,21 @@ void launch_recover_bands(const Launch &L, uint32_t units, int method, uint32_t 
     const uint32_t *UJ = L.ujob[UNIT_BAND];
     const dim3 bl(kThreads);
     if (method == RDHEI_EMR) {
-        hipLaunchKernelGGL(k_recover_quad_emr, dim3(persistent_grid(L, k_recover_quad_emr, units)), bl, 0, L.stream,
-                           L.jobs, L.njobs, L.ws, units, L.ujob[UNIT_QROW]);
+        with_keystream(L.keystream, [&](auto K) {
+            constexpr int KS = decltype(K)::value;
+            hipLaunchKernelGGL((k_recover_quad_emr<KS>), dim3(persistent_grid(L, k_recover_quad_emr<KS>, units)), bl, 0,
+                               L.stream, L.jobs, L.njobs, L.ws, units, L.ujob[UNIT_QROW]);
+        });
         if (fix_rows)
             hipLaunchKernelGGL(k_recover_fix, dim3((fix_rows + 255) / 256, fix_segs - 1, (unsigned)L.njobs), dim3(256),
                                0, L.stream, L.jobs, L.ws);
     }
     else
-        hipLaunchKernelGGL(k_recover_band_lmr, dim3(persistent_grid(L, k_recover_band_lmr, units)), bl, 0,
-                           L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+        with_keystream(L.keystream, [&](auto K) {
+            constexpr int KS = decltype(K)::value;
+            hipLaunchKernelGGL((k_recover_band_lmr<KS>), dim3(persistent_grid(L, k_recover_band_lmr<KS>, units)), bl, 0,
+                               L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+        });
 }
 
 }  // namespace rdhei

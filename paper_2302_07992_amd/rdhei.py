@@ -22,7 +22,8 @@ EMR, LMR = 0, 1
 OP_ENCRYPT, OP_EMBED, OP_EXTRACT, OP_RECOVER = 0, 1, 2, 3
 PLAN_GRAPH, PLAN_EAGER, PLAN_PER_IMAGE = 0, 1, 2
 TUNE_FORCE = 1
-OPT_PER_PIXEL, OPT_MAX_GRID, OPT_RESERVE_WS, OPT_HIDE_MODE, OPT_LMR_MIN_LEVEL = 1, 2, 3, 4, 5
+OPT_PER_PIXEL, OPT_MAX_GRID, OPT_RESERVE_WS, OPT_HIDE_MODE, OPT_LMR_MIN_LEVEL, OPT_KEYSTREAM = 1, 2, 3, 4, 5, 6
+KEYSTREAM_PHILOX, KEYSTREAM_CHACHA20 = 0, 1
 META_BYTES = 64
 
 EXPORTS = [
