@@ -288,6 +288,39 @@ __device__ __forceinline__ void step_ranks(const uint32_t rm[kWLoads], uint32_t 
     T = tot0 + tot1 + tot2 + tot3;
 }
 
+// ChaCha20 message stream for a window: the lanes take 64-byte-aligned groups
+// of four 16-byte blocks, lane l block (first & ~3) + base + l, with a uniform
+// trip count, so that the four lanes of each quad compute one ChaCha20 block
+// together (stream_block_quad); blocks outside [first, last] are computed and
+// not used.
+// Embedding: message blocks fb..lb, XORed with the stream, byte-swapped into
+// win[4 + 4q], q = block - fb.
+template <int KS>
+__device__ __forceinline__ void stage_window_quad(const Job &J, int lane, int64_t fb, int64_t lb, uint32_t *win) {
+    const int64_t fa = fb & ~(int64_t)3;
+    for (int64_t base = 0; base <= lb - fa; base += 64) {
+        const int64_t q = fa + base + lane - fb;
+        const bool in = q >= 0 && q <= lb - fb;
+        const uint4 mv = in ? gload<uint4>(J.msg + 16 * (uint64_t)(fb + q)) : make_uint4(0, 0, 0, 0);
+        const U4 ks = stream_block_quad<KS>(J.key, kDomainMessage, (uint64_t)(fa + base + lane));
+        if (in)
+            *reinterpret_cast<uint4 *>(win + 4 + 4 * q) =
+                make_uint4(__builtin_bswap32(mv.x ^ ks.x), __builtin_bswap32(mv.y ^ ks.y),
+                           __builtin_bswap32(mv.z ^ ks.z), __builtin_bswap32(mv.w ^ ks.w));
+    }
+}
+
+// Extraction: calls put(block, stream words) for the blocks B0..B1 (and the
+// aligned neighbours, whose words put must skip).
+template <int KS, typename F>
+__device__ __forceinline__ void each_stream_block_quad(const Job &J, int lane, int64_t B0, int64_t B1, F &&put) {
+    const int64_t Ba = B0 & ~(int64_t)3;
+    for (int64_t base = 0; base <= B1 - Ba; base += 64) {
+        const int64_t blk = Ba + base + lane;
+        put(blk, stream_block_quad<KS>(J.key, kDomainMessage, (uint64_t)blk));
+    }
+}
+
 template <bool EMBED, int KS>
 __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &hp, uint32_t *win, const uint32_t *htab) {
     const int lane = threadIdx.x & 63;
@@ -317,7 +350,8 @@ __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &
             mpre[i] = (uint32_t)(lane + 64 * i) < n && blk < nblk ? gload<uint4>(J.msg + 16 * blk) : make_uint4(0, 0, 0, 0);
         }
     };
-    if (EMBED) msg_prefetch(0, (uint32_t)((kWSegPx / 2 * rep + 127) / 128));   // first step: half its pixels
+    constexpr bool kPrefetch = EMBED && KS != kKsChaCha20;   // ChaCha20 loads its blocks in stage_window_quad
+    if (kPrefetch) msg_prefetch(0, (uint32_t)((kWSegPx / 2 * rep + 127) / 128));   // first step: half its pixels
     for (uint32_t seg = 0; seg < nseg; ++seg) {
         const uint64_t s0 = (uint64_t)seg * kWSegPx;
         const uint64_t s1 = s0 + kWSegPx < total ? s0 + kWSegPx : total;
@@ -344,19 +378,23 @@ __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &
             // window bits relative to the first staged 16-byte block (the prefetch base)
             const int64_t fb = wstart >> 7, lb = (wend - 1) >> 7;
             const uint32_t off0 = (uint32_t)(wstart - (fb << 7)), rend = (uint32_t)(wend - (fb << 7));
+            if constexpr (KS == kKsChaCha20) {
+                stage_window_quad<KS>(J, lane, fb, lb, win);
+            } else {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int64_t q = lane + 64 * i;
-                if (q > lb - fb) continue;
-                const uint4 mv = q < (int64_t)npre ? mpre[i] : gload<uint4>(J.msg + 16 * (uint64_t)(fb + q));
-                const U4 ks = stream_block<KS>(J.key, kDomainMessage, (uint64_t)(fb + q));
-                *reinterpret_cast<uint4 *>(win + 4 + 4 * q) =
-                    make_uint4(__builtin_bswap32(mv.x ^ ks.x), __builtin_bswap32(mv.y ^ ks.y),
-                               __builtin_bswap32(mv.z ^ ks.z), __builtin_bswap32(mv.w ^ ks.w));
+                for (int i = 0; i < 4; ++i) {
+                    const int64_t q = lane + 64 * i;
+                    if (q > lb - fb) continue;
+                    const uint4 mv = q < (int64_t)npre ? mpre[i] : gload<uint4>(J.msg + 16 * (uint64_t)(fb + q));
+                    const U4 ks = stream_block<KS>(J.key, kDomainMessage, (uint64_t)(fb + q));
+                    *reinterpret_cast<uint4 *>(win + 4 + 4 * q) =
+                        make_uint4(__builtin_bswap32(mv.x ^ ks.x), __builtin_bswap32(mv.y ^ ks.y),
+                                   __builtin_bswap32(mv.z ^ ks.z), __builtin_bswap32(mv.w ^ ks.w));
+                }
             }
             // rank already counts this step
             const uint32_t used = (uint32_t)(lb - fb + 1) + 2u;
-            msg_prefetch((rank * rep) >> 7, used < 256u ? used : 256u);
+            if (kPrefetch) msg_prefetch((rank * rep) >> 7, used < 256u ? used : 256u);
             wave_sync();
 #pragma unroll
             for (int k = 0; k < kWLoads; ++k) {
@@ -386,13 +424,24 @@ __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &
             uint32_t *msgw = reinterpret_cast<uint32_t *>(J.msg);
             if (nstore > 0) {   // one keystream block per four message words
                 const int64_t B0 = W0 >> 2, B1 = (W0 + nstore - 1) >> 2;
-                for (int64_t bq = lane; bq <= B1 - B0; bq += 64) {
-                    const U4 ks = stream_block<KS>(J.key, kDomainMessage, (uint64_t)(B0 + bq));
-                    const uint32_t kw[4] = {ks.x, ks.y, ks.z, ks.w};
+                if constexpr (KS == kKsChaCha20) {
+                    each_stream_block_quad<KS>(J, lane, B0, B1, [&](int64_t blk, const U4 &ks) {
+                        const uint32_t kw[4] = {ks.x, ks.y, ks.z, ks.w};
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int64_t w = 4 * (B0 + bq) + i;
-                        if (w >= W0 && w < W0 + nstore) gstore<uint32_t>(msgw + w, __builtin_bswap32(win[w - W0]) ^ kw[i]);
+                        for (int i = 0; i < 4; ++i) {
+                            const int64_t w = 4 * blk + i;
+                            if (w >= W0 && w < W0 + nstore) gstore<uint32_t>(msgw + w, __builtin_bswap32(win[w - W0]) ^ kw[i]);
+                        }
+                    });
+                } else {
+                    for (int64_t bq = lane; bq <= B1 - B0; bq += 64) {
+                        const U4 ks = stream_block<KS>(J.key, kDomainMessage, (uint64_t)(B0 + bq));
+                        const uint32_t kw[4] = {ks.x, ks.y, ks.z, ks.w};
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int64_t w = 4 * (B0 + bq) + i;
+                            if (w >= W0 && w < W0 + nstore) gstore<uint32_t>(msgw + w, __builtin_bswap32(win[w - W0]) ^ kw[i]);
+                        }
                     }
                 }
             }
@@ -568,13 +617,17 @@ __global__ __launch_bounds__(kThreads) void k_seg_hide(const Job *__restrict__ j
             // window bits relative to the first staged 16-byte block
             const int64_t fb = wstart >> 7, lb = (wend - 1) >> 7;
             const uint32_t off0 = (uint32_t)(wstart - (fb << 7)), rend = (uint32_t)(wend - (fb << 7));
-            for (int64_t q = lane; q <= lb - fb; q += 64) {
-                const uint64_t blk = (uint64_t)(fb + q);
-                const uint4 mv = gload<uint4>(J.msg + 16 * blk);
-                const U4 ks = stream_block<KS>(J.key, kDomainMessage, blk);
-                *reinterpret_cast<uint4 *>(win + 4 + 4 * q) =
-                    make_uint4(__builtin_bswap32(mv.x ^ ks.x), __builtin_bswap32(mv.y ^ ks.y),
-                               __builtin_bswap32(mv.z ^ ks.z), __builtin_bswap32(mv.w ^ ks.w));
+            if constexpr (KS == kKsChaCha20) {
+                stage_window_quad<KS>(J, lane, fb, lb, win);
+            } else {
+                for (int64_t q = lane; q <= lb - fb; q += 64) {
+                    const uint64_t blk = (uint64_t)(fb + q);
+                    const uint4 mv = gload<uint4>(J.msg + 16 * blk);
+                    const U4 ks = stream_block<KS>(J.key, kDomainMessage, blk);
+                    *reinterpret_cast<uint4 *>(win + 4 + 4 * q) =
+                        make_uint4(__builtin_bswap32(mv.x ^ ks.x), __builtin_bswap32(mv.y ^ ks.y),
+                                   __builtin_bswap32(mv.z ^ ks.z), __builtin_bswap32(mv.w ^ ks.w));
+                }
             }
             wave_sync();
 #pragma unroll
@@ -602,23 +655,45 @@ __global__ __launch_bounds__(kThreads) void k_seg_hide(const Job *__restrict__ j
             // neighbouring step go to the side records
             uint32_t *msgw = reinterpret_cast<uint32_t *>(J.msg);
             const int64_t B0 = W0 >> 2, B1 = (W1 - 1) >> 2;
-            for (int64_t bq = lane; bq <= B1 - B0; bq += 64) {
-                const U4 ks = stream_block<KS>(J.key, kDomainMessage, (uint64_t)(B0 + bq));
-                const uint32_t kw[4] = {ks.x, ks.y, ks.z, ks.w};
+            if constexpr (KS == kKsChaCha20) {
+                each_stream_block_quad<KS>(J, lane, B0, B1, [&](int64_t blk, const U4 &ks) {
+                    const uint32_t kw[4] = {ks.x, ks.y, ks.z, ks.w};
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int64_t w = 4 * (B0 + bq) + i;
-                    if (w < W0 || w >= W1) continue;
-                    const uint32_t own = be_mask(w, wstart, wend);
-                    const uint32_t v = (win[w - W0] ^ __builtin_bswap32(kw[i])) & own;
-                    if (own == 0xFFFFFFFFu) {
-                        gstore<uint32_t>(msgw + w, __builtin_bswap32(v));
-                    } else {
-                        PartWord pw;
-                        pw.word = w;
-                        pw.bits = __builtin_bswap32(v);
-                        pw.job = (uint32_t)j;
-                        part[2 * u + (w == W0 ? 0 : 1)] = pw;
+                    for (int i = 0; i < 4; ++i) {
+                        const int64_t w = 4 * blk + i;
+                        if (w < W0 || w >= W1) continue;
+                        const uint32_t own = be_mask(w, wstart, wend);
+                        const uint32_t v = (win[w - W0] ^ __builtin_bswap32(kw[i])) & own;
+                        if (own == 0xFFFFFFFFu) {
+                            gstore<uint32_t>(msgw + w, __builtin_bswap32(v));
+                        } else {
+                            PartWord pw;
+                            pw.word = w;
+                            pw.bits = __builtin_bswap32(v);
+                            pw.job = (uint32_t)j;
+                            part[2 * u + (w == W0 ? 0 : 1)] = pw;
+                        }
+                    }
+                });
+            } else {
+                for (int64_t bq = lane; bq <= B1 - B0; bq += 64) {
+                    const U4 ks = stream_block<KS>(J.key, kDomainMessage, (uint64_t)(B0 + bq));
+                    const uint32_t kw[4] = {ks.x, ks.y, ks.z, ks.w};
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int64_t w = 4 * (B0 + bq) + i;
+                        if (w < W0 || w >= W1) continue;
+                        const uint32_t own = be_mask(w, wstart, wend);
+                        const uint32_t v = (win[w - W0] ^ __builtin_bswap32(kw[i])) & own;
+                        if (own == 0xFFFFFFFFu) {
+                            gstore<uint32_t>(msgw + w, __builtin_bswap32(v));
+                        } else {
+                            PartWord pw;
+                            pw.word = w;
+                            pw.bits = __builtin_bswap32(v);
+                            pw.job = (uint32_t)j;
+                            part[2 * u + (w == W0 ? 0 : 1)] = pw;
+                        }
                     }
                 }
             }

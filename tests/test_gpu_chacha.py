@@ -37,7 +37,8 @@ def _msg_dev(R, msg, nbits):
 
 
 @pytest.mark.parametrize("shape,frac", [((64, 64), 1.0), ((256, 256), 1.0), ((512, 512), 0.37), ((1024, 1024), 1.0),
-                                        ((2048, 1024), 1.0), ((100, 63), 1.0), ((33, 47), 0.5), ((1, 9), 1.0)],
+                                        ((2048, 1024), 1.0), ((4096, 4096), 1.0), ((100, 63), 1.0), ((33, 47), 0.5),
+                                        ((1, 9), 1.0)],
                          ids=lambda v: f"{v[0]}x{v[1]}" if isinstance(v, tuple) else f"f{v}")
 def test_emr_chacha_roundtrip_matches_oracle(R, cctx, shape, frac):
     M, N = shape
