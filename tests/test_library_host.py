@@ -37,6 +37,22 @@ def test_every_declared_function_is_exported(R):
     assert sorted(names) == sorted(R.EXPORTS)
 
 
+def test_header_constants_match_the_binding(R):
+    """Every integer #define RDHEI_<NAME> of the header that the binding also
+    names (as <NAME>) has the same value there: options, keystream families,
+    methods, ops, status codes, metric layout."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    defs = dict(re.findall(r"#define\s+RDHEI_([A-Z0-9_]+)\s+\(?(-?\d+)\)?\s*$", text, flags=re.M))
+    checked = 0
+    for name, value in defs.items():
+        if hasattr(R, name):
+            assert getattr(R, name) == int(value), name
+            checked += 1
+    for name in ("OPT_KEYSTREAM", "KEYSTREAM_PHILOX", "KEYSTREAM_CHACHA20", "OPT_LMR_MIN_LEVEL", "METRIC_COUNT"):
+        assert name in defs and hasattr(R, name), name
+    assert checked >= 10
+
+
 def test_strerror_and_version(R):
     lib = R.load_library()
     assert lib.rdhei_strerror(R.ECAPACITY).decode().startswith("message")
