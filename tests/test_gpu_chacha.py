@@ -161,3 +161,44 @@ def test_keystream_families_differ_and_must_match(R, cctx):
     for bad in (-1, 2):
         with pytest.raises(R.RdheiError):
             pctx.set_option(R.OPT_KEYSTREAM, bad)
+
+
+def test_lmr_batch_chacha_matches_oracle(R):
+    """The batched LMR roles under ChaCha20 (device stages batched, host map
+    coder): encrypted images and marked images equal the oracle's, payloads
+    and exact recovery."""
+    print("[chacha lmr batch]", flush=True)
+    ctx = R.Context(0)
+    ctx.set_option(R.OPT_KEYSTREAM, R.KEYSTREAM_CHACHA20)
+    shapes = [(256, 256), (128, 320), (100, 90), (64, 64)]
+    imgs = [inputs.make_image_np(900 + i, *s, 8, (1.0, 3.0)[i % 2]) for i, s in enumerate(shapes)]
+    n = len(imgs)
+    d_in = [_dev(I) for I in imgs]
+    k1s, k2s = [(3 << 33) + i for i in range(n)], [(5 << 35) + i for i in range(n)]
+    enc = [torch.zeros_like(x) for x in d_in]
+    metas = R.new_meta(n)
+    mp = [metas[i] for i in range(n)]
+    ctx.lmr_batch(R.OP_ENCRYPT, R.make_jobs(d_in, enc, None, mp, k1s, None, shapes, method=R.LMR), threads=2)
+    ms = R.read_meta(metas)
+    assert all(m.status == 0 for m in ms)
+    caps = [m.capacity_bits for m in ms]
+    msgs = [inputs.make_payload(20 + i, c).numpy() for i, c in enumerate(caps)]
+    d_msg = [_msg_dev(R, m, c) for m, c in zip(msgs, caps)]
+    with O.keystream_family(O.KEYSTREAM_CHACHA20):
+        want = [O.lmr_encode(I, k, 4) for I, k in zip(imgs, k1s)]
+        for i in range(n):
+            assert (ms[i].b, ms[i].capacity_bits) == (want[i][1].b, want[i][1].capacity_bits), i
+            assert np.array_equal(enc[i].cpu().numpy(), want[i][0]), i
+    ctx.lmr_batch(R.OP_EMBED, R.make_jobs(None, enc, d_msg, mp, k2s, caps, shapes, method=R.LMR))
+    got = [torch.zeros(R.msg_bytes(c), dtype=torch.uint8, device="cuda") for c in caps]
+    ctx.lmr_batch(R.OP_EXTRACT, R.make_jobs(enc, None, got, mp, k2s, caps, shapes, method=R.LMR))
+    rec = [torch.zeros_like(x) for x in d_in]
+    ctx.lmr_batch(R.OP_RECOVER, R.make_jobs(enc, rec, None, mp, k1s, None, shapes, method=R.LMR))
+    torch.cuda.synchronize()
+    with O.keystream_family(O.KEYSTREAM_CHACHA20):
+        for i in range(n):
+            Ie_o, mo, stream = want[i]
+            eta_rot, l_rot = O.lmr_decompress(stream, *shapes[i])
+            assert np.array_equal(enc[i].cpu().numpy(), O.lmr_embed(Ie_o, mo.b, l_rot, msgs[i], caps[i], k2s[i])), i
+            assert np.array_equal(got[i].cpu().numpy()[:(caps[i] + 7) // 8], msgs[i]), i
+            assert torch.equal(rec[i], d_in[i]), i
