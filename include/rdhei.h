@@ -230,7 +230,9 @@ int rdhei_run_batch(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t n
                                     context: RDHEI_KEYSTREAM_PHILOX (default)
                                     or RDHEI_KEYSTREAM_CHACHA20.  Like the
                                     keys, the parties of an image must agree
-                                    on it; it is not recorded in the meta.     */
+                                    on it; it is not recorded in the meta.
+                                    Calls made after it is set use it; a plan
+                                    keeps the family it was created with.      */
 #define RDHEI_KEYSTREAM_PHILOX   0
 #define RDHEI_KEYSTREAM_CHACHA20 1
 int rdhei_ctx_set_option(rdhei_ctx *ctx, int32_t option, int64_t value);
