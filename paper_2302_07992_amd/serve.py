@@ -245,16 +245,21 @@ class Server:
     on_complete   called as on_complete(request_index, outputs) when a
                   request's batch retires, before its memory is reused;
                   outputs maps names to device tensors (views of the pool)
+    keystream     keystream family of every request (RDHEI_OPT_KEYSTREAM):
+                  R.KEYSTREAM_PHILOX or R.KEYSTREAM_CHACHA20
     """
 
     def __init__(self, pool_bytes: int = 1 << 30, streams: int = 2, max_inflight: Optional[int] = None,
                  max_batch: int = 2048, per_request: bool = False,
-                 on_complete: Optional[Callable[[int, Dict[str, torch.Tensor]], None]] = None, device="cuda"):
+                 on_complete: Optional[Callable[[int, Dict[str, torch.Tensor]], None]] = None, device="cuda",
+                 keystream: int = R.KEYSTREAM_PHILOX):
         if per_request:
             streams = 1
         self.per_request = per_request
         self.streams = [torch.cuda.Stream(device=device) for _ in range(streams)]
         self.ctxs = [R.Context() for _ in range(streams)]
+        for c in self.ctxs:
+            c.set_option(R.OPT_KEYSTREAM, keystream)
         self.arena = Arena(pool_bytes, device)
         self.max_inflight = max_inflight or (64 if per_request else 2 * streams)
         self.max_batch = 1 if per_request else max_batch

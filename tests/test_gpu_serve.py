@@ -136,6 +136,32 @@ def test_served_matches_oracle(S, R, workload):
     assert checked == n
 
 
+def test_served_chacha_matches_oracle(S, R):
+    """A server on the ChaCha20 keystream family (RECOVER inputs prepared
+    under ChaCha20 too) against the oracle under the same family."""
+    print("[serve] chacha20", flush=True)
+    cctx = R.Context()
+    cctx.set_option(R.OPT_KEYSTREAM, R.KEYSTREAM_CHACHA20)
+    wl = S.make_workload(24, seed=11, sides=[64, 128, 100, 256], weights=[2, 2, 1, 1], ctx=cctx, keep_originals=True)
+    n = len(wl)
+    res, got = _serve(S, wl, np.zeros(n), pool_bytes=2 << 20, streams=2, keystream=R.KEYSTREAM_CHACHA20)
+    assert res.rejected == 0 and sorted(got) == list(range(n))
+    with O.keystream_family(O.KEYSTREAM_CHACHA20):
+        for i in range(n):
+            I = wl.images[i].cpu().numpy()
+            k1, k2, nb = int(wl.k1[i]), int(wl.k2[i]), int(wl.nbits[i])
+            pay = wl.payloads[i].cpu().numpy()
+            if wl.kind[i] == 0:
+                Ie, mo = O.emr_encrypt(I, k1)
+                assert mo.capacity_bits == nb
+                assert np.array_equal(got[i]["marked"], O.emr_embed(Ie, mo.b, pay, nb, k2)), i
+            else:
+                orig = wl.originals[i].cpu().numpy()
+                _, mo = O.emr_encrypt(orig, k1)
+                assert np.array_equal(_bits(got[i]["payload"], nb), _bits(pay, nb)), i
+                assert np.array_equal(got[i]["recovered"], O.emr_recover(I, mo.b, k1)), i
+
+
 def test_request_larger_than_pool_is_rejected(S, workload):
     wl = workload
     big = int(np.argmax(wl.footprint()))
