@@ -69,6 +69,7 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=5000, help="serving-loop requests (0: skip)")
     ap.add_argument("--single-reps", type=int, default=200, help="runs of the one-image latency leg (0: skip)")
     ap.add_argument("--metrics-reps", type=int, default=3, help="timed runs of the batch metrics leg (0: skip)")
+    ap.add_argument("--tile-b-reps", type=int, default=3, help="timed runs of the per-tile b leg (0: skip)")
     ap.add_argument("--large-sides", default="8192,16384", help="single large images timed stage by stage ('' to skip)")
     ap.add_argument("--lmr-images", type=int, default=2000, help="LMR batch of 512x512 images (0: skip)")
     ap.add_argument("--keystream-images", type=int, default=2000,
@@ -717,6 +718,42 @@ def main():
         log(f"[bench] metrics: {metrics['ms']} ms, Table EMR_results {metrics['emr_results']}, "
             f"analysis {metrics['analysis_avg']}")
 
+    # ---- per-tile b (first step towards the conclusion's dynamic b) ----
+    # rdhei_tile_b over the whole batch: the capacity one b per 64x64 tile
+    # would trace against the method's one b per image, and the kernel's time
+    # (reads 1 B/px).
+    tile_b = None
+    if args.tile_b_reps > 0 and S % 64 == 0:
+        import ctypes
+        lib = rdhei.load_library()
+        tjobs = rdhei.make_metric_jobs([(imgs[i], None) for i in range(B)])
+        ntiles = B * (S // 64) ** 2
+        tb = torch.empty(ntiles, dtype=torch.uint8, device=dev)
+        tcap = torch.empty(B, dtype=torch.int64, device=dev)
+
+        def run_tile_b():
+            rc = lib.rdhei_tile_b(ctx.h, tjobs, B, ctypes.c_void_p(tb.data_ptr()), ctypes.c_void_p(tcap.data_ptr()),
+                                  ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+            assert rc == 0, rc
+        run_tile_b()
+        torch.cuda.synchronize()
+        a, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.tile_b_reps):
+            run_tile_b()
+        b_.record()
+        torch.cuda.synchronize()
+        t_ms = a.elapsed_time(b_) / args.tile_b_reps
+        tcaps = tcap.cpu().numpy()
+        hist = np.bincount(tb.cpu().numpy(), minlength=8)[2:8]
+        tile_b = {"der_bpp_global_b": round(float(caps.sum()) / (B * MN), 4),
+                  "der_bpp_tile_b": round(float(tcaps.sum()) / (B * MN), 4),
+                  "images_gaining": int((tcaps > caps).sum()), "tile_b_hist_2_7": [int(x) for x in hist],
+                  "ms": round(t_ms, 4), "read_GBps": round(B * MN / (t_ms * 1e-3) / 1e9, 1)}
+        log(f"[bench] per-tile b: DER {tile_b['der_bpp_tile_b']} bpp against {tile_b['der_bpp_global_b']} with one b "
+            f"per image; {t_ms:.3f} ms ({tile_b['read_GBps']} GB/s)")
+        del tb, tcap
+
     # ---- CPU oracle on a bounded sample of the same workload ----
     # Full round trips of the oracle, single thread, on images spread over the
     # batch with their own keys and payloads; only the oracle calls are timed.
@@ -836,6 +873,7 @@ def main():
         "large": large,
         "single": single,
         "metrics": metrics,
+        "tile_b": tile_b,
         "lmr": lmr,
         "keystream": keystream,
     }

@@ -299,6 +299,26 @@ typedef struct {
 int rdhei_metrics(rdhei_ctx *ctx, const rdhei_metric_job *jobs, int32_t njobs, int32_t flags, double *d_out,
                   void *stream);
 
+/* ---- Per-tile b (the conclusion's dynamic b, first step) -----------------------
+ * The conclusion suggests a b that varies over the image.  This call measures
+ * what one b per 64x64 tile would trace (a reading of this library; it hides
+ * nothing).  For tile t of an image: Z_b(t) = pixels of the tile, its first
+ * column excepted, whose b most significant bits equal those of their left
+ * neighbour (the location-map glide of Sec. III-A restarted at the tile's first
+ * column), b = 2..7; b_t = the first b reaching the largest b * Z_b(t), as the
+ * global b is chosen; the image's capacity = sum over tiles of b_t * Z_{b_t}(t)
+ * bits.
+ *   jobs        image in .a (.b unused), height and width positive multiples of
+ *               64, .a 16-byte aligned
+ *   d_tile_b    device, one byte per tile of every image: images in job order,
+ *               tiles row-major
+ *   d_capacity  device, one int64 per image
+ * Asynchronous on `stream`.  Errors (nothing launched): RDHEI_EINVAL for NULL
+ * pointers, njobs < 1, a side that is not a positive multiple of 64, an
+ * unaligned image or more than 2^31 tiles. */
+int rdhei_tile_b(rdhei_ctx *ctx, const rdhei_metric_job *jobs, int32_t njobs, uint8_t *d_tile_b, int64_t *d_capacity,
+                 void *stream);
+
 /* ---- Diagnostics ---------------------------------------------------------- */
 const char *rdhei_strerror(int code);
 /* Text of the last HIP error seen by this thread (empty if none). */

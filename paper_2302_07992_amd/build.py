@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librdhei.so")
-SOURCES = ["api.hip", "k_tiles.hip", "k_hide.hip", "k_generic.hip", "k_lmr.hip", "k_metrics.hip", "lmr_coder.cpp"]
+SOURCES = ["api.hip", "k_tiles.hip", "k_hide.hip", "k_generic.hip", "k_lmr.hip", "k_metrics.hip", "k_dynb.hip", "lmr_coder.cpp"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",

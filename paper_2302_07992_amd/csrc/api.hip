@@ -364,7 +364,7 @@ struct rdhei_ctx {
     int keystream = kKsPhilox;
     std::map<std::string, int> tuned;   // autotuned workgroup counts by op/stage/size class
     int max_grid = 0;
-    DevBuf ws, jobs, scratch, batch_tables, lmr_dev, metrics;
+    DevBuf ws, jobs, scratch, batch_tables, lmr_dev, metrics, tileb;
     HostBuf lmr_host;
     PinnedRing ring;
     std::vector<uint8_t> h_a, h_b, h_c;
@@ -998,6 +998,7 @@ void rdhei_ctx_destroy(rdhei_ctx *ctx) {
     ctx->batch_tables.release();
     ctx->lmr_dev.release();
     ctx->metrics.release();
+    ctx->tileb.release();
     ctx->lmr_host.release();
     ctx->ring.release_all();
     delete ctx;
@@ -1153,6 +1154,43 @@ int rdhei_metrics(rdhei_ctx *ctx, const rdhei_metric_job *jobs, int32_t njobs, i
     launch_metrics(reinterpret_cast<const MetricJob *>(ctx->metrics.p), njobs,
                    reinterpret_cast<MetricAcc *>(ctx->metrics.p + tb), (uint32_t)units, (uint32_t)tiles,
                    with_ssim ? 1 : 0, d_out, st);
+    HIPCHK(hipGetLastError());
+    return RDHEI_OK;
+}
+
+int rdhei_tile_b(rdhei_ctx *ctx, const rdhei_metric_job *jobs, int32_t njobs, uint8_t *d_tile_b, int64_t *d_capacity,
+                 void *stream) {
+    if (!ctx || !jobs || njobs < 1 || !d_tile_b || !d_capacity) return RDHEI_EINVAL;
+    std::vector<TileBJob> hj((size_t)njobs);
+    uint64_t tiles = 0;
+    for (int i = 0; i < njobs; ++i) {
+        const rdhei_metric_job &q = jobs[i];
+        if (!q.a || !aligned16(q.a) || q.height < kTile || q.width < kTile || q.height % kTile || q.width % kTile)
+            return RDHEI_EINVAL;
+        TileBJob &t = hj[(size_t)i];
+        t.img = q.a;
+        t.M = q.height;
+        t.N = q.width;
+        t.tile_first = (uint32_t)tiles;
+        t.pad = 0;
+        tiles += (uint64_t)(q.height / kTile) * (uint64_t)(q.width / kTile);
+        if (tiles > (1ull << 31)) return RDHEI_EINVAL;   // tile indices and the grid stride stay below 2^32
+    }
+    int rc = set_device(ctx->device);
+    if (rc) return rc;
+    const size_t tb = (size_t)njobs * sizeof(TileBJob);
+    rc = ctx->tileb.need(tb);
+    if (rc) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    uint8_t *host = nullptr;
+    int slot = 0;
+    rc = ctx->ring.acquire(tb, &host, &slot);
+    if (rc) return rc;
+    memcpy(host, hj.data(), tb);
+    HIPCHK(hipMemcpyAsync(ctx->tileb.p, host, tb, hipMemcpyHostToDevice, st));
+    HIPCHK(hipEventRecord(ctx->ring.done[slot], st));
+    ctx->ring.used[slot] = true;
+    launch_tile_b(reinterpret_cast<const TileBJob *>(ctx->tileb.p), njobs, (uint32_t)tiles, d_tile_b, d_capacity, st);
     HIPCHK(hipGetLastError());
     return RDHEI_OK;
 }

@@ -93,6 +93,15 @@ __host__ __device__ inline uint64_t stat_z_offset(const Job &J) {
     return J.ws_stats + (uint64_t)stat_slots(J) * kStatWords * 4;
 }
 
+// Per-tile b of one image (k_dynb.hip): 64x64 tiles numbered from tile_first.
+struct TileBJob {
+    const uint8_t *img;
+    int32_t M, N;
+    uint32_t tile_first;
+    uint32_t pad;
+};
+void launch_tile_b(const TileBJob *jobs, int njobs, uint32_t tiles, uint8_t *tile_b, int64_t *cap, hipStream_t st);
+
 // ---- launchers (defined in the .hip files) ---------------------------------
 struct Launch {
     const Job *jobs;          // device job table

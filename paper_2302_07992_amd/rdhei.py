@@ -32,7 +32,7 @@ EXPORTS = [
     "rdhei_workspace_size", "rdhei_run_batch", "rdhei_plan_create", "rdhei_plan_run", "rdhei_plan_destroy", "rdhei_plan_set_grid",
     "rdhei_plan_stage_count", "rdhei_plan_stage_name", "rdhei_plan_run_stage",
     "rdhei_plan_autotune", "rdhei_plan_stage_grid",
-    "rdhei_lmr_batch", "rdhei_lmr_compress", "rdhei_lmr_decompress", "rdhei_metrics",
+    "rdhei_lmr_batch", "rdhei_lmr_compress", "rdhei_lmr_decompress", "rdhei_metrics", "rdhei_tile_b",
     "rdhei_strerror", "rdhei_last_error", "rdhei_version",
 ]
 
@@ -124,6 +124,7 @@ def load_library(path: str = LIB_PATH):
     lib.rdhei_lmr_compress.argtypes = [vp, vp, i32, i32, vp, i64, ctypes.POINTER(i64)]
     lib.rdhei_lmr_decompress.argtypes = [vp, i64, i32, i32, vp, vp]
     lib.rdhei_metrics.argtypes = [vp, ctypes.POINTER(MetricJobStruct), i32, i32, vp, vp]
+    lib.rdhei_tile_b.argtypes = [vp, ctypes.POINTER(MetricJobStruct), i32, vp, vp, vp]
     lib.rdhei_strerror.argtypes = [ctypes.c_int]
     lib.rdhei_strerror.restype = ctypes.c_char_p
     lib.rdhei_last_error.argtypes = []
@@ -262,6 +263,21 @@ class Context:
         _check(self.lib.rdhei_metrics(self.h, jobs, n, METRIC_SSIM if ssim else 0, ctypes.c_void_p(out.data_ptr()),
                                       _stream(stream)), "rdhei_metrics")
         return out
+
+    def tile_b(self, images, stream=None):
+        """Per-tile b of each image (contiguous 2-D uint8 device tensors, sides
+        multiples of 64; rdhei_tile_b): (tile_b, capacity) device tensors, one
+        byte per 64x64 tile of every image in order (row-major) and one int64
+        capacity in bits per image.  Asynchronous."""
+        jobs = make_metric_jobs([(x, None) for x in images])
+        n = len(jobs)
+        ntiles = sum((int(x.shape[0]) // 64) * (int(x.shape[1]) // 64) for x in images)
+        dev = images[0].device
+        tb = torch.empty(max(ntiles, 1), dtype=torch.uint8, device=dev)
+        cap = torch.empty(n, dtype=torch.int64, device=dev)
+        _check(self.lib.rdhei_tile_b(self.h, jobs, n, ctypes.c_void_p(tb.data_ptr()), ctypes.c_void_p(cap.data_ptr()),
+                                     _stream(stream)), "rdhei_tile_b")
+        return tb[:ntiles], cap
 
     def lmr_batch(self, op: int, jobs, threads: int = 0, stream=None) -> dict:
         """One LMR role over a job array (method LMR); returns the seconds spent
