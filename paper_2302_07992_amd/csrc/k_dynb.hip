@@ -24,26 +24,16 @@ __global__ __launch_bounds__(kThreads) void k_tile_b(const TileBJob *__restrict_
     __shared__ uint32_t part[kW][8];
     const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = tid >> 2, g = tid & 3;
-    auto job_of = [&](uint32_t t) {
+    for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         int lo = 0, hi = njobs - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (jobs[mid].tile_first <= t) lo = mid; else hi = mid - 1;
         }
-        return lo;
-    };
-    // this thread's 16 pixels of tile t
-    auto fetch = [&](uint32_t t) {
-        const TileBJob &J = jobs[job_of(t)];
+        const TileBJob &J = jobs[lo];
         const uint32_t lt = t - J.tile_first, tpr = (uint32_t)J.N / kTile;
         const uint32_t ty = lt / tpr, tx = lt % tpr;
-        return gload<uint4>(J.img + (uint64_t)(ty * kTile + r) * (uint64_t)J.N + tx * kTile + 16 * g);
-    };
-    uint4 nxt = blockIdx.x < tiles ? fetch(blockIdx.x) : make_uint4(0, 0, 0, 0);
-    for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
-        const uint4 v = nxt;
-        if (t + gridDim.x < tiles) nxt = fetch(t + gridDim.x);   // the next tile's pixels, loaded a tile ahead
-        const int lo = job_of(t);
+        const uint4 v = gload<uint4>(J.img + (uint64_t)(ty * kTile + r) * (uint64_t)J.N + tx * kTile + 16 * g);
         const uint32_t w[4] = {v.x, v.y, v.z, v.w};
         // byte 15 of the segment to the left in the same tile row (lane - 1 of the quad)
         const uint32_t from_left = qperm<0x90>(v.w >> 24);
