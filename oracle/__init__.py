@@ -2,9 +2,9 @@
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  The product library never loads it.
-The arithmetic lives in ``rdhei_oracle.c`` (plain C, single-threaded) and in
-``lmr_coder.py`` (the bi-level map coder); this module only builds the C file
-with gcc and marshals numpy arrays.  ``metrics.py`` holds the Sec. IV image
+The arithmetic lives in ``rdhei_oracle.c`` (plain C, single-threaded; it also
+holds the bi-level map coder of the LMR variant); ``oracle.py`` only builds
+the C file with gcc and marshals numpy arrays.  ``metrics.py`` holds the Sec. IV image
 metrics in plain numpy (``from oracle import metrics``).
 """
 from .oracle import *  # noqa: F401,F403

@@ -40,7 +40,7 @@ def _load():
     i64p = ctypes.POINTER(ctypes.c_int64)
     u32p = ctypes.POINTER(ctypes.c_uint32)
     lib.or_philox4x32_10.argtypes = [u32p, u32p, u32p]
-    lib.or_keystream.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, u8p]
+    lib.or_keystream.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, u8p]
     lib.or_chacha20_block.argtypes = [u32p, ctypes.c_uint32, u32p, u8p]
     lib.or_set_keystream.argtypes = [ctypes.c_int]
     lib.or_location_map.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, u8p]
@@ -51,31 +51,34 @@ def _load():
     lib.or_max_level.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.or_max_level.restype = ctypes.c_int
     lib.or_rotate.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, u8p, ctypes.c_int, ctypes.c_int]
-    lib.or_emr_encrypt.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, u8p, ctypes.c_void_p]
-    lib.or_emr_embed.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, u8p, ctypes.c_int64, ctypes.c_uint64]
+    lib.or_emr_encrypt.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64, u8p,
+                                   ctypes.c_void_p]
+    lib.or_emr_embed.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, u8p, ctypes.c_int64, ctypes.c_uint64,
+                                 ctypes.c_uint64]
     lib.or_emr_embed.restype = ctypes.c_int64
-    lib.or_emr_extract.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, u8p, ctypes.c_int64, ctypes.c_uint64]
+    lib.or_emr_extract.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, u8p, ctypes.c_int64,
+                                   ctypes.c_uint64, ctypes.c_uint64]
     lib.or_emr_extract.restype = ctypes.c_int64
-    lib.or_emr_recover.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.c_uint64, u8p]
+    lib.or_emr_recover.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, u8p]
     lib.or_lmr_rotated_maps.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.c_int,
-                                        ctypes.c_uint64, u8p, u8p]
+                                        ctypes.c_uint64, ctypes.c_uint64, u8p, u8p]
     lib.or_lmr_encrypt.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.c_uint64,
-                                   u8p, ctypes.c_int64, u8p]
+                                   ctypes.c_uint64, u8p, ctypes.c_int64, u8p]
     lib.or_lmr_embed.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, u8p, u8p,
-                                 ctypes.c_int64, ctypes.c_uint64]
+                                 ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64]
     lib.or_lmr_embed.restype = ctypes.c_int64
     lib.or_lmr_extract.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, u8p, u8p,
-                                   ctypes.c_int64, ctypes.c_uint64]
+                                   ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64]
     lib.or_lmr_extract.restype = ctypes.c_int64
     lib.or_lmr_recover.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.c_int,
-                                   ctypes.c_uint64, u8p, u8p, u8p]
+                                   ctypes.c_uint64, ctypes.c_uint64, u8p, u8p, u8p]
     lib.or_plane_encode.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, u8p, ctypes.c_int64]
     lib.or_plane_encode.restype = ctypes.c_int64
     lib.or_plane_decode.argtypes = [u8p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, u8p]
     lib.or_lmr_compress.argtypes = [u8p, u8p, ctypes.c_int32, ctypes.c_int32, u8p, ctypes.c_int64]
     lib.or_lmr_compress.restype = ctypes.c_int64
     lib.or_lmr_decompress.argtypes = [u8p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, u8p, u8p]
-    lib.or_lmr_encode.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32, u8p,
+    lib.or_lmr_encode.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32, u8p,
                                   ctypes.c_void_p, u8p, ctypes.POINTER(ctypes.c_int64)]
     _lib = lib
     return lib
@@ -145,9 +148,10 @@ def keystream_family(family: int):
         lib.or_set_keystream(KEYSTREAM_PHILOX)
 
 
-def keystream(key: int, domain: int, first: int, count: int) -> np.ndarray:
+def keystream(key: int, domain: int, first: int, count: int, nonce: int = 0) -> np.ndarray:
+    """Bytes [first, first + count) of the stream (key, nonce, domain)."""
     out = np.zeros(max(count, 1), dtype=np.uint8)
-    _load().or_keystream(key, domain, first, count, _u8(out))
+    _load().or_keystream(key, nonce, domain, first, count, _u8(out))
     return out[:count]
 
 
@@ -183,15 +187,15 @@ def rotate(X, s, min_level: int = 1, inverse: bool = False) -> np.ndarray:
     return X
 
 
-def image_keystream(k1: int, M: int, N: int) -> np.ndarray:
-    return keystream(k1, 1, 0, M * N).reshape(M, N)
+def image_keystream(k1: int, M: int, N: int, nonce: int = 0) -> np.ndarray:
+    return keystream(k1, 1, 0, M * N, nonce).reshape(M, N)
 
 
-def emr_encrypt(I, k1: int):
+def emr_encrypt(I, k1: int, nonce: int = 0):
     I = _img(I)
     Ie = np.zeros_like(I)
     m = _OrMeta()
-    _load().or_emr_encrypt(_u8(I), I.shape[0], I.shape[1], k1, _u8(Ie), ctypes.byref(m))
+    _load().or_emr_encrypt(_u8(I), I.shape[0], I.shape[1], k1, nonce, _u8(Ie), ctypes.byref(m))
     return Ie, OracleMeta(m.b, m.min_level, m.max_level, m.redundant, m.capacity_bits)
 
 
@@ -199,73 +203,75 @@ def _msg_buf(nbits: int) -> np.ndarray:
     return np.zeros(max((nbits + 7) // 8, 1), dtype=np.uint8)
 
 
-def emr_embed(Ie, b: int, msg: np.ndarray, nbits: int, k2: int) -> np.ndarray:
+def emr_embed(Ie, b: int, msg: np.ndarray, nbits: int, k2: int, nonce: int = 0) -> np.ndarray:
     X = _img(Ie).copy()
     msg = np.ascontiguousarray(msg, dtype=np.uint8)
     if msg.size == 0:
         msg = _msg_buf(0)
-    r = _load().or_emr_embed(_u8(X), X.shape[0], X.shape[1], b, _u8(msg), nbits, k2)
+    r = _load().or_emr_embed(_u8(X), X.shape[0], X.shape[1], b, _u8(msg), nbits, k2, nonce)
     if r < 0:
         raise ValueError("message longer than capacity")
     return X
 
 
-def emr_extract(Ie, b: int, nbits: int, k2: int) -> np.ndarray:
+def emr_extract(Ie, b: int, nbits: int, k2: int, nonce: int = 0) -> np.ndarray:
     X = _img(Ie)
     out = _msg_buf(nbits)
-    _load().or_emr_extract(_u8(X), X.shape[0], X.shape[1], b, _u8(out), nbits, k2)
+    _load().or_emr_extract(_u8(X), X.shape[0], X.shape[1], b, _u8(out), nbits, k2, nonce)
     return out[:(nbits + 7) // 8]
 
 
-def emr_recover(Ie, b: int, k1: int) -> np.ndarray:
+def emr_recover(Ie, b: int, k1: int, nonce: int = 0) -> np.ndarray:
     X = _img(Ie)
     out = np.zeros_like(X)
-    _load().or_emr_recover(_u8(X), X.shape[0], X.shape[1], b, k1, _u8(out))
+    _load().or_emr_recover(_u8(X), X.shape[0], X.shape[1], b, k1, nonce, _u8(out))
     return out
 
 
-def lmr_rotated_maps(I, b: int, min_level: int, k1: int):
+def lmr_rotated_maps(I, b: int, min_level: int, k1: int, nonce: int = 0):
     I = _img(I)
     l_rot = np.zeros_like(I)
     eta_rot = np.zeros_like(I)
-    _load().or_lmr_rotated_maps(_u8(I), I.shape[0], I.shape[1], b, min_level, k1, _u8(l_rot), _u8(eta_rot))
+    _load().or_lmr_rotated_maps(_u8(I), I.shape[0], I.shape[1], b, min_level, k1, nonce, _u8(l_rot),
+                                _u8(eta_rot))
     return l_rot, eta_rot
 
 
-def lmr_encrypt(I, min_level: int, k1: int, stream: np.ndarray, stream_bits: int) -> np.ndarray:
+def lmr_encrypt(I, min_level: int, k1: int, stream: np.ndarray, stream_bits: int, nonce: int = 0) -> np.ndarray:
     I = _img(I)
     stream = np.ascontiguousarray(stream, dtype=np.uint8)
     if stream.size == 0:
         stream = _msg_buf(0)
     Ie = np.zeros_like(I)
-    _load().or_lmr_encrypt(_u8(I), I.shape[0], I.shape[1], min_level, k1, _u8(stream), stream_bits, _u8(Ie))
+    _load().or_lmr_encrypt(_u8(I), I.shape[0], I.shape[1], min_level, k1, nonce, _u8(stream), stream_bits,
+                           _u8(Ie))
     return Ie
 
 
-def lmr_embed(Ie, b: int, l_rot, msg, nbits: int, k2: int) -> np.ndarray:
+def lmr_embed(Ie, b: int, l_rot, msg, nbits: int, k2: int, nonce: int = 0) -> np.ndarray:
     X = _img(Ie).copy()
     l_rot = _img(l_rot)
     msg = np.ascontiguousarray(msg, dtype=np.uint8)
     if msg.size == 0:
         msg = _msg_buf(0)
-    r = _load().or_lmr_embed(_u8(X), X.shape[0], X.shape[1], b, _u8(l_rot), _u8(msg), nbits, k2)
+    r = _load().or_lmr_embed(_u8(X), X.shape[0], X.shape[1], b, _u8(l_rot), _u8(msg), nbits, k2, nonce)
     if r < 0:
         raise ValueError("message longer than capacity")
     return X
 
 
-def lmr_extract(Ie, b: int, l_rot, nbits: int, k2: int) -> np.ndarray:
+def lmr_extract(Ie, b: int, l_rot, nbits: int, k2: int, nonce: int = 0) -> np.ndarray:
     X = _img(Ie)
     l_rot = _img(l_rot)
     out = _msg_buf(nbits)
-    _load().or_lmr_extract(_u8(X), X.shape[0], X.shape[1], b, _u8(l_rot), _u8(out), nbits, k2)
+    _load().or_lmr_extract(_u8(X), X.shape[0], X.shape[1], b, _u8(l_rot), _u8(out), nbits, k2, nonce)
     return out[:(nbits + 7) // 8]
 
 
-def lmr_recover(Ie, b: int, min_level: int, k1: int, l_rot, eta_rot) -> np.ndarray:
+def lmr_recover(Ie, b: int, min_level: int, k1: int, l_rot, eta_rot, nonce: int = 0) -> np.ndarray:
     X = _img(Ie)
     out = np.zeros_like(X)
-    _load().or_lmr_recover(_u8(X), X.shape[0], X.shape[1], b, min_level, k1,
+    _load().or_lmr_recover(_u8(X), X.shape[0], X.shape[1], b, min_level, k1, nonce,
                            _u8(_img(l_rot)), _u8(_img(eta_rot)), _u8(out))
     return out
 
@@ -306,7 +312,7 @@ def lmr_decompress(stream, M: int, N: int):
     return eta, l
 
 
-def lmr_encode(I, k1: int, min_level: int = 4):
+def lmr_encode(I, k1: int, min_level: int = 4, nonce: int = 0):
     """Full LMR encoding with rotation blocks 2^min_level..2^n: (I_e, meta,
     stream bytes) or (None, meta, None) for a bad case."""
     I = _img(I)
@@ -315,7 +321,8 @@ def lmr_encode(I, k1: int, min_level: int = 4):
     m = _OrMeta()
     stream = np.zeros(M * N // 8 + 16, dtype=np.uint8)
     bits = ctypes.c_int64()
-    rc = _load().or_lmr_encode(_u8(I), M, N, k1, min_level, _u8(Ie), ctypes.byref(m), _u8(stream), ctypes.byref(bits))
+    rc = _load().or_lmr_encode(_u8(I), M, N, k1, nonce, min_level, _u8(Ie), ctypes.byref(m), _u8(stream),
+                               ctypes.byref(bits))
     meta = OracleMeta(m.b, m.min_level, m.max_level, m.redundant, m.capacity_bits)
     if rc != 0:
         return None, meta, None

@@ -13,16 +13,18 @@
  *
  * Conventions the paper leaves open are fixed as follows (each is a reading of
  * a silent or ambiguous passage; the product follows the same readings):
- *   - keystream: Philox4x32-10 (Salmon et al., SC'11); byte idx of a stream is
- *     little-endian byte (idx & 15) of the block with counter
- *     (idx>>4 low word, idx>>4 high word, domain, 0) and key (K low, K high).
- *     Domain 1 = image keystream s (key K1), domain 2 = message keystream
- *     (key K2).  The paper asks only for a secure stream cipher (Sec. III-A,
- *     "Secret key generation").  The second family, selected with
- *     or_set_keystream(1), is ChaCha20: byte idx is byte idx%64 of the
- *     ChaCha20 block (IETF layout) with key (K as 8 little-endian bytes, 24
- *     zero bytes), counter (idx/64) mod 2^32 and nonce words (domain,
- *     idx/2^38, 0).
+ *   - keystream: Philox4x32-10 (Salmon et al., SC'11); byte idx of the stream
+ *     (key, nonce, domain) is little-endian byte (idx & 15) of the block with
+ *     counter (idx>>4, nonce high word, domain, nonce low word) and key
+ *     (K low, K high), for idx < 2^36.  Domain 1 = image keystream s (key K1),
+ *     domain 2 = message keystream (key K2); the nonce is a per-image value
+ *     the content owner picks and the side information carries, so that two
+ *     images under one key never share a stream.  The paper asks only for a
+ *     secure stream cipher (Sec. III-A, "Secret key generation").  The second
+ *     family, selected with or_set_keystream(1), is ChaCha20: byte idx is byte
+ *     idx%64 of the ChaCha20 block (IETF layout) with key (K as 8
+ *     little-endian bytes, 24 zero bytes), counter idx/64 and nonce words
+ *     (domain, nonce low word, nonce high word), for idx < 2^38.
  *   - a pixel is redundant (label 0) when its b MSBs equal those of the
  *     tracker (the text of Sec. III-A wins over the indicator printed in the
  *     gliding equation).
@@ -107,9 +109,11 @@ static int or_family = 0;
 
 void or_set_keystream(int family) { or_family = family; }
 
-/* Bytes [first, first+count) of the stream (key, domain). */
-void or_keystream(uint64_t key, uint32_t domain, uint64_t first, uint64_t count, uint8_t *out)
+/* Bytes [first, first+count) of the stream (key, nonce, domain).  Streams are
+ * at most 2^36 bytes long (Philox's block index fills one counter word). */
+void or_keystream(uint64_t key, uint64_t nonce, uint32_t domain, uint64_t first, uint64_t count, uint8_t *out)
 {
+    if (first + count > ((uint64_t)1 << 36)) abort();
     uint32_t k[2] = {(uint32_t)key, (uint32_t)(key >> 32)};
     if (or_family == 1) {
         uint32_t ck[8] = {k[0], k[1], 0u, 0u, 0u, 0u, 0u, 0u};
@@ -119,8 +123,8 @@ void or_keystream(uint64_t key, uint32_t domain, uint64_t first, uint64_t count,
             uint64_t idx = first + t;
             uint64_t c = idx >> 6;
             if (c != have) {
-                uint32_t nonce[3] = {domain, (uint32_t)(c >> 32), 0u};
-                or_chacha20_block(ck, (uint32_t)c, nonce, block);
+                uint32_t nw[3] = {domain, (uint32_t)nonce, (uint32_t)(nonce >> 32)};
+                or_chacha20_block(ck, (uint32_t)c, nw, block);
                 have = c;
             }
             out[t] = block[idx & 63];
@@ -130,7 +134,7 @@ void or_keystream(uint64_t key, uint32_t domain, uint64_t first, uint64_t count,
     for (uint64_t t = 0; t < count; ++t) {
         uint64_t idx = first + t;
         uint64_t blk = idx >> 4;
-        uint32_t ctr[4] = {(uint32_t)blk, (uint32_t)(blk >> 32), domain, 0u};
+        uint32_t ctr[4] = {(uint32_t)blk, (uint32_t)(nonce >> 32), domain, (uint32_t)nonce};
         uint32_t w[4];
         or_philox4x32_10(ctr, k, w);
         unsigned within = (unsigned)(idx & 15);
@@ -271,7 +275,8 @@ typedef struct or_meta {
 /* Encoding phase (Sec. III-A): location map for the optimal b in [2,7],
  * rotation of I and l with K1's keystream, XOR encryption, and the rotated
  * map written into the LSB plane. */
-void or_emr_encrypt(const uint8_t *I, int32_t M, int32_t N, uint64_t k1, uint8_t *Ie, or_meta *meta)
+void or_emr_encrypt(const uint8_t *I, int32_t M, int32_t N, uint64_t k1, uint64_t nonce, uint8_t *Ie,
+                    or_meta *meta)
 {
     size_t MN = (size_t)M * (size_t)N;
     int64_t Z[6];
@@ -281,7 +286,7 @@ void or_emr_encrypt(const uint8_t *I, int32_t M, int32_t N, uint64_t k1, uint8_t
     or_location_map(I, M, N, b, l);
 
     uint8_t *s = (uint8_t *)malloc(MN + 1);
-    or_keystream(k1, 1, 0, MN, s);
+    or_keystream(k1, nonce, 1, 0, MN, s);
 
     uint8_t *Irot = (uint8_t *)malloc(MN + 1);
     memcpy(Irot, I, MN);
@@ -314,7 +319,7 @@ static void put_bit(uint8_t *bytes, int64_t t, int v)
  * rotated location map (1 byte per pixel).  Returns the number of bits
  * written, or -1 if the message does not fit. */
 int64_t or_hide(uint8_t *X, int32_t M, int32_t N, const uint8_t *lmap, int top, int nrep,
-                const uint8_t *msg, int64_t nbits, uint64_t k2)
+                const uint8_t *msg, int64_t nbits, uint64_t k2, uint64_t nonce)
 {
     size_t MN = (size_t)M * (size_t)N;
     int64_t cap = 0;
@@ -322,7 +327,7 @@ int64_t or_hide(uint8_t *X, int32_t M, int32_t N, const uint8_t *lmap, int top, 
     if (nbits > cap) return -1;
     int64_t nbytes = (nbits + 7) / 8;
     uint8_t *ks = (uint8_t *)malloc((size_t)nbytes + 1);
-    or_keystream(k2, 2, 0, (uint64_t)nbytes, ks);
+    or_keystream(k2, nonce, 2, 0, (uint64_t)nbytes, ks);
     int64_t t = 0;
     for (size_t p = 0; p < MN && t < nbits; ++p) {
         if (lmap[p] != 0) continue;
@@ -339,12 +344,12 @@ int64_t or_hide(uint8_t *X, int32_t M, int32_t N, const uint8_t *lmap, int top, 
 /* Extraction (Sec. III-A decoding with K2): concatenate the replaceable bits
  * of the pixels marked 0, raster order, and decrypt with K2's stream. */
 int64_t or_reveal(const uint8_t *X, int32_t M, int32_t N, const uint8_t *lmap, int top, int nrep,
-                  uint8_t *msg, int64_t nbits, uint64_t k2)
+                  uint8_t *msg, int64_t nbits, uint64_t k2, uint64_t nonce)
 {
     size_t MN = (size_t)M * (size_t)N;
     int64_t nbytes = (nbits + 7) / 8;
     uint8_t *ks = (uint8_t *)malloc((size_t)nbytes + 1);
-    or_keystream(k2, 2, 0, (uint64_t)nbytes, ks);
+    or_keystream(k2, nonce, 2, 0, (uint64_t)nbytes, ks);
     memset(msg, 0, (size_t)nbytes);
     int64_t t = 0;
     for (size_t p = 0; p < MN && t < nbits; ++p) {
@@ -359,22 +364,24 @@ int64_t or_reveal(const uint8_t *X, int32_t M, int32_t N, const uint8_t *lmap, i
 }
 
 /* EMR data hiding: the rotated map is the LSB plane of I_e; b MSBs replaced. */
-int64_t or_emr_embed(uint8_t *Ie, int32_t M, int32_t N, int b, const uint8_t *msg, int64_t nbits, uint64_t k2)
+int64_t or_emr_embed(uint8_t *Ie, int32_t M, int32_t N, int b, const uint8_t *msg, int64_t nbits, uint64_t k2,
+                     uint64_t nonce)
 {
     size_t MN = (size_t)M * (size_t)N;
     uint8_t *l = (uint8_t *)malloc(MN + 1);
     for (size_t p = 0; p < MN; ++p) l[p] = Ie[p] & 1;
-    int64_t r = or_hide(Ie, M, N, l, 7, b, msg, nbits, k2);
+    int64_t r = or_hide(Ie, M, N, l, 7, b, msg, nbits, k2, nonce);
     free(l);
     return r;
 }
 
-int64_t or_emr_extract(const uint8_t *Ie, int32_t M, int32_t N, int b, uint8_t *msg, int64_t nbits, uint64_t k2)
+int64_t or_emr_extract(const uint8_t *Ie, int32_t M, int32_t N, int b, uint8_t *msg, int64_t nbits, uint64_t k2,
+                       uint64_t nonce)
 {
     size_t MN = (size_t)M * (size_t)N;
     uint8_t *l = (uint8_t *)malloc(MN + 1);
     for (size_t p = 0; p < MN; ++p) l[p] = Ie[p] & 1;
-    int64_t r = or_reveal(Ie, M, N, l, 7, b, msg, nbits, k2);
+    int64_t r = or_reveal(Ie, M, N, l, 7, b, msg, nbits, k2, nonce);
     free(l);
     return r;
 }
@@ -396,12 +403,12 @@ static void recovery_glide(uint8_t *D, const uint8_t *l, int32_t M, int32_t N, u
 
 /* EMR image recovery: l from the LSBs, XOR decryption, de-rotation of the
  * decrypted image and the map in descending level order, then the glide. */
-void or_emr_recover(const uint8_t *Ie, int32_t M, int32_t N, int b, uint64_t k1, uint8_t *out)
+void or_emr_recover(const uint8_t *Ie, int32_t M, int32_t N, int b, uint64_t k1, uint64_t nonce, uint8_t *out)
 {
     size_t MN = (size_t)M * (size_t)N;
     uint8_t *s = (uint8_t *)malloc(MN + 1);
     uint8_t *l = (uint8_t *)malloc(MN + 1);
-    or_keystream(k1, 1, 0, MN, s);
+    or_keystream(k1, nonce, 1, 0, MN, s);
     for (size_t p = 0; p < MN; ++p) {
         l[p] = Ie[p] & 1;
         out[p] = (uint8_t)(Ie[p] ^ s[p]);
@@ -420,12 +427,12 @@ void or_emr_recover(const uint8_t *Ie, int32_t M, int32_t N, int b, uint64_t k1,
 /* Maps for LMR with a given b (b in [2,8]) and min_level: the rotated
  * location map and the rotated first-MSB map eta = (I AND 128) mod 127, one
  * byte per pixel each. */
-void or_lmr_rotated_maps(const uint8_t *I, int32_t M, int32_t N, int b, int min_level, uint64_t k1,
+void or_lmr_rotated_maps(const uint8_t *I, int32_t M, int32_t N, int b, int min_level, uint64_t k1, uint64_t nonce,
                          uint8_t *l_rot, uint8_t *eta_rot)
 {
     size_t MN = (size_t)M * (size_t)N;
     uint8_t *s = (uint8_t *)malloc(MN + 1);
-    or_keystream(k1, 1, 0, MN, s);
+    or_keystream(k1, nonce, 1, 0, MN, s);
     or_location_map(I, M, N, b, l_rot);
     for (size_t p = 0; p < MN; ++p) eta_rot[p] = (uint8_t)((I[p] & 128) % 127);
     or_rotate(l_rot, M, N, s, min_level, 0);
@@ -436,12 +443,12 @@ void or_lmr_rotated_maps(const uint8_t *I, int32_t M, int32_t N, int b, int min_
 /* LMR encryption with a given stream for the first-MSB plane: rotate I,
  * XOR with s, then bit 7 of pixel p (raster order) := stream bit p for
  * p < stream_bits. */
-void or_lmr_encrypt(const uint8_t *I, int32_t M, int32_t N, int min_level, uint64_t k1,
+void or_lmr_encrypt(const uint8_t *I, int32_t M, int32_t N, int min_level, uint64_t k1, uint64_t nonce,
                     const uint8_t *stream, int64_t stream_bits, uint8_t *Ie)
 {
     size_t MN = (size_t)M * (size_t)N;
     uint8_t *s = (uint8_t *)malloc(MN + 1);
-    or_keystream(k1, 1, 0, MN, s);
+    or_keystream(k1, nonce, 1, 0, MN, s);
     memcpy(Ie, I, MN);
     or_rotate(Ie, M, N, s, min_level, 0);
     for (size_t p = 0; p < MN; ++p) Ie[p] = (uint8_t)(Ie[p] ^ s[p]);
@@ -453,28 +460,28 @@ void or_lmr_encrypt(const uint8_t *I, int32_t M, int32_t N, int min_level, uint6
 /* LMR data hiding / extraction: (b-1) bits at bits 6..8-b of every pixel the
  * (decompressed, rotated) location map marks 0. */
 int64_t or_lmr_embed(uint8_t *Ie, int32_t M, int32_t N, int b, const uint8_t *l_rot,
-                     const uint8_t *msg, int64_t nbits, uint64_t k2)
+                     const uint8_t *msg, int64_t nbits, uint64_t k2, uint64_t nonce)
 {
-    return or_hide(Ie, M, N, l_rot, 6, b - 1, msg, nbits, k2);
+    return or_hide(Ie, M, N, l_rot, 6, b - 1, msg, nbits, k2, nonce);
 }
 
 int64_t or_lmr_extract(const uint8_t *Ie, int32_t M, int32_t N, int b, const uint8_t *l_rot,
-                       uint8_t *msg, int64_t nbits, uint64_t k2)
+                       uint8_t *msg, int64_t nbits, uint64_t k2, uint64_t nonce)
 {
-    return or_reveal(Ie, M, N, l_rot, 6, b - 1, msg, nbits, k2);
+    return or_reveal(Ie, M, N, l_rot, 6, b - 1, msg, nbits, k2, nonce);
 }
 
 /* LMR recovery (Sec. III-B decoding with K1): XOR decryption, de-rotation of
  * the image and both maps, bit 7 from eta, then the glide over bits
  * 6..8-b guided by l. */
-void or_lmr_recover(const uint8_t *Ie, int32_t M, int32_t N, int b, int min_level, uint64_t k1,
+void or_lmr_recover(const uint8_t *Ie, int32_t M, int32_t N, int b, int min_level, uint64_t k1, uint64_t nonce,
                     const uint8_t *l_rot, const uint8_t *eta_rot, uint8_t *out)
 {
     size_t MN = (size_t)M * (size_t)N;
     uint8_t *s = (uint8_t *)malloc(MN + 1);
     uint8_t *l = (uint8_t *)malloc(MN + 1);
     uint8_t *eta = (uint8_t *)malloc(MN + 1);
-    or_keystream(k1, 1, 0, MN, s);
+    or_keystream(k1, nonce, 1, 0, MN, s);
     memcpy(l, l_rot, MN);
     memcpy(eta, eta_rot, MN);
     for (size_t p = 0; p < MN; ++p) out[p] = (uint8_t)(Ie[p] ^ s[p]);
@@ -634,7 +641,7 @@ int or_lmr_decompress(const uint8_t *in, int64_t len, int32_t M, int32_t N, uint
  * also starts at 2^1, 2^2 and 2^3), compress, and keep the first whose
  * stream fits the M*N-bit MSB plane (the "next most optimal location map"
  * fallback).  Returns 0 and fills Ie/meta/stream, or -1 for a bad case. */
-int or_lmr_encode(const uint8_t *I, int32_t M, int32_t N, uint64_t k1, int32_t min_level, uint8_t *Ie,
+int or_lmr_encode(const uint8_t *I, int32_t M, int32_t N, uint64_t k1, uint64_t nonce, int32_t min_level, uint8_t *Ie,
                   or_meta *meta, uint8_t *stream, int64_t *stream_bits)
 {
     size_t MN = (size_t)M * (size_t)N;
@@ -656,7 +663,7 @@ int or_lmr_encode(const uint8_t *I, int32_t M, int32_t N, uint64_t k1, int32_t m
     int64_t len = -1;
     for (int k = 0; k < 7 && !chosen; ++k) {
         int b = order[k];
-        or_lmr_rotated_maps(I, M, N, b, min_level, k1, l_rot, eta_rot);
+        or_lmr_rotated_maps(I, M, N, b, min_level, k1, nonce, l_rot, eta_rot);
         len = or_lmr_compress(eta_rot, l_rot, M, N, stream, cap);
         if (len >= 0) chosen = b;
     }
@@ -672,6 +679,6 @@ int or_lmr_encode(const uint8_t *I, int32_t M, int32_t N, uint64_t k1, int32_t m
     meta->redundant = Z[chosen - 2];
     meta->capacity_bits = (int64_t)(chosen - 1) * Z[chosen - 2];
     *stream_bits = 8 * len;
-    or_lmr_encrypt(I, M, N, min_level, k1, stream, 8 * len, Ie);
+    or_lmr_encrypt(I, M, N, min_level, k1, nonce, stream, 8 * len, Ie);
     return 0;
 }

@@ -49,12 +49,12 @@ def test_chacha20_zero_key_block():
 @pytest.mark.parametrize("key,domain,first,count", [
     (0x0123456789ABCDEF, 1, 0, 1000),
     (0xFEDCBA9876543210, 2, 64 * 5 + 17, 300),
-    (42, 1, (1 << 38) - 200, 200),          # the last bytes below the 32-bit counter wrap
+    (42, 1, (1 << 36) - 200, 200),          # the last bytes of the longest stream the oracle draws
 ])
 def test_keystream_family_is_the_ietf_chacha20_stream(key, domain, first, count):
-    """Byte idx of stream (key, domain) is byte idx of the RFC 8439 keystream
-    with key = K as 8 little-endian bytes then 24 zero bytes, nonce = (domain,
-    0, 0) as little-endian words, counter from 0, for idx below 2^38."""
+    """Byte idx of stream (key, nonce 0, domain) is byte idx of the RFC 8439
+    keystream with key = K as 8 little-endian bytes then 24 zero bytes, nonce =
+    (domain, 0, 0) as little-endian words, counter from 0."""
     kb = key.to_bytes(8, "little") + bytes(24)
     nonce = domain.to_bytes(4, "little") + bytes(8)
     c0 = first // 64
@@ -66,16 +66,20 @@ def test_keystream_family_is_the_ietf_chacha20_stream(key, domain, first, count)
     assert not np.array_equal(O.keystream(key, domain, first, count), ref)   # back to Philox
 
 
-def test_keystream_high_counter_word_goes_to_the_nonce():
-    """Past 2^38 bytes the counter's high part moves into nonce word 1: byte
-    2^38 + t is byte t of the stream with nonce (domain, 1, 0)."""
-    key, domain = 7, 2
+@pytest.mark.parametrize("nonce", [1, 0x89ABCDEF, 0x0123456789ABCDEF, (1 << 64) - 1])
+def test_keystream_nonce_fills_ietf_nonce_words_1_and_2(nonce):
+    """The per-image nonce is the second and third word of the RFC 8439 nonce:
+    stream (key, nonce, domain) is OpenSSL's keystream with nonce bytes
+    domain, nonce low word, nonce high word (little-endian)."""
+    key, domain = 0x1122334455667788, 2
     kb = key.to_bytes(8, "little") + bytes(24)
-    nonce = domain.to_bytes(4, "little") + (1).to_bytes(4, "little") + bytes(4)
-    ref = _openssl_stream(kb, 0, nonce, 128)
+    nb = domain.to_bytes(4, "little") + (nonce & 0xFFFFFFFF).to_bytes(4, "little") + (nonce >> 32).to_bytes(4, "little")
+    ref = _openssl_stream(kb, 3, nb, 192)[7:7 + 150]
     with O.keystream_family(O.KEYSTREAM_CHACHA20):
-        got = O.keystream(key, domain, 1 << 38, 128)
+        got = O.keystream(key, domain, 3 * 64 + 7, 150, nonce)
+        zero = O.keystream(key, domain, 3 * 64 + 7, 150, 0)
     assert np.array_equal(got, ref)
+    assert not np.array_equal(got, zero)
 
 
 def test_chacha_round_trip_in_the_oracle():

@@ -30,18 +30,47 @@ def test_philox_known_answers():
 
 
 def test_keystream_byte_layout():
-    """Byte idx of a stream is little-endian byte idx%16 of block idx/16
-    with counter (idx/16, 0, domain, 0) -- the layout the library header fixes."""
+    """Convention check, not an external pin (the counter layout is this
+    library's choice; the block function itself is pinned by the known
+    answers above and the ChaCha20 family by OpenSSL): byte idx of stream
+    (key, nonce, domain) is little-endian byte idx%16 of the block with counter
+    (idx/16, nonce high word, domain, nonce low word)."""
     key = 0x0123456789ABCDEF
-    ks = O.keystream(key, 1, 0, 64)
-    for blk in range(4):
-        w = O.philox4x32_10([blk, 0, 1, 0], [key & 0xFFFFFFFF, key >> 32])
-        expect = np.frombuffer(w.astype("<u4").tobytes(), dtype=np.uint8)
-        assert np.array_equal(ks[16 * blk:16 * blk + 16], expect)
-    # an offset window is the same stream
-    assert np.array_equal(O.keystream(key, 1, 5, 40), ks[5:45])
-    # domains are distinct streams
-    assert not np.array_equal(O.keystream(key, 2, 0, 64), ks)
+    for nonce in (0, 0x00000005_00000007):
+        ks = O.keystream(key, 1, 0, 64, nonce)
+        for blk in range(4):
+            w = O.philox4x32_10([blk, nonce >> 32, 1, nonce & 0xFFFFFFFF], [key & 0xFFFFFFFF, key >> 32])
+            expect = np.frombuffer(w.astype("<u4").tobytes(), dtype=np.uint8)
+            assert np.array_equal(ks[16 * blk:16 * blk + 16], expect)
+        # an offset window is the same stream
+        assert np.array_equal(O.keystream(key, 1, 5, 40, nonce), ks[5:45])
+        # domains are distinct streams
+        assert not np.array_equal(O.keystream(key, 2, 0, 64, nonce), ks)
+
+
+@pytest.mark.parametrize("family", [0, 1])
+def test_nonce_separates_images_under_one_key(family):
+    """Sec. III-A (secret key generation): with one K1, two nonces give two
+    unrelated keystreams and rotations -- the XOR of two encryptions of the same
+    image is no longer zero above the LSB plane -- while the same nonce gives
+    the same encryption, and every role round-trips only with the nonce the
+    content owner used."""
+    I = inputs.make_image_np(5, 96, 128, 8, 3.0)
+    with O.keystream_family(family):
+        a, ma = O.emr_encrypt(I, 77, nonce=1)
+        b, mb = O.emr_encrypt(I, 77, nonce=2)
+        a2, _ = O.emr_encrypt(I, 77, nonce=1)
+        assert np.array_equal(a, a2)
+        assert (ma.b, ma.capacity_bits) == (mb.b, mb.capacity_bits)   # labels do not depend on the key
+        x = (a ^ b) >> 1
+        assert np.count_nonzero(x) > 0.9 * x.size
+        nbits = int(ma.capacity_bits) // 8 * 8
+        msg = np.random.default_rng(1).integers(0, 256, (nbits + 7) // 8).astype(np.uint8)
+        w = O.emr_embed(a, ma.b, msg, nbits, 78, nonce=1)
+        assert np.array_equal(O.emr_extract(w, ma.b, nbits, 78, nonce=1), msg)
+        assert not np.array_equal(O.emr_extract(w, ma.b, nbits, 78, nonce=3), msg)
+        assert np.array_equal(O.emr_recover(w, ma.b, 77, nonce=1) >> 1, I >> 1)
+        assert not np.array_equal(O.emr_recover(w, ma.b, 77, nonce=2) >> 1, I >> 1)
 
 
 # ----------------------------------------------------------- location maps
