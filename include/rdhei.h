@@ -34,18 +34,22 @@
  *
  * Keystream (Sec. III-A, secret key generation, asks for a cryptographically
  * secure stream cipher); one of two counter-based families, chosen per context
- * with RDHEI_OPT_KEYSTREAM.  Domain 1 = image keystream s (K1), domain 2 =
- * message keystream (K2).
- *   - RDHEI_KEYSTREAM_PHILOX (default): byte idx of stream (key, domain) is
- *     little-endian byte idx%16 of Philox4x32-10 (Salmon et al., SC'11) with
- *     counter (idx/16 low word, idx/16 high word, domain, 0) and key (key low
- *     word, key high word).
+ * with RDHEI_OPT_KEYSTREAM.  A stream is named by (key, nonce, domain): domain
+ * 1 = image keystream s (K1), domain 2 = message keystream (K2); the nonce is
+ * a per-image 64-bit value the content owner passes to encryption, recorded
+ * in the meta record and used by every role of that image for both streams,
+ * so that images encrypted under one key never share a keystream or a
+ * rotation (use a distinct nonce per image and key).  Streams stay below 2^36
+ * bytes (images of at most 2^31 pixels).
+ *   - RDHEI_KEYSTREAM_PHILOX (default): byte idx is little-endian byte idx%16
+ *     of Philox4x32-10 (Salmon et al., SC'11) with counter (idx/16, nonce high
+ *     word, domain, nonce low word) and key (key low word, key high word).
  *   - RDHEI_KEYSTREAM_CHACHA20: byte idx is byte idx%64 of the ChaCha20 block
  *     (Bernstein 2008; the 32-bit-counter, 96-bit-nonce layout of RFC 8439)
  *     with the 256-bit key (key as 8 little-endian bytes, then 24 zero
- *     bytes), block counter (idx/64) mod 2^32 and nonce words (domain,
- *     idx/2^38, 0): for images below 2^38 pixels, exactly the RFC 8439
- *     keystream for that key and nonce from counter 0.
+ *     bytes), block counter idx/64 and nonce words (domain, nonce low word,
+ *     nonce high word): exactly the RFC 8439 keystream for that key and nonce
+ *     from counter 0.
  */
 #ifndef RDHEI_H
 #define RDHEI_H
@@ -82,7 +86,8 @@ typedef struct rdhei_meta {
     int64_t capacity_bits;   /* b*Z_b (EMR) or (b-1)*Z_b (LMR)                 */
     int64_t map_bits;        /* LMR: bits of the map stream in the MSB plane   */
     int32_t status;          /* RDHEI_OK or the device-side error of a stage   */
-    int32_t reserved[3];
+    int32_t reserved;
+    uint64_t nonce;          /* keystream nonce given to rdhei_encrypt          */
 } rdhei_meta;
 
 typedef struct rdhei_ctx rdhei_ctx;
@@ -94,7 +99,8 @@ void rdhei_ctx_destroy(rdhei_ctx *ctx);
 
 /* Content owner (Sec. III-A encoding phase; Sec. III-B encoding phase).
  * Reads d_img (M x N), writes the encrypted image d_enc (M x N; must not
- * alias d_img) and *d_meta (device memory).
+ * alias d_img) and *d_meta (device memory), which records `nonce`: the
+ * per-image keystream nonce of K1's image stream and K2's message stream.
  * EMR: location map for the b in [2,7] maximising b*Z_b (optimal-b equation),
  * rotation of image and map by key-driven block turns at block sizes
  * 2^1..2^n (rotation equation), XOR with s (encryption equation), map into
@@ -103,7 +109,7 @@ void rdhei_ctx_destroy(rdhei_ctx *ctx);
  * on the host and written into the MSB plane (candidates tried in order of
  * (b-1)*Z_b; RDHEI_ENOFIT when none fits).  Synchronises `stream`. */
 int rdhei_encrypt(rdhei_ctx *ctx, const uint8_t *d_img, uint8_t *d_enc, int32_t M, int32_t N,
-                  uint64_t k1, int32_t method, rdhei_meta *d_meta, void *stream);
+                  uint64_t k1, uint64_t nonce, int32_t method, rdhei_meta *d_meta, void *stream);
 
 /* Data hider (Sec. III-A / III-B data hiding phase).  d_marked holds I_e on
  * entry and I_e' on return (in place).  The first nbits bits of d_msg are
@@ -142,13 +148,16 @@ int rdhei_recover(rdhei_ctx *ctx, const uint8_t *d_marked, int32_t M, int32_t N,
 /* One image of a batch.  All pointers are device memory; sizes may differ
  * between images.  in/out/msg follow the single-image call of the op:
  * ENCRYPT: in = I, out = I_e;  EMBED: out = I_e (modified in place), msg in;
- * EXTRACT: in = I_e', msg out;  RECOVER: in = I_e', out = I'. */
+ * EXTRACT: in = I_e', msg out;  RECOVER: in = I_e', out = I'.
+ * nonce: ENCRYPT only, the image's keystream nonce (recorded in its meta;
+ * the other ops read it from there). */
 typedef struct rdhei_job {
     const uint8_t *in;
     uint8_t *out;
     uint8_t *msg;
     rdhei_meta *meta;
     uint64_t key;
+    uint64_t nonce;
     int64_t nbits;           /* EMBED/EXTRACT: bits, or < 0 for the capacity   */
     int32_t height, width;
     int32_t method;          /* plans run EMR only (RDHEI_EMR)                 */

@@ -184,6 +184,8 @@ int make_layout(int op, const rdhei_job *in, int n, const LayoutOpts &opt, Layou
         J.msg = q.msg;
         J.meta = q.meta;
         J.key = q.key;
+        J.nonce = op == RDHEI_OP_ENCRYPT ? q.nonce : 0;
+        J.nonce_meta = op == RDHEI_OP_ENCRYPT ? 0 : 1;
         J.nbits = q.nbits;
         J.M = q.height;
         J.N = q.width;
@@ -192,8 +194,10 @@ int make_layout(int op, const rdhei_job *in, int n, const LayoutOpts &opt, Layou
         J.max_level = floor_log2_min(q.height, q.width);
         const uint64_t MN = (uint64_t)q.height * (uint64_t)q.width;
         const bool rot = op == RDHEI_OP_ENCRYPT || op == RDHEI_OP_RECOVER;
+        // the tile map holds 14-bit tile coordinates: images with more tiles
+        // along a side take the per-pixel path
         J.fast = rot && !force_per_pixel && q.height % kTile == 0 && q.width % kTile == 0 && aligned16(J.in) &&
-                 aligned16(J.out) ? 1 : 0;
+                 aligned16(J.out) && q.height / kTile <= kTmapMaxTiles && q.width / kTile <= kTmapMaxTiles ? 1 : 0;
         if (J.fast) {
             J.tiles_x = q.width / kTile;
             J.tiles_y = q.height / kTile;
@@ -482,11 +486,11 @@ void msb_plane(const uint8_t *img, int64_t bits, std::vector<uint8_t> &out) {
 }
 
 int lmr_encrypt(rdhei_ctx *ctx, const uint8_t *d_img, uint8_t *d_enc, int32_t M, int32_t N, uint64_t k1,
-                rdhei_meta *d_meta, hipStream_t st) {
+                uint64_t nonce, rdhei_meta *d_meta, hipStream_t st) {
     int rc = set_device(ctx->device);
     if (rc) return rc;
     rdhei_job q{};
-    q.in = d_img; q.out = d_enc; q.meta = d_meta; q.key = k1; q.nbits = 0;
+    q.in = d_img; q.out = d_enc; q.meta = d_meta; q.key = k1; q.nonce = nonce; q.nbits = 0;
     q.height = M; q.width = N; q.method = RDHEI_LMR;
     Layout Ly;
     rc = make_layout(RDHEI_OP_ENCRYPT, &q, 1, opts_of(ctx), Ly);
@@ -551,6 +555,7 @@ int lmr_encrypt(rdhei_ctx *ctx, const uint8_t *d_img, uint8_t *d_enc, int32_t M,
     }
     rdhei_meta m{};
     m.height = M; m.width = N; m.method = RDHEI_LMR; m.min_level = J0.min_level; m.max_level = J0.max_level;
+    m.nonce = nonce;
     if (!chosen) {
         m.status = RDHEI_ENOFIT;
         HIPCHK(hipMemcpyAsync(d_meta, &m, sizeof m, hipMemcpyHostToDevice, st));
@@ -790,6 +795,7 @@ int lmr_encrypt_batch(rdhei_ctx *ctx, const rdhei_job *jobs, int n, int threads,
         const Job &J = Ly.jobs[(size_t)i];
         rdhei_meta m{};
         m.height = J.M; m.width = J.N; m.method = RDHEI_LMR; m.min_level = J.min_level; m.max_level = J.max_level;
+        m.nonce = J.nonce;
         const int b = chosen[(size_t)i];
         if (b) {
             const int64_t *z = Z + 7 * i;
@@ -1029,16 +1035,16 @@ int rdhei_ctx_set_option(rdhei_ctx *ctx, int32_t option, int64_t value) {
 }
 
 int rdhei_encrypt(rdhei_ctx *ctx, const uint8_t *d_img, uint8_t *d_enc, int32_t M, int32_t N, uint64_t k1,
-                  int32_t method, rdhei_meta *d_meta, void *stream) {
+                  uint64_t nonce, int32_t method, rdhei_meta *d_meta, void *stream) {
     if (!ctx) return RDHEI_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (method == RDHEI_LMR) {
         if (!d_img || !d_enc || !d_meta || d_img == d_enc || M < 1 || N < 1) return RDHEI_EINVAL;
-        return lmr_encrypt(ctx, d_img, d_enc, M, N, k1, d_meta, st);
+        return lmr_encrypt(ctx, d_img, d_enc, M, N, k1, nonce, d_meta, st);
     }
     if (method != RDHEI_EMR) return RDHEI_EINVAL;
     rdhei_job q{};
-    q.in = d_img; q.out = d_enc; q.meta = d_meta; q.key = k1;
+    q.in = d_img; q.out = d_enc; q.meta = d_meta; q.key = k1; q.nonce = nonce;
     q.height = M; q.width = N; q.method = RDHEI_EMR;
     return run_single(ctx, RDHEI_OP_ENCRYPT, q, st);
 }

@@ -70,13 +70,13 @@ __device__ __forceinline__ void chacha_qr(uint32_t &a, uint32_t &b, uint32_t &c,
 }
 
 // Words 4q..4q+3 of the ChaCha20 block with key (k0, k1, 0, ..., 0), counter
-// ctr and nonce (n0, n1, 0).
+// ctr and nonce (n0, n1, n2).
 __device__ __forceinline__ U4 chacha20_quarter(uint32_t k0, uint32_t k1, uint32_t ctr, uint32_t n0, uint32_t n1,
-                                               uint32_t q) {
+                                               uint32_t n2, uint32_t q) {
     const uint32_t c0 = 0x61707865u, c1 = 0x3320646eu, c2 = 0x79622d32u, c3 = 0x6b206574u;
     uint32_t x0 = c0, x1 = c1, x2 = c2, x3 = c3;
     uint32_t x4 = k0, x5 = k1, x6 = 0, x7 = 0, x8 = 0, x9 = 0, x10 = 0, x11 = 0;
-    uint32_t x12 = ctr, x13 = n0, x14 = n1, x15 = 0;
+    uint32_t x12 = ctr, x13 = n0, x14 = n1, x15 = n2;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         chacha_qr(x0, x4, x8, x12);
@@ -92,7 +92,7 @@ __device__ __forceinline__ U4 chacha20_quarter(uint32_t k0, uint32_t k1, uint32_
     o.x = q == 0 ? x0 + c0 : q == 1 ? x4 + k0 : q == 2 ? x8 : x12 + ctr;
     o.y = q == 0 ? x1 + c1 : q == 1 ? x5 + k1 : q == 2 ? x9 : x13 + n0;
     o.z = q == 0 ? x2 + c2 : q == 1 ? x6 : q == 2 ? x10 : x14 + n1;
-    o.w = q == 0 ? x3 + c3 : q == 1 ? x7 : q == 2 ? x11 : x15;
+    o.w = q == 0 ? x3 + c3 : q == 1 ? x7 : q == 2 ? x11 : x15 + n2;
     return o;
 }
 
@@ -117,11 +117,12 @@ __device__ __forceinline__ uint32_t chacha_row(uint32_t a, uint32_t b, uint32_t 
 // g) and turned back afterwards.  A transpose inside the quad leaves lane g
 // with words 4g..4g+3.  A quarter of the full block's work per lane; every lane
 // of each quad must be active.
-__device__ __forceinline__ U4 chacha20_quad(uint32_t k0, uint32_t k1, uint32_t ctr, uint32_t n0, uint32_t n1) {
+__device__ __forceinline__ U4 chacha20_quad(uint32_t k0, uint32_t k1, uint32_t ctr, uint32_t n0, uint32_t n1,
+                                            uint32_t n2) {
     const uint32_t g = __lane_id() & 3u;
     const uint32_t cst = g == 0 ? 0x61707865u : g == 1 ? 0x3320646eu : g == 2 ? 0x79622d32u : 0x6b206574u;
     const uint32_t key = g == 0 ? k0 : g == 1 ? k1 : 0u;
-    const uint32_t ctl = g == 0 ? ctr : g == 1 ? n0 : g == 2 ? n1 : 0u;
+    const uint32_t ctl = g == 0 ? ctr : g == 1 ? n0 : g == 2 ? n1 : n2;
     uint32_t a = cst, b = key, c = 0u, d = ctl;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
@@ -150,18 +151,21 @@ __device__ __forceinline__ U4 chacha20_quad(uint32_t k0, uint32_t k1, uint32_t c
 constexpr uint32_t kDomainImage = 1;
 constexpr uint32_t kDomainMessage = 2;
 
-// The 16 stream bytes [16*blk, 16*blk+16) as four little-endian words.
-// Philox: one block per 16 bytes, counter (blk, domain, 0).  ChaCha20: the
-// 64-byte block blk/4 with the 64-bit key in key words 0-1, block counter
-// (blk/4) mod 2^32 and nonce (domain, blk/2^34, 0), so the stream is ChaCha20's
-// own byte stream for that key and nonce.
+// The 16 stream bytes [16*blk, 16*blk+16) of the stream (key, nonce, domain)
+// as four little-endian words (streams stay below 2^36 bytes: images of at
+// most 2^31 pixels, messages of at most 7 bits per pixel).  Philox: one block
+// per 16 bytes, counter (blk, nonce high word, domain, nonce low word).
+// ChaCha20: the 64-byte block blk/4 with the 64-bit key in key words 0-1,
+// block counter blk/4 and nonce (domain, nonce low word, nonce high word), so
+// the stream is ChaCha20's own byte stream for that key and 96-bit nonce.
 template <int KS>
-__device__ __forceinline__ U4 stream_block(uint64_t key, uint32_t domain, uint64_t blk) {
+__device__ __forceinline__ U4 stream_block(uint64_t key, uint64_t nonce, uint32_t domain, uint64_t blk) {
     if constexpr (KS == kKsChaCha20)
-        return chacha20_quarter((uint32_t)key, (uint32_t)(key >> 32), (uint32_t)(blk >> 2), domain,
-                                (uint32_t)(blk >> 34), (uint32_t)blk & 3u);
+        return chacha20_quarter((uint32_t)key, (uint32_t)(key >> 32), (uint32_t)(blk >> 2), domain, (uint32_t)nonce,
+                                (uint32_t)(nonce >> 32), (uint32_t)blk & 3u);
     else
-        return philox((uint32_t)blk, (uint32_t)(blk >> 32), domain, 0u, (uint32_t)key, (uint32_t)(key >> 32));
+        return philox((uint32_t)blk, (uint32_t)(nonce >> 32), domain, (uint32_t)nonce, (uint32_t)key,
+                      (uint32_t)(key >> 32));
 }
 
 // stream_block for call sites where the four lanes of every lane quad ask,
@@ -170,16 +174,17 @@ __device__ __forceinline__ U4 stream_block(uint64_t key, uint32_t domain, uint64
 // tile row, and tile rows start on multiples of 64 because M and N are).
 // ChaCha20 then shares one block among the four lanes.
 template <int KS>
-__device__ __forceinline__ U4 stream_block_quad(uint64_t key, uint32_t domain, uint64_t blk) {
+__device__ __forceinline__ U4 stream_block_quad(uint64_t key, uint64_t nonce, uint32_t domain, uint64_t blk) {
     if constexpr (KS == kKsChaCha20)
-        return chacha20_quad((uint32_t)key, (uint32_t)(key >> 32), (uint32_t)(blk >> 2), domain, (uint32_t)(blk >> 34));
+        return chacha20_quad((uint32_t)key, (uint32_t)(key >> 32), (uint32_t)(blk >> 2), domain, (uint32_t)nonce,
+                             (uint32_t)(nonce >> 32));
     else
-        return stream_block<KS>(key, domain, blk);
+        return stream_block<KS>(key, nonce, domain, blk);
 }
 
 template <int KS>
-__device__ __forceinline__ uint32_t stream_byte(uint64_t key, uint32_t domain, uint64_t idx) {
-    U4 v = stream_block<KS>(key, domain, idx >> 4);
+__device__ __forceinline__ uint32_t stream_byte(uint64_t key, uint64_t nonce, uint32_t domain, uint64_t idx) {
+    U4 v = stream_block<KS>(key, nonce, domain, idx >> 4);
     uint32_t w = ((idx >> 2) & 3) == 0 ? v.x : ((idx >> 2) & 3) == 1 ? v.y : ((idx >> 2) & 3) == 2 ? v.z : v.w;
     return (w >> (8 * (idx & 3))) & 0xFFu;
 }
@@ -222,6 +227,12 @@ __device__ __forceinline__ int find_job(const Job *jobs, int njobs, uint32_t u, 
         if (jobs[mid].ubase[KIND] <= u) lo = mid; else hi = mid - 1;
     }
     return lo;
+}
+
+// Per-image keystream nonce: the content owner's choice at encryption (in the
+// job table), read back from the public meta record by the other roles.
+__device__ __forceinline__ uint64_t job_nonce(const Job &J) {
+    return J.nonce_meta ? uni64(gload<uint64_t>(&J.meta->nonce)) : J.nonce;
 }
 
 // ---- Rotation ------------------------------------------------------------------
@@ -283,7 +294,8 @@ __device__ __forceinline__ void upper_walk(const Job &J, const uint8_t *pyr, int
 }
 
 // Tile-map entry: destination tile row (bits 0..13), column (bits 14..27) and
-// quarter turns of the content (bits 28..29).
+// quarter turns of the content (bits 28..29); the host sends images with more
+// than kTmapMaxTiles tiles along a side to the per-pixel path.
 __device__ __forceinline__ uint32_t tmap_pack(int dy, int dx, uint32_t turns) {
     return (uint32_t)dy | ((uint32_t)dx << 14) | (turns << 28);
 }

@@ -48,6 +48,10 @@ inline void with_keystream(int ks, F &&f) {
     else f(std::integral_constant<int, kKsPhilox>{});
 }
 
+// Tile-map entries hold destination tile coordinates in 14 bits each, so the
+// tiled path takes images of at most this many tiles along each side.
+constexpr int kTmapMaxTiles = 1 << 14;
+
 // Encryption cuts band pairs into segments of at most kQuadSeg 2x2 tile quads
 // (one work unit each); EMR recovery takes whole band pairs.
 constexpr int kQuadSeg = 4;
@@ -62,6 +66,7 @@ struct Job {
     const uint8_t *etabits;   // LMR: rotated first-MSB bit plane (encrypted domain)
     const uint8_t *stream;    // LMR encrypt: map stream for the MSB plane
     uint64_t key;
+    uint64_t nonce;           // keystream nonce (encryption: the caller's; other ops read meta->nonce)
     int64_t nbits;            // embed/extract request (< 0: capacity)
     int64_t stream_bits;      // LMR encrypt: stream length in bits
     int32_t M, N;
@@ -72,6 +77,7 @@ struct Job {
     int32_t fast;             // 1: tiled path; 0: per-pixel path
     int32_t tiles_x, tiles_y;
     int32_t nseg;             // hiding / extraction steps of seg_pixels() raster pixels
+    int32_t nonce_meta;       // 1: the keystream nonce comes from meta->nonce (device)
     uint32_t ubase[UNIT_KINDS];
     uint32_t ucount[UNIT_KINDS];
     uint64_t ws_codes;        // tile code records (fast) / all-level codes (per-pixel path)

@@ -17,6 +17,7 @@ __host__ __device__ inline uint64_t gen_off(int M, int N, int m) {
 template <int KS>
 __global__ void k_gen_level1(const Job *__restrict__ jobs, int j, uint8_t *__restrict__ ws) {
     const Job &J = jobs[j];
+    const uint64_t nz = job_nonce(J);
     const uint32_t gx = (uint32_t)(J.N >> 1), gy = (uint32_t)(J.M >> 1);
     const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q == 0) {
@@ -26,9 +27,9 @@ __global__ void k_gen_level1(const Job *__restrict__ jobs, int j, uint8_t *__res
     if (q >= (uint64_t)gx * gy) return;
     const uint32_t Y = (uint32_t)(q / gx), X = (uint32_t)(q % gx);
     const uint64_t p = (uint64_t)(2 * Y) * (uint64_t)J.N + 2 * X;
-    const uint32_t sum = stream_byte<KS>(J.key, kDomainImage, p) + stream_byte<KS>(J.key, kDomainImage, p + 1) +
-                         stream_byte<KS>(J.key, kDomainImage, p + J.N) +
-                         stream_byte<KS>(J.key, kDomainImage, p + J.N + 1);
+    const uint32_t sum = stream_byte<KS>(J.key, nz, kDomainImage, p) + stream_byte<KS>(J.key, nz, kDomainImage, p + 1) +
+                         stream_byte<KS>(J.key, nz, kDomainImage, p + J.N) +
+                         stream_byte<KS>(J.key, nz, kDomainImage, p + J.N + 1);
     ws[J.ws_codes + gen_off(J.M, J.N, 1) + q] = (uint8_t)(sum & 3u);
 }
 
@@ -88,6 +89,7 @@ __device__ inline void gen_forward(const Job &J, const uint8_t *codes, uint32_t 
 template <int MODE, int KS>
 __global__ void k_gen_encrypt(const Job *__restrict__ jobs, int j, uint8_t *__restrict__ ws) {
     const Job &J = jobs[j];
+    const uint64_t nz = job_nonce(J);
     const uint64_t total = (uint64_t)J.M * (uint64_t)J.N;
     const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= total) return;
@@ -104,7 +106,7 @@ __global__ void k_gen_encrypt(const Job *__restrict__ jobs, int j, uint8_t *__re
         ws[J.ws_bytes + p] = (uint8_t)((l << 1) | (v >> 7));
         return;
     }
-    const uint32_t s = stream_byte<KS>(J.key, kDomainImage, p);
+    const uint32_t s = stream_byte<KS>(J.key, nz, kDomainImage, p);
     uint32_t e;
     if (MODE == ENC_EMR) {
         e = ((v ^ s) & 0xFEu) | l;
@@ -139,6 +141,7 @@ __global__ void k_gen_pack(const Job *__restrict__ jobs, int j, const uint8_t *_
 template <int METHOD, int KS>
 __global__ void k_gen_recover(const Job *__restrict__ jobs, int j, const uint8_t *__restrict__ ws) {
     const Job &J = jobs[j];
+    const uint64_t nz = job_nonce(J);
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (uint32_t)J.M) return;
     const int b = J.meta->b;
@@ -149,7 +152,7 @@ __global__ void k_gen_recover(const Job *__restrict__ jobs, int j, const uint8_t
         gen_forward(J, ws + J.ws_codes, i, x, py, px);
         const uint64_t p = (uint64_t)py * (uint64_t)J.N + px;
         const uint32_t e = J.in[p];
-        uint32_t D = e ^ stream_byte<KS>(J.key, kDomainImage, p);
+        uint32_t D = e ^ stream_byte<KS>(J.key, nz, kDomainImage, p);
         uint32_t l;
         if (METHOD == RDHEI_EMR) {
             l = e & 1u;

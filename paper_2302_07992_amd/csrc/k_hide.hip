@@ -27,6 +27,7 @@ constexpr uint64_t kWholeMaxPx = 1ull << 20;
 struct HideParams {
     uint32_t rep, shift;      // replaceable bits per redundant pixel, position of the lowest
     int64_t nbits;            // bits requested (resolved against the capacity)
+    uint64_t nonce;           // keystream nonce of the image (from the meta record)
     bool ok;
 };
 
@@ -42,6 +43,7 @@ __device__ __forceinline__ HideParams hide_params(const Job &J) {
     h.rep = uni(h.rep);
     h.shift = uni(h.shift);
     h.nbits = (int64_t)uni64((uint64_t)h.nbits);
+    h.nonce = uni64(m->nonce);
     h.ok = uni(h.ok ? 1u : 0u) != 0;
     return h;
 }
@@ -230,8 +232,8 @@ __device__ __forceinline__ uint32_t be_mask(int64_t w, int64_t lo, int64_t hi) {
 
 // Message keystream word w, big-endian bit order.
 template <int KS>
-__device__ __forceinline__ uint32_t ks_word(uint64_t key, int64_t w) {
-    const U4 ks = stream_block<KS>(key, kDomainMessage, (uint64_t)w >> 2);
+__device__ __forceinline__ uint32_t ks_word(uint64_t key, uint64_t nonce, int64_t w) {
+    const U4 ks = stream_block<KS>(key, nonce, kDomainMessage, (uint64_t)w >> 2);
     const uint32_t kw = (w & 3) == 0 ? ks.x : (w & 3) == 1 ? ks.y : (w & 3) == 2 ? ks.z : ks.w;
     return __builtin_bswap32(kw);
 }
@@ -296,13 +298,14 @@ __device__ __forceinline__ void step_ranks(const uint32_t rm[kWLoads], uint32_t 
 // Embedding: message blocks fb..lb, XORed with the stream, byte-swapped into
 // win[4 + 4q], q = block - fb.
 template <int KS>
-__device__ __forceinline__ void stage_window_quad(const Job &J, int lane, int64_t fb, int64_t lb, uint32_t *win) {
+__device__ __forceinline__ void stage_window_quad(const Job &J, uint64_t nonce, int lane, int64_t fb, int64_t lb,
+                                                  uint32_t *win) {
     const int64_t fa = fb & ~(int64_t)3;
     for (int64_t base = 0; base <= lb - fa; base += 64) {
         const int64_t q = fa + base + lane - fb;
         const bool in = q >= 0 && q <= lb - fb;
         const uint4 mv = in ? gload<uint4>(J.msg + 16 * (uint64_t)(fb + q)) : make_uint4(0, 0, 0, 0);
-        const U4 ks = stream_block_quad<KS>(J.key, kDomainMessage, (uint64_t)(fa + base + lane));
+        const U4 ks = stream_block_quad<KS>(J.key, nonce, kDomainMessage, (uint64_t)(fa + base + lane));
         if (in)
             *reinterpret_cast<uint4 *>(win + 4 + 4 * q) =
                 make_uint4(__builtin_bswap32(mv.x ^ ks.x), __builtin_bswap32(mv.y ^ ks.y),
@@ -313,11 +316,12 @@ __device__ __forceinline__ void stage_window_quad(const Job &J, int lane, int64_
 // Extraction: calls put(block, stream words) for the blocks B0..B1 (and the
 // aligned neighbours, whose words put must skip).
 template <int KS, typename F>
-__device__ __forceinline__ void each_stream_block_quad(const Job &J, int lane, int64_t B0, int64_t B1, F &&put) {
+__device__ __forceinline__ void each_stream_block_quad(const Job &J, uint64_t nonce, int lane, int64_t B0, int64_t B1,
+                                                       F &&put) {
     const int64_t Ba = B0 & ~(int64_t)3;
     for (int64_t base = 0; base <= B1 - Ba; base += 64) {
         const int64_t blk = Ba + base + lane;
-        put(blk, stream_block_quad<KS>(J.key, kDomainMessage, (uint64_t)blk));
+        put(blk, stream_block_quad<KS>(J.key, nonce, kDomainMessage, (uint64_t)blk));
     }
 }
 
@@ -379,14 +383,14 @@ __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &
             const int64_t fb = wstart >> 7, lb = (wend - 1) >> 7;
             const uint32_t off0 = (uint32_t)(wstart - (fb << 7)), rend = (uint32_t)(wend - (fb << 7));
             if constexpr (KS == kKsChaCha20) {
-                stage_window_quad<KS>(J, lane, fb, lb, win);
+                stage_window_quad<KS>(J, hp.nonce, lane, fb, lb, win);
             } else {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int64_t q = lane + 64 * i;
                     if (q > lb - fb) continue;
                     const uint4 mv = q < (int64_t)npre ? mpre[i] : gload<uint4>(J.msg + 16 * (uint64_t)(fb + q));
-                    const U4 ks = stream_block<KS>(J.key, kDomainMessage, (uint64_t)(fb + q));
+                    const U4 ks = stream_block<KS>(J.key, hp.nonce, kDomainMessage, (uint64_t)(fb + q));
                     *reinterpret_cast<uint4 *>(win + 4 + 4 * q) =
                         make_uint4(__builtin_bswap32(mv.x ^ ks.x), __builtin_bswap32(mv.y ^ ks.y),
                                    __builtin_bswap32(mv.z ^ ks.z), __builtin_bswap32(mv.w ^ ks.w));
@@ -425,7 +429,7 @@ __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &
             if (nstore > 0) {   // one keystream block per four message words
                 const int64_t B0 = W0 >> 2, B1 = (W0 + nstore - 1) >> 2;
                 if constexpr (KS == kKsChaCha20) {
-                    each_stream_block_quad<KS>(J, lane, B0, B1, [&](int64_t blk, const U4 &ks) {
+                    each_stream_block_quad<KS>(J, hp.nonce, lane, B0, B1, [&](int64_t blk, const U4 &ks) {
                         const uint32_t kw[4] = {ks.x, ks.y, ks.z, ks.w};
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
@@ -435,7 +439,7 @@ __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &
                     });
                 } else {
                     for (int64_t bq = lane; bq <= B1 - B0; bq += 64) {
-                        const U4 ks = stream_block<KS>(J.key, kDomainMessage, (uint64_t)(B0 + bq));
+                        const U4 ks = stream_block<KS>(J.key, hp.nonce, kDomainMessage, (uint64_t)(B0 + bq));
                         const uint32_t kw[4] = {ks.x, ks.y, ks.z, ks.w};
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
@@ -454,7 +458,7 @@ __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &
         // the message's last word: bits past nbits are stored as zero
         const uint32_t own = be_mask(carry_word, 0, hp.nbits);
         gstore<uint32_t>(reinterpret_cast<uint32_t *>(J.msg) + carry_word,
-                         __builtin_bswap32((carry ^ ks_word<KS>(J.key, carry_word)) & own));
+                         __builtin_bswap32((carry ^ ks_word<KS>(J.key, hp.nonce, carry_word)) & own));
     }
 }
 
@@ -618,12 +622,12 @@ __global__ __launch_bounds__(kThreads) void k_seg_hide(const Job *__restrict__ j
             const int64_t fb = wstart >> 7, lb = (wend - 1) >> 7;
             const uint32_t off0 = (uint32_t)(wstart - (fb << 7)), rend = (uint32_t)(wend - (fb << 7));
             if constexpr (KS == kKsChaCha20) {
-                stage_window_quad<KS>(J, lane, fb, lb, win);
+                stage_window_quad<KS>(J, hp.nonce, lane, fb, lb, win);
             } else {
                 for (int64_t q = lane; q <= lb - fb; q += 64) {
                     const uint64_t blk = (uint64_t)(fb + q);
                     const uint4 mv = gload<uint4>(J.msg + 16 * blk);
-                    const U4 ks = stream_block<KS>(J.key, kDomainMessage, blk);
+                    const U4 ks = stream_block<KS>(J.key, hp.nonce, kDomainMessage, blk);
                     *reinterpret_cast<uint4 *>(win + 4 + 4 * q) =
                         make_uint4(__builtin_bswap32(mv.x ^ ks.x), __builtin_bswap32(mv.y ^ ks.y),
                                    __builtin_bswap32(mv.z ^ ks.z), __builtin_bswap32(mv.w ^ ks.w));
@@ -656,7 +660,7 @@ __global__ __launch_bounds__(kThreads) void k_seg_hide(const Job *__restrict__ j
             uint32_t *msgw = reinterpret_cast<uint32_t *>(J.msg);
             const int64_t B0 = W0 >> 2, B1 = (W1 - 1) >> 2;
             if constexpr (KS == kKsChaCha20) {
-                each_stream_block_quad<KS>(J, lane, B0, B1, [&](int64_t blk, const U4 &ks) {
+                each_stream_block_quad<KS>(J, hp.nonce, lane, B0, B1, [&](int64_t blk, const U4 &ks) {
                     const uint32_t kw[4] = {ks.x, ks.y, ks.z, ks.w};
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
@@ -677,7 +681,7 @@ __global__ __launch_bounds__(kThreads) void k_seg_hide(const Job *__restrict__ j
                 });
             } else {
                 for (int64_t bq = lane; bq <= B1 - B0; bq += 64) {
-                    const U4 ks = stream_block<KS>(J.key, kDomainMessage, (uint64_t)(B0 + bq));
+                    const U4 ks = stream_block<KS>(J.key, hp.nonce, kDomainMessage, (uint64_t)(B0 + bq));
                     const uint32_t kw[4] = {ks.x, ks.y, ks.z, ks.w};
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {

@@ -139,6 +139,7 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
         }
         const int j = (int)uni((uint32_t)find_job<UNIT_TILE>(jobs, njobs, u, ujob));
         const Job &J = jobs[j];
+        const uint64_t nz = job_nonce(J);
         const uint32_t t = u - J.ubase[UNIT_TILE];
         const int ty = (int)(t / (uint32_t)J.tiles_x), tx = (int)(t % (uint32_t)J.tiles_x);
         const uint64_t idx0 = (uint64_t)(ty * kTile + 4 * q) * (uint64_t)J.N + (uint64_t)(tx * kTile + 16 * g);
@@ -147,8 +148,8 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
         uint32_t h[2][4];
 #pragma unroll
         for (int pp = 0; pp < 2; ++pp) {
-            const U4 sa = stream_block_quad<KS>(J.key, kDomainImage, (idx0 + (uint64_t)(2 * pp) * J.N) >> 4);
-            const U4 sb = stream_block_quad<KS>(J.key, kDomainImage, (idx0 + (uint64_t)(2 * pp + 1) * J.N) >> 4);
+            const U4 sa = stream_block_quad<KS>(J.key, nz, kDomainImage, (idx0 + (uint64_t)(2 * pp) * J.N) >> 4);
+            const U4 sb = stream_block_quad<KS>(J.key, nz, kDomainImage, (idx0 + (uint64_t)(2 * pp + 1) * J.N) >> 4);
             const uint32_t wa[4] = {sa.x, sa.y, sa.z, sa.w}, wb[4] = {sb.x, sb.y, sb.z, sb.w};
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -312,7 +313,8 @@ __device__ void finish_stats(const Job &J, uint8_t *ws) {
         m.min_level = J.min_level; m.max_level = J.max_level;
         m.redundant = Z[best]; m.capacity_bits = (int64_t)best * Z[best];
         m.map_bits = 0; m.status = RDHEI_OK;
-        m.reserved[0] = m.reserved[1] = m.reserved[2] = 0;
+        m.reserved = 0;
+        m.nonce = J.nonce;
         *J.meta = m;
     }
 }
@@ -522,6 +524,7 @@ __global__ __launch_bounds__(kThreads) void k_encrypt_quad(const Job *__restrict
         const uint4 rc = rc_n;
         const uint32_t b_cur = uni(b_n), st_cur = uni(st_n), tm = uni(tm_n), halo_mem = halo_n;
         const Job &J = jobs[S.j];
+        const uint64_t nz = job_nonce(J);
         const int ty = 2 * S.p + half, tx = 2 * (S.c0 + c) + side;
         const bool have = ty < J.tiles_y && tx < J.tiles_x;   // wave-uniform
         const bool first = c == 0;
@@ -566,10 +569,10 @@ __global__ __launch_bounds__(kThreads) void k_encrypt_quad(const Job *__restrict
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const uint32_t d = (w[k] ^ lw[k]) & topm;
-                uint32_t nz = ((((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d) >> 7) & 0x01010101u;  // l per byte
-                if (k == 0 && tx == 0 && g == 0) nz |= 1u;                                  // column 0
-                if (MODE == ENC_EMR) o[i][k] = (w[k] & 0xFEFEFEFEu) | nz;
-                else o[i][k] = (nz << 1) | ((w[k] >> 7) & 0x01010101u);                     // l<<1 | eta
+                uint32_t lbl = ((((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d) >> 7) & 0x01010101u;  // l per byte
+                if (k == 0 && tx == 0 && g == 0) lbl |= 1u;                                  // column 0
+                if (MODE == ENC_EMR) o[i][k] = (w[k] & 0xFEFEFEFEu) | lbl;
+                else o[i][k] = (lbl << 1) | ((w[k] >> 7) & 0x01010101u);                     // l<<1 | eta
             }
         }
         if (lane < kCodeRecord / 16) reinterpret_cast<uint4 *>(rec)[lane] = rc;
@@ -615,7 +618,7 @@ __global__ __launch_bounds__(kThreads) void k_encrypt_quad(const Job *__restrict
                 gstore<uint16_t>(J.out + (didx >> 3), (uint16_t)lb);
                 gstore<uint16_t>(J.msg + (didx >> 3), (uint16_t)eb);
             } else {
-                const U4 sk = stream_block_quad<KS>(J.key, kDomainImage, didx >> 4);
+                const U4 sk = stream_block_quad<KS>(J.key, nz, kDomainImage, didx >> 4);
                 uint4 e;
                 if (MODE == ENC_EMR) {
                     e = make_uint4(qv.x ^ (sk.x & 0xFEFEFEFEu), qv.y ^ (sk.y & 0xFEFEFEFEu),
@@ -686,6 +689,7 @@ __global__ __launch_bounds__(kThreads) void k_recover_band_lmr(const Job *__rest
 
     for (uint32_t u = u0; u < u1; ++u) {
         const Job &J = jobs[uni((uint32_t)find_job<UNIT_BAND>(jobs, njobs, u, ujob))];
+        const uint64_t nz = job_nonce(J);
         const int ty = (int)(u - J.ubase[UNIT_BAND]);
         const int b = (int)uni(b_n);
         const uint32_t mask = (0xFFu << (8 - b)) & 0x7Fu;   // bits 6..8-b (bit 7 comes from the eta map)
@@ -702,7 +706,7 @@ __global__ __launch_bounds__(kThreads) void k_recover_band_lmr(const Job *__rest
             uint32_t up;
             tmap_unpack(reinterpret_cast<const uint32_t *>(ws + J.ws_tmap)[ty * J.tiles_x + tx], ey, ex, up);
             const uint64_t eidx = (uint64_t)(ey * kTile + r) * (uint64_t)J.N + (uint64_t)(ex * kTile + 16 * g);
-            const U4 s = stream_block_quad<KS>(J.key, kDomainImage, eidx >> 4);
+            const U4 s = stream_block_quad<KS>(J.key, nz, kDomainImage, eidx >> 4);
             uint32_t D[4] = {e.x ^ s.x, e.y ^ s.y, e.z ^ s.z, e.w ^ s.w};
             uint32_t Lw[4];
 #pragma unroll
@@ -905,6 +909,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         int ty = 0, tx = 0;
         const bool have = tile_of(cur, ty, tx);   // wave-uniform
         const Job &J = jobs[cur.S.j];
+        const uint64_t nz = job_nonce(J);
         const bool first = cur.c == 0, last = cur.c == cur.S.nc - 1;
         const bool segd = cur.S.ns > 1;            // rows continue in other segments (fixed up afterwards)
         const bool right_in = 2 * (cur.S.c0 + cur.c) + 1 < J.tiles_x;
@@ -919,7 +924,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
             uint32_t dw[4][4], lw[4][4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const U4 s = stream_block_quad<KS>(J.key, kDomainImage, (e0 + (uint64_t)i * J.N) >> 4);
+                const U4 s = stream_block_quad<KS>(J.key, nz, kDomainImage, (e0 + (uint64_t)i * J.N) >> 4);
                 const uint32_t ew[4] = {e[i].x, e[i].y, e[i].z, e[i].w}, sw[4] = {s.x, s.y, s.z, s.w};
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {

@@ -47,7 +47,7 @@ class MetaStruct(ctypes.Structure):
     _fields_ = [("height", ctypes.c_int32), ("width", ctypes.c_int32), ("method", ctypes.c_int32),
                 ("b", ctypes.c_int32), ("min_level", ctypes.c_int32), ("max_level", ctypes.c_int32),
                 ("redundant", ctypes.c_int64), ("capacity_bits", ctypes.c_int64), ("map_bits", ctypes.c_int64),
-                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32), ("nonce", ctypes.c_uint64)]
 
 
 assert ctypes.sizeof(MetaStruct) == META_BYTES
@@ -65,14 +65,15 @@ METRIC_NAMES = ("entropy_a", "chi2_a", "entropy_b", "chi2_b", "npcr", "uaci", "p
 
 class JobStruct(ctypes.Structure):
     _fields_ = [("inp", ctypes.c_void_p), ("out", ctypes.c_void_p), ("msg", ctypes.c_void_p),
-                ("meta", ctypes.c_void_p), ("key", ctypes.c_uint64), ("nbits", ctypes.c_int64),
+                ("meta", ctypes.c_void_p), ("key", ctypes.c_uint64), ("nonce", ctypes.c_uint64),
+                ("nbits", ctypes.c_int64),
                 ("height", ctypes.c_int32), ("width", ctypes.c_int32), ("method", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
 
 # numpy view of rdhei_job, for building large job tables without Python loops
 JOB_DTYPE = np.dtype([("inp", "<u8"), ("out", "<u8"), ("msg", "<u8"), ("meta", "<u8"), ("key", "<u8"),
-                      ("nbits", "<i8"), ("height", "<i4"), ("width", "<i4"), ("method", "<i4"),
+                      ("nonce", "<u8"), ("nbits", "<i8"), ("height", "<i4"), ("width", "<i4"), ("method", "<i4"),
                       ("reserved", "<i4")])
 assert JOB_DTYPE.itemsize == ctypes.sizeof(JobStruct)
 
@@ -103,7 +104,7 @@ def load_library(path: str = LIB_PATH):
     lib.rdhei_ctx_destroy.argtypes = [vp]
     lib.rdhei_ctx_destroy.restype = None
     lib.rdhei_ctx_set_option.argtypes = [vp, i32, i64]
-    lib.rdhei_encrypt.argtypes = [vp, vp, vp, i32, i32, u64, i32, vp, vp]
+    lib.rdhei_encrypt.argtypes = [vp, vp, vp, i32, i32, u64, u64, i32, vp, vp]
     lib.rdhei_embed.argtypes = [vp, vp, i32, i32, i32, vp, vp, i64, u64, vp]
     lib.rdhei_extract.argtypes = [vp, vp, i32, i32, i32, vp, vp, i64, u64, vp]
     lib.rdhei_recover.argtypes = [vp, vp, i32, i32, i32, vp, vp, u64, vp]
@@ -173,6 +174,7 @@ class Meta:
     capacity_bits: int
     map_bits: int
     status: int
+    nonce: int = 0
 
 
 def read_meta(t: torch.Tensor):
@@ -183,7 +185,7 @@ def read_meta(t: torch.Tensor):
     for r in rows:
         m = MetaStruct.from_buffer_copy(r.tobytes())
         out.append(Meta(m.height, m.width, m.method, m.b, m.min_level, m.max_level, m.redundant,
-                        m.capacity_bits, m.map_bits, m.status))
+                        m.capacity_bits, m.map_bits, m.status, m.nonce))
     return out[0] if a.ndim == 1 else out
 
 
@@ -191,7 +193,7 @@ def read_meta_array(t: torch.Tensor) -> np.ndarray:
     """Vectorised decode of (n, 64) metas: structured numpy array."""
     dt = np.dtype([("height", "<i4"), ("width", "<i4"), ("method", "<i4"), ("b", "<i4"), ("min_level", "<i4"),
                    ("max_level", "<i4"), ("redundant", "<i8"), ("capacity_bits", "<i8"), ("map_bits", "<i8"),
-                   ("status", "<i4"), ("reserved", "<i4", (3,))])
+                   ("status", "<i4"), ("reserved", "<i4"), ("nonce", "<u8")])
     return t.detach().to("cpu").contiguous().numpy().reshape(-1).view(dt)
 
 
@@ -220,10 +222,12 @@ class Context:
         _check(self.lib.rdhei_ctx_set_option(self.h, option, value), "rdhei_ctx_set_option")
 
     def encrypt(self, img: torch.Tensor, enc: torch.Tensor, k1: int, meta: torch.Tensor, method: int = EMR,
-                stream=None) -> None:
+                stream=None, nonce: int = 0) -> None:
+        """Content owner: encrypt `img` into `enc` with key k1 and the image's
+        keystream nonce (recorded in `meta` for the other roles)."""
         M, N = img.shape
-        _check(self.lib.rdhei_encrypt(self.h, _ptr(img), _ptr(enc), M, N, k1, method, _ptr(meta), _stream(stream)),
-               "rdhei_encrypt")
+        _check(self.lib.rdhei_encrypt(self.h, _ptr(img), _ptr(enc), M, N, k1, nonce, method, _ptr(meta),
+                                      _stream(stream)), "rdhei_encrypt")
 
     def embed(self, marked: torch.Tensor, meta: torch.Tensor, msg: torch.Tensor, nbits: int, k2: int,
               method: int = EMR, stream=None) -> None:
@@ -311,8 +315,9 @@ def make_metric_jobs(pairs) -> ctypes.Array:
 
 
 def make_jobs(ins: Sequence, outs: Sequence, msgs: Sequence, metas: Sequence, keys: Sequence[int],
-              nbits: Sequence[int], shapes: Sequence, method: int = EMR):
-    """Job array from per-image pointers (ints) or tensors (None allowed)."""
+              nbits: Sequence[int], shapes: Sequence, method: int = EMR, nonces: Optional[Sequence[int]] = None):
+    """Job array from per-image pointers (ints) or tensors (None allowed);
+    nonces: per-image keystream nonces of an ENCRYPT batch (default 0)."""
     n = len(keys)
     arr = (JobStruct * n)()
 
@@ -327,6 +332,7 @@ def make_jobs(ins: Sequence, outs: Sequence, msgs: Sequence, metas: Sequence, ke
         arr[i].msg = p(msgs[i]) if msgs is not None else None
         arr[i].meta = p(metas[i])
         arr[i].key = int(keys[i]) & ((1 << 64) - 1)
+        arr[i].nonce = (int(nonces[i]) & ((1 << 64) - 1)) if nonces is not None else 0
         arr[i].nbits = int(nbits[i]) if nbits is not None else 0
         arr[i].height, arr[i].width = int(shapes[i][0]), int(shapes[i][1])
         arr[i].method = method

@@ -125,7 +125,7 @@ def make_workload(n: int, seed: int = 0, embed_frac: float = 0.6, sides=None, we
         if M not in scratch:
             scratch[M] = torch.empty(M, M, dtype=torch.uint8, device=device)
         enc = torch.empty(M, M, dtype=torch.uint8, device=device) if kind[i] == RECOVER_REQ else scratch[M]
-        ctx.encrypt(img, enc, k1, meta)
+        ctx.encrypt(img, enc, k1, meta, nonce=s)
         torch.cuda.synchronize()
         cap = int(R.read_meta(meta).capacity_bits)
         payload = make_payload(s, cap, device)
@@ -292,12 +292,14 @@ class Server:
             enc["out"] = base + out["img_e"]
             enc["meta"] = base + out["meta_e"]
             enc["key"] = wl.k1[e]
+            enc["nonce"] = wl.seed[e]
             enc["height"] = wl.side[e]
             enc["width"] = wl.side[e]
             emb = enc.copy()
             emb["inp"] = 0
             emb["msg"] = wl.msg_ptr[e]
             emb["key"] = wl.k2[e]
+            emb["nonce"] = 0
             emb["nbits"] = wl.nbits[e]
             tabs += [(R.OP_ENCRYPT, enc, ("out", "meta")), (R.OP_EMBED, emb, ("out", "meta"))]
         if len(r):
@@ -322,7 +324,8 @@ class Server:
         lib, h = self.lib, ctx.h
         M = int(j["height"])
         if op == R.OP_ENCRYPT:
-            rc = lib.rdhei_encrypt(h, int(j["inp"]), int(j["out"]), M, M, int(j["key"]), R.EMR, int(j["meta"]), sp)
+            rc = lib.rdhei_encrypt(h, int(j["inp"]), int(j["out"]), M, M, int(j["key"]), int(j["nonce"]), R.EMR,
+                                   int(j["meta"]), sp)
         elif op == R.OP_EMBED:
             rc = lib.rdhei_embed(h, int(j["out"]), M, M, R.EMR, int(j["meta"]), int(j["msg"]), int(j["nbits"]),
                                  int(j["key"]), sp)

@@ -41,29 +41,39 @@ def _msg_dev(R, msg, nbits):
     return buf
 
 
-def _roundtrip(R, ctx, I, k1, k2, frac=1.0):
+def _roundtrip(R, ctx, I, k1, k2, frac=1.0, nonce=0, threads=False):
+    """Every role against the oracle, element by element.  threads: the
+    oracle's recovery runs beside its embedding, on the GPU's marked image
+    once that equals the oracle's (for the largest images)."""
     M, N = I.shape
-    print(f"[emr roundtrip] shape={M}x{N} k1={k1}", flush=True)
-    Ie_o, mo = O.emr_encrypt(I, k1)
+    print(f"[emr roundtrip] shape={M}x{N} k1={k1} nonce={nonce}", flush=True)
+    Ie_o, mo = O.emr_encrypt(I, k1, nonce=nonce)
     d_img = _dev(I)
     d_enc = torch.empty_like(d_img)
     meta = R.new_meta()
-    ctx.encrypt(d_img, d_enc, k1, meta)
+    ctx.encrypt(d_img, d_enc, k1, meta, nonce=nonce)
     torch.cuda.synchronize()
     m = R.read_meta(meta)
     assert (m.status, m.b, m.redundant, m.capacity_bits) == (0, mo.b, mo.redundant, mo.capacity_bits)
-    assert (m.min_level, m.max_level) == (mo.min_level, mo.max_level)
+    assert (m.min_level, m.max_level, m.nonce) == (mo.min_level, mo.max_level, nonce)
     Ie = d_enc.cpu().numpy()
     mism = np.argwhere(Ie != Ie_o)
     assert mism.size == 0, f"encrypt mismatch at {mism[:5].tolist()} of {len(mism)}"
+    del Ie
 
     nbits = int(mo.capacity_bits * frac)
     msg = inputs.make_payload(k2, nbits).numpy()
-    Iem_o = O.emr_embed(Ie_o, mo.b, msg, nbits, k2)
     ctx.embed(d_enc, meta, _msg_dev(R, msg, nbits), nbits, k2)
     torch.cuda.synchronize()
     assert R.read_meta(meta).status == 0
     Iem = d_enc.cpu().numpy()
+    pool = rec_f = None
+    if threads:
+        from concurrent.futures import ThreadPoolExecutor
+        pool = ThreadPoolExecutor(1)
+        rec_f = pool.submit(O.emr_recover, Iem, mo.b, k1, nonce)
+    Iem_o = O.emr_embed(Ie_o, mo.b, msg, nbits, k2, nonce=nonce)
+    del Ie_o
     mism = np.argwhere(Iem != Iem_o)
     assert mism.size == 0, f"embed mismatch at {mism[:5].tolist()} of {len(mism)}"
 
@@ -71,14 +81,16 @@ def _roundtrip(R, ctx, I, k1, k2, frac=1.0):
     ctx.extract(d_enc, meta, d_out, nbits, k2)
     got = d_out.cpu().numpy()
     nb = (nbits + 7) // 8
-    assert np.array_equal(got[:nb], O.emr_extract(Iem_o, mo.b, nbits, k2))
+    assert np.array_equal(got[:nb], O.emr_extract(Iem_o, mo.b, nbits, k2, nonce=nonce))
     assert np.array_equal(got[:nb], msg[:nb])
     assert not got[nb:(nbits + 31) // 32 * 4].any()
 
     d_rec = torch.empty_like(d_img)
     ctx.recover(d_enc, meta, d_rec, k1)
     rec = d_rec.cpu().numpy()
-    rec_o = O.emr_recover(Iem_o, mo.b, k1)
+    rec_o = rec_f.result() if threads else O.emr_recover(Iem_o, mo.b, k1, nonce=nonce)
+    if pool:
+        pool.shutdown()
     mism = np.argwhere(rec != rec_o)
     assert mism.size == 0, f"recover mismatch at {mism[:5].tolist()} of {len(mism)}"
     assert np.array_equal(rec >> 1, I >> 1)
@@ -96,6 +108,39 @@ def test_emr_per_pixel_path_matches_oracle(R, ctx, shape):
     M, N = shape
     I = _image(M * 5 + N, M, N, sigma=8.0)
     _roundtrip(R, ctx, I, 3 + M, 4 + N)
+
+
+@pytest.mark.parametrize("family", [0, 1], ids=["philox", "chacha20"])
+@pytest.mark.parametrize("shape", [(256, 320), (33, 47), (1024, 512)], ids=lambda s: f"{s[0]}x{s[1]}")
+def test_emr_nonce_matches_oracle(R, shape, family):
+    """A per-image keystream nonce (Sec. III-A, secret key generation): the
+    content owner's nonce is recorded in the meta and every role uses it for
+    the image and message streams, tiled, per-pixel and in steps, under both
+    keystream families."""
+    c = R.Context(0)
+    c.set_option(R.OPT_KEYSTREAM, family)
+    M, N = shape
+    I = _image(M + 3 * N, M, N)
+    with O.keystream_family(family):
+        _roundtrip(R, c, I, 41 + M, 42 + N, nonce=0xFEDCBA9876543210 + M)
+
+
+def test_nonce_changes_every_stream(R, ctx):
+    """One image, one key, two nonces: the encryptions differ above the LSB
+    plane almost everywhere (no shared keystream or rotation), and one
+    nonce reproduces itself."""
+    I = _image(7, 256, 256)
+    d = _dev(I)
+    outs = []
+    for z in (1, 2, 1):
+        e = torch.empty_like(d)
+        m = R.new_meta()
+        ctx.encrypt(d, e, 99, m, nonce=z)
+        torch.cuda.synchronize()
+        outs.append(e.cpu().numpy())
+    assert np.array_equal(outs[0], outs[2])
+    x = (outs[0] ^ outs[1]) >> 1
+    assert np.count_nonzero(x) > 0.9 * x.size
 
 
 @pytest.mark.parametrize("frac", [0.0, 0.01, 0.37, 0.999])
@@ -140,7 +185,28 @@ def test_emr_8192_full_image(R, ctx):
     _roundtrip(R, ctx, I, 303, 404, frac=0.77)
 
 
-@pytest.mark.parametrize("shape", [(8192, 16384), (12288, 12288), (16384, 16384)])
+def test_emr_16384_full_image(R, ctx):
+    """The large-image workload's larger size, 16384 x 16384: the only size
+    with a level-14 block (a quarter turn of the whole image, Sec. III-A
+    rotation), 65,536 tiles whose workgroups each take several quad segments
+    in a row, and a 91-MB payload; every role against the oracle pixel for
+    pixel, with a non-zero nonce.  The oracle's recovery runs beside its
+    embedding (about a minute of oracle time in all)."""
+    print("[large] 16384x16384 oracle parity", flush=True)
+    I = inputs.make_band_image(77 + 16384, 16384, 16384, 8, 3.0, "cpu").numpy()
+    _roundtrip(R, ctx, I, 909, 910, frac=1.0, nonce=16384, threads=True)
+
+
+def test_emr_tile_map_limit_takes_per_pixel_path(R, ctx):
+    """64 x 1,048,640: 16,385 tiles along each row, one more than the tile
+    map's 14-bit tile coordinates hold.  Such an image takes the per-pixel
+    path and matches the oracle in every role."""
+    print("[limit] 64x1048640 oracle parity", flush=True)
+    I = inputs.make_band_image(5, 64, 1048640, 8, 3.0, "cpu").numpy()
+    _roundtrip(R, ctx, I, 31, 32, frac=0.5, nonce=3)
+
+
+@pytest.mark.parametrize("shape", [(8192, 16384), (12288, 12288)])
 def test_emr_large_images_roundtrip(R, ctx, shape):
     """Images above 8192 in a dimension, where every workgroup of the tile
     kernels takes several quad segments in a row.  Sizes the oracle cannot
@@ -377,14 +443,16 @@ def test_batched_plan_uneven_sizes_matches_oracle(R, hide_mode):
     metas = R.new_meta(n)
     k1s = [1000 + i for i in range(n)]
     k2s = [2000 + i for i in range(n)]
-    jobs = R.make_jobs(d_in, d_enc, None, [metas[i] for i in range(n)], k1s, None, shapes)
+    nonces = [0] + [(0x9E3779B97F4A7C15 * (i + 1)) % (1 << 64) for i in range(1, n)]   # per-image nonces
+    jobs = R.make_jobs(d_in, d_enc, None, [metas[i] for i in range(n)], k1s, None, shapes, nonces=nonces)
     enc_plan = R.Plan(ctx, R.OP_ENCRYPT, jobs)
     enc_plan.run()
     torch.cuda.synchronize()
     ms = R.read_meta(metas)
-    oracle = [O.emr_encrypt(I, k) for I, k in zip(imgs, k1s)]
+    oracle = [O.emr_encrypt(I, k, nonce=z) for I, k, z in zip(imgs, k1s, nonces)]
     for i in range(n):
         assert ms[i].b == oracle[i][1].b and ms[i].capacity_bits == oracle[i][1].capacity_bits
+        assert ms[i].nonce == nonces[i]
         assert np.array_equal(d_enc[i].cpu().numpy(), oracle[i][0]), f"image {i} {shapes[i]}"
     caps = [m.capacity_bits for m in ms]
     msgs = [inputs.make_payload(k, c).numpy() for k, c in zip(k2s, caps)]
@@ -398,11 +466,11 @@ def test_batched_plan_uneven_sizes_matches_oracle(R, hide_mode):
     rec.run()
     torch.cuda.synchronize()
     for i in range(n):
-        Iem_o = O.emr_embed(oracle[i][0], oracle[i][1].b, msgs[i], caps[i], k2s[i])
+        Iem_o = O.emr_embed(oracle[i][0], oracle[i][1].b, msgs[i], caps[i], k2s[i], nonce=nonces[i])
         assert np.array_equal(d_enc[i].cpu().numpy(), Iem_o)
         nb = (caps[i] + 7) // 8
         assert np.array_equal(d_got[i].cpu().numpy()[:nb], msgs[i])
-        assert np.array_equal(d_rec[i].cpu().numpy(), O.emr_recover(Iem_o, oracle[i][1].b, k1s[i]))
+        assert np.array_equal(d_rec[i].cpu().numpy(), O.emr_recover(Iem_o, oracle[i][1].b, k1s[i], nonce=nonces[i]))
     # replays give the same bytes (recover and extract are pure functions of I_e')
     first = [x.clone() for x in d_rec]
     for _ in range(2):

@@ -40,7 +40,7 @@ def _alone(R, wl, i):
         meta = R.new_meta()
         msg = torch.zeros(R.msg_bytes(nbits), dtype=torch.uint8, device="cuda")
         msg[: wl.payloads[i].numel()] = wl.payloads[i]
-        ctx.encrypt(wl.images[i], enc, int(wl.k1[i]), meta)
+        ctx.encrypt(wl.images[i], enc, int(wl.k1[i]), meta, nonce=int(wl.seed[i]))
         ctx.embed(enc, meta, msg, nbits, int(wl.k2[i]))
         torch.cuda.synchronize()
         return {"marked": enc.cpu().numpy(), "meta": meta.cpu().numpy()}
@@ -119,18 +119,18 @@ def test_served_matches_oracle(S, R, workload):
     checked = 0
     for i in range(n):
         I = wl.images[i].cpu().numpy()
-        k1, k2, nb = int(wl.k1[i]), int(wl.k2[i]), int(wl.nbits[i])
+        k1, k2, nb, nz = int(wl.k1[i]), int(wl.k2[i]), int(wl.nbits[i]), int(wl.seed[i])
         pay = wl.payloads[i].cpu().numpy()
         if wl.kind[i] == 0:
-            Ie, mo = O.emr_encrypt(I, k1)
+            Ie, mo = O.emr_encrypt(I, k1, nonce=nz)
             assert mo.capacity_bits == nb
-            marked = O.emr_embed(Ie, mo.b, pay, nb, k2)
+            marked = O.emr_embed(Ie, mo.b, pay, nb, k2, nonce=nz)
             assert np.array_equal(got[i]["marked"], marked), i
         else:
             orig = wl.originals[i].cpu().numpy()
-            _, mo = O.emr_encrypt(orig, k1)
+            _, mo = O.emr_encrypt(orig, k1, nonce=nz)
             assert np.array_equal(_bits(got[i]["payload"], nb), _bits(pay, nb)), i
-            assert np.array_equal(got[i]["recovered"], O.emr_recover(I, mo.b, k1)), i
+            assert np.array_equal(got[i]["recovered"], O.emr_recover(I, mo.b, k1, nonce=nz)), i
             assert np.all((got[i]["recovered"] ^ orig) <= 1)
         checked += 1
     assert checked == n
@@ -149,17 +149,17 @@ def test_served_chacha_matches_oracle(S, R):
     with O.keystream_family(O.KEYSTREAM_CHACHA20):
         for i in range(n):
             I = wl.images[i].cpu().numpy()
-            k1, k2, nb = int(wl.k1[i]), int(wl.k2[i]), int(wl.nbits[i])
+            k1, k2, nb, nz = int(wl.k1[i]), int(wl.k2[i]), int(wl.nbits[i]), int(wl.seed[i])
             pay = wl.payloads[i].cpu().numpy()
             if wl.kind[i] == 0:
-                Ie, mo = O.emr_encrypt(I, k1)
+                Ie, mo = O.emr_encrypt(I, k1, nonce=nz)
                 assert mo.capacity_bits == nb
-                assert np.array_equal(got[i]["marked"], O.emr_embed(Ie, mo.b, pay, nb, k2)), i
+                assert np.array_equal(got[i]["marked"], O.emr_embed(Ie, mo.b, pay, nb, k2, nonce=nz)), i
             else:
                 orig = wl.originals[i].cpu().numpy()
-                _, mo = O.emr_encrypt(orig, k1)
+                _, mo = O.emr_encrypt(orig, k1, nonce=nz)
                 assert np.array_equal(_bits(got[i]["payload"], nb), _bits(pay, nb)), i
-                assert np.array_equal(got[i]["recovered"], O.emr_recover(I, mo.b, k1)), i
+                assert np.array_equal(got[i]["recovered"], O.emr_recover(I, mo.b, k1, nonce=nz)), i
 
 
 def test_request_larger_than_pool_is_rejected(S, workload):

@@ -62,7 +62,7 @@ def test_strerror_and_version(R):
 def test_host_argument_errors_need_no_gpu(R):
     lib = R.load_library()
     assert lib.rdhei_ctx_create(None, 0) == R.EINVAL
-    assert lib.rdhei_encrypt(None, None, None, 4, 4, 1, 0, None, None) == R.EINVAL
+    assert lib.rdhei_encrypt(None, None, None, 4, 4, 1, 0, 0, None, None) == R.EINVAL
     assert lib.rdhei_plan_run(None, None) == R.EINVAL
 
 
