@@ -33,6 +33,45 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def host_cores() -> int:
+    """Host cores this process may run on: the affinity set, capped by a
+    cgroup CPU quota when one is set."""
+    n = os.cpu_count() or 1
+    try:
+        n = min(n, len(os.sched_getaffinity(0)))
+    except (AttributeError, OSError):
+        pass
+    try:
+        quota, period = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if quota != "max":
+            n = min(n, max(1, -(-int(quota) // int(period))))
+    except (OSError, ValueError):
+        pass
+    return n
+
+
+def run_parity(tasks, threads):
+    """Oracle comparisons on host threads (the oracle's C calls release the
+    interpreter lock).  tasks: (group, pixels, fn) with fn() -> bool.  Returns
+    per-group {checked, ok} and the wall time and pixels of the whole pass."""
+    from concurrent.futures import ThreadPoolExecutor
+    groups = {}
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        futs = [(g, px, ex.submit(fn)) for g, px, fn in tasks]
+        for k, (g, px, f) in enumerate(futs):
+            ok = bool(f.result())
+            r = groups.setdefault(g, {"checked": 0, "ok": True, "pixels": 0})
+            r["checked"] += 1
+            r["ok"] = r["ok"] and ok
+            r["pixels"] += px
+            if not ok:
+                log(f"[parity] {g}: task {k} differs from the oracle")
+            if (k + 1) % 2000 == 0:
+                log(f"[parity] {k + 1}/{len(futs)} compared")
+    return groups, time.perf_counter() - t0
+
+
 def measured_traffic(stage: str, px: int):
     """HBM bytes per launch of a stage from the committed rocprofv3 counter
     summary, or None when the kernel sources changed since it was taken."""
@@ -60,10 +99,11 @@ def parse():
     ap.add_argument("--mode", choices=["graph", "eager"], default="graph")
     ap.add_argument("--per-image-steps", type=int, default=1, help="steps timed with per-image launches (0: skip)")
     ap.add_argument("--stage-reps", type=int, default=5)
-    ap.add_argument("--check", type=int, default=6, help="at least this many images of the CPU oracle leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="bounded oracle timing (0: skip)")
     ap.add_argument("--cpu-threads", type=int, default=0,
-                    help="host threads of the all-core oracle figure (0: up to 16; 1: skip it)")
+                    help="host threads of the all-core oracle parity pass (0: every core this process may use)")
+    ap.add_argument("--parity", type=int, default=1,
+                    help="1: compare every image of every batch leg (and the large images) with the oracle")
     ap.add_argument("--max-grid", type=int, default=0)
     ap.add_argument("--autotune", type=int, default=3, help="timed runs per candidate launch shape (0: defaults)")
     ap.add_argument("--serve-requests", type=int, default=5000, help="serving-loop requests (0: skip)")
@@ -134,7 +174,7 @@ def serve_bench(args):
             "loads": loads, "per_request": pr}
 
 
-def lmr_bench(args):
+def lmr_bench(args, tasks=None):
     """LMR-RDHEI lossless path: 512x512 images (sigma 1/3/8 cycling, 8
     sinusoids), the four roles as batched calls with the map coder on host
     threads (timed apart from the device stages), payload at capacity; every
@@ -151,7 +191,7 @@ def lmr_bench(args):
     imgs = torch.empty(B, S, S, dtype=torch.uint8, device=dev)
     for i in range(B):
         imgs[i].copy_(inputs.make_image(50_000 + i, S, S, 8, (1.0, 3.0, 8.0)[i % 3], dev))
-    def run(level):
+    def run(level, collect=None):
         enc = torch.zeros_like(imgs)
         rec = torch.zeros_like(imgs)
         metas = rdhei.new_meta(B)
@@ -160,11 +200,14 @@ def lmr_bench(args):
         shapes = [(S, S)] * B
         k1 = [inputs.key_pair(50_000 + i)[0] for i in range(B)]
         k2 = [inputs.key_pair(50_000 + i)[1] for i in range(B)]
+        nonces = [50_000 + i for i in range(B)]
         mp = [metas[i] for i in range(B)]
         torch.cuda.synchronize()
         times = {}
         times["encrypt"] = ctx.lmr_batch(rdhei.OP_ENCRYPT, rdhei.make_jobs(list(imgs), list(enc), None, mp, k1, None, shapes,
-                                                                          method=rdhei.LMR), args.lmr_threads)
+                                                                          method=rdhei.LMR, nonces=nonces),
+                                         args.lmr_threads)
+        enc_pre = enc.cpu().numpy() if collect is not None else None
         meta = rdhei.read_meta_array(metas)
         good = meta["status"] == 0
         caps = np.where(good, meta["capacity_bits"], 0).astype(np.int64)
@@ -204,11 +247,31 @@ def lmr_bench(args):
         log(f"[lmr] blocks from 2^{level}: good {out['good']} bad {out['bad']} exact={exact} payload_ok={bits_ok} "
             f"DER {out['der_bpp']}; "
             f"device {dev_s:.3f}s coder {cod_s:.3f}s total {tot_s:.3f}s")
+        if collect is not None:
+            # every image of the batch against the oracle's LMR roles (Sec. III-B)
+            import oracle as O
+            H = {"I": imgs.cpu().numpy(), "Ie": enc_pre, "marked": enc.cpu().numpy(), "rec": rec.cpu().numpy(),
+                 "pay": payload.cpu().numpy(), "got": got.cpu().numpy()}
+
+            def check(i):
+                Ie_o, mo, st = O.lmr_encode(H["I"][i], k1[i], level, nonce=nonces[i])
+                if Ie_o is None:
+                    return int(meta["status"][i]) == rdhei.ENOFIT
+                c, o = int(caps[i]), int(offs[i])
+                if (int(meta["b"][i]), c) != (mo.b, int(mo.capacity_bits)) or not np.array_equal(H["Ie"][i], Ie_o):
+                    return False
+                eta, lm = O.lmr_decompress(st, S, S)
+                W = O.lmr_embed(Ie_o, mo.b, lm, H["pay"][o:o + (c + 7) // 8], c, k2[i], nonce=nonces[i])
+                g_o = O.lmr_extract(W, mo.b, lm, c, k2[i], nonce=nonces[i])
+                r_o = O.lmr_recover(W, mo.b, level, k1[i], lm, eta, nonce=nonces[i])
+                return (np.array_equal(H["marked"][i], W) and np.array_equal(H["got"][o:o + len(g_o)], g_o)
+                        and np.array_equal(H["rec"][i], r_o) and np.array_equal(r_o, H["I"][i]))
+            collect.extend(("lmr", S * S, (lambda i=i: check(i))) for i in range(B))
         del enc, rec, payload, got
         torch.cuda.empty_cache()
         return out
 
-    out = run(4)
+    out = run(4, tasks)
     # Table LMR_block_size: the same batch with rotation blocks from 2^1, 2^2, 2^3 (and 2^4 above)
     out["block_sizes"] = []
     for level in (1, 2, 3, 4):
@@ -300,7 +363,7 @@ def single_bench(args):
             "mpx_per_s": round(S * S / (best * 1e-3) / 1e6, 1), "identical_runs": bool(same)}
 
 
-def large_bench(args):
+def large_bench(args, tasks=None):
     """Single large images (sigma 3, 8 sinusoids, drawn in row bands) through
     encrypt / embed (payload at capacity) / extract / recover, each stage timed
     with HIP events on its stream; checked at full size: the extracted bits
@@ -321,17 +384,19 @@ def large_bench(args):
         rec = torch.empty_like(img)
         meta = rdhei.new_meta()
         k1, k2 = inputs.key_pair(seed)
-        ctx.encrypt(img, enc, k1, meta)
+        nonce = seed
+        ctx.encrypt(img, enc, k1, meta, nonce=nonce)
         torch.cuda.synchronize()
         m = rdhei.read_meta(meta)
         cap = int(m.capacity_bits)
+        enc_pre = enc.cpu().numpy() if tasks is not None else None
         nbytes = rdhei.msg_bytes(cap)
         g = torch.Generator(device=dev)
         g.manual_seed(seed)
         msg = torch.randint(0, 256, (nbytes,), generator=g, device=dev, dtype=torch.int32).to(torch.uint8)
         got = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
         ops = {
-            "encrypt": lambda: ctx.encrypt(img, enc, k1, meta),
+            "encrypt": lambda: ctx.encrypt(img, enc, k1, meta, nonce=nonce),
             "embed": lambda: ctx.embed(enc, meta, msg, cap, k2),
             "extract": lambda: ctx.extract(enc, meta, got, cap, k2),
             "recover": lambda: ctx.recover(enc, meta, rec, k1),
@@ -371,6 +436,30 @@ def large_bench(args):
         log(f"[large] {side}: {row['ms']} -> {row['mpx_per_s']} Mpx/s, extract_ok={bits_ok}, "
             f"lsb_only={lsb_only}, PSNR {row['psnr_db']} dB")
         out.append(row)
+        if tasks is not None:
+            # the whole image against the oracle, pixel for pixel (Sec. III-A
+            # encoding, data hiding, decoding with K2 and with K1), as two
+            # host tasks: encrypt -> embed -> extract, and recovery of the GPU's
+            # marked image (which the first task checks against the oracle's)
+            import oracle as O
+            H = {"I": img.cpu().numpy(), "Ie": enc_pre, "marked": enc.cpu().numpy(), "rec": rec.cpu().numpy(),
+                 "msg": msg.cpu().numpy()[:(cap + 7) // 8], "got": got.cpu().numpy()}
+
+            def fwd(H=H, k1=k1, k2=k2, nonce=nonce, b=int(m.b), cap=cap):
+                Ie_o, mo = O.emr_encrypt(H["I"], k1, nonce=nonce)
+                if (mo.b, int(mo.capacity_bits)) != (b, cap) or not np.array_equal(H["Ie"], Ie_o):
+                    return False
+                W = O.emr_embed(Ie_o, mo.b, H["msg"], cap, k2, nonce=nonce)
+                del Ie_o
+                if not np.array_equal(H["marked"], W):
+                    return False
+                g_o = O.emr_extract(W, mo.b, cap, k2, nonce=nonce)
+                return np.array_equal(H["got"][:len(g_o)], g_o)
+
+            def back(H=H, k1=k1, nonce=nonce, b=int(m.b)):
+                return np.array_equal(H["rec"], O.emr_recover(H["marked"], b, k1, nonce=nonce))
+            tasks.append((f"large{side}", px, fwd))
+            tasks.append((f"large{side}", 0, back))
         del img, enc, rec, msg, got
         torch.cuda.empty_cache()
     return out
@@ -492,9 +581,10 @@ def main():
     shapes = [(S, S)] * B
     k1 = [inputs.key_pair(i)[0] for i in range(B)]
     k2 = [inputs.key_pair(i)[1] for i in range(B)]
+    nonces = list(range(B))          # per-image keystream nonce = the image's seed
     mptr = [metas[i] for i in range(B)]
     flags = rdhei.PLAN_GRAPH if args.mode == "graph" else rdhei.PLAN_EAGER
-    enc_jobs = rdhei.make_jobs(list(imgs), list(enc), None, mptr, k1, None, shapes)
+    enc_jobs = rdhei.make_jobs(list(imgs), list(enc), None, mptr, k1, None, shapes, nonces=nonces)
     enc_plan = rdhei.Plan(ctx, rdhei.OP_ENCRYPT, enc_jobs, flags)
     enc_plan.run()
     torch.cuda.synchronize()
@@ -528,11 +618,12 @@ def main():
         cut = np.linspace(0, B, args.pipes + 1).astype(int)
         for a, b in zip(cut[:-1], cut[1:]):
             sl = slice(int(a), int(b))
-            sh, mp, c1, c2, cp = shapes[sl], mptr[sl], k1[sl], k2[sl], caps[sl]
+            sh, mp, c1, c2, cp, nz = shapes[sl], mptr[sl], k1[sl], k2[sl], caps[sl], nonces[sl]
             po, px_ = [base_p + int(o) for o in offs[sl]], [base_x + int(o) for o in offs[sl]]
             pipes.append({
                 "encrypt": rdhei.Plan(ctx, rdhei.OP_ENCRYPT,
-                                      rdhei.make_jobs(list(imgs[sl]), list(enc[sl]), None, mp, c1, None, sh), flags),
+                                      rdhei.make_jobs(list(imgs[sl]), list(enc[sl]), None, mp, c1, None, sh, nonces=nz),
+                                      flags),
                 "embed": rdhei.Plan(ctx, rdhei.OP_EMBED, rdhei.make_jobs(None, list(enc[sl]), po, mp, c2, cp, sh), flags),
                 "extract": rdhei.Plan(ctx, rdhei.OP_EXTRACT, rdhei.make_jobs(list(enc[sl]), None, px_, mp, c2, cp, sh),
                                       flags),
@@ -754,86 +845,64 @@ def main():
             f"per image; {t_ms:.3f} ms ({tile_b['read_GBps']} GB/s)")
         del tb, tcap
 
-    # ---- CPU oracle on a bounded sample of the same workload ----
-    # Full round trips of the oracle, single thread, on images spread over the
-    # batch with their own keys and payloads; only the oracle calls are timed.
-    # The same round trips check the GPU's outputs of those images (marked
-    # image, extracted bits, recovered image), outside the timed part.
+    # ---- CPU oracle: bounded single-thread timing, then every image ----
+    # cpu_baseline: full round trips of the oracle, one thread, on images
+    # spread over the batch with their own keys, nonces and payloads, for
+    # about --cpu-seconds; only the oracle calls are timed.
+    # parity: after a fresh batched step, every image of the batch (marked
+    # image, extracted bits, recovered image, capacity) against the oracle on
+    # all host cores; that pass also gives the all-core oracle throughput.
     cpu = cpu_all = None
     parity = {"checked": 0, "ok": True}
-    if args.cpu_seconds > 0 or args.check > 0:
+    tasks_late = [] if args.parity else None      # LMR batch and large images, checked at the end
+    threads = args.cpu_threads or host_cores()
+    if args.cpu_seconds > 0 or args.parity:
         import oracle as O
         step()                       # the outputs checked are the batched plans'
         torch.cuda.synchronize()
-        stride = next(k for k in range(max(1, B // 7), B + 1) if math.gcd(k, B) == 1) if B > 1 else 1
-        n, el = 0, 0.0
-        while (args.cpu_seconds > 0 and el < args.cpu_seconds) or n < args.check:
-            i = (n * stride) % B
-            I = imgs[i].cpu().numpy()
-            cap = int(caps[i])
-            msg = payload[int(offs[i]):int(offs[i]) + (cap + 7) // 8].cpu().numpy()
-            t0 = time.perf_counter()
-            Ie_o, mo = O.emr_encrypt(I, k1[i])
-            Iem_o = O.emr_embed(Ie_o, mo.b, msg, mo.capacity_bits, k2[i])
-            got_o = O.emr_extract(Iem_o, mo.b, mo.capacity_bits, k2[i])
-            rec_o = O.emr_recover(Iem_o, mo.b, k1[i])
-            el += time.perf_counter() - t0
-            got = extracted[int(offs[i]):int(offs[i]) + (cap + 7) // 8].cpu().numpy()
-            ok = (mo.capacity_bits == cap and np.array_equal(enc[i].cpu().numpy(), Iem_o)
-                  and np.array_equal(got, got_o) and np.array_equal(rec[i].cpu().numpy(), rec_o))
-            parity["checked"] += 1
-            parity["ok"] = parity["ok"] and bool(ok)
-            n += 1
-        log(f"[bench] oracle round trips on {n} images, all equal to the GPU's: {parity['ok']}")
+        Hb = {"I": imgs.cpu().numpy(), "marked": enc.cpu().numpy(), "rec": rec.cpu().numpy(),
+              "pay": payload.cpu().numpy(), "got": extracted.cpu().numpy()}
+
+        def round_trip(i):
+            c, o = int(caps[i]), int(offs[i])
+            Ie_o, mo = O.emr_encrypt(Hb["I"][i], k1[i], nonce=nonces[i])
+            Iem_o = O.emr_embed(Ie_o, mo.b, Hb["pay"][o:o + (c + 7) // 8], mo.capacity_bits, k2[i], nonce=nonces[i])
+            got_o = O.emr_extract(Iem_o, mo.b, mo.capacity_bits, k2[i], nonce=nonces[i])
+            rec_o = O.emr_recover(Iem_o, mo.b, k1[i], nonce=nonces[i])
+            return (int(mo.capacity_bits) == c and np.array_equal(Hb["marked"][i], Iem_o)
+                    and np.array_equal(Hb["got"][o:o + len(got_o)], got_o) and np.array_equal(Hb["rec"][i], rec_o))
+
         if args.cpu_seconds > 0:
+            stride = next(k for k in range(max(1, B // 7), B + 1) if math.gcd(k, B) == 1) if B > 1 else 1
+            n, el, ok1 = 0, 0.0, True
+            while el < args.cpu_seconds and n < B:
+                t0 = time.perf_counter()
+                ok1 = round_trip((n * stride) % B) and ok1
+                el += time.perf_counter() - t0
+                n += 1
             cpu = {"value": round(n * MN / el / 1e6, 3), "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
-                   "sample": f"{n} images spread over the batch ({S}x{S}), full round trip, single thread, "
-                             f"{el:.1f}s of oracle time; the same round trips checked the GPU's outputs"}
+                   "sample": f"{n} images spread over the batch ({S}x{S}), full round trip (encrypt, embed, extract, "
+                             f"recover), single thread, {el:.1f}s of oracle time; all equal to the GPU's: {ok1}"}
             log(f"[bench] cpu oracle: {cpu['value']} Mpx/s over {n} images")
-        if args.cpu_seconds > 0 and args.cpu_threads != 1:
-            # the same oracle on every host thread at once (its C calls release
-            # the interpreter lock), images taken in the same spread order
-            import threading
-            from concurrent.futures import ThreadPoolExecutor
-            nthr = args.cpu_threads or min(16, os.cpu_count() or 1)
-            host = []
-            for k in range(min(n, B)):
-                i = (k * stride) % B
-                c = int(caps[i])
-                host.append((imgs[i].cpu().numpy(), i, payload[int(offs[i]):int(offs[i]) + (c + 7) // 8].cpu().numpy()))
-            lock, box = threading.Lock(), {"next": 0, "done": 0}
-            stop = time.perf_counter() + args.cpu_seconds / 2
-
-            def worker():
-                while time.perf_counter() < stop:
-                    with lock:
-                        k = box["next"]
-                        box["next"] += 1
-                    I, i, m = host[k % len(host)]
-                    Ie_o, mo = O.emr_encrypt(I, k1[i])
-                    Iem_o = O.emr_embed(Ie_o, mo.b, m, mo.capacity_bits, k2[i])
-                    O.emr_extract(Iem_o, mo.b, mo.capacity_bits, k2[i])
-                    O.emr_recover(Iem_o, mo.b, k1[i])
-                    with lock:
-                        box["done"] += 1
-
-            t0 = time.perf_counter()
-            with ThreadPoolExecutor(max_workers=nthr) as ex:
-                for f in [ex.submit(worker) for _ in range(nthr)]:
-                    f.result()
-            wall = time.perf_counter() - t0
-            cpu_all = {"value": round(box["done"] * MN / wall / 1e6, 3), "unit": "Mpixel/s", "cores": nthr,
-                       "kind": "oracle", "sample": f"{box['done']} full round trips of the same images, {nthr} "
-                                                   f"threads, {wall:.1f}s wall"}
-            log(f"[bench] cpu oracle on {nthr} threads: {cpu_all['value']} Mpx/s")
+        if args.parity:
+            log(f"[parity] {B} images against the oracle on {threads} host threads")
+            res, wall = run_parity([("batch", MN, (lambda i=i: round_trip(i))) for i in range(B)], threads)
+            parity = {"checked": res["batch"]["checked"], "ok": res["batch"]["ok"], "threads": threads,
+                      "wall_s": round(wall, 2)}
+            cpu_all = {"value": round(B * MN / wall / 1e6, 3), "unit": "Mpixel/s", "cores": threads,
+                       "host_cpu_count": os.cpu_count(), "kind": "oracle",
+                       "sample": f"all {B} images of the batch, full round trips compared with the GPU's outputs, "
+                                 f"{threads} threads (every core this process may use), {wall:.1f}s wall"}
+            log(f"[parity] batch: {parity}; oracle on {threads} threads: {cpu_all['value']} Mpx/s")
+        del Hb
 
     lmr = None
     if args.lmr_images > 0:
-        lmr = lmr_bench(args)
+        lmr = lmr_bench(args, tasks_late)
 
     large = None
     if args.large_sides:
-        large = large_bench(args)
+        large = large_bench(args, tasks_late)
     single = single_bench(args) if args.single_reps > 0 else None
     keystream = keystream_bench(args) if args.keystream_images > 0 else None
 
@@ -851,6 +920,18 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {nb} bytes done")
         del src, dst
+
+    if tasks_late:
+        # the LMR batch and the large images against the oracle, after every timed leg
+        log(f"[parity] LMR batch and large images: {len(tasks_late)} oracle tasks on {threads} threads")
+        res, wall = run_parity(tasks_late, threads)
+        if lmr is not None and "lmr" in res:
+            lmr["parity"] = {"checked": res["lmr"]["checked"], "ok": res["lmr"]["ok"],
+                             "method_blocks_from": 4}
+        for row in large or []:
+            r = res.get(f"large{row['side']}")
+            row["oracle_equal"] = bool(r and r["ok"])
+        log(f"[parity] {({k: (v['checked'], v['ok']) for k, v in res.items()})} in {wall:.1f}s")
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
@@ -878,7 +959,9 @@ def main():
         "keystream": keystream,
     }
     print(json.dumps(out), flush=True)
-    if (not parity["ok"] or (large and not all(r["extract_ok"] and r["lsb_only"] for r in large))
+    if (not parity["ok"] or (large and not all(r["extract_ok"] and r["lsb_only"] and r.get("oracle_equal", True)
+                                               for r in large))
+            or (lmr and not lmr.get("parity", {}).get("ok", True))
             or (single and not single["identical_runs"])
             or (keystream and not all(keystream[f]["extract_ok"] and keystream[f]["lsb_only"]
                                       for f in ("philox", "chacha20")))
