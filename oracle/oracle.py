@@ -80,6 +80,17 @@ def _load():
     lib.or_lmr_decompress.argtypes = [u8p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, u8p, u8p]
     lib.or_lmr_encode.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32, u8p,
                                   ctypes.c_void_p, u8p, ctypes.POINTER(ctypes.c_int64)]
+    lib.or_demr_tile_b.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, u8p, i64p]
+    lib.or_demr_encrypt.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64, u8p, u8p,
+                                    ctypes.c_void_p]
+    lib.or_demr_encrypt.restype = ctypes.c_int
+    lib.or_demr_embed.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, u8p, u8p, ctypes.c_int64, ctypes.c_uint64,
+                                  ctypes.c_uint64]
+    lib.or_demr_embed.restype = ctypes.c_int64
+    lib.or_demr_extract.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, u8p, u8p, ctypes.c_int64, ctypes.c_uint64,
+                                    ctypes.c_uint64]
+    lib.or_demr_extract.restype = ctypes.c_int64
+    lib.or_demr_recover.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, u8p, ctypes.c_uint64, ctypes.c_uint64, u8p]
     _lib = lib
     return lib
 
@@ -327,6 +338,62 @@ def lmr_encode(I, k1: int, min_level: int = 4, nonce: int = 0):
     if rc != 0:
         return None, meta, None
     return Ie, meta, stream[: bits.value // 8].copy()
+
+
+# ---- dynamic b: one b per 64x64 tile (the conclusion's future work; reading in rdhei_oracle.c)
+DEMR_TILE = 64
+
+
+def demr_tile_b(I):
+    """(b_t as a (M/64, N/64) uint8 array, Z_b(t) as (M/64, N/64, 6) for b = 2..7)."""
+    I = _img(I)
+    M, N = I.shape
+    assert M % DEMR_TILE == 0 and N % DEMR_TILE == 0
+    tb = np.zeros((M // DEMR_TILE, N // DEMR_TILE), dtype=np.uint8)
+    Z = np.zeros((M // DEMR_TILE, N // DEMR_TILE, 6), dtype=np.int64)
+    _load().or_demr_tile_b(_u8(I), M, N, _u8(tb), Z.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    return tb, Z
+
+
+def demr_encrypt(I, k1: int, nonce: int = 0):
+    """(I_e, meta with b = 0, b table in encrypted-tile order)."""
+    I = _img(I)
+    M, N = I.shape
+    assert M % DEMR_TILE == 0 and N % DEMR_TILE == 0
+    Ie = np.zeros_like(I)
+    bt = np.zeros((M // DEMR_TILE, N // DEMR_TILE), dtype=np.uint8)
+    m = _OrMeta()
+    rc = _load().or_demr_encrypt(_u8(I), M, N, k1, nonce, _u8(Ie), _u8(bt), ctypes.byref(m))
+    assert rc == 0, "rotated b map not constant on an encrypted tile"
+    return Ie, OracleMeta(m.b, m.min_level, m.max_level, m.redundant, m.capacity_bits), bt
+
+
+def demr_embed(Ie, btab, msg, nbits: int, k2: int, nonce: int = 0) -> np.ndarray:
+    X = _img(Ie).copy()
+    bt = np.ascontiguousarray(btab, dtype=np.uint8)
+    msg = np.ascontiguousarray(msg, dtype=np.uint8)
+    if msg.size == 0:
+        msg = _msg_buf(0)
+    r = _load().or_demr_embed(_u8(X), X.shape[0], X.shape[1], _u8(bt), _u8(msg), nbits, k2, nonce)
+    if r < 0:
+        raise ValueError("message longer than capacity")
+    return X
+
+
+def demr_extract(Ie, btab, nbits: int, k2: int, nonce: int = 0) -> np.ndarray:
+    X = _img(Ie)
+    bt = np.ascontiguousarray(btab, dtype=np.uint8)
+    out = _msg_buf(nbits)
+    _load().or_demr_extract(_u8(X), X.shape[0], X.shape[1], _u8(bt), _u8(out), nbits, k2, nonce)
+    return out[:(nbits + 7) // 8]
+
+
+def demr_recover(Ie, btab, k1: int, nonce: int = 0) -> np.ndarray:
+    X = _img(Ie)
+    bt = np.ascontiguousarray(btab, dtype=np.uint8)
+    out = np.zeros_like(X)
+    _load().or_demr_recover(_u8(X), X.shape[0], X.shape[1], _u8(bt), k1, nonce, _u8(out))
+    return out
 
 
 def psnr(a, b) -> float:

@@ -420,6 +420,187 @@ void or_emr_recover(const uint8_t *Ie, int32_t M, int32_t N, int b, uint64_t k1,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Dynamic b (Sec. V, future work).  The paper suggests tracing more         */
+/* redundant bits with a b that varies over the image and defines nothing    */
+/* further.  Reading: one b per 64 x 64 tile (sides multiples of 64).  A     */
+/* pixel (i, j), j >= 1, is redundant when its b_t MSBs equal those of its   */
+/* left neighbour (i, j-1), t its tile -- with one b for the whole image that */
+/* is exactly the set the Omega glide marks (Sec. III-A), here carried over   */
+/* tile borders.  b_t is chosen by the optimal-b rule on the tile's own      */
+/* counts.  Everything else is the EMR method: rotation, XOR, the map in the  */
+/* LSB plane, data hiding into the top b MSBs of redundant pixels, where b is */
+/* that of the pixel's tile.  The b table is side information in encrypted-  */
+/* tile order (the data hider has no K1 to follow tiles through the          */
+/* rotation).                                                                */
+/* ------------------------------------------------------------------------ */
+
+#define OR_TILE 64
+
+/* Z_b(t) for b = 2..7 (Z[6 t + b - 2], tiles row-major) by the left-neighbour
+ * rule, and b_t: the first b reaching the largest b * Z_b(t). */
+void or_demr_tile_b(const uint8_t *I, int32_t M, int32_t N, uint8_t *tile_b, int64_t *Z)
+{
+    int32_t tx_n = N / OR_TILE, ty_n = M / OR_TILE;
+    for (int32_t ty = 0; ty < ty_n; ++ty) {
+        for (int32_t tx = 0; tx < tx_n; ++tx) {
+            int64_t *z = Z + 6 * ((int64_t)ty * tx_n + tx);
+            for (int b = 2; b <= 7; ++b) {
+                int64_t n = 0;
+                for (int32_t i = ty * OR_TILE; i < (ty + 1) * OR_TILE; ++i)
+                    for (int32_t j = tx * OR_TILE; j < (tx + 1) * OR_TILE; ++j) {
+                        if (j == 0) continue;
+                        uint8_t v = I[(int64_t)i * N + j], w = I[(int64_t)i * N + j - 1];
+                        if ((v >> (8 - b)) == (w >> (8 - b))) ++n;
+                    }
+                z[b - 2] = n;
+            }
+            tile_b[(int64_t)ty * tx_n + tx] = (uint8_t)or_select_b(z, 2, 7);
+        }
+    }
+}
+
+/* Per-pixel b from a tile table (tiles row-major). */
+static void expand_tile_b(const uint8_t *tile_b, int32_t M, int32_t N, uint8_t *bmap)
+{
+    int32_t tx_n = N / OR_TILE;
+    for (int32_t i = 0; i < M; ++i)
+        for (int32_t j = 0; j < N; ++j)
+            bmap[(int64_t)i * N + j] = tile_b[(int64_t)(i / OR_TILE) * tx_n + j / OR_TILE];
+}
+
+/* Encoding with a b per tile: labels by the rule above, rotation of I, the
+ * map and the per-pixel b with K1's keystream, XOR, the map in the LSB plane.
+ * btab_enc receives the b table in encrypted-tile order (read from the
+ * rotated per-pixel b, which is constant on every encrypted tile because
+ * levels above 2^6 move whole tiles); returns -1 if it is not (never for
+ * sides that are multiples of 64). */
+int or_demr_encrypt(const uint8_t *I, int32_t M, int32_t N, uint64_t k1, uint64_t nonce, uint8_t *Ie,
+                    uint8_t *btab_enc, or_meta *meta)
+{
+    size_t MN = (size_t)M * (size_t)N;
+    int32_t tx_n = N / OR_TILE, ty_n = M / OR_TILE;
+    size_t T = (size_t)tx_n * (size_t)ty_n;
+    uint8_t *tb = (uint8_t *)malloc(T + 1);
+    int64_t *Z = (int64_t *)malloc(6 * T * sizeof(int64_t) + 8);
+    or_demr_tile_b(I, M, N, tb, Z);
+    int64_t red = 0, cap = 0;
+    for (size_t t = 0; t < T; ++t) {
+        red += Z[6 * t + tb[t] - 2];
+        cap += (int64_t)tb[t] * Z[6 * t + tb[t] - 2];
+    }
+    uint8_t *bmap = (uint8_t *)malloc(MN + 1);
+    expand_tile_b(tb, M, N, bmap);
+    uint8_t *l = (uint8_t *)malloc(MN + 1);
+    for (int32_t i = 0; i < M; ++i)
+        for (int32_t j = 0; j < N; ++j) {
+            int64_t p = (int64_t)i * N + j;
+            int sh = 8 - bmap[p];
+            l[p] = (uint8_t)(j == 0 || (I[p] >> sh) != (I[p - 1] >> sh));
+        }
+    uint8_t *s = (uint8_t *)malloc(MN + 1);
+    or_keystream(k1, nonce, 1, 0, MN, s);
+    uint8_t *Irot = (uint8_t *)malloc(MN + 1);
+    memcpy(Irot, I, MN);
+    or_rotate(Irot, M, N, s, 1, 0);
+    or_rotate(l, M, N, s, 1, 0);
+    or_rotate(bmap, M, N, s, 1, 0);
+    for (size_t p = 0; p < MN; ++p) Ie[p] = (uint8_t)(((s[p] ^ Irot[p]) & 0xFE) | (l[p] & 1));
+    int rc = 0;
+    for (int32_t ty = 0; ty < ty_n; ++ty)
+        for (int32_t tx = 0; tx < tx_n; ++tx) {
+            uint8_t v = bmap[(int64_t)ty * OR_TILE * N + (int64_t)tx * OR_TILE];
+            btab_enc[(int64_t)ty * tx_n + tx] = v;
+            for (int32_t i = ty * OR_TILE; i < (ty + 1) * OR_TILE; ++i)
+                for (int32_t j = tx * OR_TILE; j < (tx + 1) * OR_TILE; ++j)
+                    if (bmap[(int64_t)i * N + j] != v) rc = -1;
+        }
+    meta->b = 0;
+    meta->min_level = 1;
+    meta->max_level = or_max_level(M, N);
+    meta->redundant = red;
+    meta->capacity_bits = cap;
+    free(tb); free(Z); free(bmap); free(l); free(s); free(Irot);
+    return rc;
+}
+
+/* Data hiding / extraction with the b of each pixel's (encrypted) tile: the
+ * message, XORed with K2's stream, fills the top b bits of the pixels whose
+ * LSB is 0, raster order, most significant first (a running bit counter). */
+int64_t or_demr_embed(uint8_t *Ie, int32_t M, int32_t N, const uint8_t *btab_enc, const uint8_t *msg, int64_t nbits,
+                      uint64_t k2, uint64_t nonce)
+{
+    size_t MN = (size_t)M * (size_t)N;
+    uint8_t *bmap = (uint8_t *)malloc(MN + 1);
+    expand_tile_b(btab_enc, M, N, bmap);
+    int64_t cap = 0;
+    for (size_t p = 0; p < MN; ++p) cap += (Ie[p] & 1) == 0 ? bmap[p] : 0;
+    if (nbits > cap) { free(bmap); return -1; }
+    int64_t nbytes = (nbits + 7) / 8;
+    uint8_t *ks = (uint8_t *)malloc((size_t)nbytes + 1);
+    or_keystream(k2, nonce, 2, 0, (uint64_t)nbytes, ks);
+    int64_t t = 0;
+    for (size_t p = 0; p < MN && t < nbits; ++p) {
+        if ((Ie[p] & 1) != 0) continue;
+        for (int u = 0; u < bmap[p] && t < nbits; ++u, ++t) {
+            int bit = get_bit(msg, t) ^ get_bit(ks, t);
+            Ie[p] = (uint8_t)((Ie[p] & ~(1u << (7 - u))) | ((unsigned)bit << (7 - u)));
+        }
+    }
+    free(ks); free(bmap);
+    return t;
+}
+
+int64_t or_demr_extract(const uint8_t *Ie, int32_t M, int32_t N, const uint8_t *btab_enc, uint8_t *msg, int64_t nbits,
+                        uint64_t k2, uint64_t nonce)
+{
+    size_t MN = (size_t)M * (size_t)N;
+    uint8_t *bmap = (uint8_t *)malloc(MN + 1);
+    expand_tile_b(btab_enc, M, N, bmap);
+    int64_t nbytes = (nbits + 7) / 8;
+    uint8_t *ks = (uint8_t *)malloc((size_t)nbytes + 1);
+    or_keystream(k2, nonce, 2, 0, (uint64_t)nbytes, ks);
+    memset(msg, 0, (size_t)nbytes);
+    int64_t t = 0;
+    for (size_t p = 0; p < MN && t < nbits; ++p) {
+        if ((Ie[p] & 1) != 0) continue;
+        for (int u = 0; u < bmap[p] && t < nbits; ++u, ++t)
+            put_bit(msg, t, ((Ie[p] >> (7 - u)) & 1) ^ get_bit(ks, t));
+    }
+    free(ks); free(bmap);
+    return t;
+}
+
+/* Recovery with K1: l from the LSBs, XOR decryption, de-rotation of the image,
+ * the map and the per-pixel b (spread from the table in the encrypted
+ * domain), then left to right along each row: a pixel labelled 0 takes the
+ * top b MSBs (b of its tile) of its left neighbour as restored. */
+void or_demr_recover(const uint8_t *Ie, int32_t M, int32_t N, const uint8_t *btab_enc, uint64_t k1, uint64_t nonce,
+                     uint8_t *out)
+{
+    size_t MN = (size_t)M * (size_t)N;
+    uint8_t *s = (uint8_t *)malloc(MN + 1);
+    uint8_t *l = (uint8_t *)malloc(MN + 1);
+    uint8_t *bmap = (uint8_t *)malloc(MN + 1);
+    or_keystream(k1, nonce, 1, 0, MN, s);
+    expand_tile_b(btab_enc, M, N, bmap);
+    for (size_t p = 0; p < MN; ++p) {
+        l[p] = Ie[p] & 1;
+        out[p] = (uint8_t)(Ie[p] ^ s[p]);
+    }
+    or_rotate(out, M, N, s, 1, 1);
+    or_rotate(l, M, N, s, 1, 1);
+    or_rotate(bmap, M, N, s, 1, 1);
+    for (int32_t i = 0; i < M; ++i)
+        for (int32_t j = 1; j < N; ++j) {
+            int64_t p = (int64_t)i * N + j;
+            if (l[p] != 0) continue;
+            uint8_t mask = (uint8_t)(0xFF << (8 - bmap[p]));
+            out[p] = (uint8_t)((out[p - 1] & mask) | (out[p] & (uint8_t)~mask));
+        }
+    free(s); free(l); free(bmap);
+}
+
+/* ------------------------------------------------------------------------ */
 /* LMR-RDHEI (Sec. III-B).  The map compression is an external step here:    */
 /* the caller hands in the compressed stream; this file never compresses.    */
 /* ------------------------------------------------------------------------ */
