@@ -220,6 +220,21 @@ int rdhei_workspace_size(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int3
 int rdhei_run_batch(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t njobs, void *d_workspace,
                     int64_t workspace_bytes, void *stream);
 
+/* rdhei_run_batch without allocation, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, hosts that forbid
+ * hipMalloc): the job tables and the workspace live in a static device array
+ * of 64 MiB that the library holds on every GPU it runs on until the process
+ * ends; no hipMalloc, hipFree or pinned host allocation is made.  Same ops,
+ * jobs and results as rdhei_run_batch (EMR only).  A batch whose tables and
+ * workspace exceed 64 MiB is rejected with RDHEI_ENOMEM before anything is
+ * launched (rdhei_last_error gives the bytes it needs); for scale, one
+ * 512 x 512 encryption takes about 23 KB, a 16384 x 16384 image about 26 MB.
+ * Every call on a GPU shares that GPU's array: calls whose launches overlap on
+ * one GPU (different streams, or different contexts on one device) race and
+ * must be ordered by the caller; calls on one stream are ordered.  The array
+ * keeps the last call's contents; each call initialises what it reads. */
+int rdhei_run_batch_static(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t njobs, void *stream);
+
 /* Context options. */
 #define RDHEI_OPT_PER_PIXEL  1   /* 1: force the per-pixel path for every shape  */
 #define RDHEI_OPT_MAX_GRID   2   /* workgroup cap of grid-stride launches         */

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <thread>
 #include <cstdio>
 #include <cstring>
@@ -362,6 +363,7 @@ struct PinnedRing {
 
 struct rdhei_ctx {
     int device = 0;
+    uint8_t *static_ws = nullptr;      // this device's address of the static scratch array
     int per_pixel = 0;
     int hide_mode = 0;
     int lmr_min_level = 4;
@@ -974,6 +976,39 @@ int plan_issue(rdhei_plan *P, hipStream_t st) {
 
 }  // namespace
 
+// ---- Static scratch for callers that cannot allocate ------------------------------
+// rdhei_run_batch_static keeps its job tables and workspace in this file-scope
+// device array instead of allocating.  Every GPU the library runs on holds
+// its own copy, at its own address, until the process ends.  In host code the
+// name `scratch` is only a stand-in: kernels and copies get the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be the current device;
+// looked up once per device.
+int scratch_address(int device, uint8_t **out) {
+    if (device < 0 || device >= kMaxDevices) return RDHEI_EINVAL;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_err("hipGetSymbolAddress(scratch)", e);
+            return RDHEI_EDEVICE;
+        }
+        g_scratch_addr[device] = static_cast<uint8_t *>(p);
+    }
+    *out = g_scratch_addr[device];
+    return RDHEI_OK;
+}
+}  // namespace
+
 // ---- C ABI ---------------------------------------------------------------------------
 extern "C" {
 
@@ -987,9 +1022,18 @@ int rdhei_ctx_create(rdhei_ctx **out, int device) {
         return RDHEI_EDEVICE;
     }
     if (device < 0 || device >= n) return RDHEI_EINVAL;
+    e = hipSetDevice(device);
+    if (e != hipSuccess) {
+        set_err("hipSetDevice", e);
+        return RDHEI_EDEVICE;
+    }
+    uint8_t *sw = nullptr;
+    const int rc = scratch_address(device, &sw);
+    if (rc) return rc;
     rdhei_ctx *c = new (std::nothrow) rdhei_ctx();
     if (!c) return RDHEI_ENOMEM;
     c->device = device;
+    c->static_ws = sw;
     *out = c;
     return RDHEI_OK;
 }
@@ -1246,6 +1290,44 @@ int rdhei_run_batch(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t n
     for (int k = 0; k < UNIT_KINDS; ++k) L.ujob[k] = Ly.ujob[k].empty() ? nullptr : reinterpret_cast<const uint32_t *>(dtab + off[k]);
     L.njobs = (int32_t)Ly.jobs.size();
     L.ws = ws;
+    L.stream = st;
+    L.max_grid = ctx->max_grid;
+    L.g_status = Ly.g_status;
+    L.g_part = Ly.g_part;
+    L.keystream = Ly.keystream;
+    for (const Stage &sg : stages_of(Ly, Ly.units, Ly.per_pixel)) sg.fn(L);
+    HIPCHK(hipGetLastError());
+    return RDHEI_OK;
+}
+
+int rdhei_run_batch_static(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t njobs, void *stream) {
+    if (!ctx || !jobs || njobs < 1) return RDHEI_EINVAL;
+    if (!ctx->static_ws) return RDHEI_EDEVICE;
+    int rc = set_device(ctx->device);
+    if (rc) return rc;
+    Layout Ly;
+    rc = make_layout(op, jobs, njobs, opts_of(ctx), Ly);
+    if (rc) return rc;
+    if (Ly.method != RDHEI_EMR) return RDHEI_EINVAL;
+    size_t off[UNIT_KINDS];
+    const uint64_t tb = align_up(table_bytes(Ly, off), 256);
+    if (tb + Ly.ws_bytes > kStaticScratchBytes) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "rdhei_run_batch_static: batch needs %llu bytes of scratch, the static array holds %llu",
+                 (unsigned long long)(tb + Ly.ws_bytes), (unsigned long long)kStaticScratchBytes);
+        g_err = buf;
+        return RDHEI_ENOMEM;
+    }
+    // job and unit tables at the start of the array, the workspace after them;
+    // the tables are copied from pageable host memory, which the copy stages
+    // before it returns, so nothing outlives the call
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    uint8_t *base = ctx->static_ws;
+    Launch L;
+    rc = upload_tables(Ly, base, st, false, L);
+    if (rc) return rc;
+    L.njobs = (int32_t)Ly.jobs.size();
+    L.ws = base + tb;
     L.stream = st;
     L.max_grid = ctx->max_grid;
     L.g_status = Ly.g_status;

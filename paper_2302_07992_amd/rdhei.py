@@ -29,7 +29,7 @@ META_BYTES = 64
 EXPORTS = [
     "rdhei_ctx_create", "rdhei_ctx_destroy", "rdhei_ctx_set_option",
     "rdhei_encrypt", "rdhei_embed", "rdhei_extract", "rdhei_recover",
-    "rdhei_workspace_size", "rdhei_run_batch", "rdhei_plan_create", "rdhei_plan_run", "rdhei_plan_destroy", "rdhei_plan_set_grid",
+    "rdhei_workspace_size", "rdhei_run_batch", "rdhei_run_batch_static", "rdhei_plan_create", "rdhei_plan_run", "rdhei_plan_destroy", "rdhei_plan_set_grid",
     "rdhei_plan_stage_count", "rdhei_plan_stage_name", "rdhei_plan_run_stage",
     "rdhei_plan_autotune", "rdhei_plan_stage_grid",
     "rdhei_lmr_batch", "rdhei_lmr_compress", "rdhei_lmr_decompress", "rdhei_metrics", "rdhei_tile_b",
@@ -110,6 +110,7 @@ def load_library(path: str = LIB_PATH):
     lib.rdhei_recover.argtypes = [vp, vp, i32, i32, i32, vp, vp, u64, vp]
     lib.rdhei_workspace_size.argtypes = [vp, i32, ctypes.POINTER(JobStruct), i32, ctypes.POINTER(ctypes.c_int64)]
     lib.rdhei_run_batch.argtypes = [vp, i32, ctypes.POINTER(JobStruct), i32, vp, ctypes.c_int64, vp]
+    lib.rdhei_run_batch_static.argtypes = [vp, i32, ctypes.POINTER(JobStruct), i32, vp]
     lib.rdhei_plan_create.argtypes = [vp, i32, ctypes.POINTER(JobStruct), i32, i32, ctypes.POINTER(vp)]
     lib.rdhei_plan_run.argtypes = [vp, vp]
     lib.rdhei_plan_destroy.argtypes = [vp]
@@ -254,6 +255,12 @@ class Context:
         p, n = _jobs_arg(jobs)
         _check(self.lib.rdhei_run_batch(self.h, op, p, n, ctypes.c_void_p(workspace_ptr or None),
                                         workspace_bytes, _stream(stream)), "rdhei_run_batch")
+
+    def run_batch_static(self, op: int, jobs, stream=None) -> None:
+        """One EMR op over a job array with the library's static device
+        scratch (rdhei_run_batch_static: no allocation)."""
+        p, n = _jobs_arg(jobs)
+        _check(self.lib.rdhei_run_batch_static(self.h, op, p, n, _stream(stream)), "rdhei_run_batch_static")
 
     def metrics(self, pairs, ssim: bool = True, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
         """Sec. IV image metrics of each (a, b) pair (b may be None), or of a
