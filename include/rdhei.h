@@ -323,15 +323,15 @@ typedef struct {
 int rdhei_metrics(rdhei_ctx *ctx, const rdhei_metric_job *jobs, int32_t njobs, int32_t flags, double *d_out,
                   void *stream);
 
-/* ---- Per-tile b (the conclusion's dynamic b, first step) -----------------------
- * The conclusion suggests a b that varies over the image.  This call measures
- * what one b per 64x64 tile would trace (a reading of this library; it hides
- * nothing).  For tile t of an image: Z_b(t) = pixels of the tile, its first
- * column excepted, whose b most significant bits equal those of their left
- * neighbour (the location-map glide of Sec. III-A restarted at the tile's first
- * column), b = 2..7; b_t = the first b reaching the largest b * Z_b(t), as the
- * global b is chosen; the image's capacity = sum over tiles of b_t * Z_{b_t}(t)
- * bits.
+/* ---- Per-tile b (the conclusion's dynamic b) -----------------------------------
+ * The conclusion suggests a b that varies over the image.  This call computes
+ * the choice of this library's dynamic-b reading, one b per 64x64 tile,
+ * without encrypting: for tile t of an image, Z_b(t) = pixels of the tile,
+ * image column 0 excepted, whose b most significant bits equal those of their
+ * left neighbour (for a tile's first column the neighbour lies in the tile to
+ * its left: the location-map rule of Sec. III-A carried over tile borders),
+ * b = 2..7; b_t = the first b reaching the largest b * Z_b(t), as the global b
+ * is chosen; the image's capacity = sum over tiles of b_t * Z_{b_t}(t) bits.
  *   jobs        image in .a (.b unused), height and width positive multiples of
  *               64, .a 16-byte aligned
  *   d_tile_b    device, one byte per tile of every image: images in job order,

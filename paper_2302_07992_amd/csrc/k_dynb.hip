@@ -1,9 +1,10 @@
 // Per-tile b: for each 64x64 tile, the counts Z_b(t) (b = 2..7) of pixels
-// other than the tile's first column whose b MSBs equal their left
-// neighbour's, the tile's b_t (first b reaching the largest b * Z_b(t)) and
-// the image's capacity, sum of b_t * Z_{b_t}(t).  A first step towards the
-// dynamic b the conclusion suggests; it reads 1 B/px and writes one byte per
-// tile.
+// (other than those of image column 0) whose b MSBs equal their left
+// neighbour's -- for a tile's first column the neighbour lies in the tile to
+// the left --, the tile's b_t (first b reaching the largest b * Z_b(t)) and
+// the image's capacity, sum of b_t * Z_{b_t}(t): the choice and capacity of
+// the dynamic-b variant (one b per tile, the conclusion's suggestion).  Reads
+// 1 B/px (plus the byte left of each tile row) and writes one byte per tile.
 #include "device.hpp"
 
 namespace rdhei {
@@ -33,10 +34,13 @@ __global__ __launch_bounds__(kThreads) void k_tile_b(const TileBJob *__restrict_
         const TileBJob &J = jobs[lo];
         const uint32_t lt = t - J.tile_first, tpr = (uint32_t)J.N / kTile;
         const uint32_t ty = lt / tpr, tx = lt % tpr;
-        const uint4 v = gload<uint4>(J.img + (uint64_t)(ty * kTile + r) * (uint64_t)J.N + tx * kTile + 16 * g);
+        const uint8_t *row = J.img + (uint64_t)(ty * kTile + r) * (uint64_t)J.N + tx * kTile + 16 * g;
+        const uint4 v = gload<uint4>(row);
         const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-        // byte 15 of the segment to the left in the same tile row (lane - 1 of the quad)
-        const uint32_t from_left = qperm<0x90>(v.w >> 24);
+        // byte 15 of the segment to the left in the same tile row (lane - 1 of
+        // the quad); for the tile's first column, the byte left of the tile
+        uint32_t from_left = qperm<0x90>(v.w >> 24);
+        if (g == 0) from_left = tx > 0 ? (uint32_t)gload<uint8_t>(row - 1) : 0u;
         uint64_t acc = 0;
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
@@ -44,7 +48,7 @@ __global__ __launch_bounds__(kThreads) void k_tile_b(const TileBJob *__restrict_
             const uint32_t left = k == 0 ? from_left : (w[(k - 1) >> 2] >> (8 * ((k - 1) & 3))) & 0xFFu;
             const uint32_t lam = __clz(((x ^ left) << 24) | 0x00800000u);   // 0..8
             const uint32_t c = (lam < 7u ? (lam > 1u ? lam : 1u) : 7u) - 1u;
-            if (k > 0 || g > 0) acc += 1ull << (8 * c);                     // the tile's first column has no left pixel
+            if (k > 0 || g > 0 || tx > 0) acc += 1ull << (8 * c);           // image column 0 has no left pixel
         }
 #pragma unroll
         for (int c = 0; c < 7; ++c) {

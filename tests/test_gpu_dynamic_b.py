@@ -1,4 +1,5 @@
-"""Parity of the per-tile-b kernel (rdhei_tile_b) with oracle/dynamic_b.py,
+"""Parity of the per-tile-b kernel (rdhei_tile_b) with oracle/dynamic_b.py (the
+dynamic-b reading: the location-map rule carried over tile borders),
 bit-exact (integer counts and choices), through the C ABI."""
 import numpy as np
 import pytest
