@@ -119,6 +119,9 @@ def parse():
     ap.add_argument("--serve-streams", type=int, default=2)
     ap.add_argument("--serve-loads", default="0.5,0.7,0.9", help="offered load as fractions of batched capacity")
     ap.add_argument("--pipes", type=int, default=2, help="independent parts of the batch on as many streams")
+    ap.add_argument("--stagger", type=int, default=0,
+                    help="1: each part's encryption starts when the previous part's ends, so that the parts' "
+                         "vector-bound and memory-bound stages overlap")
     ap.add_argument("--serial-receiver", action="store_true",
                     help="run extraction and recovery one after the other instead of on two streams")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -642,9 +645,14 @@ def main():
         if pipes:
             start = torch.cuda.Event()
             start.record(main)
+            prev_enc = None
             for pp, (st, st2) in zip(pipes, pipe_streams):
                 st.wait_event(start)
+                if args.stagger and prev_enc is not None:
+                    st.wait_event(prev_enc)      # this part's encryption follows the previous part's
                 pp["encrypt"].run(st)
+                prev_enc = torch.cuda.Event()
+                prev_enc.record(st)
                 pp["embed"].run(st)
                 if args.serial_receiver:
                     pp["extract"].run(st)
@@ -941,7 +949,7 @@ def main():
                                "(sinusoids + noise, sigma in 1/3/8/20, 2..32 sinusoids), payload at capacity",
                    "images": B, "side": S, "mode": args.mode, "der_bpp": round(der, 4),
                    "receiver": "serial" if args.serial_receiver else "extract and recover on two streams",
-                   "pipes": max(1, args.pipes),
+                   "pipes": max(1, args.pipes), "stagger": bool(args.stagger),
                    "autotuned_workgroups": tuned},
         "roofline": roof,
         "step_hbm_frac": round(alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

@@ -190,18 +190,35 @@ int         rdhei_plan_stage_count(rdhei_plan *plan);
 const char *rdhei_plan_stage_name(rdhei_plan *plan, int32_t k);
 int         rdhei_plan_run_stage(rdhei_plan *plan, int32_t k, void *stream);
 
-/* Launch-shape autotuner.  Times every stage of a batched plan at several
- * workgroup counts (the launcher's default -- what fits on the device at
- * once -- and 1, 2, 4, 8, 16 and 32 workgroups per compute unit), `reps` runs
- * each, and keeps the fastest per stage (a change must win by more than 2 %).
- * Choices are cached in the context by op, stage and size class (log2 of the
- * plan's pixels and images) and reused by later plans of the same class
- * unless RDHEI_TUNE_FORCE is set.  Tuning reruns the stages on the plan's
- * own buffers (every stage is idempotent) and leaves them as one run of the
- * plan does; it synchronises `stream`.  PER_IMAGE plans are left as they are.
+/* Launch-shape autotuner.  For each layout variant of the plan -- the hiding
+ * mode of EMBED/EXTRACT plans whose images may be walked whole (one wave per
+ * image, or counted 4096-pixel steps), the quads per work unit of
+ * ENCRYPT/RECOVER plans (2, 4, 8, 16) -- it times every stage at several
+ * workgroup counts (the launcher's default -- what fits on the device at once
+ * -- and 1, 2, 4, 8, 16 and 32 workgroups per compute unit), max(reps, 5)
+ * timed runs each after a warm-up.  A candidate replaces the current choice
+ * only when its median run is shorter by more than half the two spreads
+ * (max - min of the runs) together, and by 2 % at least; variants compete the
+ * same way on the sum of their stages' medians, the plan's own variant first.
+ * Choices are cached in the context by device (architecture and compute
+ * units), op, keystream family and size class (log2 of the plan's pixels and
+ * images), written to the context's tune file if it has one
+ * (rdhei_ctx_set_tune_file), and reused by later plans of the same key unless
+ * RDHEI_TUNE_FORCE is set.  Tuning reruns the stages on the plan's own
+ * buffers (every stage is idempotent), may lay the plan out again (same
+ * results, other work units), and leaves the buffers as one run of the plan
+ * does; it synchronises `stream`.  PER_IMAGE plans are left as they are.
  * rdhei_plan_set_grid clears the tuned counts. */
 #define RDHEI_TUNE_FORCE 1
 int rdhei_plan_autotune(rdhei_plan *plan, int32_t reps, int32_t flags, void *stream);
+/* The plan's layout variant: hiding mode (RDHEI_OPT_HIDE_MODE values) and
+ * quads per work unit (either pointer may be NULL). */
+int rdhei_plan_tuned(rdhei_plan *plan, int32_t *hide_mode, int32_t *qseg);
+/* Persist the autotuner's choices: entries of the JSON file at `path` (if it
+ * exists) are loaded into the context now, and the file is rewritten after
+ * every autotune.  NULL or "" keeps choices in memory only.  RDHEI_EINVAL for
+ * a malformed file. */
+int rdhei_ctx_set_tune_file(rdhei_ctx *ctx, const char *path);
 /* Workgroup count stage k runs with (0: the launcher's default), or < 0 on error. */
 int rdhei_plan_stage_grid(rdhei_plan *plan, int32_t k);
 
@@ -257,6 +274,9 @@ int rdhei_run_batch_static(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, in
                                     on it; it is not recorded in the meta.
                                     Calls made after it is set use it; a plan
                                     keeps the family it was created with.      */
+#define RDHEI_OPT_QUAD_SEG  7    /* encryption and EMR recovery: 2x2 tile quads
+                                    per work unit along a band pair (1..64,
+                                    default 4); results are identical        */
 #define RDHEI_KEYSTREAM_PHILOX   0
 #define RDHEI_KEYSTREAM_CHACHA20 1
 int rdhei_ctx_set_option(rdhei_ctx *ctx, int32_t option, int64_t value);

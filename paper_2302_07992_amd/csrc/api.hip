@@ -9,6 +9,7 @@
 #include <mutex>
 #include <thread>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -133,13 +134,14 @@ struct LayoutOpts {
     int hide_mode = 0;        // RDHEI_OPT_HIDE_MODE
     int lmr_min_level = 4;    // RDHEI_OPT_LMR_MIN_LEVEL
     int keystream = kKsPhilox;   // RDHEI_OPT_KEYSTREAM
+    int qseg = kQuadSeg;         // quads per encryption / EMR recovery work unit
 };
 
 // Whether image q of a hiding op may be walked whole by one workgroup.
-// Segments of at most kQuadSeg 2x2 tile quads per band pair (tiled images).
+// Segments of at most J.qseg 2x2 tile quads per band pair (tiled images).
 uint32_t quad_segments(const Job &J) {
     const uint32_t nq = (uint32_t)((J.tiles_x + 1) / 2);
-    return (nq + kQuadSeg - 1) / kQuadSeg;
+    return (nq + (uint32_t)J.qseg - 1) / (uint32_t)J.qseg;
 }
 
 bool whole_eligible(int op, const rdhei_job &q) {
@@ -204,6 +206,7 @@ int make_layout(int op, const rdhei_job *in, int n, const LayoutOpts &opt, Layou
             J.tiles_y = q.height / kTile;
         }
         J.nseg = (int32_t)((MN + seg_pixels() - 1) / seg_pixels());
+        J.qseg = opt.qseg;
         if (rot) {
             const uint64_t tiles = (uint64_t)J.tiles_x * J.tiles_y;
             J.ws_codes = ws;
@@ -320,6 +323,13 @@ void issue(const Layout &Ly, const Launch &L, const uint32_t *units, const int *
 }  // namespace
 
 // ------------------------------------------------------------------------------
+// One autotuner choice: the layout variant and each stage's workgroup count.
+struct TuneRecord {
+    int hide_mode = 0;
+    int qseg = kQuadSeg;
+    std::vector<int> grids;
+};
+
 // Ring of pinned host buffers for asynchronous job-table uploads: a slot is
 // reused only after the copy issued from it has completed.
 struct PinnedRing {
@@ -368,7 +378,9 @@ struct rdhei_ctx {
     int hide_mode = 0;
     int lmr_min_level = 4;
     int keystream = kKsPhilox;
-    std::map<std::string, int> tuned;   // autotuned workgroup counts by op/stage/size class
+    int qseg = kQuadSeg;
+    std::map<std::string, TuneRecord> tuned;   // autotuner choices by device/op/size class
+    std::string tune_file;              // where the choices persist (empty: memory only)
     int max_grid = 0;
     DevBuf ws, jobs, scratch, batch_tables, lmr_dev, metrics, tileb;
     HostBuf lmr_host;
@@ -378,6 +390,9 @@ struct rdhei_ctx {
 
 struct rdhei_plan {
     rdhei_ctx *ctx = nullptr;
+    int op = 0;
+    std::vector<rdhei_job> src;    // the caller's jobs (host copy), for re-layout by the autotuner
+    LayoutOpts opts;               // layout options the plan is laid out with
     Layout layout;
     DevBuf ws, jobs, single;       // single: per-image one-job tables
     int flags = 0;
@@ -405,6 +420,7 @@ LayoutOpts opts_of(const rdhei_ctx *ctx) {
     o.hide_mode = ctx->hide_mode;
     o.lmr_min_level = ctx->lmr_min_level;
     o.keystream = ctx->keystream;
+    o.qseg = ctx->qseg;
     return o;
 }
 
@@ -974,6 +990,128 @@ int plan_issue(rdhei_plan *P, hipStream_t st) {
     return RDHEI_OK;
 }
 
+// ---- Autotuner helpers ------------------------------------------------------------
+
+// Cache key of a plan: the device (architecture and compute units), the op,
+// the keystream family, the per-pixel switch and the size class (log2 of the
+// plan's pixels and images).
+std::string tune_key(const rdhei_plan *P, int cus) {
+    hipDeviceProp_t prop;
+    std::string arch = "gpu";
+    if (hipGetDeviceProperties(&prop, P->ctx->device) == hipSuccess) arch = prop.gcnArchName;
+    for (char &c : arch)
+        if (c == '"' || c == '\\' || c == ' ') c = '_';
+    uint64_t px = 0;
+    for (const rdhei_job &q : P->src) px += (uint64_t)q.height * (uint64_t)q.width;
+    int px_cls = 0, job_cls = 0;
+    while ((px >> px_cls) > 1) ++px_cls;
+    while (((uint64_t)P->src.size() >> job_cls) > 1) ++job_cls;
+    return arch + ":" + std::to_string(cus) + "cu/op" + std::to_string(P->op) + "/ks" + std::to_string(P->opts.keystream) +
+           "/pp" + std::to_string(P->opts.per_pixel ? 1 : 0) + "/px" + std::to_string(px_cls) + "/jobs" +
+           std::to_string(job_cls);
+}
+
+// Lay the plan out with a tuner record's variant (if it differs) and take its
+// workgroup counts; drops a captured graph.
+int plan_apply(rdhei_plan *P, const TuneRecord &v) {
+    LayoutOpts o = P->opts;
+    o.hide_mode = v.hide_mode;
+    o.qseg = v.qseg;
+    if (o.hide_mode != P->opts.hide_mode || o.qseg != P->opts.qseg) {
+        Layout Ly;
+        int rc = make_layout(P->op, P->src.data(), (int)P->src.size(), o, Ly);
+        if (rc) return rc;
+        size_t off[UNIT_KINDS];
+        if ((rc = P->jobs.need(table_bytes(Ly, off))) || (rc = P->ws.need(Ly.ws_bytes))) return rc;
+        Launch L;
+        if ((rc = upload_tables(Ly, P->jobs.p, nullptr, true, L))) return rc;
+        L.keystream = Ly.keystream;
+        P->base = L;
+        P->layout = Ly;
+        P->opts = o;
+        P->stages = stages_of(P->layout, P->layout.units, P->layout.per_pixel);
+    }
+    P->stage_grid.assign(P->stages.size(), 0);
+    if (v.grids.size() == P->stages.size()) P->stage_grid = v.grids;
+    if (P->exec) { (void)hipGraphExecDestroy(P->exec); P->exec = nullptr; }
+    if (P->graph) { (void)hipGraphDestroy(P->graph); P->graph = nullptr; }
+    return RDHEI_OK;
+}
+
+// The context's choices as JSON in its tune file (written to a temporary file,
+// then renamed over the old one).
+void tune_save(const rdhei_ctx *ctx) {
+    if (ctx->tune_file.empty()) return;
+    const std::string tmp = ctx->tune_file + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    fprintf(f, "{\n  \"rdhei_tune\": 1,\n  \"entries\": {");
+    bool first = true;
+    for (const auto &kv : ctx->tuned) {
+        fprintf(f, "%s\n    \"%s\": {\"hide_mode\": %d, \"qseg\": %d, \"grids\": [", first ? "" : ",", kv.first.c_str(),
+                kv.second.hide_mode, kv.second.qseg);
+        for (size_t i = 0; i < kv.second.grids.size(); ++i) fprintf(f, "%s%d", i ? ", " : "", kv.second.grids[i]);
+        fprintf(f, "]}");
+        first = false;
+    }
+    fprintf(f, "\n  }\n}\n");
+    const bool ok = fclose(f) == 0;
+    if (ok) (void)std::rename(tmp.c_str(), ctx->tune_file.c_str());
+}
+
+// Reads the entries a tune file holds (the format tune_save writes); a missing
+// file is an empty cache, a malformed one RDHEI_EINVAL.
+int tune_load(rdhei_ctx *ctx) {
+    FILE *f = fopen(ctx->tune_file.c_str(), "r");
+    if (!f) return RDHEI_OK;
+    std::string t;
+    char buf[4096];
+    size_t n;
+    while ((n = fread(buf, 1, sizeof buf, f)) > 0) t.append(buf, n);
+    fclose(f);
+    size_t p = t.find("\"entries\"");
+    if (p == std::string::npos) return RDHEI_EINVAL;
+    p = t.find('{', p);
+    if (p == std::string::npos) return RDHEI_EINVAL;
+    auto int_after = [&](const std::string &name, size_t from, size_t to, int &out) {
+        const size_t k = t.find("\"" + name + "\"", from);
+        if (k == std::string::npos || k > to) return false;
+        const size_t c = t.find(':', k);
+        if (c == std::string::npos || c > to) return false;
+        out = (int)strtol(t.c_str() + c + 1, nullptr, 10);
+        return true;
+    };
+    std::map<std::string, TuneRecord> got;
+    for (;;) {
+        const size_t k0 = t.find('"', p + 1);
+        if (k0 == std::string::npos) break;
+        const size_t k1 = t.find('"', k0 + 1);
+        const size_t o0 = k1 == std::string::npos ? std::string::npos : t.find('{', k1);
+        const size_t o1 = o0 == std::string::npos ? std::string::npos : t.find('}', o0);
+        if (o1 == std::string::npos) return RDHEI_EINVAL;
+        TuneRecord r;
+        if (!int_after("hide_mode", o0, o1, r.hide_mode) || !int_after("qseg", o0, o1, r.qseg)) return RDHEI_EINVAL;
+        if (r.hide_mode < 0 || r.hide_mode > 2 || r.qseg < 1 || r.qseg > kQuadSegMax) return RDHEI_EINVAL;
+        const size_t g0 = t.find('[', o0), g1 = t.find(']', o0);
+        if (g0 == std::string::npos || g1 == std::string::npos || g1 > o1) return RDHEI_EINVAL;
+        for (const char *c = t.c_str() + g0 + 1; c < t.c_str() + g1;) {
+            char *e = nullptr;
+            const long v = strtol(c, &e, 10);
+            if (e == c) { ++c; continue; }
+            if (v < 0 || v > (1 << 30)) return RDHEI_EINVAL;
+            r.grids.push_back((int)v);
+            c = e;
+        }
+        got[t.substr(k0 + 1, k1 - k0 - 1)] = r;
+        p = o1;
+        const size_t nx = t.find_first_not_of(" \t\r\n", o1 + 1);
+        if (nx == std::string::npos || t[nx] != ',') break;
+        p = nx;
+    }
+    for (auto &kv : got) ctx->tuned[kv.first] = kv.second;
+    return RDHEI_OK;
+}
+
 }  // namespace
 
 // ---- Static scratch for callers that cannot allocate ------------------------------
@@ -1069,6 +1207,9 @@ int rdhei_ctx_set_option(rdhei_ctx *ctx, int32_t option, int64_t value) {
     } else if (option == RDHEI_OPT_KEYSTREAM) {
         if (value != RDHEI_KEYSTREAM_PHILOX && value != RDHEI_KEYSTREAM_CHACHA20) return RDHEI_EINVAL;
         ctx->keystream = (int)value;
+    } else if (option == RDHEI_OPT_QUAD_SEG) {
+        if (value < 1 || value > kQuadSegMax) return RDHEI_EINVAL;
+        ctx->qseg = (int)value;
     } else if (option == RDHEI_OPT_RESERVE_WS) {
         if (value < 0) return RDHEI_EINVAL;
         int rc = set_device(ctx->device);
@@ -1348,9 +1489,12 @@ int rdhei_plan_create(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t
     rdhei_plan *P = new (std::nothrow) rdhei_plan();
     if (!P) return RDHEI_ENOMEM;
     P->ctx = ctx;
+    P->op = op;
     P->flags = flags;
     P->max_grid = ctx->max_grid;
-    rc = make_layout(op, jobs, njobs, opts_of(ctx), P->layout);
+    P->opts = opts_of(ctx);
+    P->src.assign(jobs, jobs + njobs);
+    rc = make_layout(op, jobs, njobs, P->opts, P->layout);
     if (!rc && P->layout.method != RDHEI_EMR) rc = RDHEI_EINVAL;
     size_t toff[UNIT_KINDS];
     if (!rc) rc = P->jobs.need(table_bytes(P->layout, toff));
@@ -1462,61 +1606,138 @@ int rdhei_plan_autotune(rdhei_plan *P, int32_t reps, int32_t flags, void *stream
     int rc = set_device(P->ctx->device);
     if (rc) return rc;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    rdhei_ctx *ctx = P->ctx;
     int cus = 0;
-    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->ctx->device));
-    // size class of the plan: log2 of its pixels and of its images
-    uint64_t px = 0;
-    for (const Job &J : P->layout.jobs) px += (uint64_t)J.M * (uint64_t)J.N;
-    int px_cls = 0, job_cls = 0;
-    while ((px >> px_cls) > 1) ++px_cls;
-    while (((uint64_t)P->layout.jobs.size() >> job_cls) > 1) ++job_cls;
-    // the stages read what the stages before them wrote: bring the plan's
-    // buffers to a consistent state first (every stage is idempotent)
-    std::fill(P->stage_grid.begin(), P->stage_grid.end(), 0);
-    rc = plan_issue(P, st);
-    if (rc) return rc;
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    const std::string key = tune_key(P, cus);
+    auto it = ctx->tuned.find(key);
+    if (it != ctx->tuned.end() && !(flags & RDHEI_TUNE_FORCE)) {
+        rc = plan_apply(P, it->second);
+        if (rc) return rc;
+        rc = plan_issue(P, st);
+        if (rc) return rc;
+        HIPCHK(hipStreamSynchronize(st));
+        return RDHEI_OK;
+    }
+    const int samples = std::max<int>(reps, 5);
+    const LayoutOpts base = P->opts;
+    // layout variants: the hiding mode of embed/extract plans whose images may
+    // be walked whole, the quads per work unit of encrypt/recover plans with
+    // band pairs of more than one quad
+    std::vector<TuneRecord> variants;
+    {
+        TuneRecord v0;
+        v0.hide_mode = base.hide_mode;
+        v0.qseg = base.qseg;
+        variants.push_back(v0);
+        const bool hide = P->op == RDHEI_OP_EMBED || P->op == RDHEI_OP_EXTRACT;
+        bool eligible = false;
+        uint32_t max_nq = 0;
+        for (const rdhei_job &q : P->src) {
+            eligible = eligible || whole_eligible(P->op, q);
+            if (q.height % kTile == 0 && q.width % kTile == 0) max_nq = std::max<uint32_t>(max_nq, (uint32_t)(q.width / kTile + 1) / 2);
+        }
+        if (hide && eligible)
+            for (int hm : {1, 2}) {
+                TuneRecord v = v0;
+                v.hide_mode = hm;
+                variants.push_back(v);
+            }
+        if (!hide && max_nq > 1)
+            for (int qs : {2, 4, 8, 16}) {
+                if (qs == v0.qseg || (uint32_t)qs / 2 >= max_nq) continue;   // longer than every band pair: same as a shorter one
+                TuneRecord v = v0;
+                v.qseg = qs;
+                variants.push_back(v);
+            }
+    }
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
+    // one timed run of stage k at the plan's current grid choice
+    auto time_stage = [&](size_t k, float &ms) -> int {
+        if (hipEventRecord(e0, st) != hipSuccess) return RDHEI_EDEVICE;
+        int r = rdhei_plan_run_stage(P, (int32_t)k, stream);
+        if (r) return r;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return RDHEI_EDEVICE;
+        return RDHEI_OK;
+    };
     const int cand[] = {0, cus, 2 * cus, 4 * cus, 8 * cus, 16 * cus, 32 * cus};
-    for (size_t k = 0; k < P->stages.size() && !rc; ++k) {
-        const std::string key = std::to_string(P->layout.op) + "/" + P->stages[k].name + "/" + std::to_string(px_cls) +
-                                "/" + std::to_string(job_cls);
-        auto it = P->ctx->tuned.find(key);
-        if (it != P->ctx->tuned.end() && !(flags & RDHEI_TUNE_FORCE)) {
-            P->stage_grid[k] = it->second;
-            continue;
-        }
-        float best = 1e30f;
-        int best_g = 0;
-        for (int g : cand) {
-            P->stage_grid[k] = g;
-            rc = rdhei_plan_run_stage(P, (int32_t)k, stream);     // warm-up
-            if (rc) break;
-            if (hipEventRecord(e0, st) != hipSuccess) { rc = RDHEI_EDEVICE; break; }
-            for (int r = 0; r < reps && !rc; ++r) rc = rdhei_plan_run_stage(P, (int32_t)k, stream);
-            if (rc) break;
-            float ms = 0.f;
-            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = RDHEI_EDEVICE; break; }
-            if (ms < best * 0.98f) {     // a new choice must win by more than noise
-                best = ms;
-                best_g = g;
+    TuneRecord best_v;
+    float best_total = 0.f, best_spread = 0.f;
+    for (size_t vi = 0; vi < variants.size() && !rc; ++vi) {
+        TuneRecord v = variants[vi];
+        v.grids.clear();
+        rc = plan_apply(P, v);
+        if (rc) break;
+        // the stages read what the stages before them wrote: bring the
+        // plan's buffers to a consistent state first (every stage is idempotent)
+        rc = plan_issue(P, st);
+        if (rc) break;
+        float total = 0.f, spread = 0.f;
+        for (size_t k = 0; k < P->stages.size() && !rc; ++k) {
+            // per candidate: the median and the spread (max - min) of `samples`
+            // timed runs after one warm-up; a candidate replaces the current
+            // choice only when its median is lower by more than the two
+            // spreads together (and by 2 % at least)
+            float cm = 0.f, cs = 0.f;
+            int cg = 0;
+            bool have = false;
+            for (int g : cand) {
+                P->stage_grid[k] = g;
+                rc = rdhei_plan_run_stage(P, (int32_t)k, stream);
+                if (rc) break;
+                std::vector<float> t((size_t)samples);
+                for (int r = 0; r < samples && !rc; ++r) rc = time_stage(k, t[(size_t)r]);
+                if (rc) break;
+                std::sort(t.begin(), t.end());
+                const float med = t[t.size() / 2], spr = t.back() - t.front();
+                if (!have || med < cm - std::max(0.02f * cm, 0.5f * (cs + spr))) {
+                    cm = med;
+                    cs = spr;
+                    cg = g;
+                    have = true;
+                }
             }
+            P->stage_grid[k] = cg;
+            v.grids.push_back(cg);
+            total += cm;
+            spread += cs;
         }
-        P->stage_grid[k] = best_g;
-        if (!rc) P->ctx->tuned[key] = best_g;
+        if (rc) break;
+        if (vi == 0 || total < best_total - std::max(0.02f * best_total, 0.5f * (best_spread + spread))) {
+            best_total = total;
+            best_spread = spread;
+            best_v = v;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
+    rc = plan_apply(P, best_v);
+    if (rc) return rc;
+    ctx->tuned[key] = best_v;
+    tune_save(ctx);
     // leave the buffers as one run with the chosen shapes leaves them
-    if (P->exec) { (void)hipGraphExecDestroy(P->exec); P->exec = nullptr; }
-    if (P->graph) { (void)hipGraphDestroy(P->graph); P->graph = nullptr; }
     rc = plan_issue(P, st);
     if (rc) return rc;
     HIPCHK(hipStreamSynchronize(st));
     return RDHEI_OK;
+}
+
+int rdhei_plan_tuned(rdhei_plan *P, int32_t *hide_mode, int32_t *qseg) {
+    if (!P) return RDHEI_EINVAL;
+    if (hide_mode) *hide_mode = P->opts.hide_mode;
+    if (qseg) *qseg = P->opts.qseg;
+    return RDHEI_OK;
+}
+
+int rdhei_ctx_set_tune_file(rdhei_ctx *ctx, const char *path) {
+    if (!ctx) return RDHEI_EINVAL;
+    ctx->tune_file = path ? path : "";
+    if (ctx->tune_file.empty()) return RDHEI_OK;
+    return tune_load(ctx);
 }
 
 void rdhei_plan_destroy(rdhei_plan *P) {

@@ -52,9 +52,11 @@ inline void with_keystream(int ks, F &&f) {
 // tiled path takes images of at most this many tiles along each side.
 constexpr int kTmapMaxTiles = 1 << 14;
 
-// Encryption cuts band pairs into segments of at most kQuadSeg 2x2 tile quads
-// (one work unit each); EMR recovery takes whole band pairs.
+// Encryption and EMR recovery cut band pairs into segments of at most
+// Job::qseg 2x2 tile quads (one work unit each); kQuadSeg is the default, the
+// autotuner may choose another length per plan (1..kQuadSegMax).
 constexpr int kQuadSeg = 4;
+constexpr int kQuadSegMax = 64;
 
 // Device-side descriptor of one image of a launch.
 struct Job {
@@ -78,6 +80,7 @@ struct Job {
     int32_t tiles_x, tiles_y;
     int32_t nseg;             // hiding / extraction steps of seg_pixels() raster pixels
     int32_t nonce_meta;       // 1: the keystream nonce comes from meta->nonce (device)
+    int32_t qseg;             // 2x2 tile quads per work unit of encryption / EMR recovery
     uint32_t ubase[UNIT_KINDS];
     uint32_t ucount[UNIT_KINDS];
     uint64_t ws_codes;        // tile code records (fast) / all-level codes (per-pixel path)

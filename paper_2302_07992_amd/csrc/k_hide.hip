@@ -134,6 +134,9 @@ __device__ __forceinline__ void window_or(uint32_t *win, uint32_t p, uint32_t s)
 // to the staged window, before its guard word); bits at rend and beyond are
 // not part of the payload.  Whole words use the field permutes; the one word
 // where the payload ends goes pixel by pixel.
+// TAIL: the payload may end inside these pixels (the last step of an image
+// hiding less than its capacity); otherwise every field lies inside it.
+template <bool TAIL = true>
 __device__ __forceinline__ void embed16(uint32_t w[4], uint32_t rm, uint32_t rel, uint32_t rend, const uint32_t *win,
                                         const Hide4 &hk, const uint32_t *T) {
     const uint32_t rep = hk.rep;
@@ -151,6 +154,10 @@ __device__ __forceinline__ void embed16(uint32_t w[4], uint32_t rm, uint32_t rel
         const uint32_t e = vperm(0u, cp, T[16 + m]) << hk.shift;
         const uint32_t K = T[32 + m] & hk.rep_bytes;
         const uint32_t x = w[q];
+        if (!TAIL) {
+            w[q] = (x & ~K) | (e & K);
+            continue;
+        }
         w[q] = rel <= rend ? ((x & ~K) | (e & K)) : x;
         if (__builtin_expect(rel > rend && pos < rend, 0)) {
             // the word where the payload ends: pixel by pixel
@@ -175,6 +182,7 @@ __device__ __forceinline__ void embed16(uint32_t w[4], uint32_t rm, uint32_t rel
 // Extraction from 16 pixels: the payload bits of the redundant pixels are ORed
 // into the window (word 0 = first window word) from position rel on; bits at
 // rend and beyond are dropped.
+template <bool TAIL = true>
 __device__ __forceinline__ void extract16(const uint32_t w[4], uint32_t rm, uint32_t rel, uint32_t rend, uint32_t *win,
                                           const Hide4 &hk, const uint32_t *T) {
     const uint32_t rep = hk.rep;
@@ -183,6 +191,14 @@ __device__ __forceinline__ void extract16(const uint32_t w[4], uint32_t rm, uint
         const uint32_t m = (rm >> (4 * q)) & 0xFu;
         const uint32_t pos = rel;
         rel += __umul24((uint32_t)__popc(m), rep);
+        if (!TAIL) {
+            // every field inside the payload; an empty word ORs zeros
+            const uint32_t c = vperm(0u, (w[q] >> hk.shift) & hk.low_bytes, T[m]);
+            const uint32_t v = ((c >> 8) & 0x00FF00FFu) << rep | (c & 0x00FF00FFu);
+            const uint32_t s = __builtin_amdgcn_alignbit(v >> 16, v << (32u - 2u * rep), 2u * rep);
+            window_or(win, pos, s);
+            continue;
+        }
         if (m == 0 || pos >= rend) continue;
         if (__builtin_expect(rel <= rend, 1)) {
             // the fields of the word's redundant pixels, in order, then packed
@@ -325,19 +341,24 @@ __device__ __forceinline__ void each_stream_block_quad(const Job &J, uint64_t no
     }
 }
 
+// Whole images are at most kWholeMaxPx pixels, so every bit offset of their
+// payload (at most 7 bits per pixel) fits in 32 bits.
+static_assert(kWholeMaxPx * 7 < (1ull << 31), "whole-image bit offsets are 32-bit");
+
 template <bool EMBED, int KS>
 __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &hp, uint32_t *win, const uint32_t *htab) {
     const int lane = threadIdx.x & 63;
     const uint8_t *img = EMBED ? J.out : J.in;
-    const uint64_t total = (uint64_t)J.M * (uint64_t)J.N;
+    const uint32_t total = (uint32_t)((uint64_t)J.M * (uint64_t)J.N);
     const uint32_t nseg = (uint32_t)((total + kWSegPx - 1) / kWSegPx);
     const uint32_t rep = hp.rep;
+    const uint32_t nbits = (uint32_t)hp.nbits;
     const Hide4 hk = hide4_params(hp);
-    uint64_t rank = 0;
+    uint32_t rank = 0;
     uint32_t carry = 0;          // extraction: bits of the partial word left by the previous step
-    int64_t carry_word = -1;
+    uint32_t carry_word = ~0u;   // its word index (none: ~0)
     uint4 nxt[kWLoads];
-    wseg_load(img, 0, total < kWSegPx ? total : kWSegPx, lane, nxt);
+    wseg_load(img, 0, total < kWSegPx ? total : (uint32_t)kWSegPx, lane, nxt);
     // embedding: message blocks of the next step, loaded a step ahead.  A step
     // needs at most 4096 * 7 bits = 224 blocks from its first one; as many are
     // prefetched as the previous step used, plus two (neighbouring steps of an
@@ -345,27 +366,28 @@ __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &
     // further blocks it needs itself.
     uint4 mpre[4];
     uint32_t npre = 0;
-    const uint64_t nblk = (uint64_t)(hp.nbits + 127) >> 7;
-    auto msg_prefetch = [&](uint64_t first_blk, uint32_t n) {
+    const uint32_t nblk = (nbits + 127) >> 7;
+    auto msg_prefetch = [&](uint32_t first_blk, uint32_t n) {
         npre = n;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const uint64_t blk = first_blk + (uint64_t)(lane + 64 * i);
-            mpre[i] = (uint32_t)(lane + 64 * i) < n && blk < nblk ? gload<uint4>(J.msg + 16 * blk) : make_uint4(0, 0, 0, 0);
+            const uint32_t blk = first_blk + (uint32_t)(lane + 64 * i);
+            mpre[i] = (uint32_t)(lane + 64 * i) < n && blk < nblk ? gload<uint4>(J.msg + 16 * (uint64_t)blk)
+                                                                  : make_uint4(0, 0, 0, 0);
         }
     };
     constexpr bool kPrefetch = EMBED && KS != kKsChaCha20;   // ChaCha20 loads its blocks in stage_window_quad
     if (kPrefetch) msg_prefetch(0, (uint32_t)((kWSegPx / 2 * rep + 127) / 128));   // first step: half its pixels
     for (uint32_t seg = 0; seg < nseg; ++seg) {
-        const uint64_t s0 = (uint64_t)seg * kWSegPx;
-        const uint64_t s1 = s0 + kWSegPx < total ? s0 + kWSegPx : total;
+        const uint32_t s0 = seg * (uint32_t)kWSegPx;
+        const uint32_t s1 = s0 + (uint32_t)kWSegPx < total ? s0 + (uint32_t)kWSegPx : total;
         uint4 px[kWLoads];
 #pragma unroll
         for (int k = 0; k < kWLoads; ++k) px[k] = nxt[k];
         {   // the next step's pixels (the last step reloads itself)
             const uint32_t ns = seg + 1 < nseg ? seg + 1 : seg;
-            const uint64_t n0 = (uint64_t)ns * kWSegPx;
-            wseg_load(img, n0, n0 + kWSegPx < total ? n0 + kWSegPx : total, lane, nxt);
+            const uint32_t n0 = ns * (uint32_t)kWSegPx;
+            wseg_load(img, n0, n0 + (uint32_t)kWSegPx < total ? n0 + (uint32_t)kWSegPx : total, lane, nxt);
         }
         uint32_t rm[kWLoads];
 #pragma unroll
@@ -373,23 +395,23 @@ __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &
             rm[k] = redundant16(J, px[k], s0 + (uint64_t)k * 1024u + 16 * (uint64_t)lane, s1);
         uint32_t lr[kWLoads], T;
         step_ranks(rm, lr, T);
-        const int64_t wstart = (int64_t)(rank * rep);
-        if (wstart >= hp.nbits) break;
-        int64_t wend = (int64_t)((rank + T) * rep);
-        if (wend > hp.nbits) wend = hp.nbits;
+        const uint32_t wstart = rank * rep;
+        if (wstart >= nbits) break;
+        uint32_t wend = (rank + T) * rep;
+        if (wend > nbits) wend = nbits;
         rank += T;
         if (T > 0 && EMBED) {
             // window bits relative to the first staged 16-byte block (the prefetch base)
-            const int64_t fb = wstart >> 7, lb = (wend - 1) >> 7;
-            const uint32_t off0 = (uint32_t)(wstart - (fb << 7)), rend = (uint32_t)(wend - (fb << 7));
+            const uint32_t fb = wstart >> 7, lb = (wend - 1) >> 7;
+            const uint32_t off0 = wstart - (fb << 7), rend = wend - (fb << 7);
             if constexpr (KS == kKsChaCha20) {
                 stage_window_quad<KS>(J, hp.nonce, lane, fb, lb, win);
             } else {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int64_t q = lane + 64 * i;
+                    const uint32_t q = (uint32_t)(lane + 64 * i);
                     if (q > lb - fb) continue;
-                    const uint4 mv = q < (int64_t)npre ? mpre[i] : gload<uint4>(J.msg + 16 * (uint64_t)(fb + q));
+                    const uint4 mv = q < npre ? mpre[i] : gload<uint4>(J.msg + 16 * (uint64_t)(fb + q));
                     const U4 ks = stream_block<KS>(J.key, hp.nonce, kDomainMessage, (uint64_t)(fb + q));
                     *reinterpret_cast<uint4 *>(win + 4 + 4 * q) =
                         make_uint4(__builtin_bswap32(mv.x ^ ks.x), __builtin_bswap32(mv.y ^ ks.y),
@@ -397,64 +419,105 @@ __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &
                 }
             }
             // rank already counts this step
-            const uint32_t used = (uint32_t)(lb - fb + 1) + 2u;
+            const uint32_t used = lb - fb + 1u + 2u;
             if (kPrefetch) msg_prefetch((rank * rep) >> 7, used < 256u ? used : 256u);
             wave_sync();
+            if (wend == rank * rep) {   // the whole step inside the payload (uniform)
 #pragma unroll
-            for (int k = 0; k < kWLoads; ++k) {
-                const uint32_t rel = off0 + lr[k] * rep;
-                if (!rm[k] || rel >= rend) continue;
-                uint32_t w[4] = {px[k].x, px[k].y, px[k].z, px[k].w};
-                embed16(w, rm[k], rel, rend, win + 3, hk, htab);   // word 0 of the window is a guard
-                gstore<uint4>(J.out + s0 + (uint64_t)k * 1024u + 16 * (uint64_t)lane, make_uint4(w[0], w[1], w[2], w[3]));
+                for (int k = 0; k < kWLoads; ++k) {
+                    if (!rm[k]) continue;
+                    uint32_t w[4] = {px[k].x, px[k].y, px[k].z, px[k].w};
+                    embed16<false>(w, rm[k], off0 + lr[k] * rep, rend, win + 3, hk, htab);
+                    gstore<uint4>(J.out + s0 + (uint64_t)k * 1024u + 16 * (uint64_t)lane, make_uint4(w[0], w[1], w[2], w[3]));
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < kWLoads; ++k) {
+                    const uint32_t rel = off0 + lr[k] * rep;
+                    if (!rm[k] || rel >= rend) continue;
+                    uint32_t w[4] = {px[k].x, px[k].y, px[k].z, px[k].w};
+                    embed16(w, rm[k], rel, rend, win + 3, hk, htab);   // word 0 of the window is a guard
+                    gstore<uint4>(J.out + s0 + (uint64_t)k * 1024u + 16 * (uint64_t)lane, make_uint4(w[0], w[1], w[2], w[3]));
+                }
             }
             wave_sync();
         } else if (T > 0) {
-            const int64_t W0 = wstart >> 5, W1 = (wend + 31) >> 5;
-            const uint32_t off0 = (uint32_t)(wstart & 31), rend = (uint32_t)(wend - 32 * W0);
-            for (int64_t q = lane; q < W1 - W0 + 1; q += 64) win[q] = (q == 0 && carry_word == W0) ? carry : 0u;
-            wave_sync();
-#pragma unroll
-            for (int k = 0; k < kWLoads; ++k) {
-                const uint32_t rel = off0 + lr[k] * rep;
-                if (!rm[k] || rel >= rend) continue;
-                const uint32_t w[4] = {px[k].x, px[k].y, px[k].z, px[k].w};
-                extract16(w, rm[k], rel, rend, win, hk, htab);
+            // The window starts at the first message word of the keystream
+            // block holding bit wstart (word 4 B0), so that every block's four
+            // words are one aligned 16-byte LDS read.
+            const uint32_t W0 = wstart >> 5, W1 = (wend + 31) >> 5, B0 = W0 >> 2;
+            const uint32_t base = 4 * B0, off0 = wstart - 32 * base, rend = wend - 32 * base;
+            const uint32_t nq = ((W1 - base) >> 2) + 1;    // 16-byte pieces: words 0..W1-base (the last
+                                                           // may take a zero OR past the run's end)
+            for (uint32_t q = (uint32_t)lane; q < nq; q += 64) {
+                uint4 z = make_uint4(0, 0, 0, 0);
+                if (carry_word != ~0u && carry_word >= base && (carry_word - base) >> 2 == q) {
+                    const uint32_t c = (carry_word - base) & 3u;
+                    z.x = c == 0 ? carry : 0u;
+                    z.y = c == 1 ? carry : 0u;
+                    z.z = c == 2 ? carry : 0u;
+                    z.w = c == 3 ? carry : 0u;
+                }
+                *reinterpret_cast<uint4 *>(win + 4 * q) = z;
             }
             wave_sync();
-            // complete words go out; a trailing partial word waits for the next step
+            if (wend == rank * rep) {   // the whole step inside the payload (uniform)
+#pragma unroll
+                for (int k = 0; k < kWLoads; ++k) {
+                    const uint32_t w[4] = {px[k].x, px[k].y, px[k].z, px[k].w};
+                    extract16<false>(w, rm[k], off0 + lr[k] * rep, rend, win, hk, htab);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < kWLoads; ++k) {
+                    const uint32_t rel = off0 + lr[k] * rep;
+                    if (!rm[k] || rel >= rend) continue;
+                    const uint32_t w[4] = {px[k].x, px[k].y, px[k].z, px[k].w};
+                    extract16(w, rm[k], rel, rend, win, hk, htab);
+                }
+            }
+            wave_sync();
+            // complete words [W0, Wend) go out; a trailing partial word waits for the next step
             const bool partial = (wend & 31) != 0;
-            const int64_t nstore = partial ? (W1 - 1 - W0) : (W1 - W0);
+            const uint32_t Wend = partial ? W1 - 1 : W1;
             uint32_t *msgw = reinterpret_cast<uint32_t *>(J.msg);
-            if (nstore > 0) {   // one keystream block per four message words
-                const int64_t B0 = W0 >> 2, B1 = (W0 + nstore - 1) >> 2;
+            if (Wend > W0) {   // one keystream block per four message words
+                const uint32_t B1 = (Wend - 1) >> 2;
                 if constexpr (KS == kKsChaCha20) {
-                    each_stream_block_quad<KS>(J, hp.nonce, lane, B0, B1, [&](int64_t blk, const U4 &ks) {
+                    each_stream_block_quad<KS>(J, hp.nonce, lane, (int64_t)B0, (int64_t)B1, [&](int64_t blk, const U4 &ks) {
                         const uint32_t kw[4] = {ks.x, ks.y, ks.z, ks.w};
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
-                            const int64_t w = 4 * blk + i;
-                            if (w >= W0 && w < W0 + nstore) gstore<uint32_t>(msgw + w, __builtin_bswap32(win[w - W0]) ^ kw[i]);
+                            const uint32_t w = 4 * (uint32_t)blk + (uint32_t)i;
+                            if (blk >= (int64_t)B0 && w >= W0 && w < Wend)
+                                gstore<uint32_t>(msgw + w, __builtin_bswap32(win[w - base]) ^ kw[i]);
                         }
                     });
                 } else {
-                    for (int64_t bq = lane; bq <= B1 - B0; bq += 64) {
-                        const U4 ks = stream_block<KS>(J.key, hp.nonce, kDomainMessage, (uint64_t)(B0 + bq));
-                        const uint32_t kw[4] = {ks.x, ks.y, ks.z, ks.w};
+                    for (uint32_t bq = (uint32_t)lane; bq <= B1 - B0; bq += 64) {
+                        const uint32_t blk = B0 + bq;
+                        const U4 ks = stream_block<KS>(J.key, hp.nonce, kDomainMessage, (uint64_t)blk);
+                        const uint4 v = *reinterpret_cast<const uint4 *>(win + 4 * bq);
+                        const uint4 o = make_uint4(__builtin_bswap32(v.x) ^ ks.x, __builtin_bswap32(v.y) ^ ks.y,
+                                                   __builtin_bswap32(v.z) ^ ks.z, __builtin_bswap32(v.w) ^ ks.w);
+                        const uint32_t w0 = 4 * blk;
+                        if (w0 >= W0 && w0 + 4 <= Wend) {
+                            gstore<uint4>(msgw + w0, o);            // the whole block
+                        } else {
+                            const uint32_t ow[4] = {o.x, o.y, o.z, o.w};
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const int64_t w = 4 * (B0 + bq) + i;
-                            if (w >= W0 && w < W0 + nstore) gstore<uint32_t>(msgw + w, __builtin_bswap32(win[w - W0]) ^ kw[i]);
+                            for (int i = 0; i < 4; ++i)
+                                if (w0 + i >= W0 && w0 + i < Wend) gstore<uint32_t>(msgw + w0 + i, ow[i]);
                         }
                     }
                 }
             }
-            carry_word = partial ? W1 - 1 : -1;
-            carry = partial ? uni(win[W1 - 1 - W0]) : 0u;
+            carry_word = partial ? W1 - 1 : ~0u;
+            carry = partial ? uni(win[W1 - 1 - base]) : 0u;
             wave_sync();
         }
     }
-    if (!EMBED && carry_word >= 0 && lane == 0) {
+    if (!EMBED && carry_word != ~0u && lane == 0) {
         // the message's last word: bits past nbits are stored as zero
         const uint32_t own = be_mask(carry_word, 0, hp.nbits);
         gstore<uint32_t>(reinterpret_cast<uint32_t *>(J.msg) + carry_word,

@@ -425,7 +425,7 @@ __global__ __launch_bounds__(kThreads) void k_fin_tmap(const Job *__restrict__ j
 
 // Work unit u of a quad launch: quads c0 .. c0 + nc - 1 of band pair p (tile
 // rows 2p, 2p + 1) of image j; band pairs are cut into ns segments of at most
-// kQuadSeg quads, s is this one.  Wave-uniform.
+// J.qseg quads, s is this one.  Wave-uniform.
 struct QSeg {
     int j, p, c0, nc, s, ns;
 };
@@ -433,13 +433,14 @@ __device__ __forceinline__ QSeg qseg_of(const Job *jobs, int njobs, const uint32
     QSeg r;
     r.j = (int)uni((uint32_t)find_job<UNIT_QROW>(jobs, njobs, u, ujob));
     const Job &J = jobs[r.j];
-    const uint32_t nq = (uint32_t)((J.tiles_x + 1) >> 1), ns = (nq + kQuadSeg - 1) / kQuadSeg;
+    const uint32_t qs = (uint32_t)J.qseg;
+    const uint32_t nq = (uint32_t)((J.tiles_x + 1) >> 1), ns = (nq + qs - 1) / qs;
     const uint32_t v = u - J.ubase[UNIT_QROW];
     r.p = (int)(v / ns);
     r.s = (int)(v % ns);
     r.ns = (int)ns;
-    r.c0 = r.s * kQuadSeg;
-    r.nc = (int)(nq - (uint32_t)r.c0 < (uint32_t)kQuadSeg ? nq - (uint32_t)r.c0 : (uint32_t)kQuadSeg);
+    r.c0 = r.s * (int)qs;
+    r.nc = (int)(nq - (uint32_t)r.c0 < qs ? nq - (uint32_t)r.c0 : qs);
     return r;
 }
 
@@ -1096,7 +1097,8 @@ constexpr uint32_t kFixPiece = 64;
 __global__ void k_recover_fix(const Job *__restrict__ jobs, const uint8_t *__restrict__ ws) {
     const Job &J = jobs[blockIdx.z];
     if (!J.fast || J.method != RDHEI_EMR) return;
-    const uint32_t nq = (uint32_t)((J.tiles_x + 1) >> 1), ns = (nq + kQuadSeg - 1) / kQuadSeg;
+    const uint32_t qs = (uint32_t)J.qseg;
+    const uint32_t nq = (uint32_t)((J.tiles_x + 1) >> 1), ns = (nq + qs - 1) / qs;
     const uint32_t sg = blockIdx.y + 1u;
     if (sg >= ns) return;
     const uint32_t R = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1116,7 +1118,7 @@ __global__ void k_recover_fix(const Job *__restrict__ jobs, const uint8_t *__res
     const int b = J.fixed_b > 0 ? J.fixed_b : J.meta->b;
     const uint32_t mrep = ((0xFFu << (8 - b)) & 0xFFu) * 0x01010101u;   // replaceable bits, every byte
     const uint32_t cv = carry * 0x01010101u;
-    const uint32_t x0 = sg * (uint32_t)kQuadSeg * 2u * (uint32_t)kTile;
+    const uint32_t x0 = sg * qs * 2u * (uint32_t)kTile;
     const uint32_t n = lead < (uint32_t)J.N - x0 ? lead : (uint32_t)J.N - x0;
     // rows and segments start on 64-byte boundaries; the bytes of the last
     // block past the lead keep their values

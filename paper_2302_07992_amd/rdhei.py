@@ -23,6 +23,7 @@ OP_ENCRYPT, OP_EMBED, OP_EXTRACT, OP_RECOVER = 0, 1, 2, 3
 PLAN_GRAPH, PLAN_EAGER, PLAN_PER_IMAGE = 0, 1, 2
 TUNE_FORCE = 1
 OPT_PER_PIXEL, OPT_MAX_GRID, OPT_RESERVE_WS, OPT_HIDE_MODE, OPT_LMR_MIN_LEVEL, OPT_KEYSTREAM = 1, 2, 3, 4, 5, 6
+OPT_QUAD_SEG = 7
 KEYSTREAM_PHILOX, KEYSTREAM_CHACHA20 = 0, 1
 META_BYTES = 64
 
@@ -31,7 +32,7 @@ EXPORTS = [
     "rdhei_encrypt", "rdhei_embed", "rdhei_extract", "rdhei_recover",
     "rdhei_workspace_size", "rdhei_run_batch", "rdhei_run_batch_static", "rdhei_plan_create", "rdhei_plan_run", "rdhei_plan_destroy", "rdhei_plan_set_grid",
     "rdhei_plan_stage_count", "rdhei_plan_stage_name", "rdhei_plan_run_stage",
-    "rdhei_plan_autotune", "rdhei_plan_stage_grid",
+    "rdhei_plan_autotune", "rdhei_plan_stage_grid", "rdhei_plan_tuned", "rdhei_ctx_set_tune_file",
     "rdhei_lmr_batch", "rdhei_lmr_compress", "rdhei_lmr_decompress", "rdhei_metrics", "rdhei_tile_b",
     "rdhei_strerror", "rdhei_last_error", "rdhei_version",
 ]
@@ -122,6 +123,8 @@ def load_library(path: str = LIB_PATH):
     lib.rdhei_plan_run_stage.argtypes = [vp, i32, vp]
     lib.rdhei_plan_autotune.argtypes = [vp, i32, i32, vp]
     lib.rdhei_plan_stage_grid.argtypes = [vp, i32]
+    lib.rdhei_plan_tuned.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.rdhei_ctx_set_tune_file.argtypes = [vp, ctypes.c_char_p]
     lib.rdhei_lmr_batch.argtypes = [vp, i32, ctypes.POINTER(JobStruct), i32, i32, ctypes.POINTER(ctypes.c_double), vp]
     lib.rdhei_lmr_compress.argtypes = [vp, vp, i32, i32, vp, i64, ctypes.POINTER(i64)]
     lib.rdhei_lmr_decompress.argtypes = [vp, i64, i32, i32, vp, vp]
@@ -221,6 +224,12 @@ class Context:
 
     def set_option(self, option: int, value: int) -> None:
         _check(self.lib.rdhei_ctx_set_option(self.h, option, value), "rdhei_ctx_set_option")
+
+    def set_tune_file(self, path) -> None:
+        """Persist the autotuner's choices in a JSON file (loaded now if it
+        exists, rewritten after every autotune); None: memory only."""
+        _check(self.lib.rdhei_ctx_set_tune_file(self.h, None if path is None else str(path).encode()),
+               "rdhei_ctx_set_tune_file")
 
     def encrypt(self, img: torch.Tensor, enc: torch.Tensor, k1: int, meta: torch.Tensor, method: int = EMR,
                 stream=None, nonce: int = 0) -> None:
@@ -377,6 +386,12 @@ class Plan:
         _check(self.lib.rdhei_plan_autotune(self.h, reps, TUNE_FORCE if force else 0, _stream(stream)),
                "rdhei_plan_autotune")
         return self.stage_grids()
+
+    def tuned(self) -> dict:
+        """The plan's layout variant: hiding mode and quads per work unit."""
+        hm, qs = ctypes.c_int32(), ctypes.c_int32()
+        _check(self.lib.rdhei_plan_tuned(self.h, ctypes.byref(hm), ctypes.byref(qs)), "rdhei_plan_tuned")
+        return {"hide_mode": hm.value, "qseg": qs.value}
 
     def stage_grids(self) -> list:
         return [int(self.lib.rdhei_plan_stage_grid(self.h, k)) for k in range(self.lib.rdhei_plan_stage_count(self.h))]

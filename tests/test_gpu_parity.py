@@ -660,53 +660,85 @@ def test_lmr_bad_case_reported(R, ctx):
     assert R.read_meta(meta).status == R.ENOFIT
 
 
-def test_autotune_keeps_results_and_caches(R):
-    """The launch-shape autotuner only changes workgroup counts: tuned plans
-    give the untuned plans' bytes, every choice is one of the candidates, and a
-    second plan of the same size class reuses the cached choices."""
+def test_autotune_keeps_results_and_caches(R, tmp_path):
+    """The autotuner changes launch shapes and layout variants only (hiding by
+    whole images or by steps, quads per work unit): tuned plans give the
+    untuned plans' bytes, every workgroup count is a candidate, every variant
+    one of those tried; the choices persist in the tune file, and a fresh
+    context reading that file gives a new plan of the same key the same
+    choices without timing anything."""
     print("[autotune]", flush=True)
+    tune_file = tmp_path / "tune.json"
     ctx = R.Context(0)
+    ctx.set_tune_file(tune_file)
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     cand = {0, cus, 2 * cus, 4 * cus, 8 * cus, 16 * cus, 32 * cus}
-    shapes = [(256, 256)] * 12 + [(128, 64)] * 4 + [(45, 77)]
+    shapes = [(256, 256)] * 12 + [(128, 1024)] * 4 + [(45, 77)]
     n = len(shapes)
     imgs = [_dev(_image(1300 + i, *s)) for i, s in enumerate(shapes)]
     k1s, k2s = [17 + i for i in range(n)], [29 + i for i in range(n)]
 
-    def run(tune):
+    def run(c, tune):
         enc = [torch.empty_like(x) for x in imgs]
         rec = [torch.empty_like(x) for x in imgs]
         metas = R.new_meta(n)
         mp = [metas[i] for i in range(n)]
-        p_enc = R.Plan(ctx, R.OP_ENCRYPT, R.make_jobs(imgs, enc, None, mp, k1s, None, shapes))
+        p_enc = R.Plan(c, R.OP_ENCRYPT, R.make_jobs(imgs, enc, None, mp, k1s, None, shapes, nonces=k1s))
         p_enc.run()
         torch.cuda.synchronize()
         caps = [m.capacity_bits for m in R.read_meta(metas)]
-        msgs = [_msg_dev(R, inputs.make_payload(k, c).numpy(), c) for k, c in zip(k2s, caps)]
-        got = [torch.zeros(R.msg_bytes(c), dtype=torch.uint8, device="cuda") for c in caps]
+        msgs = [_msg_dev(R, inputs.make_payload(k, cp).numpy(), cp) for k, cp in zip(k2s, caps)]
+        got = [torch.zeros(R.msg_bytes(cp), dtype=torch.uint8, device="cuda") for cp in caps]
         plans = [p_enc,
-                 R.Plan(ctx, R.OP_EMBED, R.make_jobs(None, enc, msgs, mp, k2s, caps, shapes)),
-                 R.Plan(ctx, R.OP_EXTRACT, R.make_jobs(enc, None, got, mp, k2s, caps, shapes)),
-                 R.Plan(ctx, R.OP_RECOVER, R.make_jobs(enc, rec, None, mp, k1s, None, shapes))]
-        grids = []
+                 R.Plan(c, R.OP_EMBED, R.make_jobs(None, enc, msgs, mp, k2s, caps, shapes)),
+                 R.Plan(c, R.OP_EXTRACT, R.make_jobs(enc, None, got, mp, k2s, caps, shapes)),
+                 R.Plan(c, R.OP_RECOVER, R.make_jobs(enc, rec, None, mp, k1s, None, shapes))]
+        grids, variants = [], []
         for p in plans:
             p.run()
             if tune:
                 grids.append(p.autotune(reps=1))
+                variants.append(p.tuned())
         for p in plans:          # a full pass after tuning, graph re-captured
             p.run()
         torch.cuda.synchronize()
-        outs = [x.cpu().numpy() for x in enc + rec] + [g.cpu().numpy()[: (c + 7) // 8] for g, c in zip(got, caps)]
-        return outs, grids, plans
+        outs = [x.cpu().numpy() for x in enc + rec] + [g.cpu().numpy()[: (cp + 7) // 8] for g, cp in zip(got, caps)]
+        return outs, grids, variants, plans
 
-    base, _, _ = run(False)
-    tuned, grids, plans = run(True)
+    base, _, _, _ = run(ctx, False)
+    tuned, grids, variants, plans = run(ctx, True)
     for a, b in zip(base, tuned):
         assert np.array_equal(a, b)
     for g in grids:
         assert set(g) <= cand
+    assert variants[0]["qseg"] in (1, 2, 4, 8, 16) and variants[1]["hide_mode"] in (0, 1, 2)
     again = plans[0].autotune(reps=1)            # cached: same answer without forcing
     assert again == grids[0]
+    text = tune_file.read_text()
+    assert '"entries"' in text and text.count('"grids"') >= 4
+    # a fresh context with the same file: the choices come from the file
+    ctx2 = R.Context(0)
+    ctx2.set_tune_file(tune_file)
+    again2, grids2, variants2, _ = run(ctx2, True)
+    for a, b in zip(base, again2):
+        assert np.array_equal(a, b)
+    assert grids2 == grids and variants2 == variants
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"rdhei_tune": 1, "entries": {"x": {"hide_mode": 9, "qseg": 4, "grids": [0]}}}')
+    with pytest.raises(R.RdheiError):
+        R.Context(0).set_tune_file(bad)
+
+
+@pytest.mark.parametrize("qseg", [1, 2, 16])
+@pytest.mark.parametrize("shape", [(256, 2048), (1024, 1536)], ids=lambda s: f"{s[0]}x{s[1]}")
+def test_quad_segment_lengths_match_oracle(R, qseg, shape):
+    """RDHEI_OPT_QUAD_SEG: band pairs cut into work units of 1, 2 or 16 quads
+    (rows continued across units by the recovery fix-up) give the oracle's
+    bytes in every role."""
+    c = R.Context(0)
+    c.set_option(R.OPT_QUAD_SEG, qseg)
+    M, N = shape
+    _roundtrip(R, c, _image(qseg + M, M, N), 61 + qseg, 62 + qseg, nonce=qseg)
 
 
 def test_lmr_batch_matches_single_image(R):
