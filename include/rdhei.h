@@ -70,6 +70,9 @@ extern "C" {
 
 #define RDHEI_EMR 0          /* Sec. III-A: map in the LSB plane, b in [2,7]   */
 #define RDHEI_LMR 1          /* Sec. III-B: maps compressed into the MSB plane */
+#define RDHEI_DEMR 2         /* dynamic b (Sec. V, future work): EMR with one b
+                                per 64x64 tile; batch entry points only, sides
+                                multiples of 64, see rdhei_job.btab           */
 
 /* Public side information of one encrypted image (64 bytes, plain data).
  * The paper carries b and the message length implicitly; this record makes
@@ -79,11 +82,13 @@ typedef struct rdhei_meta {
     int32_t height;          /* M                                              */
     int32_t width;           /* N                                              */
     int32_t method;          /* RDHEI_EMR or RDHEI_LMR                         */
-    int32_t b;               /* MSBs compared per pixel (EMR 2..7, LMR 2..8)   */
+    int32_t b;               /* MSBs compared per pixel (EMR 2..7, LMR 2..8;
+                                DEMR: 0, the b of each tile is in its table) */
     int32_t min_level;       /* rotation block sizes 2^min_level..2^max_level  */
     int32_t max_level;
     int64_t redundant;       /* Z_b: pixels labelled 0 (redundant)             */
-    int64_t capacity_bits;   /* b*Z_b (EMR) or (b-1)*Z_b (LMR)                 */
+    int64_t capacity_bits;   /* b*Z_b (EMR), (b-1)*Z_b (LMR), sum over tiles of
+                                b_t*Z_{b_t}(t) (DEMR)                          */
     int64_t map_bits;        /* LMR: bits of the map stream in the MSB plane   */
     int32_t status;          /* RDHEI_OK or the device-side error of a stage   */
     int32_t reserved;
@@ -150,7 +155,18 @@ int rdhei_recover(rdhei_ctx *ctx, const uint8_t *d_marked, int32_t M, int32_t N,
  * ENCRYPT: in = I, out = I_e;  EMBED: out = I_e (modified in place), msg in;
  * EXTRACT: in = I_e', msg out;  RECOVER: in = I_e', out = I'.
  * nonce: ENCRYPT only, the image's keystream nonce (recorded in its meta;
- * the other ops read it from there). */
+ * the other ops read it from there).
+ * btab: RDHEI_DEMR only (NULL otherwise), device memory of (height/64) *
+ * (width/64) bytes: the b of every 64x64 tile in encrypted-tile order
+ * (row-major over the encrypted image), public side information like the
+ * meta.  ENCRYPT writes it; EMBED, EXTRACT and RECOVER read it.  Dynamic b
+ * (the conclusion's suggestion; this library's reading): a pixel (i, j),
+ * j >= 1, is redundant when its b_t most significant bits equal those of its
+ * left neighbour, t its tile (the location-map rule of Sec. III-A carried over
+ * tile borders); b_t in [2,7] is the first b reaching the largest b * Z_b(t)
+ * over the tile's own counts; data hiding replaces the top b_t bits of the
+ * tile's redundant pixels; recovery copies, left to right, the top b_t bits of
+ * the restored left neighbour into each pixel labelled 0. */
 typedef struct rdhei_job {
     const uint8_t *in;
     uint8_t *out;
@@ -160,8 +176,9 @@ typedef struct rdhei_job {
     uint64_t nonce;
     int64_t nbits;           /* EMBED/EXTRACT: bits, or < 0 for the capacity   */
     int32_t height, width;
-    int32_t method;          /* plans run EMR only (RDHEI_EMR)                 */
+    int32_t method;          /* plans and direct batches: RDHEI_EMR, RDHEI_DEMR */
     int32_t reserved;
+    uint8_t *btab;           /* RDHEI_DEMR: the tile b table (see above)        */
 } rdhei_job;
 
 /* Plan flags. */

@@ -170,7 +170,7 @@ int make_layout(int op, const rdhei_job *in, int n, const LayoutOpts &opt, Layou
         const rdhei_job &q = in[i];
         if (q.height < 1 || q.width < 1) return RDHEI_EINVAL;
         if ((int64_t)q.height * q.width > ((int64_t)1 << 31)) return RDHEI_EINVAL;
-        if (q.method != RDHEI_EMR && q.method != RDHEI_LMR) return RDHEI_EINVAL;
+        if (q.method != RDHEI_EMR && q.method != RDHEI_LMR && q.method != RDHEI_DEMR) return RDHEI_EINVAL;
         if (q.method != L.method) return RDHEI_EINVAL;
         if (!q.meta) return RDHEI_EINVAL;
         switch (op) {
@@ -193,7 +193,7 @@ int make_layout(int op, const rdhei_job *in, int n, const LayoutOpts &opt, Layou
         J.M = q.height;
         J.N = q.width;
         J.method = q.method;
-        J.min_level = q.method == RDHEI_EMR ? 1 : opt.lmr_min_level;
+        J.min_level = q.method == RDHEI_LMR ? opt.lmr_min_level : 1;
         J.max_level = floor_log2_min(q.height, q.width);
         const uint64_t MN = (uint64_t)q.height * (uint64_t)q.width;
         const bool rot = op == RDHEI_OP_ENCRYPT || op == RDHEI_OP_RECOVER;
@@ -201,6 +201,17 @@ int make_layout(int op, const rdhei_job *in, int n, const LayoutOpts &opt, Layou
         // along a side take the per-pixel path
         J.fast = rot && !force_per_pixel && q.height % kTile == 0 && q.width % kTile == 0 && aligned16(J.in) &&
                  aligned16(J.out) && q.height / kTile <= kTmapMaxTiles && q.width / kTile <= kTmapMaxTiles ? 1 : 0;
+        if (q.method == RDHEI_DEMR) {
+            // one b per tile: the tiled path for every op, and the tile table;
+            // payload bit offsets stay below 2^32 (images of at most 2^29 pixels)
+            if ((int64_t)q.height * q.width > ((int64_t)1 << 29)) return RDHEI_EINVAL;
+            if (!q.btab || !(rot ? J.fast : (q.height % kTile == 0 && q.width % kTile == 0 &&
+                                             q.height / kTile <= kTmapMaxTiles && q.width / kTile <= kTmapMaxTiles)))
+                return RDHEI_EINVAL;
+            J.btab = q.btab;
+            J.tiles_x = q.width / kTile;
+            J.tiles_y = q.height / kTile;
+        }
         if (J.fast) {
             J.tiles_x = q.width / kTile;
             J.tiles_y = q.height / kTile;
@@ -216,8 +227,13 @@ int make_layout(int op, const rdhei_job *in, int n, const LayoutOpts &opt, Layou
             J.ws_tmap = ws;
             ws = align_up(ws + (J.fast ? tiles * 4 : 0), 256);
             J.ws_stats = ws;
-            ws = align_up(stat_z_offset(J) + 64, 256);   // counter slots, then Z as 64-bit values
-            if (op == RDHEI_OP_RECOVER && q.method == RDHEI_EMR && J.fast && quad_segments(J) > 1) {
+            // counter slots, then Z as 64-bit values, then the DEMR accumulators
+            ws = align_up(stat_dyn_acc(J) + 16, 256);
+            if (q.method == RDHEI_DEMR && op == RDHEI_OP_ENCRYPT) {
+                J.ws_btab = ws;                          // b of every tile, original order
+                ws = align_up(ws + tiles, 256);
+            }
+            if (op == RDHEI_OP_RECOVER && q.method != RDHEI_LMR && J.fast && quad_segments(J) > 1) {
                 J.ws_fix = ws;   // two u16 per image row and quad segment
                 ws = align_up(ws + (uint64_t)J.M * quad_segments(J) * 4u, 256);
             }
@@ -230,7 +246,7 @@ int make_layout(int op, const rdhei_job *in, int n, const LayoutOpts &opt, Layou
         // are cut into 4096-pixel steps (UNIT_SEG)
         const bool hide = op == RDHEI_OP_EMBED || op == RDHEI_OP_EXTRACT;
         const bool whole = whole_ok && whole_eligible(op, q);
-        const bool quads = J.fast && (op == RDHEI_OP_ENCRYPT || (op == RDHEI_OP_RECOVER && q.method == RDHEI_EMR));
+        const bool quads = J.fast && (op == RDHEI_OP_ENCRYPT || (op == RDHEI_OP_RECOVER && q.method != RDHEI_LMR));
         const bool bands = J.fast && op == RDHEI_OP_RECOVER && q.method == RDHEI_LMR;
         const uint32_t cnt[UNIT_KINDS] = {J.fast ? (uint32_t)(J.tiles_x * J.tiles_y) : 0u,
                                           bands ? (uint32_t)J.tiles_y : 0u,
@@ -279,7 +295,8 @@ std::vector<Stage> stages_of(const Layout &Ly, const uint32_t *units_in, std::ve
                              for (int j : pp) { launch_generic_levels(L, j, hj[j]); launch_generic_stats(L, j, hj[j]); }
                          }});
         S.push_back({"finalize_stats", [=](const Launch &L) { launch_finalize(L, true, big, hj); }});
-        if (uq) S.push_back({"encrypt_tiles", [=](const Launch &L) { launch_encrypt_tiles(L, uq, ENC_EMR); }});
+        const int emode = method == RDHEI_DEMR ? ENC_DEMR : ENC_EMR;
+        if (uq) S.push_back({"encrypt_tiles", [=](const Launch &L) { launch_encrypt_tiles(L, uq, emode); }});
         if (!pp.empty())
             S.push_back({"per_pixel_encrypt", [=](const Launch &L) {
                              for (int j : pp) launch_generic_encrypt(L, j, hj[j], ENC_EMR);
@@ -291,10 +308,10 @@ std::vector<Stage> stages_of(const Layout &Ly, const uint32_t *units_in, std::ve
                              for (int j : pp) launch_generic_levels(L, j, hj[j]);
                          }});
         if (ut) S.push_back({"finalize_pyramid", [=](const Launch &L) { launch_finalize(L, false, big, hj); }});
-        const uint32_t urec = method == RDHEI_EMR ? uq : ub;
+        const uint32_t urec = method != RDHEI_LMR ? uq : ub;
         uint32_t fix_rows = 0, fix_segs = 0;   // images cut into quad segments get their rows completed afterwards
         for (const Job &J : hj)
-            if (J.fast && method == RDHEI_EMR && quad_segments(J) > 1) {
+            if (J.fast && method != RDHEI_LMR && quad_segments(J) > 1) {
                 fix_rows = std::max(fix_rows, (uint32_t)J.M);
                 fix_segs = std::max(fix_segs, quad_segments(J));
             }
@@ -478,6 +495,7 @@ int stage(rdhei_ctx *ctx, const Layout &Ly, DevBuf &jobs, DevBuf &ws, hipStream_
     L.g_status = Ly.g_status;
     L.g_part = Ly.g_part;
     L.keystream = Ly.keystream;
+    L.dyn = Ly.method == RDHEI_DEMR;
     return RDHEI_OK;
 }
 
@@ -966,6 +984,7 @@ int plan_issue(rdhei_plan *P, hipStream_t st) {
     L.max_grid = P->max_grid;
     const Layout &Ly = P->layout;
     L.keystream = Ly.keystream;
+    L.dyn = Ly.method == RDHEI_DEMR;
     L.g_status = Ly.g_status;
     L.g_part = Ly.g_part;
     if (P->flags == RDHEI_PLAN_PER_IMAGE) {
@@ -1026,6 +1045,7 @@ int plan_apply(rdhei_plan *P, const TuneRecord &v) {
         Launch L;
         if ((rc = upload_tables(Ly, P->jobs.p, nullptr, true, L))) return rc;
         L.keystream = Ly.keystream;
+        L.dyn = Ly.method == RDHEI_DEMR;
         P->base = L;
         P->layout = Ly;
         P->opts = o;
@@ -1395,7 +1415,7 @@ int rdhei_run_batch(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t n
     Layout Ly;
     rc = make_layout(op, jobs, njobs, opts_of(ctx), Ly);
     if (rc) return rc;
-    if (Ly.method != RDHEI_EMR) return RDHEI_EINVAL;
+    if (Ly.method == RDHEI_LMR) return RDHEI_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     uint8_t *ws = (uint8_t *)d_workspace;
     if (ws) {
@@ -1436,6 +1456,7 @@ int rdhei_run_batch(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t n
     L.g_status = Ly.g_status;
     L.g_part = Ly.g_part;
     L.keystream = Ly.keystream;
+    L.dyn = Ly.method == RDHEI_DEMR;
     for (const Stage &sg : stages_of(Ly, Ly.units, Ly.per_pixel)) sg.fn(L);
     HIPCHK(hipGetLastError());
     return RDHEI_OK;
@@ -1449,7 +1470,7 @@ int rdhei_run_batch_static(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, in
     Layout Ly;
     rc = make_layout(op, jobs, njobs, opts_of(ctx), Ly);
     if (rc) return rc;
-    if (Ly.method != RDHEI_EMR) return RDHEI_EINVAL;
+    if (Ly.method == RDHEI_LMR) return RDHEI_EINVAL;
     size_t off[UNIT_KINDS];
     const uint64_t tb = align_up(table_bytes(Ly, off), 256);
     if (tb + Ly.ws_bytes > kStaticScratchBytes) {
@@ -1474,6 +1495,7 @@ int rdhei_run_batch_static(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, in
     L.g_status = Ly.g_status;
     L.g_part = Ly.g_part;
     L.keystream = Ly.keystream;
+    L.dyn = Ly.method == RDHEI_DEMR;
     for (const Stage &sg : stages_of(Ly, Ly.units, Ly.per_pixel)) sg.fn(L);
     HIPCHK(hipGetLastError());
     return RDHEI_OK;
@@ -1495,12 +1517,13 @@ int rdhei_plan_create(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t
     P->opts = opts_of(ctx);
     P->src.assign(jobs, jobs + njobs);
     rc = make_layout(op, jobs, njobs, P->opts, P->layout);
-    if (!rc && P->layout.method != RDHEI_EMR) rc = RDHEI_EINVAL;
+    if (!rc && P->layout.method == RDHEI_LMR) rc = RDHEI_EINVAL;
     size_t toff[UNIT_KINDS];
     if (!rc) rc = P->jobs.need(table_bytes(P->layout, toff));
     if (!rc) rc = P->ws.need(P->layout.ws_bytes);
     if (!rc) rc = upload_tables(P->layout, P->jobs.p, nullptr, true, P->base);
     P->base.keystream = P->layout.keystream;
+    P->base.dyn = P->layout.method == RDHEI_DEMR;
     if (!rc && flags == RDHEI_PLAN_PER_IMAGE) {
         P->per_image.resize((size_t)njobs);
         size_t total = 0;

@@ -67,6 +67,7 @@ struct Job {
     const uint8_t *lbits;     // LMR: rotated location-map bit plane (encrypted domain)
     const uint8_t *etabits;   // LMR: rotated first-MSB bit plane (encrypted domain)
     const uint8_t *stream;    // LMR encrypt: map stream for the MSB plane
+    uint8_t *btab;            // DEMR: b of every tile, encrypted-tile order (caller's)
     uint64_t key;
     uint64_t nonce;           // keystream nonce (encryption: the caller's; other ops read meta->nonce)
     int64_t nbits;            // embed/extract request (< 0: capacity)
@@ -90,6 +91,7 @@ struct Job {
     uint64_t ws_bytes;        // per-pixel path: byte-per-pixel scratch
     uint64_t ws_fix;          // EMR recovery of images cut into quad segments: per segment and row,
                               // leading pixels without a carry, then the last labelled value (u16 each)
+    uint64_t ws_btab;         // DEMR encryption: b of every tile in original order
 };
 
 // Counter slots of an image's statistics: one per 64 tiles, at most 64.
@@ -101,6 +103,9 @@ __host__ __device__ inline uint32_t stat_slots(const Job &J) {
 __host__ __device__ inline uint64_t stat_z_offset(const Job &J) {
     return J.ws_stats + (uint64_t)stat_slots(J) * kStatWords * 4;
 }
+// DEMR: the image's redundant pixels and capacity summed over its tiles (two
+// u64 after the 64-bit Z values).
+__host__ __device__ inline uint64_t stat_dyn_acc(const Job &J) { return stat_z_offset(J) + 64; }
 
 // Per-tile b of one image (k_dynb.hip): 64x64 tiles numbered from tile_first.
 struct TileBJob {
@@ -121,6 +126,7 @@ struct Launch {
     int max_grid;             // cap on workgroups of a grid-stride launch
     uint64_t g_status = 0, g_part = 0;   // hiding workspace: step counts / ranks, partial-word records
     int keystream = kKsPhilox;           // keystream family of every job of the launch
+    bool dyn = false;                    // the launch's images use one b per tile (RDHEI_DEMR)
 };
 
 void launch_tile_prep(const Launch &L, uint32_t units, bool stats);
@@ -155,7 +161,7 @@ void launch_generic_recover(const Launch &L, int j, const Job &h);
 uint64_t generic_code_bytes(int M, int N, int n);
 
 // Encrypt-kernel modes.
-enum EncMode { ENC_EMR = 0, ENC_LMR = 1, ENC_LMR_MAPS = 2 };
+enum EncMode { ENC_EMR = 0, ENC_LMR = 1, ENC_LMR_MAPS = 2, ENC_DEMR = 3 };
 
 // ---- image metrics (rdhei_metrics) ----
 // One image pair of a metrics launch.  Work units: kMetricChunk-pixel runs of

@@ -35,11 +35,12 @@ __device__ __forceinline__ HideParams hide_params(const Job &J) {
     const rdhei_meta *m = J.meta;
     HideParams h;
     const int b = m->b;
-    h.rep = (uint32_t)(J.method == RDHEI_EMR ? b : b - 1);
+    h.rep = (uint32_t)(J.method == RDHEI_LMR ? b - 1 : b);
     h.shift = (uint32_t)(8 - b);
     const int64_t cap = m->capacity_bits;
     h.nbits = J.nbits < 0 ? cap : J.nbits;
-    h.ok = (m->status == RDHEI_OK) && h.nbits <= cap && h.rep >= 1 && h.rep <= 7;
+    // dynamic b: the b of each tile comes from the tile table (meta.b is 0)
+    h.ok = (m->status == RDHEI_OK) && h.nbits <= cap && (J.method == RDHEI_DEMR || (h.rep >= 1 && h.rep <= 7));
     h.rep = uni(h.rep);
     h.shift = uni(h.shift);
     h.nbits = (int64_t)uni64((uint64_t)h.nbits);
@@ -69,7 +70,7 @@ __device__ __forceinline__ void store16(uint8_t *img, uint64_t pos, uint64_t tot
 __device__ __forceinline__ uint32_t redundant16(const Job &J, uint4 px, uint64_t pos, uint64_t total) {
     uint32_t m = 0;
     if (pos >= total) return 0u;
-    if (J.method == RDHEI_EMR) {
+    if (J.method != RDHEI_LMR) {
         // LSB 0 -> redundant: the inverted LSBs of the bytes, weighted by their
         // bit position with 4-byte dot products
         const uint32_t lo = __builtin_amdgcn_udot4(
@@ -110,6 +111,30 @@ __device__ __forceinline__ Hide4 hide4_params(const HideParams &hp) {
     const uint32_t low = (1u << hp.rep) - 1u;
     h.low_bytes = low * 0x01010101u;
     h.rep_bytes = (low << hp.shift) * 0x01010101u;
+    h.low_pairs = low * 0x00010001u;
+    return h;
+}
+
+// Dynamic b: the b of the tile holding raster pixel pos (16-pixel loads never
+// straddle a tile: tiles are 64 wide).  The row comes from a double-precision
+// product with 1/N and one integer correction (pos < 2^31, so the product is
+// off by at most one).
+__device__ __forceinline__ uint32_t tile_b_at(const Job &J, uint64_t pos, double inv_n) {
+    uint32_t r = (uint32_t)((double)pos * inv_n);
+    if ((uint64_t)(r + 1u) * (uint64_t)J.N <= pos) ++r;
+    if ((uint64_t)r * (uint64_t)J.N > pos) --r;
+    const uint32_t c = (uint32_t)(pos - (uint64_t)r * (uint64_t)J.N);
+    return (uint32_t)gload<uint8_t>(J.btab + (uint64_t)(r >> kTileLog) * (uint64_t)J.tiles_x + (c >> kTileLog));
+}
+
+// Word-wise field moves for a b (EMR-style: the top b bits are replaced).
+__device__ __forceinline__ Hide4 hide4_of_b(uint32_t b) {
+    Hide4 h;
+    h.rep = b;
+    h.shift = 8u - b;
+    const uint32_t low = (1u << b) - 1u;
+    h.low_bytes = low * 0x01010101u;
+    h.rep_bytes = (low << h.shift) * 0x01010101u;
     h.low_pairs = low * 0x00010001u;
     return h;
 }
@@ -290,10 +315,12 @@ __device__ __forceinline__ void wseg_load(const uint8_t *img, uint64_t s0, uint6
 
 // Ranks of the step's redundant pixels: for each load k of the lane, the
 // redundant pixels of the step before its first pixel; T = the step's total.
-__device__ __forceinline__ void step_ranks(const uint32_t rm[kWLoads], uint32_t lr[kWLoads], uint32_t &T) {
-    // counts of loads 0, 1 and 2, 3 in 16-bit halves (at most 1024 each)
-    const uint32_t c01 = (uint32_t)__popc(rm[0]) | ((uint32_t)__popc(rm[1]) << 16);
-    const uint32_t c23 = (uint32_t)__popc(rm[2]) | ((uint32_t)__popc(rm[3]) << 16);
+// cnt[k]: the lane's count for load k (redundant pixels, or with a b per tile
+// their payload bits: at most 7 * 16 per lane, 7,168 per load of the wave).
+__device__ __forceinline__ void step_ranks(const uint32_t cnt[kWLoads], uint32_t lr[kWLoads], uint32_t &T) {
+    // counts of loads 0, 1 and 2, 3 in 16-bit halves (at most 7,168 each)
+    const uint32_t c01 = cnt[0] | (cnt[1] << 16);
+    const uint32_t c23 = cnt[2] | (cnt[3] << 16);
     const uint32_t i01 = wave_scan_incl(c01), i23 = wave_scan_incl(c23);
     const uint32_t t01 = uni((uint32_t)__builtin_amdgcn_readlane((int)i01, 63));
     const uint32_t t23 = uni((uint32_t)__builtin_amdgcn_readlane((int)i23, 63));
@@ -345,15 +372,19 @@ __device__ __forceinline__ void each_stream_block_quad(const Job &J, uint64_t no
 // payload (at most 7 bits per pixel) fits in 32 bits.
 static_assert(kWholeMaxPx * 7 < (1ull << 31), "whole-image bit offsets are 32-bit");
 
-template <bool EMBED, int KS>
+// DYN: a b per tile (RDHEI_DEMR): each 16-pixel load takes its tile's b, and
+// ranks count payload bits instead of redundant pixels (unit = 1 bit, not rep).
+template <bool EMBED, int KS, bool DYN = false>
 __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &hp, uint32_t *win, const uint32_t *htab) {
     const int lane = threadIdx.x & 63;
     const uint8_t *img = EMBED ? J.out : J.in;
     const uint32_t total = (uint32_t)((uint64_t)J.M * (uint64_t)J.N);
     const uint32_t nseg = (uint32_t)((total + kWSegPx - 1) / kWSegPx);
-    const uint32_t rep = hp.rep;
+    const uint32_t rep = DYN ? 4u : hp.rep;          // DYN: only a prefetch estimate
+    const uint32_t unit = DYN ? 1u : hp.rep;         // payload bits per rank step
     const uint32_t nbits = (uint32_t)hp.nbits;
-    const Hide4 hk = hide4_params(hp);
+    const Hide4 hk0 = hide4_params(hp);
+    const double inv_n = 1.0 / (double)J.N;
     uint32_t rank = 0;
     uint32_t carry = 0;          // extraction: bits of the partial word left by the previous step
     uint32_t carry_word = ~0u;   // its word index (none: ~0)
@@ -389,15 +420,21 @@ __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &
             const uint32_t n0 = ns * (uint32_t)kWSegPx;
             wseg_load(img, n0, n0 + (uint32_t)kWSegPx < total ? n0 + (uint32_t)kWSegPx : total, lane, nxt);
         }
-        uint32_t rm[kWLoads];
+        uint32_t rm[kWLoads], cnt[kWLoads];
+        Hide4 hks[kWLoads];
 #pragma unroll
-        for (int k = 0; k < kWLoads; ++k)
-            rm[k] = redundant16(J, px[k], s0 + (uint64_t)k * 1024u + 16 * (uint64_t)lane, s1);
+        for (int k = 0; k < kWLoads; ++k) {
+            const uint32_t pos = s0 + (uint32_t)k * 1024u + 16u * (uint32_t)lane;
+            rm[k] = redundant16(J, px[k], pos, s1);
+            hks[k] = hk0;
+            if (DYN) hks[k] = hide4_of_b(pos < s1 ? tile_b_at(J, pos, inv_n) : 2u);
+            cnt[k] = DYN ? (uint32_t)__popc(rm[k]) * hks[k].rep : (uint32_t)__popc(rm[k]);
+        }
         uint32_t lr[kWLoads], T;
-        step_ranks(rm, lr, T);
-        const uint32_t wstart = rank * rep;
+        step_ranks(cnt, lr, T);
+        const uint32_t wstart = rank * unit;
         if (wstart >= nbits) break;
-        uint32_t wend = (rank + T) * rep;
+        uint32_t wend = (rank + T) * unit;
         if (wend > nbits) wend = nbits;
         rank += T;
         if (T > 0 && EMBED) {
@@ -420,23 +457,23 @@ __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &
             }
             // rank already counts this step
             const uint32_t used = lb - fb + 1u + 2u;
-            if (kPrefetch) msg_prefetch((rank * rep) >> 7, used < 256u ? used : 256u);
+            if (kPrefetch) msg_prefetch((rank * unit) >> 7, used < 256u ? used : 256u);
             wave_sync();
-            if (wend == rank * rep) {   // the whole step inside the payload (uniform)
+            if (wend == rank * unit) {   // the whole step inside the payload (uniform)
 #pragma unroll
                 for (int k = 0; k < kWLoads; ++k) {
                     if (!rm[k]) continue;
                     uint32_t w[4] = {px[k].x, px[k].y, px[k].z, px[k].w};
-                    embed16<false>(w, rm[k], off0 + lr[k] * rep, rend, win + 3, hk, htab);
+                    embed16<false>(w, rm[k], off0 + lr[k] * unit, rend, win + 3, hks[k], htab);
                     gstore<uint4>(J.out + s0 + (uint64_t)k * 1024u + 16 * (uint64_t)lane, make_uint4(w[0], w[1], w[2], w[3]));
                 }
             } else {
 #pragma unroll
                 for (int k = 0; k < kWLoads; ++k) {
-                    const uint32_t rel = off0 + lr[k] * rep;
+                    const uint32_t rel = off0 + lr[k] * unit;
                     if (!rm[k] || rel >= rend) continue;
                     uint32_t w[4] = {px[k].x, px[k].y, px[k].z, px[k].w};
-                    embed16(w, rm[k], rel, rend, win + 3, hk, htab);   // word 0 of the window is a guard
+                    embed16(w, rm[k], rel, rend, win + 3, hks[k], htab);   // word 0 of the window is a guard
                     gstore<uint4>(J.out + s0 + (uint64_t)k * 1024u + 16 * (uint64_t)lane, make_uint4(w[0], w[1], w[2], w[3]));
                 }
             }
@@ -461,19 +498,19 @@ __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &
                 *reinterpret_cast<uint4 *>(win + 4 * q) = z;
             }
             wave_sync();
-            if (wend == rank * rep) {   // the whole step inside the payload (uniform)
+            if (wend == rank * unit) {   // the whole step inside the payload (uniform)
 #pragma unroll
                 for (int k = 0; k < kWLoads; ++k) {
                     const uint32_t w[4] = {px[k].x, px[k].y, px[k].z, px[k].w};
-                    extract16<false>(w, rm[k], off0 + lr[k] * rep, rend, win, hk, htab);
+                    extract16<false>(w, rm[k], off0 + lr[k] * unit, rend, win, hks[k], htab);
                 }
             } else {
 #pragma unroll
                 for (int k = 0; k < kWLoads; ++k) {
-                    const uint32_t rel = off0 + lr[k] * rep;
+                    const uint32_t rel = off0 + lr[k] * unit;
                     if (!rm[k] || rel >= rend) continue;
                     const uint32_t w[4] = {px[k].x, px[k].y, px[k].z, px[k].w};
-                    extract16(w, rm[k], rel, rend, win, hk, htab);
+                    extract16(w, rm[k], rel, rend, win, hks[k], htab);
                 }
             }
             wave_sync();
@@ -527,7 +564,7 @@ __device__ __forceinline__ void hide_image_wave(const Job &J, const HideParams &
 
 // One wave per workgroup, one image per wave (a grid-stride loop when the grid
 // is capped).
-template <bool EMBED, int KS>
+template <bool EMBED, int KS, bool DYN = false>
 __global__ __launch_bounds__(64) void k_hide_wave(const Job *__restrict__ jobs, int njobs, uint32_t units,
                                                   const uint32_t *__restrict__ ujob) {
     __shared__ __align__(16) uint32_t win[kWWinWords];
@@ -542,7 +579,7 @@ __global__ __launch_bounds__(64) void k_hide_wave(const Job *__restrict__ jobs, 
         if (!hp.ok) {
             if (lane == 0 && J.meta->status == RDHEI_OK) J.meta->status = RDHEI_ECAPACITY;
         } else {
-            hide_image_wave<EMBED, KS>(J, hp, win, htab);
+            hide_image_wave<EMBED, KS, DYN>(J, hp, win, htab);
         }
         wave_sync();
     }
@@ -572,9 +609,14 @@ __global__ __launch_bounds__(kThreads) void k_seg_count(const Job *__restrict__ 
         uint4 px[kWLoads];
         step_load(J.in, s0, s1, lane, px);
         uint32_t c = 0;
+        const bool dyn = J.method == RDHEI_DEMR;   // uniform: counts payload bits (a b per tile)
+        const double inv_n = 1.0 / (double)J.N;
 #pragma unroll
-        for (int k = 0; k < kWLoads; ++k)
-            c += (uint32_t)__popc(redundant16(J, px[k], s0 + (uint64_t)k * 1024u + 16 * (uint64_t)lane, s1));
+        for (int k = 0; k < kWLoads; ++k) {
+            const uint64_t pos = s0 + (uint64_t)k * 1024u + 16 * (uint64_t)lane;
+            const uint32_t n = (uint32_t)__popc(redundant16(J, px[k], pos, s1));
+            c += dyn && n ? n * tile_b_at(J, pos, inv_n) : n;
+        }
         c = wave_scan_incl(c);
         if (lane == 63) cnt[u] = c;
     }
@@ -644,7 +686,7 @@ __global__ __launch_bounds__(kScanThreads) void k_seg_scan(const Job *__restrict
 }
 
 // Pass 3: hide (EMBED) or extract the payload bits of every step at its rank.
-template <bool EMBED, int KS>
+template <bool EMBED, int KS, bool DYN = false>
 __global__ __launch_bounds__(kThreads) void k_seg_hide(const Job *__restrict__ jobs, int njobs, uint32_t units,
                                                         const uint32_t *__restrict__ ujob,
                                                         const uint32_t *__restrict__ rank, PartWord *__restrict__ part) {
@@ -664,17 +706,25 @@ __global__ __launch_bounds__(kThreads) void k_seg_hide(const Job *__restrict__ j
             if (lane == 0 && u == J.ubase[UNIT_SEG] && J.meta->status == RDHEI_OK) J.meta->status = RDHEI_ECAPACITY;
             continue;
         }
-        const uint32_t rep = hp.rep;
-        const Hide4 hk = hide4_params(hp);
+        const uint32_t rep = DYN ? 1u : hp.rep;       // payload bits per rank step (DYN: ranks count bits)
+        const Hide4 hk0 = hide4_params(hp);
         const uint64_t total = (uint64_t)J.M * (uint64_t)J.N;
         const uint64_t s0 = (uint64_t)(u - J.ubase[UNIT_SEG]) * kWSegPx;
         const uint64_t s1 = s0 + kWSegPx < total ? s0 + kWSegPx : total;
+        const double inv_n = 1.0 / (double)J.N;
         uint4 px[kWLoads];
         step_load(J.in, s0, s1, lane, px);
-        uint32_t rm[kWLoads], lr[kWLoads], T;
+        uint32_t rm[kWLoads], cnt[kWLoads], lr[kWLoads], T;
+        Hide4 hks[kWLoads];
 #pragma unroll
-        for (int k = 0; k < kWLoads; ++k) rm[k] = redundant16(J, px[k], s0 + (uint64_t)k * 1024u + 16 * (uint64_t)lane, s1);
-        step_ranks(rm, lr, T);
+        for (int k = 0; k < kWLoads; ++k) {
+            const uint64_t pos = s0 + (uint64_t)k * 1024u + 16 * (uint64_t)lane;
+            rm[k] = redundant16(J, px[k], pos, s1);
+            hks[k] = hk0;
+            if (DYN) hks[k] = hide4_of_b(pos < s1 ? tile_b_at(J, pos, inv_n) : 2u);
+            cnt[k] = (uint32_t)__popc(rm[k]) * (DYN ? hks[k].rep : 1u);
+        }
+        step_ranks(cnt, lr, T);
         const uint64_t r0 = uni(rank[u]);
         const int64_t wstart = (int64_t)(r0 * rep);
         int64_t wend = (int64_t)((r0 + T) * rep);
@@ -702,7 +752,7 @@ __global__ __launch_bounds__(kThreads) void k_seg_hide(const Job *__restrict__ j
                 const uint32_t rel = off0 + lr[k] * rep;
                 if (!rm[k] || rel >= rend) continue;
                 uint32_t w[4] = {px[k].x, px[k].y, px[k].z, px[k].w};
-                embed16(w, rm[k], rel, rend, win + 3, hk, htab);   // word 0 of the window is a guard
+                embed16(w, rm[k], rel, rend, win + 3, hks[k], htab);   // word 0 of the window is a guard
                 store16(J.out, s0 + (uint64_t)k * 1024u + 16 * (uint64_t)lane, s1, make_uint4(w[0], w[1], w[2], w[3]));
             }
         } else {
@@ -715,7 +765,7 @@ __global__ __launch_bounds__(kThreads) void k_seg_hide(const Job *__restrict__ j
                 const uint32_t rel = off0 + lr[k] * rep;
                 if (!rm[k] || rel >= rend) continue;
                 const uint32_t w[4] = {px[k].x, px[k].y, px[k].z, px[k].w};
-                extract16(w, rm[k], rel, rend, win, hk, htab);
+                extract16(w, rm[k], rel, rend, win, hks[k], htab);
             }
             wave_sync();
             // one keystream block per four message words; words shared with a
@@ -803,8 +853,14 @@ void launch_hide_images(const Launch &L, uint32_t units, bool embed) {
     }
     with_keystream(L.keystream, [&](auto K) {
         constexpr int KS = decltype(K)::value;
-        if (embed)
+        if (embed && L.dyn)
+            hipLaunchKernelGGL((k_hide_wave<true, KS, true>), dim3(g), dim3(64), 0, L.stream, L.jobs, L.njobs, units,
+                               L.ujob[UNIT_IMG]);
+        else if (embed)
             hipLaunchKernelGGL((k_hide_wave<true, KS>), dim3(g), dim3(64), 0, L.stream, L.jobs, L.njobs, units,
+                               L.ujob[UNIT_IMG]);
+        else if (L.dyn)
+            hipLaunchKernelGGL((k_hide_wave<false, KS, true>), dim3(g), dim3(64), 0, L.stream, L.jobs, L.njobs, units,
                                L.ujob[UNIT_IMG]);
         else
             hipLaunchKernelGGL((k_hide_wave<false, KS>), dim3(g), dim3(64), 0, L.stream, L.jobs, L.njobs, units,
@@ -834,8 +890,12 @@ void launch_embed(const Launch &L, uint32_t units) {
     hipLaunchKernelGGL(k_seg_count, dim3(g), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, units, L.ujob[UNIT_SEG], cnt);
     hipLaunchKernelGGL(k_seg_scan, dim3((unsigned)L.njobs), dim3(kScanThreads), 0, L.stream, L.jobs, cnt);
     with_keystream(L.keystream, [&](auto K) {
-        hipLaunchKernelGGL((k_seg_hide<true, decltype(K)::value>), dim3(g), dim3(kThreads), 0, L.stream, L.jobs,
-                           L.njobs, units, L.ujob[UNIT_SEG], cnt, part);
+        if (L.dyn)
+            hipLaunchKernelGGL((k_seg_hide<true, decltype(K)::value, true>), dim3(g), dim3(kThreads), 0, L.stream, L.jobs,
+                               L.njobs, units, L.ujob[UNIT_SEG], cnt, part);
+        else
+            hipLaunchKernelGGL((k_seg_hide<true, decltype(K)::value>), dim3(g), dim3(kThreads), 0, L.stream, L.jobs,
+                               L.njobs, units, L.ujob[UNIT_SEG], cnt, part);
     });
 }
 
@@ -847,8 +907,12 @@ void launch_extract(const Launch &L, uint32_t units) {
     hipLaunchKernelGGL(k_seg_count, dim3(g), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, units, L.ujob[UNIT_SEG], cnt);
     hipLaunchKernelGGL(k_seg_scan, dim3((unsigned)L.njobs), dim3(kScanThreads), 0, L.stream, L.jobs, cnt);
     with_keystream(L.keystream, [&](auto K) {
-        hipLaunchKernelGGL((k_seg_hide<false, decltype(K)::value>), dim3(g), dim3(kThreads), 0, L.stream, L.jobs,
-                           L.njobs, units, L.ujob[UNIT_SEG], cnt, part);
+        if (L.dyn)
+            hipLaunchKernelGGL((k_seg_hide<false, decltype(K)::value, true>), dim3(g), dim3(kThreads), 0, L.stream,
+                               L.jobs, L.njobs, units, L.ujob[UNIT_SEG], cnt, part);
+        else
+            hipLaunchKernelGGL((k_seg_hide<false, decltype(K)::value>), dim3(g), dim3(kThreads), 0, L.stream, L.jobs,
+                               L.njobs, units, L.ujob[UNIT_SEG], cnt, part);
     });
     const uint32_t n = 2 * units;
     hipLaunchKernelGGL(k_extract_fix, dim3((n + 255) / 256), dim3(256), 0, L.stream, L.jobs, part, n, 0);

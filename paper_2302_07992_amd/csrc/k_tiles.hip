@@ -47,7 +47,11 @@ __device__ __forceinline__ void unit_range(uint32_t units, uint32_t &u0, uint32_
 // thresholds at once.  Counts stay in registers across the tiles of one image
 // and go to one of the image's counter slots with one atomic add per wave.
 // ----------------------------------------------------------------------------
-template <bool STATS, int KS>
+// DYN (dynamic b, RDHEI_DEMR): every tile's counts give the tile's own b_t,
+// the first b in 2..7 reaching the largest b * Z_b(t); b_t goes to the
+// image's tile table (original order) and Z_{b_t}(t), b_t * Z_{b_t}(t) are
+// added to the image's totals.
+template <bool STATS, int KS, bool DYN = false>
 __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ jobs, int njobs,
                                                          uint8_t *__restrict__ ws, uint32_t units,
                                                          const uint32_t *__restrict__ ujob) {
@@ -204,7 +208,7 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
         }
 
         if (STATS) {
-            if (j != cur_j || held == kHeldMax) {
+            if (!DYN && (j != cur_j || held == kHeldMax)) {
                 flush(cur_j);
                 cur_j = j;
             }
@@ -256,9 +260,38 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
                 sx = c;
             }
             ++held;
+            if (DYN) {
+                // this tile's Z_b, b = 2..7 (64 pixels per lane), its b_t and capacity
+                uint32_t best_b = 2, best_z = 0, best_s = 0;
+#pragma unroll
+                for (int b = 2; b <= 7; ++b) {
+                    const uint32_t m = 0x01010101u << (8 - b);
+                    const uint32_t ge = (uint32_t)__popc(ones & m) + 2u * (uint32_t)__popc(twos & m) +
+                                        4u * (uint32_t)__popc(fours & m) + 8u * (uint32_t)__popc(eights & m) +
+                                        16u * (uint32_t)__popc(hi[0] & m);
+                    const uint32_t z = uni((uint32_t)__builtin_amdgcn_readlane((int)wave_scan_incl(64u - ge), 63));
+                    if (b == 2 || (uint32_t)b * z > best_s) {
+                        best_b = (uint32_t)b;
+                        best_z = z;
+                        best_s = (uint32_t)b * z;
+                    }
+                }
+                if (lane == 0) {
+                    ws[J.ws_btab + t] = (uint8_t)best_b;
+                    unsigned long long *acc = reinterpret_cast<unsigned long long *>(ws + stat_dyn_acc(J));
+                    if (best_z) {
+                        atomicAdd(acc, (unsigned long long)best_z);
+                        atomicAdd(acc + 1, (unsigned long long)best_s);
+                    }
+                }
+                ones = twos = fours = eights = 0;
+#pragma unroll
+                for (int p2 = 0; p2 < kHiPlanes; ++p2) hi[p2] = 0;
+                held = 0;
+            }
         }
     }
-    flush(cur_j);
+    if (!DYN) flush(cur_j);
 }
 
 // Clears the statistics record of every tiled image before k_tile_prep<true>
@@ -274,6 +307,8 @@ __global__ void k_stats_zero(const Job *__restrict__ jobs, int njobs, uint8_t *_
         st[2 * q] = make_uint4(0, 0, 0, 0);
         st[2 * q + 1] = make_uint4(0, 0, 0, 0);
     }
+    if (jobs[j].method == RDHEI_DEMR && blockIdx.y == 0)
+        *reinterpret_cast<uint4 *>(ws + stat_dyn_acc(jobs[j])) = make_uint4(0, 0, 0, 0);
 }
 
 // ----------------------------------------------------------------------------
@@ -304,7 +339,17 @@ __device__ void finish_stats(const Job &J, uint8_t *ws) {
     for (int b = 2; b <= 8; ++b) Z[b] = (int64_t)v[b - 2];
     int64_t *zout = reinterpret_cast<int64_t *>(ws + stat_z_offset(J));
     for (int b = 2; b <= 8; ++b) zout[b - 2] = Z[b];
-    if (J.method == RDHEI_EMR) {
+    if (J.method == RDHEI_DEMR) {
+        const unsigned long long *acc = reinterpret_cast<const unsigned long long *>(ws + stat_dyn_acc(J));
+        rdhei_meta m;
+        m.height = J.M; m.width = J.N; m.method = RDHEI_DEMR; m.b = 0;
+        m.min_level = J.min_level; m.max_level = J.max_level;
+        m.redundant = (int64_t)acc[0]; m.capacity_bits = (int64_t)acc[1];
+        m.map_bits = 0; m.status = RDHEI_OK;
+        m.reserved = 0;
+        m.nonce = J.nonce;
+        *J.meta = m;
+    } else if (J.method == RDHEI_EMR) {
         int best = 2;
         for (int b = 3; b <= 7; ++b)
             if ((int64_t)b * Z[b] > (int64_t)best * Z[best]) best = b;
@@ -498,7 +543,7 @@ __global__ __launch_bounds__(kThreads) void k_encrypt_quad(const Job *__restrict
             halo_n = hb;
         }
         rc_n = gload<uint4>(ws + J.ws_codes + (uint64_t)t * kCodeRecord + 16 * (lane % (kCodeRecord / 16)));
-        b_n = (uint32_t)gload<int32_t>(&J.meta->b);
+        b_n = MODE == ENC_DEMR ? (uint32_t)gload<uint8_t>(ws + J.ws_btab + t) : (uint32_t)gload<int32_t>(&J.meta->b);
         st_n = (uint32_t)gload<int32_t>(&J.meta->status);
         tm_n = gload<uint32_t>(ws + J.ws_tmap + 4 * (uint64_t)t);
     };
@@ -543,11 +588,14 @@ __global__ __launch_bounds__(kThreads) void k_encrypt_quad(const Job *__restrict
         c = c1;
         S = S1;
         if (!have) continue;                                              // uniform per wave
-        if (MODE == ENC_EMR && st_cur != (uint32_t)RDHEI_OK) continue;     // uniform per wave
+        constexpr bool kEmrLike = MODE == ENC_EMR || MODE == ENC_DEMR;      // the map in the LSB plane
+        if (kEmrLike && st_cur != (uint32_t)RDHEI_OK) continue;           // uniform per wave
         const int b = J.fixed_b > 0 ? J.fixed_b : (int)b_cur;
         int dy, dx;
         uint32_t up;
         tmap_unpack(tm, dy, dx, up);
+        // dynamic b: the tile's b into the table, at the tile's encrypted position
+        if (MODE == ENC_DEMR && lane == 0) gstore<uint8_t>(J.btab + dy * J.tiles_x + dx, (uint8_t)b);
         // the byte left of rows 4q..4q+3 of this tile (column 0 of the image has none)
         const uint32_t halo = side ? edge[slot][wave - 1][q]
                                    : (tx == 0 ? 0u : (first ? halo_mem : edge_prev));
@@ -572,7 +620,7 @@ __global__ __launch_bounds__(kThreads) void k_encrypt_quad(const Job *__restrict
                 const uint32_t d = (w[k] ^ lw[k]) & topm;
                 uint32_t lbl = ((((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d) >> 7) & 0x01010101u;  // l per byte
                 if (k == 0 && tx == 0 && g == 0) lbl |= 1u;                                  // column 0
-                if (MODE == ENC_EMR) o[i][k] = (w[k] & 0xFEFEFEFEu) | lbl;
+                if (kEmrLike) o[i][k] = (w[k] & 0xFEFEFEFEu) | lbl;
                 else o[i][k] = (lbl << 1) | ((w[k] >> 7) & 0x01010101u);                     // l<<1 | eta
             }
         }
@@ -621,7 +669,7 @@ __global__ __launch_bounds__(kThreads) void k_encrypt_quad(const Job *__restrict
             } else {
                 const U4 sk = stream_block_quad<KS>(J.key, nz, kDomainImage, didx >> 4);
                 uint4 e;
-                if (MODE == ENC_EMR) {
+                if (kEmrLike) {
                     e = make_uint4(qv.x ^ (sk.x & 0xFEFEFEFEu), qv.y ^ (sk.y & 0xFEFEFEFEu),
                                    qv.z ^ (sk.z & 0xFEFEFEFEu), qv.w ^ (sk.w & 0xFEFEFEFEu));
                 } else {
@@ -812,8 +860,13 @@ __global__ __launch_bounds__(kThreads) void k_recover_band_lmr(const Job *__rest
 static __constant__ perm4::InvTables kInvTables = perm4::kInvTables;
 static __constant__ glide4::Tables kGlideTables = glide4::kTables;
 
+// DYN (dynamic b, RDHEI_DEMR): each tile has its own b (from the tile table,
+// at the tile's encrypted position) and a pixel labelled 0 takes the top b
+// bits of its restored left neighbour, so what crosses a tile border is the
+// restored last pixel of the row (last labelled value in the tile's replaceable
+// bits, decrypted bits below), not the last labelled value.
 // (At most 128 VGPRs: four waves per SIMD, which is what the LDS allows.)
-template <int KS>
+template <int KS, bool DYN = false>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_recover_quad_emr(
     const Job *__restrict__ jobs, int njobs, uint8_t *__restrict__ ws, uint32_t units, const uint32_t *__restrict__ ujob) {
     constexpr int kW = kThreads / 64;
@@ -826,6 +879,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     // the column of its first labelled pixel (64: none; segmented images only)
     __shared__ __align__(8) uint16_t sums[2][kW][kTile];
     __shared__ __align__(8) uint16_t carry[2][2][kTile];       // per band half: carry into the next quad
+    __shared__ __align__(4) uint8_t lastpx[DYN ? 2 : 1][kW][kTile];   // DYN: decrypted column 63 of each tile row
+    __shared__ uint32_t tileb[DYN ? 2 : 1][kW];                       // DYN: each wave's tile b
     const int lane = threadIdx.x & 63, wave = (int)uni(threadIdx.x >> 6);   // wave-uniform
     const int q = lane >> 2, g = lane & 3;                      // rows 4q..4q+3, columns 16g..16g+15
     const int side = wave & 1, half = wave >> 1;                // this wave's tile in the quad
@@ -869,7 +924,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         if (!tile_of(P, ty, tx)) return;
         const Job &J = jobs[P.S.j];
         tm = gload<uint32_t>(ws + J.ws_tmap + 4 * (uint64_t)(ty * J.tiles_x + tx));
-        bb = (uint32_t)gload<int32_t>(&J.meta->b);
+        if (DYN) {
+            int ey, ex;
+            uint32_t up;
+            tmap_unpack(uni(tm), ey, ex, up);
+            bb = (uint32_t)gload<uint8_t>(J.btab + ey * J.tiles_x + ex);
+        } else {
+            bb = (uint32_t)gload<int32_t>(&J.meta->b);
+        }
     };
     uint4 e_n[4], rc_n = make_uint4(0, 0, 0, 0);
     auto fetch = [&](const Pos &P, uint32_t tm) {
@@ -1003,6 +1065,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
                 *reinterpret_cast<uint2 *>(&sums[slot][wave][4 * q]) =
                     make_uint2((tsum[0] | (fcol[0] << 9)) | ((tsum[1] | (fcol[1] << 9)) << 16),
                                (tsum[2] | (fcol[2] << 9)) | ((tsum[3] | (fcol[3] << 9)) << 16));
+            if (DYN && g == 3)
+                *reinterpret_cast<uint32_t *>(&lastpx[DYN ? slot : 0][wave][4 * q]) =
+                    (Do[0][3] >> 24) | ((Do[1][3] >> 24) << 8) | ((Do[2][3] >> 24) << 16) | (Do[3][3] & 0xFF000000u);
+            if (DYN && lane == 0) tileb[DYN ? slot : 0][wave] = bq;
         }
         __syncthreads();
         if (have) {
@@ -1028,9 +1094,25 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const uint32_t from_left = first ? 0u : cr[i];           // into the quad (none at a segment start)
-                const uint32_t tin = lf[i] ? lf[i] : from_left;          // into this tile
+                uint32_t tin = lf[i] ? lf[i] : from_left;                // into this tile
+                if (DYN) {
+                    // the restored last pixel of the row of the tile to the left
+                    tin = from_left;
+                    if (side) {
+                        const uint32_t src = lf[i] ? lf[i] : from_left;
+                        const uint32_t bl = tileb[DYN ? slot : 0][wave - 1];
+                        const uint32_t ml = (0xFFu << (8 - bl)) & 0xFFu;
+                        const uint32_t dl = lastpx[DYN ? slot : 0][wave - 1][4 * q + i];
+                        tin = src ? ((src & ml) | (dl & ~ml & 0xFFu) | 0x100u) : 0u;
+                    }
+                }
                 const uint32_t cin = excl[i] ? excl[i] : tin;            // into this lane
                 nc[i] = tsum[i] ? tsum[i] : tin;                         // out of this tile
+                if (DYN) {
+                    const uint32_t dl = qperm<0xFF>(Do[i][3] >> 24);     // this row's column 63 (lane 3 of the row)
+                    const uint32_t mt = mrep & 0xFFu;
+                    nc[i] = nc[i] ? ((nc[i] & mt) | (dl & ~mt & 0xFFu) | 0x100u) : 0u;
+                }
                 uint32_t f = (cin & 0xFFu) << 24;
                 uint32_t o[4];
 #pragma unroll
@@ -1094,9 +1176,70 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
 // completes those pixels, kFixPiece bytes at a time (all loads of a piece
 // before its stores).  Records are segment-major: [s][row].  Image blockIdx.z.
 constexpr uint32_t kFixPiece = 64;
+
+// Dynamic b: a pixel labelled 0 takes the top b bits (b of its tile) of its
+// restored left neighbour, so the value entering segment sg is the restored
+// last pixel of the row before it: from the nearest segment to the left whose
+// row end is known (fix_sum flag 0x100; segment 0 always is), carried through
+// the tiles of the segments between (none labelled in this row, so each
+// tile's restored last pixel is the carry in its b bits and its decrypted
+// value below them, as the quad kernel left it), then spread over the lead
+// tile by tile.
+__device__ void recover_fix_dyn(const Job &J, const uint8_t *ws, uint32_t R, uint32_t sg, uint32_t qs, uint32_t ns,
+                                uint32_t lead, const uint16_t *fix_sum) {
+    const uint32_t *tmap = reinterpret_cast<const uint32_t *>(ws + J.ws_tmap);
+    const uint32_t ty = R >> kTileLog;
+    auto mask_of = [&](uint32_t tx) {           // replaceable bits of tile (ty, tx)
+        int ey, ex;
+        uint32_t up;
+        tmap_unpack(tmap[ty * (uint32_t)J.tiles_x + tx], ey, ex, up);
+        const uint32_t b = J.btab[ey * J.tiles_x + ex];
+        return (0xFFu << (8 - b)) & 0xFFu;
+    };
+    uint8_t *row = J.out + (uint64_t)R * (uint64_t)J.N;
+    uint32_t k = sg;
+    uint32_t carry = 0;
+    while (k-- > 0) {
+        const uint32_t sum = fix_sum[(uint64_t)k * J.M + R];
+        if (sum & 0x100u) {
+            carry = sum & 0xFFu;
+            break;
+        }
+    }
+    const uint32_t seg_px = qs * 2u * (uint32_t)kTile;
+    for (uint32_t x = (k + 1) * seg_px; x < sg * seg_px; x += kTile) {   // unlabelled segments between
+        const uint32_t m = mask_of(x >> kTileLog);
+        carry = (carry & m) | (row[x + kTile - 1] & ~m & 0xFFu);
+    }
+    const uint32_t x0 = sg * seg_px;
+    const uint32_t n = lead < (uint32_t)J.N - x0 ? lead : (uint32_t)J.N - x0;
+    for (uint32_t t0 = 0; t0 < n; t0 += kTile) {                         // the lead, one tile at a time
+        const uint32_t m = mask_of((x0 + t0) >> kTileLog);
+        const uint32_t cv = (carry & m) * 0x01010101u, mb = m * 0x01010101u;
+        const uint32_t e = n - t0 < (uint32_t)kTile ? n - t0 : (uint32_t)kTile;
+#pragma unroll
+        for (int q = 0; q < kTile / 16; ++q) {
+            const uint32_t k16 = 16u * (uint32_t)q;
+            if (k16 >= e) continue;
+            uint4 v = *reinterpret_cast<const uint4 *>(row + x0 + t0 + k16);
+            uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t lo = k16 + 4u * (uint32_t)j;
+                const uint32_t take = lo >= e ? 0u : (e - lo >= 4u ? 4u : e - lo);
+                const uint32_t bm = take == 4u ? 0xFFFFFFFFu : ((1u << (8u * take)) - 1u);
+                const uint32_t pm = bm & mb;
+                w[j] = (w[j] & ~pm) | (cv & pm);
+            }
+            *reinterpret_cast<uint4 *>(row + x0 + t0 + k16) = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+        if (e == (uint32_t)kTile) carry = (carry & m) | (row[x0 + t0 + kTile - 1] & ~m & 0xFFu);
+    }
+}
+
 __global__ void k_recover_fix(const Job *__restrict__ jobs, const uint8_t *__restrict__ ws) {
     const Job &J = jobs[blockIdx.z];
-    if (!J.fast || J.method != RDHEI_EMR) return;
+    if (!J.fast || J.method == RDHEI_LMR) return;
     const uint32_t qs = (uint32_t)J.qseg;
     const uint32_t nq = (uint32_t)((J.tiles_x + 1) >> 1), ns = (nq + qs - 1) / qs;
     const uint32_t sg = blockIdx.y + 1u;
@@ -1107,6 +1250,10 @@ __global__ void k_recover_fix(const Job *__restrict__ jobs, const uint8_t *__res
     const uint16_t *fix_sum = fix_lead + (uint64_t)J.M * ns;
     const uint32_t lead = fix_lead[(uint64_t)sg * J.M + R];
     if (!lead) return;
+    if (J.method == RDHEI_DEMR) {
+        recover_fix_dyn(J, ws, R, sg, qs, ns, lead, fix_sum);
+        return;
+    }
     uint32_t carry = 0;
     for (uint32_t t = sg; t-- > 0;) {
         const uint32_t sum = fix_sum[(uint64_t)t * J.M + R];
@@ -1195,7 +1342,10 @@ void launch_tile_prep(const Launch &L, uint32_t units, bool stats) {
     }
     with_keystream(L.keystream, [&](auto K) {
         constexpr int KS = decltype(K)::value;
-        if (stats)
+        if (stats && L.dyn)
+            hipLaunchKernelGGL((k_tile_prep<true, KS, true>), dim3(persistent_grid(L, k_tile_prep<true, KS, true>, units)),
+                               dim3(kThreads), 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+        else if (stats)
             hipLaunchKernelGGL((k_tile_prep<true, KS>), dim3(persistent_grid(L, k_tile_prep<true, KS>, units)),
                                dim3(kThreads), 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
         else
@@ -1233,6 +1383,9 @@ void launch_encrypt_tiles(const Launch &L, uint32_t units, int mode) {
         if (mode == ENC_EMR)
             hipLaunchKernelGGL((k_encrypt_quad<ENC_EMR, KS>), dim3(persistent_grid(L, k_encrypt_quad<ENC_EMR, KS>, units)),
                                bl, 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
+        else if (mode == ENC_DEMR)
+            hipLaunchKernelGGL((k_encrypt_quad<ENC_DEMR, KS>), dim3(persistent_grid(L, k_encrypt_quad<ENC_DEMR, KS>, units)),
+                               bl, 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
         else if (mode == ENC_LMR)
             hipLaunchKernelGGL((k_encrypt_quad<ENC_LMR, KS>), dim3(persistent_grid(L, k_encrypt_quad<ENC_LMR, KS>, units)),
                                bl, 0, L.stream, L.jobs, L.njobs, L.ws, units, UJ);
@@ -1247,11 +1400,15 @@ void launch_recover_bands(const Launch &L, uint32_t units, int method, uint32_t 
     if (!units) return;
     const uint32_t *UJ = L.ujob[UNIT_BAND];
     const dim3 bl(kThreads);
-    if (method == RDHEI_EMR) {
+    if (method != RDHEI_LMR) {
         with_keystream(L.keystream, [&](auto K) {
             constexpr int KS = decltype(K)::value;
-            hipLaunchKernelGGL((k_recover_quad_emr<KS>), dim3(persistent_grid(L, k_recover_quad_emr<KS>, units)), bl, 0,
-                               L.stream, L.jobs, L.njobs, L.ws, units, L.ujob[UNIT_QROW]);
+            if (L.dyn)
+                hipLaunchKernelGGL((k_recover_quad_emr<KS, true>), dim3(persistent_grid(L, k_recover_quad_emr<KS, true>, units)),
+                                   bl, 0, L.stream, L.jobs, L.njobs, L.ws, units, L.ujob[UNIT_QROW]);
+            else
+                hipLaunchKernelGGL((k_recover_quad_emr<KS>), dim3(persistent_grid(L, k_recover_quad_emr<KS>, units)), bl, 0,
+                                   L.stream, L.jobs, L.njobs, L.ws, units, L.ujob[UNIT_QROW]);
         });
         if (fix_rows)
             hipLaunchKernelGGL(k_recover_fix, dim3((fix_rows + 255) / 256, fix_segs - 1, (unsigned)L.njobs), dim3(256),

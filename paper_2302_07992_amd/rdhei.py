@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librdhei.so")
 
 OK, EINVAL, ECAPACITY, ENOFIT, ENOMEM, EDEVICE, ECORRUPT = 0, -1, -2, -3, -4, -5, -6
-EMR, LMR = 0, 1
+EMR, LMR, DEMR = 0, 1, 2
 OP_ENCRYPT, OP_EMBED, OP_EXTRACT, OP_RECOVER = 0, 1, 2, 3
 PLAN_GRAPH, PLAN_EAGER, PLAN_PER_IMAGE = 0, 1, 2
 TUNE_FORCE = 1
@@ -69,13 +69,13 @@ class JobStruct(ctypes.Structure):
                 ("meta", ctypes.c_void_p), ("key", ctypes.c_uint64), ("nonce", ctypes.c_uint64),
                 ("nbits", ctypes.c_int64),
                 ("height", ctypes.c_int32), ("width", ctypes.c_int32), ("method", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("btab", ctypes.c_void_p)]
 
 
 # numpy view of rdhei_job, for building large job tables without Python loops
 JOB_DTYPE = np.dtype([("inp", "<u8"), ("out", "<u8"), ("msg", "<u8"), ("meta", "<u8"), ("key", "<u8"),
                       ("nonce", "<u8"), ("nbits", "<i8"), ("height", "<i4"), ("width", "<i4"), ("method", "<i4"),
-                      ("reserved", "<i4")])
+                      ("reserved", "<i4"), ("btab", "<u8")])
 assert JOB_DTYPE.itemsize == ctypes.sizeof(JobStruct)
 
 
@@ -331,9 +331,11 @@ def make_metric_jobs(pairs) -> ctypes.Array:
 
 
 def make_jobs(ins: Sequence, outs: Sequence, msgs: Sequence, metas: Sequence, keys: Sequence[int],
-              nbits: Sequence[int], shapes: Sequence, method: int = EMR, nonces: Optional[Sequence[int]] = None):
+              nbits: Sequence[int], shapes: Sequence, method: int = EMR, nonces: Optional[Sequence[int]] = None,
+              btabs: Optional[Sequence] = None):
     """Job array from per-image pointers (ints) or tensors (None allowed);
-    nonces: per-image keystream nonces of an ENCRYPT batch (default 0)."""
+    nonces: per-image keystream nonces of an ENCRYPT batch (default 0);
+    btabs: DEMR tile b tables (device, (height/64) * (width/64) bytes each)."""
     n = len(keys)
     arr = (JobStruct * n)()
 
@@ -353,6 +355,7 @@ def make_jobs(ins: Sequence, outs: Sequence, msgs: Sequence, metas: Sequence, ke
         arr[i].height, arr[i].width = int(shapes[i][0]), int(shapes[i][1])
         arr[i].method = method
         arr[i].reserved = 0
+        arr[i].btab = p(btabs[i]) if btabs is not None else None
     return arr
 
 
