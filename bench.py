@@ -110,6 +110,7 @@ def parse():
     ap.add_argument("--single-reps", type=int, default=200, help="runs of the one-image latency leg (0: skip)")
     ap.add_argument("--metrics-reps", type=int, default=3, help="timed runs of the batch metrics leg (0: skip)")
     ap.add_argument("--tile-b-reps", type=int, default=3, help="timed runs of the per-tile b leg (0: skip)")
+    ap.add_argument("--demr", type=int, default=1, help="dynamic-b round trip over the batch (0: skip)")
     ap.add_argument("--large-sides", default="8192,16384", help="single large images timed stage by stage ('' to skip)")
     ap.add_argument("--lmr-images", type=int, default=2000, help="LMR batch of 512x512 images (0: skip)")
     ap.add_argument("--keystream-images", type=int, default=2000,
@@ -465,6 +466,134 @@ def large_bench(args, tasks=None):
             tasks.append((f"large{side}", 0, back))
         del img, enc, rec, msg, got
         torch.cuda.empty_cache()
+    return out
+
+
+def demr_bench(args, imgs, k1, k2, nonces, caps_emr, tasks=None):
+    """Dynamic b (one b per 64x64 tile, RDHEI_DEMR) over the same batch: the
+    same four roles as batched graph plans, the receiver's two roles on two
+    streams, payload at each image's tile-wise capacity; the DER gained over
+    one b per image, the step time, and (tasks) every image against the
+    oracle's demr_* roles."""
+    import numpy as np
+    import torch
+
+    from paper_2302_07992_amd import rdhei
+    dev = imgs.device
+    B, S = imgs.shape[0], imgs.shape[1]
+    MN = S * S
+    ctx = rdhei.Context(0)
+    enc = torch.empty_like(imgs)
+    rec = torch.empty_like(imgs)
+    btab = torch.empty(B, (S // 64) ** 2, dtype=torch.uint8, device=dev)
+    metas = rdhei.new_meta(B)
+    mp = [metas[i] for i in range(B)]
+    shapes = [(S, S)] * B
+    bts = list(btab)
+    enc_plan = rdhei.Plan(ctx, rdhei.OP_ENCRYPT, rdhei.make_jobs(list(imgs), list(enc), None, mp, k1, None, shapes,
+                                                                 method=rdhei.DEMR, nonces=nonces, btabs=bts))
+    enc_plan.run()
+    torch.cuda.synchronize()
+    meta = rdhei.read_meta_array(metas)
+    assert (meta["status"] == 0).all()
+    caps = meta["capacity_bits"].astype(np.int64)
+    sizes = np.array([rdhei.msg_bytes(int(c)) for c in caps], dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    g = torch.Generator(device=dev)
+    g.manual_seed(777)
+    payload = torch.randint(0, 256, (int(sizes.sum()),), generator=g, device=dev, dtype=torch.int32).to(torch.uint8)
+    got = torch.zeros_like(payload)
+    bp, bx = payload.data_ptr(), got.data_ptr()
+    plans = {
+        "encrypt": enc_plan,
+        "embed": rdhei.Plan(ctx, rdhei.OP_EMBED, rdhei.make_jobs(None, list(enc), [bp + int(o) for o in offs], mp, k2,
+                                                                 caps, shapes, method=rdhei.DEMR, btabs=bts)),
+        "extract": rdhei.Plan(ctx, rdhei.OP_EXTRACT, rdhei.make_jobs(list(enc), None, [bx + int(o) for o in offs], mp, k2,
+                                                                     caps, shapes, method=rdhei.DEMR, btabs=bts)),
+        "recover": rdhei.Plan(ctx, rdhei.OP_RECOVER, rdhei.make_jobs(list(enc), list(rec), None, mp, k1, None, shapes,
+                                                                     method=rdhei.DEMR, btabs=bts)),
+    }
+    side = torch.cuda.Stream(device=dev)
+
+    def step():
+        main = torch.cuda.current_stream()
+        plans["encrypt"].run(main)
+        plans["embed"].run(main)
+        marked = torch.cuda.Event()
+        marked.record(main)
+        side.wait_event(marked)
+        plans["recover"].run(side)
+        plans["extract"].run(main)
+        restored = torch.cuda.Event()
+        restored.record(side)
+        main.wait_event(restored)
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    if args.autotune > 0 and not args.max_grid:
+        for p in plans.values():
+            p.autotune(reps=args.autotune)
+        step()
+        torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    stages = {}
+    for k, p in plans.items():
+        for si, name in enumerate(p.stages()):
+            p.run_stage(si)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(args.stage_reps):
+                p.run_stage(si)
+            b.record()
+            torch.cuda.synchronize()
+            stages[f"{k}/{name}"] = round(a.elapsed_time(b) / args.stage_reps, 4)
+    step()
+    torch.cuda.synchronize()
+    restored_lsb = bool(torch.equal(rec >> 1, imgs >> 1))
+    # the first capacity_bits bits of each message buffer (MSB first) must come back
+    full = caps // 8
+    d = np.zeros(int(sizes.sum()) + 1, dtype=np.int64)
+    np.add.at(d, offs, 1)
+    np.add.at(d, offs + full, -1)
+    mask = np.where(np.cumsum(d[:-1]) > 0, 0xFF, 0).astype(np.uint8)
+    part = caps % 8 != 0
+    mask[(offs + full)[part]] = (0xFF << (8 - caps[part] % 8)) & 0xFF
+    ok_bits = not bool(((payload ^ got) & torch.from_numpy(mask).to(dev)).any())
+    hist = np.bincount(btab.cpu().numpy().ravel(), minlength=8)[2:8]
+    px = B * MN
+    out = {"workload": f"the same {B} x {S}x{S} batch, one b per 64x64 tile, payload at capacity",
+           "ms_per_step": round(ms, 4), "value": round(px / (ms * 1e-3) / 1e6, 1), "unit": "Mpixel/s",
+           "der_bpp": round(float(caps.sum()) / px, 4), "der_bpp_one_b": round(float(np.sum(caps_emr)) / px, 4),
+           "images_gaining": int((caps > np.asarray(caps_emr)).sum()),
+           "side_info_bytes_per_image": int((S // 64) ** 2), "tile_b_hist_2_7": [int(x) for x in hist],
+           "stages_ms": stages, "payload_ok": ok_bits, "upper_bits_restored": restored_lsb}
+    log(f"[demr] {ms:.3f} ms/step {out['value']} Mpx/s DER {out['der_bpp']} (one b: {out['der_bpp_one_b']}); "
+        f"payload_ok={ok_bits}; stages {stages}")
+    if tasks is not None:
+        import oracle as O
+        H = {"I": imgs.cpu().numpy(), "marked": enc.cpu().numpy(), "rec": rec.cpu().numpy(),
+             "bt": btab.cpu().numpy(), "pay": payload.cpu().numpy(), "got": got.cpu().numpy()}
+
+        def check(i):
+            c, o = int(caps[i]), int(offs[i])
+            Ie_o, mo, bt_o = O.demr_encrypt(H["I"][i], k1[i], nonce=nonces[i])
+            W = O.demr_embed(Ie_o, bt_o, H["pay"][o:o + (c + 7) // 8], c, k2[i], nonce=nonces[i])
+            g_o = O.demr_extract(W, bt_o, c, k2[i], nonce=nonces[i])
+            r_o = O.demr_recover(W, bt_o, k1[i], nonce=nonces[i])
+            return (int(mo.capacity_bits) == c and np.array_equal(H["bt"][i], bt_o.ravel())
+                    and np.array_equal(H["marked"][i], W) and np.array_equal(H["got"][o:o + len(g_o)], g_o)
+                    and np.array_equal(H["rec"][i], r_o))
+        tasks.extend(("demr", MN, (lambda i=i: check(i))) for i in range(B))
+    for p in plans.values():
+        p.close()
     return out
 
 
@@ -904,6 +1033,10 @@ def main():
             log(f"[parity] batch: {parity}; oracle on {threads} threads: {cpu_all['value']} Mpx/s")
         del Hb
 
+    demr = None
+    if args.demr and S % 64 == 0:
+        demr = demr_bench(args, imgs, k1, k2, nonces, caps, tasks_late)
+
     lmr = None
     if args.lmr_images > 0:
         lmr = lmr_bench(args, tasks_late)
@@ -931,11 +1064,13 @@ def main():
 
     if tasks_late:
         # the LMR batch and the large images against the oracle, after every timed leg
-        log(f"[parity] LMR batch and large images: {len(tasks_late)} oracle tasks on {threads} threads")
+        log(f"[parity] dynamic-b and LMR batches, large images: {len(tasks_late)} oracle tasks on {threads} threads")
         res, wall = run_parity(tasks_late, threads)
         if lmr is not None and "lmr" in res:
             lmr["parity"] = {"checked": res["lmr"]["checked"], "ok": res["lmr"]["ok"],
                              "method_blocks_from": 4}
+        if demr is not None and "demr" in res:
+            demr["parity"] = {"checked": res["demr"]["checked"], "ok": res["demr"]["ok"]}
         for row in large or []:
             r = res.get(f"large{row['side']}")
             row["oracle_equal"] = bool(r and r["ok"])
@@ -963,6 +1098,7 @@ def main():
         "single": single,
         "metrics": metrics,
         "tile_b": tile_b,
+        "demr": demr,
         "lmr": lmr,
         "keystream": keystream,
     }
@@ -970,6 +1106,7 @@ def main():
     if (not parity["ok"] or (large and not all(r["extract_ok"] and r["lsb_only"] and r.get("oracle_equal", True)
                                                for r in large))
             or (lmr and not lmr.get("parity", {}).get("ok", True))
+            or (demr and not (demr["payload_ok"] and demr["upper_bits_restored"] and demr.get("parity", {}).get("ok", True)))
             or (single and not single["identical_runs"])
             or (keystream and not all(keystream[f]["extract_ok"] and keystream[f]["lsb_only"]
                                       for f in ("philox", "chacha20")))
