@@ -208,8 +208,8 @@ const char *rdhei_plan_stage_name(rdhei_plan *plan, int32_t k);
 int         rdhei_plan_run_stage(rdhei_plan *plan, int32_t k, void *stream);
 
 /* Launch-shape autotuner.  For each layout variant of the plan -- the hiding
- * mode of EMBED/EXTRACT plans whose images may be walked whole (one wave per
- * image, or counted 4096-pixel steps), the quads per work unit of
+ * mode of EMBED/EXTRACT plans (one wave per image where the batch allows it,
+ * 4096-pixel steps in one pass, counted 4096-pixel steps), the quads per work unit of
  * ENCRYPT/RECOVER plans (2, 4, 8, 16) -- it times every stage at several
  * workgroup counts (the launcher's default -- what fits on the device at once
  * -- and 1, 2, 4, 8, 16 and 32 workgroups per compute unit), max(reps, 5)
@@ -273,12 +273,16 @@ int rdhei_run_batch_static(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, in
 #define RDHEI_OPT_PER_PIXEL  1   /* 1: force the per-pixel path for every shape  */
 #define RDHEI_OPT_MAX_GRID   2   /* workgroup cap of grid-stride launches         */
 #define RDHEI_OPT_RESERVE_WS 3   /* allocate this many workspace bytes now        */
-#define RDHEI_OPT_HIDE_MODE  4   /* embed/extract of images up to 1 Mpx: 0 one
-                                    wave walks each image once a batch holds
-                                    enough of them to fill the device, else
-                                    counted 4096-pixel steps; 1 always one wave
-                                    per image; 2 always steps.  Results are
-                                    identical.                                   */
+#define RDHEI_OPT_HIDE_MODE  4   /* embed/extract: 0 one wave walks each image
+                                    of up to 1 Mpx once a batch holds enough of
+                                    them to fill the device, other images go by
+                                    4096-pixel steps, counted, scanned, then
+                                    hidden (three passes); 1 one wave per image
+                                    wherever allowed; 2 always counted steps;
+                                    3 steps in one pass, each taking its rank
+                                    from a look-back over the steps before it
+                                    (pays where images have few steps; slow for
+                                    large ones).  Results are identical.         */
 #define RDHEI_OPT_LMR_MIN_LEVEL 5 /* LMR rotation blocks 2^v..2^n, v in 1..4
                                     (default 4, the method's; Table
                                     LMR_block_size compares 1..4).  Every role

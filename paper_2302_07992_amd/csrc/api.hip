@@ -121,6 +121,7 @@ struct Layout {
     uint64_t ws_bytes = 0;
     uint32_t units[UNIT_KINDS] = {};
     uint64_t g_status = 0, g_part = 0;   // hiding workspace (embed/extract)
+    bool one_pass = false;               // steps hidden in one pass (look-back), else counted first
     int op = 0;
     int method = RDHEI_EMR;
     int keystream = kKsPhilox;
@@ -158,6 +159,7 @@ int make_layout(int op, const rdhei_job *in, int n, const LayoutOpts &opt, Layou
     L.keystream = opt.keystream;
     if (n < 1) return RDHEI_EINVAL;
     L.method = in[0].method;
+    L.one_pass = opt.hide_mode == 3;
     const bool force_per_pixel = opt.per_pixel;
     bool whole_ok = opt.hide_mode == 1;
     if (opt.hide_mode == 0) {
@@ -327,8 +329,9 @@ std::vector<Stage> stages_of(const Layout &Ly, const uint32_t *units_in, std::ve
         const uint32_t ui = units[UNIT_IMG];
         const bool emb = op == RDHEI_OP_EMBED;
         if (ui) S.push_back({emb ? "embed_images" : "extract_images", [=](const Launch &L) { launch_hide_images(L, ui, emb); }});
-        if (us && op == RDHEI_OP_EMBED) S.push_back({"embed", [=](const Launch &L) { launch_embed(L, us); }});
-        else if (us) S.push_back({"extract", [=](const Launch &L) { launch_extract(L, us); }});
+        const bool one = Ly.one_pass;
+        if (us && op == RDHEI_OP_EMBED) S.push_back({"embed", [=](const Launch &L) { launch_embed(L, us, one); }});
+        else if (us) S.push_back({"extract", [=](const Launch &L) { launch_extract(L, us, one); }});
     }
     return S;
 }
@@ -1111,7 +1114,7 @@ int tune_load(rdhei_ctx *ctx) {
         if (o1 == std::string::npos) return RDHEI_EINVAL;
         TuneRecord r;
         if (!int_after("hide_mode", o0, o1, r.hide_mode) || !int_after("qseg", o0, o1, r.qseg)) return RDHEI_EINVAL;
-        if (r.hide_mode < 0 || r.hide_mode > 2 || r.qseg < 1 || r.qseg > kQuadSegMax) return RDHEI_EINVAL;
+        if (r.hide_mode < 0 || r.hide_mode > 3 || r.qseg < 1 || r.qseg > kQuadSegMax) return RDHEI_EINVAL;
         const size_t g0 = t.find('[', o0), g1 = t.find(']', o0);
         if (g0 == std::string::npos || g1 == std::string::npos || g1 > o1) return RDHEI_EINVAL;
         for (const char *c = t.c_str() + g0 + 1; c < t.c_str() + g1;) {
@@ -1219,7 +1222,7 @@ int rdhei_ctx_set_option(rdhei_ctx *ctx, int32_t option, int64_t value) {
         if (value < 0 || value > (1 << 30)) return RDHEI_EINVAL;
         ctx->max_grid = (int)value;
     } else if (option == RDHEI_OPT_HIDE_MODE) {
-        if (value < 0 || value > 2) return RDHEI_EINVAL;
+        if (value < 0 || value > 3) return RDHEI_EINVAL;
         ctx->hide_mode = (int)value;
     } else if (option == RDHEI_OPT_LMR_MIN_LEVEL) {
         if (value < 1 || value > 4) return RDHEI_EINVAL;
@@ -1644,9 +1647,10 @@ int rdhei_plan_autotune(rdhei_plan *P, int32_t reps, int32_t flags, void *stream
     }
     const int samples = std::max<int>(reps, 5);
     const LayoutOpts base = P->opts;
-    // layout variants: the hiding mode of embed/extract plans whose images may
-    // be walked whole, the quads per work unit of encrypt/recover plans with
-    // band pairs of more than one quad
+    // layout variants: the hiding mode of embed/extract plans (whole images
+    // where the batch has them, steps in one pass, counted steps), the quads
+    // per work unit of encrypt/recover plans with band pairs of more than one
+    // quad
     std::vector<TuneRecord> variants;
     {
         TuneRecord v0;
@@ -1660,8 +1664,10 @@ int rdhei_plan_autotune(rdhei_plan *P, int32_t reps, int32_t flags, void *stream
             eligible = eligible || whole_eligible(P->op, q);
             if (q.height % kTile == 0 && q.width % kTile == 0) max_nq = std::max<uint32_t>(max_nq, (uint32_t)(q.width / kTile + 1) / 2);
         }
-        if (hide && eligible)
-            for (int hm : {1, 2}) {
+        // whole images (where the batch allows), steps in one pass, counted steps
+        if (hide)
+            for (int hm : {1, 3, 2}) {
+                if (hm == v0.hide_mode || (hm == 1 && !eligible)) continue;
                 TuneRecord v = v0;
                 v.hide_mode = hm;
                 variants.push_back(v);

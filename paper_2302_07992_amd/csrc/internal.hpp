@@ -151,8 +151,10 @@ uint64_t whole_max_pixels();    // largest image walked whole by one wave
 uint32_t whole_image_min();
 void launch_hide_images(const Launch &L, uint32_t units, bool embed);
 void hide_ws_layout(uint32_t units, uint64_t base, uint64_t &ranks, uint64_t &part, uint64_t &end);
-void launch_embed(const Launch &L, uint32_t units);
-void launch_extract(const Launch &L, uint32_t units);
+// one_pass: steps hidden in one pass with a decoupled look-back; otherwise
+// counted, scanned and hidden in three passes
+void launch_embed(const Launch &L, uint32_t units, bool one_pass);
+void launch_extract(const Launch &L, uint32_t units, bool one_pass);
 // per-pixel path, one image (job index j of the table; host copy h)
 void launch_generic_levels(const Launch &L, int j, const Job &h);
 void launch_generic_stats(const Launch &L, int j, const Job &h);

@@ -6,10 +6,14 @@
 //
 // The work is cut into steps of 4096 raster pixels, one wave each.  Batches
 // of small images walk each image with one wave, step after step, the rank
-// carried in registers.  Otherwise (large images, small batches) three
-// launches, none of which waits on another workgroup: count the redundant
-// pixels of every step, turn each image's counts into exclusive prefix sums,
-// then hide or extract every step at its rank.
+// carried in registers.  Otherwise (large images, small batches) the steps
+// are spread over the device in three launches, none of which waits on
+// another workgroup: count the redundant pixels of every step, turn each
+// image's counts into exclusive prefix sums, then hide or extract every step
+// at its rank.  On request the steps go in one pass instead, each taking its
+// rank from the steps before it with a decoupled look-back.
+#include <algorithm>
+
 #include "device.hpp"
 #include "hide4.hpp"
 
@@ -685,7 +689,137 @@ __global__ __launch_bounds__(kScanThreads) void k_seg_scan(const Job *__restrict
     }
 }
 
-// Pass 3: hide (EMBED) or extract the payload bits of every step at its rank.
+// One step's pixels, redundancy masks, field moves and ranks inside the step
+// (T: the step's total, in redundant pixels, or payload bits with DYN).
+struct StepState {
+    uint4 px[kWLoads];
+    uint32_t rm[kWLoads], lr[kWLoads], T;
+    Hide4 hks[kWLoads];
+    uint64_t s0, s1;
+};
+
+template <bool DYN>
+__device__ __forceinline__ void step_prepare(const Job &J, uint32_t u, const Hide4 &hk0, StepState &S) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t total = (uint64_t)J.M * (uint64_t)J.N;
+    S.s0 = (uint64_t)(u - J.ubase[UNIT_SEG]) * kWSegPx;
+    S.s1 = S.s0 + kWSegPx < total ? S.s0 + kWSegPx : total;
+    const double inv_n = 1.0 / (double)J.N;
+    step_load(J.in, S.s0, S.s1, lane, S.px);
+    uint32_t cnt[kWLoads];
+#pragma unroll
+    for (int k = 0; k < kWLoads; ++k) {
+        const uint64_t pos = S.s0 + (uint64_t)k * 1024u + 16 * (uint64_t)lane;
+        S.rm[k] = redundant16(J, S.px[k], pos, S.s1);
+        S.hks[k] = hk0;
+        if (DYN) S.hks[k] = hide4_of_b(pos < S.s1 ? tile_b_at(J, pos, inv_n) : 2u);
+        cnt[k] = (uint32_t)__popc(S.rm[k]) * (DYN ? S.hks[k].rep : 1u);
+    }
+    step_ranks(cnt, S.lr, S.T);
+}
+
+// Hide (EMBED) or extract the payload bits of one step whose first redundant
+// pixel (or payload bit, DYN) has image-wide rank r0.
+template <bool EMBED, int KS, bool DYN>
+__device__ __forceinline__ void step_hide(const Job &J, int j, uint32_t u, const HideParams &hp, const StepState &S,
+                                          uint64_t r0, uint32_t *win, const uint32_t *htab, PartWord *__restrict__ part) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t rep = DYN ? 1u : hp.rep;       // payload bits per rank step (DYN: ranks count bits)
+    const uint32_t T = S.T;
+    const uint64_t s0 = S.s0, s1 = S.s1;
+    const int64_t wstart = (int64_t)(r0 * rep);
+    int64_t wend = (int64_t)((r0 + T) * rep);
+    if (wend > hp.nbits) wend = hp.nbits;
+    if (T == 0 || wstart >= wend) return;
+    if (EMBED) {
+        // window bits relative to the first staged 16-byte block
+        const int64_t fb = wstart >> 7, lb = (wend - 1) >> 7;
+        const uint32_t off0 = (uint32_t)(wstart - (fb << 7)), rend = (uint32_t)(wend - (fb << 7));
+        if constexpr (KS == kKsChaCha20) {
+            stage_window_quad<KS>(J, hp.nonce, lane, fb, lb, win);
+        } else {
+            for (int64_t q = lane; q <= lb - fb; q += 64) {
+                const uint64_t blk = (uint64_t)(fb + q);
+                const uint4 mv = gload<uint4>(J.msg + 16 * blk);
+                const U4 ks = stream_block<KS>(J.key, hp.nonce, kDomainMessage, blk);
+                *reinterpret_cast<uint4 *>(win + 4 + 4 * q) =
+                    make_uint4(__builtin_bswap32(mv.x ^ ks.x), __builtin_bswap32(mv.y ^ ks.y),
+                               __builtin_bswap32(mv.z ^ ks.z), __builtin_bswap32(mv.w ^ ks.w));
+            }
+        }
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < kWLoads; ++k) {
+            const uint32_t rel = off0 + S.lr[k] * rep;
+            if (!S.rm[k] || rel >= rend) continue;
+            uint32_t w[4] = {S.px[k].x, S.px[k].y, S.px[k].z, S.px[k].w};
+            embed16(w, S.rm[k], rel, rend, win + 3, S.hks[k], htab);   // word 0 of the window is a guard
+            store16(J.out, s0 + (uint64_t)k * 1024u + 16 * (uint64_t)lane, s1, make_uint4(w[0], w[1], w[2], w[3]));
+        }
+    } else {
+        const int64_t W0 = wstart >> 5, W1 = (wend + 31) >> 5;
+        const uint32_t off0 = (uint32_t)(wstart & 31), rend = (uint32_t)(wend - 32 * W0);
+        for (int64_t q = lane; q < W1 - W0 + 1; q += 64) win[q] = 0u;
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < kWLoads; ++k) {
+            const uint32_t rel = off0 + S.lr[k] * rep;
+            if (!S.rm[k] || rel >= rend) continue;
+            const uint32_t w[4] = {S.px[k].x, S.px[k].y, S.px[k].z, S.px[k].w};
+            extract16(w, S.rm[k], rel, rend, win, S.hks[k], htab);
+        }
+        wave_sync();
+        // one keystream block per four message words; words shared with a
+        // neighbouring step go to the side records
+        uint32_t *msgw = reinterpret_cast<uint32_t *>(J.msg);
+        const int64_t B0 = W0 >> 2, B1 = (W1 - 1) >> 2;
+        if constexpr (KS == kKsChaCha20) {
+            each_stream_block_quad<KS>(J, hp.nonce, lane, B0, B1, [&](int64_t blk, const U4 &ks) {
+                const uint32_t kw[4] = {ks.x, ks.y, ks.z, ks.w};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int64_t w = 4 * blk + i;
+                    if (w < W0 || w >= W1) continue;
+                    const uint32_t own = be_mask(w, wstart, wend);
+                    const uint32_t v = (win[w - W0] ^ __builtin_bswap32(kw[i])) & own;
+                    if (own == 0xFFFFFFFFu) {
+                        gstore<uint32_t>(msgw + w, __builtin_bswap32(v));
+                    } else {
+                        PartWord pw;
+                        pw.word = w;
+                        pw.bits = __builtin_bswap32(v);
+                        pw.job = (uint32_t)j;
+                        part[2 * u + (w == W0 ? 0 : 1)] = pw;
+                    }
+                }
+            });
+        } else {
+            for (int64_t bq = lane; bq <= B1 - B0; bq += 64) {
+                const U4 ks = stream_block<KS>(J.key, hp.nonce, kDomainMessage, (uint64_t)(B0 + bq));
+                const uint32_t kw[4] = {ks.x, ks.y, ks.z, ks.w};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int64_t w = 4 * (B0 + bq) + i;
+                    if (w < W0 || w >= W1) continue;
+                    const uint32_t own = be_mask(w, wstart, wend);
+                    const uint32_t v = (win[w - W0] ^ __builtin_bswap32(kw[i])) & own;
+                    if (own == 0xFFFFFFFFu) {
+                        gstore<uint32_t>(msgw + w, __builtin_bswap32(v));
+                    } else {
+                        PartWord pw;
+                        pw.word = w;
+                        pw.bits = __builtin_bswap32(v);
+                        pw.job = (uint32_t)j;
+                        part[2 * u + (w == W0 ? 0 : 1)] = pw;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Pass 3 of the counted steps: hide or extract every step at the rank the
+// scan gave it.
 template <bool EMBED, int KS, bool DYN = false>
 __global__ __launch_bounds__(kThreads) void k_seg_hide(const Job *__restrict__ jobs, int njobs, uint32_t units,
                                                         const uint32_t *__restrict__ ujob,
@@ -706,117 +840,132 @@ __global__ __launch_bounds__(kThreads) void k_seg_hide(const Job *__restrict__ j
             if (lane == 0 && u == J.ubase[UNIT_SEG] && J.meta->status == RDHEI_OK) J.meta->status = RDHEI_ECAPACITY;
             continue;
         }
-        const uint32_t rep = DYN ? 1u : hp.rep;       // payload bits per rank step (DYN: ranks count bits)
-        const Hide4 hk0 = hide4_params(hp);
-        const uint64_t total = (uint64_t)J.M * (uint64_t)J.N;
-        const uint64_t s0 = (uint64_t)(u - J.ubase[UNIT_SEG]) * kWSegPx;
-        const uint64_t s1 = s0 + kWSegPx < total ? s0 + kWSegPx : total;
-        const double inv_n = 1.0 / (double)J.N;
-        uint4 px[kWLoads];
-        step_load(J.in, s0, s1, lane, px);
-        uint32_t rm[kWLoads], cnt[kWLoads], lr[kWLoads], T;
-        Hide4 hks[kWLoads];
-#pragma unroll
-        for (int k = 0; k < kWLoads; ++k) {
-            const uint64_t pos = s0 + (uint64_t)k * 1024u + 16 * (uint64_t)lane;
-            rm[k] = redundant16(J, px[k], pos, s1);
-            hks[k] = hk0;
-            if (DYN) hks[k] = hide4_of_b(pos < s1 ? tile_b_at(J, pos, inv_n) : 2u);
-            cnt[k] = (uint32_t)__popc(rm[k]) * (DYN ? hks[k].rep : 1u);
-        }
-        step_ranks(cnt, lr, T);
-        const uint64_t r0 = uni(rank[u]);
-        const int64_t wstart = (int64_t)(r0 * rep);
-        int64_t wend = (int64_t)((r0 + T) * rep);
-        if (wend > hp.nbits) wend = hp.nbits;
-        if (T == 0 || wstart >= wend) continue;
-        if (EMBED) {
-            // window bits relative to the first staged 16-byte block
-            const int64_t fb = wstart >> 7, lb = (wend - 1) >> 7;
-            const uint32_t off0 = (uint32_t)(wstart - (fb << 7)), rend = (uint32_t)(wend - (fb << 7));
-            if constexpr (KS == kKsChaCha20) {
-                stage_window_quad<KS>(J, hp.nonce, lane, fb, lb, win);
+        StepState S;
+        step_prepare<DYN>(J, u, hide4_params(hp), S);
+        step_hide<EMBED, KS, DYN>(J, j, u, hp, S, uni(rank[u]), win, htab, part);
+        wave_sync();
+    }
+}
+
+// ---- steps in one pass: decoupled look-back ------------------------------------
+// Each wave takes steps in ticket order (an atomic counter), so every step
+// before the one it holds has been taken by a running wave.  It publishes its
+// step's total (flag AGG), then walks back over the published words of the
+// earlier steps of the same image, 64 at a time, until it meets one that
+// already holds its inclusive prefix (flag INCL) or the image's first step;
+// it publishes its own inclusive prefix and hides at the exclusive one.  A
+// step's own total needs nothing from other steps, so every wait ends: the
+// image's first step publishes INCL at once.  The image is read once,
+// instead of once to count and once to hide.
+// Status words: flag in bits 62..63, value below (a prefix is < 7 * 2^31).
+constexpr uint64_t kLbAgg = 1ull << 62, kLbIncl = 2ull << 62, kLbValue = (1ull << 62) - 1;
+// Polls of one look-back window before the wait is given up (RDHEI_EDEVICE in
+// the image's meta); far beyond any real wait.
+constexpr uint32_t kLbMaxPolls = 1u << 22;
+
+__device__ __forceinline__ void lb_publish(uint64_t *st, uint64_t v) {
+    __hip_atomic_store(st, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t lb_read(const uint64_t *st) {
+    return __hip_atomic_load(const_cast<uint64_t *>(st), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive prefix of step u (first step of its image: ufirst); false when the
+// wait was given up.  Every lane runs every iteration (the window's loads are
+// clamped into the image's steps, decisions come from ballots), so the loop's
+// control flow is the same for all lanes.
+__device__ __forceinline__ bool lb_look_back(const uint64_t *status, uint32_t u, uint32_t ufirst, uint64_t &prefix) {
+    const int lane = threadIdx.x & 63;
+    prefix = 0;
+    int64_t p = (int64_t)u - 1;
+    uint32_t polls = 0;
+    bool done = false, ok = true;
+    while (!done) {
+        const int64_t q = p - lane;
+        const bool inside = q >= (int64_t)ufirst;
+        const uint64_t r = lb_read(status + (inside ? q : (int64_t)ufirst));
+        const uint64_t s = inside ? r : kLbIncl;                         // before the image: prefix 0
+        const uint32_t flag = (uint32_t)(s >> 62);
+        const uint64_t incl = __ballot(flag == 2u);
+        const uint64_t wait = __ballot(flag == 0u);
+        const int li = incl ? (int)__builtin_ctzll(incl) : 64;   // nearest INCL lane
+        const uint64_t need = li >= 63 ? ~0ull : ((2ull << li) - 1ull);
+        if (wait & need) {
+            if (++polls > kLbMaxPolls) {
+                ok = false;
+                done = true;
             } else {
-                for (int64_t q = lane; q <= lb - fb; q += 64) {
-                    const uint64_t blk = (uint64_t)(fb + q);
-                    const uint4 mv = gload<uint4>(J.msg + 16 * blk);
-                    const U4 ks = stream_block<KS>(J.key, hp.nonce, kDomainMessage, blk);
-                    *reinterpret_cast<uint4 *>(win + 4 + 4 * q) =
-                        make_uint4(__builtin_bswap32(mv.x ^ ks.x), __builtin_bswap32(mv.y ^ ks.y),
-                                   __builtin_bswap32(mv.z ^ ks.z), __builtin_bswap32(mv.w ^ ks.w));
-                }
-            }
-            wave_sync();
-#pragma unroll
-            for (int k = 0; k < kWLoads; ++k) {
-                const uint32_t rel = off0 + lr[k] * rep;
-                if (!rm[k] || rel >= rend) continue;
-                uint32_t w[4] = {px[k].x, px[k].y, px[k].z, px[k].w};
-                embed16(w, rm[k], rel, rend, win + 3, hks[k], htab);   // word 0 of the window is a guard
-                store16(J.out, s0 + (uint64_t)k * 1024u + 16 * (uint64_t)lane, s1, make_uint4(w[0], w[1], w[2], w[3]));
+                __builtin_amdgcn_s_sleep(1);
             }
         } else {
-            const int64_t W0 = wstart >> 5, W1 = (wend + 31) >> 5;
-            const uint32_t off0 = (uint32_t)(wstart & 31), rend = (uint32_t)(wend - 32 * W0);
-            for (int64_t q = lane; q < W1 - W0 + 1; q += 64) win[q] = 0u;
-            wave_sync();
-#pragma unroll
-            for (int k = 0; k < kWLoads; ++k) {
-                const uint32_t rel = off0 + lr[k] * rep;
-                if (!rm[k] || rel >= rend) continue;
-                const uint32_t w[4] = {px[k].x, px[k].y, px[k].z, px[k].w};
-                extract16(w, rm[k], rel, rend, win, hks[k], htab);
-            }
-            wave_sync();
-            // one keystream block per four message words; words shared with a
-            // neighbouring step go to the side records
-            uint32_t *msgw = reinterpret_cast<uint32_t *>(J.msg);
-            const int64_t B0 = W0 >> 2, B1 = (W1 - 1) >> 2;
-            if constexpr (KS == kKsChaCha20) {
-                each_stream_block_quad<KS>(J, hp.nonce, lane, B0, B1, [&](int64_t blk, const U4 &ks) {
-                    const uint32_t kw[4] = {ks.x, ks.y, ks.z, ks.w};
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int64_t w = 4 * blk + i;
-                        if (w < W0 || w >= W1) continue;
-                        const uint32_t own = be_mask(w, wstart, wend);
-                        const uint32_t v = (win[w - W0] ^ __builtin_bswap32(kw[i])) & own;
-                        if (own == 0xFFFFFFFFu) {
-                            gstore<uint32_t>(msgw + w, __builtin_bswap32(v));
-                        } else {
-                            PartWord pw;
-                            pw.word = w;
-                            pw.bits = __builtin_bswap32(v);
-                            pw.job = (uint32_t)j;
-                            part[2 * u + (w == W0 ? 0 : 1)] = pw;
-                        }
-                    }
-                });
+            // the AGG totals (below 2^15 each) of lanes before li, then li's prefix
+            const uint32_t a = lane < li ? (uint32_t)(s & kLbValue) : 0u;
+            prefix += uni((uint32_t)__builtin_amdgcn_readlane((int)wave_scan_incl(a), 63));
+            if (li < 64) {
+                const uint64_t v = s & kLbValue;
+                prefix += ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), li) << 32) |
+                          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, li);
+                done = true;
             } else {
-                for (int64_t bq = lane; bq <= B1 - B0; bq += 64) {
-                    const U4 ks = stream_block<KS>(J.key, hp.nonce, kDomainMessage, (uint64_t)(B0 + bq));
-                    const uint32_t kw[4] = {ks.x, ks.y, ks.z, ks.w};
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int64_t w = 4 * (B0 + bq) + i;
-                        if (w < W0 || w >= W1) continue;
-                        const uint32_t own = be_mask(w, wstart, wend);
-                        const uint32_t v = (win[w - W0] ^ __builtin_bswap32(kw[i])) & own;
-                        if (own == 0xFFFFFFFFu) {
-                            gstore<uint32_t>(msgw + w, __builtin_bswap32(v));
-                        } else {
-                            PartWord pw;
-                            pw.word = w;
-                            pw.bits = __builtin_bswap32(v);
-                            pw.job = (uint32_t)j;
-                            part[2 * u + (w == W0 ? 0 : 1)] = pw;
-                        }
-                    }
-                }
+                p -= 64;
+                polls = 0;
             }
+        }
+    }
+    return ok;
+}
+
+// status: units + 1 words, cleared by k_lb_clear (the last one is the ticket
+// counter).  Every lane takes part in the ticket's atomic add (lane 0 adds 1,
+// the others 0) and the loop has no early continue, so the control flow
+// around the ticket never depends on the lane: a wave's lanes always agree
+// on the step they hold.
+template <bool EMBED, int KS, bool DYN = false>
+__global__ __launch_bounds__(kThreads) void k_seg_hide1(const Job *__restrict__ jobs, int njobs, uint32_t units,
+                                                         const uint32_t *__restrict__ ujob, uint64_t *__restrict__ status,
+                                                         PartWord *__restrict__ part) {
+    __shared__ __align__(16) uint32_t wins[kThreads / 64][kWWinWords];
+    __shared__ uint32_t htab[hide4::kWords];
+    const int lane = threadIdx.x & 63, wave = (int)uni(threadIdx.x >> 6);
+    uint32_t *win = wins[wave];
+    stage_hide_tables(htab, (int)threadIdx.x);
+    __syncthreads();
+    unsigned long long *ticket = reinterpret_cast<unsigned long long *>(status + units);
+    auto claim = [&]() -> uint32_t {
+        const uint32_t t = (uint32_t)atomicAdd(ticket, lane == 0 ? 1ull : 0ull);
+        return uni(t);   // lane 0's: the step this wave takes
+    };
+    for (uint32_t u = claim(); u < units; u = claim()) {
+        if (!EMBED && lane < 2) part[2 * u + lane].word = -1;
+        const int j = (int)uni((uint32_t)find_job<UNIT_SEG>(jobs, njobs, u, ujob));
+        const Job &J = jobs[j];
+        const uint32_t ufirst = J.ubase[UNIT_SEG];
+        const HideParams hp = hide_params(J);
+        if (hp.ok) {
+            StepState S;
+            step_prepare<DYN>(J, u, hide4_params(hp), S);
+            uint64_t r0 = 0;
+            bool have = true;
+            if (u == ufirst) {
+                if (lane == 0) lb_publish(status + u, kLbIncl | S.T);
+            } else {
+                if (lane == 0) lb_publish(status + u, kLbAgg | S.T);
+                have = lb_look_back(status, u, ufirst, r0);
+                if (lane == 0) lb_publish(status + u, have ? (kLbIncl | (r0 + S.T)) : kLbIncl);
+                if (!have && lane == 0) J.meta->status = RDHEI_EDEVICE;
+            }
+            if (have) step_hide<EMBED, KS, DYN>(J, j, u, hp, S, r0, win, htab, part);
+        } else if (lane == 0) {
+            // every step of the image is skipped; nothing waits on this word
+            lb_publish(status + u, kLbIncl);
+            if (u == ufirst && J.meta->status == RDHEI_OK) J.meta->status = RDHEI_ECAPACITY;
         }
         wave_sync();
     }
+}
+
+__global__ void k_lb_clear(uint64_t *__restrict__ status, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += gridDim.x * blockDim.x) status[i] = 0;
 }
 
 // ---- launchers ---------------------------------------------------------------------
@@ -882,38 +1031,49 @@ static inline unsigned step_grid(const Launch &L, uint32_t units) {
     return grid_for(L, (units + kThreads / 64 - 1) / (kThreads / 64));
 }
 
-void launch_embed(const Launch &L, uint32_t units) {
-    if (!units) return;
+// The step path of a hiding op: one pass with look-back, or count, scan and
+// hide.  The look-back status words and ticket share the rank region.
+template <bool EMBED>
+static void launch_steps(const Launch &L, uint32_t units, bool one_pass) {
     uint32_t *cnt = reinterpret_cast<uint32_t *>(L.ws + L.g_status);
+    uint64_t *status = reinterpret_cast<uint64_t *>(L.ws + L.g_status);
     PartWord *part = reinterpret_cast<PartWord *>(L.ws + L.g_part);
     const unsigned g = step_grid(L, units);
-    hipLaunchKernelGGL(k_seg_count, dim3(g), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, units, L.ujob[UNIT_SEG], cnt);
-    hipLaunchKernelGGL(k_seg_scan, dim3((unsigned)L.njobs), dim3(kScanThreads), 0, L.stream, L.jobs, cnt);
-    with_keystream(L.keystream, [&](auto K) {
-        if (L.dyn)
-            hipLaunchKernelGGL((k_seg_hide<true, decltype(K)::value, true>), dim3(g), dim3(kThreads), 0, L.stream, L.jobs,
-                               L.njobs, units, L.ujob[UNIT_SEG], cnt, part);
-        else
-            hipLaunchKernelGGL((k_seg_hide<true, decltype(K)::value>), dim3(g), dim3(kThreads), 0, L.stream, L.jobs,
-                               L.njobs, units, L.ujob[UNIT_SEG], cnt, part);
-    });
+    if (one_pass) {
+        const unsigned gc = (unsigned)std::min<uint32_t>((units + 1 + 255) / 256, 1024u);
+        hipLaunchKernelGGL(k_lb_clear, dim3(gc), dim3(256), 0, L.stream, status, units);
+        with_keystream(L.keystream, [&](auto K) {
+            if (L.dyn)
+                hipLaunchKernelGGL((k_seg_hide1<EMBED, decltype(K)::value, true>), dim3(g), dim3(kThreads), 0, L.stream,
+                                   L.jobs, L.njobs, units, L.ujob[UNIT_SEG], status, part);
+            else
+                hipLaunchKernelGGL((k_seg_hide1<EMBED, decltype(K)::value>), dim3(g), dim3(kThreads), 0, L.stream,
+                                   L.jobs, L.njobs, units, L.ujob[UNIT_SEG], status, part);
+        });
+    } else {
+        hipLaunchKernelGGL(k_seg_count, dim3(g), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, units, L.ujob[UNIT_SEG],
+                           cnt);
+        hipLaunchKernelGGL(k_seg_scan, dim3((unsigned)L.njobs), dim3(kScanThreads), 0, L.stream, L.jobs, cnt);
+        with_keystream(L.keystream, [&](auto K) {
+            if (L.dyn)
+                hipLaunchKernelGGL((k_seg_hide<EMBED, decltype(K)::value, true>), dim3(g), dim3(kThreads), 0, L.stream,
+                                   L.jobs, L.njobs, units, L.ujob[UNIT_SEG], cnt, part);
+            else
+                hipLaunchKernelGGL((k_seg_hide<EMBED, decltype(K)::value>), dim3(g), dim3(kThreads), 0, L.stream, L.jobs,
+                                   L.njobs, units, L.ujob[UNIT_SEG], cnt, part);
+        });
+    }
 }
 
-void launch_extract(const Launch &L, uint32_t units) {
+void launch_embed(const Launch &L, uint32_t units, bool one_pass) {
     if (!units) return;
-    uint32_t *cnt = reinterpret_cast<uint32_t *>(L.ws + L.g_status);
+    launch_steps<true>(L, units, one_pass);
+}
+
+void launch_extract(const Launch &L, uint32_t units, bool one_pass) {
+    if (!units) return;
+    launch_steps<false>(L, units, one_pass);
     PartWord *part = reinterpret_cast<PartWord *>(L.ws + L.g_part);
-    const unsigned g = step_grid(L, units);
-    hipLaunchKernelGGL(k_seg_count, dim3(g), dim3(kThreads), 0, L.stream, L.jobs, L.njobs, units, L.ujob[UNIT_SEG], cnt);
-    hipLaunchKernelGGL(k_seg_scan, dim3((unsigned)L.njobs), dim3(kScanThreads), 0, L.stream, L.jobs, cnt);
-    with_keystream(L.keystream, [&](auto K) {
-        if (L.dyn)
-            hipLaunchKernelGGL((k_seg_hide<false, decltype(K)::value, true>), dim3(g), dim3(kThreads), 0, L.stream,
-                               L.jobs, L.njobs, units, L.ujob[UNIT_SEG], cnt, part);
-        else
-            hipLaunchKernelGGL((k_seg_hide<false, decltype(K)::value>), dim3(g), dim3(kThreads), 0, L.stream, L.jobs,
-                               L.njobs, units, L.ujob[UNIT_SEG], cnt, part);
-    });
     const uint32_t n = 2 * units;
     hipLaunchKernelGGL(k_extract_fix, dim3((n + 255) / 256), dim3(256), 0, L.stream, L.jobs, part, n, 0);
     hipLaunchKernelGGL(k_extract_fix, dim3((n + 255) / 256), dim3(256), 0, L.stream, L.jobs, part, n, 1);
@@ -922,11 +1082,12 @@ void launch_extract(const Launch &L, uint32_t units) {
 uint64_t seg_pixels() { return kWSegPx; }
 uint64_t whole_max_pixels() { return kWholeMaxPx; }
 
-// Hiding workspace of a launch: the count / rank of every step, then two
-// partial-word records per step.
+// Hiding workspace of a launch: the count / rank of every step (one pass: its
+// look-back status word, then the ticket counter), then two partial-word
+// records per step.
 void hide_ws_layout(uint32_t units, uint64_t base, uint64_t &ranks, uint64_t &part, uint64_t &end) {
     ranks = base;
-    part = (ranks + (uint64_t)units * 4 + 255) / 256 * 256;
+    part = (ranks + ((uint64_t)units + 1) * 8 + 255) / 256 * 256;
     end = (part + (uint64_t)units * 2 * sizeof(PartWord) + 255) / 256 * 256;
 }
 

@@ -72,7 +72,7 @@ def test_emr_chacha_roundtrip_matches_oracle(R, cctx, shape, frac):
     assert np.array_equal(d_rec.cpu().numpy() >> 1, I >> 1)
 
 
-@pytest.mark.parametrize("hide_mode", [1, 2], ids=["whole", "segments"])
+@pytest.mark.parametrize("hide_mode", [1, 2, 3], ids=["whole", "counted", "one_pass"])
 def test_batched_chacha_plan_matches_oracle(R, hide_mode):
     """A graph-captured batch of tiled and per-pixel images under ChaCha20;
     hiding walks images whole (one wave each) or in counted steps."""

@@ -144,7 +144,7 @@ def _demr_round_trip(R, ctx, imgs, k1s, k2s, nonces, frac=1.0, plans=False):
 DEMR_SHAPES = [(64, 64), (128, 192), (256, 256), (512, 512), (64, 1024), (192, 320)]
 
 
-@pytest.mark.parametrize("hide_mode", [0, 1, 2], ids=["auto", "whole", "steps"])
+@pytest.mark.parametrize("hide_mode", [0, 1, 2, 3], ids=["auto", "whole", "counted", "one_pass"])
 @pytest.mark.parametrize("frac", [1.0, 0.37])
 def test_demr_batch_matches_oracle(R, hide_mode, frac):
     """Dynamic b (one b per 64x64 tile, the conclusion's future work): a batch

@@ -168,6 +168,17 @@ def test_emr_4096_full_image(R, ctx):
     _roundtrip(R, ctx, I, 101, 202, frac=1.0)
 
 
+def test_emr_one_pass_hiding_large_image(R):
+    """Steps hidden in one pass (RDHEI_OPT_HIDE_MODE 3) on a 4096 x 3072
+    image: 3,072 steps, so most look-backs cross many 64-step windows before
+    they meet a published prefix; a payload ending inside a pixel."""
+    print("[large] 4096x3072 one-pass hiding, oracle parity", flush=True)
+    c = R.Context(0)
+    c.set_option(R.OPT_HIDE_MODE, 3)
+    I = inputs.make_band_image(15, 4096, 3072, 8, 8.0, "cpu").numpy()
+    _roundtrip(R, c, I, 111, 222, frac=0.83)
+
+
 def test_emr_large_ragged_tile_grid(R, ctx):
     """4480 x 3840: 70 x 60 tiles, above the size where finalisation is split
     over 16 x 16-tile blocks, with partial blocks at both edges."""
@@ -340,7 +351,7 @@ def test_invalid_arguments_rejected_on_host(R, ctx):
     with pytest.raises(R.RdheiError):
         ctx.encrypt(d, torch.empty_like(d), 1, meta, method=7)
     c2 = R.Context(0)
-    for opt, bad in ((R.OPT_HIDE_MODE, 3), (R.OPT_HIDE_MODE, -1), (R.OPT_MAX_GRID, -5), (R.OPT_RESERVE_WS, -1),
+    for opt, bad in ((R.OPT_HIDE_MODE, 4), (R.OPT_HIDE_MODE, -1), (R.OPT_MAX_GRID, -5), (R.OPT_RESERVE_WS, -1),
                      (R.OPT_LMR_MIN_LEVEL, 0), (R.OPT_LMR_MIN_LEVEL, 5), (99, 0)):
         with pytest.raises(R.RdheiError):
             c2.set_option(opt, bad)
@@ -400,15 +411,19 @@ def test_run_batch_matches_plan(R, ctx):
             assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("hide_mode", [3, 2], ids=["one_pass", "counted"])
 @pytest.mark.parametrize("max_grid", [1, 3, 7])
-def test_capped_grids_match_oracle(R, max_grid):
+def test_capped_grids_match_oracle(R, max_grid, hide_mode):
     """Launches capped at a few workgroups: each wave of the statistics pass
     sums the pixels of many tiles (96 per wave at one workgroup, past the
     point where it takes its counts out early) and crosses image boundaries in
-    a batch; the quad kernels take many segments in a row."""
-    print(f"[capped grid] {max_grid}", flush=True)
+    a batch; the quad kernels take many segments in a row; hiding steps of
+    the 1.5 Mpx image go through few waves, in one pass (each wave looks back
+    only at steps it or another running wave took earlier) or counted."""
+    print(f"[capped grid] {max_grid} hide_mode={hide_mode}", flush=True)
     ctx = R.Context(0)
     ctx.set_option(R.OPT_MAX_GRID, max_grid)
+    ctx.set_option(R.OPT_HIDE_MODE, hide_mode)
     _roundtrip(R, ctx, _image(4000 + max_grid, 1024, 1536), 51 + max_grid, 61 + max_grid, frac=0.9)
     shapes = [(512, 512), (256, 768), (64, 64), (384, 1280), (128, 128)]
     n = len(shapes)
@@ -426,11 +441,12 @@ def test_capped_grids_match_oracle(R, max_grid):
         assert np.array_equal(d_enc[i].cpu().numpy(), Ie_o), shapes[i]
 
 
-@pytest.mark.parametrize("hide_mode", [0, 1, 2], ids=["auto", "whole", "segments"])
+@pytest.mark.parametrize("hide_mode", [0, 1, 2, 3], ids=["auto", "whole", "counted", "one_pass"])
 def test_batched_plan_uneven_sizes_matches_oracle(R, hide_mode):
     """One plan per op over images of different shapes (tiled and per-pixel
     in the same launch), graph-captured, replayed twice; hiding either walks
-    small images whole (one wave each) or in counted 4096-pixel steps."""
+    small images whole (one wave each) or goes by 4096-pixel steps, in one
+    pass or counted first."""
     print(f"[batched uneven] hide_mode={hide_mode}", flush=True)
     ctx = R.Context(0)
     ctx.set_option(R.OPT_HIDE_MODE, hide_mode)
@@ -521,7 +537,7 @@ def test_batched_wide_images_quad_segments(R):
         assert mism.size == 0, f"recover image {i} {shapes[i]}: {mism[:5].tolist()} of {len(mism)}"
 
 
-@pytest.mark.parametrize("hide_mode", [1, 2], ids=["whole", "segments"])
+@pytest.mark.parametrize("hide_mode", [1, 2, 3], ids=["whole", "counted", "one_pass"])
 def test_batched_partial_payloads_match_oracle(R, hide_mode):
     """Batched embed/extract with payloads that end inside a pixel's field and
     inside a word of four pixels (nbits not a multiple of rep), next to full
@@ -711,7 +727,7 @@ def test_autotune_keeps_results_and_caches(R, tmp_path):
         assert np.array_equal(a, b)
     for g in grids:
         assert set(g) <= cand
-    assert variants[0]["qseg"] in (1, 2, 4, 8, 16) and variants[1]["hide_mode"] in (0, 1, 2)
+    assert variants[0]["qseg"] in (1, 2, 4, 8, 16) and variants[1]["hide_mode"] in (0, 1, 2, 3)
     again = plans[0].autotune(reps=1)            # cached: same answer without forcing
     assert again == grids[0]
     text = tune_file.read_text()
