@@ -369,8 +369,9 @@ def single_bench(args):
 
 def large_bench(args, tasks=None):
     """Single large images (sigma 3, 8 sinusoids, drawn in row bands) through
-    encrypt / embed (payload at capacity) / extract / recover, each stage timed
-    with HIP events on its stream; checked at full size: the extracted bits
+    encrypt / embed (payload at capacity) / extract / recover, each role timed
+    with HIP events on its stream as an autotuned one-image graph plan (and
+    through the single-image entry points); checked at full size: the extracted bits
     equal the payload, and the recovered image differs from the original only
     in bit 0 (EMR keeps no copy of the LSB plane)."""
     import numpy as np
@@ -399,28 +400,46 @@ def large_bench(args, tasks=None):
         g.manual_seed(seed)
         msg = torch.randint(0, 256, (nbytes,), generator=g, device=dev, dtype=torch.int32).to(torch.uint8)
         got = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
-        ops = {
+        direct = {
             "encrypt": lambda: ctx.encrypt(img, enc, k1, meta, nonce=nonce),
             "embed": lambda: ctx.embed(enc, meta, msg, cap, k2),
             "extract": lambda: ctx.extract(enc, meta, got, cap, k2),
             "recover": lambda: ctx.recover(enc, meta, rec, k1),
         }
-        times = {}
-        # embedding rewrites only the MSBs it owns from the unchanged labels,
-        # so repeating it in place gives the same marked image every time
-        for name in ["encrypt", "embed", "extract", "recover"]:
-            ops[name]()                                   # warm-up; leaves the stage's output
+        # the same roles as one-image graph plans, autotuned like the batch's
+        shp, mp = [(side, side)], [meta]
+        plans = {
+            "encrypt": rdhei.Plan(ctx, rdhei.OP_ENCRYPT, rdhei.make_jobs([img], [enc], None, mp, [k1], None, shp,
+                                                                         nonces=[nonce])),
+            "embed": rdhei.Plan(ctx, rdhei.OP_EMBED, rdhei.make_jobs(None, [enc], [msg], mp, [k2], [cap], shp)),
+            "extract": rdhei.Plan(ctx, rdhei.OP_EXTRACT, rdhei.make_jobs([enc], None, [got], mp, [k2], [cap], shp)),
+            "recover": rdhei.Plan(ctx, rdhei.OP_RECOVER, rdhei.make_jobs([enc], [rec], None, mp, [k1], None, shp)),
+        }
+        tuned = {}
+
+        def timed(fn, reps=5):
+            fn()                                          # warm-up; leaves the stage's output
             torch.cuda.synchronize()
-            reps = 3
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record()
             for _ in range(reps):
-                ops[name]()
+                fn()
             b.record()
             torch.cuda.synchronize()
-            times[name] = a.elapsed_time(b) / reps
-        ops["extract"]()
-        ops["recover"]()
+            return a.elapsed_time(b) / reps
+
+        times, times_direct = {}, {}
+        # embedding rewrites only the MSBs it owns from the unchanged labels,
+        # so repeating it in place gives the same marked image every time
+        for name in ["encrypt", "embed", "extract", "recover"]:
+            times_direct[name] = timed(direct[name])
+            p = plans[name]
+            if args.autotune > 0 and not args.max_grid:
+                grids = p.autotune(reps=args.autotune)
+                tuned[name] = {"grids": dict(zip(p.stages(), grids)), **p.tuned()}
+            times[name] = timed(p.run)
+        plans["extract"].run()
+        plans["recover"].run()
         torch.cuda.synchronize()
         nb = cap // 8
         bits_ok = bool(torch.equal(got[:nb], msg[:nb]))
@@ -433,12 +452,20 @@ def large_bench(args, tasks=None):
         psnr = 10 * np.log10(255.0 ** 2 / (mism / float(side * side))) if mism else float("inf")
         px = side * side
         rt = sum(times.values())
+        rt_direct = sum(times_direct.values())
+        alg = (7.0 + cap / px / 4.0) * px
         row = {"side": side, "b": int(m.b), "capacity_bits": cap, "der_bpp": round(cap / px, 4),
                "ms": {k: round(v, 4) for k, v in times.items()}, "round_trip_ms": round(rt, 4),
-               "mpx_per_s": round(px / (rt * 1e-3) / 1e6, 1), "extract_ok": bits_ok, "lsb_only": lsb_only,
-               "psnr_db": round(psnr, 4)}
-        log(f"[large] {side}: {row['ms']} -> {row['mpx_per_s']} Mpx/s, extract_ok={bits_ok}, "
-            f"lsb_only={lsb_only}, PSNR {row['psnr_db']} dB")
+               "mpx_per_s": round(px / (rt * 1e-3) / 1e6, 1),
+               "hbm_frac": round(alg / (rt * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "tuned": tuned,
+               "direct_ms": {k: round(v, 4) for k, v in times_direct.items()},
+               "direct_round_trip_ms": round(rt_direct, 4),
+               "extract_ok": bits_ok, "lsb_only": lsb_only, "psnr_db": round(psnr, 4)}
+        log(f"[large] {side}: plans {row['ms']} -> {row['mpx_per_s']} Mpx/s ({row['hbm_frac']} of the HBM roofline); "
+            f"direct calls {row['direct_ms']}; tuned {tuned}; extract_ok={bits_ok}, lsb_only={lsb_only}, "
+            f"PSNR {row['psnr_db']} dB")
+        for p in plans.values():
+            p.close()
         out.append(row)
         if tasks is not None:
             # the whole image against the oracle, pixel for pixel (Sec. III-A

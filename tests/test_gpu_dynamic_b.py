@@ -148,8 +148,9 @@ DEMR_SHAPES = [(64, 64), (128, 192), (256, 256), (512, 512), (64, 1024), (192, 3
 @pytest.mark.parametrize("frac", [1.0, 0.37])
 def test_demr_batch_matches_oracle(R, hide_mode, frac):
     """Dynamic b (one b per 64x64 tile, the conclusion's future work): a batch
-    of tiled shapes and textures, hiding by whole images or by counted steps,
-    full and partial payloads, every role equal to the oracle."""
+    of tiled shapes and textures, hiding by whole images, counted steps or
+    steps in one pass, full and partial payloads, every role equal to the
+    oracle."""
     print(f"[demr] batch hide_mode={hide_mode} frac={frac}", flush=True)
     c = R.Context(0)
     c.set_option(R.OPT_HIDE_MODE, hide_mode)
