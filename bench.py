@@ -24,9 +24,9 @@ if ROOT not in sys.path:
 METRIC = "Mpixel/s embed+recover (batched vs per-image) at bit-exact; p99 latency served"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_emr_batch_4000x512.md")
-STAGE_KERNEL = {"tile_prep_stats": "rdhei::k_tile_prep<true, 0>", "encrypt_tiles": "rdhei::k_encrypt_quad<0, 0>",
-                "embed_images": "rdhei::k_hide_wave<true, 0>", "extract_images": "rdhei::k_hide_wave<false, 0>",
-                "recover_bands": "rdhei::k_recover_quad_emr<0>"}
+STAGE_KERNEL = {"tile_prep_stats": "rdhei::k_tile_prep<true, 0, false>", "encrypt_tiles": "rdhei::k_encrypt_quad<0, 0>",
+                "embed_images": "rdhei::k_hide_wave<true, 0, false>", "extract_images": "rdhei::k_hide_wave<false, 0, false>",
+                "recover_bands": "rdhei::k_recover_quad_emr<0, false>"}
 
 
 def log(*a):

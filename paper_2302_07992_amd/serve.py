@@ -266,56 +266,83 @@ class Server:
         self.on_complete = on_complete
         self.lib = R.load_library()
         self._rr = 0
+        self._tmpl = {}
 
     # ---- one batch -------------------------------------------------------
+    @staticmethod
+    def _templates(wl: Workload) -> dict:
+        """Per-request job rows of the four ops with every field that does not
+        depend on where a batch's outputs land, and the requests' output sizes:
+        built once per workload, so a batch only gathers rows and sets its
+        output pointers."""
+        n = len(wl)
+        px = wl.pixels
+        t = {}
+        enc = np.zeros(n, R.JOB_DTYPE)
+        enc["inp"] = wl.in_ptr
+        enc["key"] = wl.k1
+        enc["nonce"] = wl.seed
+        enc["height"] = wl.side
+        enc["width"] = wl.side
+        emb = enc.copy()
+        emb["inp"] = 0
+        emb["msg"] = wl.msg_ptr
+        emb["key"] = wl.k2
+        emb["nonce"] = 0
+        emb["nbits"] = wl.nbits
+        ext = np.zeros(n, R.JOB_DTYPE)
+        ext["inp"] = wl.in_ptr
+        ext["meta"] = wl.meta_ptr
+        ext["key"] = wl.k2
+        ext["nbits"] = wl.nbits
+        ext["height"] = wl.side
+        ext["width"] = wl.side
+        rec = ext.copy()
+        rec["nbits"] = 0
+        rec["key"] = wl.k1
+        t.update(enc=enc, emb=emb, ext=ext, rec=rec)
+        # outputs back to back: EMBED (image, meta), then RECOVER (msg, image)
+        t["img_al"] = _al(px)
+        t["sz_e"] = t["img_al"] + _ALIGN
+        t["sz_r_msg"] = _al(msg_bytes(wl.nbits))
+        t["sz_r"] = t["sz_r_msg"] + t["img_al"]
+        t["is_e"] = wl.kind == EMBED_REQ
+        return t
+
     def _tables(self, wl: Workload, idx: np.ndarray, base: int):
         """Job tables of the four ops and the output offsets of a batch whose
         outputs start at device address `base` (256-byte aligned)."""
-        e = idx[wl.kind[idx] == EMBED_REQ]
-        r = idx[wl.kind[idx] == RECOVER_REQ]
-        px_e = wl.pixels[e]
-        px_r = wl.pixels[r]
-        # outputs back to back: EMBED (image, meta), then RECOVER (msg, image)
-        sz_e = _al(px_e) + _ALIGN
-        sz_r_msg = _al(msg_bytes(wl.nbits[r]))
-        sz_r = sz_r_msg + _al(px_r)
-        off_e = np.concatenate(([0], np.cumsum(sz_e)))[:-1].astype(np.int64)
-        end_e = int(sz_e.sum())
-        off_r = end_e + np.concatenate(([0], np.cumsum(sz_r)))[:-1].astype(np.int64)
-        total = end_e + int(sz_r.sum())
-        out = {"e": e, "r": r, "img_e": off_e, "meta_e": off_e + _al(px_e), "msg_r": off_r,
-               "img_r": off_r + sz_r_msg}
+        t = self._tmpl.get(id(wl))
+        if t is None or t["wl"] is not wl:
+            t = self._templates(wl)
+            t["wl"] = wl
+            self._tmpl = {id(wl): t}
+        me = t["is_e"][idx]
+        e = idx[me]
+        r = idx[~me]
+        sz_e = t["sz_e"][e]
+        sz_r = t["sz_r"][r]
+        cs_e = np.cumsum(sz_e)
+        end_e = int(cs_e[-1]) if len(e) else 0
+        off_e = cs_e - sz_e
+        off_r = end_e + np.cumsum(sz_r) - sz_r
+        total = end_e + (int(sz_r.sum()) if len(r) else 0)
+        out = {"e": e, "r": r, "img_e": off_e, "meta_e": off_e + t["img_al"][e], "msg_r": off_r,
+               "img_r": off_r + t["sz_r_msg"][r]}
         tabs = []
         if len(e):
-            enc = np.zeros(len(e), R.JOB_DTYPE)
-            enc["inp"] = wl.in_ptr[e]
+            enc = t["enc"][e]
             enc["out"] = base + out["img_e"]
             enc["meta"] = base + out["meta_e"]
-            enc["key"] = wl.k1[e]
-            enc["nonce"] = wl.seed[e]
-            enc["height"] = wl.side[e]
-            enc["width"] = wl.side[e]
-            emb = enc.copy()
-            emb["inp"] = 0
-            emb["msg"] = wl.msg_ptr[e]
-            emb["key"] = wl.k2[e]
-            emb["nonce"] = 0
-            emb["nbits"] = wl.nbits[e]
+            emb = t["emb"][e]
+            emb["out"] = enc["out"]
+            emb["meta"] = enc["meta"]
             tabs += [(R.OP_ENCRYPT, enc, ("out", "meta")), (R.OP_EMBED, emb, ("out", "meta"))]
         if len(r):
-            ext = np.zeros(len(r), R.JOB_DTYPE)
-            ext["inp"] = wl.in_ptr[r]
+            ext = t["ext"][r]
             ext["msg"] = base + out["msg_r"]
-            ext["meta"] = wl.meta_ptr[r]
-            ext["key"] = wl.k2[r]
-            ext["nbits"] = wl.nbits[r]
-            ext["height"] = wl.side[r]
-            ext["width"] = wl.side[r]
-            rec = ext.copy()
-            rec["msg"] = 0
-            rec["nbits"] = 0
+            rec = t["rec"][r]
             rec["out"] = base + out["img_r"]
-            rec["key"] = wl.k1[r]
             tabs += [(R.OP_EXTRACT, ext, ("msg",)), (R.OP_RECOVER, rec, ("out",))]
         return tabs, out, total
 

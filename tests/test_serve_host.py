@@ -70,3 +70,56 @@ def test_footprint_covers_outputs():
     fp = wl.footprint()
     assert np.all(fp > ob)
     assert fp[2] - ob[2] >= 100 * 100 // 2      # untiled shape: larger workspace bound
+
+
+def test_batch_tables_fields_and_layout():
+    """A batch's job tables: every field of every op comes from its request
+    (inputs, keys, nonce, sizes, payload bits), and the outputs are laid out
+    back to back from the base, 256-byte aligned, without overlap: EMBED
+    requests' marked image then meta, then RECOVER requests' payload then
+    restored image."""
+    from paper_2302_07992_amd import rdhei as R
+    rng = np.random.default_rng(7)
+    n = 400
+    wl = serve.Workload(kind=np.where(rng.random(n) < 0.6, serve.EMBED_REQ, serve.RECOVER_REQ).astype(np.int8),
+                        side=rng.choice([64, 256, 512, 1024], n).astype(np.int32), seed=np.arange(n) * 3 + 1,
+                        nbits=rng.integers(0, 200000, n), k1=np.arange(n, dtype=np.uint64) * 5 + 1,
+                        k2=np.arange(n, dtype=np.uint64) * 7 + 2, in_ptr=np.arange(n, dtype=np.uint64) * 4096 + 256,
+                        msg_ptr=np.arange(n, dtype=np.uint64) * 512 + 1024, meta_ptr=np.arange(n, dtype=np.uint64) * 256 + 512)
+
+    class Host:                 # the table builder needs no device state
+        _tmpl = {}
+        _templates = staticmethod(serve.Server._templates)
+
+    base = 1 << 40
+    for trial in range(50):
+        a = int(rng.integers(0, n - 40))
+        idx = np.arange(a, a + int(rng.integers(1, 40)))
+        tabs, out, total = serve.Server._tables(Host(), wl, idx, base)
+        ops = {op: t for op, t, _ in tabs}
+        e, r = out["e"], out["r"]
+        assert sorted(np.concatenate([e, r]).tolist()) == idx.tolist()
+        assert np.all(wl.kind[e] == serve.EMBED_REQ) and np.all(wl.kind[r] == serve.RECOVER_REQ)
+        spans = []
+        if len(e):
+            enc, emb = ops[R.OP_ENCRYPT], ops[R.OP_EMBED]
+            px = wl.pixels[e]
+            assert np.array_equal(enc["inp"], wl.in_ptr[e]) and np.array_equal(enc["key"], wl.k1[e])
+            assert np.array_equal(enc["nonce"], wl.seed[e].astype(np.uint64))
+            assert np.array_equal(emb["msg"], wl.msg_ptr[e]) and np.array_equal(emb["key"], wl.k2[e])
+            assert np.array_equal(emb["nbits"], wl.nbits[e]) and not emb["inp"].any() and not emb["nonce"].any()
+            assert np.array_equal(enc["out"], emb["out"]) and np.array_equal(enc["meta"], emb["meta"])
+            assert np.array_equal(enc["height"], wl.side[e]) and np.array_equal(emb["width"], wl.side[e])
+            spans += [(int(o), int(o) + int(p)) for o, p in zip(enc["out"], px)]
+            spans += [(int(m), int(m) + R.META_BYTES) for m in enc["meta"]]
+        if len(r):
+            ext, rec = ops[R.OP_EXTRACT], ops[R.OP_RECOVER]
+            assert np.array_equal(ext["inp"], wl.in_ptr[r]) and np.array_equal(rec["inp"], wl.in_ptr[r])
+            assert np.array_equal(ext["meta"], wl.meta_ptr[r]) and np.array_equal(rec["meta"], wl.meta_ptr[r])
+            assert np.array_equal(ext["key"], wl.k2[r]) and np.array_equal(rec["key"], wl.k1[r])
+            assert np.array_equal(ext["nbits"], wl.nbits[r]) and not rec["nbits"].any() and not rec["msg"].any()
+            spans += [(int(m), int(m) + int(b)) for m, b in zip(ext["msg"], serve.msg_bytes(wl.nbits[r]))]
+            spans += [(int(o), int(o) + int(p)) for o, p in zip(rec["out"], wl.pixels[r])]
+        spans.sort()
+        assert all(s0 % 256 == 0 and base <= s0 and s1 <= base + total for s0, s1 in spans)
+        assert all(a1 <= b0 for (_, a1), (b0, _) in zip(spans, spans[1:]))
