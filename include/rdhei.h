@@ -254,6 +254,20 @@ int rdhei_workspace_size(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int3
 int rdhei_run_batch(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t njobs, void *d_workspace,
                     int64_t workspace_bytes, void *stream);
 
+/* Several EMR ops of one batch in order on `stream` (for example encrypt then
+ * embed of a server's new requests, extract and recover of its returning
+ * ones), all sharing one workspace: what rdhei_run_batch does for each op in
+ * turn, with one table upload and one call for all of them.  ops[i] runs over
+ * jobs[i][0 .. njobs[i]-1]; 1 <= n_ops <= 8; an op reads what the ops before
+ * it in the list wrote, in stream order.  rdhei_roles_workspace_size gives the
+ * workspace bytes (the largest of the ops'); d_workspace as for
+ * rdhei_run_batch (NULL: the context's own).  Errors as rdhei_run_batch, with
+ * nothing launched when any op's table is invalid. */
+int rdhei_roles_workspace_size(rdhei_ctx *ctx, int32_t n_ops, const int32_t *ops, const rdhei_job *const *jobs,
+                               const int32_t *njobs, int64_t *bytes);
+int rdhei_run_roles(rdhei_ctx *ctx, int32_t n_ops, const int32_t *ops, const rdhei_job *const *jobs,
+                    const int32_t *njobs, void *d_workspace, int64_t workspace_bytes, void *stream);
+
 /* rdhei_run_batch without allocation, for callers that cannot allocate device
  * memory (code under stream capture, tight serving loops, hosts that forbid
  * hipMalloc): the job tables and the workspace live in a static device array

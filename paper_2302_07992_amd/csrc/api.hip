@@ -2,6 +2,7 @@
 // launch sequence of every stage, plans (hipGraph capture/replay), and the
 // LMR host stages.
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <functional>
@@ -1461,6 +1462,103 @@ int rdhei_run_batch(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, int32_t n
     L.keystream = Ly.keystream;
     L.dyn = Ly.method == RDHEI_DEMR;
     for (const Stage &sg : stages_of(Ly, Ly.units, Ly.per_pixel)) sg.fn(L);
+    HIPCHK(hipGetLastError());
+    return RDHEI_OK;
+}
+
+// Several ops of one batch in stream order, sharing one workspace: every
+// op's layout, then all their tables in one staging slot and one upload.
+static int roles_layouts(rdhei_ctx *ctx, int32_t n_ops, const int32_t *ops, const rdhei_job *const *jobs,
+                         const int32_t *njobs, std::vector<Layout> &lys, uint64_t &ws_bytes) {
+    if (!ctx || n_ops < 1 || n_ops > 8 || !ops || !jobs || !njobs) return RDHEI_EINVAL;
+    lys.assign((size_t)n_ops, Layout());
+    ws_bytes = 256;
+    for (int i = 0; i < n_ops; ++i) {
+        if (!jobs[i] || njobs[i] < 1) return RDHEI_EINVAL;
+        const int rc = make_layout(ops[i], jobs[i], njobs[i], opts_of(ctx), lys[(size_t)i]);
+        if (rc) return rc;
+        if (lys[(size_t)i].method == RDHEI_LMR) return RDHEI_EINVAL;
+        ws_bytes = std::max<uint64_t>(ws_bytes, lys[(size_t)i].ws_bytes);
+    }
+    return RDHEI_OK;
+}
+
+int rdhei_roles_workspace_size(rdhei_ctx *ctx, int32_t n_ops, const int32_t *ops, const rdhei_job *const *jobs,
+                               const int32_t *njobs, int64_t *bytes) {
+    if (!ctx || !bytes) return RDHEI_EINVAL;
+    const int rs = set_device(ctx->device);
+    if (rs) return rs;
+    std::vector<Layout> lys;
+    uint64_t ws = 0;
+    const int rc = roles_layouts(ctx, n_ops, ops, jobs, njobs, lys, ws);
+    if (rc) return rc;
+    *bytes = (int64_t)ws;
+    return RDHEI_OK;
+}
+
+int rdhei_run_roles(rdhei_ctx *ctx, int32_t n_ops, const int32_t *ops, const rdhei_job *const *jobs,
+                    const int32_t *njobs, void *d_workspace, int64_t workspace_bytes, void *stream) {
+    if (!ctx || ((uintptr_t)d_workspace & 255)) return RDHEI_EINVAL;
+    int rc = set_device(ctx->device);
+    if (rc) return rc;
+    std::vector<Layout> lys;
+    uint64_t ws_need = 0;
+    rc = roles_layouts(ctx, n_ops, ops, jobs, njobs, lys, ws_need);
+    if (rc) return rc;
+    uint8_t *ws = (uint8_t *)d_workspace;
+    if (ws) {
+        if (workspace_bytes < (int64_t)ws_need) return RDHEI_EINVAL;
+    } else {
+        rc = ctx->ws.need(ws_need);
+        if (rc) return rc;
+        ws = ctx->ws.p;
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    // the ops' tables back to back in one staging slot
+    std::vector<size_t> base((size_t)n_ops);
+    std::vector<std::array<size_t, UNIT_KINDS>> offs((size_t)n_ops);
+    size_t tb = 0;
+    for (int i = 0; i < n_ops; ++i) {
+        base[(size_t)i] = tb;
+        tb += align_up(table_bytes(lys[(size_t)i], offs[(size_t)i].data()), 256);
+    }
+    const size_t region = align_up(std::max<size_t>(tb, 1 << 16), 256);
+    if (ctx->batch_tables.n / PinnedRing::kSlots < region) {
+        rc = ctx->batch_tables.need(PinnedRing::kSlots * region);   // synchronises
+        if (rc) return rc;
+    }
+    uint8_t *host = nullptr;
+    int slot = 0;
+    rc = ctx->ring.acquire(tb, &host, &slot);
+    if (rc) return rc;
+    uint8_t *dtab = ctx->batch_tables.p + (size_t)slot * (ctx->batch_tables.n / PinnedRing::kSlots);
+    for (int i = 0; i < n_ops; ++i) {
+        const Layout &Ly = lys[(size_t)i];
+        uint8_t *h = host + base[(size_t)i];
+        memcpy(h, Ly.jobs.data(), Ly.jobs.size() * sizeof(Job));
+        for (int k = 0; k < UNIT_KINDS; ++k)
+            if (!Ly.ujob[k].empty()) memcpy(h + offs[(size_t)i][k], Ly.ujob[k].data(), Ly.ujob[k].size() * 4);
+    }
+    HIPCHK(hipMemcpyAsync(dtab, host, tb, hipMemcpyHostToDevice, st));
+    HIPCHK(hipEventRecord(ctx->ring.done[slot], st));
+    ctx->ring.used[slot] = true;
+    for (int i = 0; i < n_ops; ++i) {
+        const Layout &Ly = lys[(size_t)i];
+        uint8_t *d = dtab + base[(size_t)i];
+        Launch L;
+        L.jobs = reinterpret_cast<const Job *>(d);
+        for (int k = 0; k < UNIT_KINDS; ++k)
+            L.ujob[k] = Ly.ujob[k].empty() ? nullptr : reinterpret_cast<const uint32_t *>(d + offs[(size_t)i][k]);
+        L.njobs = (int32_t)Ly.jobs.size();
+        L.ws = ws;
+        L.stream = st;
+        L.max_grid = ctx->max_grid;
+        L.g_status = Ly.g_status;
+        L.g_part = Ly.g_part;
+        L.keystream = Ly.keystream;
+        L.dyn = Ly.method == RDHEI_DEMR;
+        for (const Stage &sg : stages_of(Ly, Ly.units, Ly.per_pixel)) sg.fn(L);
+    }
     HIPCHK(hipGetLastError());
     return RDHEI_OK;
 }

@@ -30,7 +30,8 @@ META_BYTES = 64
 EXPORTS = [
     "rdhei_ctx_create", "rdhei_ctx_destroy", "rdhei_ctx_set_option",
     "rdhei_encrypt", "rdhei_embed", "rdhei_extract", "rdhei_recover",
-    "rdhei_workspace_size", "rdhei_run_batch", "rdhei_run_batch_static", "rdhei_plan_create", "rdhei_plan_run", "rdhei_plan_destroy", "rdhei_plan_set_grid",
+    "rdhei_workspace_size", "rdhei_run_batch", "rdhei_run_batch_static",
+    "rdhei_roles_workspace_size", "rdhei_run_roles", "rdhei_plan_create", "rdhei_plan_run", "rdhei_plan_destroy", "rdhei_plan_set_grid",
     "rdhei_plan_stage_count", "rdhei_plan_stage_name", "rdhei_plan_run_stage",
     "rdhei_plan_autotune", "rdhei_plan_stage_grid", "rdhei_plan_tuned", "rdhei_ctx_set_tune_file",
     "rdhei_lmr_batch", "rdhei_lmr_compress", "rdhei_lmr_decompress", "rdhei_metrics", "rdhei_tile_b",
@@ -112,6 +113,10 @@ def load_library(path: str = LIB_PATH):
     lib.rdhei_workspace_size.argtypes = [vp, i32, ctypes.POINTER(JobStruct), i32, ctypes.POINTER(ctypes.c_int64)]
     lib.rdhei_run_batch.argtypes = [vp, i32, ctypes.POINTER(JobStruct), i32, vp, ctypes.c_int64, vp]
     lib.rdhei_run_batch_static.argtypes = [vp, i32, ctypes.POINTER(JobStruct), i32, vp]
+    lib.rdhei_roles_workspace_size.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(i32),
+                                               ctypes.POINTER(ctypes.c_int64)]
+    lib.rdhei_run_roles.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(i32), vp,
+                                    ctypes.c_int64, vp]
     lib.rdhei_plan_create.argtypes = [vp, i32, ctypes.POINTER(JobStruct), i32, i32, ctypes.POINTER(vp)]
     lib.rdhei_plan_run.argtypes = [vp, vp]
     lib.rdhei_plan_destroy.argtypes = [vp]
@@ -264,6 +269,39 @@ class Context:
         p, n = _jobs_arg(jobs)
         _check(self.lib.rdhei_run_batch(self.h, op, p, n, ctypes.c_void_p(workspace_ptr or None),
                                         workspace_bytes, _stream(stream)), "rdhei_run_batch")
+
+    @staticmethod
+    def _roles_args(roles):
+        """(n, ops, tables, counts) C arrays of [(op, job table), ...]; the
+        tables (ctypes arrays or JOB_DTYPE arrays) must stay alive meanwhile."""
+        n = len(roles)
+        ops = (ctypes.c_int32 * n)(*[int(op) for op, _ in roles])
+        tabs = (ctypes.c_void_p * n)()
+        cnt = (ctypes.c_int32 * n)()
+        for i, (_, t) in enumerate(roles):
+            if isinstance(t, np.ndarray):
+                if t.dtype != JOB_DTYPE or not t.flags.c_contiguous:
+                    raise TypeError("job table must be a contiguous JOB_DTYPE array")
+                tabs[i] = t.ctypes.data
+            else:
+                tabs[i] = ctypes.addressof(t)
+            cnt[i] = len(t)
+        return n, ops, tabs, cnt
+
+    def roles_workspace_size(self, roles) -> int:
+        """Workspace bytes of run_roles over [(op, job table), ...]."""
+        n, ops, tabs, cnt = self._roles_args(roles)
+        out = ctypes.c_int64(0)
+        _check(self.lib.rdhei_roles_workspace_size(self.h, n, ops, tabs, cnt, ctypes.byref(out)),
+               "rdhei_roles_workspace_size")
+        return int(out.value)
+
+    def run_roles(self, roles, workspace_ptr: int = 0, workspace_bytes: int = 0, stream=None) -> None:
+        """Several EMR ops of one batch, [(op, job table), ...], in order on
+        `stream` with one table upload (rdhei_run_roles)."""
+        n, ops, tabs, cnt = self._roles_args(roles)
+        _check(self.lib.rdhei_run_roles(self.h, n, ops, tabs, cnt, ctypes.c_void_p(workspace_ptr or None),
+                                        workspace_bytes, _stream(stream)), "rdhei_run_roles")
 
     def run_batch_static(self, op: int, jobs, stream=None) -> None:
         """One EMR op over a job array with the library's static device

@@ -11,8 +11,8 @@ framework (Sec. I and III-A):
 Requests arrive over time.  Whenever a launch slot is free the loop admits
 the queued requests, oldest first, whose device memory (their outputs plus
 the batch's workspace) fits in a fixed pool, and issues them as one batch:
-one ``rdhei_run_batch`` per op, on the next of a few streams, with the
-workspace carved from the same pool.  Batches whose completion event has
+one ``rdhei_run_roles`` call for all of the batch's ops (one table upload),
+on the next of a few streams, with the workspace carved from the same pool.  Batches whose completion event has
 fired are retired and their memory returned.  Requests that arrive while
 other batches run are admitted as soon as a slot and pool memory are free,
 so their work overlaps on the device.  Latency is arrival to the completion
@@ -370,7 +370,7 @@ class Server:
         # table contents depend on the output base only through its alignment,
         # so size the workspace with the pool base, then shift the pointers
         tabs, out, total = self._tables(wl, idx, self.arena.base)
-        ws = 0 if self.per_request else int(_al(max(ctx.workspace_size(op, t) for op, t, _ in tabs)))
+        ws = 0 if self.per_request else int(_al(ctx.roles_workspace_size([(op, t) for op, t, _ in tabs])))
         blk = self.arena.alloc(max(ws + total, est))
         if blk is None:
             return None
@@ -383,8 +383,9 @@ class Server:
                 t[f] += np.uint64(shift)
             if self.per_request:
                 self._issue_single(ctx, sp, op, t[0])
-            else:
-                ctx.run_batch(op, t, base, ws, st)
+        if not self.per_request:
+            # every op of the batch in one call: one table upload
+            ctx.run_roles([(op, t) for op, t, _ in tabs], base, ws, st)
         ev = torch.cuda.Event(enable_timing=True)
         ev.record(st)
         for k in ("img_e", "meta_e", "msg_r", "img_r"):

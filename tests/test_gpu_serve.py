@@ -170,3 +170,63 @@ def test_request_larger_than_pool_is_rejected(S, workload):
     assert res.rejected >= 1
     assert not np.isfinite(res.latency_s[big])
     assert big not in got
+
+
+def test_run_roles_equals_run_batch_per_op(R):
+    """rdhei_run_roles (every op of a batch in one call, one table upload,
+    one shared workspace) gives the bytes of one rdhei_run_batch per op: a
+    mixed batch of new requests (encrypt then embed) and returning ones
+    (extract and recover), tiled and per-pixel shapes."""
+    from paper_2302_07992_amd import inputs
+    print("[serve] run_roles against run_batch", flush=True)
+    ctx = R.Context(0)
+    shapes = [(256, 256), (128, 320), (100, 63), (512, 512)]
+    n = len(shapes)
+    imgs = [inputs.make_image(900 + i, M, N, 8, 3.0, "cuda") for i, (M, N) in enumerate(shapes)]
+    k1 = [11 + i for i in range(n)]
+    k2 = [21 + i for i in range(n)]
+    # capacities and a marked image for every shape (the returning requests' inputs)
+    metas0 = R.new_meta(n)
+    marked = [torch.empty_like(x) for x in imgs]
+    ctx.run_batch(R.OP_ENCRYPT, R.make_jobs(imgs, marked, None, [metas0[i] for i in range(n)], k1, None, shapes,
+                                             nonces=list(range(n))))
+    torch.cuda.synchronize()
+    caps = [int(m.capacity_bits) for m in R.read_meta(metas0)]
+    msgs = [inputs.make_payload(k, c, "cuda") for k, c in zip(k2, caps)]
+    bufs = []
+    for m, c in zip(msgs, caps):
+        b = torch.zeros(R.msg_bytes(c), dtype=torch.uint8, device="cuda")
+        b[: m.numel()] = m
+        bufs.append(b)
+    ctx.run_batch(R.OP_EMBED, R.make_jobs(None, marked, bufs, [metas0[i] for i in range(n)], k2, caps, shapes))
+    torch.cuda.synchronize()
+
+    def once(use_roles):
+        metas = R.new_meta(n)
+        mp = [metas[i] for i in range(n)]
+        enc = [torch.empty_like(x) for x in imgs]
+        got = [torch.zeros(R.msg_bytes(c), dtype=torch.uint8, device="cuda") for c in caps]
+        rec = [torch.empty_like(x) for x in imgs]
+        roles = [(R.OP_ENCRYPT, R.make_jobs(imgs, enc, None, mp, k1, None, shapes, nonces=list(range(n)))),
+                 (R.OP_EMBED, R.make_jobs(None, enc, bufs, mp, k2, caps, shapes)),
+                 (R.OP_EXTRACT, R.make_jobs(marked, None, got, [metas0[i] for i in range(n)], k2, caps, shapes)),
+                 (R.OP_RECOVER, R.make_jobs(marked, rec, None, [metas0[i] for i in range(n)], k1, None, shapes))]
+        if use_roles:
+            wsb = ctx.roles_workspace_size(roles)
+            assert wsb >= max(ctx.workspace_size(op, t) for op, t in roles)
+            ws = torch.empty(wsb + 256, dtype=torch.uint8, device="cuda")
+            base = (ws.data_ptr() + 255) // 256 * 256
+            ctx.run_roles(roles, base, wsb)
+        else:
+            for op, t in roles:
+                ctx.run_batch(op, t)
+        torch.cuda.synchronize()
+        return ([e.cpu() for e in enc], [g.cpu() for g in got], [r.cpu() for r in rec], metas.cpu())
+
+    a, b = once(False), once(True)
+    for xa, xb in zip(a[:3], b[:3]):
+        for u, v in zip(xa, xb):
+            assert torch.equal(u, v)
+    assert torch.equal(a[3], b[3])
+    for g, m, c in zip(a[1], msgs, caps):
+        assert torch.equal(g[: c // 8], m[: c // 8].cpu())
