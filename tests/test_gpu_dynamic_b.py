@@ -240,3 +240,13 @@ def test_demr_invalid_arguments(R, ctx):
                                                 method=R.DEMR))
     with pytest.raises(R.RdheiError):
         ctx.encrypt(y, torch.empty_like(y), 1, meta, method=R.DEMR)
+
+
+def test_demr_4096_big_image_matches_oracle(R):
+    """A 4096 x 4096 image (4,096 tiles: the statistics and pyramid are
+    finalised across workgroups, the b totals in the top pass; 4,096 hiding
+    steps with bit-weighted ranks) through every role against the oracle,
+    with a payload ending inside a pixel."""
+    print("[demr] 4096^2", flush=True)
+    I = inputs.make_band_image(17, 4096, 4096, 8, 3.0, "cpu").numpy()
+    _demr_round_trip(R, R.Context(0), [I], [27], [28], [29], frac=0.91)
