@@ -25,8 +25,10 @@ METRIC = "Mpixel/s embed+recover (batched vs per-image) at bit-exact; p99 latenc
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_emr_batch_4000x512.md")
 STAGE_KERNEL = {"tile_prep_stats": "rdhei::k_tile_prep<true, 0, false>", "encrypt_tiles": "rdhei::k_encrypt_quad<0, 0>",
+                "encrypt_images": "rdhei::k_encrypt_image<0, 0, 8>",
                 "embed_images": "rdhei::k_hide_wave<true, 0, false>", "extract_images": "rdhei::k_hide_wave<false, 0, false>",
-                "recover_bands": "rdhei::k_recover_quad_emr<0, false>"}
+                "recover_bands": "rdhei::k_recover_quad_emr<0, false, false>",
+                "recover_images": "rdhei::k_recover_quad_emr<0, false, true>"}
 
 
 def log(*a):
@@ -873,12 +875,14 @@ def main():
 
     # ---- per-stage timing (HIP events on the launch stream) ----
     # algorithmic bytes per pixel of each stage: read I and write I_e
-    # (encryption), read I (statistics), read and write the marked image plus
-    # the payload (embedding), read the marked image and write the payload
-    # (extraction), read I_e' and write I' (recovery); the keystream pyramid
-    # of recovery reads nothing, finalisation is per image
-    per_px = {"encrypt": {"tile_prep_stats": 1.0, "encrypt_tiles": 2.0},
-              "recover": {"recover_bands": 2.0},
+    # (encryption; also the whole role one workgroup per image, whose second
+    # read of I is not counted), read I (statistics), read and write the
+    # marked image plus the payload (embedding), read the marked image and
+    # write the payload (extraction), read I_e' and write I' (recovery, by
+    # stages or one workgroup per image); the keystream pyramid of recovery
+    # reads nothing, finalisation is per image
+    per_px = {"encrypt": {"tile_prep_stats": 1.0, "encrypt_tiles": 2.0, "encrypt_images": 2.0},
+              "recover": {"recover_bands": 2.0, "recover_images": 2.0},
               "embed": {"embed_images": 2.0 + der / 8, "embed": 2.0 + der / 8},
               "extract": {"extract_images": 1.0 + der / 8, "extract": 1.0 + der / 8}}
     stages = []

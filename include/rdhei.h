@@ -209,8 +209,10 @@ int         rdhei_plan_run_stage(rdhei_plan *plan, int32_t k, void *stream);
 
 /* Launch-shape autotuner.  For each layout variant of the plan -- the hiding
  * mode of EMBED/EXTRACT plans (one wave per image where the batch allows it,
- * 4096-pixel steps in one pass, counted 4096-pixel steps), the quads per work unit of
- * ENCRYPT/RECOVER plans (2, 4, 8, 16) -- it times every stage at several
+ * 4096-pixel steps in one pass, counted 4096-pixel steps), for ENCRYPT and
+ * RECOVER plans by stages or one workgroup per image (where the batch allows
+ * it) and, by stages, the quads per work unit (2, 4, 8, 16) -- it times every
+ * stage at several
  * workgroup counts (the launcher's default -- what fits on the device at once
  * -- and 1, 2, 4, 8, 16 and 32 workgroups per compute unit), max(reps, 5)
  * timed runs each after a warm-up.  A candidate replaces the current choice
@@ -228,9 +230,10 @@ int         rdhei_plan_run_stage(rdhei_plan *plan, int32_t k, void *stream);
  * rdhei_plan_set_grid clears the tuned counts. */
 #define RDHEI_TUNE_FORCE 1
 int rdhei_plan_autotune(rdhei_plan *plan, int32_t reps, int32_t flags, void *stream);
-/* The plan's layout variant: hiding mode (RDHEI_OPT_HIDE_MODE values) and
- * quads per work unit (either pointer may be NULL). */
-int rdhei_plan_tuned(rdhei_plan *plan, int32_t *hide_mode, int32_t *qseg);
+/* The plan's layout variant: hiding mode (RDHEI_OPT_HIDE_MODE values), quads
+ * per work unit and workgroup-per-image mode (RDHEI_OPT_WG_PER_IMAGE values);
+ * any pointer may be NULL. */
+int rdhei_plan_tuned(rdhei_plan *plan, int32_t *hide_mode, int32_t *qseg, int32_t *wg_image);
 /* Persist the autotuner's choices: entries of the JSON file at `path` (if it
  * exists) are loaded into the context now, and the file is rewritten after
  * every autotune.  NULL or "" keeps choices in memory only.  RDHEI_EINVAL for
@@ -312,6 +315,22 @@ int rdhei_run_batch_static(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, in
 #define RDHEI_OPT_QUAD_SEG  7    /* encryption and EMR recovery: 2x2 tile quads
                                     per work unit along a band pair (1..64,
                                     default 4); results are identical        */
+#define RDHEI_OPT_WG_PER_IMAGE 8 /* EMR and DEMR encryption and recovery of
+                                    batches whose images are all tiled (sides
+                                    multiples of 64) with at most 1024 tiles
+                                    each: 0 one workgroup per image once the
+                                    batch has eight images per compute unit,
+                                    else by stages; 1 by stages (every tile's
+                                    label statistics or keystream codes, then
+                                    per-image finalisation, then the
+                                    permuting pass, each launch spread over
+                                    all tiles); 2 one workgroup per image does
+                                    all of an image in one launch (encryption
+                                    reads the image the second time soon
+                                    after the first; the vector-bound code
+                                    work of some images overlaps the memory-
+                                    bound pass of others).  Other batches go
+                                    by stages.  Results are identical.       */
 #define RDHEI_KEYSTREAM_PHILOX   0
 #define RDHEI_KEYSTREAM_CHACHA20 1
 int rdhei_ctx_set_option(rdhei_ctx *ctx, int32_t option, int64_t value);

@@ -123,6 +123,7 @@ struct Layout {
     uint32_t units[UNIT_KINDS] = {};
     uint64_t g_status = 0, g_part = 0;   // hiding workspace (embed/extract)
     bool one_pass = false;               // steps hidden in one pass (look-back), else counted first
+    bool images = false;                 // encryption / recovery one workgroup per image, else by stages
     int op = 0;
     int method = RDHEI_EMR;
     int keystream = kKsPhilox;
@@ -137,6 +138,7 @@ struct LayoutOpts {
     int lmr_min_level = 4;    // RDHEI_OPT_LMR_MIN_LEVEL
     int keystream = kKsPhilox;   // RDHEI_OPT_KEYSTREAM
     int qseg = kQuadSeg;         // quads per encryption / EMR recovery work unit
+    int wg_image = 0;            // RDHEI_OPT_WG_PER_IMAGE
 };
 
 // Whether image q of a hiding op may be walked whole by one workgroup.
@@ -154,6 +156,41 @@ bool whole_eligible(int op, const rdhei_job &q) {
            aligned16(pin) && aligned16(q.out);
 }
 
+// Whether image q of a rotation role (encrypt / recover) takes the tiled path:
+// sides multiples of 64, 16-byte aligned buffers, at most kTmapMaxTiles tiles
+// along each side (the tile map's coordinate width).
+bool tiled_ok(int op, const rdhei_job &q, bool force_per_pixel) {
+    const bool rot = op == RDHEI_OP_ENCRYPT || op == RDHEI_OP_RECOVER;
+    return rot && !force_per_pixel && q.height % kTile == 0 && q.width % kTile == 0 && aligned16(q.in) &&
+           aligned16(q.out) && q.height / kTile <= kTmapMaxTiles && q.width / kTile <= kTmapMaxTiles;
+}
+
+// Whether a batch of a rotation role may go one workgroup per image: EMR or
+// DEMR, every image tiled with at most kImageWgMaxTiles tiles.
+bool wg_image_ok(int op, const rdhei_job *in, int n, bool force_per_pixel) {
+    if (op != RDHEI_OP_ENCRYPT && op != RDHEI_OP_RECOVER) return false;
+    for (int i = 0; i < n; ++i) {
+        const rdhei_job &q = in[i];
+        if (q.method != RDHEI_EMR && q.method != RDHEI_DEMR) return false;
+        if (!tiled_ok(op, q, force_per_pixel)) return false;
+        if ((uint64_t)(q.height / kTile) * (uint64_t)(q.width / kTile) > kImageWgMaxTiles) return false;
+    }
+    return n > 0;
+}
+
+// Images from which RDHEI_OPT_WG_PER_IMAGE 0 goes one workgroup per image:
+// eight per compute unit, so that the last round of images is a small part of
+// the launch.
+size_t wg_image_min() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    }
+    return 8 * (size_t)cus;
+}
+
 int make_layout(int op, const rdhei_job *in, int n, const LayoutOpts &opt, Layout &L) {
     L = Layout();
     L.op = op;
@@ -162,6 +199,8 @@ int make_layout(int op, const rdhei_job *in, int n, const LayoutOpts &opt, Layou
     L.method = in[0].method;
     L.one_pass = opt.hide_mode == 3;
     const bool force_per_pixel = opt.per_pixel;
+    L.images = opt.wg_image != 1 && wg_image_ok(op, in, n, force_per_pixel) &&
+               (opt.wg_image == 2 || (size_t)n >= wg_image_min());
     bool whole_ok = opt.hide_mode == 1;
     if (opt.hide_mode == 0) {
         uint32_t eligible = 0;
@@ -202,8 +241,7 @@ int make_layout(int op, const rdhei_job *in, int n, const LayoutOpts &opt, Layou
         const bool rot = op == RDHEI_OP_ENCRYPT || op == RDHEI_OP_RECOVER;
         // the tile map holds 14-bit tile coordinates: images with more tiles
         // along a side take the per-pixel path
-        J.fast = rot && !force_per_pixel && q.height % kTile == 0 && q.width % kTile == 0 && aligned16(J.in) &&
-                 aligned16(J.out) && q.height / kTile <= kTmapMaxTiles && q.width / kTile <= kTmapMaxTiles ? 1 : 0;
+        J.fast = tiled_ok(op, q, force_per_pixel) ? 1 : 0;
         if (q.method == RDHEI_DEMR) {
             // one b per tile: the tiled path for every op, and the tile table;
             // payload bit offsets stay below 2^32 (images of at most 2^29 pixels)
@@ -221,6 +259,7 @@ int make_layout(int op, const rdhei_job *in, int n, const LayoutOpts &opt, Layou
         }
         J.nseg = (int32_t)((MN + seg_pixels() - 1) / seg_pixels());
         J.qseg = opt.qseg;
+        if (L.images) J.qseg = std::max(opt.qseg, (J.tiles_x + 1) / 2);   // a band pair is one segment
         if (rot) {
             const uint64_t tiles = (uint64_t)J.tiles_x * J.tiles_y;
             J.ws_codes = ws;
@@ -291,7 +330,11 @@ std::vector<Stage> stages_of(const Layout &Ly, const uint32_t *units_in, std::ve
     std::vector<int> big;   // images finalised across many workgroups
     for (size_t i = 0; i < hj.size(); ++i)
         if (hj[i].fast && (uint32_t)(hj[i].tiles_x * hj[i].tiles_y) >= kBigTiles) big.push_back((int)i);
-    if (op == RDHEI_OP_ENCRYPT) {
+    if (op == RDHEI_OP_ENCRYPT && Ly.images) {
+        S.push_back({"encrypt_images", [=](const Launch &L) { launch_encrypt_images(L); }});
+    } else if (op == RDHEI_OP_RECOVER && Ly.images) {
+        S.push_back({"recover_images", [=](const Launch &L) { launch_recover_images(L); }});
+    } else if (op == RDHEI_OP_ENCRYPT) {
         if (ut) S.push_back({"tile_prep_stats", [=](const Launch &L) { launch_tile_prep(L, ut, true); }});
         if (!pp.empty())
             S.push_back({"per_pixel_levels_stats", [=](const Launch &L) {
@@ -348,6 +391,7 @@ void issue(const Layout &Ly, const Launch &L, const uint32_t *units, const int *
 struct TuneRecord {
     int hide_mode = 0;
     int qseg = kQuadSeg;
+    int wg_image = 0;
     std::vector<int> grids;
 };
 
@@ -400,6 +444,7 @@ struct rdhei_ctx {
     int lmr_min_level = 4;
     int keystream = kKsPhilox;
     int qseg = kQuadSeg;
+    int wg_image = 0;
     std::map<std::string, TuneRecord> tuned;   // autotuner choices by device/op/size class
     std::string tune_file;              // where the choices persist (empty: memory only)
     int max_grid = 0;
@@ -442,6 +487,7 @@ LayoutOpts opts_of(const rdhei_ctx *ctx) {
     o.lmr_min_level = ctx->lmr_min_level;
     o.keystream = ctx->keystream;
     o.qseg = ctx->qseg;
+    o.wg_image = ctx->wg_image;
     return o;
 }
 
@@ -1040,7 +1086,8 @@ int plan_apply(rdhei_plan *P, const TuneRecord &v) {
     LayoutOpts o = P->opts;
     o.hide_mode = v.hide_mode;
     o.qseg = v.qseg;
-    if (o.hide_mode != P->opts.hide_mode || o.qseg != P->opts.qseg) {
+    o.wg_image = v.wg_image;
+    if (o.hide_mode != P->opts.hide_mode || o.qseg != P->opts.qseg || o.wg_image != P->opts.wg_image) {
         Layout Ly;
         int rc = make_layout(P->op, P->src.data(), (int)P->src.size(), o, Ly);
         if (rc) return rc;
@@ -1072,8 +1119,8 @@ void tune_save(const rdhei_ctx *ctx) {
     fprintf(f, "{\n  \"rdhei_tune\": 1,\n  \"entries\": {");
     bool first = true;
     for (const auto &kv : ctx->tuned) {
-        fprintf(f, "%s\n    \"%s\": {\"hide_mode\": %d, \"qseg\": %d, \"grids\": [", first ? "" : ",", kv.first.c_str(),
-                kv.second.hide_mode, kv.second.qseg);
+        fprintf(f, "%s\n    \"%s\": {\"hide_mode\": %d, \"qseg\": %d, \"wg_image\": %d, \"grids\": [", first ? "" : ",",
+                kv.first.c_str(), kv.second.hide_mode, kv.second.qseg, kv.second.wg_image);
         for (size_t i = 0; i < kv.second.grids.size(); ++i) fprintf(f, "%s%d", i ? ", " : "", kv.second.grids[i]);
         fprintf(f, "]}");
         first = false;
@@ -1115,7 +1162,10 @@ int tune_load(rdhei_ctx *ctx) {
         if (o1 == std::string::npos) return RDHEI_EINVAL;
         TuneRecord r;
         if (!int_after("hide_mode", o0, o1, r.hide_mode) || !int_after("qseg", o0, o1, r.qseg)) return RDHEI_EINVAL;
-        if (r.hide_mode < 0 || r.hide_mode > 3 || r.qseg < 1 || r.qseg > kQuadSegMax) return RDHEI_EINVAL;
+        if (!int_after("wg_image", o0, o1, r.wg_image)) r.wg_image = 0;   // files written before the field existed
+        if (r.hide_mode < 0 || r.hide_mode > 3 || r.qseg < 1 || r.qseg > kQuadSegMax || r.wg_image < 0 ||
+            r.wg_image > 2)
+            return RDHEI_EINVAL;
         const size_t g0 = t.find('[', o0), g1 = t.find(']', o0);
         if (g0 == std::string::npos || g1 == std::string::npos || g1 > o1) return RDHEI_EINVAL;
         for (const char *c = t.c_str() + g0 + 1; c < t.c_str() + g1;) {
@@ -1234,6 +1284,9 @@ int rdhei_ctx_set_option(rdhei_ctx *ctx, int32_t option, int64_t value) {
     } else if (option == RDHEI_OPT_QUAD_SEG) {
         if (value < 1 || value > kQuadSegMax) return RDHEI_EINVAL;
         ctx->qseg = (int)value;
+    } else if (option == RDHEI_OPT_WG_PER_IMAGE) {
+        if (value < 0 || value > 2) return RDHEI_EINVAL;
+        ctx->wg_image = (int)value;
     } else if (option == RDHEI_OPT_RESERVE_WS) {
         if (value < 0) return RDHEI_EINVAL;
         int rc = set_device(ctx->device);
@@ -1754,6 +1807,7 @@ int rdhei_plan_autotune(rdhei_plan *P, int32_t reps, int32_t flags, void *stream
         TuneRecord v0;
         v0.hide_mode = base.hide_mode;
         v0.qseg = base.qseg;
+        v0.wg_image = base.wg_image;
         variants.push_back(v0);
         const bool hide = P->op == RDHEI_OP_EMBED || P->op == RDHEI_OP_EXTRACT;
         bool eligible = false;
@@ -1770,11 +1824,20 @@ int rdhei_plan_autotune(rdhei_plan *P, int32_t reps, int32_t flags, void *stream
                 v.hide_mode = hm;
                 variants.push_back(v);
             }
+        // encryption / recovery by stages or one workgroup per image (where the batch allows)
+        const bool img_ok = wg_image_ok(P->op, P->src.data(), (int)P->src.size(), base.per_pixel);
+        if (img_ok) {
+            TuneRecord v = v0;
+            v.wg_image = P->layout.images ? 1 : 2;
+            variants.push_back(v);
+        }
+        // quads per work unit (stage-wise encryption and recovery)
         if (!hide && max_nq > 1)
             for (int qs : {2, 4, 8, 16}) {
                 if (qs == v0.qseg || (uint32_t)qs / 2 >= max_nq) continue;   // longer than every band pair: same as a shorter one
                 TuneRecord v = v0;
                 v.qseg = qs;
+                if (img_ok) v.wg_image = 1;
                 variants.push_back(v);
             }
     }
@@ -1853,10 +1916,11 @@ int rdhei_plan_autotune(rdhei_plan *P, int32_t reps, int32_t flags, void *stream
     return RDHEI_OK;
 }
 
-int rdhei_plan_tuned(rdhei_plan *P, int32_t *hide_mode, int32_t *qseg) {
+int rdhei_plan_tuned(rdhei_plan *P, int32_t *hide_mode, int32_t *qseg, int32_t *wg_image) {
     if (!P) return RDHEI_EINVAL;
     if (hide_mode) *hide_mode = P->opts.hide_mode;
     if (qseg) *qseg = P->opts.qseg;
+    if (wg_image) *wg_image = P->opts.wg_image;
     return RDHEI_OK;
 }
 

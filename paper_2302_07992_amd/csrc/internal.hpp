@@ -143,6 +143,15 @@ constexpr int kFinBlock = 16;
 // big: indices of such jobs; hj: the host copy of the job table
 void launch_finalize(const Launch &L, bool stats, const std::vector<int> &big, const std::vector<Job> &hj);
 void launch_encrypt_tiles(const Launch &L, uint32_t units, int mode);
+// EMR / DEMR encryption and recovery of whole images, one workgroup per image
+// (of kEncImageWaves waves for encryption): statistics or keystream codes,
+// finalisation and the permuting pass in one kernel.  Every image of the
+// launch must be tiled, with at most kImageWgMaxTiles tiles; for recovery
+// every band pair must be one quad segment.
+constexpr uint32_t kImageWgMaxTiles = 1024;
+constexpr int kEncImageWaves = 8;
+void launch_encrypt_images(const Launch &L);
+void launch_recover_images(const Launch &L);
 // fix_rows, fix_segs: most rows and most quad segments per band pair of the EMR
 // images cut into segments (fix_rows 0: none)
 void launch_recover_bands(const Launch &L, uint32_t units, int method, uint32_t fix_rows, uint32_t fix_segs);

@@ -31,6 +31,195 @@ __device__ __forceinline__ void unit_range(uint32_t units, uint32_t &u0, uint32_
 }
 
 // ----------------------------------------------------------------------------
+// Per-tile building blocks shared by the staged kernels (k_tile_prep,
+// k_encrypt_quad) and the one-workgroup-per-image encryption (k_encrypt_image).
+// Lane (q, g) of the wave that owns a tile holds rows 4q..4q+3, columns
+// 16g..16g+15 of it.
+// ----------------------------------------------------------------------------
+
+// Rotation codes of tile t (levels 1..6 inside the tile, Sec. III-A rotation
+// equation: block code = (sum of s over the block) mod 4) into the tile's code
+// record, and the tile's own code (level 6) into the pyramid.
+template <int KS>
+__device__ __forceinline__ void tile_codes(const Job &J, uint64_t nz, uint32_t t, int ty, int tx, int q, int g, int lane,
+                                           uint8_t *__restrict__ ws) {
+    const uint64_t idx0 = (uint64_t)(ty * kTile + 4 * q) * (uint64_t)J.N + (uint64_t)(tx * kTile + 16 * g);
+
+    // level 1 (2x2) pair sums: h[pp][k] bytes 0 and 2, rows 4q+2pp..+1, columns 16g+4k..+3
+    uint32_t h[2][4];
+#pragma unroll
+    for (int pp = 0; pp < 2; ++pp) {
+        const U4 sa = stream_block_quad<KS>(J.key, nz, kDomainImage, (idx0 + (uint64_t)(2 * pp) * J.N) >> 4);
+        const U4 sb = stream_block_quad<KS>(J.key, nz, kDomainImage, (idx0 + (uint64_t)(2 * pp + 1) * J.N) >> 4);
+        const uint32_t wa[4] = {sa.x, sa.y, sa.z, sa.w}, wb[4] = {sb.x, sb.y, sb.z, sb.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t a = (wa[k] & 0x03030303u) + (wb[k] & 0x03030303u);   // <= 6 per byte
+            h[pp][k] = a + (a >> 8);                                            // bytes 0, 2: <= 12
+        }
+    }
+    // level-1 codes: code row 4q/2 + pp, code columns 8g..8g+7 -> 16 bits
+    uint8_t *rec = ws + J.ws_codes + (uint64_t)t * kCodeRecord;
+#pragma unroll
+    for (int pp = 0; pp < 2; ++pp) {
+        const uint32_t c = vperm(h[pp][1], h[pp][0], 0x06040200u) & 0x03030303u;
+        const uint32_t d = vperm(h[pp][3], h[pp][2], 0x06040200u) & 0x03030303u;
+        const uint32_t c8 = (c | (c >> 6) | (c >> 12) | (c >> 18)) & 0xFFu;
+        const uint32_t d8 = (d | (d >> 6) | (d >> 12) | (d >> 18)) & 0xFFu;
+        gstore<uint16_t>(rec + code_off(1) + (2 * q + pp) * 8 + 2 * g, (uint16_t)(c8 | (d8 << 8)));
+    }
+    // level 2 (4x4): block (q, 4g + k)
+    uint32_t L2[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t v = h[0][k] + h[1][k];
+        L2[k] = (v + (v >> 16)) & 0xFFu;                    // <= 48
+    }
+    gstore<uint8_t>(rec + code_off(2) + q * 4 + g,
+                    (uint8_t)((L2[0] & 3u) | ((L2[1] & 3u) << 2) | ((L2[2] & 3u) << 4) | ((L2[3] & 3u) << 6)));
+    // level 3 (8x8): block (q/2, 2g + jj) for even q, from lanes q and q+1
+    const uint32_t hs = (L2[0] + L2[1]) | ((L2[2] + L2[3]) << 16);
+    // (lanes of a row of 16 are q = 4r..4r+3, so these partners stay in the row)
+    const uint32_t L3 = hs + row_shl<4>(hs);                // halves: columns 2g, 2g+1
+    const uint32_t nib = (L3 & 3u) | ((L3 >> 14) & 0xCu);
+    const uint32_t nib_hi = row_shl<1>(nib);
+    if ((q & 1) == 0 && (g & 1) == 0)
+        gstore<uint8_t>(rec + code_off(3) + (q >> 1) * 2 + (g >> 1), (uint8_t)(nib | (nib_hi << 4)));
+    // level 4 (16x16): block (q/4, g) for q % 4 == 0, from lanes q, q+2
+    const uint32_t l3s = (L3 & 0xFFFFu) + (L3 >> 16);
+    const uint32_t L4 = l3s + row_shl<8>(l3s);
+    const uint32_t c4 = L4 & 3u;
+    const uint32_t c4row = c4 | (row_shl<1>(c4) << 2) | (row_shl<2>(c4) << 4) | (row_shl<3>(c4) << 6);
+    if ((q & 3) == 0 && g == 0) gstore<uint8_t>(rec + code_off(4) + (q >> 2), (uint8_t)c4row);
+    // level 5 (32x32): the sums of 16x16 column pairs sit in lanes 0, 2 (rows 0..15),
+    // 16, 18 (16..31), 32, 34, 48, 50; level 6 (the tile) follows, on the scalar unit
+    const uint32_t l4h = L4 + row_shl<1>(L4);
+    auto at = [&](int l) { return (uint32_t)__builtin_amdgcn_readlane((int)l4h, l); };
+    const uint32_t c5a = (at(0) + at(16)) & 3u, c5b = (at(2) + at(18)) & 3u;
+    const uint32_t c5c = (at(32) + at(48)) & 3u, c5d = (at(34) + at(50)) & 3u;
+    if (lane == 0) {
+        const uint32_t c6 = (c5a + c5b + c5c + c5d) & 3u;
+        gstore<uint8_t>(rec + code_off(5), (uint8_t)(c5a | (c5b << 2) | (c5c << 4) | (c5d << 6)));
+        gstore<uint8_t>(rec + code_off(6), (uint8_t)c6);
+        ws[J.ws_pyr + t] = (uint8_t)c6;
+    }
+}
+
+// The lane's pixels of tile (ty, tx), and the byte left of each of its four
+// rows (meaningful in lanes g = 0 of tiles past column 0).
+__device__ __forceinline__ void tile_load(const Job &J, int ty, int tx, int q, int g, uint4 p[4], uint32_t &left) {
+    const uint8_t *row = J.in + (uint64_t)(ty * kTile + 4 * q) * (uint64_t)J.N + (uint64_t)(tx * kTile + 16 * g);
+    uint32_t lb = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        p[i] = gload<uint4>(row + (uint64_t)i * J.N);
+        lb |= (uint32_t)gload<uint8_t>(row + (uint64_t)i * J.N - ((g == 0 && tx > 0) ? 1 : 0)) << (8 * i);
+    }
+    left = lb;
+}
+
+// Per lane, the thermometer codes of its pixels (bit k of a byte: x >= 2^k,
+// x = pixel XOR left neighbour) are summed bit-sliced: a carry-save tree over
+// the 16 words of a tile (ones, twos, fours, eights: weights 1..8) and a ripple
+// counter of the tree's sixteens across tiles (hi[p]: weight 16 * 2^p).  Z_b =
+// pixels - (pixels with x >= 2^(8-b)); the counters are emptied after at most
+// kHeldMax tiles (before hi can overflow).
+constexpr int kHiPlanes = 6;
+constexpr uint32_t kHeldMax = (1u << kHiPlanes) - 1u;
+struct Thermo {
+    uint32_t ones, twos, fours, eights, hi[kHiPlanes];
+};
+__device__ __forceinline__ void thermo_clear(Thermo &C) {
+    C.ones = C.twos = C.fours = C.eights = 0;
+#pragma unroll
+    for (int p = 0; p < kHiPlanes; ++p) C.hi[p] = 0;
+}
+// carry-save adder: h:l = a + b + c, bitwise
+__device__ __forceinline__ void csa(uint32_t &h, uint32_t &l, uint32_t a, uint32_t b, uint32_t c) {
+    h = __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);   // majority
+    l = __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);   // parity
+}
+// lambda >= b exactly when x = pixel XOR left neighbour is below 2^(8-b): y
+// smears each byte of x down, so bit k of y says x >= 2^k.  left: the byte left
+// of each of the lane's four rows (lanes g = 0); column 0 counts as differing.
+__device__ __forceinline__ void tile_thermo(const uint4 p[4], uint32_t left, int tx, int g, uint32_t y[16]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t w[4] = {p[i].x, p[i].y, p[i].z, p[i].w};
+        // byte left of the lane's 16 pixels: lane g-1 of the row, or the previous tile for g = 0
+        uint32_t lb = (uint32_t)__builtin_amdgcn_mov_dpp((int)(p[i].w >> 24), 0x90, 0xF, 0xF, false);
+        if (g == 0) lb = (left >> (8 * i)) & 0xFFu;
+        uint32_t x[4];
+        x[0] = w[0] ^ ((w[0] << 8) | lb);
+        x[1] = w[1] ^ __builtin_amdgcn_alignbit(w[1], w[0], 24);
+        x[2] = w[2] ^ __builtin_amdgcn_alignbit(w[2], w[1], 24);
+        x[3] = w[3] ^ __builtin_amdgcn_alignbit(w[3], w[2], 24);
+        if (tx == 0 && g == 0) x[0] |= 0xFFu;     // column 0 has no left neighbour
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            uint32_t t = x[k];                                                // t | (t >> s) & mask
+            t = __builtin_amdgcn_bitop3_b32(t, t >> 1, 0x7F7F7F7Fu, 0xF8);
+            t = __builtin_amdgcn_bitop3_b32(t, t >> 2, 0x3F3F3F3Fu, 0xF8);
+            t = __builtin_amdgcn_bitop3_b32(t, t >> 4, 0x0F0F0F0Fu, 0xF8);
+            y[4 * i + k] = t;
+        }
+    }
+}
+// One tile's 16 thermometer words into the counters: ones, twos, fours,
+// eights, and the word of sixteens rippled into hi.
+__device__ __forceinline__ void thermo_add(Thermo &C, const uint32_t y[16]) {
+    uint32_t tA, tB, fA, fB, eA, eB, sx;
+    csa(tA, C.ones, C.ones, y[0], y[1]);
+    csa(tB, C.ones, C.ones, y[2], y[3]);
+    csa(fA, C.twos, C.twos, tA, tB);
+    csa(tA, C.ones, C.ones, y[4], y[5]);
+    csa(tB, C.ones, C.ones, y[6], y[7]);
+    csa(fB, C.twos, C.twos, tA, tB);
+    csa(eA, C.fours, C.fours, fA, fB);
+    csa(tA, C.ones, C.ones, y[8], y[9]);
+    csa(tB, C.ones, C.ones, y[10], y[11]);
+    csa(fA, C.twos, C.twos, tA, tB);
+    csa(tA, C.ones, C.ones, y[12], y[13]);
+    csa(tB, C.ones, C.ones, y[14], y[15]);
+    csa(fB, C.twos, C.twos, tA, tB);
+    csa(eB, C.fours, C.fours, fA, fB);
+    csa(sx, C.eights, C.eights, eA, eB);
+#pragma unroll
+    for (int p = 0; p < kHiPlanes; ++p) {
+        const uint32_t c = C.hi[p] & sx;
+        C.hi[p] ^= sx;
+        sx = c;
+    }
+}
+// This lane's pixels with x >= 2^(8-b) in the counters (planes: hi planes in use).
+__device__ __forceinline__ uint32_t thermo_ge(const Thermo &C, int b, int planes) {
+    const uint32_t m = 0x01010101u << (8 - b);
+    uint32_t h = 0;
+#pragma unroll
+    for (int p = 0; p < kHiPlanes; ++p)
+        if (p < planes) h += (uint32_t)__popc(C.hi[p] & m) << p;
+    return (uint32_t)__popc(C.ones & m) + 2u * (uint32_t)__popc(C.twos & m) + 4u * (uint32_t)__popc(C.fours & m) +
+           8u * (uint32_t)__popc(C.eights & m) + 16u * h;
+}
+// Dynamic b: the b_t of the one tile in the counters (the first b in 2..7
+// reaching the largest b * Z_b(t)), its Z_{b_t}(t) and b_t * Z_{b_t}(t);
+// wave-uniform.
+__device__ __forceinline__ void thermo_tile_b(const Thermo &C, uint32_t &best_b, uint32_t &best_z, uint32_t &best_s) {
+    best_b = 2;
+    best_z = 0;
+    best_s = 0;
+#pragma unroll
+    for (int b = 2; b <= 7; ++b) {
+        const uint32_t z = uni((uint32_t)__builtin_amdgcn_readlane((int)wave_scan_incl(64u - thermo_ge(C, b, 1)), 63));
+        if (b == 2 || (uint32_t)b * z > best_s) {
+            best_b = (uint32_t)b;
+            best_z = z;
+            best_s = (uint32_t)b * z;
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
 // Keystream code pyramid of one tile (Sec. III-A rotation equation: block code
 // = (sum of s over the block) mod 4 at every level 2^1..2^6 inside the tile)
 // and, for encryption, the counts Z_b of pixels whose leading-shared-bit count
@@ -75,26 +264,12 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
         const Job &J = jobs[uni((uint32_t)find_job<UNIT_TILE>(jobs, njobs, u, ujob))];
         const uint32_t t = u - J.ubase[UNIT_TILE];
         const int ty = (int)(t / (uint32_t)J.tiles_x), tx = (int)(t % (uint32_t)J.tiles_x);
-        const uint8_t *row = J.in + (uint64_t)(ty * kTile + 4 * q) * (uint64_t)J.N + (uint64_t)(tx * kTile + 16 * g);
-        uint32_t lb = 0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            p_n[i] = gload<uint4>(row + (uint64_t)i * J.N);
-            lb |= (uint32_t)gload<uint8_t>(row + (uint64_t)i * J.N - ((g == 0 && tx > 0) ? 1 : 0)) << (8 * i);
-        }
-        left_n = lb;
+        tile_load(J, ty, tx, q, g, p_n, left_n);
     };
     if (STATS && u0 < r1) fetch(u0);
 
-    // Per lane, the thermometer codes of its pixels (bit k of a byte: x >= 2^k)
-    // are summed bit-sliced: a carry-save tree over the 16 words of a tile
-    // (ones, twos, fours, eights: weights 1..8) and a ripple counter of the
-    // tree's sixteens across tiles (hi[p]: weight 16 * 2^p).  Z_b = pixels -
-    // (pixels with x >= 2^(8-b)), taken out when the wave leaves an image or
-    // after kHeldMax tiles (before hi can overflow).
-    constexpr int kHiPlanes = 6;
-    constexpr uint32_t kHeldMax = (1u << kHiPlanes) - 1u;
-    uint32_t ones = 0, twos = 0, fours = 0, eights = 0, hi[kHiPlanes] = {0, 0, 0, 0, 0, 0};
+    Thermo C;
+    thermo_clear(C);
     uint32_t held = 0;   // tiles in the counters (wave-uniform)
     int cur_j = -1;
     auto flush = [&](int jj) {                  // wave sums into one of the image's counter slots
@@ -105,24 +280,11 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
         const uint32_t px = 64u * held;         // this lane's pixels
 #pragma unroll
         for (int b = 2; b <= 8; ++b) {
-            const uint32_t m = 0x01010101u << (8 - b);
-            uint32_t h = 0;
-#pragma unroll
-            for (int p = 0; p < kHiPlanes; ++p) h += (uint32_t)__popc(hi[p] & m) << p;
-            const uint32_t ge = (uint32_t)__popc(ones & m) + 2u * (uint32_t)__popc(twos & m) +
-                                4u * (uint32_t)__popc(fours & m) + 8u * (uint32_t)__popc(eights & m) + 16u * h;
-            const uint32_t v = wave_scan_incl(px - ge);   // lane 63: the wave's Z_b
+            const uint32_t v = wave_scan_incl(px - thermo_ge(C, b, kHiPlanes));   // lane 63: the wave's Z_b
             if (lane == 63 && v) atomicAdd(&st[b - 2], v);
         }
-        ones = twos = fours = eights = 0;
-#pragma unroll
-        for (int p = 0; p < kHiPlanes; ++p) hi[p] = 0;
+        thermo_clear(C);
         held = 0;
-    };
-    // carry-save adder: h:l = a + b + c, bitwise
-    auto csa = [](uint32_t &h, uint32_t &l, uint32_t a, uint32_t b, uint32_t c) {
-        h = __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);   // majority
-        l = __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);   // parity
     };
 
     // STATS: one barrier per iteration keeps the waves of a workgroup on the
@@ -146,136 +308,21 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
         const uint64_t nz = job_nonce(J);
         const uint32_t t = u - J.ubase[UNIT_TILE];
         const int ty = (int)(t / (uint32_t)J.tiles_x), tx = (int)(t % (uint32_t)J.tiles_x);
-        const uint64_t idx0 = (uint64_t)(ty * kTile + 4 * q) * (uint64_t)J.N + (uint64_t)(tx * kTile + 16 * g);
-
-        // level 1 (2x2) pair sums: h[pp][k] bytes 0 and 2, rows 4q+2pp..+1, columns 16g+4k..+3
-        uint32_t h[2][4];
-#pragma unroll
-        for (int pp = 0; pp < 2; ++pp) {
-            const U4 sa = stream_block_quad<KS>(J.key, nz, kDomainImage, (idx0 + (uint64_t)(2 * pp) * J.N) >> 4);
-            const U4 sb = stream_block_quad<KS>(J.key, nz, kDomainImage, (idx0 + (uint64_t)(2 * pp + 1) * J.N) >> 4);
-            const uint32_t wa[4] = {sa.x, sa.y, sa.z, sa.w}, wb[4] = {sb.x, sb.y, sb.z, sb.w};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint32_t a = (wa[k] & 0x03030303u) + (wb[k] & 0x03030303u);   // <= 6 per byte
-                h[pp][k] = a + (a >> 8);                                            // bytes 0, 2: <= 12
-            }
-        }
-        // level-1 codes: code row 4q/2 + pp, code columns 8g..8g+7 -> 16 bits
-        uint8_t *rec = ws + J.ws_codes + (uint64_t)t * kCodeRecord;
-#pragma unroll
-        for (int pp = 0; pp < 2; ++pp) {
-            const uint32_t c = vperm(h[pp][1], h[pp][0], 0x06040200u) & 0x03030303u;
-            const uint32_t d = vperm(h[pp][3], h[pp][2], 0x06040200u) & 0x03030303u;
-            const uint32_t c8 = (c | (c >> 6) | (c >> 12) | (c >> 18)) & 0xFFu;
-            const uint32_t d8 = (d | (d >> 6) | (d >> 12) | (d >> 18)) & 0xFFu;
-            gstore<uint16_t>(rec + code_off(1) + (2 * q + pp) * 8 + 2 * g, (uint16_t)(c8 | (d8 << 8)));
-        }
-        // level 2 (4x4): block (q, 4g + k)
-        uint32_t L2[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t v = h[0][k] + h[1][k];
-            L2[k] = (v + (v >> 16)) & 0xFFu;                    // <= 48
-        }
-        gstore<uint8_t>(rec + code_off(2) + q * 4 + g,
-                        (uint8_t)((L2[0] & 3u) | ((L2[1] & 3u) << 2) | ((L2[2] & 3u) << 4) | ((L2[3] & 3u) << 6)));
-        // level 3 (8x8): block (q/2, 2g + jj) for even q, from lanes q and q+1
-        const uint32_t hs = (L2[0] + L2[1]) | ((L2[2] + L2[3]) << 16);
-        // (lanes of a row of 16 are q = 4r..4r+3, so these partners stay in the row)
-        const uint32_t L3 = hs + row_shl<4>(hs);                // halves: columns 2g, 2g+1
-        const uint32_t nib = (L3 & 3u) | ((L3 >> 14) & 0xCu);
-        const uint32_t nib_hi = row_shl<1>(nib);
-        if ((q & 1) == 0 && (g & 1) == 0)
-            gstore<uint8_t>(rec + code_off(3) + (q >> 1) * 2 + (g >> 1), (uint8_t)(nib | (nib_hi << 4)));
-        // level 4 (16x16): block (q/4, g) for q % 4 == 0, from lanes q, q+2
-        const uint32_t l3s = (L3 & 0xFFFFu) + (L3 >> 16);
-        const uint32_t L4 = l3s + row_shl<8>(l3s);
-        const uint32_t c4 = L4 & 3u;
-        const uint32_t c4row = c4 | (row_shl<1>(c4) << 2) | (row_shl<2>(c4) << 4) | (row_shl<3>(c4) << 6);
-        if ((q & 3) == 0 && g == 0) gstore<uint8_t>(rec + code_off(4) + (q >> 2), (uint8_t)c4row);
-        // level 5 (32x32): the sums of 16x16 column pairs sit in lanes 0, 2 (rows 0..15),
-        // 16, 18 (16..31), 32, 34, 48, 50; level 6 (the tile) follows, on the scalar unit
-        const uint32_t l4h = L4 + row_shl<1>(L4);
-        auto at = [&](int l) { return (uint32_t)__builtin_amdgcn_readlane((int)l4h, l); };
-        const uint32_t c5a = (at(0) + at(16)) & 3u, c5b = (at(2) + at(18)) & 3u;
-        const uint32_t c5c = (at(32) + at(48)) & 3u, c5d = (at(34) + at(50)) & 3u;
-        if (lane == 0) {
-            const uint32_t c6 = (c5a + c5b + c5c + c5d) & 3u;
-            gstore<uint8_t>(rec + code_off(5), (uint8_t)(c5a | (c5b << 2) | (c5c << 4) | (c5d << 6)));
-            gstore<uint8_t>(rec + code_off(6), (uint8_t)c6);
-            ws[J.ws_pyr + t] = (uint8_t)c6;
-        }
+        tile_codes<KS>(J, nz, t, ty, tx, q, g, lane, ws);
 
         if (STATS) {
             if (!DYN && (j != cur_j || held == kHeldMax)) {
                 flush(cur_j);
                 cur_j = j;
             }
-            // lambda >= b exactly when x = pixel XOR left neighbour is below 2^(8-b):
-            // y smears each byte of x down, so bit k of y says x >= 2^k
             uint32_t y[16];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const uint32_t w[4] = {p[i].x, p[i].y, p[i].z, p[i].w};
-                // byte left of the lane's 16 pixels: lane g-1 of the row, or the previous tile for g = 0
-                uint32_t lb = (uint32_t)__builtin_amdgcn_mov_dpp((int)(p[i].w >> 24), 0x90, 0xF, 0xF, false);
-                if (g == 0) lb = (left >> (8 * i)) & 0xFFu;
-                uint32_t x[4];
-                x[0] = w[0] ^ ((w[0] << 8) | lb);
-                x[1] = w[1] ^ __builtin_amdgcn_alignbit(w[1], w[0], 24);
-                x[2] = w[2] ^ __builtin_amdgcn_alignbit(w[2], w[1], 24);
-                x[3] = w[3] ^ __builtin_amdgcn_alignbit(w[3], w[2], 24);
-                if (tx == 0 && g == 0) x[0] |= 0xFFu;     // column 0 has no left neighbour
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    uint32_t t = x[k];                                                // t | (t >> s) & mask
-                    t = __builtin_amdgcn_bitop3_b32(t, t >> 1, 0x7F7F7F7Fu, 0xF8);
-                    t = __builtin_amdgcn_bitop3_b32(t, t >> 2, 0x3F3F3F3Fu, 0xF8);
-                    t = __builtin_amdgcn_bitop3_b32(t, t >> 4, 0x0F0F0F0Fu, 0xF8);
-                    y[4 * i + k] = t;
-                }
-            }
-            // 16 words into ones/twos/fours/eights and one word of sixteens
-            uint32_t tA, tB, fA, fB, eA, eB, sx;
-            csa(tA, ones, ones, y[0], y[1]);
-            csa(tB, ones, ones, y[2], y[3]);
-            csa(fA, twos, twos, tA, tB);
-            csa(tA, ones, ones, y[4], y[5]);
-            csa(tB, ones, ones, y[6], y[7]);
-            csa(fB, twos, twos, tA, tB);
-            csa(eA, fours, fours, fA, fB);
-            csa(tA, ones, ones, y[8], y[9]);
-            csa(tB, ones, ones, y[10], y[11]);
-            csa(fA, twos, twos, tA, tB);
-            csa(tA, ones, ones, y[12], y[13]);
-            csa(tB, ones, ones, y[14], y[15]);
-            csa(fB, twos, twos, tA, tB);
-            csa(eB, fours, fours, fA, fB);
-            csa(sx, eights, eights, eA, eB);
-#pragma unroll
-            for (int p2 = 0; p2 < kHiPlanes; ++p2) {
-                const uint32_t c = hi[p2] & sx;
-                hi[p2] ^= sx;
-                sx = c;
-            }
+            tile_thermo(p, left, tx, g, y);
+            thermo_add(C, y);
             ++held;
             if (DYN) {
                 // this tile's Z_b, b = 2..7 (64 pixels per lane), its b_t and capacity
-                uint32_t best_b = 2, best_z = 0, best_s = 0;
-#pragma unroll
-                for (int b = 2; b <= 7; ++b) {
-                    const uint32_t m = 0x01010101u << (8 - b);
-                    const uint32_t ge = (uint32_t)__popc(ones & m) + 2u * (uint32_t)__popc(twos & m) +
-                                        4u * (uint32_t)__popc(fours & m) + 8u * (uint32_t)__popc(eights & m) +
-                                        16u * (uint32_t)__popc(hi[0] & m);
-                    const uint32_t z = uni((uint32_t)__builtin_amdgcn_readlane((int)wave_scan_incl(64u - ge), 63));
-                    if (b == 2 || (uint32_t)b * z > best_s) {
-                        best_b = (uint32_t)b;
-                        best_z = z;
-                        best_s = (uint32_t)b * z;
-                    }
-                }
+                uint32_t best_b, best_z, best_s;
+                thermo_tile_b(C, best_b, best_z, best_s);
                 if (lane == 0) {
                     ws[J.ws_btab + t] = (uint8_t)best_b;
                     unsigned long long *acc = reinterpret_cast<unsigned long long *>(ws + stat_dyn_acc(J));
@@ -284,9 +331,7 @@ __global__ __launch_bounds__(kThreads) void k_tile_prep(const Job *__restrict__ 
                         atomicAdd(acc + 1, (unsigned long long)best_s);
                     }
                 }
-                ones = twos = fours = eights = 0;
-#pragma unroll
-                for (int p2 = 0; p2 < kHiPlanes; ++p2) hi[p2] = 0;
+                thermo_clear(C);
                 held = 0;
             }
         }
@@ -364,7 +409,9 @@ __device__ void finish_stats(const Job &J, uint8_t *ws) {
     }
 }
 
-// Upper pyramid levels lo..max_level, level by level, by one workgroup.
+// Upper pyramid levels lo..max_level, level by level, by one workgroup of NT
+// threads.
+template <int NT = kThreads>
 __device__ void upper_levels(const Job &J, uint8_t *pyr, int lo) {
     const int tid = threadIdx.x;
     for (int m = lo; m <= J.max_level; ++m) {
@@ -373,11 +420,29 @@ __device__ void upper_levels(const Job &J, uint8_t *pyr, int lo) {
         const uint32_t cx = (uint32_t)(J.N >> (m - 1));
         const uint8_t *child = pyr + pyr_off(J.M, J.N, m - 1);
         uint8_t *cur = pyr + pyr_off(J.M, J.N, m);
-        for (uint32_t q = tid; q < gy * gx; q += kThreads) {
+        for (uint32_t q = tid; q < gy * gx; q += NT) {
             const uint32_t Y = q / gx, X = q % gx;
             const uint8_t *a = child + (2 * Y) * cx + 2 * X;
             cur[q] = (uint8_t)((a[0] + a[1] + a[cx] + a[cx + 1]) & 3);
         }
+    }
+    __syncthreads();
+}
+
+// Upper pyramid levels and tile map of image J by one workgroup of NT threads
+// (the per-image kernels; the tile sums are in the pyramid); ends with a
+// barrier.
+template <int NT>
+__device__ void image_pyramid_tmap(const Job &J, uint8_t *ws) {
+    uint8_t *pyr = ws + J.ws_pyr;
+    upper_levels<NT>(J, pyr, kTileLog + 1);
+    uint32_t *tmap = reinterpret_cast<uint32_t *>(ws + J.ws_tmap);
+    const uint32_t tiles_x = (uint32_t)J.tiles_x, ntiles = tiles_x * (uint32_t)J.tiles_y;
+    for (uint32_t t = threadIdx.x; t < ntiles; t += NT) {
+        int dy, dx;
+        uint32_t turns;
+        upper_walk(J, pyr, (int)(t / tiles_x), (int)(t % tiles_x), dy, dx, turns);
+        tmap[t] = tmap_pack(dy, dx, turns);
     }
     __syncthreads();
 }
@@ -467,6 +532,117 @@ __global__ __launch_bounds__(kThreads) void k_fin_tmap(const Job *__restrict__ j
     reinterpret_cast<uint32_t *>(ws + J.ws_tmap)[q] = tmap_pack(dy, dx, turns);
 }
 
+// Encryption of one tile by its wave (Sec. III-A encoding): label each pixel
+// (l = 1 unless its b MSBs match its left neighbour's; column 0 always 1), move
+// its 4x4 block whole to the block's rotated position (tile map entry tm, the
+// tile's code record rc), XOR with the keystream at the destination and put l
+// in the LSB.  LMR: full-byte XOR, then bit 7 of raster pixel p takes stream
+// bit p; LMR_MAPS: the rotated location map and first-MSB map as bit planes.
+// halo: the byte left of each of the lane's four rows (lanes g = 0); rec, dst:
+// the wave's LDS record and tile buffers.
+template <int MODE, int KS>
+__device__ __forceinline__ void encrypt_tile(const Job &J, uint64_t nz, const uint4 p[4], uint32_t halo, int b, uint32_t tm,
+                                             uint4 rc, int tx, uint8_t *rec, uint8_t *dst, const uint32_t *ptab, int q,
+                                             int g, int lane) {
+    constexpr bool kEmrLike = MODE == ENC_EMR || MODE == ENC_DEMR;      // the map in the LSB plane
+    int dy, dx;
+    uint32_t up;
+    tmap_unpack(tm, dy, dx, up);
+    // dynamic b: the tile's b into the table, at the tile's encrypted position
+    if (MODE == ENC_DEMR && lane == 0) gstore<uint8_t>(J.btab + dy * J.tiles_x + dx, (uint8_t)b);
+
+    // labels (Sec. III-A location map): l = 1 unless the b MSBs equal the left neighbour's
+    uint32_t o[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t w[4] = {p[i].x, p[i].y, p[i].z, p[i].w};
+        const uint32_t from_left = (uint32_t)__builtin_amdgcn_mov_dpp((int)(p[i].w >> 24), 0x90, 0xF, 0xF, false);
+        if (MODE == ENC_LMR) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) o[i][k] = w[k];
+            continue;
+        }
+        const uint32_t left = g > 0 ? from_left : (halo >> (8 * i)) & 0xFFu;
+        const uint32_t topm = ((0xFFu << (8 - b)) & 0xFFu) * 0x01010101u;
+        const uint32_t lw[4] = {(w[0] << 8) | left, __builtin_amdgcn_alignbit(w[1], w[0], 24),
+                                __builtin_amdgcn_alignbit(w[2], w[1], 24), __builtin_amdgcn_alignbit(w[3], w[2], 24)};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t d = (w[k] ^ lw[k]) & topm;
+            uint32_t lbl = ((((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d) >> 7) & 0x01010101u;  // l per byte
+            if (k == 0 && tx == 0 && g == 0) lbl |= 1u;                                  // column 0
+            if (kEmrLike) o[i][k] = (w[k] & 0xFEFEFEFEu) | lbl;
+            else o[i][k] = (lbl << 1) | ((w[k] >> 7) & 0x01010101u);                     // l<<1 | eta
+        }
+    }
+    if (lane < kCodeRecord / 16) reinterpret_cast<uint4 *>(rec)[lane] = rc;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    // this lane's four 4x4 blocks (row q, columns 4g..4g+3) go whole to their destinations
+    uint32_t ny[4], nx[4], R1[4], k0[4], k1[4];
+    block_turns4(rec, J.min_level, up, (uint32_t)q, (uint32_t)g, ny, nx, R1, k0, k1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t w[4] = {o[0][k], o[1][k], o[2][k], o[3][k]};
+        uint32_t ob[4];
+        block_forward(ptab, R1[k], k0[k], k1[k], w, ob);
+        *reinterpret_cast<uint4 *>(dst + blk_addr(ny[k], nx[k])) = make_uint4(ob[0], ob[1], ob[2], ob[3]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    // the lane's destination blocks (q, 4g + k): row i of the strip is row i of each
+    uint4 db[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) db[k] = *reinterpret_cast<const uint4 *>(dst + blk_addr((uint32_t)q, (uint32_t)(4 * g + k)));
+    const uint32_t rows[4][4] = {{db[0].x, db[1].x, db[2].x, db[3].x}, {db[0].y, db[1].y, db[2].y, db[3].y},
+                                 {db[0].z, db[1].z, db[2].z, db[3].z}, {db[0].w, db[1].w, db[2].w, db[3].w}};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint4 qv = make_uint4(rows[i][0], rows[i][1], rows[i][2], rows[i][3]);
+        const uint64_t didx = (uint64_t)(dy * kTile + 4 * q + i) * (uint64_t)J.N + (uint64_t)(dx * kTile + 16 * g);
+        if (MODE == ENC_LMR_MAPS) {
+            // bit planes, MSB-first: pixel didx+k -> byte (didx+k)/8, bit 7-(k%8)
+            const uint32_t qq[4] = {qv.x, qv.y, qv.z, qv.w};
+            uint32_t lb = 0, eb = 0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const uint32_t v = (qq[k >> 2] >> (8 * (k & 3))) & 3u;
+                const int pos = (k < 8) ? (7 - k) : (23 - k);   // little-endian u16 of two MSB-first bytes
+                lb |= ((v >> 1) & 1u) << pos;
+                eb |= (v & 1u) << pos;
+            }
+            gstore<uint16_t>(J.out + (didx >> 3), (uint16_t)lb);
+            gstore<uint16_t>(J.msg + (didx >> 3), (uint16_t)eb);
+        } else {
+            const U4 sk = stream_block_quad<KS>(J.key, nz, kDomainImage, didx >> 4);
+            uint4 e;
+            if (kEmrLike) {
+                e = make_uint4(qv.x ^ (sk.x & 0xFEFEFEFEu), qv.y ^ (sk.y & 0xFEFEFEFEu),
+                               qv.z ^ (sk.z & 0xFEFEFEFEu), qv.w ^ (sk.w & 0xFEFEFEFEu));
+            } else {
+                e = make_uint4(qv.x ^ sk.x, qv.y ^ sk.y, qv.z ^ sk.z, qv.w ^ sk.w);
+                if ((int64_t)didx < J.stream_bits) {
+                    // 16 stream bits for pixels didx..didx+15 (didx is a multiple of 16)
+                    const uint32_t sb = ((uint32_t)J.stream[didx >> 3] << 8) | J.stream[(didx >> 3) + 1];
+                    uint32_t ew[4] = {e.x, e.y, e.z, e.w};
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) {
+                        if ((int64_t)didx + k < J.stream_bits) {
+                            const uint32_t bit = (sb >> (15 - k)) & 1u;
+                            ew[k >> 2] = (ew[k >> 2] & ~(0x80u << (8 * (k & 3)))) | (bit << (8 * (k & 3) + 7));
+                        }
+                    }
+                    e = make_uint4(ew[0], ew[1], ew[2], ew[3]);
+                }
+            }
+            gstore<uint4>(J.out + didx, e);
+        }
+    }
+}
 
 // Work unit u of a quad launch: quads c0 .. c0 + nc - 1 of band pair p (tile
 // rows 2p, 2p + 1) of image j; band pairs are cut into ns segments of at most
@@ -591,106 +767,182 @@ __global__ __launch_bounds__(kThreads) void k_encrypt_quad(const Job *__restrict
         constexpr bool kEmrLike = MODE == ENC_EMR || MODE == ENC_DEMR;      // the map in the LSB plane
         if (kEmrLike && st_cur != (uint32_t)RDHEI_OK) continue;           // uniform per wave
         const int b = J.fixed_b > 0 ? J.fixed_b : (int)b_cur;
-        int dy, dx;
-        uint32_t up;
-        tmap_unpack(tm, dy, dx, up);
-        // dynamic b: the tile's b into the table, at the tile's encrypted position
-        if (MODE == ENC_DEMR && lane == 0) gstore<uint8_t>(J.btab + dy * J.tiles_x + dx, (uint8_t)b);
         // the byte left of rows 4q..4q+3 of this tile (column 0 of the image has none)
         const uint32_t halo = side ? edge[slot][wave - 1][q]
                                    : (tx == 0 ? 0u : (first ? halo_mem : edge_prev));
+        encrypt_tile<MODE, KS>(J, nz, p, halo, b, tm, rc, tx, rec, dst, ptab, q, g, lane);
+    }
+}
 
-        // labels (Sec. III-A location map): l = 1 unless the b MSBs equal the left neighbour's
-        uint32_t o[4][4];
+// ----------------------------------------------------------------------------
+// Encryption of whole small images, one workgroup of NW waves per image: the
+// same arithmetic as k_tile_prep<true> -> k_finalize<true> -> k_encrypt_quad
+// (Sec. III-A encoding), in three phases separated by workgroup barriers.
+//  1. Tiles are dealt to the waves in turn: rotation codes and label counts
+//     (the counts meet in LDS instead of global counter slots).
+//  2. Optimal b and the meta record, the upper pyramid levels, the tile map.
+//  3. NW/4 band pairs side by side, four waves (one 2x2 quad) each, walking
+//     their quads left to right; the byte left of each tile row passes through
+//     LDS as in k_encrypt_quad.
+// Phase 3 reads the image a second time soon after phase 1 read it on the same
+// CU (from the device's last-level cache rather than HBM when the images in
+// flight fit there), and one launch replaces four.  The phases of the
+// workgroups on a CU interleave, so vector-bound code and count work overlaps
+// memory-bound encryption.  Images must be on the tiled path with at
+// most kImageWgMaxTiles tiles, method EMR or DEMR.
+// ----------------------------------------------------------------------------
+template <int MODE, int KS, int NW>
+__global__ __launch_bounds__(NW * 64) void k_encrypt_image(const Job *__restrict__ jobs, int njobs,
+                                                           uint8_t *__restrict__ ws) {
+    static_assert(NW % 4 == 0, "four waves per quad");
+    static_assert(MODE == ENC_EMR || MODE == ENC_DEMR, "EMR-style encryption only");
+    constexpr bool DYN = MODE == ENC_DEMR;
+    constexpr int kG = NW / 4;                                    // band pairs side by side
+    __shared__ __align__(16) uint8_t dsts[NW][kTile * kTile];    // per wave: the destination tile
+    __shared__ __align__(16) uint8_t recs[NW][kCodeRecord];      // per wave: the tile's code record
+    __shared__ __align__(16) uint32_t ptab[perm4::kWords];
+    __shared__ __align__(16) uint32_t edge[2][NW][kTile / 4];    // per tile: column 63, four rows per word
+    __shared__ uint32_t zc[8];                                    // Z_b, b = 2..8
+    __shared__ unsigned long long dacc[2];                        // DEMR: redundant pixels, capacity
+    __shared__ int32_t sb;                                        // the image's b
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = (int)uni((uint32_t)tid >> 6);   // wave-uniform
+    const int q = lane >> 2, g = lane & 3;
+    stage_perm_tables(ptab, tid);
+    uint8_t *dst = dsts[wave];
+    uint8_t *rec = recs[wave];
+
+    for (int j = blockIdx.x; j < njobs; j += gridDim.x) {
+        const Job &J = jobs[j];
+        const uint64_t nz = job_nonce(J);
+        const uint32_t tiles_x = (uint32_t)J.tiles_x, ntiles = tiles_x * (uint32_t)J.tiles_y;
+        if (tid < 8) zc[tid] = 0;
+        if (tid < 2) dacc[tid] = 0;
+
+        // ---- 1. codes and counts: tile t = it * NW + wave
+        Thermo C;
+        thermo_clear(C);
+        uint32_t held = 0;
+        auto flush = [&]() {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const uint32_t w[4] = {p[i].x, p[i].y, p[i].z, p[i].w};
-            const uint32_t from_left = (uint32_t)__builtin_amdgcn_mov_dpp((int)(p[i].w >> 24), 0x90, 0xF, 0xF, false);
-            if (MODE == ENC_LMR) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) o[i][k] = w[k];
-                continue;
+            for (int b = 2; b <= 8; ++b) {
+                const uint32_t v = wave_scan_incl(64u * held - thermo_ge(C, b, kHiPlanes));
+                if (lane == 63 && v) atomicAdd(&zc[b - 2], v);
             }
-            const uint32_t left = g > 0 ? from_left : (halo >> (8 * i)) & 0xFFu;
-            const uint32_t topm = ((0xFFu << (8 - b)) & 0xFFu) * 0x01010101u;
-            const uint32_t lw[4] = {(w[0] << 8) | left, __builtin_amdgcn_alignbit(w[1], w[0], 24),
-                                    __builtin_amdgcn_alignbit(w[2], w[1], 24), __builtin_amdgcn_alignbit(w[3], w[2], 24)};
+            thermo_clear(C);
+            held = 0;
+        };
+        uint4 p_n[4];
+        uint32_t left_n = 0;
+        auto fetch1 = [&](uint32_t t) {
+            tile_load(J, (int)(t / tiles_x), (int)(t % tiles_x), q, g, p_n, left_n);
+        };
+        if ((uint32_t)wave < ntiles) fetch1((uint32_t)wave);
+        const uint32_t nit = (ntiles + NW - 1) / NW;                 // uniform in the workgroup
+        for (uint32_t it = 0; it < nit; ++it) {
+            const uint32_t t = it * NW + (uint32_t)wave;
+            __syncthreads();                                          // (also: the counters are cleared)
+            if (t >= ntiles) continue;
+            uint4 p[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint32_t d = (w[k] ^ lw[k]) & topm;
-                uint32_t lbl = ((((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d) >> 7) & 0x01010101u;  // l per byte
-                if (k == 0 && tx == 0 && g == 0) lbl |= 1u;                                  // column 0
-                if (kEmrLike) o[i][k] = (w[k] & 0xFEFEFEFEu) | lbl;
-                else o[i][k] = (lbl << 1) | ((w[k] >> 7) & 0x01010101u);                     // l<<1 | eta
-            }
-        }
-        if (lane < kCodeRecord / 16) reinterpret_cast<uint4 *>(rec)[lane] = rc;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-        // this lane's four 4x4 blocks (row q, columns 4g..4g+3) go whole to their destinations
-        uint32_t ny[4], nx[4], R1[4], k0[4], k1[4];
-        block_turns4(rec, J.min_level, up, (uint32_t)q, (uint32_t)g, ny, nx, R1, k0, k1);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t w[4] = {o[0][k], o[1][k], o[2][k], o[3][k]};
-            uint32_t ob[4];
-            block_forward(ptab, R1[k], k0[k], k1[k], w, ob);
-            *reinterpret_cast<uint4 *>(dst + blk_addr(ny[k], nx[k])) = make_uint4(ob[0], ob[1], ob[2], ob[3]);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-        // the lane's destination blocks (q, 4g + k): row i of the strip is row i of each
-        uint4 db[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) db[k] = *reinterpret_cast<const uint4 *>(dst + blk_addr((uint32_t)q, (uint32_t)(4 * g + k)));
-        const uint32_t rows[4][4] = {{db[0].x, db[1].x, db[2].x, db[3].x}, {db[0].y, db[1].y, db[2].y, db[3].y},
-                                     {db[0].z, db[1].z, db[2].z, db[3].z}, {db[0].w, db[1].w, db[2].w, db[3].w}};
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const uint4 qv = make_uint4(rows[i][0], rows[i][1], rows[i][2], rows[i][3]);
-            const uint64_t didx = (uint64_t)(dy * kTile + 4 * q + i) * (uint64_t)J.N + (uint64_t)(dx * kTile + 16 * g);
-            if (MODE == ENC_LMR_MAPS) {
-                // bit planes, MSB-first: pixel didx+k -> byte (didx+k)/8, bit 7-(k%8)
-                const uint32_t qq[4] = {qv.x, qv.y, qv.z, qv.w};
-                uint32_t lb = 0, eb = 0;
-#pragma unroll
-                for (int k = 0; k < 16; ++k) {
-                    const uint32_t v = (qq[k >> 2] >> (8 * (k & 3))) & 3u;
-                    const int pos = (k < 8) ? (7 - k) : (23 - k);   // little-endian u16 of two MSB-first bytes
-                    lb |= ((v >> 1) & 1u) << pos;
-                    eb |= (v & 1u) << pos;
-                }
-                gstore<uint16_t>(J.out + (didx >> 3), (uint16_t)lb);
-                gstore<uint16_t>(J.msg + (didx >> 3), (uint16_t)eb);
-            } else {
-                const U4 sk = stream_block_quad<KS>(J.key, nz, kDomainImage, didx >> 4);
-                uint4 e;
-                if (kEmrLike) {
-                    e = make_uint4(qv.x ^ (sk.x & 0xFEFEFEFEu), qv.y ^ (sk.y & 0xFEFEFEFEu),
-                                   qv.z ^ (sk.z & 0xFEFEFEFEu), qv.w ^ (sk.w & 0xFEFEFEFEu));
-                } else {
-                    e = make_uint4(qv.x ^ sk.x, qv.y ^ sk.y, qv.z ^ sk.z, qv.w ^ sk.w);
-                    if ((int64_t)didx < J.stream_bits) {
-                        // 16 stream bits for pixels didx..didx+15 (didx is a multiple of 16)
-                        const uint32_t sb = ((uint32_t)J.stream[didx >> 3] << 8) | J.stream[(didx >> 3) + 1];
-                        uint32_t ew[4] = {e.x, e.y, e.z, e.w};
-#pragma unroll
-                        for (int k = 0; k < 16; ++k) {
-                            if ((int64_t)didx + k < J.stream_bits) {
-                                const uint32_t bit = (sb >> (15 - k)) & 1u;
-                                ew[k >> 2] = (ew[k >> 2] & ~(0x80u << (8 * (k & 3)))) | (bit << (8 * (k & 3) + 7));
-                            }
-                        }
-                        e = make_uint4(ew[0], ew[1], ew[2], ew[3]);
+            for (int i = 0; i < 4; ++i) p[i] = p_n[i];
+            const uint32_t left = left_n;
+            fetch1(t + NW < ntiles ? t + NW : t);                    // the last tile reloads itself
+            const int ty = (int)(t / tiles_x), tx = (int)(t % tiles_x);
+            tile_codes<KS>(J, nz, t, ty, tx, q, g, lane, ws);
+            if (!DYN && held == kHeldMax) flush();
+            uint32_t y[16];
+            tile_thermo(p, left, tx, g, y);
+            thermo_add(C, y);
+            ++held;
+            if (DYN) {
+                uint32_t best_b, best_z, best_s;
+                thermo_tile_b(C, best_b, best_z, best_s);
+                if (lane == 0) {
+                    ws[J.ws_btab + t] = (uint8_t)best_b;
+                    if (best_z) {
+                        atomicAdd(&dacc[0], (unsigned long long)best_z);
+                        atomicAdd(&dacc[1], (unsigned long long)best_s);
                     }
                 }
-                gstore<uint4>(J.out + didx, e);
+                thermo_clear(C);
+                held = 0;
             }
         }
+        if (!DYN && held) flush();
+        __syncthreads();
+
+        // ---- 2. optimal b (Sec. III-A: argmax of b*Z_b, smallest b on ties), meta, upper levels, tile map
+        if (tid == 0) {
+            int64_t *zout = reinterpret_cast<int64_t *>(ws + stat_z_offset(J));
+            for (int b = 2; b <= 8; ++b) zout[b - 2] = (int64_t)zc[b - 2];
+            rdhei_meta m;
+            m.height = J.M; m.width = J.N; m.method = J.method;
+            m.min_level = J.min_level; m.max_level = J.max_level;
+            m.map_bits = 0; m.status = RDHEI_OK;
+            m.reserved = 0;
+            m.nonce = J.nonce;
+            if (DYN) {
+                m.b = 0;
+                m.redundant = (int64_t)dacc[0];
+                m.capacity_bits = (int64_t)dacc[1];
+                sb = 0;
+            } else {
+                int best = 2;
+                for (int b = 3; b <= 7; ++b)
+                    if ((int64_t)b * zc[b - 2] > (int64_t)best * zc[best - 2]) best = b;
+                m.b = best;
+                m.redundant = (int64_t)zc[best - 2];
+                m.capacity_bits = (int64_t)best * zc[best - 2];
+                sb = J.fixed_b > 0 ? J.fixed_b : best;
+            }
+            *J.meta = m;
+        }
+        image_pyramid_tmap<NW * 64>(J, ws);
+        const uint32_t *tmap = reinterpret_cast<const uint32_t *>(ws + J.ws_tmap);
+
+        // ---- 3. encryption: group gq takes band pairs gq, gq + kG, ..., their quads left to right
+        const int gq = wave >> 2, side = wave & 1, half = (wave >> 1) & 1;   // this wave's tile in the quad
+        const uint32_t npairs = ((uint32_t)J.tiles_y + 1) / 2, nq = (tiles_x + 1) / 2;
+        const uint32_t nit3 = (npairs + kG - 1) / kG * nq;                  // uniform in the workgroup
+        const int b_img = sb;
+        uint4 rc_n = make_uint4(0, 0, 0, 0);
+        uint32_t tm_n = 0, bt_n = 0;
+        auto fetch3 = [&](uint32_t it) {
+            const uint32_t pr = it / nq * kG + (uint32_t)gq, c = it % nq;
+            const int ty = (int)(2 * pr) + half, tx = (int)(2 * c) + side;
+            if (ty >= J.tiles_y || tx >= J.tiles_x) return;
+            const uint32_t t = (uint32_t)ty * tiles_x + (uint32_t)tx;
+            uint32_t unused;
+            tile_load(J, ty, tx, q, g, p_n, unused);
+            rc_n = gload<uint4>(ws + J.ws_codes + (uint64_t)t * kCodeRecord + 16 * (lane % (kCodeRecord / 16)));
+            tm_n = tmap[t];
+            if (DYN) bt_n = ws[J.ws_btab + t];
+        };
+        if (nit3) fetch3(0);
+        for (uint32_t it = 0; it < nit3; ++it) {
+            uint4 p[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) p[i] = p_n[i];
+            const uint4 rc = rc_n;
+            const uint32_t tm = uni(tm_n), bt = uni(bt_n);
+            const uint32_t pr = it / nq * kG + (uint32_t)gq, c = it % nq;
+            const int ty = (int)(2 * pr) + half, tx = (int)(2 * c) + side;
+            const bool have = ty < J.tiles_y && tx < J.tiles_x;              // wave-uniform
+            const uint32_t slot = it & 1u;
+            // column 63 of the previous quad's right tile, read before this barrier
+            const uint32_t edge_prev = side ? 0u : edge[slot ^ 1u][wave + 1][q];
+            if (have && g == 3)
+                edge[slot][wave][q] = (p[0].w >> 24) | ((p[1].w >> 24) << 8) | ((p[2].w >> 24) << 16) | (p[3].w & 0xFF000000u);
+            __syncthreads();
+            if (it + 1 < nit3) fetch3(it + 1);
+            if (!have) continue;                                              // uniform per wave
+            const int b = DYN ? (int)bt : b_img;
+            // the byte left of rows 4q..4q+3 (a band pair starts at column 0, which has none)
+            const uint32_t halo = side ? edge[slot][wave - 1][q] : (tx == 0 ? 0u : edge_prev);
+            encrypt_tile<MODE, KS>(J, nz, p, halo, b, tm, rc, tx, rec, dst, ptab, q, g, lane);
+        }
+        __syncthreads();                                                      // LDS is reused by the next image
     }
 }
 
@@ -865,8 +1117,14 @@ static __constant__ glide4::Tables kGlideTables = glide4::kTables;
 // bits of its restored left neighbour, so what crosses a tile border is the
 // restored last pixel of the row (last labelled value in the tile's replaceable
 // bits, decrypted bits below), not the last labelled value.
+// IMG: one workgroup per image (grid-stride over the images): the keystream
+// code pyramid of its tiles (as k_tile_prep<false>), the upper levels and
+// tile map (as k_finalize<false>), then its quads as below; every band pair
+// is one segment (Job::qseg covers it), so no row fix-up follows.  The
+// workgroups on a CU are in different phases, so the vector-bound pyramid of
+// some images overlaps the memory-bound recovery of others.
 // (At most 128 VGPRs: four waves per SIMD, which is what the LDS allows.)
-template <int KS, bool DYN = false>
+template <int KS, bool DYN = false, bool IMG = false>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_recover_quad_emr(
     const Job *__restrict__ jobs, int njobs, uint8_t *__restrict__ ws, uint32_t units, const uint32_t *__restrict__ ujob) {
     constexpr int kW = kThreads / 64;
@@ -892,8 +1150,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     if (threadIdx.x < glide4::kWords) gtab[threadIdx.x] = kGlideTables.fill_sel[threadIdx.x];
     __syncthreads();
 
-    uint32_t r0, r1;
-    unit_range(units, r0, r1);
+    uint32_t r0 = 0, r1 = 0;
+    if (!IMG) unit_range(units, r0, r1);
     // quad positions (unit u, quad c of its segment S), wave-uniform
     struct Pos {
         uint32_t u;
@@ -947,6 +1205,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         rc_n = gload<uint4>(ws + J.ws_codes + (uint64_t)(ty * J.tiles_x + tx) * kCodeRecord + 16 * (lane % (kCodeRecord / 16)));
     };
 
+    // IMG: the images of this workgroup in turn, each one's quads as the units
+    for (int j_img = IMG ? (int)blockIdx.x : 0;; j_img += (int)gridDim.x) {
+    if (IMG) {
+        if (j_img >= njobs) break;
+        const Job &J = jobs[j_img];
+        const uint64_t nz = job_nonce(J);
+        const uint32_t tiles_x = (uint32_t)J.tiles_x, ntiles = tiles_x * (uint32_t)J.tiles_y;
+        for (uint32_t t = (uint32_t)wave; t < ntiles; t += kW)
+            tile_codes<KS>(J, nz, t, (int)(t / tiles_x), (int)(t % tiles_x), q, g, lane, ws);
+        __syncthreads();
+        image_pyramid_tmap<kThreads>(J, ws);
+        r0 = J.ubase[UNIT_QROW];
+        r1 = r0 + J.ucount[UNIT_QROW];
+    }
     Pos cur{r0, 0, QSeg{0, 0, 0, 1, 0, 1}};
     if (r0 < r1) cur.S = qseg_of(jobs, njobs, ujob, r0);
     Pos nxt = advance(cur);
@@ -974,7 +1246,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         const Job &J = jobs[cur.S.j];
         const uint64_t nz = job_nonce(J);
         const bool first = cur.c == 0, last = cur.c == cur.S.nc - 1;
-        const bool segd = cur.S.ns > 1;            // rows continue in other segments (fixed up afterwards)
+        const bool segd = !IMG && cur.S.ns > 1;   // rows continue in other segments (fixed up afterwards)
         const bool right_in = 2 * (cur.S.c0 + cur.c) + 1 < J.tiles_x;
         const uint32_t slot = it & 1u;
         uint32_t Do[4][4], sel[4][4], excl[4], tsum[4], fcol[4];
@@ -1165,6 +1437,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         }
         cur = nxt;
         nxt = nn;
+    }
+    if (!IMG) break;
+    __syncthreads();                              // LDS is reused by the next image
     }
 }
 
@@ -1393,6 +1668,36 @@ void launch_encrypt_tiles(const Launch &L, uint32_t units, int mode) {
             hipLaunchKernelGGL((k_encrypt_quad<ENC_LMR_MAPS, KS>),
                                dim3(persistent_grid(L, k_encrypt_quad<ENC_LMR_MAPS, KS>, units)), bl, 0, L.stream, L.jobs,
                                L.njobs, L.ws, units, UJ);
+    });
+}
+
+// One workgroup per image by default (more than fit on the device at once:
+// the hardware starts each as another ends, so the workgroups on a CU are in
+// different phases), or the caller's cap with images dealt round-robin.
+void launch_encrypt_images(const Launch &L) {
+    if (!L.njobs) return;
+    const unsigned grid = grid_for(L, (uint32_t)L.njobs);
+    with_keystream(L.keystream, [&](auto K) {
+        constexpr int KS = decltype(K)::value;
+        auto go = [&](auto kernel) {
+            hipLaunchKernelGGL(kernel, dim3(grid), dim3(kEncImageWaves * 64), 0, L.stream, L.jobs, L.njobs, L.ws);
+        };
+        if (L.dyn) go(k_encrypt_image<ENC_DEMR, KS, kEncImageWaves>);
+        else go(k_encrypt_image<ENC_EMR, KS, kEncImageWaves>);
+    });
+}
+
+void launch_recover_images(const Launch &L) {
+    if (!L.njobs) return;
+    const unsigned grid = grid_for(L, (uint32_t)L.njobs);
+    with_keystream(L.keystream, [&](auto K) {
+        constexpr int KS = decltype(K)::value;
+        if (L.dyn)
+            hipLaunchKernelGGL((k_recover_quad_emr<KS, true, true>), dim3(grid), dim3(kThreads), 0, L.stream, L.jobs,
+                               L.njobs, L.ws, 0u, L.ujob[UNIT_QROW]);
+        else
+            hipLaunchKernelGGL((k_recover_quad_emr<KS, false, true>), dim3(grid), dim3(kThreads), 0, L.stream, L.jobs,
+                               L.njobs, L.ws, 0u, L.ujob[UNIT_QROW]);
     });
 }
 

@@ -24,6 +24,7 @@ PLAN_GRAPH, PLAN_EAGER, PLAN_PER_IMAGE = 0, 1, 2
 TUNE_FORCE = 1
 OPT_PER_PIXEL, OPT_MAX_GRID, OPT_RESERVE_WS, OPT_HIDE_MODE, OPT_LMR_MIN_LEVEL, OPT_KEYSTREAM = 1, 2, 3, 4, 5, 6
 OPT_QUAD_SEG = 7
+OPT_WG_PER_IMAGE = 8
 KEYSTREAM_PHILOX, KEYSTREAM_CHACHA20 = 0, 1
 META_BYTES = 64
 
@@ -128,7 +129,7 @@ def load_library(path: str = LIB_PATH):
     lib.rdhei_plan_run_stage.argtypes = [vp, i32, vp]
     lib.rdhei_plan_autotune.argtypes = [vp, i32, i32, vp]
     lib.rdhei_plan_stage_grid.argtypes = [vp, i32]
-    lib.rdhei_plan_tuned.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.rdhei_plan_tuned.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.rdhei_ctx_set_tune_file.argtypes = [vp, ctypes.c_char_p]
     lib.rdhei_lmr_batch.argtypes = [vp, i32, ctypes.POINTER(JobStruct), i32, i32, ctypes.POINTER(ctypes.c_double), vp]
     lib.rdhei_lmr_compress.argtypes = [vp, vp, i32, i32, vp, i64, ctypes.POINTER(i64)]
@@ -429,10 +430,11 @@ class Plan:
         return self.stage_grids()
 
     def tuned(self) -> dict:
-        """The plan's layout variant: hiding mode and quads per work unit."""
-        hm, qs = ctypes.c_int32(), ctypes.c_int32()
-        _check(self.lib.rdhei_plan_tuned(self.h, ctypes.byref(hm), ctypes.byref(qs)), "rdhei_plan_tuned")
-        return {"hide_mode": hm.value, "qseg": qs.value}
+        """The plan's layout variant: hiding mode, quads per work unit, workgroup-per-image mode."""
+        hm, qs, wi = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(self.lib.rdhei_plan_tuned(self.h, ctypes.byref(hm), ctypes.byref(qs), ctypes.byref(wi)),
+               "rdhei_plan_tuned")
+        return {"hide_mode": hm.value, "qseg": qs.value, "wg_image": wi.value}
 
     def stage_grids(self) -> list:
         return [int(self.lib.rdhei_plan_stage_grid(self.h, k)) for k in range(self.lib.rdhei_plan_stage_count(self.h))]

@@ -111,6 +111,41 @@ def test_batched_chacha_plan_matches_oracle(R, hide_mode):
             assert np.array_equal(d_rec[i].cpu().numpy(), O.emr_recover(Iem_o, mo.b, k1s[i]))
 
 
+def test_chacha_per_image_matches_oracle(R):
+    """Encryption and recovery one workgroup per image
+    (RDHEI_OPT_WG_PER_IMAGE 2) under ChaCha20 with per-image nonces: meta,
+    I_e and I' equal the oracle's."""
+    print("[chacha encrypt per image]", flush=True)
+    ctx = R.Context(0)
+    ctx.set_option(R.OPT_KEYSTREAM, R.KEYSTREAM_CHACHA20)
+    ctx.set_option(R.OPT_WG_PER_IMAGE, 2)
+    shapes = [(64, 64), (256, 256), (512, 512), (320, 256), (128, 1024), (576, 192)]
+    imgs = [inputs.make_image_np(340 + i, *s, 2 + i, (1, 3, 8)[i % 3]) for i, s in enumerate(shapes)]
+    n = len(imgs)
+    d_in = [_dev(I) for I in imgs]
+    d_enc = [torch.empty_like(x) for x in d_in]
+    metas = R.new_meta(n)
+    k1s = [(5 << 44) + i for i in range(n)]
+    nonces = [(3 << 61) | i for i in range(n)]
+    plan = R.Plan(ctx, R.OP_ENCRYPT, R.make_jobs(d_in, d_enc, None, [metas[i] for i in range(n)], k1s, None, shapes,
+                                                  nonces=nonces))
+    assert plan.stages() == ["encrypt_images"]
+    plan.run()
+    torch.cuda.synchronize()
+    ms = R.read_meta(metas)
+    d_rec = [torch.empty_like(x) for x in d_in]
+    rp = R.Plan(ctx, R.OP_RECOVER, R.make_jobs(d_enc, d_rec, None, [metas[i] for i in range(n)], k1s, None, shapes))
+    assert rp.stages() == ["recover_images"]
+    rp.run()
+    torch.cuda.synchronize()
+    with O.keystream_family(O.KEYSTREAM_CHACHA20):
+        for i in range(n):
+            Ie_o, mo = O.emr_encrypt(imgs[i], k1s[i], nonce=nonces[i])
+            assert (ms[i].b, ms[i].capacity_bits, ms[i].nonce) == (mo.b, mo.capacity_bits, nonces[i])
+            assert np.array_equal(d_enc[i].cpu().numpy(), Ie_o), f"image {i} {shapes[i]}"
+            assert np.array_equal(d_rec[i].cpu().numpy(), O.emr_recover(Ie_o, mo.b, k1s[i], nonce=nonces[i]))
+
+
 @pytest.mark.parametrize("shape", [(256, 256), (100, 90)], ids=lambda s: f"{s[0]}x{s[1]}")
 def test_lmr_chacha_matches_oracle(R, cctx, shape):
     """LMR under ChaCha20 (tiled and per-pixel): encrypted image, marked

@@ -163,6 +163,23 @@ def test_demr_batch_matches_oracle(R, hide_mode, frac):
                      [(7 * i) << 33 | i for i in range(n)], frac=frac)
 
 
+def test_demr_per_image_matches_oracle(R):
+    """RDHEI_OPT_WG_PER_IMAGE 2 (encryption and recovery of each image in
+    one workgroup): per-tile b, the image totals, the b table and I_e, then
+    every role, equal to the oracle, direct and as graph plans."""
+    print("[demr] encrypt per image", flush=True)
+    c = R.Context(0)
+    c.set_option(R.OPT_WG_PER_IMAGE, 2)
+    imgs = [inputs.make_image_np(170 + i, M, N, 2 + 5 * i, (1.0, 3.0, 8.0, 20.0)[i % 4]) for i, (M, N) in
+            enumerate(DEMR_SHAPES)]
+    imgs += [_mixed_rows(23, 256, 1024), np.full((128, 128), 91, np.uint8),
+             np.random.default_rng(4).integers(0, 256, (64, 192)).astype(np.uint8)]
+    n = len(imgs)
+    for plans in (False, True):
+        _demr_round_trip(R, c, imgs, [500 + i for i in range(n)], [600 + i for i in range(n)],
+                         [(11 * i) << 31 | i for i in range(n)], plans=plans)
+
+
 def _mixed_rows(seed, M, N):
     """Tiles whose b differ (noise under a fixed top, flat, smooth) and rows
     with no label across whole tiles and segments."""

@@ -351,7 +351,8 @@ def test_invalid_arguments_rejected_on_host(R, ctx):
     with pytest.raises(R.RdheiError):
         ctx.encrypt(d, torch.empty_like(d), 1, meta, method=7)
     c2 = R.Context(0)
-    for opt, bad in ((R.OPT_HIDE_MODE, 4), (R.OPT_HIDE_MODE, -1), (R.OPT_MAX_GRID, -5), (R.OPT_RESERVE_WS, -1),
+    for opt, bad in ((R.OPT_HIDE_MODE, 4), (R.OPT_HIDE_MODE, -1), (R.OPT_WG_PER_IMAGE, 3), (R.OPT_WG_PER_IMAGE, -1),
+                     (R.OPT_MAX_GRID, -5), (R.OPT_RESERVE_WS, -1),
                      (R.OPT_LMR_MIN_LEVEL, 0), (R.OPT_LMR_MIN_LEVEL, 5), (99, 0)):
         with pytest.raises(R.RdheiError):
             c2.set_option(opt, bad)
@@ -755,6 +756,138 @@ def test_quad_segment_lengths_match_oracle(R, qseg, shape):
     c.set_option(R.OPT_QUAD_SEG, qseg)
     M, N = shape
     _roundtrip(R, c, _image(qseg + M, M, N), 61 + qseg, 62 + qseg, nonce=qseg)
+
+
+ENC_IMAGE_SHAPES = [(64, 64), (64, 128), (128, 64), (192, 320), (320, 192), (512, 512), (64, 2048), (1472, 64),
+                    (448, 576), (2048, 2048)]
+
+
+def test_per_image_encrypt_and_recover_match_oracle(R):
+    """RDHEI_OPT_WG_PER_IMAGE 2: encryption (each image's label statistics,
+    optimal b, upper rotation levels, tile map and permuting pass) and
+    recovery (keystream code pyramid, upper levels, tile map, then the quads
+    of whole band pairs) one workgroup per image.  Tile grids from one tile to
+    the 1,024-tile maximum (odd counts both ways, more band pairs than quad
+    groups, one tile row or column), textures giving different b, constant,
+    checkerboard and noise images, and per-image nonces: meta, I_e, I_e' and
+    I' equal the oracle's, direct and replayed as graphs.  A batch with an
+    image past the tile limit goes by stages."""
+    print("[per image encrypt, recover]", flush=True)
+    c = R.Context(0)
+    c.set_option(R.OPT_WG_PER_IMAGE, 2)
+    shapes = list(ENC_IMAGE_SHAPES)
+    imgs = [_image(700 + i, *s, sigma=(1, 3, 8, 20)[i % 4], nsin=2 + 3 * i) for i, s in enumerate(shapes)]
+    for kind, s in (("white", (128, 192)), ("checker", (192, 128)), ("noise", (256, 64)), ("ramp", (64, 320))):
+        imgs.append(_degenerate(kind, *s))
+        shapes.append(s)
+    n = len(imgs)
+    d_in = [_dev(I) for I in imgs]
+    d_enc = [torch.full_like(x, 0x5C) for x in d_in]
+    metas = R.new_meta(n)
+    mp = [metas[i] for i in range(n)]
+    k1s = [900 + 7 * i for i in range(n)]
+    nonces = [(0x9E3779B97F4A7C15 * (i + 3)) % (1 << 64) for i in range(n)]
+    jobs = R.make_jobs(d_in, d_enc, None, mp, k1s, None, shapes, nonces=nonces)
+    plan = R.Plan(c, R.OP_ENCRYPT, jobs)
+    assert plan.stages() == ["encrypt_images"]
+    oracle = [O.emr_encrypt(I, k, nonce=z) for I, k, z in zip(imgs, k1s, nonces)]
+
+    def check(tag):
+        torch.cuda.synchronize()
+        ms = R.read_meta(metas)
+        for i, (Ie_o, mo) in enumerate(oracle):
+            got = (ms[i].status, ms[i].b, ms[i].redundant, ms[i].capacity_bits, ms[i].min_level, ms[i].max_level,
+                   ms[i].nonce)
+            assert got == (0, mo.b, mo.redundant, mo.capacity_bits, mo.min_level, mo.max_level, nonces[i]), \
+                f"{tag} meta {i} {shapes[i]}"
+            e = d_enc[i].cpu().numpy()
+            mism = np.argwhere(e != Ie_o)
+            assert mism.size == 0, f"{tag} encrypt {i} {shapes[i]} at {mism[:5].tolist()} of {len(mism)}"
+
+    c.run_batch(R.OP_ENCRYPT, jobs)
+    check("direct")
+    assert len({m.b for m in R.read_meta(metas)}) >= 3
+    for x in d_enc:
+        x.fill_(0xA3)
+    plan.run()
+    plan.run()
+    check("graph")
+    # hiding by batch, then recovery one workgroup per image, against the oracle
+    caps = [m.capacity_bits for m in R.read_meta(metas)]
+    k2s = [11 + i for i in range(n)]
+    msgs = [inputs.make_payload(k, cp).numpy() for k, cp in zip(k2s, caps)]
+    R.Plan(c, R.OP_EMBED, R.make_jobs(None, d_enc, [_msg_dev(R, m, cp) for m, cp in zip(msgs, caps)], mp, k2s, caps,
+                                      shapes)).run()
+    d_rec = [torch.full_like(x, 0x3C) for x in d_in]
+    rec = R.Plan(c, R.OP_RECOVER, R.make_jobs(d_enc, d_rec, None, mp, k1s, None, shapes))
+    assert rec.stages() == ["recover_images"]
+    rec.run()
+    torch.cuda.synchronize()
+    for i, (Ie_o, mo) in enumerate(oracle):
+        Iem_o = O.emr_embed(Ie_o, mo.b, msgs[i], caps[i], k2s[i], nonce=nonces[i])
+        assert np.array_equal(d_enc[i].cpu().numpy(), Iem_o), f"embed {i} {shapes[i]}"
+        got = d_rec[i].cpu().numpy()
+        want = O.emr_recover(Iem_o, mo.b, k1s[i], nonce=nonces[i])
+        mism = np.argwhere(got != want)
+        assert mism.size == 0, f"recover {i} {shapes[i]} at {mism[:5].tolist()} of {len(mism)}"
+    first = [x.clone() for x in d_rec]
+    for x in d_rec:
+        x.fill_(0x3C)
+    c.run_batch(R.OP_RECOVER, R.make_jobs(d_enc, d_rec, None, mp, k1s, None, shapes))
+    rec.run()
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(first, d_rec))
+    # past the tile limit (2112 x 2048: 1,089 tiles) the batch goes by stages
+    big = [(2112, 2048), (64, 64)]
+    bi = [_image(750 + i, *s) for i, s in enumerate(big)]
+    db = [_dev(I) for I in bi]
+    de = [torch.empty_like(x) for x in db]
+    mb = R.new_meta(2)
+    pb = R.Plan(c, R.OP_ENCRYPT, R.make_jobs(db, de, None, [mb[0], mb[1]], [5, 6], None, big, nonces=[1, 2]))
+    assert "encrypt_images" not in pb.stages()
+    assert "recover_images" not in R.Plan(c, R.OP_RECOVER, R.make_jobs(de, db, None, [mb[0], mb[1]], [5, 6], None,
+                                                                        big)).stages()
+    pb.run()
+    torch.cuda.synchronize()
+    for i in range(2):
+        Ie_o, mo = O.emr_encrypt(bi[i], 5 + i, nonce=1 + i)
+        assert R.read_meta(mb)[i].capacity_bits == mo.capacity_bits
+        assert np.array_equal(de[i].cpu().numpy(), Ie_o)
+
+
+def test_wg_per_image_auto_for_large_batches(R):
+    """RDHEI_OPT_WG_PER_IMAGE 0 encrypts and recovers one workgroup per image
+    once a batch of eligible images has eight per compute unit, by stages
+    below that, and 1 always by stages; the bytes are the same either way."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    n = 8 * cus
+    shapes = [(64, 64)] * n
+    imgs = [_dev(_image(800 + i, 64, 64, sigma=(1, 3, 8, 20)[i % 4], nsin=2 + i % 7)) for i in range(n)]
+    outs = {}
+    for mode in (0, 1):
+        c = R.Context(0)
+        c.set_option(R.OPT_WG_PER_IMAGE, mode)
+        enc = [torch.empty_like(x) for x in imgs]
+        metas = R.new_meta(n)
+        mp = [metas[i] for i in range(n)]
+        full = R.Plan(c, R.OP_ENCRYPT, R.make_jobs(imgs, enc, None, mp, list(range(n)), None, shapes))
+        small = R.Plan(c, R.OP_ENCRYPT, R.make_jobs(imgs[:n - 1], enc[:n - 1], None, mp[:n - 1], list(range(n - 1)),
+                                                    None, shapes[:n - 1]))
+        assert ("encrypt_images" in full.stages()) == (mode == 0)
+        assert "encrypt_images" not in small.stages()
+        full.run()
+        rec = [torch.empty_like(x) for x in imgs]
+        rp = R.Plan(c, R.OP_RECOVER, R.make_jobs(enc, rec, None, mp, list(range(n)), None, shapes))
+        assert ("recover_images" in rp.stages()) == (mode == 0)
+        rp.run()
+        torch.cuda.synchronize()
+        outs[mode] = (torch.stack(enc).cpu().numpy(), metas.cpu().numpy().copy(), torch.stack(rec).cpu().numpy())
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+    for i in (0, n // 2, n - 1):
+        Ie_o, mo = O.emr_encrypt(_image(800 + i, 64, 64, sigma=(1, 3, 8, 20)[i % 4], nsin=2 + i % 7), i)
+        assert np.array_equal(outs[0][0][i], Ie_o)
+        assert np.array_equal(outs[0][2][i], O.emr_recover(Ie_o, mo.b, i))
 
 
 def test_lmr_batch_matches_single_image(R):
