@@ -105,6 +105,23 @@ def test_static_batch_whole_image_hiding(R):
         _equal(got, want)
 
 
+def test_static_batch_one_workgroup_per_image(R):
+    """Encryption and recovery one workgroup per image (RDHEI_OPT_WG_PER_IMAGE
+    2) through the static array: 40 tiled images of mixed shapes, then 3
+    images of 64 x 64, against rdhei_run_batch with the same option."""
+    ctx = R.Context(0)
+    ref = R.Context(0)
+    for c in (ctx, ref):
+        c.set_option(R.OPT_WG_PER_IMAGE, 2)
+    for n, shapes in [(40, [(128, 128), (192, 320), (512, 512), (64, 1024)]), (3, [(64, 64)])]:
+        shapes = [shapes[i % len(shapes)] for i in range(n)]
+        print(f"[no-alloc] one workgroup per image: {n} images", flush=True)
+        imgs, k1, k2, nonces = _batch(R, shapes, 70 + n)
+        got = _round_trip(R, ctx, shapes, imgs, k1, k2, nonces, lambda op, j: ctx.run_batch_static(op, j))
+        want = _round_trip(R, ref, shapes, imgs, k1, k2, nonces, lambda op, j: ref.run_batch(op, j))
+        _equal(got, want)
+
+
 def test_static_batch_rejects_oversized_batch(R):
     """3,000 encryptions of 512 x 512 need about 70 MB of tables and
     workspace, more than the 64 MiB array: RDHEI_ENOMEM, nothing written."""
