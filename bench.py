@@ -23,6 +23,9 @@ if ROOT not in sys.path:
 
 METRIC = "Mpixel/s embed+recover (batched vs per-image) at bit-exact; p99 latency served"
 HBM_PEAK_GBS = 8000.0
+# vector issue rate of the device: 256 CUs x 4 SIMDs, one wave64 instruction
+# per four cycles each (16 lanes per SIMD) at 2.4 GHz
+VALU_WAVE_INSTR_PER_S = 256 * 4 * 2.4e9 / 4
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_emr_batch_4000x512.md")
 STAGE_KERNEL = {"tile_prep_stats": "rdhei::k_tile_prep<true, 0, false>", "encrypt_tiles": "rdhei::k_encrypt_quad<0, 0>",
                 "encrypt_images": "rdhei::k_encrypt_image<0, 0, 8>",
@@ -74,9 +77,10 @@ def run_parity(tasks, threads):
     return groups, time.perf_counter() - t0
 
 
-def measured_traffic(stage: str, px: int):
-    """HBM bytes per launch of a stage from the committed rocprofv3 counter
-    summary, or None when the kernel sources changed since it was taken."""
+def measured_counters(stage: str):
+    """A stage's kernel in the committed rocprofv3 counter summary (HBM bytes
+    and vector instructions per pixel), or None when the kernel sources
+    changed since the counters were taken."""
     import hashlib
     try:
         text = open(TRAFFIC_PROFILE).read()
@@ -85,10 +89,24 @@ def measured_traffic(stage: str, px: int):
             path = os.path.join(ROOT, "paper_2302_07992_amd", "csrc", name)
             if hashlib.sha256(open(path, "rb").read()).hexdigest()[:16] != digest:
                 return None
-        k = data["kernels"][STAGE_KERNEL[stage]]
-        return round((k["fetch_B_per_px"] + k["write_B_per_px"]) * px)
+        return data["kernels"][STAGE_KERNEL[stage]]
     except (OSError, KeyError, IndexError, ValueError):
         return None
+
+
+def measured_traffic(stage: str, px: int):
+    """HBM bytes per launch of a stage from the committed counter summary."""
+    k = measured_counters(stage)
+    return round((k["fetch_B_per_px"] + k["write_B_per_px"]) * px) if k else None
+
+
+def valu_share(stage: str, px: int, ms: float):
+    """Time the device needs to issue the stage's vector instructions (counted
+    per pixel in the committed counter summary) over the stage's time."""
+    k = measured_counters(stage)
+    if not k or "valu_wave_instr_per_px" not in k:
+        return None
+    return round(k["valu_wave_instr_per_px"] * px / VALU_WAVE_INSTR_PER_S / (ms * 1e-3), 3)
 
 
 def parse():
@@ -908,7 +926,8 @@ def main():
     dom = max((s for s in stages if s["alg_GBps"]), key=lambda s: s["ms"])
     roof = {"bound": "hbm", "kernel": dom["stage"], "achieved": dom["alg_GBps"], "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(dom["alg_GBps"] / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(dom["stage"], px), "alg_bytes": round(per_px[dom["op"]][dom["stage"]] * px)}
+            "traffic": measured_traffic(dom["stage"], px), "alg_bytes": round(per_px[dom["op"]][dom["stage"]] * px),
+            "valu_issue_share": valu_share(dom["stage"], px, dom["ms"])}
 
     # ---- per-image launches of the same kernels ----
     per_image = None
