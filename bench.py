@@ -137,7 +137,7 @@ def parse():
                     help="batch of 512x512 images timed under both keystream families (0: skip)")
     ap.add_argument("--lmr-threads", type=int, default=0, help="host coder threads (0: all)")
     ap.add_argument("--serve-pool-mib", type=int, default=2048, help="device pool of the serving loop")
-    ap.add_argument("--serve-streams", type=int, default=2)
+    ap.add_argument("--serve-streams", type=int, default=1)
     ap.add_argument("--serve-loads", default="0.5,0.7,0.9", help="offered load as fractions of batched capacity")
     ap.add_argument("--pipes", type=int, default=2, help="independent parts of the batch on as many streams")
     ap.add_argument("--stagger", type=int, default=0,

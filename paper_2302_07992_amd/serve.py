@@ -237,7 +237,9 @@ class Server:
     """Continuous-batching server over librdhei.
 
     pool_bytes    device memory for outputs and workspaces of requests in flight
-    streams       launch streams (one library context each)
+    streams       launch streams (one library context each; default one: the
+                  device runs one batch at a time, with the next one queued
+                  behind it, which keeps the latency tail short)
     max_inflight  batches on the device at once (default 2 per stream)
     max_batch     requests per batch
     per_request   issue each request alone through the single-image entry
@@ -249,7 +251,7 @@ class Server:
                   R.KEYSTREAM_PHILOX or R.KEYSTREAM_CHACHA20
     """
 
-    def __init__(self, pool_bytes: int = 1 << 30, streams: int = 2, max_inflight: Optional[int] = None,
+    def __init__(self, pool_bytes: int = 1 << 30, streams: int = 1, max_inflight: Optional[int] = None,
                  max_batch: int = 2048, per_request: bool = False,
                  on_complete: Optional[Callable[[int, Dict[str, torch.Tensor]], None]] = None, device="cuda",
                  keystream: int = R.KEYSTREAM_PHILOX):
