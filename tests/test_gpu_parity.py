@@ -855,6 +855,37 @@ def test_per_image_encrypt_and_recover_match_oracle(R):
         assert np.array_equal(de[i].cpu().numpy(), Ie_o)
 
 
+@pytest.mark.parametrize("max_grid", [1, 3])
+def test_per_image_capped_grid_matches_oracle(R, max_grid):
+    """One workgroup per image with the grid capped (RDHEI_OPT_MAX_GRID): each
+    workgroup takes several images in turn, reusing its LDS; encryption and
+    recovery equal the oracle's for every image."""
+    print(f"[per image, capped grid] {max_grid}", flush=True)
+    c = R.Context(0)
+    c.set_option(R.OPT_WG_PER_IMAGE, 2)
+    c.set_option(R.OPT_MAX_GRID, max_grid)
+    shapes = [(64, 64), (192, 320), (128, 128), (256, 64), (64, 448), (320, 192), (512, 512)]
+    imgs = [_image(860 + i, *sh, sigma=(1, 3, 8, 20)[i % 4], nsin=3 + i) for i, sh in enumerate(shapes)]
+    n = len(imgs)
+    d_in = [_dev(I) for I in imgs]
+    d_enc = [torch.empty_like(x) for x in d_in]
+    d_rec = [torch.empty_like(x) for x in d_in]
+    metas = R.new_meta(n)
+    mp = [metas[i] for i in range(n)]
+    k1s = [70 + i for i in range(n)]
+    nonces = [5 * i + 1 for i in range(n)]
+    c.run_batch(R.OP_ENCRYPT, R.make_jobs(d_in, d_enc, None, mp, k1s, None, shapes, nonces=nonces))
+    c.run_batch(R.OP_RECOVER, R.make_jobs(d_enc, d_rec, None, mp, k1s, None, shapes))
+    torch.cuda.synchronize()
+    ms = R.read_meta(metas)
+    for i in range(n):
+        Ie_o, mo = O.emr_encrypt(imgs[i], k1s[i], nonce=nonces[i])
+        assert (ms[i].b, ms[i].capacity_bits) == (mo.b, mo.capacity_bits), i
+        assert np.array_equal(d_enc[i].cpu().numpy(), Ie_o), f"encrypt {i} {shapes[i]}"
+        assert np.array_equal(d_rec[i].cpu().numpy(), O.emr_recover(Ie_o, mo.b, k1s[i], nonce=nonces[i])), \
+            f"recover {i} {shapes[i]}"
+
+
 def test_wg_per_image_auto_for_large_batches(R):
     """RDHEI_OPT_WG_PER_IMAGE 0 encrypts and recovers one workgroup per image
     once a batch of eligible images has eight per compute unit, by stages
