@@ -784,11 +784,10 @@ __global__ __launch_bounds__(kThreads) void k_encrypt_quad(const Job *__restrict
 //  3. NW/4 band pairs side by side, four waves (one 2x2 quad) each, walking
 //     their quads left to right; the byte left of each tile row passes through
 //     LDS as in k_encrypt_quad.
-// Phase 3 reads the image a second time soon after phase 1 read it on the same
-// CU (from the device's last-level cache rather than HBM when the images in
-// flight fit there), and one launch replaces four.  The phases of the
-// workgroups on a CU interleave, so vector-bound code and count work overlaps
-// memory-bound encryption.  Images must be on the tiled path with at
+// Phase 3 reads the image a second time soon after phase 1 read it (past L2,
+// so from the device's last-level cache or HBM), and one launch replaces
+// four.  The phases of the workgroups on a CU interleave, so vector-bound code
+// and count work overlaps memory-bound encryption.  Images must be on the tiled path with at
 // most kImageWgMaxTiles tiles, method EMR or DEMR.
 // ----------------------------------------------------------------------------
 template <int MODE, int KS, int NW>
