@@ -319,7 +319,7 @@ int rdhei_run_batch_static(rdhei_ctx *ctx, int32_t op, const rdhei_job *jobs, in
                                     batches whose images are all tiled (sides
                                     multiples of 64) with at most 1024 tiles
                                     each: 0 one workgroup per image once the
-                                    batch has eight images per compute unit,
+                                    batch has four images per compute unit,
                                     else by stages; 1 by stages (every tile's
                                     label statistics or keystream codes, then
                                     per-image finalisation, then the

@@ -179,8 +179,9 @@ bool wg_image_ok(int op, const rdhei_job *in, int n, bool force_per_pixel) {
 }
 
 // Images from which RDHEI_OPT_WG_PER_IMAGE 0 goes one workgroup per image:
-// eight per compute unit, so that the last round of images is a small part of
-// the launch.
+// four per compute unit (fewer leave too little to interleave on each CU and
+// the last round of images too large a part of the launch: with two per CU
+// recovery is slower than by stages).
 size_t wg_image_min() {
     static int cus = 0;
     if (!cus) {
@@ -188,7 +189,7 @@ size_t wg_image_min() {
         (void)hipGetDevice(&dev);
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
     }
-    return 8 * (size_t)cus;
+    return 4 * (size_t)cus;
 }
 
 int make_layout(int op, const rdhei_job *in, int n, const LayoutOpts &opt, Layout &L) {

@@ -888,10 +888,10 @@ def test_per_image_capped_grid_matches_oracle(R, max_grid):
 
 def test_wg_per_image_auto_for_large_batches(R):
     """RDHEI_OPT_WG_PER_IMAGE 0 encrypts and recovers one workgroup per image
-    once a batch of eligible images has eight per compute unit, by stages
+    once a batch of eligible images has four per compute unit, by stages
     below that, and 1 always by stages; the bytes are the same either way."""
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    n = 8 * cus
+    n = 4 * cus
     shapes = [(64, 64)] * n
     imgs = [_dev(_image(800 + i, 64, 64, sigma=(1, 3, 8, 20)[i % 4], nsin=2 + i % 7)) for i in range(n)]
     outs = {}
