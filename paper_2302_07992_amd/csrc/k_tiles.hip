@@ -779,7 +779,8 @@ __global__ __launch_bounds__(kThreads) void k_encrypt_quad(const Job *__restrict
 // same arithmetic as k_tile_prep<true> -> k_finalize<true> -> k_encrypt_quad
 // (Sec. III-A encoding), in three phases separated by workgroup barriers.
 //  1. Tiles are dealt to the waves in turn: rotation codes and label counts
-//     (the counts meet in LDS instead of global counter slots).
+//     (the counts meet in LDS instead of global counter slots); the waves
+//     run free until the phase ends.
 //  2. Optimal b and the meta record, the upper pyramid levels, the tile map.
 //  3. NW/4 band pairs side by side, four waves (one 2x2 quad) each, walking
 //     their quads left to right; the byte left of each tile row passes through
@@ -837,10 +838,12 @@ __global__ __launch_bounds__(NW * 64) void k_encrypt_image(const Job *__restrict
             tile_load(J, (int)(t / tiles_x), (int)(t % tiles_x), q, g, p_n, left_n);
         };
         if ((uint32_t)wave < ntiles) fetch1((uint32_t)wave);
-        const uint32_t nit = (ntiles + NW - 1) / NW;                 // uniform in the workgroup
+        // no barrier per iteration (unlike k_tile_prep): the image is read
+        // again in phase 3 anyway, and free-running waves measured faster
+        const uint32_t nit = (ntiles + NW - 1) / NW;
+        __syncthreads();                                              // the counters are cleared
         for (uint32_t it = 0; it < nit; ++it) {
             const uint32_t t = it * NW + (uint32_t)wave;
-            __syncthreads();                                          // (also: the counters are cleared)
             if (t >= ntiles) continue;
             uint4 p[4];
 #pragma unroll
