@@ -6,6 +6,7 @@
 // work units (tiles of one image stay on one workgroup, hence on one XCD and
 // its L2) and loads the next unit's inputs before working on the current one.
 #include <mutex>
+#include <type_traits>
 #include <unordered_map>
 
 #include "device.hpp"
@@ -911,9 +912,10 @@ __global__ __launch_bounds__(NW * 64) void k_encrypt_image(const Job *__restrict
         uint4 rc_n = make_uint4(0, 0, 0, 0);
         uint32_t tm_n = 0, bt_n = 0;
         auto fetch3 = [&](uint32_t it) {
+            // a tile outside the image loads the nearest one inside instead (its
+            // values go unused): loads without a branch need no register copies
             const uint32_t pr = it / nq * kG + (uint32_t)gq, c = it % nq;
-            const int ty = (int)(2 * pr) + half, tx = (int)(2 * c) + side;
-            if (ty >= J.tiles_y || tx >= J.tiles_x) return;
+            const int ty = min((int)(2 * pr) + half, J.tiles_y - 1), tx = min((int)(2 * c) + side, J.tiles_x - 1);
             const uint32_t t = (uint32_t)ty * tiles_x + (uint32_t)tx;
             uint32_t unused;
             tile_load(J, ty, tx, q, g, p_n, unused);
@@ -1194,13 +1196,27 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         }
     };
     uint4 e_n[4], rc_n = make_uint4(0, 0, 0, 0);
-    auto fetch = [&](const Pos &P, uint32_t tm) {
+    // Loads the pixels and code record of P's tile.  Inside the quad loop a
+    // position past the range keeps the last segment, so its image is tiled:
+    // a tile outside that image, and a stale tile-map entry, are clamped onto
+    // the image and loaded unused, so the loads need no branch (and no
+    // register copies); before the loop (CLAMP false) a missing tile loads nothing.
+    auto fetch = [&](const Pos &P, uint32_t tm, auto clamp) {
+        constexpr bool CLAMP = decltype(clamp)::value;
         int ty = 0, tx = 0;
-        if (!tile_of(P, ty, tx)) return;
+        if (!CLAMP && !tile_of(P, ty, tx)) return;
         const Job &J = jobs[P.S.j];
+        if (CLAMP) {
+            ty = min(2 * P.S.p + half, J.tiles_y - 1);
+            tx = min(2 * (P.S.c0 + P.c) + side, J.tiles_x - 1);
+        }
         int ey, ex;
         uint32_t up;
         tmap_unpack(uni(tm), ey, ex, up);
+        if (CLAMP) {
+            ey = min(ey, J.tiles_y - 1);
+            ex = min(ex, J.tiles_x - 1);
+        }
         const uint8_t *src = J.in + (uint64_t)(ey * kTile + 4 * q) * (uint64_t)J.N + (uint64_t)(ex * kTile + 16 * g);
 #pragma unroll
         for (int i = 0; i < 4; ++i) e_n[i] = gload<uint4>(src + (uint64_t)i * J.N);
@@ -1226,7 +1242,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     Pos nxt = advance(cur);
     uint32_t tm = 0, b_cur = 0, tm1 = 0, b1 = 0;
     load_tm(cur, tm, b_cur);
-    fetch(cur, tm);
+    fetch(cur, tm, std::false_type{});
     load_tm(nxt, tm1, b1);
     uint32_t lead[4] = {0, 0, 0, 0}, open[4] = {1, 1, 1, 1};   // left waves of segmented images
 
@@ -1237,7 +1253,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         const uint4 rc = rc_n;
         const uint32_t tm_cur = uni(tm), bq = uni(b_cur);
         // pipeline: pixels of the next quad, tile map of the one after
-        fetch(nxt, tm1);
+        fetch(nxt, tm1, std::true_type{});
         const Pos nn = advance(nxt);
         tm = tm1;
         b_cur = b1;
