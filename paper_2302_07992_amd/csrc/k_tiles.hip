@@ -564,13 +564,18 @@ __device__ __forceinline__ void encrypt_tile(const Job &J, uint64_t nz, const ui
             continue;
         }
         const uint32_t left = g > 0 ? from_left : (halo >> (8 * i)) & 0xFFu;
-        const uint32_t topm = ((0xFFu << (8 - b)) & 0xFFu) * 0x01010101u;
+        // the b MSBs of a byte below bit 7 (b >= 1, so bit 7 is always among them)
+        const uint32_t topm7 = ((0x7Fu << (8 - b)) & 0x7Fu) * 0x01010101u;
         const uint32_t lw[4] = {(w[0] << 8) | left, __builtin_amdgcn_alignbit(w[1], w[0], 24),
                                 __builtin_amdgcn_alignbit(w[2], w[1], 24), __builtin_amdgcn_alignbit(w[3], w[2], 24)};
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const uint32_t d = (w[k] ^ lw[k]) & topm;
-            uint32_t lbl = ((((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d) >> 7) & 0x01010101u;  // l per byte
+            // x = pixel XOR left neighbour; per byte, r = its b MSBs below bit 7:
+            // r + 0x7F reaches bit 7 exactly when r != 0 and never carries into
+            // the next byte, so bit 7 of t says the b MSBs differ
+            const uint32_t x = w[k] ^ lw[k];
+            const uint32_t t = ((x & topm7) + 0x7F7F7F7Fu) | x;
+            uint32_t lbl = (t >> 7) & 0x01010101u;                                        // l per byte
             if (k == 0 && tx == 0 && g == 0) lbl |= 1u;                                  // column 0
             if (kEmrLike) o[i][k] = (w[k] & 0xFEFEFEFEu) | lbl;
             else o[i][k] = (lbl << 1) | ((w[k] >> 7) & 0x01010101u);                     // l<<1 | eta
@@ -704,11 +709,11 @@ __global__ __launch_bounds__(kThreads) void k_encrypt_quad(const Job *__restrict
     auto seg_of = [&](uint32_t u) { return qseg_of(jobs, njobs, ujob, u); };
     uint4 p_n[4], rc_n = make_uint4(0, 0, 0, 0);
     uint32_t b_n = 0, st_n = 0, tm_n = 0, halo_n = 0;
-    // loads of this wave's tile of quad c of segment S; false when it lies outside the image
+    // loads of this wave's tile of quad c of segment S; a tile outside the image
+    // loads the nearest one inside instead (unused): no branch, no register copies
     auto fetch = [&](const QSeg &S, int c) {
         const Job &J = jobs[S.j];
-        const int ty = 2 * S.p + half, tx = 2 * (S.c0 + c) + side;
-        if (ty >= J.tiles_y || tx >= J.tiles_x) return;
+        const int ty = min(2 * S.p + half, J.tiles_y - 1), tx = min(2 * (S.c0 + c) + side, J.tiles_x - 1);
         const uint32_t t = (uint32_t)(ty * J.tiles_x + tx);
         const uint8_t *row = J.in + (uint64_t)(ty * kTile + 4 * q) * (uint64_t)J.N + (uint64_t)(tx * kTile + 16 * g);
 #pragma unroll
