@@ -838,25 +838,20 @@ __global__ __launch_bounds__(NW * 64) void k_encrypt_image(const Job *__restrict
             thermo_clear(C);
             held = 0;
         };
-        uint4 p_n[4];
-        uint32_t left_n = 0;
-        auto fetch1 = [&](uint32_t t) {
-            tile_load(J, (int)(t / tiles_x), (int)(t % tiles_x), q, g, p_n, left_n);
-        };
-        if ((uint32_t)wave < ntiles) fetch1((uint32_t)wave);
         // no barrier per iteration (unlike k_tile_prep): the image is read
-        // again in phase 3 anyway, and free-running waves measured faster
+        // again in phase 3 anyway, and free-running waves measured faster.
+        // No prefetch either: the tile's loads are issued first and the
+        // keystream codes, which do not need them, run while they are in
+        // flight (measured faster than carrying the next tile in registers)
         const uint32_t nit = (ntiles + NW - 1) / NW;
         __syncthreads();                                              // the counters are cleared
         for (uint32_t it = 0; it < nit; ++it) {
             const uint32_t t = it * NW + (uint32_t)wave;
             if (t >= ntiles) continue;
-            uint4 p[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) p[i] = p_n[i];
-            const uint32_t left = left_n;
-            fetch1(t + NW < ntiles ? t + NW : t);                    // the last tile reloads itself
             const int ty = (int)(t / tiles_x), tx = (int)(t % tiles_x);
+            uint4 p[4];
+            uint32_t left;
+            tile_load(J, ty, tx, q, g, p, left);
             tile_codes<KS>(J, nz, t, ty, tx, q, g, lane, ws);
             if (!DYN && held == kHeldMax) flush();
             uint32_t y[16];
@@ -914,7 +909,7 @@ __global__ __launch_bounds__(NW * 64) void k_encrypt_image(const Job *__restrict
         const uint32_t npairs = ((uint32_t)J.tiles_y + 1) / 2, nq = (tiles_x + 1) / 2;
         const uint32_t nit3 = (npairs + kG - 1) / kG * nq;                  // uniform in the workgroup
         const int b_img = sb;
-        uint4 rc_n = make_uint4(0, 0, 0, 0);
+        uint4 p_n[4], rc_n = make_uint4(0, 0, 0, 0);
         uint32_t tm_n = 0, bt_n = 0;
         auto fetch3 = [&](uint32_t it) {
             // a tile outside the image loads the nearest one inside instead (its
